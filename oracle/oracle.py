@@ -1,0 +1,163 @@
+"""ctypes wrapper around the C oracle (``liboracle.so``).  Test infrastructure only.
+
+A network is passed as plain arrays: ``reac`` and ``prod`` of shape (M, S) with
+non-negative integer coefficients, ``rates`` (M,) binary64 stochastic rate constants and
+``x0`` (S,) int32 initial counts.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+from . import build_oracle
+
+OK, INVALID, NOMEM, OVERFLOW, EVENT_LIMIT = 0, 1, 2, 4, 5
+
+_lib = None
+
+
+class _Net(ctypes.Structure):
+    _fields_ = [("S", ctypes.c_int32), ("M", ctypes.c_int32),
+                ("reac", ctypes.c_void_p), ("prod", ctypes.c_void_p),
+                ("rate", ctypes.c_void_p), ("x0", ctypes.c_void_p)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = build_oracle.build()
+        L = ctypes.CDLL(path)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_philox4x32_10.restype = None
+        L.orc_neglog.argtypes = [ctypes.c_double]
+        L.orc_neglog.restype = ctypes.c_double
+        L.orc_uniforms.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+        L.orc_uniforms.restype = None
+        vp = ctypes.c_void_p
+        L.orc_trajectory.argtypes = [ctypes.POINTER(_Net), ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double,
+                                     vp, ctypes.c_int32, ctypes.c_uint64,
+                                     vp, vp, vp, vp, vp, vp]
+        L.orc_trajectory.restype = ctypes.c_int
+        L.orc_run.argtypes = [ctypes.POINTER(_Net), ctypes.c_int64, ctypes.c_double, vp, ctypes.c_int32,
+                              ctypes.c_uint64, ctypes.c_uint64,
+                              ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                              vp, vp, vp, vp, vp, ctypes.c_int]
+        L.orc_run.restype = ctypes.c_int
+        L.orc_grad.argtypes = [ctypes.POINTER(_Net), ctypes.c_int64, ctypes.c_double, vp, ctypes.c_int32,
+                               ctypes.c_uint64, ctypes.c_uint64, vp, vp, vp, vp, ctypes.c_int]
+        L.orc_grad.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+class Net:
+    """Holds contiguous copies of a network's arrays and the ctypes struct that points at them."""
+
+    def __init__(self, reac, prod, rates, x0):
+        self.reac = np.ascontiguousarray(reac, dtype=np.int32)
+        self.prod = np.ascontiguousarray(prod, dtype=np.int32)
+        self.rates = np.ascontiguousarray(rates, dtype=np.float64)
+        self.x0 = np.ascontiguousarray(x0, dtype=np.int32)
+        self.M, self.S = self.reac.shape
+        self.c = _Net(self.S, self.M, self.reac.ctypes.data, self.prod.ctypes.data,
+                      self.rates.ctypes.data, self.x0.ctypes.data)
+
+
+def as_net(model, rates=None):
+    return Net(model["reac"], model["prod"], model["rates"] if rates is None else rates, model["x0"])
+
+
+def default_threads():
+    n = os.environ.get("ORACLE_THREADS")
+    if n:
+        return int(n)
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def philox(ctr, key):
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return [o[i] for i in range(4)]
+
+
+def neglog(r):
+    return lib().orc_neglog(float(r))
+
+
+def uniforms(seed, traj, k):
+    r1, r2 = ctypes.c_double(), ctypes.c_double()
+    lib().orc_uniforms(seed, traj, k, ctypes.byref(r1), ctypes.byref(r2))
+    return r1.value, r2.value
+
+
+def trajectory(model, seed, traj, t_end, grid, max_events=2**62, rates=None):
+    """Returns (status, dict) with states (G,S) int32, events, draws, t_last, n_fired (M,), a_int (M,)."""
+    net = as_net(model, rates)
+    grid = np.ascontiguousarray(grid, dtype=np.float64)
+    G = grid.shape[0]
+    states = np.zeros((G, net.S), dtype=np.int32)
+    ev = np.zeros(1, dtype=np.uint64)
+    dr = np.zeros(1, dtype=np.uint64)
+    tl = np.zeros(1, dtype=np.float64)
+    nf = np.zeros(net.M, dtype=np.int64)
+    ai = np.zeros(net.M, dtype=np.float64)
+    st = lib().orc_trajectory(ctypes.byref(net.c), seed, traj, t_end, _ptr(grid), G, max_events,
+                              _ptr(states), _ptr(ev), _ptr(dr), _ptr(tl), _ptr(nf), _ptr(ai))
+    return st, dict(states=states, events=int(ev[0]), draws=int(dr[0]), t_last=float(tl[0]),
+                    n_fired=nf, a_int=ai)
+
+
+def run(model, N, t_end, grid, seed, hist=None, max_events=2**62, rates=None, threads=None,
+        want_sums=False):
+    """Mean / variance per (grid point, species); optional histogram spec (species, lo, width, nbins).
+
+    Returns (status, dict(mean (G,S), var (G,S), hist (G,nbins) or None, events, sums)).
+    ``sums`` holds the exact (sum X, sum X^2) as Python ints, shape (G,S,2), if requested.
+    """
+    net = as_net(model, rates)
+    grid = np.ascontiguousarray(grid, dtype=np.float64)
+    G = grid.shape[0]
+    mean = np.zeros((G, net.S))
+    var = np.zeros((G, net.S))
+    h = None
+    hs = (0, 0, 1, 1)
+    if hist is not None:
+        hs = tuple(int(v) for v in hist)
+        h = np.zeros((G, hs[3]), dtype=np.uint32)
+    sums = np.zeros((G, net.S, 4), dtype=np.int64) if want_sums else None
+    ev = np.zeros(1, dtype=np.uint64)
+    st = lib().orc_run(ctypes.byref(net.c), int(N), float(t_end), _ptr(grid), G, seed, max_events,
+                       hs[0], hs[1], hs[2], hs[3], _ptr(mean), _ptr(var), _ptr(h), _ptr(sums), _ptr(ev),
+                       threads or default_threads())
+    out = dict(mean=mean, var=var, hist=h, events=int(ev[0]))
+    if want_sums:
+        def i128(hi, lo):
+            return (int(hi) << 64) | (int(lo) & 0xFFFFFFFFFFFFFFFF)
+        out["sums"] = [[(i128(sums[g, s, 0], sums[g, s, 1]), i128(sums[g, s, 2], sums[g, s, 3]))
+                        for s in range(net.S)] for g in range(G)]
+    return st, out
+
+
+def grad(model, N, t_end, grid, seed, w, mhat, max_events=2**62, rates=None, threads=None):
+    """Likelihood-ratio gradient wrt log rate constants.  Returns (status, grad (M,), l1 (M,))."""
+    net = as_net(model, rates)
+    grid = np.ascontiguousarray(grid, dtype=np.float64)
+    G = grid.shape[0]
+    w = np.ascontiguousarray(w, dtype=np.float64).reshape(G, net.S)
+    mhat = np.ascontiguousarray(mhat, dtype=np.float64).reshape(G, net.S)
+    g_out = np.zeros(net.M)
+    l1 = np.zeros(net.M)
+    st = lib().orc_grad(ctypes.byref(net.c), int(N), float(t_end), _ptr(grid), G, seed, max_events,
+                        _ptr(w), _ptr(mhat), _ptr(g_out), _ptr(l1), threads or default_threads())
+    return st, g_out, l1

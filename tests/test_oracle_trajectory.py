@@ -1,0 +1,162 @@
+"""Exact per-trajectory pins for the oracle, and the readings of the edge cases.
+
+* Stoichiometry: x(T) = x0 + sum_j nu_j n_j(T) for every trajectory; counts never go
+  negative; events = sum_j n_j; draws = events (+1 when the last draw overshot t_end).
+* Right-continuous alignment: a grid point placed exactly at an event time sees the event,
+  the binary64 number just below it does not; an event at exactly t_end is applied.
+* Absorbing states, zero rates, the 2A pair count at x = 1, t_end = 0, a single grid
+  point, duplicate grid points, int32 overflow and the event limit.
+* A second implementation (oracle/mirror.py, pure Python) agrees bit for bit.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mirror
+from oracle import oracle as orc
+from paper_1007_1768_amd import inputs
+
+
+def _nu(m):
+    return (np.asarray(m["prod"], np.int64) - np.asarray(m["reac"], np.int64))
+
+
+def _check_invariants(m, seed, traj, t_end, G=11):
+    grid = inputs.uniform_grid(t_end, G)
+    st, r = orc.trajectory(m, seed, traj, t_end, grid)
+    assert st == orc.OK
+    xT = r["states"][-1].astype(np.int64)           # grid ends at t_end: final state
+    assert np.array_equal(xT, np.asarray(m["x0"], np.int64) + _nu(m).T @ r["n_fired"])
+    assert (r["states"] >= 0).all()
+    assert r["events"] == int(r["n_fired"].sum())
+    assert r["draws"] in (r["events"], r["events"] + 1)
+    assert 0.0 <= r["t_last"] <= t_end
+    assert (r["a_int"] >= 0).all()
+    return r
+
+
+def test_invariants_viral_and_immigration_death():
+    for traj in range(20):
+        _check_invariants(inputs.viral(), 2, traj, 50.0)
+        _check_invariants(inputs.immigration_death(), 1, traj, 100.0)
+
+
+def test_invariants_random_networks():
+    nets = inputs.random_networks(count=6)
+    for net in nets:
+        for traj in range(3):
+            _check_invariants(net, net["seed"], traj, min(net["t_end"], 2.0))
+
+
+def test_large_stoichiometry_200():
+    # an HIV-style burst: I -> I + 200 V (Section 3.2's stoichiometry example)
+    m = inputs._model("burst", ["I", "V"], [({"I": 1}, {"I": 1, "V": 200}, 2.0), ({"V": 1}, {}, 0.5),
+                                            ({"I": 1}, {}, 0.3)], [5, 0])
+    for traj in range(10):
+        r = _check_invariants(m, 3, traj, 10.0)
+        assert (r["states"][:, 1] % 1 == 0).all()
+
+
+def test_mirror_agrees_bitwise():
+    cases = [(inputs.immigration_death(), 1, 30.0, 31), (inputs.viral(), 2, 5.0, 26)]
+    nets = inputs.random_networks(count=3)
+    cases.append((nets[0], nets[0]["seed"], 0.3, 7))
+    for m, seed, t_end, G in cases:
+        grid = inputs.uniform_grid(t_end, G)
+        for traj in (0, 1, 7, 12345):
+            st, r = orc.trajectory(m, seed, traj, t_end, grid)
+            assert st == orc.OK
+            mr = mirror.trajectory(m, seed, traj, t_end, grid)
+            assert np.array_equal(r["states"], np.asarray(mr["states"], dtype=np.int32))
+            assert r["events"] == mr["events"] and r["draws"] == mr["draws"]
+            assert r["t_last"] == mr["t_last"]
+            assert list(r["n_fired"]) == mr["n_fired"]
+            assert [float(v) for v in r["a_int"]] == mr["a_int"]
+
+
+def test_right_continuity_at_event_times():
+    m = inputs.viral()
+    t_end = 3.0
+    st, base = orc.trajectory(m, 2, 5, t_end, np.array([t_end]))
+    assert st == orc.OK and base["events"] > 2
+    tl = base["t_last"]
+    below = math.nextafter(tl, -math.inf)
+    st, r = orc.trajectory(m, 2, 5, t_end, np.array([below, tl, tl, t_end]))
+    assert st == orc.OK
+    assert np.array_equal(r["states"][1], base["states"][0])      # event at tl is included at tl
+    assert np.array_equal(r["states"][2], r["states"][1])         # duplicate grid point
+    assert not np.array_equal(r["states"][0], r["states"][1])     # ... but not just below it
+    # an event at exactly t_end is applied
+    st, r2 = orc.trajectory(m, 2, 5, tl, np.array([tl]))
+    assert st == orc.OK
+    assert r2["events"] == base["events"] and r2["t_last"] == tl
+    assert np.array_equal(r2["states"][0], base["states"][0])
+    # prefix property: the same trajectory observed on a shorter horizon
+    st, r3 = orc.trajectory(m, 2, 5, below, np.array([below]))
+    assert r3["events"] == base["events"] - 1
+    assert np.array_equal(r3["states"][0], r["states"][0])
+
+
+def test_absorbing_state_pure_death():
+    m = inputs._model("death", ["X"], [({"X": 1}, {}, 1.0)], [5])
+    st, r = orc.trajectory(m, 4, 0, 1000.0, inputs.uniform_grid(1000.0, 5))
+    assert st == orc.OK
+    assert r["events"] == 5 and r["draws"] == 5          # no draw once a0 == 0
+    assert (r["states"][1:] == 0).all()
+    assert r["a_int"][0] > 0
+
+
+def test_zero_rates_and_pair_count_at_one():
+    m = inputs.viral(rates=np.zeros(9))
+    st, r = orc.trajectory(m, 2, 0, 50.0, inputs.uniform_grid(50.0, 4))
+    assert st == orc.OK and r["events"] == 0 and r["draws"] == 0
+    assert (r["states"] == np.asarray(m["x0"])).all()
+    dimer = inputs._model("dimer1", ["A", "B"], [({"A": 2}, {"B": 1}, 5.0)], [1, 0])
+    st, r = orc.trajectory(dimer, 2, 0, 50.0, inputs.uniform_grid(50.0, 4))
+    assert st == orc.OK and r["events"] == 0 and r["draws"] == 0
+
+
+def test_t_end_zero_and_single_grid_point():
+    m = inputs.viral()
+    st, r = orc.trajectory(m, 2, 0, 0.0, np.array([0.0]))
+    assert st == orc.OK and r["events"] == 0 and r["draws"] == 1
+    assert (r["states"][0] == np.asarray(m["x0"])).all()
+    st, out = orc.run(m, 5, 0.0, np.array([0.0, 0.0]), seed=2)
+    assert st == orc.OK
+    assert (out["mean"] == np.asarray(m["x0"])).all() and (out["var"] == 0).all()
+    st, out = orc.run(m, 1, 10.0, np.array([10.0]), seed=2)
+    assert st == orc.OK and (out["var"] == 0).all()
+
+
+def test_overflow_and_event_limit_are_errors():
+    m = inputs._model("grow", ["X"], [({}, {"X": 1}, 1.0)], [2**31 - 10])
+    st, r = orc.trajectory(m, 1, 0, 1000.0, np.array([1000.0]))
+    assert st == orc.OVERFLOW
+    st, _ = orc.run(m, 3, 1000.0, np.array([1000.0]), seed=1)
+    assert st == orc.OVERFLOW
+    st, r = orc.trajectory(inputs.viral(), 2, 0, 50.0, np.array([50.0]), max_events=100)
+    assert st == orc.EVENT_LIMIT
+    st, r = orc.trajectory(inputs.viral(), 2, 0, 50.0, np.array([50.0]), max_events=10**9)
+    assert st == orc.OK
+
+
+@pytest.mark.parametrize("bad", ["order3", "neg_rate", "nan_rate", "neg_x0", "grid_order", "grid_range"])
+def test_invalid_inputs_rejected(bad):
+    m = inputs.viral()
+    grid = inputs.uniform_grid(50.0, 5)
+    t_end = 50.0
+    if bad == "order3":
+        m["reac"][0, 0] = 3
+    elif bad == "neg_rate":
+        m["rates"][1] = -1.0
+    elif bad == "nan_rate":
+        m["rates"][1] = float("nan")
+    elif bad == "neg_x0":
+        m["x0"][2] = -1
+    elif bad == "grid_order":
+        grid = grid[::-1].copy()
+    elif bad == "grid_range":
+        grid = grid + 1.0
+    st, _ = orc.trajectory(m, 1, 0, t_end, grid)
+    assert st == orc.INVALID
