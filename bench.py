@@ -1,0 +1,233 @@
+"""Benchmark: SSA reaction events per second on one MI355X, with the VALU roofline and the
+CPU oracle as a reported baseline.
+
+One step is the whole hot path over one batch of synthetic input: the forward pass
+(trajectories, grid alignment, cross-trajectory mean and variance) followed by the
+likelihood-ratio backward pass of a squared-error loss on the grid means (re-simulating
+the same trajectories).  Both run through the library's persistent work-stealing kernel.
+
+Default workload: the 4-species viral network, 10^4 trajectories, t_end = 50, 1000-point
+grid; the loss target is the mean of the same network with log rates perturbed by
+N(0, 0.1^2) (computed once, outside the timed region).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload viral|differentiated|large]
+       [--no-cpu-baseline] [--copy-calibration]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+from paper_1007_1768_amd import inputs  # noqa: E402
+
+PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9     # full-rate VALU lane operations per second (MI355X)
+HBM_PEAK = 8.0e12
+
+# Algorithmic VALU work per SSA event, in full-rate lane operations (a 32x32->64-bit
+# multiply and a reciprocal count 4, as quarter-rate instructions).  See the design doc.
+W_PHILOX = 10 * (2 * 4 + 2)        # per round: two 32x32->64 products, two 3-way xors
+W_UNIFORMS = 2 * 7                 # two 53-bit conversions
+W_NEGLOG = 37                      # exponent split, (m-1)/(m+1), 10-term Horner, recombination
+W_DIV = 13                         # one IEEE binary64 division (reciprocal + refinement + fixup)
+
+
+def propensity_ops(model):
+    reac = np.asarray(model["reac"])
+    ops = 0
+    for row in reac:
+        order = int(row.sum())
+        if order == 0:
+            ops += 1
+        elif order == 1:
+            ops += 2
+        elif (row == 2).any():
+            ops += 5
+        else:
+            ops += 4
+    return ops
+
+
+def mean_changes(model, n_fired_share=None):
+    nu = np.asarray(model["prod"]) - np.asarray(model["reac"])
+    per = (nu != 0).sum(axis=1)
+    if n_fired_share is None:
+        return float(per.mean())
+    return float((per * n_fired_share).sum())
+
+
+def w_forward(model, crossing_frac, changes):
+    M = model["reac"].shape[0]
+    return (W_PHILOX + W_UNIFORMS + W_NEGLOG + W_DIV + 1 + propensity_ops(model) + (M - 1) + 2 * M
+            + changes * 6 + crossing_frac * 2 * W_DIV)
+
+
+def w_backward(model, crossings_per_event):
+    M, S = model["reac"].shape
+    return (W_PHILOX + W_UNIFORMS + W_NEGLOG + W_DIV + 1 + propensity_ops(model) + (M - 1) + 2 * M
+            + 4 * M + crossings_per_event * (2 * S + 4 * M + W_DIV))
+
+
+def workload(name):
+    w = dict(inputs.WORKLOADS[name])
+    m = w["model"]()
+    return m, w
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="viral", choices=["viral", "differentiated", "large"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (for HBM counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(the sharding design is in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1007_1768_amd import ssa
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    if args.copy_calibration:
+        n = (1 << 30) // 8
+        x = torch.ones(n, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}))
+        return
+
+    m, w = workload(args.workload)
+    N, t_end, G, seed = w["n_traj"], w["t_end"], w["G"], w["seed"]
+    grid_np = inputs.uniform_grid(t_end, G)
+    grid = torch.tensor(grid_np, dtype=torch.float64, device=dev)
+    model = ssa.Model.from_dict(m)
+    hist = w.get("hist")
+    stream = torch.cuda.current_stream()
+
+    # target of the loss: the same network with perturbed log rates (untimed)
+    prates = torch.tensor(inputs.perturbed_rates(m, w.get("perturb_seed", 404)), device=dev)
+    target, _, _, _ = ssa.run_device(model, N, t_end, grid, w.get("target_seed", 44), rates=prates)
+    torch.cuda.synchronize()
+
+    S, M = m["reac"].shape[1], m["reac"].shape[0]
+    mean = torch.empty((G, S), dtype=torch.float64, device=dev)
+    var = torch.empty_like(mean)
+    hbuf = torch.empty((G, hist[3]), dtype=torch.int32, device=dev) if hist else None
+    gbuf = torch.empty(M, dtype=torch.float64, device=dev)
+
+    def step():
+        _, _, _, sf = ssa.run_device(model, N, t_end, grid, seed, hist=hist, out=(mean, var, hbuf),
+                                     with_stats=True)
+        wts = 2.0 * (mean - target)
+        _, sb = ssa.backward_device(model, N, t_end, grid, seed, wts, mean, out=gbuf, with_stats=True)
+        return sf, sb
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fwd_ms, bwd_ms, events = [], [], 0
+    stats_f = stats_b = None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(args.steps):
+        stats_f, stats_b = step()
+        fwd_ms.append(stats_f["kernel_ms"])
+        bwd_ms.append(stats_b["kernel_ms"])
+        events += stats_f["events"] + stats_b["events"]
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = e0.elapsed_time(e1) / args.steps
+    ev_per_step = stats_f["events"] + stats_b["events"]
+    value = ev_per_step / (step_ms * 1e-3)
+
+    # forward-only timing (same kernels, no backward), for the grad / plain ratio
+    f_only = []
+    for _ in range(3):
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        ssa.run_device(model, N, t_end, grid, seed, hist=hist, out=(mean, var, hbuf), with_stats=True)
+        torch.cuda.synchronize()
+        f_only.append(time.perf_counter() - a0)
+    fwd_only_ms = 1e3 * float(np.median(f_only))
+
+    # roofline of the dominant kernel (algorithmic lane-ops per launch / mean launch time)
+    crossings = G * N / max(stats_f["events"], 1)                 # grid points passed per event
+    cross_frac = min(1.0, crossings)
+    changes = mean_changes(m)
+    fwd_avg = float(np.mean(fwd_ms))
+    bwd_avg = float(np.mean(bwd_ms))
+    if bwd_avg >= fwd_avg:
+        kname, kms, wop = "sim_kernel<kBwd>", bwd_avg, w_backward(m, crossings)
+    else:
+        kname, kms, wop = "sim_kernel<kFwd>", fwd_avg, w_forward(m, cross_frac, changes)
+    achieved = wop * stats_f["events"] / (kms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_LANE_OPS / 1e12, 3),
+                "unit": "Tlane-op/s", "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 5), "traffic": None,
+                "kernel": kname, "kernel_ms": round(kms, 4), "ops_per_event": round(wop, 1)}
+
+    out = {
+        "metric": "SSA reaction events/sec on 1 MI355X (+ % VALU roofline); batched & grad vs plain",
+        "value": round(value, 1),
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+i32",
+        "data": "synthetic",
+        "config": {"workload": "%s: %d trajectories, t_end %g, %d-point grid, forward mean/var + LR backward"
+                               % (args.workload, N, t_end, G),
+                   "n_traj": N, "grid_points": G, "t_end": t_end, "species": S, "reactions": M,
+                   "histogram": list(hist) if hist else None},
+        "fwd_events_per_step": stats_f["events"],
+        "bwd_events_per_step": stats_b["events"],
+        "fwd_kernel_ms": round(fwd_avg, 4),
+        "bwd_kernel_ms": round(bwd_avg, 4),
+        "fwd_only_ms": round(fwd_only_ms, 4),
+        "grad_vs_plain": round(step_ms / fwd_only_ms, 3),
+        "wall_s": round(wall, 3),
+        "roofline": roofline,
+    }
+
+    if not args.no_cpu_baseline:
+        from oracle import oracle as orc
+        thr = orc.default_threads()
+        # bounded sample: a slice of the same workload sized for ~10-30 s of oracle time
+        n_cpu = min(N, int(os.environ.get("BENCH_CPU_TRAJ", str(min(N, 20000)))))
+        a0 = time.perf_counter()
+        st, ref = orc.run(m, n_cpu, t_end, grid_np, seed, hist=hist, threads=thr)
+        tw = target.cpu().numpy()
+        st2, g, _ = orc.grad(m, n_cpu, t_end, grid_np, seed, 2.0 * (ref["mean"] - tw), ref["mean"], threads=thr)
+        cpu_s = time.perf_counter() - a0
+        out["cpu_baseline"] = {"value": round(2 * ref["events"] / cpu_s, 1), "unit": "events/s", "cores": thr,
+                               "kind": "oracle",
+                               "sample": "%d of %d trajectories, forward + gradient, %.1f s" % (n_cpu, N, cpu_s)}
+    print(json.dumps(out), flush=True)
+    model.close()
+
+
+if __name__ == "__main__":
+    main()

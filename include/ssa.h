@@ -1,0 +1,154 @@
+/*
+ * ssa.h -- C ABI of libssa: many independent Gillespie direct-method trajectories of a
+ * mass-action reaction network on one MI355X (gfx950), aligned on a time grid and reduced
+ * across trajectories into per-grid-point mean and variance, with a likelihood-ratio
+ * gradient and a batched many-network form.
+ *
+ * Paper: Aldinucci, Bracciali, Lio, Sorathiya, Torquati, "StochKit-FF: Efficient Systems
+ * Biology on Multicore Architectures" (2010).
+ *   - Section 2: the stochastic simulation of a CTMC by Gillespie's algorithm (one
+ *     trajectory per realisation, exact exponential waiting times).
+ *   - Section 3.2: a model is an integer state vector, an integer stoichiometric matrix,
+ *     mass-action propensities and a simulated duration; StochRxn_ff runs copies of one
+ *     simulation or parameter-swept simulations.
+ *   - Section 3.2.1: "selective memory" aligns the trajectories' points by simulation time
+ *     and reduces them online with associative, commutative functions (mean, variance).
+ *
+ * Arithmetic contract shared (as prose, not code) with the CPU oracle:
+ *   propensity  a_j = c_j * h_j(x), h exact in 64-bit integers then rounded once:
+ *               1 | x_A | x_A x_B | x_A (x_A - 1) / 2 for 2A
+ *   sums        S_0 = a_0, S_j = S_{j-1} + a_j (left to right), a0 = S_{M-1}
+ *   random      Philox4x32-10, key = (seed lo, seed hi), counter = (k lo, k hi, i lo, i hi)
+ *               for draw k (0-based) of trajectory i (0-based within its network)
+ *   uniforms    r1 = (((o1<<32|o0) >> 11) + 1) 2^-53 in (0,1],  r2 = ((o3<<32|o2) >> 11) 2^-53
+ *   time        tau = neglog(r1) / a0; neglog is the atanh-series -ln with fixed roundings
+ *   selection   u = r2 * a0; smallest j with S_j > u, else the largest j with a_j > 0
+ *   horizon     events with t_next > t_end are not applied; a0 == 0 is absorbing (no draw)
+ *   alignment   right-continuous: x(t_g) includes every event with t_e <= t_g
+ *   reduction   unbiased variance (divide by N - 1; 0 when N == 1)
+ *
+ * Conventions:
+ *   - Every function returns an ssa_status; on failure ssa_last_error() (thread-local)
+ *     describes it.  No C++ exception crosses this boundary.
+ *   - The caller owns every buffer it passes.  The library owns model and batch handles,
+ *     released by the matching *_destroy (NULL is accepted and ignored).
+ *   - Host pointers ("host") are read or written synchronously.  Device pointers ("device")
+ *     must be device memory on the current HIP device; *_device calls are asynchronous on
+ *     the given hipStream_t (NULL = the null stream) unless stats is non-NULL, in which case
+ *     the call waits for the stream and fills stats.
+ *   - Layouts are row-major: [G*S] means index g*S + s.
+ */
+#ifndef SSA_H
+#define SSA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SSA_OK = 0,
+    SSA_E_INVALID = 1,      /* bad argument: sizes, coefficients, rates, grid, NULL pointer */
+    SSA_E_NOMEM = 2,        /* device or host allocation failed */
+    SSA_E_DEVICE = 3,       /* a HIP call failed (message in ssa_last_error) */
+    SSA_E_OVERFLOW = 4,     /* a species count left the int32 range in some trajectory */
+    SSA_E_EVENT_LIMIT = 5,  /* a trajectory reached max_events before t_end */
+    SSA_E_UNSUPPORTED = 6   /* valid request outside what this build implements */
+} ssa_status;
+
+typedef struct ssa_model ssa_model;
+typedef struct ssa_batch ssa_batch;
+
+/* Optional per-grid-point histogram of one species: bin = clamp((x - lo) div width, 0,
+ * nbins - 1); counts are exact.  Output layout [G*nbins] uint32. */
+typedef struct {
+    int32_t species;
+    int32_t lo;
+    int32_t width;   /* > 0 */
+    int32_t nbins;   /* 1..4096 */
+} ssa_hist_spec;
+
+/* Filled when a non-NULL pointer is passed (the call then synchronises). */
+typedef struct {
+    uint64_t events;      /* events applied with t <= t_end, summed over trajectories */
+    uint64_t max_steps;   /* largest per-trajectory event count */
+    uint32_t flags;       /* bit 0: overflow seen, bit 1: event limit reached */
+    float kernel_ms;      /* device time of the simulation kernel(s) */
+} ssa_stats;
+
+/* Model (Section 3.2 model format).
+ *   n_species S >= 1, n_reactions M >= 1 (M <= 4096, S <= 1024)
+ *   reactants [M*S] host: coefficients >= 0, sum per reaction <= 2 (order <= 2)
+ *   products  [M*S] host: coefficients >= 0 (e.g. 200), each <= 2^20
+ *   rates     [M]   host: stochastic rate constants c_j, finite, >= 0
+ *   x0        [S]   host: initial counts >= 0
+ * The arrays are copied (to the current device); the handle is immutable and may be shared
+ * by threads that use the same device.  Errors: SSA_E_INVALID, SSA_E_NOMEM, SSA_E_DEVICE. */
+ssa_status ssa_model_create(int32_t n_species, int32_t n_reactions, const int32_t *reactants,
+                            const int32_t *products, const double *rates, const int32_t *x0,
+                            ssa_model **out);
+void ssa_model_destroy(ssa_model *model);
+
+/* Host convenience (synchronous): n_traj trajectories 0..n_traj-1 on [0, t_end], grid
+ * [n_grid] host (non-decreasing, inside [0, t_end]), outputs mean and var [G*S] host.
+ * stats may be NULL.  Errors: SSA_E_INVALID, SSA_E_NOMEM, SSA_E_DEVICE, SSA_E_OVERFLOW,
+ * SSA_E_EVENT_LIMIT (outputs undefined on error). */
+ssa_status ssa_run(const ssa_model *model, int64_t n_traj, double t_end, const double *grid,
+                   int32_t n_grid, uint64_t seed, double *mean, double *var, ssa_stats *stats);
+
+/* Device form.  rates: [M] device, overrides the model's rate constants (NULL = model's).
+ * grid [G] device; mean, var [G*S] device; hist + d_hist [G*nbins] device (both NULL for
+ * none).  max_events: per-trajectory cap (0 = 2^62).  Asynchronous on stream when stats is
+ * NULL: an overflow or event-limit condition is then only reported by a later call with
+ * stats, so pass stats when the model may overflow.  The grid is validated on the device
+ * side only in the sense that a non-monotone grid gives undefined results; use ssa_run for
+ * checked host grids. */
+ssa_status ssa_run_device(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
+                          const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events,
+                          double *mean, double *var, const ssa_hist_spec *hist, uint32_t *d_hist,
+                          void *stream, ssa_stats *stats);
+
+/* Likelihood-ratio gradient of a loss L(mean) with respect to theta_j = ln c_j, by
+ * re-simulating the same trajectories (same seed, same Philox counters):
+ *   grad_j = sum_{g,s} w_{g,s} (1/N) sum_i (X^i_s(t_g) - mhat_{g,s}) (n^i_j(t_g) - A^i_j(t_g))
+ * with n_j the firing count and A_j the integrated propensity.  All pointers device:
+ * rates [M] (NULL = model's), grid [G], w [G*S] (dL/dmean), mhat [G*S] (centring, usually
+ * the forward mean), grad [M] output.  Supports M <= 16.  Same status codes as
+ * ssa_run_device (SSA_E_UNSUPPORTED above 16 reactions). */
+ssa_status ssa_backward_device(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
+                               const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events,
+                               const double *w, const double *mhat, double *grad, void *stream,
+                               ssa_stats *stats);
+
+/* Per-trajectory record of trajectories traj_begin .. traj_begin+count-1 (synchronous, all
+ * pointers host): states [count*G*S] int32 at the grid points, events [count], draws
+ * [count] (Philox blocks consumed), t_last [count] (time of the last applied event, 0 if
+ * none), n_fired [count*M] and a_int [count*M] (integral of a_j over [0, t_end]) may be
+ * NULL.  rates [M] host or NULL.  For the parity tests against the CPU oracle. */
+ssa_status ssa_record(const ssa_model *model, const double *rates, int64_t traj_begin, int64_t count,
+                      double t_end, const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events,
+                      int32_t *states, uint64_t *events, uint64_t *draws, double *t_last,
+                      int64_t *n_fired, double *a_int);
+
+/* Batched form (Section 3.2, parameter-swept simulations in one call): n_models networks,
+ * each with its own trajectory count, horizon, grid (host [n_grid[b]]) and seed; trajectory
+ * i of network b uses the same counters as ssa_run on that network alone, so the results
+ * equal the per-network runs.  All networks run in one persistent work-stealing launch.
+ * The handle owns the device copies of the grids and its scratch memory. */
+ssa_status ssa_batch_create(int32_t n_models, const ssa_model *const *models, const int64_t *n_traj,
+                            const double *t_end, const double *const *grids, const int32_t *n_grid,
+                            const uint64_t *seeds, ssa_batch **out);
+/* means[b], vars[b]: device pointers [G_b * S_b].  Asynchronous unless stats != NULL. */
+ssa_status ssa_batch_run(ssa_batch *batch, double *const *means, double *const *vars, void *stream,
+                         ssa_stats *stats);
+void ssa_batch_destroy(ssa_batch *batch);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char *ssa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSA_H */

@@ -1,0 +1,1046 @@
+// ssa_api.hip -- host runtime behind include/ssa.h: validation, device layout of a model,
+// per-network kernel specialisation (run-time compilation), work lists, launches,
+// finalize and error reporting.
+#include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ssa.h"
+#include "ssa_kernels.hpp"
+
+using namespace ssa;
+
+namespace {
+
+// Device sources of the run-time specialised kernels, embedded at build time.
+#pragma clang diagnostic push
+#pragma clang diagnostic ignored "-Wc23-extensions"
+const char kSrcDevice[] = {
+#embed "ssa_device.hpp"
+    , 0};
+const char kSrcSim[] = {
+#embed "ssa_sim.hpp"
+    , 0};
+const char kSrcJit[] = {
+#embed "ssa_jit.hpp"
+    , 0};
+#pragma clang diagnostic pop
+
+thread_local std::string g_err;
+
+ssa_status fail(ssa_status st, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess)                                                                      \
+            return fail(e_ == hipErrorOutOfMemory ? SSA_E_NOMEM : SSA_E_DEVICE, "%s: %s (%s:%d)",  \
+                        #expr, hipGetErrorString(e_), __FILE__, __LINE__);                         \
+    } while (0)
+
+constexpr int32_t kMaxSpecies = 1024;
+constexpr int32_t kMaxReactions = 4096;
+constexpr int32_t kMaxProduct = (1 << 19) - 4;
+constexpr uint64_t kDefaultMaxEvents = 1ull << 62;
+constexpr int32_t kJitMaxReactions = 32;     // specialised kernels keep a_j, S_j in registers
+constexpr int32_t kJitMaxSpecies = 64;
+
+// Device allocations made by one call, released on the stream in reverse order.
+struct StreamScratch {
+    hipStream_t stream;
+    std::vector<void *> ptrs;
+    explicit StreamScratch(hipStream_t s) : stream(s) {}
+    hipError_t alloc(void **p, size_t bytes) {
+        hipError_t e = hipMallocAsync(p, std::max<size_t>(bytes, 256), stream);
+        if (e == hipSuccess) ptrs.push_back(*p);
+        return e;
+    }
+    ~StreamScratch() {
+        for (auto it = ptrs.rbegin(); it != ptrs.rend(); ++it) (void)hipFreeAsync(*it, stream);
+    }
+};
+
+// Keep freed stream-ordered memory in the pool between calls instead of returning it.
+void keep_pool(int dev) {
+    static std::once_flag once[64];
+    if (dev < 0 || dev >= 64) return;
+    std::call_once(once[dev], [dev] {
+        hipMemPool_t pool;
+        if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+            uint64_t thr = ~0ull;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+        }
+    });
+}
+
+int cu_count(int dev) {
+    static int cache[64] = {0};
+    if (dev >= 0 && dev < 64 && cache[dev]) return cache[dev];
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    if (dev >= 0 && dev < 64) cache[dev] = n;
+    return n;
+}
+
+// Kernel choice for single-network launches: the kernel specialised to the network
+// (default) or the compiled table-driven one (SSA_KERNEL=generic).  Both give bit-identical
+// results; the variable only selects the implementation.
+bool prefer_generic() {
+    const char *e = std::getenv("SSA_KERNEL");
+    return e && std::strcmp(e, "generic") == 0;
+}
+
+// ---------------------------------------------------------------------------------------
+// Run-time specialisation
+// ---------------------------------------------------------------------------------------
+struct JitKernels {
+    hipModule_t module = nullptr;
+    hipFunction_t fwd = nullptr, fwd_atomic = nullptr, rec = nullptr, bwd = nullptr;
+};
+
+std::mutex g_jit_mu;
+std::map<std::pair<int, std::string>, std::shared_ptr<JitKernels>> g_jit_cache;
+
+std::string device_arch(int dev) {
+    hipDeviceProp_t p;
+    if (hipGetDeviceProperties(&p, dev) != hipSuccess) return "gfx950";
+    std::string a = p.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
+}
+
+}  // namespace
+
+struct ssa_model {
+    int32_t S = 0, M = 0, device = 0;
+    std::vector<int32_t> reac, prod;  // [M*S] as given
+    std::vector<double> rate;         // [M]
+    std::vector<int32_t> x0;          // [S]
+    int32_t m_pad = 0;                // generic tables padded to this many reactions
+    int32_t max_changes = 0;          // largest number of species one reaction changes
+    uint32_t *d_rx = nullptr;         // [m_pad] packed reactant encoding
+    double *d_rate = nullptr;         // [m_pad] zero-padded rates
+    int32_t *d_chg = nullptr;         // [M * kChg] packed changes
+    int32_t *d_x0 = nullptr;          // [S]
+    std::string jit_src;              // generated network description for specialisation
+};
+
+struct ssa_batch {
+    int32_t B = 0, device = 0, s_rows = 0, m_rows = 0, mm = 0;
+    std::vector<const ssa_model *> models;
+    std::vector<int64_t> n_traj;
+    std::vector<int32_t> G;
+    NetDev *d_nets = nullptr;
+    int32_t *d_item_net = nullptr;
+    int64_t *d_item_begin = nullptr;
+    int32_t *d_item_count = nullptr;
+    int32_t n_items = 0;
+    std::vector<double *> d_grids;
+    unsigned long long *d_D = nullptr;      // per network [G][S][2] sums then [G][S] high parts
+    size_t D_words = 0;
+    std::vector<size_t> D_off;
+    unsigned int *d_counter = nullptr;
+    unsigned long long *d_stats = nullptr;
+    GridInfo *d_ginfo = nullptr;
+};
+
+namespace {
+
+// FNV-1a over the embedded kernel sources.  Stamped into every generated program so a
+// compilation cache keyed on the main source text can never return code built from
+// different headers.
+uint64_t kernel_sources_hash() {
+    uint64_t h = 1469598103934665603ull;
+    for (const char *src : {kSrcDevice, kSrcSim, kSrcJit})
+        for (const char *c = src; *c; ++c) h = (h ^ (unsigned char)*c) * 1099511628211ull;
+    return h;
+}
+
+// Generated description of one network for ssa_jit.hpp.
+std::string generate_net_source(const ssa_model *m) {
+    const int32_t S = m->S, M = m->M;
+    std::string s;
+    char buf[512];
+    snprintf(buf, sizeof buf, "// kernel sources %016llx\n", (unsigned long long)kernel_sources_hash());
+    s += buf;
+    s += "#include \"ssa_device.hpp\"\nnamespace ssa_gen {\nstruct Net {\n";
+    snprintf(buf, sizeof buf, "    static constexpr int S = %d, M = %d;\n", S, M);
+    s += buf;
+    s += "    __device__ static __forceinline__ void init(int32_t (&x)[S]) {\n";
+    for (int32_t q = 0; q < S; ++q) {
+        snprintf(buf, sizeof buf, "        x[%d] = %d;\n", q, m->x0[q]);
+        s += buf;
+    }
+    s += "    }\n";
+    s += "    template <class R>\n    __device__ static __forceinline__ void props(const int32_t (&x)[S], R c, "
+         "double (&a)[M]) {\n";
+    for (int32_t j = 0; j < M; ++j) {
+        int32_t order = 0, sa = -1, sb = -1;
+        for (int32_t q = 0; q < S; ++q) {
+            const int32_t r = m->reac[(size_t)j * S + q];
+            for (int32_t t = 0; t < r; ++t) (sa < 0 ? sa : sb) = q;
+            order += r;
+        }
+        if (order == 0)
+            snprintf(buf, sizeof buf, "        a[%d] = c[%d] * 1.0;\n", j, j);
+        else if (order == 1)
+            snprintf(buf, sizeof buf, "        a[%d] = c[%d] * (double)x[%d];\n", j, j, sa);
+        else if (sa != sb)
+            snprintf(buf, sizeof buf, "        a[%d] = c[%d] * ((double)x[%d] * (double)x[%d]);\n", j, j, sa, sb);
+        else
+            snprintf(buf, sizeof buf,
+                     "        a[%d] = c[%d] * (((double)x[%d] * (double)max(x[%d] - 1, 0)) * 0.5);\n", j, j, sa, sa);
+        s += buf;
+    }
+    s += "    }\n";
+    s += "    __device__ static __forceinline__ void deltas(int32_t j, int32_t (&d)[S]) {\n";
+    for (int32_t q = 0; q < S; ++q) {
+        std::string e = "0";
+        for (int32_t j = M - 1; j >= 0; --j) {
+            const int32_t dl = m->prod[(size_t)j * S + q] - m->reac[(size_t)j * S + q];
+            if (!dl) continue;
+            snprintf(buf, sizeof buf, "(j == %d ? %d : %s)", j, dl, e.c_str());
+            e = buf;
+        }
+        s += "        d[" + std::to_string(q) + "] = " + e + ";\n";
+    }
+    s += "    }\n};\n}  // namespace ssa_gen\n#include \"ssa_jit.hpp\"\n";
+    return s;
+}
+
+ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out) {
+    const auto key = std::make_pair(dev, m->jit_src);
+    {
+        std::lock_guard<std::mutex> lk(g_jit_mu);
+        auto it = g_jit_cache.find(key);
+        if (it != g_jit_cache.end()) {
+            out = it->second;
+            return SSA_OK;
+        }
+    }
+    hiprtcProgram prog;
+    const char *hdrs[] = {kSrcDevice, kSrcSim, kSrcJit};
+    const char *names[] = {"ssa_device.hpp", "ssa_sim.hpp", "ssa_jit.hpp"};
+    if (hiprtcCreateProgram(&prog, m->jit_src.c_str(), "ssa_net.hip", 3, hdrs, names) != HIPRTC_SUCCESS)
+        return fail(SSA_E_DEVICE, "hiprtcCreateProgram failed");
+    const std::string arch = "--offload-arch=" + device_arch(dev);
+    const char *opts[] = {arch.c_str(), "-O3", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
+                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    const hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+    if (rc != HIPRTC_SUCCESS) {
+        size_t ls = 0;
+        hiprtcGetProgramLogSize(prog, &ls);
+        std::string log(ls + 1, '\0');
+        hiprtcGetProgramLog(prog, &log[0]);
+        hiprtcDestroyProgram(&prog);
+        return fail(SSA_E_DEVICE, "run-time compilation failed: %s", log.substr(0, 800).c_str());
+    }
+    size_t cs = 0;
+    hiprtcGetCodeSize(prog, &cs);
+    std::vector<char> code(cs);
+    hiprtcGetCode(prog, code.data());
+    hiprtcDestroyProgram(&prog);
+    auto k = std::make_shared<JitKernels>();
+    HIP_TRY(hipModuleLoadData(&k->module, code.data()));
+    HIP_TRY(hipModuleGetFunction(&k->fwd, k->module, "ssa_jit_fwd"));
+    HIP_TRY(hipModuleGetFunction(&k->fwd_atomic, k->module, "ssa_jit_fwd_atomic"));
+    HIP_TRY(hipModuleGetFunction(&k->rec, k->module, "ssa_jit_rec"));
+    HIP_TRY(hipModuleGetFunction(&k->bwd, k->module, "ssa_jit_bwd"));
+    std::lock_guard<std::mutex> lk(g_jit_mu);
+    auto ins = g_jit_cache.emplace(key, k);
+    out = ins.first->second;
+    return SSA_OK;
+}
+
+bool jit_eligible(const ssa_model *m) {
+    return !prefer_generic() && m->M <= kJitMaxReactions && m->S <= kJitMaxSpecies;
+}
+
+ssa_status validate_grid_host(const double *grid, int32_t G, double t_end) {
+    if (!(t_end >= 0.0) || !std::isfinite(t_end)) return fail(SSA_E_INVALID, "t_end must be finite and >= 0");
+    if (G <= 0 || !grid) return fail(SSA_E_INVALID, "grid must have at least one point");
+    for (int32_t g = 0; g < G; ++g) {
+        if (!(grid[g] >= 0.0) || !(grid[g] <= t_end))
+            return fail(SSA_E_INVALID, "grid[%d] = %g outside [0, t_end]", g, grid[g]);
+        if (g && !(grid[g] >= grid[g - 1])) return fail(SSA_E_INVALID, "grid decreases at %d", g);
+    }
+    return SSA_OK;
+}
+
+NetDev base_net(const ssa_model *m, const double *rates, int64_t n_traj, double t_end, const double *grid,
+                int32_t G, uint64_t seed, uint64_t max_events) {
+    NetDev n;
+    std::memset(&n, 0, sizeof n);
+    n.S = m->S;
+    n.M = m->M;
+    n.G = G;
+    n.n_traj = n_traj;
+    n.t_end = t_end;
+    n.key0 = (uint32_t)seed;
+    n.key1 = (uint32_t)(seed >> 32);
+    n.max_events = max_events ? max_events : kDefaultMaxEvents;
+    n.rx = m->d_rx;
+    n.rate = rates ? rates : m->d_rate;
+    n.chg = m->d_chg;
+    n.x0 = m->d_x0;
+    n.grid = grid;
+    return n;
+}
+
+// generic kernel: register slots for a_j and S_j (0 = two-pass variant for large M)
+int generic_mm(int32_t M) { return M <= 8 ? 8 : (M <= 16 ? 16 : (M <= 32 ? 32 : 0)); }
+
+int64_t grid_blocks(int per_cu, int dev, int64_t n_items) {
+    per_cu = std::max(per_cu, 1);
+    int64_t blocks = std::min<int64_t>((int64_t)per_cu * cu_count(dev), (n_items + 3) / 4);
+    return std::max<int64_t>(blocks, 1);
+}
+
+size_t generic_lds(const WorkList &wl) {
+    return (size_t)(wl.s_rows + 1) * kBlock * sizeof(int32_t) +
+           (size_t)(kBlock / kWave) * wl.m_rows * kChg * sizeof(int32_t);
+}
+
+template <int MODE, int MM, bool BATCH>
+hipError_t launch_generic_mm(const WorkList &wl, int64_t n_items, int dev, hipStream_t st) {
+    auto kern = sim_kernel<MODE, MM, BATCH>;
+    const size_t lds = generic_lds(wl);
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid_blocks(per_cu, dev, n_items)), dim3(kBlock), lds, st, wl);
+    return hipGetLastError();
+}
+
+template <int MODE, bool BATCH>
+hipError_t launch_generic(int mm, const WorkList &wl, int64_t n_items, int dev, hipStream_t st) {
+    if (mm == 8) return launch_generic_mm<MODE, 8, BATCH>(wl, n_items, dev, st);
+    if (mm == 16) return launch_generic_mm<MODE, 16, BATCH>(wl, n_items, dev, st);
+    if (mm == 32) return launch_generic_mm<MODE, 32, BATCH>(wl, n_items, dev, st);
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------------------
+// Forward launches (selective-memory windows, see ssa_sim.hpp)
+// ---------------------------------------------------------------------------------------
+
+// Bytes of LDS per wave for the window (SSA_WIN_BYTES overrides; 512 .. 16384).
+size_t window_budget() {
+    size_t b = 4096;
+    if (const char *e = std::getenv("SSA_WIN_BYTES")) b = (size_t)std::strtoull(e, nullptr, 10);
+    return std::min<size_t>(std::max<size_t>(b, 512), 16384);
+}
+
+// Window length in bins: the largest power of two whose S x 2 int64 words per bin fit the
+// budget, capped at 1024 and at the grid length rounded up to a power of two.
+int32_t window_bins(int32_t S, int32_t G) {
+    const size_t per_bin = (size_t)S * 2 * sizeof(long long);
+    int32_t W = 1;
+    while (W < 1024 && (size_t)(2 * W) * per_bin <= window_budget() && W < G) W *= 2;
+    return W;
+}
+
+// Flush target: "slab" (wave-private slabs, then a reduction), "atomic", or by size.
+int flush_choice() {
+    const char *e = std::getenv("SSA_FWD_FLUSH");
+    if (e && std::strcmp(e, "slab") == 0) return 1;
+    if (e && std::strcmp(e, "atomic") == 0) return 0;
+    return -1;
+}
+
+size_t slab_budget() {
+    size_t b = (size_t)1 << 30;
+    if (const char *e = std::getenv("SSA_SLAB_BYTES")) b = (size_t)std::strtoull(e, nullptr, 10);
+    return b;
+}
+
+struct FwdKernel {
+    bool jit = false;
+    hipFunction_t f_slab = nullptr, f_atomic = nullptr;     // run-time specialised
+    const void *g_slab = nullptr, *g_atomic = nullptr;      // generic
+    size_t lds = 0;
+};
+
+template <int MM, bool BATCH>
+void generic_fwd_kernels(FwdKernel &k) {
+    k.g_slab = (const void *)fwd_kernel<MM, BATCH, true>;
+    k.g_atomic = (const void *)fwd_kernel<MM, BATCH, false>;
+}
+
+template <bool BATCH>
+bool pick_generic_fwd(int mm, FwdKernel &k) {
+    if (mm == 8) generic_fwd_kernels<8, BATCH>(k);
+    else if (mm == 16) generic_fwd_kernels<16, BATCH>(k);
+    else if (mm == 32) generic_fwd_kernels<32, BATCH>(k);
+    else if (mm == 0) generic_fwd_kernels<0, BATCH>(k);
+    else return false;
+    return true;
+}
+
+hipError_t fwd_blocks(const FwdKernel &k, bool slab, int dev, int64_t n_items, int64_t &blocks) {
+    int per_cu = 0;
+    hipError_t e = k.jit ? hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, slab ? k.f_slab : k.f_atomic,
+                                                                                kBlock, k.lds)
+                         : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, slab ? k.g_slab : k.g_atomic, kBlock,
+                                                                        k.lds);
+    if (e != hipSuccess) return e;
+    blocks = grid_blocks(per_cu, dev, n_items);
+    return hipSuccess;
+}
+
+hipError_t fwd_launch(const FwdKernel &k, bool slab, int64_t blocks, WorkList &wl, hipStream_t st) {
+    if (k.jit) {
+        void *args[] = {&wl};
+        return hipModuleLaunchKernel(slab ? k.f_slab : k.f_atomic, (unsigned)blocks, 1, 1, kBlock, 1, 1,
+                                     (unsigned)k.lds, st, args, nullptr);
+    }
+    void *args[] = {&wl};
+    return hipLaunchKernel(slab ? k.g_slab : k.g_atomic, dim3((unsigned)blocks), dim3(kBlock), args, k.lds, st);
+}
+
+hipError_t launch_jit(hipFunction_t f, WorkList &wl, int64_t n_items, int dev, hipStream_t st) {
+    int per_cu = 0;
+    hipError_t e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBlock, 0);
+    if (e != hipSuccess) return e;
+    void *args[] = {&wl};
+    return hipModuleLaunchKernel(f, (unsigned)grid_blocks(per_cu, dev, n_items), 1, 1, kBlock, 1, 1, 0, st, args,
+                                 nullptr);
+}
+
+hipError_t launch_grid_info(const double *grid, int32_t G, double t_end, GridInfo *out, hipStream_t st) {
+    hipLaunchKernelGGL(grid_info_kernel, dim3(1), dim3(256), 0, st, grid, G, t_end, out);
+    return hipGetLastError();
+}
+
+// Host twin of grid_info_kernel for host grids.
+GridInfo host_grid_info(const double *grid, int32_t G, double t_end) {
+    GridInfo gi;
+    std::memset(&gi, 0, sizeof gi);
+    const double D = (double)(G - 1);
+    const double Tc[2] = {t_end, grid[G - 1]};
+    int ok[2] = {0, 0};
+    for (int c = 0; c < 2; ++c) {
+        ok[c] = (G >= 2 && Tc[c] > 0.0) ? 1 : 0;
+        for (int32_t g = 0; g < G && ok[c]; ++g)
+            if (grid[g] != (Tc[c] * (double)g) / D) ok[c] = 0;
+    }
+    gi.uniform = (ok[0] || ok[1]) ? 1 : 0;
+    gi.T = ok[0] ? Tc[0] : Tc[1];
+    gi.D = D;
+    gi.lo = grid[0];
+    const double span = grid[G - 1] - grid[0];
+    gi.scale = (G > 1 && span > 0.0) ? (double)(G - 1) / span : 0.0;
+    return gi;
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
+    const size_t words = (bytes + 7) / 8;
+    if (!words) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(zero_kernel, dim3(blocks), dim3(256), 0, st, (unsigned long long *)p, words);
+    return hipGetLastError();
+}
+
+ssa_status collect_stats(unsigned long long *d_stats, hipStream_t st, hipEvent_t e0, hipEvent_t e1,
+                         ssa_stats *stats) {
+    unsigned long long h[3] = {0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(h, d_stats, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (stats) {
+        stats->events = h[0];
+        stats->max_steps = h[1];
+        stats->flags = (uint32_t)h[2];
+        float ms = 0.f;
+        if (e0 && e1) (void)hipEventElapsedTime(&ms, e0, e1);
+        stats->kernel_ms = ms;
+    }
+    if (h[2] & kFlagOverflow) return fail(SSA_E_OVERFLOW, "a species count left the int32 range");
+    if (h[2] & kFlagEventLimit) return fail(SSA_E_EVENT_LIMIT, "a trajectory reached max_events before t_end");
+    return SSA_OK;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    bool make() { return hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess; }
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// Finalize of one network: exact prefix over the grid and the moments.
+hipError_t launch_finalize(const unsigned long long *D, const unsigned long long *Dhi, int32_t G, int32_t S,
+                           const int32_t *d_x0, int64_t n_traj, double *mean, double *var, hipStream_t st) {
+    hipLaunchKernelGGL(moment_final_kernel, dim3(S), dim3(1024), 0, st, D, Dhi, G, S, d_x0, n_traj, mean, var,
+                       (int64_t *)nullptr);
+    return hipGetLastError();
+}
+
+// Single-network launch of one simulation mode through the kernel specialised to the
+// network, or the generic one (which reads rates in zero-padded slots: a caller's rates
+// array is copied into a padded buffer first).
+ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_items, int dev, hipStream_t st,
+                         const double *user_rates, StreamScratch &scr) {
+    if (jit_eligible(m)) {
+        std::shared_ptr<JitKernels> k;
+        ssa_status s = get_jit(m, dev, k);
+        if (s) return s;
+        hipFunction_t f = mode == kRec ? k->rec : k->bwd;
+        HIP_TRY(launch_jit(f, wl, n_items, dev, st));
+        return SSA_OK;
+    }
+    const int mm = generic_mm(m->M);
+    if (mm == 0) return fail(SSA_E_UNSUPPORTED, "record / backward support at most %d reactions", kJitMaxReactions);
+    if (m->max_changes > kChg)
+        return fail(SSA_E_UNSUPPORTED, "the generic kernel handles at most %d changed species per reaction", kChg);
+    if (user_rates) {
+        void *pr = nullptr;
+        HIP_TRY(scr.alloc(&pr, sizeof(double) * m->m_pad));
+        HIP_TRY(launch_zero(pr, sizeof(double) * m->m_pad, st));
+        HIP_TRY(hipMemcpyAsync(pr, user_rates, sizeof(double) * m->M, hipMemcpyDeviceToDevice, st));
+        wl.net0.rate = (const double *)pr;
+    }
+    wl.s_rows = m->S;
+    wl.m_rows = m->M;
+    hipError_t e = mode == kRec ? launch_generic<kRec, false>(mm, wl, n_items, dev, st)
+                                : launch_generic<kBwd, false>(mm, wl, n_items, dev, st);
+    HIP_TRY(e);
+    return SSA_OK;
+}
+
+// Forward launch of one network.  D receives the [G][S][2] difference sums: from wave-
+// private slabs and a reduction when the slabs fit the budget, else by atomic flushes
+// into D directly.  Dhi ([G][S], high parts) must be zero on entry.
+ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int dev, hipStream_t st,
+                          const double *user_rates, StreamScratch &scr, unsigned long long *D, float *kernel_ms) {
+    const int32_t G = wl.net0.G, S = m->S;
+    FwdKernel k;
+    wl.win_bins = window_bins(S, G);
+    wl.win_words = wl.win_bins * S * 2;
+    const size_t win_bytes = (size_t)(kBlock / kWave) * wl.win_words * sizeof(long long);
+    if (jit_eligible(m)) {
+        std::shared_ptr<JitKernels> jk;
+        ssa_status s = get_jit(m, dev, jk);
+        if (s) return s;
+        k.jit = true;
+        k.f_slab = jk->fwd;
+        k.f_atomic = jk->fwd_atomic;
+        k.lds = win_bytes;
+    } else {
+        if (m->max_changes > kChg)
+            return fail(SSA_E_UNSUPPORTED, "the generic kernel handles at most %d changed species per reaction", kChg);
+        if (!pick_generic_fwd<false>(generic_mm(m->M), k)) return fail(SSA_E_UNSUPPORTED, "no kernel");
+        if (user_rates) {
+            void *pr = nullptr;
+            HIP_TRY(scr.alloc(&pr, sizeof(double) * m->m_pad));
+            HIP_TRY(launch_zero(pr, sizeof(double) * m->m_pad, st));
+            HIP_TRY(hipMemcpyAsync(pr, user_rates, sizeof(double) * m->M, hipMemcpyDeviceToDevice, st));
+            wl.net0.rate = (const double *)pr;
+        }
+        wl.s_rows = S;
+        wl.m_rows = m->M;
+        k.lds = generic_int_words(wl.s_rows, wl.m_rows) * sizeof(int32_t) + win_bytes;
+    }
+    const size_t cell_words = (size_t)G * S * 2;
+    int64_t blocks = 0;
+    HIP_TRY(fwd_blocks(k, true, dev, n_items, blocks));
+    const size_t slab_bytes = (size_t)blocks * (kBlock / kWave) * cell_words * sizeof(unsigned long long);
+    const int choice = flush_choice();
+    const bool slab = choice == 1 || (choice < 0 && slab_bytes <= slab_budget());
+    if (slab) {
+        void *sl = nullptr;
+        HIP_TRY(scr.alloc(&sl, slab_bytes));
+        HIP_TRY(launch_zero(sl, slab_bytes, st));
+        wl.slabs = (unsigned long long *)sl;
+    } else {
+        HIP_TRY(fwd_blocks(k, false, dev, n_items, blocks));
+        HIP_TRY(launch_zero(D, cell_words * sizeof(unsigned long long), st));
+    }
+    EventPair ev;
+    if (kernel_ms && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
+    HIP_TRY(fwd_launch(k, slab, blocks, wl, st));
+    if (kernel_ms && ev.b) HIP_TRY(hipEventRecord(ev.b, st));
+    if (slab) {
+        const int64_t words = (int64_t)cell_words;
+        hipLaunchKernelGGL(slab_reduce_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st,
+                           (const unsigned long long *)wl.slabs, blocks * (kBlock / kWave), words, D);
+        HIP_TRY(hipGetLastError());
+    }
+    if (kernel_ms && ev.b) {
+        HIP_TRY(hipEventSynchronize(ev.b));
+        (void)hipEventElapsedTime(kernel_ms, ev.a, ev.b);
+    }
+    return SSA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *ssa_last_error(void) { return g_err.c_str(); }
+
+ssa_status ssa_model_create(int32_t S, int32_t M, const int32_t *reac, const int32_t *prod, const double *rates,
+                            const int32_t *x0, ssa_model **out) {
+    if (!out) return fail(SSA_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (S <= 0 || M <= 0 || S > kMaxSpecies || M > kMaxReactions)
+        return fail(SSA_E_INVALID, "need 1 <= S <= %d and 1 <= M <= %d", kMaxSpecies, kMaxReactions);
+    if (!reac || !prod || !rates || !x0) return fail(SSA_E_INVALID, "NULL model array");
+    std::unique_ptr<ssa_model> m(new (std::nothrow) ssa_model);
+    if (!m) return fail(SSA_E_NOMEM, "host allocation failed");
+    m->S = S;
+    m->M = M;
+    m->reac.assign(reac, reac + (size_t)M * S);
+    m->prod.assign(prod, prod + (size_t)M * S);
+    m->rate.assign(rates, rates + M);
+    m->x0.assign(x0, x0 + S);
+    for (int32_t s = 0; s < S; ++s)
+        if (x0[s] < 0) return fail(SSA_E_INVALID, "x0[%d] < 0", s);
+    m->m_pad = ((M + kPadReactions - 1) / kPadReactions) * kPadReactions;
+    std::vector<uint32_t> rx(m->m_pad, 0u);          // padding: rows 0, 0 -> h = 1, rate 0
+    std::vector<double> rpad(m->m_pad, 0.0);
+    std::vector<int32_t> chg((size_t)M * kChg, 0);
+    for (int32_t j = 0; j < M; ++j) {
+        if (!(rates[j] >= 0.0) || !std::isfinite(rates[j]))
+            return fail(SSA_E_INVALID, "rate[%d] must be finite and >= 0", j);
+        rpad[j] = rates[j];
+        int32_t order = 0, sa = -1, sb = -1;
+        for (int32_t s = 0; s < S; ++s) {
+            const int32_t r = reac[(size_t)j * S + s], p = prod[(size_t)j * S + s];
+            if (r < 0 || p < 0 || p > kMaxProduct)
+                return fail(SSA_E_INVALID, "reaction %d: coefficients must be in [0, 2^19 - 4]", j);
+            order += r;
+            if (order > 2) return fail(SSA_E_INVALID, "reaction %d: order above 2", j);
+            for (int32_t q = 0; q < r; ++q) (sa < 0 ? sa : sb) = s;
+        }
+        uint32_t ra = 0, rb = 0, d = 0;    // LDS rows: 0 = all ones, species s = row s + 1
+        if (order >= 1) ra = (uint32_t)sa + 1;
+        if (order == 2) {
+            rb = (uint32_t)sb + 1;
+            d = (sa == sb) ? 1u : 0u;
+        }
+        rx[j] = ra | (rb << 12) | (d << 24);
+        int32_t nchg = 0;
+        for (int32_t s = 0; s < S; ++s) {
+            const int32_t dl = prod[(size_t)j * S + s] - reac[(size_t)j * S + s];
+            if (!dl) continue;
+            if (nchg < kChg) chg[(size_t)j * kChg + nchg] = (s + 1) | (dl << kRowBits);
+            ++nchg;
+        }
+        m->max_changes = std::max(m->max_changes, nchg);
+    }
+    if (m->max_changes > kChg && (M > kJitMaxReactions || S > kJitMaxSpecies))
+        return fail(SSA_E_UNSUPPORTED, "a reaction changes more than %d species in a network too large to specialise",
+                    kChg);
+    m->jit_src = generate_net_source(m.get());
+    hipError_t e = hipGetDevice(&m->device);
+    if (e == hipSuccess) e = hipMalloc(&m->d_rx, sizeof(uint32_t) * m->m_pad);
+    if (e == hipSuccess) e = hipMalloc(&m->d_rate, sizeof(double) * m->m_pad);
+    if (e == hipSuccess) e = hipMalloc(&m->d_chg, sizeof(int32_t) * M * kChg);
+    if (e == hipSuccess) e = hipMalloc(&m->d_x0, sizeof(int32_t) * S);
+    if (e == hipSuccess) e = hipMemcpy(m->d_rx, rx.data(), sizeof(uint32_t) * m->m_pad, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->d_rate, rpad.data(), sizeof(double) * m->m_pad, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->d_chg, chg.data(), sizeof(int32_t) * M * kChg, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(m->d_x0, m->x0.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        ssa_model_destroy(m.release());
+        return fail(e == hipErrorOutOfMemory ? SSA_E_NOMEM : SSA_E_DEVICE, "model upload: %s", hipGetErrorString(e));
+    }
+    *out = m.release();
+    return SSA_OK;
+}
+
+void ssa_model_destroy(ssa_model *m) {
+    if (!m) return;
+    if (m->d_rx) (void)hipFree(m->d_rx);
+    if (m->d_rate) (void)hipFree(m->d_rate);
+    if (m->d_chg) (void)hipFree(m->d_chg);
+    if (m->d_x0) (void)hipFree(m->d_x0);
+    delete m;
+}
+
+ssa_status ssa_run_device(const ssa_model *m, const double *rates, int64_t n_traj, double t_end, const double *grid,
+                          int32_t G, uint64_t seed, uint64_t max_events, double *mean, double *var,
+                          const ssa_hist_spec *hist, uint32_t *d_hist, void *stream, ssa_stats *stats) {
+    if (!m) return fail(SSA_E_INVALID, "model is NULL");
+    if (n_traj <= 0) return fail(SSA_E_INVALID, "n_traj must be > 0");
+    if (G <= 0 || !grid || !mean || !var) return fail(SSA_E_INVALID, "grid / mean / var missing");
+    if (!(t_end >= 0.0) || !std::isfinite(t_end)) return fail(SSA_E_INVALID, "t_end must be finite and >= 0");
+    if ((hist == nullptr) != (d_hist == nullptr)) return fail(SSA_E_INVALID, "hist spec and buffer go together");
+    if (hist && (hist->species < 0 || hist->species >= m->S || hist->width <= 0 || hist->nbins <= 0 ||
+                 hist->nbins > 4096))
+        return fail(SSA_E_INVALID, "bad histogram spec");
+    if (n_traj > ((int64_t)1 << 31) * kChunk) return fail(SSA_E_INVALID, "n_traj too large");
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    keep_pool(dev);
+    StreamScratch scr(st);
+
+    NetDev n = base_net(m, rates, n_traj, t_end, grid, G, seed, max_events);
+    const size_t cells = (size_t)G * m->S;
+    const size_t H_bytes = hist ? sizeof(int32_t) * (size_t)G * hist->nbins : 0;
+    void *D = nullptr, *Dhi = nullptr, *Hd = nullptr, *ctl = nullptr;
+    HIP_TRY(scr.alloc(&D, sizeof(unsigned long long) * 2 * cells));
+    HIP_TRY(scr.alloc(&Dhi, sizeof(unsigned long long) * cells));
+    HIP_TRY(scr.alloc(&ctl, 64 + sizeof(GridInfo)));
+    if (hist) HIP_TRY(scr.alloc(&Hd, H_bytes));
+    HIP_TRY(launch_zero(Dhi, sizeof(unsigned long long) * cells, st));
+    HIP_TRY(launch_zero(ctl, 64, st));
+    if (hist) HIP_TRY(launch_zero(Hd, H_bytes, st));
+    n.ginfo = (const GridInfo *)((char *)ctl + 64);
+    HIP_TRY(launch_grid_info(grid, G, t_end, (GridInfo *)n.ginfo, st));
+    n.D = (unsigned long long *)D;
+    n.Dhi = (unsigned long long *)Dhi;
+    if (hist) {
+        n.Hd = (int32_t *)Hd;
+        n.nb_hist = hist->nbins;
+        n.h_species = hist->species;
+        n.h_lo = hist->lo;
+        n.h_width = hist->width;
+    }
+    WorkList wl;
+    std::memset(&wl, 0, sizeof wl);
+    wl.net0 = n;
+    wl.range_begin = 0;
+    wl.range_end = n_traj;
+    const int64_t n_items = (n_traj + kChunk - 1) / kChunk;
+    wl.n_items = (int32_t)n_items;
+    wl.counter = (unsigned int *)ctl;
+    wl.stats = (unsigned long long *)((char *)ctl + 32);
+
+    float kms = 0.f;
+    ssa_status s = launch_forward(m, wl, n_items, dev, st, rates, scr, n.D, stats ? &kms : nullptr);
+    if (s) return s;
+    HIP_TRY(launch_finalize(n.D, n.Dhi, G, m->S, m->d_x0, n_traj, mean, var, st));
+    if (hist) {
+        const int32_t xv = m->x0[hist->species];
+        const int32_t ib = xv < hist->lo ? 0 : std::min((xv - hist->lo) / hist->width, hist->nbins - 1);
+        hipLaunchKernelGGL(hist_prefix_kernel, dim3(hist->nbins), dim3(1024), 0, st, (const int32_t *)Hd, G,
+                           hist->nbins, ib, n_traj, d_hist);
+        HIP_TRY(hipGetLastError());
+    }
+    if (stats) {
+        s = collect_stats(wl.stats, st, nullptr, nullptr, stats);
+        stats->kernel_ms = kms;
+        return s;
+    }
+    return SSA_OK;
+}
+
+ssa_status ssa_run(const ssa_model *m, int64_t n_traj, double t_end, const double *grid, int32_t G, uint64_t seed,
+                   double *mean, double *var, ssa_stats *stats) {
+    if (!m || !mean || !var) return fail(SSA_E_INVALID, "NULL argument");
+    ssa_status s = validate_grid_host(grid, G, t_end);
+    if (s) return s;
+    double *dg = nullptr, *dm = nullptr, *dv = nullptr;
+    const size_t cells = (size_t)G * m->S;
+    auto cleanup = [&] {
+        if (dg) (void)hipFree(dg);
+        if (dm) (void)hipFree(dm);
+        if (dv) (void)hipFree(dv);
+    };
+    hipError_t e = hipMalloc(&dg, sizeof(double) * G);
+    if (e == hipSuccess) e = hipMalloc(&dm, sizeof(double) * cells);
+    if (e == hipSuccess) e = hipMalloc(&dv, sizeof(double) * cells);
+    if (e == hipSuccess) e = hipMemcpy(dg, grid, sizeof(double) * G, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(e == hipErrorOutOfMemory ? SSA_E_NOMEM : SSA_E_DEVICE, "%s", hipGetErrorString(e));
+    }
+    ssa_stats local;
+    s = ssa_run_device(m, nullptr, n_traj, t_end, dg, G, seed, 0, dm, dv, nullptr, nullptr, nullptr,
+                       stats ? stats : &local);
+    if (s == SSA_OK) {
+        e = hipMemcpy(mean, dm, sizeof(double) * cells, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(var, dv, sizeof(double) * cells, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) s = fail(SSA_E_DEVICE, "%s", hipGetErrorString(e));
+    }
+    cleanup();
+    return s;
+}
+
+ssa_status ssa_backward_device(const ssa_model *m, const double *rates, int64_t n_traj, double t_end,
+                               const double *grid, int32_t G, uint64_t seed, uint64_t max_events, const double *w,
+                               const double *mhat, double *grad, void *stream, ssa_stats *stats) {
+    if (!m) return fail(SSA_E_INVALID, "model is NULL");
+    if (n_traj <= 0 || G <= 0 || !grid || !w || !mhat || !grad) return fail(SSA_E_INVALID, "bad argument");
+    if (!(t_end >= 0.0) || !std::isfinite(t_end)) return fail(SSA_E_INVALID, "t_end must be finite and >= 0");
+    if (m->M > kJitMaxReactions)
+        return fail(SSA_E_UNSUPPORTED, "backward supports at most %d reactions", kJitMaxReactions);
+    if (n_traj > ((int64_t)1 << 31) * kChunk) return fail(SSA_E_INVALID, "n_traj too large");
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    keep_pool(dev);
+    StreamScratch scr(st);
+    NetDev n = base_net(m, rates, n_traj, t_end, grid, G, seed, max_events);
+    void *gt = nullptr, *gt2 = nullptr, *ctl = nullptr, *wm = nullptr;
+    const size_t rows_bytes = sizeof(double) * (size_t)n_traj * m->M;
+    HIP_TRY(scr.alloc(&wm, sizeof(double) * 2 * (size_t)G * m->S));
+    HIP_TRY(scr.alloc(&gt, rows_bytes));
+    HIP_TRY(scr.alloc(&gt2, rows_bytes / 2 + sizeof(double) * m->M));
+    HIP_TRY(scr.alloc(&ctl, 64 + sizeof(GridInfo)));
+    HIP_TRY(launch_zero(ctl, 64, st));
+    n.ginfo = (const GridInfo *)((char *)ctl + 64);
+    HIP_TRY(launch_grid_info(grid, G, t_end, (GridInfo *)n.ginfo, st));
+    {
+        const int64_t cells = (int64_t)G * m->S;
+        hipLaunchKernelGGL(pack_wm_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, w, mhat, G, m->S,
+                           (double *)wm);
+        HIP_TRY(hipGetLastError());
+    }
+    n.wm = (const double *)wm;
+    n.gtraj = (double *)gt;
+    WorkList wl;
+    std::memset(&wl, 0, sizeof wl);
+    wl.net0 = n;
+    wl.range_begin = 0;
+    wl.range_end = n_traj;
+    const int64_t n_items = (n_traj + kChunk - 1) / kChunk;
+    wl.n_items = (int32_t)n_items;
+    wl.counter = (unsigned int *)ctl;
+    wl.stats = (unsigned long long *)((char *)ctl + 32);
+    EventPair ev;
+    if (stats && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
+    ssa_status s = launch_single(kBwd, m, wl, n_items, dev, st, rates, scr);
+    if (s) return s;
+    if (stats && ev.b) HIP_TRY(hipEventRecord(ev.b, st));
+    // fixed-order pairwise reduction of the per-trajectory rows
+    double *src = (double *)gt, *dst = (double *)gt2;
+    int64_t rows = n_traj;
+    while (rows > 1) {
+        const int64_t orows = (rows + 1) / 2;
+        const int64_t cells = orows * m->M;
+        hipLaunchKernelGGL(pair_sum_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, src, rows,
+                           m->M, dst);
+        HIP_TRY(hipGetLastError());
+        std::swap(src, dst);
+        rows = orows;
+    }
+    hipLaunchKernelGGL(scale_kernel, dim3(1), dim3(std::max(64, ((m->M + 63) / 64) * 64)), 0, st, src, m->M,
+                       1.0 / (double)n_traj, grad);
+    HIP_TRY(hipGetLastError());
+    if (stats) return collect_stats(wl.stats, st, ev.a, ev.b, stats);
+    return SSA_OK;
+}
+
+ssa_status ssa_record(const ssa_model *m, const double *rates, int64_t traj_begin, int64_t count, double t_end,
+                      const double *grid, int32_t G, uint64_t seed, uint64_t max_events, int32_t *states,
+                      uint64_t *events, uint64_t *draws, double *t_last, int64_t *n_fired, double *a_int) {
+    if (!m || !states || !events || !draws || !t_last) return fail(SSA_E_INVALID, "NULL argument");
+    if (traj_begin < 0 || count <= 0) return fail(SSA_E_INVALID, "bad trajectory range");
+    if (count > ((int64_t)1 << 31) * kChunk) return fail(SSA_E_INVALID, "count too large");
+    ssa_status s = validate_grid_host(grid, G, t_end);
+    if (s) return s;
+    if (m->M > kJitMaxReactions) return fail(SSA_E_UNSUPPORTED, "record supports at most %d reactions", kJitMaxReactions);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipStream_t st = nullptr;
+    StreamScratch scr(st);
+    const size_t sb = sizeof(int32_t) * (size_t)count * G * m->S;
+    void *d_grid = nullptr, *d_states = nullptr, *d_ev = nullptr, *d_dr = nullptr, *d_tl = nullptr, *d_nf = nullptr,
+         *d_ai = nullptr, *d_rates = nullptr, *ctl = nullptr;
+    HIP_TRY(scr.alloc(&d_grid, sizeof(double) * G));
+    HIP_TRY(scr.alloc(&d_states, sb));
+    HIP_TRY(scr.alloc(&d_ev, sizeof(uint64_t) * count));
+    HIP_TRY(scr.alloc(&d_dr, sizeof(uint64_t) * count));
+    HIP_TRY(scr.alloc(&d_tl, sizeof(double) * count));
+    HIP_TRY(scr.alloc(&d_nf, sizeof(int64_t) * count * m->M));
+    HIP_TRY(scr.alloc(&d_ai, sizeof(double) * count * m->M));
+    HIP_TRY(scr.alloc(&ctl, 64 + sizeof(GridInfo)));
+    if (rates) HIP_TRY(scr.alloc(&d_rates, sizeof(double) * m->M));
+    HIP_TRY(hipMemcpyAsync(d_grid, grid, sizeof(double) * G, hipMemcpyHostToDevice, st));
+    if (rates) HIP_TRY(hipMemcpyAsync(d_rates, rates, sizeof(double) * m->M, hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_zero(ctl, 64, st));
+    const GridInfo hgi = host_grid_info(grid, G, t_end);
+    HIP_TRY(hipMemcpyAsync((char *)ctl + 64, &hgi, sizeof hgi, hipMemcpyHostToDevice, st));
+    NetDev n = base_net(m, (const double *)d_rates, traj_begin + count, t_end, (const double *)d_grid, G, seed,
+                        max_events);
+    n.ginfo = (const GridInfo *)((char *)ctl + 64);
+    n.rec_begin = traj_begin;
+    n.rec_states = (int32_t *)d_states;
+    n.rec_events = (uint64_t *)d_ev;
+    n.rec_draws = (uint64_t *)d_dr;
+    n.rec_tlast = (double *)d_tl;
+    n.rec_nf = (int64_t *)d_nf;
+    n.rec_aint = (double *)d_ai;
+    WorkList wl;
+    std::memset(&wl, 0, sizeof wl);
+    wl.net0 = n;
+    wl.range_begin = traj_begin;
+    wl.range_end = traj_begin + count;
+    const int64_t n_items = (count + kChunk - 1) / kChunk;
+    wl.n_items = (int32_t)n_items;
+    wl.counter = (unsigned int *)ctl;
+    wl.stats = (unsigned long long *)((char *)ctl + 32);
+    s = launch_single(kRec, m, wl, n_items, dev, st, (const double *)d_rates, scr);
+    if (s) return s;
+    HIP_TRY(hipStreamSynchronize(st));
+    HIP_TRY(hipMemcpy(states, d_states, sb, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(events, d_ev, sizeof(uint64_t) * count, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(draws, d_dr, sizeof(uint64_t) * count, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(t_last, d_tl, sizeof(double) * count, hipMemcpyDeviceToHost));
+    if (n_fired) HIP_TRY(hipMemcpy(n_fired, d_nf, sizeof(int64_t) * count * m->M, hipMemcpyDeviceToHost));
+    if (a_int) HIP_TRY(hipMemcpy(a_int, d_ai, sizeof(double) * count * m->M, hipMemcpyDeviceToHost));
+    unsigned long long h[3] = {0, 0, 0};
+    HIP_TRY(hipMemcpy(h, (char *)ctl + 32, sizeof h, hipMemcpyDeviceToHost));
+    if (h[2] & kFlagOverflow) return fail(SSA_E_OVERFLOW, "a species count left the int32 range");
+    if (h[2] & kFlagEventLimit) return fail(SSA_E_EVENT_LIMIT, "a trajectory reached max_events before t_end");
+    return SSA_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Batched form: one persistent launch of the generic kernel over all networks.
+// ------------------------------------------------------------------------------------------
+ssa_status ssa_batch_create(int32_t B, const ssa_model *const *models, const int64_t *n_traj, const double *t_end,
+                            const double *const *grids, const int32_t *n_grid, const uint64_t *seeds,
+                            ssa_batch **out) {
+    if (!out) return fail(SSA_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (B <= 0 || !models || !n_traj || !t_end || !grids || !n_grid || !seeds) return fail(SSA_E_INVALID, "bad batch");
+    std::unique_ptr<ssa_batch, void (*)(ssa_batch *)> bt(new (std::nothrow) ssa_batch, ssa_batch_destroy);
+    if (!bt) return fail(SSA_E_NOMEM, "host allocation failed");
+    bt->B = B;
+    HIP_TRY(hipGetDevice(&bt->device));
+    std::vector<int32_t> item_net;
+    std::vector<int64_t> item_begin;
+    std::vector<int32_t> item_count;
+    size_t D_words = 0;
+    int32_t mmax = 0;
+    for (int32_t b = 0; b < B; ++b) {
+        const ssa_model *m = models[b];
+        if (!m) return fail(SSA_E_INVALID, "model %d is NULL", b);
+        if (n_traj[b] <= 0) return fail(SSA_E_INVALID, "n_traj[%d] must be > 0", b);
+        if (n_traj[b] > ((int64_t)1 << 31)) return fail(SSA_E_INVALID, "n_traj[%d] too large", b);
+        ssa_status s = validate_grid_host(grids[b], n_grid[b], t_end[b]);
+        if (s) return s;
+        if (m->max_changes > kChg)
+            return fail(SSA_E_UNSUPPORTED, "batched networks may change at most %d species per reaction", kChg);
+        mmax = std::max(mmax, m->M);
+        bt->s_rows = std::max(bt->s_rows, m->S);
+        bt->m_rows = std::max(bt->m_rows, m->M);
+        bt->models.push_back(m);
+        bt->n_traj.push_back(n_traj[b]);
+        bt->G.push_back(n_grid[b]);
+        bt->D_off.push_back(D_words);
+        D_words += (size_t)3 * n_grid[b] * m->S;
+        for (int64_t i = 0; i < n_traj[b]; i += kChunk) {
+            item_net.push_back(b);
+            item_begin.push_back(i);
+            item_count.push_back((int32_t)std::min<int64_t>(kChunk, n_traj[b] - i));
+        }
+    }
+    if (item_net.size() > (size_t)INT32_MAX) return fail(SSA_E_INVALID, "too many work items");
+    bt->mm = generic_mm(mmax);
+    bt->n_items = (int32_t)item_net.size();
+    bt->D_words = D_words;
+    for (int32_t b = 0; b < B; ++b) {
+        double *dg = nullptr;
+        HIP_TRY(hipMalloc(&dg, sizeof(double) * n_grid[b]));
+        bt->d_grids.push_back(dg);
+        HIP_TRY(hipMemcpy(dg, grids[b], sizeof(double) * n_grid[b], hipMemcpyHostToDevice));
+    }
+    HIP_TRY(hipMalloc(&bt->d_D, sizeof(unsigned long long) * D_words));
+    HIP_TRY(hipMalloc(&bt->d_counter, 64));
+    HIP_TRY(hipMalloc(&bt->d_nets, sizeof(NetDev) * B));
+    HIP_TRY(hipMalloc(&bt->d_ginfo, sizeof(GridInfo) * B));
+    HIP_TRY(hipMalloc(&bt->d_item_net, sizeof(int32_t) * bt->n_items));
+    HIP_TRY(hipMalloc(&bt->d_item_begin, sizeof(int64_t) * bt->n_items));
+    HIP_TRY(hipMalloc(&bt->d_item_count, sizeof(int32_t) * bt->n_items));
+    bt->d_stats = (unsigned long long *)((char *)bt->d_counter + 32);
+    std::vector<NetDev> nets;
+    std::vector<GridInfo> gis;
+    for (int32_t b = 0; b < B; ++b) {
+        NetDev n = base_net(models[b], nullptr, n_traj[b], t_end[b], bt->d_grids[b], n_grid[b], seeds[b], 0);
+        n.D = bt->d_D + bt->D_off[b];
+        n.Dhi = n.D + (size_t)2 * n_grid[b] * models[b]->S;
+        n.ginfo = bt->d_ginfo + b;
+        nets.push_back(n);
+        gis.push_back(host_grid_info(grids[b], n_grid[b], t_end[b]));
+    }
+    HIP_TRY(hipMemcpy(bt->d_nets, nets.data(), sizeof(NetDev) * B, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(bt->d_ginfo, gis.data(), sizeof(GridInfo) * B, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(bt->d_item_net, item_net.data(), sizeof(int32_t) * bt->n_items, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(bt->d_item_begin, item_begin.data(), sizeof(int64_t) * bt->n_items, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(bt->d_item_count, item_count.data(), sizeof(int32_t) * bt->n_items, hipMemcpyHostToDevice));
+    *out = bt.release();
+    return SSA_OK;
+}
+
+ssa_status ssa_batch_run(ssa_batch *bt, double *const *means, double *const *vars, void *stream, ssa_stats *stats) {
+    if (!bt || !means || !vars) return fail(SSA_E_INVALID, "NULL argument");
+    for (int32_t b = 0; b < bt->B; ++b)
+        if (!means[b] || !vars[b]) return fail(SSA_E_INVALID, "output %d is NULL", b);
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(launch_zero(bt->d_D, sizeof(unsigned long long) * bt->D_words, st));
+    HIP_TRY(launch_zero(bt->d_counter, 64, st));
+    WorkList wl;
+    std::memset(&wl, 0, sizeof wl);
+    wl.nets = bt->d_nets;
+    wl.item_net = bt->d_item_net;
+    wl.item_begin = bt->d_item_begin;
+    wl.item_count = bt->d_item_count;
+    wl.n_items = bt->n_items;
+    wl.s_rows = bt->s_rows;
+    wl.m_rows = bt->m_rows;
+    wl.counter = bt->d_counter;
+    wl.stats = bt->d_stats;
+    int32_t gmax = 0;
+    for (int32_t g : bt->G) gmax = std::max(gmax, g);
+    wl.win_bins = window_bins(bt->s_rows, gmax);
+    wl.win_words = wl.win_bins * bt->s_rows * 2;
+    FwdKernel k;
+    if (!pick_generic_fwd<true>(bt->mm, k)) return fail(SSA_E_UNSUPPORTED, "no kernel");
+    k.lds = generic_int_words(wl.s_rows, wl.m_rows) * sizeof(int32_t) +
+            (size_t)(kBlock / kWave) * wl.win_words * sizeof(long long);
+    int64_t blocks = 0;
+    HIP_TRY(fwd_blocks(k, false, bt->device, bt->n_items, blocks));
+    EventPair ev;
+    if (stats && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
+    HIP_TRY(fwd_launch(k, false, blocks, wl, st));
+    if (stats && ev.b) HIP_TRY(hipEventRecord(ev.b, st));
+    for (int32_t b = 0; b < bt->B; ++b) {
+        const ssa_model *m = bt->models[b];
+        const unsigned long long *D = bt->d_D + bt->D_off[b];
+        HIP_TRY(launch_finalize(D, D + (size_t)2 * bt->G[b] * m->S, bt->G[b], m->S, m->d_x0, bt->n_traj[b],
+                                means[b], vars[b], st));
+    }
+    if (stats) return collect_stats(bt->d_stats, st, ev.a, ev.b, stats);
+    return SSA_OK;
+}
+
+void ssa_batch_destroy(ssa_batch *bt) {
+    if (!bt) return;
+    for (double *p : bt->d_grids) (void)hipFree(p);
+    if (bt->d_D) (void)hipFree(bt->d_D);
+    if (bt->d_counter) (void)hipFree(bt->d_counter);
+    if (bt->d_nets) (void)hipFree(bt->d_nets);
+    if (bt->d_ginfo) (void)hipFree(bt->d_ginfo);
+    if (bt->d_item_net) (void)hipFree(bt->d_item_net);
+    if (bt->d_item_begin) (void)hipFree(bt->d_item_begin);
+    if (bt->d_item_count) (void)hipFree(bt->d_item_count);
+    delete bt;
+}
+
+}  // extern "C"

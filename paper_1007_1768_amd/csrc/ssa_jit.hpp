@@ -1,0 +1,81 @@
+// ssa_jit.hpp -- kernels specialised to one reaction network, compiled at run time.
+//
+// The host library generates `ssa_gen::Net` for a network (species count, reaction
+// count, initial state, the propensity expressions and the stoichiometric changes as
+// constants) and compiles this file with it.  Each lane then keeps its species counts in
+// registers with compile-time indices, evaluates every propensity as straight-line code
+// (only the rate constants are read, as scalars) and applies a reaction through per-species
+// select chains, so the event loop of ssa_sim.hpp runs without tables or LDS traffic.
+#pragma once
+
+#include "ssa_sim.hpp"
+
+namespace ssa {
+
+struct RegPolicy {
+    using Net = ssa_gen::Net;
+    int32_t x[Net::S];
+
+    __device__ __forceinline__ void switch_net(const NetDev &) {}
+    __device__ __forceinline__ void reset(const NetDev &) { Net::init(x); }
+    template <int MM>
+    __device__ __forceinline__ void eval(const NetDev &n, double (&a)[MM]) const {
+        static_assert(MM == Net::M, "one propensity slot per reaction");
+        Net::props(x, (const SSA_CONST double *)n.rate, a);
+    }
+    __device__ double one(const NetDev &n, int32_t j) const {
+        double a[Net::M];
+        Net::props(x, (const SSA_CONST double *)n.rate, a);
+        double v = 0.0;
+#pragma unroll
+        for (int q = 0; q < Net::M; ++q) v = (q == j) ? a[q] : v;
+        return v;
+    }
+    __device__ double total(const NetDev &) const { return 0.0; }
+    __device__ int32_t select(const NetDev &, double) const { return 0; }
+    template <class F>
+    __device__ __forceinline__ void for_each_species(F f) const {
+#pragma unroll
+        for (int s = 0; s < Net::S; ++s) f(s, x[s]);
+    }
+    template <class F>
+    __device__ __forceinline__ void apply(const NetDev &, int32_t sel, F f) {
+        int32_t dx[Net::S];
+        Net::deltas(sel, dx);
+#pragma unroll
+        for (int s = 0; s < Net::S; ++s) {
+            if (dx[s] != 0) {
+                const int32_t xo = x[s];
+                const int32_t xn = xo + dx[s];
+                x[s] = xn;
+                f(s, xo, xn);
+            }
+        }
+    }
+};
+
+}  // namespace ssa
+
+// Forward pass: one selective-memory window of wl.win_words int64 per wave in dynamic LDS;
+// flushes into wave-private slabs (ssa_jit_fwd) or atomically into the totals (_atomic).
+extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd(ssa::WorkList wl) {
+    extern __shared__ long long ssa_win[];
+    ssa::RegPolicy p;
+    ssa::sim_fwd<ssa_gen::Net::M, false, true>(wl, p, ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
+}
+
+extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd_atomic(ssa::WorkList wl) {
+    extern __shared__ long long ssa_win[];
+    ssa::RegPolicy p;
+    ssa::sim_fwd<ssa_gen::Net::M, false, false>(wl, p, ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
+}
+
+extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_rec(ssa::WorkList wl) {
+    ssa::RegPolicy p;
+    ssa::sim_loop<ssa::kRec, ssa_gen::Net::M, false>(wl, p);
+}
+
+extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_bwd(ssa::WorkList wl) {
+    ssa::RegPolicy p;
+    ssa::sim_loop<ssa::kBwd, ssa_gen::Net::M, false>(wl, p);
+}

@@ -1,0 +1,364 @@
+// ssa_kernels.hpp -- compiled kernels for gfx950: the generic (table-driven) simulation
+// kernel used for batched many-network launches, the grid description, the exact
+// finalize of the grid moments (slab sum, prefix over the grid, one rounding per moment),
+// the histogram prefix and the fixed-order gradient reduction.
+//
+// The generic policy keeps each lane's species counts in LDS columns x[row * 256 + tid]
+// (row 0 is all ones, species s in row s + 1): a propensity reads one uniform row, all 64
+// lanes of the wave hit consecutive words (conflict-free), and an update writes only the
+// changed rows.  Reactions are evaluated branch-free from a packed encoding,
+//   h = (x[a] * max(x[b] - d, 0)) * f,
+// with the all-ones row standing in for missing reactants:
+//   0 -> ...   a = b = 0,   d = 0, f = 1       A -> ...   a = A+1, b = 0, d = 0, f = 1
+//   A + B      a = A+1, b = B+1, d = 0, f = 1  2A -> ...  a = b = A+1, d = 1, f = 1/2
+// packed as a | b << 12 | d << 24.  f is 1 or 1/2 and multiplies exactly, so h is the
+// integer pair count rounded once, as the contract requires.  The tables are padded with
+// zero-rate entries so the unrolled loops need no per-reaction branches.
+// Changes of reaction j: kChg slots chg[j * kChg + i] = row | delta << 12 (delta signed,
+// |delta| < 2^19); an empty slot is 0.
+#pragma once
+
+#include "ssa_sim.hpp"
+
+namespace ssa {
+
+constexpr int kChg = 4;
+constexpr int32_t kRowBits = 12;
+constexpr int kPadReactions = 32;    // generic tables are padded to a multiple of this
+
+__host__ __device__ __forceinline__ int32_t chg_row(int32_t c) { return c & ((1 << kRowBits) - 1); }
+__host__ __device__ __forceinline__ int32_t chg_delta(int32_t c) { return c >> kRowBits; }
+
+__device__ __forceinline__ double packed_propensity(uint32_t code, double c, const int32_t *xc) {
+    const int32_t ra = (int32_t)(code & 0xfffu), rb = (int32_t)((code >> 12) & 0xfffu);
+    const int32_t d = (int32_t)(code >> 24);
+    const int32_t xa = xc[ra * kBlock];
+    const int32_t xb = max(xc[rb * kBlock] - d, 0);
+    const double f = d ? 0.5 : 1.0;
+    return c * (((double)xa * (double)xb) * f);
+}
+
+struct LdsPolicy {
+    int32_t *xc;      // this lane's column: row r at xc[r * kBlock]
+    int32_t *wchg;    // this wave's change table
+    int32_t S;
+
+    __device__ void switch_net(const NetDev &n) {
+        const uint32_t lane = __lane_id();
+        for (int32_t q = lane; q < n.M * kChg; q += kWave) wchg[q] = n.chg[q];
+        S = wave_uniform(n.S);
+    }
+    __device__ void reset(const NetDev &n) {
+        const SSA_CONST int32_t *x0 = (const SSA_CONST int32_t *)n.x0;
+        for (int32_t s = 0; s < S; ++s) xc[(s + 1) * kBlock] = x0[s];
+    }
+    template <int MM>
+    __device__ __forceinline__ void eval(const NetDev &n, double (&a)[MM]) const {
+        const SSA_CONST uint32_t *rx = (const SSA_CONST uint32_t *)n.rx;
+        const SSA_CONST double *rate = (const SSA_CONST double *)n.rate;
+#pragma unroll
+        for (int j = 0; j < MM; ++j) a[j] = packed_propensity(rx[j], rate[j], xc);
+    }
+    __device__ double one(const NetDev &n, int32_t j) const {
+        return packed_propensity(((const SSA_CONST uint32_t *)n.rx)[j], ((const SSA_CONST double *)n.rate)[j], xc);
+    }
+    __device__ double total(const NetDev &n) const {
+        const SSA_CONST uint32_t *rx = (const SSA_CONST uint32_t *)n.rx;
+        const SSA_CONST double *rate = (const SSA_CONST double *)n.rate;
+        double acc = packed_propensity(rx[0], rate[0], xc);
+        for (int32_t j = 1; j < n.M; ++j) acc = acc + packed_propensity(rx[j], rate[j], xc);
+        return acc;
+    }
+    // count of partial sums S_j <= u, recomputing S_j exactly as total() did
+    __device__ int32_t select(const NetDev &n, double u) const {
+        const SSA_CONST uint32_t *rx = (const SSA_CONST uint32_t *)n.rx;
+        const SSA_CONST double *rate = (const SSA_CONST double *)n.rate;
+        double acc = packed_propensity(rx[0], rate[0], xc);
+        int32_t cnt = acc <= u ? 1 : 0;
+        for (int32_t j = 1; j < n.M; ++j) {
+            acc = acc + packed_propensity(rx[j], rate[j], xc);
+            cnt += acc <= u ? 1 : 0;
+        }
+        return cnt;
+    }
+    template <class F>
+    __device__ __forceinline__ void for_each_species(F f) const {
+        for (int32_t s = 0; s < S; ++s) f(s, xc[(s + 1) * kBlock]);
+    }
+    template <class F>
+    __device__ __forceinline__ void apply(const NetDev &, int32_t sel, F f) {
+        const int4 cq = *(const int4 *)(wchg + sel * kChg);
+        const int32_t cs[kChg] = {cq.x, cq.y, cq.z, cq.w};
+#pragma unroll
+        for (int q = 0; q < kChg; ++q) {
+            const int32_t r = chg_row(cs[q]), dl = chg_delta(cs[q]);
+            if (dl == 0) continue;
+            const int32_t xo = xc[r * kBlock];
+            const int32_t xn = xo + dl;
+            xc[r * kBlock] = xn;
+            f(r - 1, xo, xn);
+        }
+    }
+};
+
+// LDS per block: rows [s_rows + 1][kBlock] int32 (row 0 all ones, species s in row s + 1),
+// then one change table per wave of m_rows * kChg int32, then (forward) one selective-
+// memory window per wave of win_words int64.
+__device__ __forceinline__ void generic_setup(const WorkList &wl, int32_t *lds, LdsPolicy &p) {
+    p.xc = lds + threadIdx.x;
+    p.wchg = lds + (wl.s_rows + 1) * kBlock + (threadIdx.x / kWave) * wl.m_rows * kChg;
+    p.S = 0;
+    p.xc[0] = 1;
+}
+
+__host__ __device__ __forceinline__ size_t generic_int_words(int32_t s_rows, int32_t m_rows) {
+    const size_t w = (size_t)(s_rows + 1) * kBlock + (size_t)(kBlock / kWave) * m_rows * kChg;
+    return (w + 1) & ~(size_t)1;   // 8-byte alignment of the windows that follow
+}
+
+template <int MODE, int MM, bool BATCH>
+__global__ void __launch_bounds__(kBlock) sim_kernel(WorkList wl) {
+    extern __shared__ int32_t lds_x[];
+    LdsPolicy p;
+    generic_setup(wl, lds_x, p);
+    sim_loop<MODE, MM, BATCH>(wl, p);
+}
+
+template <int MM, bool BATCH, bool SLAB>
+__global__ void __launch_bounds__(kBlock) fwd_kernel(WorkList wl) {
+    extern __shared__ int32_t lds_x[];
+    LdsPolicy p;
+    generic_setup(wl, lds_x, p);
+    long long *win = (long long *)(lds_x + generic_int_words(wl.s_rows, wl.m_rows)) +
+                     (size_t)(threadIdx.x / kWave) * wl.win_words;
+    sim_fwd<MM, BATCH, SLAB>(wl, p, win);
+}
+
+// Backward input rows [G][2S]: w_g followed by mhat_g, so one crossing reads one row.
+__global__ void pack_wm_kernel(const double *__restrict__ w, const double *__restrict__ mhat, int32_t G, int32_t S,
+                               double *__restrict__ wm) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)G * S) return;
+    const int64_t g = idx / S, s = idx % S;
+    wm[g * 2 * S + s] = w[idx];
+    wm[g * 2 * S + S + s] = mhat[idx];
+}
+
+// Grid description of a device grid: uniform if t_g == fl(fl(T g) / D) for all g with
+// D = G - 1 and T either t_end or t_{G-1} (first that fits), else general; plus the affine
+// guess.  One block of 256 threads.
+__global__ void __launch_bounds__(256) grid_info_kernel(const double *__restrict__ grid, int32_t G, double t_end,
+                                                        GridInfo *__restrict__ out) {
+    __shared__ int bad[2];
+    if (threadIdx.x < 2) bad[threadIdx.x] = 0;
+    __syncthreads();
+    const double D = (double)(G - 1);
+    const double Tc[2] = {t_end, grid[G - 1]};
+    for (int c = 0; c < 2; ++c) {
+        int mine = (G < 2 || !(Tc[c] > 0.0)) ? 1 : 0;
+        for (int32_t g = threadIdx.x; g < G && !mine; g += blockDim.x)
+            if (grid[g] != (Tc[c] * (double)g) / D) mine = 1;
+        if (mine) atomicOr(&bad[c], 1);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        GridInfo gi;
+        gi.uniform = (!bad[0] || !bad[1]) ? 1 : 0;
+        gi.T = !bad[0] ? Tc[0] : Tc[1];
+        gi.D = D;
+        gi.lo = grid[0];
+        const double span = grid[G - 1] - grid[0];
+        gi.scale = (G > 1 && span > 0.0) ? (double)(G - 1) / span : 0.0;
+        gi.pad = 0;
+        *out = gi;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Finalize: exact integer totals of sum x and sum x^2 at every grid point, then the
+// moments.
+// ---------------------------------------------------------------------------------------
+
+// 128-bit two's-complement helpers (hi:lo).
+struct i128s { uint64_t lo; int64_t hi; };
+
+__device__ __forceinline__ i128s i128_from(int64_t v) { return i128s{(uint64_t)v, v < 0 ? -1 : 0}; }
+__device__ __forceinline__ i128s i128_add(i128s x, i128s y) {
+    i128s r;
+    r.lo = x.lo + y.lo;
+    r.hi = x.hi + y.hi + (r.lo < x.lo ? 1 : 0);
+    return r;
+}
+__device__ __forceinline__ i128s i128_neg(i128s x) {
+    i128s r;
+    r.lo = ~x.lo + 1;
+    r.hi = ~x.hi + (r.lo == 0 ? 1 : 0);
+    return r;
+}
+// unsigned 64 x signed 128 -> signed 128 (low 128 bits; callers stay in range)
+__device__ __forceinline__ i128s i128_mul_u64(i128s x, uint64_t m) {
+    i128s r;
+    r.lo = x.lo * m;
+    r.hi = (int64_t)(__umul64hi(x.lo, m) + (uint64_t)x.hi * m);
+    return r;
+}
+__device__ __forceinline__ i128s i128_sq(int64_t v) {
+    const uint64_t a = (uint64_t)(v < 0 ? -v : v);
+    i128s r;
+    r.lo = a * a;
+    r.hi = (int64_t)__umul64hi(a, a);
+    return r;
+}
+// round-to-nearest conversion of a signed 128-bit integer to binary64
+__device__ __forceinline__ double i128_to_double(i128s x) {
+    bool neg = x.hi < 0;
+    if (neg) x = i128_neg(x);
+    const uint64_t hi = (uint64_t)x.hi, lo = x.lo;
+    double r;
+    if (hi == 0) {
+        r = (double)lo;
+    } else {
+        // keep 64 significant bits with a sticky bit, then one rounding by the conversion
+        if ((int64_t)hi < 0) {           // 2^127 and above: out of the range used here
+            r = __builtin_ldexp((double)hi, 64);
+            return neg ? -r : r;
+        }
+        const int lz = __clzll(hi);
+        const int sh = 64 - lz;                       // bits of hi that are used
+        const uint64_t top = (hi << lz) | (lo >> sh);
+        const uint64_t sticky = (lo << lz) != 0 ? 1u : 0u;
+        // top has 64 bits; fold the sticky bit into its lowest bit (below the 53 kept)
+        r = __builtin_ldexp((double)(top | sticky), sh);
+    }
+    return neg ? -r : r;
+}
+
+// Sum of the wave-private slabs: out[q] = sum over slabs of slabs[slab * words + q].
+__global__ void slab_reduce_kernel(const unsigned long long *__restrict__ slabs, int64_t n_slabs, int64_t words,
+                                   unsigned long long *__restrict__ out) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= words) return;
+    unsigned long long acc = 0;
+    for (int64_t k = 0; k < n_slabs; ++k) acc += slabs[k * words + q];
+    out[q] = acc;
+}
+
+// One block per species: inclusive prefix over the grid of the difference sums
+// D[g][s] = (sum nu, low sum (2x+nu)nu) and Dhi[g][s] (high parts, scaled by 2^24), giving
+// the exact totals
+//   Sx = N x0 + prefix(nu),   Sx2 = N x0^2 + prefix(low) + 2^24 prefix(high)
+// and from them the moments with one rounding each:
+//   mean = Sx / N,   var = (N Sx2 - Sx^2) / (N (N - 1))  (0 when N == 1).
+// Optionally also writes the totals as (Sx hi, Sx lo, Sx2 hi, Sx2 lo) 128-bit pairs.
+__global__ void __launch_bounds__(1024) moment_final_kernel(const unsigned long long *__restrict__ D,
+                                                            const unsigned long long *__restrict__ Dhi, int32_t G,
+                                                            int32_t S, const int32_t *__restrict__ x0,
+                                                            int64_t n_traj, double *__restrict__ mean,
+                                                            double *__restrict__ var, int64_t *__restrict__ sums) {
+    const int32_t s = blockIdx.x;
+    const int32_t nt = blockDim.x;
+    const int32_t per = (G + nt - 1) / nt;
+    const int32_t g0 = min(G, (int32_t)threadIdx.x * per), g1 = min(G, g0 + per);
+    int64_t s1 = 0, s2 = 0, s3 = 0;
+    for (int32_t g = g0; g < g1; ++g) {
+        s1 += (int64_t)D[((size_t)g * S + s) * 2];
+        s2 += (int64_t)D[((size_t)g * S + s) * 2 + 1];
+        s3 += (int64_t)Dhi[(size_t)g * S + s];
+    }
+    __shared__ int64_t sh[3][1024];
+    sh[0][threadIdx.x] = s1;
+    sh[1][threadIdx.x] = s2;
+    sh[2][threadIdx.x] = s3;
+    __syncthreads();
+    for (int off = 1; off < nt; off <<= 1) {
+        int64_t v1 = 0, v2 = 0, v3 = 0;
+        if ((int)threadIdx.x >= off) {
+            v1 = sh[0][threadIdx.x - off];
+            v2 = sh[1][threadIdx.x - off];
+            v3 = sh[2][threadIdx.x - off];
+        }
+        __syncthreads();
+        sh[0][threadIdx.x] += v1;
+        sh[1][threadIdx.x] += v2;
+        sh[2][threadIdx.x] += v3;
+        __syncthreads();
+    }
+    int64_t c1 = sh[0][threadIdx.x] - s1, c2 = sh[1][threadIdx.x] - s2, c3 = sh[2][threadIdx.x] - s3;
+    const int64_t xs = x0[s];
+    const int64_t base1 = n_traj * xs;
+    const i128s base2 = i128_mul_u64(i128_sq(xs), (uint64_t)n_traj);
+    const double dn = (double)n_traj;
+    const double dd = dn * (double)(n_traj - 1);
+    for (int32_t g = g0; g < g1; ++g) {
+        c1 += (int64_t)D[((size_t)g * S + s) * 2];
+        c2 += (int64_t)D[((size_t)g * S + s) * 2 + 1];
+        c3 += (int64_t)Dhi[(size_t)g * S + s];
+        const int64_t sx = base1 + c1;
+        const i128s sx2 = i128_add(i128_add(base2, i128_from(c2)), i128_mul_u64(i128_from(c3), 1ull << 24));
+        const size_t q = (size_t)g * S + s;
+        mean[q] = (double)sx / dn;
+        if (n_traj == 1) {
+            var[q] = 0.0;
+        } else {
+            const i128s num = i128_add(i128_mul_u64(sx2, (uint64_t)n_traj), i128_neg(i128_sq(sx)));
+            var[q] = i128_to_double(num) / dd;
+        }
+        if (sums) {
+            sums[4 * q + 0] = sx < 0 ? -1 : 0;
+            sums[4 * q + 1] = sx;
+            sums[4 * q + 2] = sx2.hi;
+            sums[4 * q + 3] = (int64_t)sx2.lo;
+        }
+    }
+}
+
+// Histogram: inclusive prefix over g of the bin differences plus N in the initial bin.
+__global__ void hist_prefix_kernel(const int32_t *__restrict__ Hd, int32_t G, int32_t nb, int32_t init_bin,
+                                   int64_t n_traj, uint32_t *__restrict__ out) {
+    const int32_t bin = blockIdx.x;
+    const int32_t nt = blockDim.x;
+    const int32_t per = (G + nt - 1) / nt;
+    const int32_t g0 = min(G, (int32_t)threadIdx.x * per), g1 = min(G, g0 + per);
+    int64_t s = 0;
+    for (int32_t g = g0; g < g1; ++g) s += Hd[(size_t)g * nb + bin];
+    __shared__ int64_t sh[1024];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < nt; off <<= 1) {
+        int64_t v = (int)threadIdx.x >= off ? sh[threadIdx.x - off] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t c = sh[threadIdx.x] - s + (bin == init_bin ? n_traj : 0);
+    for (int32_t g = g0; g < g1; ++g) {
+        c += Hd[(size_t)g * nb + bin];
+        out[(size_t)g * nb + bin] = (uint32_t)c;
+    }
+}
+
+// Fixed-order pairwise sum of the per-trajectory gradient rows, then the 1/N scale.
+// Stage: out[r][j] = in[2r][j] + in[2r+1][j] (odd tail copied).
+__global__ void pair_sum_kernel(const double *__restrict__ in, int64_t rows, int32_t M, double *__restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t orows = (rows + 1) / 2;
+    if (idx >= orows * M) return;
+    const int64_t r = idx / M;
+    const int32_t j = (int32_t)(idx % M);
+    const double v0 = in[(2 * r) * M + j];
+    out[idx] = (2 * r + 1 < rows) ? v0 + in[(2 * r + 1) * M + j] : v0;
+}
+
+__global__ void scale_kernel(const double *__restrict__ in, int32_t M, double scale, double *__restrict__ out) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < M) out[j] = in[j] * scale;
+}
+
+// Zero fill with plain stores (kept out of hipMemsetAsync so the launch sequence can be
+// captured in a graph).
+__global__ void zero_kernel(unsigned long long *__restrict__ p, size_t n_words) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0ull;
+}
+
+}  // namespace ssa

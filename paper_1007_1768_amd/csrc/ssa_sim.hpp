@@ -1,0 +1,658 @@
+// ssa_sim.hpp -- the per-lane event loop of the direct method (paper Section 2) with the
+// grid alignment of Section 3.2.1, shared by the compiled generic kernel and the kernels
+// specialised per network at run time.
+//
+// One lane runs one trajectory at a time.  A persistent grid of 256-lane workgroups pulls
+// work items (a network and a chunk of up to 64 trajectory indices) from a global
+// counter; each wave hands indices to its lanes as they finish, so lanes whose
+// trajectories end early are refilled instead of idling (trajectories end after very
+// different event counts).  A wave only switches network once all its lanes are idle, so
+// every reaction-table read stays wave-uniform.
+//
+// How a network's state is held (registers or LDS), how its propensities are formed and
+// how a reaction changes the state is delegated to a policy class:
+//   switch_net(n)                   the wave starts working on network n
+//   reset(n)                        start a trajectory at x0
+//   eval<MM>(n, a)                  a_j for j < MM (entries at or beyond n.M must be 0)
+//   one(n, j)                       a_j for a single reaction (rare path)
+//   total(n), select(n, u)          MM == 0 (many reactions): a0, and the count of partial
+//                                   sums <= u, each from a fresh pass over the reactions
+//   for_each_species(f)             f(s, x_s) for every species
+//   apply(n, sel, f)                apply reaction sel: f(s, x_old, x_new) per changed species
+//
+// Selective memory (Section 3.2.1) in difference form: the grid value x(t_g) of a
+// trajectory is x0 plus every change with t_e <= t_g, so an event at t_e contributes its
+// change nu and its change of x^2, (2x + nu) nu, to the first grid bin b with
+// t_b >= t_e; a prefix sum over the bins then gives sum x and sum x^2 at every grid point.
+// All of it is exact integer arithmetic, so the order of the additions does not matter
+// and the result is deterministic.
+//
+// The forward pass (sim_fwd) keeps these sums the way the paper's selective memory keeps
+// stream items: a wave simulates a generation of up to 64 trajectories and holds a
+// window of W grid bins in LDS that follows the wavefront of simulation time.  The window
+// starts at the smallest pending bin over the wave's lanes; a lane whose next event falls
+// beyond the window waits (it is ahead in simulation time, so it has slack), and bins
+// that every lane has passed are flushed out of LDS and the window slides on.  Flushes go
+// either to a slab of global memory private to the wave (plain coalesced read-modify-
+// writes, summed by a reduction kernel afterwards) or, for batched launches, into the
+// network's accumulators with atomic adds.
+#pragma once
+
+#include "ssa_device.hpp"
+
+#if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC_RTC__)
+#define SSA_CONST __attribute__((address_space(4)))
+#define SSA_GLOBAL __attribute__((address_space(1)))
+#else
+#define SSA_CONST
+#define SSA_GLOBAL
+#endif
+
+namespace ssa {
+
+constexpr int kBlock = 256;
+constexpr int kWave = 64;
+constexpr int kChunk = 64;         // trajectory indices per work item
+constexpr int kSmallD2 = 1 << 24;  // |(2x+nu)nu| below this goes whole to the low accumulator;
+                                   // larger values add their low 24 bits there and value >> 24
+                                   // to the high accumulator, so low words grow by < 2^24 per event
+
+enum Mode : int { kFwd = 0, kRec = 1, kBwd = 2 };
+
+enum Flags : uint32_t { kFlagOverflow = 1u, kFlagEventLimit = 2u };
+
+// Time grid description.  A grid with t_g = fl(fl(T g) / D) for every g (the uniform grid
+// of the workloads) is "uniform": its points are recomputed exactly from (T, D) instead of
+// being loaded, which keeps the event loop free of vector-memory loads.  Any other
+// non-decreasing grid is read from memory.
+struct GridInfo {
+    double T, D;        // uniform: t_g = (T * g) / D
+    double lo, scale;   // affine guess ceil((t - lo) * scale) of the first index >= t
+    int32_t uniform, pad;
+};
+
+// One network in a launch.  The reaction tables (rx, rate, chg) are read by the generic
+// policy only; run-time specialised kernels carry the structure as constants and read
+// just the rates.
+struct NetDev {
+    int32_t S, M, G, nb_hist;
+    int64_t n_traj;          // trajectories of this network in the run (partition sizes)
+    double t_end;
+    uint32_t key0, key1;     // Philox key = seed
+    uint64_t max_events;
+    const uint32_t *rx;      // [>= M] packed reactant encoding (generic policy)
+    const double *rate;      // [>= M] rate constants (zero-padded for the generic policy)
+    const int32_t *chg;      // [M * 4] packed changes (generic policy)
+    const int32_t *x0;       // [S]
+    const double *grid;
+    const GridInfo *ginfo;
+    // forward: difference sums [G][S][2] (atomic flush mode), high parts of large
+    // (2x+nu)nu contributions [G][S] (value >> 24, atomic), histogram diffs [G][nb]
+    unsigned long long *D;
+    unsigned long long *Dhi;
+    int32_t *Hd;
+    int32_t h_species, h_lo, h_width, pad0;
+    // record
+    int64_t rec_begin;
+    int32_t *rec_states;
+    uint64_t *rec_events, *rec_draws;
+    double *rec_tlast;
+    int64_t *rec_nf;
+    double *rec_aint;
+    // backward: rows [G][2S] = (w_g0..w_g,S-1, mhat_g0..mhat_g,S-1), per-trajectory rows [n_traj][M]
+    const double *wm;
+    double *gtraj;
+};
+
+// Work description.  A single-network launch passes its network by value (net0) and the
+// trajectory range [range_begin, range_end) cut into chunks of kChunk; a batched launch
+// passes a device table of networks and an explicit work-item list.
+struct WorkList {
+    NetDev net0;
+    int64_t range_begin, range_end;
+    const NetDev *nets;
+    const int32_t *item_net;     // [n_items]
+    const int64_t *item_begin;   // [n_items] first trajectory index of the chunk
+    const int32_t *item_count;   // [n_items]
+    int32_t n_items;
+    int32_t s_rows;              // species rows per block in LDS (generic policy)
+    int32_t m_rows;              // reactions per LDS change table (generic policy)
+    int32_t win_bins;            // forward: grid bins per wave window (power of two)
+    int32_t win_words;           // forward: 64-bit LDS words per wave window (win_bins * S_max * 2)
+    unsigned long long *slabs;   // forward, slab mode: [waves][G][S][2] wave-private sums
+    unsigned int *counter;       // work-item counter (zeroed before launch)
+    unsigned long long *stats;   // [0] events, [1] max steps, [2] flags
+};
+
+// Wave-uniform copies (scalar registers) of values every lane holds identically.
+__device__ __forceinline__ int32_t wave_uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t wave_uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t wave_uniform(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ __forceinline__ double wave_uniform(double v) {
+    return __longlong_as_double(wave_uniform((int64_t)__double_as_longlong(v)));
+}
+template <class T>
+__device__ __forceinline__ T *wave_uniform(T *p) {
+    return (T *)wave_uniform((int64_t)(uintptr_t)p);
+}
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    const uint32_t lane = __lane_id();
+    return lane ? (~0ull >> (64 - lane)) : 0ull;
+}
+
+// The current network.  Single-network launches read it from the kernel arguments; a
+// batched launch from the device table (scalar loads, indexed by the wave's network).
+// The Philox key is laundered once per event so its round-key schedule is recomputed
+// with scalar adds rather than pinned in scalar registers.
+template <bool BATCH>
+__device__ __forceinline__ NetDev current_net(const WorkList &wl, int32_t cur) {
+    NetDev n;
+    if (BATCH) n = ((const SSA_CONST NetDev *)wl.nets)[cur];
+    else n = wl.net0;
+    asm volatile("" : "+s"(n.key0), "+s"(n.key1));
+    return n;
+}
+
+// Grid state of the current network, held in wave-uniform registers.
+struct GridView {
+    const double *grid;
+    double T, D, lo, scale;
+    int32_t G, uniform;
+
+    __device__ __forceinline__ double at(int32_t g) const {
+        return uniform ? (T * (double)g) / D : ((const SSA_GLOBAL double *)grid)[g];
+    }
+    // First index b > g0 with t_b >= t, given t_{g0} < t (G if none); also returns t_b.
+    // The uniform and the memory variant are separate code paths so that the uniform one
+    // never waits on vector memory (which would also wait for the event's atomics).
+    template <bool UNIFORM>
+    __device__ __forceinline__ int32_t next_bin_impl(int32_t g0, double t, double &tb) const {
+        auto pt = [&](int32_t g) { return UNIFORM ? (T * (double)g) / D : ((const SSA_GLOBAL double *)grid)[g]; };
+        const double gf = ceil((t - lo) * scale);
+        int32_t b = gf <= (double)(g0 + 1) ? g0 + 1 : (gf >= (double)G ? G : (int32_t)gf);
+        double v = b < G ? pt(b) : __builtin_inf();
+        while (b < G && v < t) {
+            ++b;
+            v = b < G ? pt(b) : __builtin_inf();
+        }
+        while (b > g0 + 1) {
+            const double tp = pt(b - 1);
+            if (tp < t) break;
+            --b;
+            v = tp;
+        }
+        tb = v;
+        return b;
+    }
+    __device__ __forceinline__ int32_t next_bin(int32_t g0, double t, double &tb) const {
+        return uniform ? next_bin_impl<true>(g0, t, tb) : next_bin_impl<false>(g0, t, tb);
+    }
+};
+
+// The event loop.  MM is the number of propensity slots the policy evaluates (>= M), or 0
+// for networks too large to keep a_j and S_j in registers (forward only).
+// Record and backward passes: lanes are refilled as soon as their trajectory ends.
+template <int MODE, int MM, bool BATCH, class Policy>
+__device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
+    static_assert(MODE != kFwd && MM > 0, "record and backward need the per-reaction registers");
+    constexpr int MR = MM > 0 ? MM : 1;
+    const uint32_t lane = __lane_id();
+
+    // wave-uniform work state
+    int32_t cur = -1;
+    int64_t pool_next = 0, pool_end = 0;
+    int32_t pending = -1;
+    bool exhausted = false;
+    GridView gv;
+    gv.grid = nullptr;
+    gv.T = gv.D = gv.lo = gv.scale = 0.0;
+    gv.G = 0;
+    gv.uniform = 0;
+
+    // lane state
+    bool active = false;
+    int64_t traj = 0;
+    double t = 0.0;
+    uint64_t k = 0, ev = 0;
+    int32_t g = 0;
+    uint32_t ovf = 0;
+    uint32_t flags = 0;
+    unsigned long long tot_events = 0, max_steps = 0;
+    double a[MR];
+    double Ssum[MR];
+    double A[MODE == kFwd ? 1 : MR];
+    double nf[MODE == kFwd ? 1 : MR];
+    double gacc[MODE == kBwd ? MR : 1];
+
+    for (;;) {
+        // ---------------- refill idle lanes ----------------
+        const uint64_t idle = __ballot(!active);
+        if (idle) {
+            if (pool_next >= pool_end && !exhausted && pending < 0) {
+                int32_t item = 0;
+                if (lane == 0) item = (int32_t)atomicAdd(wl.counter, 1u);
+                item = wave_uniform(__shfl(item, 0));
+                if (item >= wl.n_items) exhausted = true; else pending = item;
+            }
+            if (pending >= 0) {
+                const int32_t b = BATCH ? wave_uniform(((const SSA_CONST int32_t *)wl.item_net)[pending]) : 0;
+                if (b == cur || idle == ~0ull) {
+                    if (BATCH) {
+                        pool_next = ((const SSA_CONST int64_t *)wl.item_begin)[pending];
+                        pool_end = pool_next + ((const SSA_CONST int32_t *)wl.item_count)[pending];
+                    } else {
+                        pool_next = wl.range_begin + (int64_t)pending * kChunk;
+                        pool_end = min(pool_next + (int64_t)kChunk, wl.range_end);
+                    }
+                    pool_next = wave_uniform(pool_next);
+                    pool_end = wave_uniform(pool_end);
+                    pending = -1;
+                    if (b != cur) {
+                        // switch network: the policy's per-wave tables and the grid view
+                        cur = b;
+                        const NetDev nn = current_net<BATCH>(wl, cur);
+                        p.switch_net(nn);
+                        const GridInfo gi = *(const SSA_CONST GridInfo *)nn.ginfo;
+                        gv.grid = wave_uniform(nn.grid);
+                        gv.T = wave_uniform(gi.T);
+                        gv.D = wave_uniform(gi.D);
+                        gv.lo = wave_uniform(gi.lo);
+                        gv.scale = wave_uniform(gi.scale);
+                        gv.G = wave_uniform(nn.G);
+                        gv.uniform = wave_uniform(gi.uniform);
+                    }
+                }
+            }
+            const int32_t n_idle = __popcll(idle);
+            if (!active && pool_next < pool_end) {
+                const int64_t mine = pool_next + __popcll(idle & lanemask_lt());
+                if (mine < pool_end) {
+                    const NetDev n = current_net<BATCH>(wl, cur);
+                    active = true;
+                    traj = mine;
+                    t = 0.0;
+                    k = 0;
+                    ev = 0;
+                    g = 0;
+                    ovf = 0;
+                    p.reset(n);
+                    if (MODE != kFwd) {
+#pragma unroll
+                        for (int j = 0; j < MM; ++j) { A[j] = 0.0; nf[j] = 0.0; }
+                    }
+                    if (MODE == kBwd) {
+#pragma unroll
+                        for (int j = 0; j < MM; ++j) gacc[j] = 0.0;
+                    }
+                }
+            }
+            pool_next = min(pool_next + (int64_t)n_idle, pool_end);
+        }
+        if (__ballot(active) == 0) {
+            if (exhausted && pending < 0) break;
+            continue;
+        }
+        if (!active) continue;
+
+        // ---------------- one event of the direct method ----------------
+        const NetDev n = current_net<BATCH>(wl, cur);
+        const int32_t M = n.M;
+        double acc;
+        if constexpr (MM > 0) {
+            p.template eval<MM>(n, a);
+            acc = a[0];
+            Ssum[0] = acc;
+#pragma unroll
+            for (int j = 1; j < MM; ++j) {
+                acc = acc + a[j];          // S_j = S_{j-1} + a_j; padded slots add +0
+                Ssum[j] = acc;
+            }
+        } else {
+            acc = p.total(n);
+        }
+        double tau = __builtin_inf();
+        double r2 = 0.0;
+        if (acc != 0.0) {
+            const u32x4 o = philox4x32_10((uint32_t)k, (uint32_t)(k >> 32), (uint32_t)traj,
+                                          (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
+            const double r1 = uniform_open0(o.v0, o.v1);
+            r2 = uniform_open1(o.v2, o.v3);
+            tau = neg_log(r1) / acc;
+            k = k + 1;
+        }
+        const double t_next = t + tau;
+
+        // grid points passed before the event: record / backward see the pre-event state
+        if (MODE == kRec) {
+            int32_t *row = n.rec_states + (size_t)(traj - n.rec_begin) * n.G * n.S;
+            while (g < n.G && gv.at(g) < t_next) {
+                p.for_each_species([&](int32_t s, int32_t xs) { row[(size_t)g * n.S + s] = xs; });
+                ++g;
+            }
+        } else if (MODE == kBwd) {
+            // all crossings of [t, t_next) share the state x and the score line
+            // z_j(t_g) = (n_j - A_j) - a_j (t_g - t): fold them into
+            //   alpha = sum_g phi_g,  beta = sum_g phi_g (t_g - t),  phi_g = sum_s w_gs (x_s - mhat_gs)
+            // and update the M accumulators once per interval.
+            if (g < n.G && gv.at(g) < t_next) {
+                double alpha = 0.0, beta = 0.0;
+                while (g < n.G) {
+                    const double tg = gv.at(g);
+                    if (!(tg < t_next)) break;
+                    const double *row = n.wm + (size_t)g * 2 * n.S;
+                    double phi = 0.0;
+                    p.for_each_species([&](int32_t s, int32_t xs) { phi = phi + row[s] * ((double)xs - row[n.S + s]); });
+                    alpha = alpha + phi;
+                    beta = beta + phi * (tg - t);
+                    ++g;
+                }
+#pragma unroll
+                for (int j = 0; j < MM; ++j) gacc[j] = gacc[j] + ((nf[j] - A[j]) * alpha - a[j] * beta);
+            }
+        }
+
+        bool finish = t_next > n.t_end;
+        if (!finish && ev >= n.max_events) {
+            flags |= kFlagEventLimit;
+            finish = true;
+        }
+        if (!finish) {
+            // selection: the number of partial sums <= u is the smallest j with S_j > u
+            const double u = r2 * acc;
+            int32_t sel = 0;
+            if constexpr (MM > 0) {
+#pragma unroll
+                for (int j = 0; j < MM; ++j) sel += (Ssum[j] <= u) ? 1 : 0;
+            } else {
+                sel = p.select(n, u);
+            }
+            if (sel >= M) {
+                // rounding left no S_j > u: the largest j with a_j > 0
+                for (int32_t j = M - 1; j >= 0; --j) {
+                    if (p.one(n, j) > 0.0) { sel = j; break; }
+                }
+                sel = min(sel, M - 1);   // a0 > 0 guarantees some a_j > 0; keeps the index in range
+            }
+            p.apply(n, sel, [&](int32_t, int32_t, int32_t xn) { ovf |= (uint32_t)xn; });
+            if ((int32_t)ovf < 0) {
+                flags |= kFlagOverflow;
+                finish = true;
+            } else {
+                if (MODE != kFwd) {
+#pragma unroll
+                    for (int j = 0; j < MM; ++j) {
+                        A[j] = A[j] + a[j] * tau;
+                        nf[j] = nf[j] + (j == sel ? 1.0 : 0.0);
+                    }
+                }
+                t = t_next;
+                ev = ev + 1;
+            }
+        }
+        if (finish) {
+            if (MODE == kRec) {
+                const int64_t r = traj - n.rec_begin;
+                n.rec_events[r] = ev;
+                n.rec_draws[r] = k;
+                n.rec_tlast[r] = t;
+                if (n.rec_nf) {
+#pragma unroll
+                    for (int j = 0; j < MM; ++j)
+                        if (j < M) n.rec_nf[r * M + j] = (int64_t)nf[j];
+                }
+                if (n.rec_aint) {
+                    const double tail = n.t_end - t;
+#pragma unroll
+                    for (int j = 0; j < MM; ++j)
+                        if (j < M) n.rec_aint[r * M + j] = A[j] + a[j] * tail;
+                }
+            }
+            if (MODE == kBwd) {
+#pragma unroll
+                for (int j = 0; j < MM; ++j)
+                    if (j < M) n.gtraj[(size_t)traj * M + j] = gacc[j];
+            }
+            tot_events += ev;
+            max_steps = max(max_steps, (unsigned long long)ev);
+            active = false;
+        }
+    }
+
+    // wave totals -> global statistics
+    for (int off = 32; off > 0; off >>= 1) {
+        tot_events += __shfl_xor(tot_events, off);
+        max_steps = max(max_steps, (unsigned long long)__shfl_xor(max_steps, off));
+        flags |= (uint32_t)__shfl_xor((int)flags, off);
+    }
+    if (lane == 0) {
+        if (tot_events) atomicAdd(wl.stats + 0, tot_events);
+        atomicMax(wl.stats + 1, max_steps);
+        if (flags) atomicOr(wl.stats + 2, (unsigned long long)flags);
+    }
+}
+
+// Smallest value over the wave's lanes (uniform result).
+__device__ __forceinline__ int32_t wave_min(int32_t v) {
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
+    return wave_uniform(v);
+}
+
+// Forward pass with the selective-memory window (see the header comment).  win: this
+// wave's LDS window, wl.win_bins bins x S species x (sum nu, sum (2x+nu)nu) as int64.
+template <int MM, bool BATCH, bool SLAB, class Policy>
+__device__ __forceinline__ void sim_fwd(const WorkList &wl, Policy &p, long long *win) {
+    constexpr int MR = MM > 0 ? MM : 1;
+    const uint32_t lane = __lane_id();
+    const int32_t W = wl.win_bins;
+    const int32_t wave_slot = (int32_t)(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave);
+
+    int32_t cur = -1;
+    GridView gv;
+    gv.grid = nullptr;
+    gv.T = gv.D = gv.lo = gv.scale = 0.0;
+    gv.G = 0;
+    gv.uniform = 0;
+    uint32_t flags = 0;
+    unsigned long long tot_events = 0, max_steps = 0;
+    double a[MR];
+    double Ssum[MR];
+
+    for (;;) {
+        // ---------------- next generation: one work item, one trajectory per lane ----------------
+        int32_t item = 0;
+        if (lane == 0) item = (int32_t)atomicAdd(wl.counter, 1u);
+        item = wave_uniform(__shfl(item, 0));
+        if (item >= wl.n_items) break;
+        int32_t b = 0;
+        int64_t begin, count;
+        if (BATCH) {
+            b = wave_uniform(((const SSA_CONST int32_t *)wl.item_net)[item]);
+            begin = wave_uniform(((const SSA_CONST int64_t *)wl.item_begin)[item]);
+            count = wave_uniform((int64_t)((const SSA_CONST int32_t *)wl.item_count)[item]);
+        } else {
+            begin = wl.range_begin + (int64_t)item * kChunk;
+            count = min((int64_t)kChunk, wl.range_end - begin);
+        }
+        if (b != cur) {
+            cur = b;
+            const NetDev nn = current_net<BATCH>(wl, cur);
+            p.switch_net(nn);
+            const GridInfo gi = *(const SSA_CONST GridInfo *)nn.ginfo;
+            gv.grid = wave_uniform(nn.grid);
+            gv.T = wave_uniform(gi.T);
+            gv.D = wave_uniform(gi.D);
+            gv.lo = wave_uniform(gi.lo);
+            gv.scale = wave_uniform(gi.scale);
+            gv.G = wave_uniform(nn.G);
+            gv.uniform = wave_uniform(gi.uniform);
+        }
+        const NetDev n0 = current_net<BATCH>(wl, cur);
+        const int32_t S = n0.S, G = n0.G, M = n0.M;
+        const int32_t row_words = S * 2;
+        unsigned long long *slab =
+            SLAB ? wl.slabs + (size_t)wave_slot * (size_t)G * row_words : n0.D;
+        for (int32_t q = lane; q < W * row_words; q += kWave) win[q] = 0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        int32_t base = 0;
+
+        // flush bins [lo, hi) of the window (lanes cooperate over consecutive words)
+        auto flush = [&](int32_t lo, int32_t hi) {
+            // the window's LDS words were written by other lanes of this wave: LDS operations
+            // of one wave complete in order, so only compiler reordering must be fenced off
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const int32_t words = (hi - lo) * row_words;
+            for (int32_t e = lane; e < words; e += kWave) {
+                const int32_t bin = lo + e / row_words, r = e - (e / row_words) * row_words;
+                long long *slot = win + (bin & (W - 1)) * row_words + r;
+                const long long v = *slot;
+                if (v != 0) {
+                    unsigned long long *dst = slab + (size_t)bin * row_words + r;
+                    if (SLAB) *dst = *dst + (unsigned long long)v;
+                    else atomicAdd(dst, (unsigned long long)v);
+                    *slot = 0;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        };
+
+        // lane state
+        bool active = (int64_t)lane < count;
+        const int64_t traj = begin + lane;
+        double t = 0.0, t_next = 0.0, u = 0.0;
+        double tg_next = gv.uniform ? 0.0 : ((const SSA_CONST double *)gv.grid)[0];
+        uint64_t k = 0, ev = 0;
+        int32_t g = 0, binp = G;
+        bool pend = false;
+        uint32_t ovf = 0;
+        if (active) p.reset(n0);
+
+        for (;;) {
+            const bool blocked = active && pend && binp < G && binp >= base + W;
+            if (active && !blocked) {
+                const NetDev n = current_net<BATCH>(wl, cur);
+                if (pend) {
+                    // apply the pending event at t_next (state unchanged since it was drawn)
+                    int32_t sel = 0;
+                    if constexpr (MM > 0) {
+#pragma unroll
+                        for (int j = 0; j < MM; ++j) sel += (Ssum[j] <= u) ? 1 : 0;
+                    } else {
+                        sel = p.select(n, u);
+                    }
+                    if (sel >= M) {
+                        for (int32_t j = M - 1; j >= 0; --j) {
+                            if (p.one(n, j) > 0.0) { sel = j; break; }
+                        }
+                        sel = min(sel, M - 1);
+                    }
+                    const int32_t bin = binp;
+                    p.apply(n, sel, [&](int32_t sp, int32_t xo, int32_t xn) {
+                        ovf |= (uint32_t)xn;
+                        if (bin < G) {
+                            const int32_t dl = xn - xo;
+                            const long long d2 = (2ll * xo + dl) * (long long)dl;
+                            long long *w = win + (bin & (W - 1)) * row_words + sp * 2;
+                            atomicAdd((unsigned long long *)w, (unsigned long long)(long long)dl);
+                            if (d2 > -kSmallD2 && d2 < kSmallD2) {
+                                atomicAdd((unsigned long long *)(w + 1), (unsigned long long)d2);
+                            } else {
+                                atomicAdd((unsigned long long *)(w + 1), (unsigned long long)(d2 & ((1ll << 24) - 1)));
+                                atomicAdd(n.Dhi + (size_t)bin * S + sp, (unsigned long long)(d2 >> 24));
+                            }
+                            if (n.Hd && sp == n.h_species) {
+                                const int32_t bo = xo < n.h_lo ? 0 : min((xo - n.h_lo) / n.h_width, n.nb_hist - 1);
+                                const int32_t bn = xn < n.h_lo ? 0 : min((xn - n.h_lo) / n.h_width, n.nb_hist - 1);
+                                if (bo != bn) {
+                                    atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bo, -1);
+                                    atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bn, 1);
+                                }
+                            }
+                        }
+                    });
+                    pend = false;
+                    if ((int32_t)ovf < 0) {
+                        flags |= kFlagOverflow;
+                        active = false;
+                    } else {
+                        t = t_next;
+                        ev = ev + 1;
+                        g = bin;
+                    }
+                }
+                if (active) {
+                    // draw the next event
+                    double acc;
+                    if constexpr (MM > 0) {
+                        p.template eval<MM>(n, a);
+                        acc = a[0];
+                        Ssum[0] = acc;
+#pragma unroll
+                        for (int j = 1; j < MM; ++j) {
+                            acc = acc + a[j];
+                            Ssum[j] = acc;
+                        }
+                    } else {
+                        acc = p.total(n);
+                    }
+                    if (acc == 0.0) {
+                        active = false;                // absorbing: the state holds to t_end
+                    } else {
+                        const u32x4 o = philox4x32_10((uint32_t)k, (uint32_t)(k >> 32), (uint32_t)traj,
+                                                      (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
+                        const double r1 = uniform_open0(o.v0, o.v1);
+                        const double r2 = uniform_open1(o.v2, o.v3);
+                        t_next = t + neg_log(r1) / acc;
+                        k = k + 1;
+                        if (t_next > n.t_end) {
+                            active = false;            // beyond the horizon: not applied
+                        } else if (ev >= n.max_events) {
+                            flags |= kFlagEventLimit;
+                            active = false;
+                        } else {
+                            u = r2 * acc;
+                            binp = g;
+                            if (g < G && t_next > tg_next) binp = gv.next_bin(g, t_next, tg_next);
+                            pend = true;
+                        }
+                    }
+                    if (!active) {
+                        tot_events += ev;
+                        max_steps = max(max_steps, (unsigned long long)ev);
+                    }
+                }
+            }
+            // window upkeep: slide when a lane is waiting beyond it
+            if (__ballot(active) == 0) break;
+            if (__ballot(active && pend && binp < G && binp >= base + W)) {
+                const int32_t m = wave_min(active && pend ? binp : G);
+                if (m > base) {
+                    flush(base, min(m, base + W));
+                    base = m;
+                }
+            }
+        }
+        flush(base, min(G, base + W));
+    }
+
+    // wave totals -> global statistics
+    for (int off = 32; off > 0; off >>= 1) {
+        tot_events += __shfl_xor(tot_events, off);
+        max_steps = max(max_steps, (unsigned long long)__shfl_xor(max_steps, off));
+        flags |= (uint32_t)__shfl_xor((int)flags, off);
+    }
+    if (lane == 0) {
+        if (tot_events) atomicAdd(wl.stats + 0, tot_events);
+        atomicMax(wl.stats + 1, max_steps);
+        if (flags) atomicOr(wl.stats + 2, (unsigned long long)flags);
+    }
+}
+
+}  // namespace ssa

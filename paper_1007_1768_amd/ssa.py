@@ -1,0 +1,274 @@
+"""Python binding of libssa (include/ssa.h): argument marshalling only.
+
+Every step of the simulation, alignment, reduction and gradient runs in the library's HIP
+kernels.  PyTorch provides device memory (tensors) and the current HIP stream; numpy
+arrays are used for host-side model descriptions.  Importing this module does not need a
+GPU; calling into the library does, and a missing library raises instead of falling back
+to anything else.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libssa.so")
+
+OK, E_INVALID, E_NOMEM, E_DEVICE, E_OVERFLOW, E_EVENT_LIMIT, E_UNSUPPORTED = range(7)
+_NAMES = {1: "SSA_E_INVALID", 2: "SSA_E_NOMEM", 3: "SSA_E_DEVICE", 4: "SSA_E_OVERFLOW",
+          5: "SSA_E_EVENT_LIMIT", 6: "SSA_E_UNSUPPORTED"}
+
+EXPORTS = ["ssa_model_create", "ssa_model_destroy", "ssa_run", "ssa_run_device", "ssa_backward_device",
+           "ssa_record", "ssa_batch_create", "ssa_batch_run", "ssa_batch_destroy", "ssa_last_error"]
+
+
+class SSAError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_NAMES.get(status, str(status)), msg))
+        self.status = status
+
+
+class HistSpec(ctypes.Structure):
+    _fields_ = [("species", ctypes.c_int32), ("lo", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("nbins", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("events", ctypes.c_uint64), ("max_steps", ctypes.c_uint64), ("flags", ctypes.c_uint32),
+                ("kernel_ms", ctypes.c_float)]
+
+    def as_dict(self):
+        return dict(events=int(self.events), max_steps=int(self.max_steps), flags=int(self.flags),
+                    kernel_ms=float(self.kernel_ms))
+
+
+_lib = None
+
+
+def load(path=None):
+    """Load libssa.so (built by paper_1007_1768_amd/build.py); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = path or LIB_PATH
+    if not os.path.exists(path):
+        raise ImportError("libssa.so not built (%s); run __graft_entry__.build()" % path)
+    L = ctypes.CDLL(path)
+    vp, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    L.ssa_model_create.argtypes = [i32, i32, vp, vp, vp, vp, ctypes.POINTER(vp)]
+    L.ssa_model_destroy.argtypes = [vp]
+    L.ssa_model_destroy.restype = None
+    L.ssa_run.argtypes = [vp, i64, dbl, vp, i32, u64, vp, vp, vp]
+    L.ssa_run_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
+    L.ssa_backward_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
+    L.ssa_record.argtypes = [vp, vp, i64, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
+    L.ssa_batch_create.argtypes = [i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
+    L.ssa_batch_run.argtypes = [vp, vp, vp, vp, vp]
+    L.ssa_batch_destroy.argtypes = [vp]
+    L.ssa_batch_destroy.restype = None
+    L.ssa_last_error.argtypes = []
+    L.ssa_last_error.restype = ctypes.c_char_p
+    for f in EXPORTS:
+        if f not in ("ssa_model_destroy", "ssa_batch_destroy", "ssa_last_error"):
+            getattr(L, f).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != OK:
+        raise SSAError(status, load().ssa_last_error().decode())
+
+
+def _p(a):
+    return None if a is None else ctypes.c_void_p(a.ctypes.data)
+
+
+def _tp(t):
+    """Device pointer of a torch tensor (None passes NULL)."""
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Model:
+    """A mass-action network on the current device (ssa_model_create)."""
+
+    def __init__(self, reac, prod, rates, x0):
+        L = load()
+        self.reac = np.ascontiguousarray(reac, dtype=np.int32)
+        self.prod = np.ascontiguousarray(prod, dtype=np.int32)
+        self.rates = np.ascontiguousarray(rates, dtype=np.float64)
+        self.x0 = np.ascontiguousarray(x0, dtype=np.int32)
+        self.M, self.S = self.reac.shape
+        h = ctypes.c_void_p()
+        _check(L.ssa_model_create(self.S, self.M, _p(self.reac), _p(self.prod), _p(self.rates), _p(self.x0),
+                                  ctypes.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def from_dict(cls, m):
+        return cls(m["reac"], m["prod"], m["rates"], m["x0"])
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().ssa_model_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def run(model, n_traj, t_end, grid, seed):
+    """Host form (ssa_run): numpy grid in, numpy (mean, var, stats) out."""
+    grid = np.ascontiguousarray(grid, dtype=np.float64)
+    G = grid.shape[0]
+    mean = np.zeros((G, model.S))
+    var = np.zeros((G, model.S))
+    st = Stats()
+    _check(load().ssa_run(model.handle, int(n_traj), float(t_end), _p(grid), G, int(seed), _p(mean), _p(var),
+                          ctypes.byref(st)))
+    return mean, var, st.as_dict()
+
+
+def run_device(model, n_traj, t_end, grid, seed, rates=None, hist=None, max_events=0, stream=None,
+               with_stats=False, out=None):
+    """Device form (ssa_run_device).  grid and rates are float64 CUDA tensors; returns
+    (mean, var, hist or None, stats or None) as tensors on grid's device."""
+    import torch
+    G = grid.shape[0]
+    if out is None:
+        mean = torch.empty((G, model.S), dtype=torch.float64, device=grid.device)
+        var = torch.empty_like(mean)
+        h = torch.empty((G, hist[3]), dtype=torch.int32, device=grid.device) if hist is not None else None
+    else:
+        mean, var, h = out
+    spec = HistSpec(*[int(v) for v in hist]) if hist is not None else None
+    st = Stats() if with_stats else None
+    _check(load().ssa_run_device(model.handle, _tp(rates), int(n_traj), float(t_end), _tp(grid), G, int(seed),
+                                 int(max_events), _tp(mean), _tp(var),
+                                 ctypes.byref(spec) if spec is not None else None, _tp(h), _stream(stream),
+                                 ctypes.byref(st) if st is not None else None))
+    return mean, var, h, (st.as_dict() if st is not None else None)
+
+
+def backward_device(model, n_traj, t_end, grid, seed, w, mhat, rates=None, max_events=0, stream=None,
+                    with_stats=False, out=None):
+    """LR gradient d loss / d log c (ssa_backward_device); returns (grad (M,), stats or None)."""
+    import torch
+    grad = torch.empty(model.M, dtype=torch.float64, device=grid.device) if out is None else out
+    st = Stats() if with_stats else None
+    _check(load().ssa_backward_device(model.handle, _tp(rates), int(n_traj), float(t_end), _tp(grid),
+                                      grid.shape[0], int(seed), int(max_events), _tp(w.contiguous()),
+                                      _tp(mhat.contiguous()), _tp(grad), _stream(stream),
+                                      ctypes.byref(st) if st is not None else None))
+    return grad, (st.as_dict() if st is not None else None)
+
+
+def record(model, traj_begin, count, t_end, grid, seed, rates=None, max_events=0):
+    """Per-trajectory record (ssa_record), host arrays; returns (status, dict) like the oracle's."""
+    grid = np.ascontiguousarray(grid, dtype=np.float64)
+    G = grid.shape[0]
+    states = np.zeros((count, G, model.S), dtype=np.int32)
+    events = np.zeros(count, dtype=np.uint64)
+    draws = np.zeros(count, dtype=np.uint64)
+    t_last = np.zeros(count, dtype=np.float64)
+    nf = np.zeros((count, model.M), dtype=np.int64)
+    ai = np.zeros((count, model.M), dtype=np.float64)
+    r = None if rates is None else np.ascontiguousarray(rates, dtype=np.float64)
+    status = load().ssa_record(model.handle, _p(r), int(traj_begin), int(count), float(t_end), _p(grid), G,
+                               int(seed), int(max_events), _p(states), _p(events), _p(draws), _p(t_last),
+                               _p(nf), _p(ai))
+    return status, dict(states=states, events=events, draws=draws, t_last=t_last, n_fired=nf, a_int=ai)
+
+
+class Batch:
+    """Many networks in one persistent launch (ssa_batch_create / ssa_batch_run)."""
+
+    def __init__(self, models, n_traj, t_end, grids, seeds):
+        L = load()
+        B = len(models)
+        self.models = list(models)
+        self.grids = [np.ascontiguousarray(g, dtype=np.float64) for g in grids]
+        self.G = [g.shape[0] for g in self.grids]
+        self.n_traj = [int(v) for v in n_traj]
+        hm = (ctypes.c_void_p * B)(*[m.handle.value for m in models])
+        nt = (ctypes.c_int64 * B)(*self.n_traj)
+        te = (ctypes.c_double * B)(*[float(v) for v in t_end])
+        gp = (ctypes.c_void_p * B)(*[g.ctypes.data for g in self.grids])
+        ng = (ctypes.c_int32 * B)(*self.G)
+        sd = (ctypes.c_uint64 * B)(*[int(v) for v in seeds])
+        h = ctypes.c_void_p()
+        _check(L.ssa_batch_create(B, hm, nt, te, gp, ng, sd, ctypes.byref(h)))
+        self.handle = h
+
+    def run(self, device, stream=None, with_stats=False, outs=None):
+        import torch
+        B = len(self.models)
+        if outs is None:
+            means = [torch.empty((self.G[b], self.models[b].S), dtype=torch.float64, device=device) for b in range(B)]
+            vars_ = [torch.empty_like(m) for m in means]
+        else:
+            means, vars_ = outs
+        mp = (ctypes.c_void_p * B)(*[m.data_ptr() for m in means])
+        vp = (ctypes.c_void_p * B)(*[v.data_ptr() for v in vars_])
+        st = Stats() if with_stats else None
+        _check(load().ssa_batch_run(self.handle, mp, vp, _stream(stream), ctypes.byref(st) if st is not None else None))
+        return means, vars_, (st.as_dict() if st is not None else None)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().ssa_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _make_function():
+    import torch
+
+    class SSAMean(torch.autograd.Function):
+        """mean = E[X(t_g)] over n_traj trajectories, differentiable in log rate constants.
+
+        forward: ssa_run_device with rates = exp(log_rates); backward: the likelihood-ratio
+        kernel (ssa_backward_device) re-simulates the same trajectories, centred on the
+        forward mean."""
+
+        @staticmethod
+        def forward(ctx, log_rates, model, n_traj, t_end, grid, seed):
+            rates = torch.exp(log_rates.detach()).contiguous()
+            mean, _, _, _ = run_device(model, n_traj, t_end, grid, seed, rates=rates)
+            ctx.save_for_backward(rates, mean)
+            ctx.cfg = (model, n_traj, t_end, grid, seed)
+            return mean
+
+        @staticmethod
+        def backward(ctx, grad_mean):
+            rates, mean = ctx.saved_tensors
+            model, n_traj, t_end, grid, seed = ctx.cfg
+            g, _ = backward_device(model, n_traj, t_end, grid, seed, grad_mean.contiguous(), mean, rates=rates)
+            return g, None, None, None, None, None
+
+    return SSAMean
+
+
+_fn = None
+
+
+def ssa_mean(log_rates, model, n_traj, t_end, grid, seed):
+    """Differentiable grid means (torch.autograd.Function over the HIP forward/backward)."""
+    global _fn
+    if _fn is None:
+        _fn = _make_function()
+    return _fn.apply(log_rates, model, n_traj, t_end, grid, seed)

@@ -1,0 +1,76 @@
+"""The C ABI library loads on a machine without a GPU and exports every function that
+include/ssa.h declares; argument validation that happens before any device call reports
+SSA_E_INVALID.  No compute call is made here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1007_1768_amd import ssa
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "ssa.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ssa_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ssa.LIB_PATH):
+        pytest.skip("libssa.so not built")
+    return ssa.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    assert names == sorted(ssa.EXPORTS), names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), name
+    assert lib.ssa_last_error() is not None
+
+
+def test_invalid_models_rejected_before_device_use(lib):
+    m = dict(reac=np.array([[3]], np.int32), prod=np.array([[0]], np.int32), rates=np.array([1.0]),
+             x0=np.array([1], np.int32))
+    for bad in ("order", "neg_rate", "nan_rate", "neg_x0", "big_product", "empty"):
+        reac, prod, rates, x0 = (m["reac"].copy(), m["prod"].copy(), m["rates"].copy(), m["x0"].copy())
+        reac[0, 0] = 1
+        if bad == "order":
+            reac[0, 0] = 3
+        elif bad == "neg_rate":
+            rates[0] = -1.0
+        elif bad == "nan_rate":
+            rates[0] = float("nan")
+        elif bad == "neg_x0":
+            x0[0] = -2
+        elif bad == "big_product":
+            prod[0, 0] = 2**21
+        h = ctypes.c_void_p()
+        S = 0 if bad == "empty" else 1
+        st = lib.ssa_model_create(S, 1, reac.ctypes.data, prod.ctypes.data, rates.ctypes.data, x0.ctypes.data,
+                                  ctypes.byref(h))
+        assert st == ssa.E_INVALID, bad
+        assert h.value is None
+        assert lib.ssa_last_error()
+
+
+def test_null_arguments_rejected(lib):
+    g = np.array([0.0, 1.0])
+    mean = np.zeros(2)
+    assert lib.ssa_run(None, 10, 1.0, g.ctypes.data, 2, 1, mean.ctypes.data, mean.ctypes.data, None) == ssa.E_INVALID
+    assert lib.ssa_run_device(None, None, 10, 1.0, None, 2, 1, 0, None, None, None, None, None, None) == ssa.E_INVALID
+    assert lib.ssa_backward_device(None, None, 10, 1.0, None, 2, 1, 0, None, None, None, None, None) == ssa.E_INVALID
+    assert lib.ssa_record(None, None, 0, 1, 1.0, None, 1, 1, 0, None, None, None, None, None, None) == ssa.E_INVALID
+    out = ctypes.c_void_p()
+    assert lib.ssa_batch_create(0, None, None, None, None, None, None, ctypes.byref(out)) == ssa.E_INVALID
+    assert lib.ssa_batch_run(None, None, None, None, None) == ssa.E_INVALID
+    lib.ssa_model_destroy(None)
+    lib.ssa_batch_destroy(None)
