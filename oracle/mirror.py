@@ -77,6 +77,32 @@ def _h(reac_row, x):
     return int(x[a]) * int(x[b])
 
 
+def _partial_sums(a, order):
+    """Cumulative propensity sums in the network's order: left to right ("seq"), or the
+    64-chunk form ("block64": sequential inside chunks of ceil(M/64), chunk totals combined
+    by a six-step doubling scan, each chunk offset by the scanned total of the chunks
+    before it)."""
+    if order == "seq":
+        out = []
+        for v in a:
+            out.append(v if not out else out[-1] + v)
+        return out
+    q = -(-len(a) // 64)
+    local = []
+    for lane in range(64):
+        run = []
+        for v in a[lane * q:(lane + 1) * q]:
+            run.append(v if not run else run[-1] + v)
+        local.append(run)
+    scan = [r[-1] if r else 0.0 for r in local]
+    step = 1
+    while step < 64:
+        scan = [scan[i] + scan[i - step] if i >= step else scan[i] for i in range(64)]
+        step *= 2
+    offset = [0.0] + scan[:-1]
+    return [offset[lane] + v for lane, run in enumerate(local) for v in run]
+
+
 def trajectory(model, seed, traj, t_end, grid, rates=None):
     """Mirror of the oracle's single-trajectory record: (states, events, draws, t_last, n_fired, a_int)."""
     reac = [[int(v) for v in row] for row in model["reac"]]
@@ -94,12 +120,8 @@ def trajectory(model, seed, traj, t_end, grid, rates=None):
     g = 0
     while True:
         a = [c[j] * float(_h(reac[j], x)) for j in range(M)]
-        Ssum = []
-        acc = 0.0
-        for j in range(M):
-            acc = a[j] if j == 0 else acc + a[j]
-            Ssum.append(acc)
-        a0 = acc
+        Ssum = _partial_sums(a, model.get("sum_order", "seq"))
+        a0 = Ssum[-1]
         if a0 == 0.0:
             tau, r2 = float("inf"), 0.0
         else:

@@ -19,7 +19,9 @@ _lib = None
 class _Net(ctypes.Structure):
     _fields_ = [("S", ctypes.c_int32), ("M", ctypes.c_int32),
                 ("reac", ctypes.c_void_p), ("prod", ctypes.c_void_p),
-                ("rate", ctypes.c_void_p), ("x0", ctypes.c_void_p)]
+                ("rate", ctypes.c_void_p), ("x0", ctypes.c_void_p), ("sum_order", ctypes.c_int32)]
+
+SUM_ORDERS = {"seq": 0, "block64": 1}
 
 
 def lib():
@@ -59,18 +61,20 @@ def _ptr(a):
 class Net:
     """Holds contiguous copies of a network's arrays and the ctypes struct that points at them."""
 
-    def __init__(self, reac, prod, rates, x0):
+    def __init__(self, reac, prod, rates, x0, sum_order="seq"):
         self.reac = np.ascontiguousarray(reac, dtype=np.int32)
         self.prod = np.ascontiguousarray(prod, dtype=np.int32)
         self.rates = np.ascontiguousarray(rates, dtype=np.float64)
         self.x0 = np.ascontiguousarray(x0, dtype=np.int32)
         self.M, self.S = self.reac.shape
         self.c = _Net(self.S, self.M, self.reac.ctypes.data, self.prod.ctypes.data,
-                      self.rates.ctypes.data, self.x0.ctypes.data)
+                      self.rates.ctypes.data, self.x0.ctypes.data, SUM_ORDERS[sum_order])
 
 
 def as_net(model, rates=None):
-    return Net(model["reac"], model["prod"], model["rates"] if rates is None else rates, model["x0"])
+    """model: dict with reac, prod, rates, x0 and optionally sum_order ("seq" or "block64")."""
+    return Net(model["reac"], model["prod"], model["rates"] if rates is None else rates, model["x0"],
+               model.get("sum_order", "seq"))
 
 
 def default_threads():

@@ -37,14 +37,17 @@ typedef __int128 i128;
 enum { ORC_OK = 0, ORC_INVALID = 1, ORC_NOMEM = 2, ORC_OVERFLOW = 4, ORC_EVENT_LIMIT = 5 };
 
 /* A reaction network: S species, M reactions, reactant / product coefficient matrices
- * (row j = reaction j, column s = species s), stochastic rate constants c_j and the
- * initial integer state. */
+ * (row j = reaction j, column s = species s), stochastic rate constants c_j, the initial
+ * integer state and the order in which the propensities are summed (see partial_sums). */
+enum { ORC_SUM_SEQ = 0, ORC_SUM_BLOCK64 = 1 };
+
 typedef struct {
     int32_t S, M;
     const int32_t *reac;  /* [M*S] */
     const int32_t *prod;  /* [M*S] */
     const double *rate;   /* [M]   */
     const int32_t *x0;    /* [S]   */
+    int32_t sum_order;    /* ORC_SUM_SEQ or ORC_SUM_BLOCK64 */
 } orc_net;
 
 /* ------------------------------------------------------------------------------------
@@ -161,6 +164,7 @@ typedef struct {
 static int check_net(const orc_net *n)
 {
     if (!n || n->S <= 0 || n->M <= 0 || !n->reac || !n->prod || !n->rate || !n->x0) return ORC_INVALID;
+    if (n->sum_order != ORC_SUM_SEQ && n->sum_order != ORC_SUM_BLOCK64) return ORC_INVALID;
     for (int j = 0; j < n->M; ++j) {
         int order = 0;
         for (int s = 0; s < n->S; ++s) {
@@ -206,6 +210,48 @@ static double propensity(const orc_net *n, const rxn_info *ri, int j, const int3
     return n->rate[j] * (double)h;
 }
 
+/* ------------------------------------------------------------------------------------
+ * Partial sums S_j of the propensities (Section 2's cumulative sums for the selection).
+ * The paper leaves the summation order open; it is a model attribute:
+ *   sequential: S_0 = a_0, S_j = S_{j-1} + a_j.
+ *   block64:    the reactions are cut into 64 consecutive chunks of q = ceil(M / 64)
+ *               (chunk l holds indices l q .. l q + q - 1 that are below M).  L_j is the
+ *               sequential sum inside the chunk, T_l the chunk total (0 for an empty
+ *               chunk).  The totals are scanned inclusively in six steps d = 1, 2, 4, ..., 32,
+ *               each step replacing v_l by v_l + v_{l-d} for l >= d from the previous
+ *               step's values; E_l is the scanned value of chunk l - 1 (E_0 = 0) and
+ *               S_j = E_l + L_j for j in chunk l.
+ * In both orders a0 = S_{M-1}.
+ * ---------------------------------------------------------------------------------- */
+static void partial_sums(int order, int M, const double *a, double *S)
+{
+    if (order == ORC_SUM_SEQ) {
+        S[0] = a[0];
+        for (int j = 1; j < M; ++j) S[j] = S[j - 1] + a[j];
+        return;
+    }
+    const int q = (M + 63) / 64;
+    double v[64], prev[64], E[64];
+    for (int l = 0; l < 64; ++l) {
+        v[l] = 0.0;
+        double L = 0.0;
+        for (int i = 0; i < q; ++i) {
+            int j = l * q + i;
+            if (j >= M) break;
+            L = (i == 0) ? a[j] : L + a[j];
+            S[j] = L;                       /* local sum for now */
+        }
+        if (l * q < M) v[l] = L;
+    }
+    for (int d = 1; d < 64; d *= 2) {
+        for (int l = 0; l < 64; ++l) prev[l] = v[l];
+        for (int l = d; l < 64; ++l) v[l] = prev[l] + prev[l - d];
+    }
+    E[0] = 0.0;
+    for (int l = 1; l < 64; ++l) E[l] = v[l - 1];
+    for (int j = 0; j < M; ++j) S[j] = E[j / q] + S[j];
+}
+
 static int check_grid(const double *grid, int32_t G, double t_end)
 {
     if (!(t_end >= 0.0) || !isfinite(t_end)) return ORC_INVALID;
@@ -222,8 +268,8 @@ static int check_grid(const double *grid, int32_t G, double t_end)
  * Section 3.2.1 and optional bookkeeping for the likelihood-ratio gradient.
  *
  * Readings:
- *   - Propensities are recomputed in full at every step; a0 and the partial sums S_j are
- *     the sequential left-to-right sums S_0 = a_0, S_j = S_{j-1} + a_j.
+ *   - Propensities are recomputed in full at every step; a0 and the partial sums S_j
+ *     follow the network's sum order (partial_sums); a0 = S_{M-1}.
  *   - If a0 == 0 the state is absorbing: no draw is made and the state holds to t_end.
  *   - Otherwise draw k gives (r1, r2); tau = neglog(r1) / a0 (IEEE division);
  *     t_next = t + tau; k counts draws made, the last (overshooting) draw included.
@@ -266,12 +312,9 @@ static int run_trajectory(const orc_net *net, const rxn_info *info, uint64_t see
     int g = 0;
     int status = ORC_OK;
     for (;;) {
-        double a0 = 0.0;
-        for (int j = 0; j < M; ++j) {
-            st->a[j] = propensity(net, &info[j], j, st->x);
-            a0 = (j == 0) ? st->a[j] : a0 + st->a[j];
-            st->Ssum[j] = a0;
-        }
+        for (int j = 0; j < M; ++j) st->a[j] = propensity(net, &info[j], j, st->x);
+        partial_sums(net->sum_order, M, st->a, st->Ssum);
+        const double a0 = st->Ssum[M - 1];
         double tau, r2 = 0.0;
         if (a0 == 0.0) {
             tau = INFINITY;

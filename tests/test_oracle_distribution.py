@@ -137,10 +137,24 @@ CME_CASES = [
 ]
 
 
-@pytest.mark.parametrize("case", CME_CASES, ids=[c[0] for c in CME_CASES])
+# A birth-death process written as 40 inflow and 40 degradation reactions of a fifth of
+# the rates each plus a catalytic second species (M = 81 > 64): in the 64-chunk sum order
+# two reactions share a chunk, so a chunk-offset slip would bias birth against death.
+_SPLIT = ([({}, {"A": 1}, 4.0 / 40)] * 40 + [({"A": 1}, {}, 0.5 / 40)] * 40 +
+          [({"A": 1}, {"A": 1, "B": 1}, 0.3)])
+CME_CASES_BLOCK64 = [
+    ("split_birth_death_block64", ["A", "B"], _SPLIT, [0, 0], [40, 60], 4.0),
+    ("homodimer_block64", ["A", "B"], CME_CASES[0][2], [20, 0], [20, 10], 3.0),
+]
+
+
+@pytest.mark.parametrize("case", CME_CASES + CME_CASES_BLOCK64,
+                         ids=[c[0] for c in CME_CASES + CME_CASES_BLOCK64])
 def test_against_master_equation(case):
     name, species, reactions, x0, caps, t_end = case
     m = inputs._model(name, species, reactions, x0)
+    if name.endswith("_block64"):
+        m["sum_order"] = "block64"
     grid = inputs.uniform_grid(t_end, 7)
     sol = cme.solve(m, caps, grid)
     assert np.all(sol["leak"] < 1e-9), sol["leak"]

@@ -75,6 +75,83 @@ def test_mirror_agrees_bitwise():
             assert [float(v) for v in r["a_int"]] == mr["a_int"]
 
 
+def _block64(m):
+    m = dict(m)
+    m["sum_order"] = "block64"
+    return m
+
+
+def test_mirror_agrees_bitwise_block64():
+    # the 64-chunk sum order, on networks with one reaction per chunk (M <= 64) and with
+    # two or three per chunk (M = 65 .. 192)
+    nets = [n for n in inputs.random_networks(count=12) if n["reac"].shape[0] > 64][:2]
+    cases = [(_block64(inputs.viral()), 2, 5.0, 26)]
+    cases += [(_block64(n), n["seed"], 0.2, 5) for n in nets]
+    big = _integer_rate_network(150, 9, seed=5, scale=0.37)
+    cases.append((_block64(big), 17, 0.5, 6))
+    for m, seed, t_end, G in cases:
+        grid = inputs.uniform_grid(t_end, G)
+        for traj in (0, 3, 99):
+            st, r = orc.trajectory(m, seed, traj, t_end, grid)
+            assert st == orc.OK
+            mr = mirror.trajectory(m, seed, traj, t_end, grid)
+            assert np.array_equal(r["states"], np.asarray(mr["states"], dtype=np.int32))
+            assert r["events"] == mr["events"] and r["draws"] == mr["draws"]
+            assert r["t_last"] == mr["t_last"]
+            assert list(r["n_fired"]) == mr["n_fired"]
+
+
+def _integer_rate_network(M, S, seed, scale=1.0):
+    """M reactions over S species with first-order and inflow reactions only; rates are
+    integers times scale (integers: every propensity and every partial sum is exact)."""
+    rng = np.random.default_rng(seed)
+    reac = np.zeros((M, S), np.int32)
+    prod = np.zeros((M, S), np.int32)
+    for j in range(M):
+        kind = j % 3
+        a, b = (int(v) for v in rng.integers(0, S, size=2))
+        if kind == 0:
+            prod[j, a] = 1                   # inflow
+        elif kind == 1:
+            reac[j, a] = 1                   # degradation
+        else:
+            reac[j, a] = 1                   # conversion
+            prod[j, b if b != a else (a + 1) % S] = 1
+    rates = rng.integers(1, 8, size=M).astype(np.float64) * scale
+    return dict(name="intnet", species=["S%d" % s for s in range(S)], reac=reac, prod=prod, rates=rates,
+                x0=rng.integers(0, 40, size=S).astype(np.int32))
+
+
+@pytest.mark.parametrize("M", [1, 7, 64, 65, 128, 129, 200])
+def test_block64_equals_sequential_when_sums_are_exact(M):
+    # With integer propensities every partial sum is exact in either order, so the two
+    # orders must select the same reactions: any chunk or offset slip in the 64-chunk sums
+    # changes some S_j and with it the trajectory.
+    m = _integer_rate_network(M, 6, seed=M)
+    grid = inputs.uniform_grid(1.0, 9)
+    for traj in range(6):
+        st1, r1 = orc.trajectory(m, 11, traj, 1.0, grid)
+        st2, r2 = orc.trajectory(_block64(m), 11, traj, 1.0, grid)
+        assert st1 == st2 == orc.OK
+        assert r1["events"] > 0
+        assert np.array_equal(r1["states"], r2["states"])
+        assert np.array_equal(r1["n_fired"], r2["n_fired"])
+        assert r1["draws"] == r2["draws"] and r1["t_last"] == r2["t_last"]
+
+
+def test_block64_keeps_invariants_with_inexact_sums():
+    # non-integer rates: the two orders round their partial sums differently (a selection
+    # differs only when u falls between the two roundings of a boundary, which is rare);
+    # the 64-chunk trajectories keep the stoichiometric invariant
+    m = _integer_rate_network(150, 9, seed=5, scale=0.37)
+    grid = inputs.uniform_grid(2.0, 5)
+    for traj in range(40):
+        st, r2 = orc.trajectory(_block64(m), 3, traj, 2.0, grid)
+        assert st == orc.OK and r2["events"] > 0
+        xT = r2["states"][-1].astype(np.int64)
+        assert np.array_equal(xT, np.asarray(m["x0"], np.int64) + _nu(m).T @ r2["n_fired"])
+
+
 def test_right_continuity_at_event_times():
     m = inputs.viral()
     t_end = 3.0
