@@ -74,6 +74,36 @@ def w_backward(model, crossings_per_event):
             + 4 * M + crossings_per_event * (2 * S + 4 * M + W_DIV))
 
 
+def kernel_sources_hash():
+    """FNV-1a 64 over the HIP sources, to tie stored counter readings to the kernels they came from."""
+    h = 0xcbf29ce484222325
+    d = os.path.join(ROOT, "paper_1007_1768_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp")):
+            for byte in open(os.path.join(d, f), "rb").read():
+                h = ((h ^ byte) * 0x100000001b3) & 0xffffffffffffffff
+    return "%016x" % h
+
+
+def stored_traffic(kernel, workload_name):
+    """HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE summary in profiles/, or None
+    when there is none or the kernel sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "%s_%s_traffic.txt" % (kernel, workload_name))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("sources_fnv64") != kernel_sources_hash():
+        return None
+    try:
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
 def workload(name):
     w = dict(inputs.WORKLOADS[name])
     m = w["model"]()
@@ -176,13 +206,15 @@ def main():
     changes = mean_changes(m)
     fwd_avg = float(np.mean(fwd_ms))
     bwd_avg = float(np.mean(bwd_ms))
+    jit = os.environ.get("SSA_KERNEL") != "generic" and M <= 32 and S <= 64
     if bwd_avg >= fwd_avg:
-        kname, kms, wop = "sim_kernel<kBwd>", bwd_avg, w_backward(m, crossings)
+        kname, kms, wop = ("ssa_jit_bwd" if jit else "sim_kernel_bwd"), bwd_avg, w_backward(m, crossings)
     else:
-        kname, kms, wop = "sim_kernel<kFwd>", fwd_avg, w_forward(m, cross_frac, changes)
+        kname, kms, wop = ("ssa_jit_fwd_atomic" if jit else "fwd_kernel"), fwd_avg, w_forward(m, cross_frac, changes)
     achieved = wop * stats_f["events"] / (kms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_LANE_OPS / 1e12, 3),
-                "unit": "Tlane-op/s", "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 5), "traffic": None,
+                "unit": "Tlane-op/s", "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 5),
+                "traffic": stored_traffic(kname, args.workload),
                 "kernel": kname, "kernel_ms": round(kms, 4), "ops_per_event": round(wop, 1)}
 
     out = {
@@ -215,16 +247,25 @@ def main():
     if not args.no_cpu_baseline:
         from oracle import oracle as orc
         thr = orc.default_threads()
-        # bounded sample: a slice of the same workload sized for ~10-30 s of oracle time
+        # bounded sample of the same workload: a slice of its trajectories (forward + gradient,
+        # as in a step), repeated until at least 10 s of oracle time have passed
         n_cpu = min(N, int(os.environ.get("BENCH_CPU_TRAJ", str(min(N, 20000)))))
-        a0 = time.perf_counter()
-        st, ref = orc.run(m, n_cpu, t_end, grid_np, seed, hist=hist, threads=thr)
         tw = target.cpu().numpy()
-        st2, g, _ = orc.grad(m, n_cpu, t_end, grid_np, seed, 2.0 * (ref["mean"] - tw), ref["mean"], threads=thr)
+        cpu_events, reps = 0, 0
+        a0 = time.perf_counter()
+        while True:
+            st, ref = orc.run(m, n_cpu, t_end, grid_np, seed, hist=hist, threads=thr)
+            st2, g, _ = orc.grad(m, n_cpu, t_end, grid_np, seed, 2.0 * (ref["mean"] - tw), ref["mean"],
+                                 threads=thr)
+            cpu_events += 2 * ref["events"]
+            reps += 1
+            if time.perf_counter() - a0 >= 10.0:
+                break
         cpu_s = time.perf_counter() - a0
-        out["cpu_baseline"] = {"value": round(2 * ref["events"] / cpu_s, 1), "unit": "events/s", "cores": thr,
+        out["cpu_baseline"] = {"value": round(cpu_events / cpu_s, 1), "unit": "events/s", "cores": thr,
                                "kind": "oracle",
-                               "sample": "%d of %d trajectories, forward + gradient, %.1f s" % (n_cpu, N, cpu_s)}
+                               "sample": "%d x (trajectories 0..%d of %d, forward + gradient), %.1f s"
+                                         % (reps, n_cpu - 1, N, cpu_s)}
     print(json.dumps(out), flush=True)
     model.close()
 

@@ -17,7 +17,13 @@
  * Arithmetic contract shared (as prose, not code) with the CPU oracle:
  *   propensity  a_j = c_j * h_j(x), h exact in 64-bit integers then rounded once:
  *               1 | x_A | x_A x_B | x_A (x_A - 1) / 2 for 2A
- *   sums        S_0 = a_0, S_j = S_{j-1} + a_j (left to right), a0 = S_{M-1}
+ *   sums        a model attribute (ssa_sum_order), a0 = S_{M-1}:
+ *               SSA_SUM_SEQ      S_0 = a_0, S_j = S_{j-1} + a_j (left to right)
+ *               SSA_SUM_BLOCK64  64 chunks of q = ceil(M/64) consecutive reactions; L_j the
+ *                                left-to-right sum inside chunk l; chunk totals scanned
+ *                                inclusively in steps d = 1, 2, ..., 32 (v_l += v_{l-d} for
+ *                                l >= d, from the previous step's values); E_l = scanned
+ *                                value of chunk l-1 (E_0 = 0); S_j = E_l + L_j
  *   random      Philox4x32-10, key = (seed lo, seed hi), counter = (k lo, k hi, i lo, i hi)
  *               for draw k (0-based) of trajectory i (0-based within its network)
  *   uniforms    r1 = (((o1<<32|o0) >> 11) + 1) 2^-53 in (0,1],  r2 = ((o3<<32|o2) >> 11) 2^-53
@@ -60,6 +66,14 @@ typedef enum {
 typedef struct ssa_model ssa_model;
 typedef struct ssa_batch ssa_batch;
 
+/* Order of the propensity sums (the paper leaves it open; results differ only in
+ * rounding).  SEQ runs one trajectory per lane; BLOCK64 runs one trajectory per wave with
+ * a wave-wide prefix scan, for networks with many reactions. */
+typedef enum {
+    SSA_SUM_SEQ = 0,
+    SSA_SUM_BLOCK64 = 1
+} ssa_sum_order;
+
 /* Optional per-grid-point histogram of one species: bin = clamp((x - lo) div width, 0,
  * nbins - 1); counts are exact.  Output layout [G*nbins] uint32. */
 typedef struct {
@@ -80,14 +94,23 @@ typedef struct {
 /* Model (Section 3.2 model format).
  *   n_species S >= 1, n_reactions M >= 1 (M <= 4096, S <= 1024)
  *   reactants [M*S] host: coefficients >= 0, sum per reaction <= 2 (order <= 2)
- *   products  [M*S] host: coefficients >= 0 (e.g. 200), each <= 2^20
+ *   products  [M*S] host: coefficients >= 0 (e.g. 200), each <= 2^19 - 4
  *   rates     [M]   host: stochastic rate constants c_j, finite, >= 0
  *   x0        [S]   host: initial counts >= 0
+ *   sum_order ssa_sum_order (SSA_SUM_BLOCK64 needs M <= 512)
+ * What runs where:
+ *   SEQ, M <= 32 and S <= 64: kernels specialised to the network at first use (run-time
+ *     compilation, cached per device), every entry point;
+ *   SEQ otherwise: the table-driven kernel, which changes at most 4 species per reaction;
+ *     record and backward need M <= 32 (SSA_E_UNSUPPORTED beyond);
+ *   BLOCK64: the one-trajectory-per-wave kernel, at most 4 changed species per reaction;
+ *     not accepted by ssa_batch_create.
  * The arrays are copied (to the current device); the handle is immutable and may be shared
- * by threads that use the same device.  Errors: SSA_E_INVALID, SSA_E_NOMEM, SSA_E_DEVICE. */
+ * by threads that use the same device.  Errors: SSA_E_INVALID, SSA_E_UNSUPPORTED,
+ * SSA_E_NOMEM, SSA_E_DEVICE. */
 ssa_status ssa_model_create(int32_t n_species, int32_t n_reactions, const int32_t *reactants,
                             const int32_t *products, const double *rates, const int32_t *x0,
-                            ssa_model **out);
+                            int32_t sum_order, ssa_model **out);
 void ssa_model_destroy(ssa_model *model);
 
 /* Host convenience (synchronous): n_traj trajectories 0..n_traj-1 on [0, t_end], grid
@@ -114,8 +137,9 @@ ssa_status ssa_run_device(const ssa_model *model, const double *rates, int64_t n
  *   grad_j = sum_{g,s} w_{g,s} (1/N) sum_i (X^i_s(t_g) - mhat_{g,s}) (n^i_j(t_g) - A^i_j(t_g))
  * with n_j the firing count and A_j the integrated propensity.  All pointers device:
  * rates [M] (NULL = model's), grid [G], w [G*S] (dL/dmean), mhat [G*S] (centring, usually
- * the forward mean), grad [M] output.  Supports M <= 16.  Same status codes as
- * ssa_run_device (SSA_E_UNSUPPORTED above 16 reactions). */
+ * the forward mean), grad [M] output.  The per-trajectory sums are reduced in a fixed
+ * pairwise order, so the result is deterministic.  Same status codes as ssa_run_device
+ * (SSA_E_UNSUPPORTED for a SEQ model with more than 32 reactions). */
 ssa_status ssa_backward_device(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
                                const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events,
                                const double *w, const double *mhat, double *grad, void *stream,
@@ -134,8 +158,10 @@ ssa_status ssa_record(const ssa_model *model, const double *rates, int64_t traj_
 /* Batched form (Section 3.2, parameter-swept simulations in one call): n_models networks,
  * each with its own trajectory count, horizon, grid (host [n_grid[b]]) and seed; trajectory
  * i of network b uses the same counters as ssa_run on that network alone, so the results
- * equal the per-network runs.  All networks run in one persistent work-stealing launch.
- * The handle owns the device copies of the grids and its scratch memory. */
+ * equal the per-network runs bit for bit.  All networks run in one persistent
+ * work-stealing launch of the table-driven kernel (SEQ models with at most 4 changed
+ * species per reaction).  The handle owns the device copies of the grids and its scratch
+ * memory. */
 ssa_status ssa_batch_create(int32_t n_models, const ssa_model *const *models, const int64_t *n_traj,
                             const double *t_end, const double *const *grids, const int32_t *n_grid,
                             const uint64_t *seeds, ssa_batch **out);

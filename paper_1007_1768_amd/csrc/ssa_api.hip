@@ -18,7 +18,7 @@
 #include <vector>
 
 #include "../../include/ssa.h"
-#include "ssa_kernels.hpp"
+#include "ssa_wave.hpp"
 
 using namespace ssa;
 
@@ -64,6 +64,7 @@ constexpr int32_t kMaxProduct = (1 << 19) - 4;
 constexpr uint64_t kDefaultMaxEvents = 1ull << 62;
 constexpr int32_t kJitMaxReactions = 32;     // specialised kernels keep a_j, S_j in registers
 constexpr int32_t kJitMaxSpecies = 64;
+constexpr int32_t kWaveMaxQ = 8;            // 64-chunk order: at most 8 reactions per lane
 
 // Device allocations made by one call, released on the stream in reverse order.
 struct StreamScratch {
@@ -138,6 +139,8 @@ struct ssa_model {
     std::vector<int32_t> x0;          // [S]
     int32_t m_pad = 0;                // generic tables padded to this many reactions
     int32_t max_changes = 0;          // largest number of species one reaction changes
+    int32_t order = SSA_SUM_SEQ;      // propensity sum order
+    int32_t q = 1;                    // 64-chunk order: reactions per lane (ceil(M / 64))
     uint32_t *d_rx = nullptr;         // [m_pad] packed reactant encoding
     double *d_rate = nullptr;         // [m_pad] zero-padded rates
     int32_t *d_chg = nullptr;         // [M * kChg] packed changes
@@ -304,6 +307,7 @@ NetDev base_net(const ssa_model *m, const double *rates, int64_t n_traj, double 
     n.chg = m->d_chg;
     n.x0 = m->d_x0;
     n.grid = grid;
+    n.q = m->q;
     return n;
 }
 
@@ -360,18 +364,16 @@ int32_t window_bins(int32_t S, int32_t G) {
     return W;
 }
 
-// Flush target: "slab" (wave-private slabs, then a reduction), "atomic", or by size.
-int flush_choice() {
+// Flush target of the forward windows: atomic adds into the totals (default), or wave-
+// private slabs summed by a reduction kernel afterwards (SSA_FWD_FLUSH=slab, when the slabs
+// fit in SSA_SLAB_BYTES, default 1 GiB).  Both give identical sums; on the 4-species
+// workloads they run at the same speed, and the atomic form needs no slab memory.
+bool want_slabs(size_t slab_bytes) {
     const char *e = std::getenv("SSA_FWD_FLUSH");
-    if (e && std::strcmp(e, "slab") == 0) return 1;
-    if (e && std::strcmp(e, "atomic") == 0) return 0;
-    return -1;
-}
-
-size_t slab_budget() {
+    if (!e || std::strcmp(e, "slab") != 0) return false;
     size_t b = (size_t)1 << 30;
-    if (const char *e = std::getenv("SSA_SLAB_BYTES")) b = (size_t)std::strtoull(e, nullptr, 10);
-    return b;
+    if (const char *q = std::getenv("SSA_SLAB_BYTES")) b = (size_t)std::strtoull(q, nullptr, 10);
+    return slab_bytes <= b;
 }
 
 struct FwdKernel {
@@ -488,6 +490,27 @@ struct EventPair {
     }
 };
 
+// One-trajectory-per-wave kernels (64-chunk sum order).
+template <int MODE>
+hipError_t launch_wave(const ssa_model *m, const WorkList &wl, int dev, hipStream_t st) {
+    const void *kern = nullptr;
+    if (m->q <= 1) kern = (const void *)wave_kernel<1, MODE>;
+    else if (m->q <= 2) kern = (const void *)wave_kernel<2, MODE>;
+    else if (m->q <= 4) kern = (const void *)wave_kernel<4, MODE>;
+    else if (m->q <= 8) kern = (const void *)wave_kernel<8, MODE>;
+    else return hipErrorInvalidValue;
+    const size_t lds = (size_t)(kBlock / kWave) * (m->S + 1) * sizeof(int32_t);
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, lds);
+    if (e != hipSuccess) return e;
+    const int64_t n_traj = wl.range_end - wl.range_begin;
+    const int64_t blocks =
+        std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(per_cu, 1) * cu_count(dev), (n_traj + 3) / 4));
+    WorkList w = wl;
+    void *args[] = {&w};
+    return hipLaunchKernel(kern, dim3((unsigned)blocks), dim3(kBlock), args, lds, st);
+}
+
 // Finalize of one network: exact prefix over the grid and the moments.
 hipError_t launch_finalize(const unsigned long long *D, const unsigned long long *Dhi, int32_t G, int32_t S,
                            const int32_t *d_x0, int64_t n_traj, double *mean, double *var, hipStream_t st) {
@@ -501,6 +524,11 @@ hipError_t launch_finalize(const unsigned long long *D, const unsigned long long
 // array is copied into a padded buffer first).
 ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_items, int dev, hipStream_t st,
                          const double *user_rates, StreamScratch &scr) {
+    (void)n_items;
+    if (m->order == SSA_SUM_BLOCK64) {
+        HIP_TRY(mode == kRec ? launch_wave<kRec>(m, wl, dev, st) : launch_wave<kBwd>(m, wl, dev, st));
+        return SSA_OK;
+    }
     if (jit_eligible(m)) {
         std::shared_ptr<JitKernels> k;
         ssa_status s = get_jit(m, dev, k);
@@ -528,12 +556,24 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
     return SSA_OK;
 }
 
-// Forward launch of one network.  D receives the [G][S][2] difference sums: from wave-
-// private slabs and a reduction when the slabs fit the budget, else by atomic flushes
-// into D directly.  Dhi ([G][S], high parts) must be zero on entry.
+// Forward launch of one network.  D receives the [G][S][2] difference sums, by atomic
+// flushes of the windows into D directly or through wave-private slabs and a reduction
+// (see want_slabs).  Dhi ([G][S], high parts) must be zero on entry.
 ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int dev, hipStream_t st,
                           const double *user_rates, StreamScratch &scr, unsigned long long *D, float *kernel_ms) {
     const int32_t G = wl.net0.G, S = m->S;
+    if (m->order == SSA_SUM_BLOCK64) {
+        HIP_TRY(launch_zero(D, (size_t)G * S * 2 * sizeof(unsigned long long), st));
+        EventPair ev;
+        if (kernel_ms && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
+        HIP_TRY(launch_wave<kFwd>(m, wl, dev, st));
+        if (kernel_ms && ev.b) {
+            HIP_TRY(hipEventRecord(ev.b, st));
+            HIP_TRY(hipEventSynchronize(ev.b));
+            (void)hipEventElapsedTime(kernel_ms, ev.a, ev.b);
+        }
+        return SSA_OK;
+    }
     FwdKernel k;
     wl.win_bins = window_bins(S, G);
     wl.win_words = wl.win_bins * S * 2;
@@ -565,8 +605,7 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
     int64_t blocks = 0;
     HIP_TRY(fwd_blocks(k, true, dev, n_items, blocks));
     const size_t slab_bytes = (size_t)blocks * (kBlock / kWave) * cell_words * sizeof(unsigned long long);
-    const int choice = flush_choice();
-    const bool slab = choice == 1 || (choice < 0 && slab_bytes <= slab_budget());
+    const bool slab = want_slabs(slab_bytes);
     if (slab) {
         void *sl = nullptr;
         HIP_TRY(scr.alloc(&sl, slab_bytes));
@@ -600,9 +639,10 @@ extern "C" {
 const char *ssa_last_error(void) { return g_err.c_str(); }
 
 ssa_status ssa_model_create(int32_t S, int32_t M, const int32_t *reac, const int32_t *prod, const double *rates,
-                            const int32_t *x0, ssa_model **out) {
+                            const int32_t *x0, int32_t sum_order, ssa_model **out) {
     if (!out) return fail(SSA_E_INVALID, "out is NULL");
     *out = nullptr;
+    if (sum_order != SSA_SUM_SEQ && sum_order != SSA_SUM_BLOCK64) return fail(SSA_E_INVALID, "unknown sum order");
     if (S <= 0 || M <= 0 || S > kMaxSpecies || M > kMaxReactions)
         return fail(SSA_E_INVALID, "need 1 <= S <= %d and 1 <= M <= %d", kMaxSpecies, kMaxReactions);
     if (!reac || !prod || !rates || !x0) return fail(SSA_E_INVALID, "NULL model array");
@@ -610,6 +650,10 @@ ssa_status ssa_model_create(int32_t S, int32_t M, const int32_t *reac, const int
     if (!m) return fail(SSA_E_NOMEM, "host allocation failed");
     m->S = S;
     m->M = M;
+    m->order = sum_order;
+    m->q = (M + kWave - 1) / kWave;
+    if (sum_order == SSA_SUM_BLOCK64 && m->q > kWaveMaxQ)
+        return fail(SSA_E_UNSUPPORTED, "the 64-chunk sum order supports at most %d reactions", kWaveMaxQ * kWave);
     m->reac.assign(reac, reac + (size_t)M * S);
     m->prod.assign(prod, prod + (size_t)M * S);
     m->rate.assign(rates, rates + M);
@@ -649,8 +693,8 @@ ssa_status ssa_model_create(int32_t S, int32_t M, const int32_t *reac, const int
         }
         m->max_changes = std::max(m->max_changes, nchg);
     }
-    if (m->max_changes > kChg && (M > kJitMaxReactions || S > kJitMaxSpecies))
-        return fail(SSA_E_UNSUPPORTED, "a reaction changes more than %d species in a network too large to specialise",
+    if (m->max_changes > kChg && (M > kJitMaxReactions || S > kJitMaxSpecies || sum_order == SSA_SUM_BLOCK64))
+        return fail(SSA_E_UNSUPPORTED, "a reaction changes more than %d species in a network run by a table-driven kernel",
                     kChg);
     m->jit_src = generate_net_source(m.get());
     hipError_t e = hipGetDevice(&m->device);
@@ -786,7 +830,7 @@ ssa_status ssa_backward_device(const ssa_model *m, const double *rates, int64_t 
     if (!m) return fail(SSA_E_INVALID, "model is NULL");
     if (n_traj <= 0 || G <= 0 || !grid || !w || !mhat || !grad) return fail(SSA_E_INVALID, "bad argument");
     if (!(t_end >= 0.0) || !std::isfinite(t_end)) return fail(SSA_E_INVALID, "t_end must be finite and >= 0");
-    if (m->M > kJitMaxReactions)
+    if (m->order == SSA_SUM_SEQ && m->M > kJitMaxReactions)
         return fail(SSA_E_UNSUPPORTED, "backward supports at most %d reactions", kJitMaxReactions);
     if (n_traj > ((int64_t)1 << 31) * kChunk) return fail(SSA_E_INVALID, "n_traj too large");
     hipStream_t st = (hipStream_t)stream;
@@ -853,7 +897,8 @@ ssa_status ssa_record(const ssa_model *m, const double *rates, int64_t traj_begi
     if (count > ((int64_t)1 << 31) * kChunk) return fail(SSA_E_INVALID, "count too large");
     ssa_status s = validate_grid_host(grid, G, t_end);
     if (s) return s;
-    if (m->M > kJitMaxReactions) return fail(SSA_E_UNSUPPORTED, "record supports at most %d reactions", kJitMaxReactions);
+    if (m->order == SSA_SUM_SEQ && m->M > kJitMaxReactions)
+        return fail(SSA_E_UNSUPPORTED, "record supports at most %d reactions", kJitMaxReactions);
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     hipStream_t st = nullptr;
@@ -937,6 +982,7 @@ ssa_status ssa_batch_create(int32_t B, const ssa_model *const *models, const int
         if (s) return s;
         if (m->max_changes > kChg)
             return fail(SSA_E_UNSUPPORTED, "batched networks may change at most %d species per reaction", kChg);
+        if (m->order != SSA_SUM_SEQ) return fail(SSA_E_UNSUPPORTED, "batched networks use the sequential sum order");
         mmax = std::max(mmax, m->M);
         bt->s_rows = std::max(bt->s_rows, m->S);
         bt->m_rows = std::max(bt->m_rows, m->M);

@@ -91,7 +91,8 @@ struct NetDev {
     unsigned long long *D;
     unsigned long long *Dhi;
     int32_t *Hd;
-    int32_t h_species, h_lo, h_width, pad0;
+    int32_t h_species, h_lo, h_width;
+    int32_t q;               // 64-chunk sum order: reactions per lane (one trajectory per wave)
     // record
     int64_t rec_begin;
     int32_t *rec_states;

@@ -1,0 +1,274 @@
+// ssa_wave.hpp -- one trajectory per wave, for networks whose propensities are summed in
+// the 64-chunk order (the wavefront-level prefix sum of the selection step, Section 2).
+//
+// Lane l owns the reactions l q .. l q + q - 1 (q = ceil(M / 64)) and keeps their packed
+// reactant codes and rate constants in registers.  Per event every lane evaluates its
+// propensities and their sequential sum inside the chunk; the 64 chunk totals go through
+// a six-step inclusive Kogge-Stone scan across the wave (offsets 1, 2, 4, ..., 32), and
+// S_j = (scanned total of the chunks before l) + (local sum up to j).  The selected
+// reaction is the smallest j with S_j > u, found with one ballot over the lanes.  The
+// species counts live in LDS, one row per wave (row 0 holds the constant 1 that stands in
+// for a missing reactant, species s is row s + 1).
+//
+// The time bookkeeping (t, k, the grid index) is the same in every lane.  Forward events
+// add their moment differences straight to the network's totals with atomic adds (one
+// trajectory per wave leaves nothing to aggregate in a window).
+#pragma once
+
+#include "ssa_kernels.hpp"
+
+namespace ssa {
+
+__device__ __forceinline__ double wave_propensity(uint32_t code, double c, const int32_t *xl) {
+    const int32_t ra = (int32_t)(code & 0xfffu), rb = (int32_t)((code >> 12) & 0xfffu);
+    const int32_t d = (int32_t)(code >> 24);
+    const int32_t xa = xl[ra];
+    const int32_t xb = max(xl[rb] - d, 0);
+    const double f = d ? 0.5 : 1.0;
+    return c * (((double)xa * (double)xb) * f);
+}
+
+__device__ __forceinline__ double shfl_up_f64(double v, int d) {
+    return __shfl_up(v, (unsigned)d, kWave);
+}
+
+__device__ __forceinline__ double wave_sum_f64(double v) {
+    for (int off = 32; off > 0; off >>= 1) v = v + __shfl_xor(v, off, kWave);
+    return v;
+}
+
+// LDS: one row of (S + 1) int32 per wave.
+template <int Q, int MODE>
+__global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
+    extern __shared__ int32_t lds_w[];
+    const uint32_t lane = __lane_id();
+    const NetDev n = wl.net0;
+    const int32_t S = n.S, M = n.M, G = n.G, q = n.q;
+    int32_t *xl = lds_w + (threadIdx.x / kWave) * (S + 1);
+
+    // this lane's reactions
+    uint32_t code[Q];
+    double c[Q];
+    int32_t jr[Q];        // reaction index, or -1 for an empty slot
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int32_t j = (int32_t)lane * q + i;
+        const bool real = i < q && j < M;
+        jr[i] = real ? j : -1;
+        code[i] = real ? n.rx[j] : 0u;
+        c[i] = real ? n.rate[j] : 0.0;
+    }
+    const int32_t last_lane = (M - 1) / q, last_slot = (M - 1) - last_lane * q;
+
+    const GridInfo gi = *(const SSA_CONST GridInfo *)n.ginfo;
+    GridView gv;
+    gv.grid = n.grid;
+    gv.T = gi.T;
+    gv.D = gi.D;
+    gv.lo = gi.lo;
+    gv.scale = gi.scale;
+    gv.G = G;
+    gv.uniform = gi.uniform;
+
+    uint32_t flags = 0;
+    unsigned long long tot_events = 0, max_steps = 0;
+
+    for (;;) {
+        int32_t item = 0;
+        if (lane == 0) item = (int32_t)atomicAdd(wl.counter, 1u);
+        item = wave_uniform(__shfl(item, 0));
+        if ((int64_t)item >= wl.range_end - wl.range_begin) break;
+        const int64_t traj = wl.range_begin + item;
+
+        if (lane == 0) xl[0] = 1;
+        for (int32_t s = lane; s < S; s += kWave) xl[s + 1] = n.x0[s];
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+
+        double t = 0.0;
+        uint64_t k = 0, ev = 0;
+        int32_t g = 0;
+        double tg_next = G > 0 ? gv.at(0) : 0.0;
+        double A[MODE == kFwd ? 1 : Q], nf[MODE == kFwd ? 1 : Q], gacc[MODE == kBwd ? Q : 1];
+        if (MODE != kFwd) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) { A[i] = 0.0; nf[i] = 0.0; }
+        }
+        if (MODE == kBwd) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) gacc[i] = 0.0;
+        }
+        bool overflow = false;
+
+        for (;;) {
+            // propensities and the local sums of this lane's chunk
+            double a[Q], L[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                a[i] = wave_propensity(code[i], c[i], xl);
+                L[i] = i == 0 ? a[0] : L[i - 1] + a[i];       // empty slots add +0
+            }
+            // inclusive Kogge-Stone scan of the chunk totals, then the exclusive offsets
+            double v = L[Q - 1];
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const double up = shfl_up_f64(v, d);
+                if ((int)lane >= d) v = v + up;
+            }
+            double E = shfl_up_f64(v, 1);
+            if (lane == 0) E = 0.0;
+            double mine_last = 0.0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) mine_last = (i == last_slot) ? E + L[i] : mine_last;
+            const double a0 = wave_uniform(__shfl(mine_last, last_lane, kWave));
+
+            double tau = __builtin_inf(), r2 = 0.0;
+            if (a0 != 0.0) {
+                const u32x4 o = philox4x32_10((uint32_t)k, (uint32_t)(k >> 32), (uint32_t)traj,
+                                              (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
+                const double r1 = uniform_open0(o.v0, o.v1);
+                r2 = uniform_open1(o.v2, o.v3);
+                tau = neg_log(r1) / a0;
+                k = k + 1;
+            }
+            const double t_next = t + tau;
+
+            if (MODE == kRec) {
+                int32_t *rows = n.rec_states + (size_t)(traj - n.rec_begin) * G * S;
+                while (g < G && gv.at(g) < t_next) {
+                    for (int32_t s = lane; s < S; s += kWave) rows[(size_t)g * S + s] = xl[s + 1];
+                    ++g;
+                }
+            } else if (MODE == kBwd) {
+                if (g < G && gv.at(g) < t_next) {
+                    double alpha = 0.0, beta = 0.0;
+                    while (g < G) {
+                        const double tg = gv.at(g);
+                        if (!(tg < t_next)) break;
+                        const double *row = n.wm + (size_t)g * 2 * S;
+                        double part = 0.0;
+                        for (int32_t s = lane; s < S; s += kWave)
+                            part = part + row[s] * ((double)xl[s + 1] - row[S + s]);
+                        const double phi = wave_sum_f64(part);
+                        alpha = alpha + phi;
+                        beta = beta + phi * (tg - t);
+                        ++g;
+                    }
+#pragma unroll
+                    for (int i = 0; i < Q; ++i) gacc[i] = gacc[i] + ((nf[i] - A[i]) * alpha - a[i] * beta);
+                }
+            }
+
+            if (t_next > n.t_end) break;
+            if (ev >= n.max_events) {
+                flags |= kFlagEventLimit;
+                break;
+            }
+            // selection: smallest j with S_j > u, else the largest j with a_j > 0
+            const double u = r2 * a0;
+            int32_t first = -1, lastpos = -1;
+#pragma unroll
+            for (int i = Q - 1; i >= 0; --i) {
+                if (jr[i] >= 0 && E + L[i] > u) first = jr[i];
+                if (lastpos < 0 && jr[i] >= 0 && a[i] > 0.0) lastpos = jr[i];
+            }
+            int32_t sel;
+            const uint64_t hit = __ballot(first >= 0);
+            if (hit) {
+                sel = __shfl(first, __ffsll((unsigned long long)hit) - 1, kWave);
+            } else {
+                const uint64_t pos = __ballot(lastpos >= 0);
+                sel = pos ? __shfl(lastpos, 63 - __clzll((unsigned long long)pos), kWave) : M - 1;
+            }
+            sel = wave_uniform(sel);
+
+            // grid bin of the event (forward)
+            int32_t bin = G;
+            if (MODE == kFwd) {
+                bin = g;
+                if (g < G && t_next > tg_next) bin = gv.next_bin(g, t_next, tg_next);
+            }
+            // apply: lanes 0 .. kChg-1 take one change slot each (distinct species)
+            if ((int)lane < kChg) {
+                const int32_t cv = n.chg[sel * kChg + lane];
+                const int32_t r = chg_row(cv), dl = chg_delta(cv);
+                if (dl != 0) {
+                    const int32_t xo = xl[r];
+                    const int64_t xw = (int64_t)xo + dl;
+                    overflow = xw > 2147483647ll || xw < -2147483647ll - 1;
+                    const int32_t xn = (int32_t)xw;
+                    xl[r] = xn;
+                    if (MODE == kFwd && bin < G && !overflow) {
+                        const int32_t sp = r - 1;
+                        unsigned long long *dd = n.D + ((size_t)bin * S + sp) * 2;
+                        const long long d2 = (2ll * xo + dl) * (long long)dl;
+                        atomicAdd(dd, (unsigned long long)(long long)dl);
+                        if (d2 > -kSmallD2 && d2 < kSmallD2) {
+                            atomicAdd(dd + 1, (unsigned long long)d2);
+                        } else {
+                            atomicAdd(dd + 1, (unsigned long long)(d2 & ((1ll << 24) - 1)));
+                            atomicAdd(n.Dhi + (size_t)bin * S + sp, (unsigned long long)(d2 >> 24));
+                        }
+                        if (n.Hd && sp == n.h_species) {
+                            const int32_t bo = xo < n.h_lo ? 0 : min((xo - n.h_lo) / n.h_width, n.nb_hist - 1);
+                            const int32_t bn = xn < n.h_lo ? 0 : min((xn - n.h_lo) / n.h_width, n.nb_hist - 1);
+                            if (bo != bn) {
+                                atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bo, -1);
+                                atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bn, 1);
+                            }
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (__ballot(overflow)) {
+                flags |= kFlagOverflow;
+                break;
+            }
+            if (MODE != kFwd) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    A[i] = A[i] + a[i] * tau;
+                    nf[i] = nf[i] + (jr[i] == sel ? 1.0 : 0.0);
+                }
+            }
+            t = t_next;
+            ev = ev + 1;
+            if (MODE == kFwd) g = bin;
+        }
+
+        if (MODE == kRec) {
+            const int64_t r = traj - n.rec_begin;
+            if (lane == 0) {
+                n.rec_events[r] = ev;
+                n.rec_draws[r] = k;
+                n.rec_tlast[r] = t;
+            }
+            // final propensities for the last partial interval of A_j
+            const double tail = n.t_end - t;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                if (jr[i] < 0) continue;
+                if (n.rec_nf) n.rec_nf[r * M + jr[i]] = (int64_t)nf[i];
+                if (n.rec_aint) n.rec_aint[r * M + jr[i]] = A[i] + wave_propensity(code[i], c[i], xl) * tail;
+            }
+        }
+        if (MODE == kBwd) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i)
+                if (jr[i] >= 0) n.gtraj[(size_t)traj * M + jr[i]] = gacc[i];
+        }
+        tot_events += ev;
+        max_steps = max(max_steps, (unsigned long long)ev);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (lane == 0) {
+        if (tot_events) atomicAdd(wl.stats + 0, tot_events);
+        atomicMax(wl.stats + 1, max_steps);
+        if (flags) atomicOr(wl.stats + 2, (unsigned long long)flags);
+    }
+}
+
+}  // namespace ssa

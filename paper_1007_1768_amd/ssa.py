@@ -55,7 +55,7 @@ def load(path=None):
         raise ImportError("libssa.so not built (%s); run __graft_entry__.build()" % path)
     L = ctypes.CDLL(path)
     vp, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
-    L.ssa_model_create.argtypes = [i32, i32, vp, vp, vp, vp, ctypes.POINTER(vp)]
+    L.ssa_model_create.argtypes = [i32, i32, vp, vp, vp, vp, i32, ctypes.POINTER(vp)]
     L.ssa_model_destroy.argtypes = [vp]
     L.ssa_model_destroy.restype = None
     L.ssa_run.argtypes = [vp, i64, dbl, vp, i32, u64, vp, vp, vp]
@@ -95,10 +95,15 @@ def _stream(stream):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-class Model:
-    """A mass-action network on the current device (ssa_model_create)."""
+SUM_ORDERS = {"seq": 0, "block64": 1}
 
-    def __init__(self, reac, prod, rates, x0):
+
+class Model:
+    """A mass-action network on the current device (ssa_model_create).  sum_order: "seq"
+    (left-to-right propensity sums, one trajectory per lane) or "block64" (64-chunk sums,
+    one trajectory per wave)."""
+
+    def __init__(self, reac, prod, rates, x0, sum_order="seq"):
         L = load()
         self.reac = np.ascontiguousarray(reac, dtype=np.int32)
         self.prod = np.ascontiguousarray(prod, dtype=np.int32)
@@ -106,13 +111,14 @@ class Model:
         self.x0 = np.ascontiguousarray(x0, dtype=np.int32)
         self.M, self.S = self.reac.shape
         h = ctypes.c_void_p()
+        self.sum_order = sum_order
         _check(L.ssa_model_create(self.S, self.M, _p(self.reac), _p(self.prod), _p(self.rates), _p(self.x0),
-                                  ctypes.byref(h)))
+                                  SUM_ORDERS[sum_order], ctypes.byref(h)))
         self.handle = h
 
     @classmethod
     def from_dict(cls, m):
-        return cls(m["reac"], m["prod"], m["rates"], m["x0"])
+        return cls(m["reac"], m["prod"], m["rates"], m["x0"], m.get("sum_order", "seq"))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -40,7 +40,7 @@ def test_library_exports_every_declared_symbol(lib):
 def test_invalid_models_rejected_before_device_use(lib):
     m = dict(reac=np.array([[3]], np.int32), prod=np.array([[0]], np.int32), rates=np.array([1.0]),
              x0=np.array([1], np.int32))
-    for bad in ("order", "neg_rate", "nan_rate", "neg_x0", "big_product", "empty"):
+    for bad in ("order", "neg_rate", "nan_rate", "neg_x0", "big_product", "empty", "sum_order"):
         reac, prod, rates, x0 = (m["reac"].copy(), m["prod"].copy(), m["rates"].copy(), m["x0"].copy())
         reac[0, 0] = 1
         if bad == "order":
@@ -55,8 +55,9 @@ def test_invalid_models_rejected_before_device_use(lib):
             prod[0, 0] = 2**21
         h = ctypes.c_void_p()
         S = 0 if bad == "empty" else 1
+        order = 7 if bad == "sum_order" else 0
         st = lib.ssa_model_create(S, 1, reac.ctypes.data, prod.ctypes.data, rates.ctypes.data, x0.ctypes.data,
-                                  ctypes.byref(h))
+                                  order, ctypes.byref(h))
         assert st == ssa.E_INVALID, bad
         assert h.value is None
         assert lib.ssa_last_error()

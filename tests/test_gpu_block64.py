@@ -1,0 +1,154 @@
+"""GPU parity of the one-trajectory-per-wave kernels (64-chunk propensity sums).
+
+Networks from one reaction per chunk (M <= 64) to eight per chunk (M = 450): record mode
+bit-identical to the oracle (states, events, draws, last event time, n_j, A_j); forward
+mean and variance equal to the oracle's; the backward gradient within 1e-12 of the
+oracle's L1 scale.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1007_1768_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ssa():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1007_1768_amd import ssa as s
+    s.load()
+    return s
+
+
+def _b64(m):
+    m = dict(m)
+    m["sum_order"] = "block64"
+    return m
+
+
+def _chain_network(M, S, seed, scale=0.37):
+    """M reactions over S species: inflows, degradations, conversions and bindings, with
+    non-integer rates (so the two sum orders round differently)."""
+    rng = np.random.default_rng(seed)
+    reac = np.zeros((M, S), np.int32)
+    prod = np.zeros((M, S), np.int32)
+    for j in range(M):
+        a, b = (int(v) for v in rng.integers(0, S, size=2))
+        if b == a:
+            b = (a + 1) % S
+        kind = j % 4
+        if kind == 0:
+            prod[j, a] = 1
+        elif kind == 1:
+            reac[j, a] = 1
+        elif kind == 2:
+            reac[j, a] = 1
+            prod[j, b] = 1
+        else:
+            reac[j, a] = 1
+            reac[j, b] = 1
+            prod[j, a] = 1
+    rates = rng.integers(1, 8, size=M).astype(np.float64) * scale
+    rates[3::4] *= 0.01
+    return _b64(dict(name="chain", species=["S%d" % s for s in range(S)], reac=reac, prod=prod, rates=rates,
+                     x0=rng.integers(0, 60, size=S).astype(np.int32)))
+
+
+def _big_random():
+    nets = [n for n in inputs.random_networks(count=16) if n["reac"].shape[0] > 64]
+    return _b64(nets[0])
+
+
+CASES = {
+    "viral_q1": (_b64(inputs.viral()), 2, 20.0, 201),
+    "random_q2": (_big_random(), 7, 0.3, 13),
+    "chain150_q3": (_chain_network(150, 12, 1), 3, 1.0, 21),
+    "chain450_q8": (_chain_network(450, 30, 2), 4, 0.5, 11),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_record_bit_exact_block64(ssa, case):
+    m, seed, t_end, G = CASES[case]
+    grid = inputs.uniform_grid(t_end, G)
+    model = ssa.Model.from_dict(m)
+    n = 70
+    st, rec = ssa.record(model, 0, n, t_end, grid, seed)
+    model.close()
+    assert st == 0
+    for i in range(n):
+        s2, r = orc.trajectory(m, seed, i, t_end, grid)
+        assert s2 == 0
+        assert np.array_equal(rec["states"][i], r["states"]), ("states", i)
+        assert int(rec["events"][i]) == r["events"], ("events", i)
+        assert int(rec["draws"][i]) == r["draws"], ("draws", i)
+        assert rec["t_last"][i] == r["t_last"], ("t_last", i)
+        assert np.array_equal(rec["n_fired"][i], r["n_fired"]), ("n_fired", i)
+        assert np.array_equal(rec["a_int"][i], r["a_int"]), ("a_int", i)
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_forward_block64(ssa, case):
+    m, seed, t_end, G = CASES[case]
+    grid = inputs.uniform_grid(t_end, G)
+    N = 515
+    hist = (0, 0, 3, 40)
+    model = ssa.Model.from_dict(m)
+    mean, var, h, stats = ssa.run_device(model, N, t_end, torch.tensor(grid, device=DEV), seed, hist=hist,
+                                         with_stats=True)
+    torch.cuda.synchronize()
+    model.close()
+    st, ref = orc.run(m, N, t_end, grid, seed, hist=hist)
+    assert st == 0
+    assert np.array_equal(mean.cpu().numpy(), ref["mean"])
+    assert np.array_equal(var.cpu().numpy(), ref["var"])
+    assert np.array_equal(h.cpu().numpy().astype(np.int64), ref["hist"].astype(np.int64))
+    assert stats["events"] == ref["events"]
+
+
+@pytest.mark.parametrize("case", ["viral_q1", "chain150_q3"])
+def test_backward_block64(ssa, case):
+    m, seed, t_end, G = CASES[case]
+    grid = inputs.uniform_grid(t_end, G)
+    N = 300
+    st, ref = orc.run(m, N, t_end, grid, seed)
+    assert st == 0
+    w = np.random.default_rng(seed).normal(size=ref["mean"].shape)
+    model = ssa.Model.from_dict(m)
+    grad, stats = ssa.backward_device(model, N, t_end, torch.tensor(grid, device=DEV), seed,
+                                      torch.tensor(w, device=DEV), torch.tensor(ref["mean"], device=DEV),
+                                      with_stats=True)
+    torch.cuda.synchronize()
+    model.close()
+    st, gref, l1 = orc.grad(m, N, t_end, grid, seed, w, ref["mean"])
+    assert st == 0
+    g = grad.cpu().numpy()
+    assert np.all(np.abs(g - gref) <= 1e-12 * l1), (np.max(np.abs(g - gref) / np.maximum(l1, 1e-300)))
+    assert stats["events"] == ref["events"]
+
+
+def test_block64_limits(ssa):
+    m = _chain_network(520, 8, 3)
+    with pytest.raises(ssa.SSAError) as e:
+        ssa.Model.from_dict(m)
+    assert e.value.status == ssa.E_UNSUPPORTED
+    ok = ssa.Model.from_dict(_b64(inputs.viral()))
+    with pytest.raises(ssa.SSAError) as e:
+        ssa.Batch([ok], [64], [1.0], [np.array([0.0, 1.0])], [1])
+    assert e.value.status == ssa.E_UNSUPPORTED
+    ok.close()
+
+
+def test_block64_overflow_reported(ssa):
+    m = _b64(inputs._model("grow", ["X"], [({}, {"X": 1}, 1.0)], [2**31 - 10]))
+    model = ssa.Model.from_dict(m)
+    g = torch.tensor([1000.0], dtype=torch.float64, device=DEV)
+    with pytest.raises(ssa.SSAError) as e:
+        ssa.run_device(model, 64, 1000.0, g, 1, with_stats=True)
+    assert e.value.status == ssa.E_OVERFLOW
+    model.close()
