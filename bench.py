@@ -4,14 +4,21 @@ CPU oracle as a reported baseline.
 One step is the whole hot path over one batch of synthetic input: the forward pass
 (trajectories, grid alignment, cross-trajectory mean and variance) followed by the
 likelihood-ratio backward pass of a squared-error loss on the grid means (re-simulating
-the same trajectories).  Both run through the library's persistent work-stealing kernel.
+the same trajectories).  Both run through the library's persistent work-stealing kernels.
+value = forward events per step / step time: the backward's re-simulated events are
+reported beside it, never added.
+
+Beside the step, the line reports the batched form against plain launches: the 64 random
+networks of the batched workload (5-40 species, 10-120 reactions, 256-16384 trajectories
+each, 200-point grids) as one graph-replayed persistent launch, against one plain launch
+per network through the same table-driven kernel; the results are checked bit-identical.
 
 Default workload: the 4-species viral network, 10^4 trajectories, t_end = 50, 1000-point
 grid; the loss target is the mean of the same network with log rates perturbed by
 N(0, 0.1^2) (computed once, outside the timed region).
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload viral|differentiated|large]
-       [--no-cpu-baseline] [--copy-calibration]
+       [--no-cpu-baseline] [--no-batched] [--copy-calibration]
 """
 import argparse
 import json
@@ -104,6 +111,48 @@ def stored_traffic(kernel, workload_name):
         return None
 
 
+def batched_vs_plain(ssa, torch, dev):
+    """The batched workload as one graph-replayed launch and as one plain launch per network."""
+    nets = inputs.random_networks()
+    models = [ssa.Model.from_dict(n) for n in nets]
+    grids = [torch.tensor(n["grid"], device=dev) for n in nets]
+    means = [torch.empty((len(n["grid"]), n["reac"].shape[1]), dtype=torch.float64, device=dev) for n in nets]
+    vars_ = [torch.empty_like(v) for v in means]
+    batch = ssa.Batch(models, [n["n_traj"] for n in nets], [n["t_end"] for n in nets], [n["grid"] for n in nets],
+                      [n["seed"] for n in nets])
+    batch.run(dev, outs=(means, vars_))                       # capture + warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, st = batch.run(dev, outs=(means, vars_), with_stats=True)
+    torch.cuda.synchronize()
+    batched_s = time.perf_counter() - t0
+    saved = os.environ.get("SSA_KERNEL")
+    os.environ["SSA_KERNEL"] = "generic"                      # the batched kernel's code path
+    identical = True
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plain = [ssa.run_device(models[b], n["n_traj"], n["t_end"], grids[b], n["seed"])[:2]
+                 for b, n in enumerate(nets)]
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - t0
+        for b, (pm, pv) in enumerate(plain):
+            identical &= bool(torch.equal(pm, means[b]) and torch.equal(pv, vars_[b]))
+    finally:
+        if saved is None:
+            os.environ.pop("SSA_KERNEL", None)
+        else:
+            os.environ["SSA_KERNEL"] = saved
+    batch.close()
+    for mo in models:
+        mo.close()
+    return {"workload": "64 random networks, 5-40 species, 10-120 reactions, %d trajectories, 200-point grids"
+                        % sum(n["n_traj"] for n in nets),
+            "events": st["events"], "batched_ms": round(batched_s * 1e3, 3), "plain_ms": round(plain_s * 1e3, 3),
+            "batched_events_per_s": round(st["events"] / batched_s, 1),
+            "speedup": round(plain_s / batched_s, 3), "identical": identical}
+
+
 def workload(name):
     w = dict(inputs.WORKLOADS[name])
     m = w["model"]()
@@ -117,6 +166,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="viral", choices=["viral", "differentiated", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched / plain comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -187,8 +237,7 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     step_ms = e0.elapsed_time(e1) / args.steps
-    ev_per_step = stats_f["events"] + stats_b["events"]
-    value = ev_per_step / (step_ms * 1e-3)
+    value = stats_f["events"] / (step_ms * 1e-3)
 
     # forward-only timing (same kernels, no backward), for the grad / plain ratio
     f_only = []
@@ -244,6 +293,9 @@ def main():
         "roofline": roofline,
     }
 
+    if not args.no_batched:
+        out["batched_vs_plain"] = batched_vs_plain(ssa, torch, dev)
+
     if not args.no_cpu_baseline:
         from oracle import oracle as orc
         thr = orc.default_threads()
@@ -257,7 +309,7 @@ def main():
             st, ref = orc.run(m, n_cpu, t_end, grid_np, seed, hist=hist, threads=thr)
             st2, g, _ = orc.grad(m, n_cpu, t_end, grid_np, seed, 2.0 * (ref["mean"] - tw), ref["mean"],
                                  threads=thr)
-            cpu_events += 2 * ref["events"]
+            cpu_events += ref["events"]
             reps += 1
             if time.perf_counter() - a0 >= 10.0:
                 break

@@ -165,6 +165,15 @@ struct ssa_batch {
     unsigned int *d_counter = nullptr;
     unsigned long long *d_stats = nullptr;
     GridInfo *d_ginfo = nullptr;
+    // finalize table (one entry per network; the output pointers of the last run)
+    std::vector<FinalNet> fin;
+    FinalNet *d_fin = nullptr;
+    int32_t *d_block_net = nullptr, *d_block_species = nullptr;
+    int32_t n_fin_blocks = 0;
+    // the launch sequence captured as a graph on first use, replayed afterwards
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -1030,15 +1039,38 @@ ssa_status ssa_batch_create(int32_t B, const ssa_model *const *models, const int
     HIP_TRY(hipMemcpy(bt->d_item_net, item_net.data(), sizeof(int32_t) * bt->n_items, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(bt->d_item_begin, item_begin.data(), sizeof(int64_t) * bt->n_items, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(bt->d_item_count, item_count.data(), sizeof(int32_t) * bt->n_items, hipMemcpyHostToDevice));
+    // finalize tables: one block per (network, species)
+    std::vector<int32_t> bn, bs;
+    bt->fin.resize(B);
+    for (int32_t b = 0; b < B; ++b) {
+        FinalNet &f = bt->fin[b];
+        f.D = bt->d_D + bt->D_off[b];
+        f.Dhi = f.D + (size_t)2 * n_grid[b] * models[b]->S;
+        f.x0 = models[b]->d_x0;
+        f.mean = f.var = nullptr;
+        f.n_traj = n_traj[b];
+        f.G = n_grid[b];
+        f.S = models[b]->S;
+        for (int32_t s = 0; s < f.S; ++s) {
+            bn.push_back(b);
+            bs.push_back(s);
+        }
+    }
+    bt->n_fin_blocks = (int32_t)bn.size();
+    HIP_TRY(hipMalloc(&bt->d_fin, sizeof(FinalNet) * B));
+    HIP_TRY(hipMalloc(&bt->d_block_net, sizeof(int32_t) * bn.size()));
+    HIP_TRY(hipMalloc(&bt->d_block_species, sizeof(int32_t) * bs.size()));
+    HIP_TRY(hipMemcpy(bt->d_block_net, bn.data(), sizeof(int32_t) * bn.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(bt->d_block_species, bs.data(), sizeof(int32_t) * bs.size(), hipMemcpyHostToDevice));
     *out = bt.release();
     return SSA_OK;
 }
 
-ssa_status ssa_batch_run(ssa_batch *bt, double *const *means, double *const *vars, void *stream, ssa_stats *stats) {
-    if (!bt || !means || !vars) return fail(SSA_E_INVALID, "NULL argument");
-    for (int32_t b = 0; b < bt->B; ++b)
-        if (!means[b] || !vars[b]) return fail(SSA_E_INVALID, "output %d is NULL", b);
-    hipStream_t st = (hipStream_t)stream;
+namespace {
+
+// The launch sequence of one batched run: zero the sums and the work counter, the
+// persistent kernel over all networks, one finalize launch for all networks.
+ssa_status batch_enqueue(ssa_batch *bt, hipStream_t st) {
     HIP_TRY(launch_zero(bt->d_D, sizeof(unsigned long long) * bt->D_words, st));
     HIP_TRY(launch_zero(bt->d_counter, 64, st));
     WorkList wl;
@@ -1062,16 +1094,63 @@ ssa_status ssa_batch_run(ssa_batch *bt, double *const *means, double *const *var
             (size_t)(kBlock / kWave) * wl.win_words * sizeof(long long);
     int64_t blocks = 0;
     HIP_TRY(fwd_blocks(k, false, bt->device, bt->n_items, blocks));
+    HIP_TRY(fwd_launch(k, false, blocks, wl, st));
+    hipLaunchKernelGGL(moment_final_batched_kernel, dim3((unsigned)bt->n_fin_blocks), dim3(1024), 0, st,
+                       (const FinalNet *)bt->d_fin, (const int32_t *)bt->d_block_net,
+                       (const int32_t *)bt->d_block_species);
+    HIP_TRY(hipGetLastError());
+    return SSA_OK;
+}
+
+// Graph replay is the default; SSA_BATCH_GRAPH=0 launches the same sequence directly.
+bool batch_use_graph() {
+    const char *e = std::getenv("SSA_BATCH_GRAPH");
+    return !(e && std::strcmp(e, "0") == 0);
+}
+
+}  // namespace
+
+ssa_status ssa_batch_run(ssa_batch *bt, double *const *means, double *const *vars, void *stream, ssa_stats *stats) {
+    if (!bt || !means || !vars) return fail(SSA_E_INVALID, "NULL argument");
+    for (int32_t b = 0; b < bt->B; ++b)
+        if (!means[b] || !vars[b]) return fail(SSA_E_INVALID, "output %d is NULL", b);
+    hipStream_t st = (hipStream_t)stream;
+    // output pointers live in the device finalize table, so a captured graph stays valid
+    // when they change; the table is rewritten only then, after the stream is idle
+    bool changed = false;
+    for (int32_t b = 0; b < bt->B; ++b) changed |= bt->fin[b].mean != means[b] || bt->fin[b].var != vars[b];
+    if (changed) {
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int32_t b = 0; b < bt->B; ++b) {
+            bt->fin[b].mean = means[b];
+            bt->fin[b].var = vars[b];
+        }
+        HIP_TRY(hipMemcpy(bt->d_fin, bt->fin.data(), sizeof(FinalNet) * bt->B, hipMemcpyHostToDevice));
+    }
     EventPair ev;
     if (stats && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
-    HIP_TRY(fwd_launch(k, false, blocks, wl, st));
-    if (stats && ev.b) HIP_TRY(hipEventRecord(ev.b, st));
-    for (int32_t b = 0; b < bt->B; ++b) {
-        const ssa_model *m = bt->models[b];
-        const unsigned long long *D = bt->d_D + bt->D_off[b];
-        HIP_TRY(launch_finalize(D, D + (size_t)2 * bt->G[b] * m->S, bt->G[b], m->S, m->d_x0, bt->n_traj[b],
-                                means[b], vars[b], st));
+    if (batch_use_graph()) {
+        if (!bt->exec) {
+            // capture on a private stream (the caller's may be the null stream)
+            if (!bt->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&bt->cap_stream, hipStreamNonBlocking));
+            HIP_TRY(hipStreamBeginCapture(bt->cap_stream, hipStreamCaptureModeThreadLocal));
+            ssa_status s = batch_enqueue(bt, bt->cap_stream);
+            hipGraph_t g = nullptr;
+            const hipError_t ce = hipStreamEndCapture(bt->cap_stream, &g);
+            if (s) {
+                if (g) (void)hipGraphDestroy(g);
+                return s;
+            }
+            HIP_TRY(ce);
+            bt->graph = g;
+            HIP_TRY(hipGraphInstantiate(&bt->exec, bt->graph, nullptr, nullptr, 0));
+        }
+        HIP_TRY(hipGraphLaunch(bt->exec, st));
+    } else {
+        ssa_status s = batch_enqueue(bt, st);
+        if (s) return s;
     }
+    if (stats && ev.b) HIP_TRY(hipEventRecord(ev.b, st));
     if (stats) return collect_stats(bt->d_stats, st, ev.a, ev.b, stats);
     return SSA_OK;
 }
@@ -1086,6 +1165,12 @@ void ssa_batch_destroy(ssa_batch *bt) {
     if (bt->d_item_net) (void)hipFree(bt->d_item_net);
     if (bt->d_item_begin) (void)hipFree(bt->d_item_begin);
     if (bt->d_item_count) (void)hipFree(bt->d_item_count);
+    if (bt->d_fin) (void)hipFree(bt->d_fin);
+    if (bt->d_block_net) (void)hipFree(bt->d_block_net);
+    if (bt->d_block_species) (void)hipFree(bt->d_block_species);
+    if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
+    if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
     delete bt;
 }
 

@@ -250,12 +250,11 @@ __global__ void slab_reduce_kernel(const unsigned long long *__restrict__ slabs,
 // and from them the moments with one rounding each:
 //   mean = Sx / N,   var = (N Sx2 - Sx^2) / (N (N - 1))  (0 when N == 1).
 // Optionally also writes the totals as (Sx hi, Sx lo, Sx2 hi, Sx2 lo) 128-bit pairs.
-__global__ void __launch_bounds__(1024) moment_final_kernel(const unsigned long long *__restrict__ D,
-                                                            const unsigned long long *__restrict__ Dhi, int32_t G,
-                                                            int32_t S, const int32_t *__restrict__ x0,
-                                                            int64_t n_traj, double *__restrict__ mean,
-                                                            double *__restrict__ var, int64_t *__restrict__ sums) {
-    const int32_t s = blockIdx.x;
+__device__ __forceinline__ void moment_final_body(const unsigned long long *__restrict__ D,
+                                                  const unsigned long long *__restrict__ Dhi, int32_t G, int32_t S,
+                                                  int32_t s, const int32_t *__restrict__ x0, int64_t n_traj,
+                                                  double *__restrict__ mean, double *__restrict__ var,
+                                                  int64_t *__restrict__ sums) {
     const int32_t nt = blockDim.x;
     const int32_t per = (G + nt - 1) / nt;
     const int32_t g0 = min(G, (int32_t)threadIdx.x * per), g1 = min(G, g0 + per);
@@ -310,6 +309,32 @@ __global__ void __launch_bounds__(1024) moment_final_kernel(const unsigned long 
             sums[4 * q + 3] = (int64_t)sx2.lo;
         }
     }
+}
+
+// One block of 1024 threads per species.
+__global__ void __launch_bounds__(1024) moment_final_kernel(const unsigned long long *__restrict__ D,
+                                                            const unsigned long long *__restrict__ Dhi, int32_t G,
+                                                            int32_t S, const int32_t *__restrict__ x0,
+                                                            int64_t n_traj, double *__restrict__ mean,
+                                                            double *__restrict__ var, int64_t *__restrict__ sums) {
+    moment_final_body(D, Dhi, G, S, blockIdx.x, x0, n_traj, mean, var, sums);
+}
+
+// Finalize of every network of a batch in one launch: block i handles species
+// block_species[i] of network block_net[i].
+struct FinalNet {
+    const unsigned long long *D, *Dhi;
+    const int32_t *x0;
+    double *mean, *var;
+    int64_t n_traj;
+    int32_t G, S;
+};
+
+__global__ void __launch_bounds__(1024) moment_final_batched_kernel(const FinalNet *__restrict__ nets,
+                                                                    const int32_t *__restrict__ block_net,
+                                                                    const int32_t *__restrict__ block_species) {
+    const FinalNet f = nets[block_net[blockIdx.x]];
+    moment_final_body(f.D, f.Dhi, f.G, f.S, block_species[blockIdx.x], f.x0, f.n_traj, f.mean, f.var, nullptr);
 }
 
 // Histogram: inclusive prefix over g of the bin differences plus N in the initial bin.

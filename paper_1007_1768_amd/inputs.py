@@ -66,11 +66,14 @@ def viral(rates=None):
 
 
 def uniform_grid(t_end, G):
-    """t_g = (t_end * g) / (G - 1): one product, then one quotient, in binary64."""
+    """t_g = (t_end * g) / (G - 1): one product, then one quotient, in binary64; the last
+    point is t_end itself (the two roundings can otherwise put it one ulp above t_end)."""
     if G == 1:
         return np.array([float(t_end)])
     g = np.arange(G, dtype=np.float64)
-    return (float(t_end) * g) / float(G - 1)
+    grid = (float(t_end) * g) / float(G - 1)
+    grid[-1] = float(t_end)
+    return grid
 
 
 def random_networks(seed=20100701, count=64, G=200):

@@ -107,3 +107,42 @@ def test_batched_equals_plain_and_oracle(ssa):
     batch.close()
     for mo in models:
         mo.close()
+
+
+def test_batched_graph_replays_match_direct_launches(ssa, monkeypatch):
+    """The batched sequence is captured as a graph on first use and replayed; every replay,
+    with unrelated device work and synchronisations in between, equals the directly
+    launched sequence, also after the output buffers change."""
+    nets = [dict(inputs.viral(), t_end=10.0, n_traj=700, grid=inputs.uniform_grid(10.0, 120), seed=21)]
+    for n in inputs.random_networks(count=30):
+        if len(nets) < 5:
+            n = dict(n)
+            n["t_end"] = min(n["t_end"], 0.5)
+            n["grid"] = inputs.uniform_grid(n["t_end"], 40)
+            n["n_traj"] = min(n["n_traj"], 400)
+            nets.append(n)
+    models = [ssa.Model.from_dict(n) for n in nets]
+    args = ([n["n_traj"] for n in nets], [n["t_end"] for n in nets], [n["grid"] for n in nets],
+            [n["seed"] for n in nets])
+    monkeypatch.setenv("SSA_BATCH_GRAPH", "0")
+    direct = ssa.Batch(models, *args)
+    dm, dv, dst = direct.run(DEV, with_stats=True)
+    torch.cuda.synchronize()
+    direct.close()
+    monkeypatch.delenv("SSA_BATCH_GRAPH")
+    batch = ssa.Batch(models, *args)
+    outs = ([torch.empty_like(m) for m in dm], [torch.empty_like(v) for v in dv])
+    for rep in range(4):
+        if rep == 2:
+            outs = ([torch.full_like(m, -1.0) for m in dm], [torch.full_like(v, -1.0) for v in dv])
+        means, vars_, st = batch.run(DEV, outs=outs, with_stats=True)
+        torch.cuda.synchronize()
+        for b in range(len(nets)):
+            assert torch.equal(means[b], dm[b]) and torch.equal(vars_[b], dv[b]), (rep, b)
+        assert st["events"] == dst["events"]
+        x = torch.randn(1 << 16, device=DEV, dtype=torch.float64)
+        float((x * 2.0).sum())
+        torch.cuda.synchronize()
+    batch.close()
+    for mo in models:
+        mo.close()
