@@ -848,22 +848,20 @@ ssa_status ssa_backward_device(const ssa_model *m, const double *rates, int64_t 
     keep_pool(dev);
     StreamScratch scr(st);
     NetDev n = base_net(m, rates, n_traj, t_end, grid, G, seed, max_events);
-    void *gt = nullptr, *gt2 = nullptr, *ctl = nullptr, *wm = nullptr;
+    void *gt = nullptr, *gt2 = nullptr, *ctl = nullptr, *bp = nullptr;
     const size_t rows_bytes = sizeof(double) * (size_t)n_traj * m->M;
-    HIP_TRY(scr.alloc(&wm, sizeof(double) * 2 * (size_t)G * m->S));
+    const int32_t ncol = 2 * m->S + 2;
+    HIP_TRY(scr.alloc(&bp, sizeof(double) * 2 * ncol * ((size_t)G + 1)));
     HIP_TRY(scr.alloc(&gt, rows_bytes));
     HIP_TRY(scr.alloc(&gt2, rows_bytes / 2 + sizeof(double) * m->M));
     HIP_TRY(scr.alloc(&ctl, 64 + sizeof(GridInfo)));
     HIP_TRY(launch_zero(ctl, 64, st));
     n.ginfo = (const GridInfo *)((char *)ctl + 64);
     HIP_TRY(launch_grid_info(grid, G, t_end, (GridInfo *)n.ginfo, st));
-    {
-        const int64_t cells = (int64_t)G * m->S;
-        hipLaunchKernelGGL(pack_wm_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, w, mhat, G, m->S,
-                           (double *)wm);
-        HIP_TRY(hipGetLastError());
-    }
-    n.wm = (const double *)wm;
+    hipLaunchKernelGGL(bwd_prefix_kernel, dim3((unsigned)ncol), dim3(256), 0, st, w, mhat, grid, G, m->S,
+                       (double *)bp);
+    HIP_TRY(hipGetLastError());
+    n.bp = (const double *)bp;
     n.gtraj = (double *)gt;
     WorkList wl;
     std::memset(&wl, 0, sizeof wl);

@@ -134,14 +134,70 @@ __global__ void __launch_bounds__(kBlock) fwd_kernel(WorkList wl) {
     sim_fwd<MM, BATCH, SLAB>(wl, p, win);
 }
 
-// Backward input rows [G][2S]: w_g followed by mhat_g, so one crossing reads one row.
-__global__ void pack_wm_kernel(const double *__restrict__ w, const double *__restrict__ mhat, int32_t G, int32_t S,
-                               double *__restrict__ wm) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)G * S) return;
-    const int64_t g = idx / S, s = idx % S;
-    wm[g * 2 * S + s] = w[idx];
-    wm[g * 2 * S + S + s] = mhat[idx];
+// Backward prefix table.  With c_g = sum_s w_gs mhat_gs the per-crossing weight is
+// phi_g = sum_s w_gs x_s - c_g, so the sums a backward interval needs over its crossings
+// g in [ga, gb),
+//   alpha = sum phi_g = sum_s x_s dW_s - dC,
+//   beta  = sum phi_g (t_g - t) = sum_s x_s (dWT_s - t dW_s) - (dCT - t dC),
+// come from differences of prefix sums (over g' < g) of the 2S + 2 columns
+//   W_s = w_gs,  WT_s = w_gs t_g,  C = c_g,  CT = c_g t_g.
+// The prefixes are kept as unevaluated double-double sums (hi + lo), so a difference of
+// two rows loses nothing to cancellation.  Row g (0 <= g <= G) holds the hi parts of the
+// 2S + 2 columns followed by their lo parts.
+__device__ __forceinline__ double bwd_column(const double *w, const double *mhat, const double *grid, int32_t S,
+                                             int32_t g, int32_t k) {
+    if (k < 2 * S) {
+        const int32_t s = k < S ? k : k - S;
+        const double v = w[(size_t)g * S + s];
+        return k < S ? v : v * grid[g];
+    }
+    double c = 0.0;
+    for (int32_t s = 0; s < S; ++s) c = c + w[(size_t)g * S + s] * mhat[(size_t)g * S + s];
+    return k == 2 * S ? c : c * grid[g];
+}
+
+// One block of 256 threads per column: chunked double-double sums, a scan of the chunk
+// totals, then the prefix rows.
+__global__ void __launch_bounds__(256) bwd_prefix_kernel(const double *__restrict__ w,
+                                                         const double *__restrict__ mhat,
+                                                         const double *__restrict__ grid, int32_t G, int32_t S,
+                                                         double *__restrict__ P) {
+    const int32_t k = blockIdx.x, ncol = 2 * S + 2, row = 2 * ncol;
+    const int32_t nt = blockDim.x, per = (G + nt - 1) / nt;
+    const int32_t g0 = min(G, (int32_t)threadIdx.x * per), g1 = min(G, g0 + per);
+    double h = 0.0, l = 0.0;
+    for (int32_t g = g0; g < g1; ++g) dd_add(h, l, bwd_column(w, mhat, grid, S, g, k), 0.0);
+    __shared__ double sh[2][256];
+    sh[0][threadIdx.x] = h;
+    sh[1][threadIdx.x] = l;
+    __syncthreads();
+    for (int off = 1; off < nt; off <<= 1) {
+        double ph = 0.0, pl = 0.0;
+        if ((int)threadIdx.x >= off) {
+            ph = sh[0][threadIdx.x - off];
+            pl = sh[1][threadIdx.x - off];
+        }
+        __syncthreads();
+        if ((int)threadIdx.x >= off) {
+            double a = sh[0][threadIdx.x], b = sh[1][threadIdx.x];
+            dd_add(a, b, ph, pl);
+            sh[0][threadIdx.x] = a;
+            sh[1][threadIdx.x] = b;
+        }
+        __syncthreads();
+    }
+    // exclusive start of this chunk
+    h = threadIdx.x ? sh[0][threadIdx.x - 1] : 0.0;
+    l = threadIdx.x ? sh[1][threadIdx.x - 1] : 0.0;
+    if (threadIdx.x == 0) {
+        P[k] = 0.0;
+        P[ncol + k] = 0.0;
+    }
+    for (int32_t g = g0; g < g1; ++g) {
+        dd_add(h, l, bwd_column(w, mhat, grid, S, g, k), 0.0);
+        P[(size_t)(g + 1) * row + k] = h;
+        P[(size_t)(g + 1) * row + ncol + k] = l;
+    }
 }
 
 // Grid description of a device grid: uniform if t_g == fl(fl(T g) / D) for all g with

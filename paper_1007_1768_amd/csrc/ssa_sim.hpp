@@ -100,8 +100,8 @@ struct NetDev {
     double *rec_tlast;
     int64_t *rec_nf;
     double *rec_aint;
-    // backward: rows [G][2S] = (w_g0..w_g,S-1, mhat_g0..mhat_g,S-1), per-trajectory rows [n_traj][M]
-    const double *wm;
+    // backward: prefix rows [G+1][2 (2S+2)] (see bwd_prefix_kernel), per-trajectory rows [n_traj][M]
+    const double *bp;
     double *gtraj;
 };
 
@@ -124,6 +124,48 @@ struct WorkList {
     unsigned int *counter;       // work-item counter (zeroed before launch)
     unsigned long long *stats;   // [0] events, [1] max steps, [2] flags
 };
+
+// Error-free transformations (Knuth's two-sum) for double-double prefix sums.
+__device__ __forceinline__ void two_sum(double a, double b, double &s, double &e) {
+    s = a + b;
+    const double bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ void dd_add(double &h, double &l, double bh, double bl) {
+    double s, e;
+    two_sum(h, bh, s, e);
+    e = e + (l + bl);
+    h = s + e;
+    l = e - (h - s);
+}
+
+// (bh + bl) - (ah + al), rounded once at the end.
+__device__ __forceinline__ double dd_diff(double ah, double al, double bh, double bl) {
+    double s, e;
+    two_sum(bh, -ah, s, e);
+    return s + (e + (bl - al));
+}
+
+// Backward sums over the crossings g in [ga, gb) of one inter-event interval starting at t
+// (state x): alpha = sum_g phi_g, beta = sum_g phi_g (t_g - t), from two prefix rows.
+template <class Policy>
+__device__ __forceinline__ void interval_sums(const Policy &p, const double *P, int32_t S, int32_t ga, int32_t gb,
+                                              double t, double &alpha, double &beta) {
+    const int32_t ncol = 2 * S + 2, row = 2 * ncol;
+    const double *ra = P + (size_t)ga * row, *rb = P + (size_t)gb * row;
+    double sw = 0.0, swt = 0.0;
+    p.for_each_species([&](int32_t s, int32_t xs) {
+        const double dW = dd_diff(ra[s], ra[ncol + s], rb[s], rb[ncol + s]);
+        const double dWT = dd_diff(ra[S + s], ra[ncol + S + s], rb[S + s], rb[ncol + S + s]);
+        sw = sw + (double)xs * dW;
+        swt = swt + (double)xs * (dWT - t * dW);
+    });
+    const double dC = dd_diff(ra[2 * S], ra[ncol + 2 * S], rb[2 * S], rb[ncol + 2 * S]);
+    const double dCT = dd_diff(ra[2 * S + 1], ra[ncol + 2 * S + 1], rb[2 * S + 1], rb[ncol + 2 * S + 1]);
+    alpha = sw - dC;
+    beta = swt - (dCT - t * dC);
+}
 
 // Wave-uniform copies (scalar registers) of values every lane holds identically.
 __device__ __forceinline__ int32_t wave_uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -221,6 +263,7 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
     double t = 0.0;
     uint64_t k = 0, ev = 0;
     int32_t g = 0;
+    double tg_cur = 0.0;       // backward: time of grid point g (the first one not yet passed)
     uint32_t ovf = 0;
     uint32_t flags = 0;
     unsigned long long tot_events = 0, max_steps = 0;
@@ -280,6 +323,7 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
                     k = 0;
                     ev = 0;
                     g = 0;
+                    tg_cur = gv.uniform ? 0.0 : ((const SSA_CONST double *)gv.grid)[0];
                     ovf = 0;
                     p.reset(n);
                     if (MODE != kFwd) {
@@ -339,21 +383,16 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
             // all crossings of [t, t_next) share the state x and the score line
             // z_j(t_g) = (n_j - A_j) - a_j (t_g - t): fold them into
             //   alpha = sum_g phi_g,  beta = sum_g phi_g (t_g - t),  phi_g = sum_s w_gs (x_s - mhat_gs)
-            // and update the M accumulators once per interval.
-            if (g < n.G && gv.at(g) < t_next) {
-                double alpha = 0.0, beta = 0.0;
-                while (g < n.G) {
-                    const double tg = gv.at(g);
-                    if (!(tg < t_next)) break;
-                    const double *row = n.wm + (size_t)g * 2 * n.S;
-                    double phi = 0.0;
-                    p.for_each_species([&](int32_t s, int32_t xs) { phi = phi + row[s] * ((double)xs - row[n.S + s]); });
-                    alpha = alpha + phi;
-                    beta = beta + phi * (tg - t);
-                    ++g;
-                }
+            // (two rows of the prefix table) and update the M accumulators once per interval.
+            if (g < n.G && tg_cur < t_next) {
+                double tb;
+                const int32_t gb = gv.next_bin(g, t_next, tb);
+                double alpha, beta;
+                interval_sums(p, n.bp, n.S, g, gb, t, alpha, beta);
 #pragma unroll
                 for (int j = 0; j < MM; ++j) gacc[j] = gacc[j] + ((nf[j] - A[j]) * alpha - a[j] * beta);
+                g = gb;
+                tg_cur = tb;
             }
         }
 

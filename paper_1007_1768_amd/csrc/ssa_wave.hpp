@@ -140,22 +140,32 @@ __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
                     ++g;
                 }
             } else if (MODE == kBwd) {
-                if (g < G && gv.at(g) < t_next) {
-                    double alpha = 0.0, beta = 0.0;
-                    while (g < G) {
-                        const double tg = gv.at(g);
-                        if (!(tg < t_next)) break;
-                        const double *row = n.wm + (size_t)g * 2 * S;
-                        double part = 0.0;
-                        for (int32_t s = lane; s < S; s += kWave)
-                            part = part + row[s] * ((double)xl[s + 1] - row[S + s]);
-                        const double phi = wave_sum_f64(part);
-                        alpha = alpha + phi;
-                        beta = beta + phi * (tg - t);
-                        ++g;
+                // crossings [g, gb) of this interval from two prefix rows (see interval_sums);
+                // the species are spread over the lanes
+                if (g < G && tg_next < t_next) {
+                    double tb;
+                    const int32_t gb = gv.next_bin(g, t_next, tb);
+                    const int32_t ncol = 2 * S + 2, rowl = 2 * ncol;
+                    const double *ra = n.bp + (size_t)g * rowl, *rb = n.bp + (size_t)gb * rowl;
+                    double sw = 0.0, swt = 0.0;
+                    for (int32_t s = lane; s < S; s += kWave) {
+                        const double xs = (double)xl[s + 1];
+                        const double dW = dd_diff(ra[s], ra[ncol + s], rb[s], rb[ncol + s]);
+                        const double dWT = dd_diff(ra[S + s], ra[ncol + S + s], rb[S + s], rb[ncol + S + s]);
+                        sw = sw + xs * dW;
+                        swt = swt + xs * (dWT - t * dW);
                     }
+                    sw = wave_sum_f64(sw);
+                    swt = wave_sum_f64(swt);
+                    const double dC = dd_diff(ra[2 * S], ra[ncol + 2 * S], rb[2 * S], rb[ncol + 2 * S]);
+                    const double dCT =
+                        dd_diff(ra[2 * S + 1], ra[ncol + 2 * S + 1], rb[2 * S + 1], rb[ncol + 2 * S + 1]);
+                    const double alpha = sw - dC;
+                    const double beta = swt - (dCT - t * dC);
 #pragma unroll
                     for (int i = 0; i < Q; ++i) gacc[i] = gacc[i] + ((nf[i] - A[i]) * alpha - a[i] * beta);
+                    g = gb;
+                    tg_next = tb;
                 }
             }
 
