@@ -357,7 +357,7 @@ hipError_t launch_generic(int mm, const WorkList &wl, int64_t n_items, int dev, 
 // Forward launches (selective-memory windows, see ssa_sim.hpp)
 // ---------------------------------------------------------------------------------------
 
-// Bytes of LDS per wave for the window (SSA_WIN_BYTES overrides; 512 .. 16384).
+// Bytes of LDS per window (SSA_WIN_BYTES overrides; 512 .. 16384); a wave holds kCohorts.
 size_t window_budget() {
     size_t b = 4096;
     if (const char *e = std::getenv("SSA_WIN_BYTES")) b = (size_t)std::strtoull(e, nullptr, 10);
@@ -586,6 +586,8 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
     FwdKernel k;
     wl.win_bins = window_bins(S, G);
     wl.win_words = wl.win_bins * S * 2;
+    // the specialised kernels run generations with one window per wave, the table-driven
+    // kernel cohorts with kCohorts windows
     const size_t win_bytes = (size_t)(kBlock / kWave) * wl.win_words * sizeof(long long);
     if (jit_eligible(m)) {
         std::shared_ptr<JitKernels> jk;
@@ -608,7 +610,7 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
         }
         wl.s_rows = S;
         wl.m_rows = m->M;
-        k.lds = generic_int_words(wl.s_rows, wl.m_rows) * sizeof(int32_t) + win_bytes;
+        k.lds = generic_int_words(wl.s_rows, wl.m_rows) * sizeof(int32_t) + kCohorts * win_bytes;
     }
     const size_t cell_words = (size_t)G * S * 2;
     int64_t blocks = 0;
@@ -1089,7 +1091,7 @@ ssa_status batch_enqueue(ssa_batch *bt, hipStream_t st) {
     FwdKernel k;
     if (!pick_generic_fwd<true>(bt->mm, k)) return fail(SSA_E_UNSUPPORTED, "no kernel");
     k.lds = generic_int_words(wl.s_rows, wl.m_rows) * sizeof(int32_t) +
-            (size_t)(kBlock / kWave) * wl.win_words * sizeof(long long);
+            (size_t)(kBlock / kWave) * kCohorts * wl.win_words * sizeof(long long);
     int64_t blocks = 0;
     HIP_TRY(fwd_blocks(k, false, bt->device, bt->n_items, blocks));
     HIP_TRY(fwd_launch(k, false, blocks, wl, st));

@@ -56,18 +56,19 @@ struct RegPolicy {
 
 }  // namespace ssa
 
-// Forward pass: one selective-memory window of wl.win_words int64 per wave in dynamic LDS;
+// Forward pass by generations: one selective-memory window of wl.win_words int64 per wave in
+// dynamic LDS;
 // flushes into wave-private slabs (ssa_jit_fwd) or atomically into the totals (_atomic).
 extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd(ssa::WorkList wl) {
     extern __shared__ long long ssa_win[];
     ssa::RegPolicy p;
-    ssa::sim_fwd<ssa_gen::Net::M, false, true>(wl, p, ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
+    ssa::sim_fwd_gen<ssa_gen::Net::M, false, true>(wl, p, ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
 }
 
 extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd_atomic(ssa::WorkList wl) {
     extern __shared__ long long ssa_win[];
     ssa::RegPolicy p;
-    ssa::sim_fwd<ssa_gen::Net::M, false, false>(wl, p, ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
+    ssa::sim_fwd_gen<ssa_gen::Net::M, false, false>(wl, p, ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
 }
 
 extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_rec(ssa::WorkList wl) {

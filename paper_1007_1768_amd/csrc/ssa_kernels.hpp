@@ -102,8 +102,8 @@ struct LdsPolicy {
 };
 
 // LDS per block: rows [s_rows + 1][kBlock] int32 (row 0 all ones, species s in row s + 1),
-// then one change table per wave of m_rows * kChg int32, then (forward) one selective-
-// memory window per wave of win_words int64.
+// then one change table per wave of m_rows * kChg int32, then (forward) kCohorts selective-
+// memory windows per wave of win_words int64 each.
 __device__ __forceinline__ void generic_setup(const WorkList &wl, int32_t *lds, LdsPolicy &p) {
     p.xc = lds + threadIdx.x;
     p.wchg = lds + (wl.s_rows + 1) * kBlock + (threadIdx.x / kWave) * wl.m_rows * kChg;
@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(kBlock) fwd_kernel(WorkList wl) {
     LdsPolicy p;
     generic_setup(wl, lds_x, p);
     long long *win = (long long *)(lds_x + generic_int_words(wl.s_rows, wl.m_rows)) +
-                     (size_t)(threadIdx.x / kWave) * wl.win_words;
+                     (size_t)(threadIdx.x / kWave) * kCohorts * wl.win_words;
     sim_fwd<MM, BATCH, SLAB>(wl, p, win);
 }
 

@@ -195,7 +195,7 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 template <bool BATCH>
 __device__ __forceinline__ NetDev current_net(const WorkList &wl, int32_t cur) {
     NetDev n;
-    if (BATCH) n = ((const SSA_CONST NetDev *)wl.nets)[cur];
+    if (BATCH) n = ((const SSA_CONST NetDev *)wl.nets)[wave_uniform(cur)];
     else n = wl.net0;
     asm volatile("" : "+s"(n.key0), "+s"(n.key1));
     return n;
@@ -269,8 +269,11 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
     unsigned long long tot_events = 0, max_steps = 0;
     double a[MR];
     double Ssum[MR];
-    double A[MODE == kFwd ? 1 : MR];
-    double nf[MODE == kFwd ? 1 : MR];
+    // record: A_j and n_j; backward: the score B_j = n_j - A_j at the current event time
+    // (updated by [j fired] - a_j tau per event) and the gradient accumulator
+    double A[MODE == kRec ? MR : 1];
+    int32_t nf[MODE == kRec ? MR : 1];
+    double B[MODE == kBwd ? MR : 1];
     double gacc[MODE == kBwd ? MR : 1];
 
     for (;;) {
@@ -326,13 +329,13 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
                     tg_cur = gv.uniform ? 0.0 : ((const SSA_CONST double *)gv.grid)[0];
                     ovf = 0;
                     p.reset(n);
-                    if (MODE != kFwd) {
+                    if (MODE == kRec) {
 #pragma unroll
-                        for (int j = 0; j < MM; ++j) { A[j] = 0.0; nf[j] = 0.0; }
+                        for (int j = 0; j < MM; ++j) { A[j] = 0.0; nf[j] = 0; }
                     }
                     if (MODE == kBwd) {
 #pragma unroll
-                        for (int j = 0; j < MM; ++j) gacc[j] = 0.0;
+                        for (int j = 0; j < MM; ++j) { B[j] = 0.0; gacc[j] = 0.0; }
                     }
                 }
             }
@@ -371,6 +374,14 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
             k = k + 1;
         }
         const double t_next = t + tau;
+        // the count of partial sums <= u (the smallest j with S_j > u), taken now so the
+        // partial sums are dead before the grid work below
+        int32_t sel = 0;
+        {
+            const double u = r2 * acc;
+#pragma unroll
+            for (int j = 0; j < MM; ++j) sel += (Ssum[j] <= u) ? 1 : 0;
+        }
 
         // grid points passed before the event: record / backward see the pre-event state
         if (MODE == kRec) {
@@ -390,7 +401,7 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
                 double alpha, beta;
                 interval_sums(p, n.bp, n.S, g, gb, t, alpha, beta);
 #pragma unroll
-                for (int j = 0; j < MM; ++j) gacc[j] = gacc[j] + ((nf[j] - A[j]) * alpha - a[j] * beta);
+                for (int j = 0; j < MM; ++j) gacc[j] = gacc[j] + (B[j] * alpha - a[j] * beta);
                 g = gb;
                 tg_cur = tb;
             }
@@ -402,15 +413,6 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
             finish = true;
         }
         if (!finish) {
-            // selection: the number of partial sums <= u is the smallest j with S_j > u
-            const double u = r2 * acc;
-            int32_t sel = 0;
-            if constexpr (MM > 0) {
-#pragma unroll
-                for (int j = 0; j < MM; ++j) sel += (Ssum[j] <= u) ? 1 : 0;
-            } else {
-                sel = p.select(n, u);
-            }
             if (sel >= M) {
                 // rounding left no S_j > u: the largest j with a_j > 0
                 for (int32_t j = M - 1; j >= 0; --j) {
@@ -423,12 +425,16 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
                 flags |= kFlagOverflow;
                 finish = true;
             } else {
-                if (MODE != kFwd) {
+                if (MODE == kRec) {
 #pragma unroll
                     for (int j = 0; j < MM; ++j) {
                         A[j] = A[j] + a[j] * tau;
-                        nf[j] = nf[j] + (j == sel ? 1.0 : 0.0);
+                        nf[j] += (j == sel) ? 1 : 0;
                     }
+                }
+                if (MODE == kBwd) {
+#pragma unroll
+                    for (int j = 0; j < MM; ++j) B[j] = B[j] + ((j == sel ? 1.0 : 0.0) - a[j] * tau);
                 }
                 t = t_next;
                 ev = ev + 1;
@@ -482,10 +488,13 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
     return wave_uniform(v);
 }
 
-// Forward pass with the selective-memory window (see the header comment).  win: this
-// wave's LDS window, wl.win_bins bins x S species x (sum nu, sum (2x+nu)nu) as int64.
+// Forward pass by generations (see the header comment): a wave takes one work item, runs
+// its (up to) 64 trajectories to the end with one window that follows the slowest lane,
+// then takes the next item.  The loop is tighter than the cohort form below, which pays
+// off for networks compiled into registers.  win: the wave's LDS window, wl.win_bins bins
+// x S species x (sum nu, sum (2x+nu)nu) as int64.
 template <int MM, bool BATCH, bool SLAB, class Policy>
-__device__ __forceinline__ void sim_fwd(const WorkList &wl, Policy &p, long long *win) {
+__device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long long *win) {
     constexpr int MR = MM > 0 ? MM : 1;
     const uint32_t lane = __lane_id();
     const int32_t W = wl.win_bins;
@@ -578,6 +587,12 @@ __device__ __forceinline__ void sim_fwd(const WorkList &wl, Policy &p, long long
             const bool blocked = active && pend && binp < G && binp >= base + W;
             if (active && !blocked) {
                 const NetDev n = current_net<BATCH>(wl, cur);
+                // the next draw does not depend on the state: start it before the update.  A
+                // pending event has consumed draw k - 1, so the next one is draw k either way.
+                const u32x4 o = philox4x32_10((uint32_t)k, (uint32_t)(k >> 32), (uint32_t)traj,
+                                              (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
+                const double r2n = uniform_open1(o.v2, o.v3);
+                const double En = neg_log(uniform_open0(o.v0, o.v1));
                 if (pend) {
                     // apply the pending event at t_next (state unchanged since it was drawn)
                     int32_t sel = 0;
@@ -645,11 +660,8 @@ __device__ __forceinline__ void sim_fwd(const WorkList &wl, Policy &p, long long
                     if (acc == 0.0) {
                         active = false;                // absorbing: the state holds to t_end
                     } else {
-                        const u32x4 o = philox4x32_10((uint32_t)k, (uint32_t)(k >> 32), (uint32_t)traj,
-                                                      (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
-                        const double r1 = uniform_open0(o.v0, o.v1);
-                        const double r2 = uniform_open1(o.v2, o.v3);
-                        t_next = t + neg_log(r1) / acc;
+                        const double r2 = r2n;
+                        t_next = t + En / acc;
                         k = k + 1;
                         if (t_next > n.t_end) {
                             active = false;            // beyond the horizon: not applied
@@ -680,6 +692,286 @@ __device__ __forceinline__ void sim_fwd(const WorkList &wl, Policy &p, long long
             }
         }
         flush(base, min(G, base + W));
+    }
+
+    // wave totals -> global statistics
+    for (int off = 32; off > 0; off >>= 1) {
+        tot_events += __shfl_xor(tot_events, off);
+        max_steps = max(max_steps, (unsigned long long)__shfl_xor(max_steps, off));
+        flags |= (uint32_t)__shfl_xor((int)flags, off);
+    }
+    if (lane == 0) {
+        if (tot_events) atomicAdd(wl.stats + 0, tot_events);
+        atomicMax(wl.stats + 1, max_steps);
+        if (flags) atomicOr(wl.stats + 2, (unsigned long long)flags);
+    }
+}
+
+// Forward pass with the selective-memory windows (see the header comment).  A wave keeps
+// two windows, wl.win_words int64 each (win_bins bins x S species x (sum nu, sum
+// (2x+nu)nu)), so two cohorts of trajectories can be in flight: a cohort is the set of
+// lanes started together; its window follows the slowest of its lanes.  A new cohort
+// starts on the idle lanes once half the wave is idle and a window is free, so lanes
+// whose trajectories end early are refilled instead of waiting for the slowest lane of
+// their cohort.
+constexpr int kCohorts = 2;
+constexpr int kCohortStart = 32;      // idle lanes needed to start a cohort beside another
+
+template <int MM, bool BATCH, bool SLAB, class Policy>
+__device__ __forceinline__ void sim_fwd(const WorkList &wl, Policy &p, long long *win) {
+    constexpr int MR = MM > 0 ? MM : 1;
+    const uint32_t lane = __lane_id();
+    const int32_t W = wl.win_bins;
+    const int32_t wave_slot = (int32_t)(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave);
+
+    // wave-uniform work state
+    int32_t cur = -1, pool_net = -1;
+    int64_t pool_next = 0, pool_end = 0;
+    bool exhausted = false;
+    int32_t base[kCohorts] = {0, 0};
+    bool live[kCohorts] = {false, false};
+    GridView gv;
+    gv.grid = nullptr;
+    gv.T = gv.D = gv.lo = gv.scale = 0.0;
+    gv.G = 0;
+    gv.uniform = 0;
+    int32_t S = 0, G = 0, M = 0, row_words = 0;
+    unsigned long long *slab = nullptr;
+
+    // lane state
+    bool active = false, pend = false;
+    int32_t coh = 0;
+    int64_t traj = 0;
+    double t = 0.0, t_next = 0.0, u = 0.0, tg_next = 0.0;
+    uint64_t k = 0, ev = 0;
+    int32_t g = 0, binp = 0;
+    uint32_t ovf = 0;
+    uint32_t flags = 0;
+    unsigned long long tot_events = 0, max_steps = 0;
+    double a[MR];
+    double Ssum[MR];
+
+    for (int32_t q = lane; q < kCohorts * wl.win_words; q += kWave) win[q] = 0;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+
+    // flush bins [lo, hi) of cohort c's window (lanes cooperate over consecutive words)
+    auto flush = [&](int32_t c, int32_t lo, int32_t hi) {
+        // the window's LDS words were written by other lanes of this wave: LDS operations
+        // of one wave complete in order, so only compiler reordering must be fenced off
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        long long *wc = win + c * wl.win_words;
+        const int32_t words = (hi - lo) * row_words;
+        for (int32_t e = lane; e < words; e += kWave) {
+            const int32_t bin = lo + e / row_words, r = e - (e / row_words) * row_words;
+            long long *slot = wc + (bin & (W - 1)) * row_words + r;
+            const long long v = *slot;
+            if (v != 0) {
+                unsigned long long *dst = slab + (size_t)bin * row_words + r;
+                if (SLAB) *dst = *dst + (unsigned long long)v;
+                else atomicAdd(dst, (unsigned long long)v);
+                *slot = 0;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    };
+
+    for (;;) {
+        // ---------------- start a cohort on the idle lanes ----------------
+        const uint64_t idle = __ballot(!active);
+        const int32_t c_free = !live[0] ? 0 : (!live[1] ? 1 : -1);
+        const bool none_live = !live[0] && !live[1];
+        if (idle && c_free >= 0 && (none_live || __popcll(idle) >= kCohortStart)) {
+            // trajectories for the idle lanes, pulling work items as needed; a wave changes
+            // network only when nothing is in flight
+            const int32_t n_idle = __popcll(idle);
+            const int32_t rank = __popcll(idle & lanemask_lt());
+            int32_t assigned = 0;
+            while (assigned < n_idle) {
+                if (pool_next >= pool_end) {
+                    if (exhausted) break;
+                    int32_t item = 0;
+                    if (lane == 0) item = (int32_t)atomicAdd(wl.counter, 1u);
+                    item = wave_uniform(__shfl(item, 0));
+                    if (item >= wl.n_items) {
+                        exhausted = true;
+                        break;
+                    }
+                    if (BATCH) {
+                        pool_net = wave_uniform(((const SSA_CONST int32_t *)wl.item_net)[item]);
+                        pool_next = wave_uniform(((const SSA_CONST int64_t *)wl.item_begin)[item]);
+                        pool_end = pool_next + wave_uniform((int64_t)((const SSA_CONST int32_t *)wl.item_count)[item]);
+                    } else {
+                        pool_net = 0;
+                        pool_next = wl.range_begin + (int64_t)item * kChunk;
+                        pool_end = min(pool_next + (int64_t)kChunk, wl.range_end);
+                    }
+                }
+                if (pool_net != cur) {
+                    if (!none_live || assigned > 0) break;
+                    cur = pool_net;
+                    const NetDev nn = current_net<BATCH>(wl, cur);
+                    p.switch_net(nn);
+                    const GridInfo gi = *(const SSA_CONST GridInfo *)nn.ginfo;
+                    gv.grid = wave_uniform(nn.grid);
+                    gv.T = wave_uniform(gi.T);
+                    gv.D = wave_uniform(gi.D);
+                    gv.lo = wave_uniform(gi.lo);
+                    gv.scale = wave_uniform(gi.scale);
+                    gv.G = wave_uniform(nn.G);
+                    gv.uniform = wave_uniform(gi.uniform);
+                    S = wave_uniform(nn.S);
+                    G = wave_uniform(nn.G);
+                    M = wave_uniform(nn.M);
+                    row_words = S * 2;
+                    slab = SLAB ? wl.slabs + (size_t)wave_slot * (size_t)G * row_words : nn.D;
+                }
+                const int32_t take = (int32_t)min((int64_t)(n_idle - assigned), pool_end - pool_next);
+                const NetDev nr = current_net<BATCH>(wl, cur);
+                if (!active && rank >= assigned && rank < assigned + take) {
+                    active = true;
+                    pend = false;
+                    coh = c_free;
+                    traj = pool_next + (rank - assigned);
+                    t = 0.0;
+                    k = 0;
+                    ev = 0;
+                    g = 0;
+                    ovf = 0;
+                    tg_next = gv.uniform ? 0.0 : ((const SSA_CONST double *)gv.grid)[0];
+                    p.reset(nr);
+                }
+                pool_next += take;
+                assigned += take;
+            }
+            if (assigned > 0) {
+                live[c_free] = true;
+                base[c_free] = 0;
+            }
+        }
+        if (__ballot(active) == 0) {
+            if (exhausted && pool_next >= pool_end) break;
+            continue;
+        }
+
+        // ---------------- one step of every unblocked active lane ----------------
+        const int32_t my_base = coh ? base[1] : base[0];
+        const bool blocked = active && pend && binp < G && binp >= my_base + W;
+        if (active && !blocked) {
+            const NetDev n = current_net<BATCH>(wl, cur);
+            // the next draw does not depend on the state: start it first
+            const u32x4 o = philox4x32_10((uint32_t)(k + (pend ? 1 : 0)), (uint32_t)((k + (pend ? 1 : 0)) >> 32),
+                                          (uint32_t)traj, (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
+            const double r1 = uniform_open0(o.v0, o.v1);
+            const double r2 = uniform_open1(o.v2, o.v3);
+            const double E = neg_log(r1);
+            if (pend) {
+                // apply the pending event at t_next (state unchanged since it was drawn)
+                int32_t sel = 0;
+                if constexpr (MM > 0) {
+#pragma unroll
+                    for (int j = 0; j < MM; ++j) sel += (Ssum[j] <= u) ? 1 : 0;
+                } else {
+                    sel = p.select(n, u);
+                }
+                if (sel >= M) {
+                    for (int32_t j = M - 1; j >= 0; --j) {
+                        if (p.one(n, j) > 0.0) { sel = j; break; }
+                    }
+                    sel = min(sel, M - 1);
+                }
+                const int32_t bin = binp;
+                const bool inb = bin < G;
+                long long *wrow = win + coh * wl.win_words + (bin & (W - 1)) * row_words;
+                p.apply(n, sel, [&](int32_t sp, int32_t xo, int32_t xn) {
+                    ovf |= (uint32_t)xn;
+                    const int32_t dl = inb ? xn - xo : 0;
+                    const long long d2 = (2ll * xo + dl) * (long long)dl;
+                    long long *w = wrow + sp * 2;
+                    atomicAdd((unsigned long long *)w, (unsigned long long)(long long)dl);
+                    if (d2 > -kSmallD2 && d2 < kSmallD2) {
+                        atomicAdd((unsigned long long *)(w + 1), (unsigned long long)d2);
+                    } else {
+                        atomicAdd((unsigned long long *)(w + 1), (unsigned long long)(d2 & ((1ll << 24) - 1)));
+                        atomicAdd(n.Dhi + (size_t)bin * S + sp, (unsigned long long)(d2 >> 24));
+                    }
+                    if (n.Hd && sp == n.h_species && dl != 0) {
+                        const int32_t bo = xo < n.h_lo ? 0 : min((xo - n.h_lo) / n.h_width, n.nb_hist - 1);
+                        const int32_t bn = xn < n.h_lo ? 0 : min((xn - n.h_lo) / n.h_width, n.nb_hist - 1);
+                        if (bo != bn) {
+                            atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bo, -1);
+                            atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bn, 1);
+                        }
+                    }
+                });
+                pend = false;
+                k = k + 1;                 // the applied event's draw
+                t = t_next;
+                ev = ev + 1;
+                g = bin;
+                if ((int32_t)ovf < 0) {
+                    flags |= kFlagOverflow;
+                    active = false;
+                }
+            }
+            if (active) {
+                // draw the next event
+                double acc;
+                if constexpr (MM > 0) {
+                    p.template eval<MM>(n, a);
+                    acc = a[0];
+                    Ssum[0] = acc;
+#pragma unroll
+                    for (int j = 1; j < MM; ++j) {
+                        acc = acc + a[j];
+                        Ssum[j] = acc;
+                    }
+                } else {
+                    acc = p.total(n);
+                }
+                t_next = t + E / acc;
+                if (acc == 0.0) {
+                    active = false;                // absorbing: the state holds to t_end, no draw
+                } else if (t_next > n.t_end) {
+                    active = false;                // beyond the horizon: drawn, not applied
+                    k = k + 1;
+                } else if (ev >= n.max_events) {
+                    flags |= kFlagEventLimit;
+                    active = false;
+                    k = k + 1;
+                } else {
+                    u = r2 * acc;
+                    binp = g;
+                    if (g < G && t_next > tg_next) binp = gv.next_bin(g, t_next, tg_next);
+                    pend = true;
+                }
+            }
+            if (!active) {
+                tot_events += ev;
+                max_steps = max(max_steps, (unsigned long long)ev);
+            }
+        }
+
+        // ---------------- window upkeep per cohort ----------------
+#pragma unroll
+        for (int c = 0; c < kCohorts; ++c) {
+            if (!live[c]) continue;
+            const bool mine = active && coh == c;
+            if (__ballot(mine) == 0) {
+                flush(c, base[c], min(G, base[c] + W));       // the cohort has ended
+                live[c] = false;
+                continue;
+            }
+            if (__ballot(mine && pend && binp < G && binp >= base[c] + W)) {
+                const int32_t m = wave_min(mine && pend ? binp : G);
+                if (m > base[c]) {
+                    flush(c, base[c], min(m, base[c] + W));
+                    base[c] = m;
+                }
+            }
+        }
     }
 
     // wave totals -> global statistics

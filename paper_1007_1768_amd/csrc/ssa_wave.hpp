@@ -89,14 +89,16 @@ __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
         uint64_t k = 0, ev = 0;
         int32_t g = 0;
         double tg_next = G > 0 ? gv.at(0) : 0.0;
-        double A[MODE == kFwd ? 1 : Q], nf[MODE == kFwd ? 1 : Q], gacc[MODE == kBwd ? Q : 1];
-        if (MODE != kFwd) {
+        // record: A_j and n_j; backward: the score B_j = n_j - A_j and the accumulator
+        double A[MODE == kRec ? Q : 1], nf[MODE == kRec ? Q : 1];
+        double B[MODE == kBwd ? Q : 1], gacc[MODE == kBwd ? Q : 1];
+        if (MODE == kRec) {
 #pragma unroll
             for (int i = 0; i < Q; ++i) { A[i] = 0.0; nf[i] = 0.0; }
         }
         if (MODE == kBwd) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) gacc[i] = 0.0;
+            for (int i = 0; i < Q; ++i) { B[i] = 0.0; gacc[i] = 0.0; }
         }
         bool overflow = false;
 
@@ -163,7 +165,7 @@ __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
                     const double alpha = sw - dC;
                     const double beta = swt - (dCT - t * dC);
 #pragma unroll
-                    for (int i = 0; i < Q; ++i) gacc[i] = gacc[i] + ((nf[i] - A[i]) * alpha - a[i] * beta);
+                    for (int i = 0; i < Q; ++i) gacc[i] = gacc[i] + (B[i] * alpha - a[i] * beta);
                     g = gb;
                     tg_next = tb;
                 }
@@ -236,12 +238,16 @@ __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
                 flags |= kFlagOverflow;
                 break;
             }
-            if (MODE != kFwd) {
+            if (MODE == kRec) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
                     A[i] = A[i] + a[i] * tau;
                     nf[i] = nf[i] + (jr[i] == sel ? 1.0 : 0.0);
                 }
+            }
+            if (MODE == kBwd) {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) B[i] = B[i] + ((jr[i] == sel ? 1.0 : 0.0) - a[i] * tau);
             }
             t = t_next;
             ev = ev + 1;
