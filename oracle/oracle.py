@@ -50,6 +50,9 @@ def lib():
         L.orc_grad.argtypes = [ctypes.POINTER(_Net), ctypes.c_int64, ctypes.c_double, vp, ctypes.c_int32,
                                ctypes.c_uint64, ctypes.c_uint64, vp, vp, vp, vp, ctypes.c_int]
         L.orc_grad.restype = ctypes.c_int
+        L.orc_jacobian.argtypes = [ctypes.POINTER(_Net), ctypes.c_int64, ctypes.c_double, vp, ctypes.c_int32,
+                                   ctypes.c_uint64, ctypes.c_uint64, vp, vp, vp, ctypes.c_int]
+        L.orc_jacobian.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -165,3 +168,16 @@ def grad(model, N, t_end, grid, seed, w, mhat, max_events=2**62, rates=None, thr
     st = lib().orc_grad(ctypes.byref(net.c), int(N), float(t_end), _ptr(grid), G, seed, max_events,
                         _ptr(w), _ptr(mhat), _ptr(g_out), _ptr(l1), threads or default_threads())
     return st, g_out, l1
+
+
+def jacobian(model, N, t_end, grid, seed, mhat, max_events=2**62, rates=None, threads=None):
+    """LR Jacobian J[g, s, j] = (1/N) sum_i (X_s(t_g) - mhat[g, s]) z_j(t_g) and its L1 scale."""
+    net = as_net(model, rates)
+    grid = np.ascontiguousarray(grid, dtype=np.float64)
+    G = grid.shape[0]
+    mh = np.ascontiguousarray(mhat, dtype=np.float64).reshape(G, net.S)
+    jac = np.zeros((G, net.S, net.M))
+    l1 = np.zeros((G, net.S, net.M))
+    st = lib().orc_jacobian(ctypes.byref(net.c), int(N), float(t_end), _ptr(grid), G, int(seed), int(max_events),
+                            _ptr(mh), _ptr(jac), _ptr(l1), int(threads or default_threads()))
+    return st, jac, l1

@@ -623,3 +623,87 @@ int orc_grad(const orc_net *net, int64_t N, double t_end, const double *grid, in
     free(info); free(tot); free(totl1);
     return status;
 }
+
+/* ------------------------------------------------------------------------------------
+ * The whole likelihood-ratio Jacobian of the grid means (the same estimator as orc_grad,
+ * before it is contracted with w):
+ *   J_{g,s,j} = (1/N) sum_i (X^i_s(t_g) - m_hat_{g,s}) z^i_j(t_g),   z_j = n_j - A_j,
+ * with l1_{g,s,j} = (1/N) sum_i |(X - m_hat) z_j| as the tolerance scale.  Layout
+ * [G][S][M].  Sums run in long double.
+ * ---------------------------------------------------------------------------------- */
+typedef struct {
+    int S, M;
+    const double *mhat;
+    long double *acc, *l1;   /* [G*S*M] of this thread */
+    double *z;               /* [M] scratch */
+} jac_ctx;
+
+static void jac_visit(void *c, int g, const traj_state *st, double tg)
+{
+    jac_ctx *jc = (jac_ctx *)c;
+    for (int j = 0; j < jc->M; ++j) {
+        double Atg = st->A[j] + st->a[j] * (tg - st->t);
+        jc->z[j] = (double)st->nf[j] - Atg;
+    }
+    for (int s = 0; s < jc->S; ++s) {
+        double d = (double)st->x[s] - jc->mhat[(size_t)g * jc->S + s];
+        size_t base = ((size_t)g * jc->S + s) * jc->M;
+        for (int j = 0; j < jc->M; ++j) {
+            double term = d * jc->z[j];
+            jc->acc[base + j] += (long double)term;
+            jc->l1[base + j] += (long double)fabs(term);
+        }
+    }
+}
+
+int orc_jacobian(const orc_net *net, int64_t N, double t_end, const double *grid, int32_t G,
+                 uint64_t seed, uint64_t max_events, const double *mhat, double *jac, double *l1,
+                 int nthreads)
+{
+    int st0 = check_net(net);
+    if (st0) return st0;
+    if (check_grid(grid, G, t_end)) return ORC_INVALID;
+    if (N <= 0 || !mhat || !jac) return ORC_INVALID;
+    const int S = net->S, M = net->M;
+    const size_t cells = (size_t)G * S * M;
+    rxn_info *info = (rxn_info *)malloc(sizeof(rxn_info) * M);
+    long double *tot = (long double *)calloc(cells, sizeof(long double));
+    long double *totl1 = (long double *)calloc(cells, sizeof(long double));
+    if (!info || !tot || !totl1) { free(info); free(tot); free(totl1); return ORC_NOMEM; }
+    build_info(net, info);
+    int status = ORC_OK;
+    if (nthreads <= 0) nthreads = 1;
+#pragma omp parallel num_threads(nthreads)
+    {
+        jac_ctx jc;
+        jc.S = S; jc.M = M; jc.mhat = mhat;
+        jc.acc = (long double *)calloc(cells, sizeof(long double));
+        jc.l1 = (long double *)calloc(cells, sizeof(long double));
+        jc.z = (double *)calloc(M, sizeof(double));
+        traj_state st;
+        int ok = jc.acc && jc.l1 && jc.z && alloc_state(net, &st, info) == ORC_OK;
+        int my_status = ok ? ORC_OK : ORC_NOMEM;
+#pragma omp for schedule(dynamic, 16)
+        for (int64_t i = 0; i < N; ++i) {
+            if (my_status != ORC_OK) continue;
+            int r = run_trajectory(net, info, seed, (uint64_t)i, t_end, grid, G, max_events, &st, NULL, NULL,
+                                   jac_visit, &jc);
+            if (r != ORC_OK) my_status = r;
+        }
+#pragma omp critical
+        {
+            if (my_status != ORC_OK && status == ORC_OK) status = my_status;
+            if (ok) for (size_t q = 0; q < cells; ++q) { tot[q] += jc.acc[q]; totl1[q] += jc.l1[q]; }
+        }
+        if (ok) free_state(&st);
+        free(jc.acc); free(jc.l1); free(jc.z);
+    }
+    if (status == ORC_OK) {
+        for (size_t q = 0; q < cells; ++q) {
+            jac[q] = (double)(tot[q] / (long double)N);
+            if (l1) l1[q] = (double)(totl1[q] / (long double)N);
+        }
+    }
+    free(info); free(tot); free(totl1);
+    return status;
+}

@@ -84,3 +84,45 @@ def test_grad_is_linear_in_weights_and_matches_grid_prefix():
     _, gb, lb = orc.grad(m, N, grid[g], grid[:g + 1], 2, w[:g + 1], mhat[:g + 1])
     assert np.allclose(ga, gb, rtol=0, atol=1e-12 * la.max())
     assert np.allclose(la, lb, rtol=1e-12)
+
+
+def test_jacobian_closed_form_immigration_death():
+    """The Jacobian routine on its own: immigration-death's dm/dln k1 = m(t) and
+    dm/dln k2 = -m + k1 t exp(-k2 t) at every grid point, within 5 standard errors."""
+    k1, k2 = 10.0, 0.1
+    m = inputs.immigration_death(k1, k2)
+    N, t_end, G = 8000, 40.0, 5
+    grid = inputs.uniform_grid(t_end, G)
+    st, out = orc.run(m, N, t_end, grid, seed=23)
+    assert st == orc.OK
+    st, J, l1 = orc.jacobian(m, N, t_end, grid, 23, out["mean"])
+    assert st == orc.OK
+    for g, t in enumerate(grid):
+        mt = (k1 / k2) * (1 - math.exp(-k2 * t))
+        exact = [mt, -mt + k1 * t * math.exp(-k2 * t)]
+        if t == 0.0:
+            assert np.all(J[g] == 0.0)
+            continue
+        # standard error of a mean of (X - m) z terms: bounded by sqrt(E[(X - m)^2 z^2] / N);
+        # Var X = m for the Poisson marginal, E[z_j^2] = E[n_j] = k1 t (births) or the
+        # expected deaths (k1 t - m), and the product is bounded by 3 m E[z^2] (fourth moments)
+        for j in range(2):
+            ez2 = k1 * t if j == 0 else k1 * t - mt
+            se = math.sqrt(3.0 * mt * ez2 / N)
+            assert abs(J[g, 0, j] - exact[j]) < 5 * se, (t, j, J[g, 0, j], exact[j], se)
+
+
+def test_jacobian_contracts_to_the_gradient():
+    """sum_{g,s} w_{g,s} J_{g,s,j} is the gradient for any w (both from the oracle's own
+    crossing visits; this ties the Jacobian to the pinned gradient routine)."""
+    m = inputs.viral()
+    t_end, G, N = 5.0, 11, 300
+    grid = inputs.uniform_grid(t_end, G)
+    st, out = orc.run(m, N, t_end, grid, seed=4)
+    st, J, l1 = orc.jacobian(m, N, t_end, grid, 4, out["mean"])
+    assert st == orc.OK
+    w = np.random.default_rng(1).normal(size=out["mean"].shape)
+    st, g, gl1 = orc.grad(m, N, t_end, grid, 4, w, out["mean"])
+    assert np.allclose(np.einsum("gs,gsj->j", w, J), g, rtol=0, atol=1e-12 * gl1.max())
+    # the L1 scales are consistent too
+    assert np.all(np.einsum("gs,gsj->j", np.abs(w), l1) >= gl1 * (1 - 1e-12))
