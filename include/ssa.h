@@ -145,6 +145,25 @@ ssa_status ssa_backward_device(const ssa_model *model, const double *rates, int6
                                const double *w, const double *mhat, double *grad, void *stream,
                                ssa_stats *stats);
 
+/* Forward pass that also returns the likelihood-ratio Jacobian of the grid means with
+ * respect to theta_j = ln c_j, from the same single simulation pass:
+ *   jac[g][s][j] = (1/N) sum_i (X^i_s(t_g) - mean_{g,s}) (n^i_j(t_g) - A^i_j(t_g))
+ * (the estimator of ssa_backward_device before it is contracted with w, centred on this
+ * run's own mean).  Arguments as ssa_run_device (no histogram); jac [G*S*M] device.  The
+ * item sums are reduced in a fixed order, so the Jacobian is deterministic.  Needs a
+ * SSA_SUM_SEQ model with M <= 32 and S <= 64 and ceil(N/64) * G * (S+1) * M * 8 bytes of
+ * scratch (at most 4 GiB, or SSA_JAC_BYTES); SSA_E_UNSUPPORTED otherwise (use
+ * ssa_backward_device). */
+ssa_status ssa_run_jacobian_device(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
+                                   const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events,
+                                   double *mean, double *var, double *jac, void *stream, ssa_stats *stats);
+
+/* grad[j] = sum_{g,s} w[g][s] jac[g][s][j] on the device (fixed summation order): the
+ * vector-Jacobian product that turns the forward Jacobian into d loss / d ln c for
+ * w = d loss / d mean.  jac [G*S*M], w [G*S], grad [M], all device; asynchronous on stream. */
+ssa_status ssa_jacobian_vjp(const double *jac, const double *w, int32_t n_grid, int32_t n_species,
+                            int32_t n_reactions, double *grad, void *stream);
+
 /* Per-trajectory record of trajectories traj_begin .. traj_begin+count-1 (synchronous, all
  * pointers host): states [count*G*S] int32 at the grid points, events [count], draws
  * [count] (Philox blocks consumed), t_last [count] (time of the last applied event, 0 if

@@ -116,7 +116,7 @@ bool prefer_generic() {
 // ---------------------------------------------------------------------------------------
 struct JitKernels {
     hipModule_t module = nullptr;
-    hipFunction_t fwd = nullptr, fwd_atomic = nullptr, rec = nullptr, bwd = nullptr;
+    hipFunction_t fwd = nullptr, fwd_atomic = nullptr, fwd_jac = nullptr, rec = nullptr, bwd = nullptr;
 };
 
 std::mutex g_jit_mu;
@@ -276,6 +276,7 @@ ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out
     HIP_TRY(hipModuleLoadData(&k->module, code.data()));
     HIP_TRY(hipModuleGetFunction(&k->fwd, k->module, "ssa_jit_fwd"));
     HIP_TRY(hipModuleGetFunction(&k->fwd_atomic, k->module, "ssa_jit_fwd_atomic"));
+    HIP_TRY(hipModuleGetFunction(&k->fwd_jac, k->module, "ssa_jit_fwd_jac"));
     HIP_TRY(hipModuleGetFunction(&k->rec, k->module, "ssa_jit_rec"));
     HIP_TRY(hipModuleGetFunction(&k->bwd, k->module, "ssa_jit_bwd"));
     std::lock_guard<std::mutex> lk(g_jit_mu);
@@ -800,6 +801,95 @@ ssa_status ssa_run_device(const ssa_model *m, const double *rates, int64_t n_tra
         stats->kernel_ms = kms;
         return s;
     }
+    return SSA_OK;
+}
+
+ssa_status ssa_run_jacobian_device(const ssa_model *m, const double *rates, int64_t n_traj, double t_end,
+                                   const double *grid, int32_t G, uint64_t seed, uint64_t max_events, double *mean,
+                                   double *var, double *jac, void *stream, ssa_stats *stats) {
+    if (!m) return fail(SSA_E_INVALID, "model is NULL");
+    if (n_traj <= 0) return fail(SSA_E_INVALID, "n_traj must be > 0");
+    if (G <= 0 || !grid || !mean || !var || !jac) return fail(SSA_E_INVALID, "grid / mean / var / jac missing");
+    if (!(t_end >= 0.0) || !std::isfinite(t_end)) return fail(SSA_E_INVALID, "t_end must be finite and >= 0");
+    if (n_traj > ((int64_t)1 << 31) * kChunk) return fail(SSA_E_INVALID, "n_traj too large");
+    if (m->order != SSA_SUM_SEQ || m->M > kJitMaxReactions || m->S > kJitMaxSpecies)
+        return fail(SSA_E_UNSUPPORTED, "the forward Jacobian needs a sequential-order network with at most %d "
+                    "reactions and %d species", kJitMaxReactions, kJitMaxSpecies);
+    const int64_t n_items = (n_traj + kChunk - 1) / kChunk;
+    const size_t jrow = (size_t)(m->S + 1) * m->M;
+    const size_t slab_bytes = (size_t)n_items * G * jrow * sizeof(double);
+    size_t budget = (size_t)4 << 30;
+    if (const char *e = std::getenv("SSA_JAC_BYTES")) budget = (size_t)std::strtoull(e, nullptr, 10);
+    if (slab_bytes > budget)
+        return fail(SSA_E_UNSUPPORTED, "forward Jacobian scratch %zu bytes exceeds %zu (use ssa_backward_device)",
+                    slab_bytes, budget);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    keep_pool(dev);
+    StreamScratch scr(st);
+    std::shared_ptr<JitKernels> jk;
+    ssa_status s = get_jit(m, dev, jk);
+    if (s) return s;
+
+    NetDev n = base_net(m, rates, n_traj, t_end, grid, G, seed, max_events);
+    const size_t cells = (size_t)G * m->S;
+    void *D = nullptr, *Dhi = nullptr, *ctl = nullptr, *slabs = nullptr;
+    HIP_TRY(scr.alloc(&D, sizeof(unsigned long long) * 2 * cells));
+    HIP_TRY(scr.alloc(&Dhi, sizeof(unsigned long long) * cells));
+    HIP_TRY(scr.alloc(&ctl, 64 + sizeof(GridInfo)));
+    HIP_TRY(scr.alloc(&slabs, slab_bytes));
+    HIP_TRY(launch_zero(D, sizeof(unsigned long long) * 2 * cells, st));
+    HIP_TRY(launch_zero(Dhi, sizeof(unsigned long long) * cells, st));
+    HIP_TRY(launch_zero(ctl, 64, st));
+    n.ginfo = (const GridInfo *)((char *)ctl + 64);
+    HIP_TRY(launch_grid_info(grid, G, t_end, (GridInfo *)n.ginfo, st));
+    n.D = (unsigned long long *)D;
+    n.Dhi = (unsigned long long *)Dhi;
+    WorkList wl;
+    std::memset(&wl, 0, sizeof wl);
+    wl.net0 = n;
+    wl.range_begin = 0;
+    wl.range_end = n_traj;
+    wl.n_items = (int32_t)n_items;
+    wl.counter = (unsigned int *)ctl;
+    wl.stats = (unsigned long long *)((char *)ctl + 32);
+    wl.jac_slabs = (double *)slabs;
+    // window: moments (S x 2 words) and Jacobian ((S+1) x M words) per bin, 16 KB per wave
+    const size_t per_bin = (size_t)m->S * 2 + jrow;
+    int32_t W = 1;
+    while (W < 1024 && (size_t)(2 * W) * per_bin * 8 <= (size_t)16384 && W < G) W *= 2;
+    wl.win_bins = W;
+    wl.win_words = (int32_t)(W * per_bin);
+    const size_t lds = (size_t)(kBlock / kWave) * wl.win_words * sizeof(long long);
+    int per_cu = 0;
+    HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, jk->fwd_jac, kBlock, lds));
+    const int64_t blocks = grid_blocks(per_cu, dev, n_items);
+    EventPair ev;
+    if (stats && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
+    {
+        void *args[] = {&wl};
+        HIP_TRY(hipModuleLaunchKernel(jk->fwd_jac, (unsigned)blocks, 1, 1, kBlock, 1, 1, (unsigned)lds, st, args,
+                                      nullptr));
+    }
+    if (stats && ev.b) HIP_TRY(hipEventRecord(ev.b, st));
+    HIP_TRY(launch_finalize(n.D, n.Dhi, G, m->S, m->d_x0, n_traj, mean, var, st));
+    {
+        const int64_t jc = (int64_t)cells * m->M;
+        hipLaunchKernelGGL(jacobian_final_kernel, dim3((unsigned)((jc + 255) / 256)), dim3(256), 0, st,
+                           (const double *)slabs, n_items, G, m->S, m->M, n_traj, (const double *)mean, jac);
+        HIP_TRY(hipGetLastError());
+    }
+    if (stats) return collect_stats(wl.stats, st, ev.a, ev.b, stats);
+    return SSA_OK;
+}
+
+ssa_status ssa_jacobian_vjp(const double *jac, const double *w, int32_t G, int32_t S, int32_t M, double *grad,
+                            void *stream) {
+    if (!jac || !w || !grad || G <= 0 || S <= 0 || M <= 0) return fail(SSA_E_INVALID, "bad argument");
+    hipLaunchKernelGGL(jacobian_vjp_kernel, dim3((unsigned)M), dim3(256), 0, (hipStream_t)stream, jac, w,
+                       (int64_t)G * S, M, grad);
+    HIP_TRY(hipGetLastError());
     return SSA_OK;
 }
 

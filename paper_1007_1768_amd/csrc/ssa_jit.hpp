@@ -71,6 +71,16 @@ extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd_atomic(ssa
     ssa::sim_fwd_gen<ssa_gen::Net::M, false, false>(wl, p, ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
 }
 
+// Forward pass with the likelihood-ratio Jacobian: per wave, the moment window
+// (win_bins x S x 2 int64) followed by the Jacobian window (win_bins x (S+1) x M doubles);
+// wl.win_words is their total in 8-byte words.
+extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd_jac(ssa::WorkList wl) {
+    extern __shared__ long long ssa_win[];
+    ssa::RegPolicy p;
+    long long *w = ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words;
+    ssa::sim_fwd_jac<ssa_gen::Net::M>(wl, p, w, (double *)(w + wl.win_bins * ssa_gen::Net::S * 2));
+}
+
 extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_rec(ssa::WorkList wl) {
     ssa::RegPolicy p;
     ssa::sim_loop<ssa::kRec, ssa_gen::Net::M, false>(wl, p);

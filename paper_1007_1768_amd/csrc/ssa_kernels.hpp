@@ -393,6 +393,47 @@ __global__ void __launch_bounds__(1024) moment_final_batched_kernel(const FinalN
     moment_final_body(f.D, f.Dhi, f.G, f.S, block_species[blockIdx.x], f.x0, f.n_traj, f.mean, f.var, nullptr);
 }
 
+// Likelihood-ratio Jacobian from the per-item slabs [items][G][S+1][M] (row S holds the
+// score sums): J[g][s][j] = F/N - mean[g][s] Z/N with F and Z summed over the items in
+// order.  One thread per (g, s, j).
+__global__ void jacobian_final_kernel(const double *__restrict__ slabs, int64_t n_items, int32_t G, int32_t S,
+                                      int32_t M, int64_t n_traj, const double *__restrict__ mean,
+                                      double *__restrict__ jac) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)G * S * M) return;
+    const int32_t j = (int32_t)(idx % M);
+    const int64_t gs = idx / M;
+    const int32_t s = (int32_t)(gs % S);
+    const int32_t g = (int32_t)(gs / S);
+    const size_t item_words = (size_t)G * (S + 1) * M;
+    const size_t fo = ((size_t)g * (S + 1) + s) * M + j, zo = ((size_t)g * (S + 1) + S) * M + j;
+    double F = 0.0, Z = 0.0;
+    for (int64_t it = 0; it < n_items; ++it) {
+        F = F + slabs[it * item_words + fo];
+        Z = Z + slabs[it * item_words + zo];
+    }
+    const double dn = (double)n_traj;
+    jac[idx] = F / dn - mean[gs] * (Z / dn);
+}
+
+// grad_j = sum_{g,s} w[g][s] jac[g][s][j]: one block of 256 threads per j, strided partial
+// sums and a fixed tree, so the result does not depend on scheduling.
+__global__ void __launch_bounds__(256) jacobian_vjp_kernel(const double *__restrict__ jac,
+                                                           const double *__restrict__ w, int64_t cells, int32_t M,
+                                                           double *__restrict__ grad) {
+    const int32_t j = blockIdx.x;
+    double acc = 0.0;
+    for (int64_t q = threadIdx.x; q < cells; q += blockDim.x) acc = acc + w[q] * jac[q * M + j];
+    __shared__ double sh[256];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) sh[threadIdx.x] = sh[threadIdx.x] + sh[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) grad[j] = sh[0];
+}
+
 // Histogram: inclusive prefix over g of the bin differences plus N in the initial bin.
 __global__ void hist_prefix_kernel(const int32_t *__restrict__ Hd, int32_t G, int32_t nb, int32_t init_bin,
                                    int64_t n_traj, uint32_t *__restrict__ out) {

@@ -121,6 +121,7 @@ struct WorkList {
     int32_t win_bins;            // forward: grid bins per wave window (power of two)
     int32_t win_words;           // forward: 64-bit LDS words per wave window (win_bins * S_max * 2)
     unsigned long long *slabs;   // forward, slab mode: [waves][G][S][2] wave-private sums
+    double *jac_slabs;           // forward with Jacobian: [items][G][S+1][M] per-work-item sums
     unsigned int *counter;       // work-item counter (zeroed before launch)
     unsigned long long *stats;   // [0] events, [1] max steps, [2] flags
 };
@@ -695,6 +696,237 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
     }
 
     // wave totals -> global statistics
+    for (int off = 32; off > 0; off >>= 1) {
+        tot_events += __shfl_xor(tot_events, off);
+        max_steps = max(max_steps, (unsigned long long)__shfl_xor(max_steps, off));
+        flags |= (uint32_t)__shfl_xor((int)flags, off);
+    }
+    if (lane == 0) {
+        if (tot_events) atomicAdd(wl.stats + 0, tot_events);
+        atomicMax(wl.stats + 1, max_steps);
+        if (flags) atomicOr(wl.stats + 2, (unsigned long long)flags);
+    }
+}
+
+// Forward pass that also accumulates the likelihood-ratio Jacobian of the grid means
+// (single network, specialised kernels).  At every grid crossing t_g of a trajectory the
+// score z_j(t_g) = B_j - a_j (t_g - t) (B_j = n_j - A_j at the interval start t, a_j the
+// interval's propensities) contributes x_s z_j to F[g][s][j] and z_j to Z[g][j]; the
+// Jacobian is J = F/N - mean Z/N (the centred estimator).  The crossings of an interval
+// [t, t_next) are the grid points [g, bin of t_next); they are added to a second LDS window
+// (jwin, win_bins bins x (S+1) x M doubles) when they fall inside it: a lane whose next
+// write lies beyond the window waits, and an interval longer than the window is added in
+// pieces as the window slides.  Every trajectory crosses every grid point, so each bin of
+// the window is complete when it is flushed and is stored (not added) into the work
+// item's own slab; a fixed-order reduction over the items then makes the Jacobian
+// independent of scheduling.
+template <int MM, class Policy>
+__device__ __forceinline__ void sim_fwd_jac(const WorkList &wl, Policy &p, long long *win, double *jwin) {
+    static_assert(MM > 0, "the Jacobian needs the per-reaction registers");
+    const uint32_t lane = __lane_id();
+    const int32_t W = wl.win_bins;
+    const NetDev n = wl.net0;
+    const int32_t S = n.S, G = n.G, M = n.M;
+    const int32_t row_words = S * 2;
+    const int32_t jrow = (S + 1) * M;
+    const GridInfo gi = *(const SSA_CONST GridInfo *)n.ginfo;
+    GridView gv;
+    gv.grid = wave_uniform(n.grid);
+    gv.T = wave_uniform(gi.T);
+    gv.D = wave_uniform(gi.D);
+    gv.lo = wave_uniform(gi.lo);
+    gv.scale = wave_uniform(gi.scale);
+    gv.G = wave_uniform(G);
+    gv.uniform = wave_uniform(gi.uniform);
+    uint32_t flags = 0;
+    unsigned long long tot_events = 0, max_steps = 0;
+    double a[MM], Ssum[MM], B[MM];
+
+    for (;;) {
+        int32_t item = 0;
+        if (lane == 0) item = (int32_t)atomicAdd(wl.counter, 1u);
+        item = wave_uniform(__shfl(item, 0));
+        if (item >= wl.n_items) break;
+        const int64_t begin = wl.range_begin + (int64_t)item * kChunk;
+        const int64_t count = min((int64_t)kChunk, wl.range_end - begin);
+        double *jslab = wl.jac_slabs + (size_t)item * G * jrow;
+        for (int32_t q = lane; q < W * row_words; q += kWave) win[q] = 0;
+        for (int32_t q = lane; q < W * jrow; q += kWave) jwin[q] = 0.0;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        int32_t base = 0;
+
+        // flush bins [lo, hi): moments by atomic adds of the non-zero words, the Jacobian
+        // window by plain stores into the item's slab
+        auto flush = [&](int32_t lo, int32_t hi) {
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            const int32_t words = (hi - lo) * row_words;
+            for (int32_t e = lane; e < words; e += kWave) {
+                const int32_t bin = lo + e / row_words, r = e - (e / row_words) * row_words;
+                long long *slot = win + (bin & (W - 1)) * row_words + r;
+                const long long v = *slot;
+                if (v != 0) {
+                    atomicAdd(n.D + (size_t)bin * row_words + r, (unsigned long long)v);
+                    *slot = 0;
+                }
+            }
+            const int32_t jwords = (hi - lo) * jrow;
+            for (int32_t e = lane; e < jwords; e += kWave) {
+                const int32_t bin = lo + e / jrow, r = e - (e / jrow) * jrow;
+                double *slot = jwin + (bin & (W - 1)) * jrow + r;
+                jslab[(size_t)bin * jrow + r] = *slot;
+                *slot = 0.0;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        };
+
+        // lane state: the pending interval [t, t_next) with crossings [gj, binp); fin marks
+        // the last interval (no event at its end)
+        bool active = (int64_t)lane < count;
+        const int64_t traj = begin + lane;
+        double t = 0.0, t_next = 0.0, u = 0.0, tau = 0.0;
+        double tg_next = gv.uniform ? 0.0 : ((const SSA_CONST double *)gv.grid)[0];
+        uint64_t k = 0, ev = 0;
+        int32_t g = 0, gj = 0, binp = G;
+        bool fin = false;
+        uint32_t ovf = 0;
+        if (active) p.reset(n);
+#pragma unroll
+        for (int j = 0; j < MM; ++j) B[j] = 0.0;
+
+        // draw the event after t (sets t_next, binp and the crossings [g, binp), or a final
+        // interval when the event lies beyond t_end or the state is absorbing)
+        auto draw = [&]() {
+            const u32x4 o = philox4x32_10((uint32_t)k, (uint32_t)(k >> 32), (uint32_t)traj,
+                                          (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
+            const double r2 = uniform_open1(o.v2, o.v3);
+            const double E = neg_log(uniform_open0(o.v0, o.v1));
+            p.template eval<MM>(n, a);
+            double acc = a[0];
+            Ssum[0] = acc;
+#pragma unroll
+            for (int j = 1; j < MM; ++j) {
+                acc = acc + a[j];
+                Ssum[j] = acc;
+            }
+            tau = E / acc;
+            t_next = t + tau;
+            gj = g;
+            if (acc == 0.0 || t_next > n.t_end) {
+                if (acc != 0.0) k = k + 1;
+                fin = true;                        // crossings [g, G), no event
+                binp = G;
+                return;
+            }
+            k = k + 1;
+            if (ev >= n.max_events) {
+                flags |= kFlagEventLimit;
+                fin = true;
+                binp = G;
+                return;
+            }
+            u = r2 * acc;
+            binp = g;
+            if (g < G && t_next > tg_next) binp = gv.next_bin(g, t_next, tg_next);
+        };
+        if (active) draw();
+
+        for (;;) {
+            // next write position: a crossing still to add, else the event's bin
+            const int32_t pnext = gj < binp ? gj : (fin ? G : binp);
+            const bool blocked = active && pnext < G && pnext >= base + W;
+            if (active && !blocked) {
+                // crossings inside the window
+                const int32_t hi = min(binp, base + W);
+                for (int32_t gg = gj; gg < hi; ++gg) {
+                    const double dt = gv.at(gg) - t;
+                    double z[MM];
+#pragma unroll
+                    for (int j = 0; j < MM; ++j) z[j] = B[j] - a[j] * dt;
+                    double *jr = jwin + (gg & (W - 1)) * jrow;
+                    p.for_each_species([&](int32_t sp, int32_t xs) {
+                        const double xd = (double)xs;
+#pragma unroll
+                        for (int j = 0; j < MM; ++j)
+                            if (j < M) atomicAdd(jr + sp * M + j, xd * z[j]);
+                    });
+#pragma unroll
+                    for (int j = 0; j < MM; ++j)
+                        if (j < M) atomicAdd(jr + S * M + j, z[j]);
+                }
+                gj = max(gj, hi);
+                if (gj >= binp) {
+                    if (fin) {
+                        active = false;
+                    } else if (binp >= G || binp < base + W) {
+                        // apply the event at t_next
+                        int32_t sel = 0;
+#pragma unroll
+                        for (int j = 0; j < MM; ++j) sel += (Ssum[j] <= u) ? 1 : 0;
+                        if (sel >= M) {
+                            for (int32_t j = M - 1; j >= 0; --j) {
+                                if (p.one(n, j) > 0.0) { sel = j; break; }
+                            }
+                            sel = min(sel, M - 1);
+                        }
+                        const int32_t bin = binp;
+                        const bool inb = bin < G;
+                        long long *wrow = win + (bin & (W - 1)) * row_words;
+                        p.apply(n, sel, [&](int32_t sp, int32_t xo, int32_t xn) {
+                            ovf |= (uint32_t)xn;
+                            const int32_t dl = inb ? xn - xo : 0;
+                            const long long d2 = (2ll * xo + dl) * (long long)dl;
+                            long long *w = wrow + sp * 2;
+                            atomicAdd((unsigned long long *)w, (unsigned long long)(long long)dl);
+                            if (d2 > -kSmallD2 && d2 < kSmallD2) {
+                                atomicAdd((unsigned long long *)(w + 1), (unsigned long long)d2);
+                            } else {
+                                atomicAdd((unsigned long long *)(w + 1), (unsigned long long)(d2 & ((1ll << 24) - 1)));
+                                atomicAdd(n.Dhi + (size_t)bin * S + sp, (unsigned long long)(d2 >> 24));
+                            }
+                            if (n.Hd && sp == n.h_species && dl != 0) {
+                                const int32_t bo = xo < n.h_lo ? 0 : min((xo - n.h_lo) / n.h_width, n.nb_hist - 1);
+                                const int32_t bn = xn < n.h_lo ? 0 : min((xn - n.h_lo) / n.h_width, n.nb_hist - 1);
+                                if (bo != bn) {
+                                    atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bo, -1);
+                                    atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bn, 1);
+                                }
+                            }
+                        });
+                        if ((int32_t)ovf < 0) {
+                            flags |= kFlagOverflow;
+                            active = false;
+                        } else {
+                            // the score moves by [j fired] - a_j tau over the interval
+#pragma unroll
+                            for (int j = 0; j < MM; ++j) B[j] = B[j] + ((j == sel ? 1.0 : 0.0) - a[j] * tau);
+                            t = t_next;
+                            ev = ev + 1;
+                            g = bin;
+                            draw();
+                        }
+                    }
+                }
+                if (!active) {
+                    tot_events += ev;
+                    max_steps = max(max_steps, (unsigned long long)ev);
+                }
+            }
+            if (__ballot(active) == 0) break;
+            const int32_t pn = gj < binp ? gj : (fin ? G : binp);
+            if (__ballot(active && pn < G && pn >= base + W)) {
+                const int32_t m = wave_min(active ? pn : G);
+                if (m > base) {
+                    flush(base, min(m, base + W));
+                    base = m;
+                }
+            }
+        }
+        flush(base, min(G, base + W));
+    }
+
     for (int off = 32; off > 0; off >>= 1) {
         tot_events += __shfl_xor(tot_events, off);
         max_steps = max(max_steps, (unsigned long long)__shfl_xor(max_steps, off));

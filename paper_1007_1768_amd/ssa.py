@@ -19,6 +19,7 @@ _NAMES = {1: "SSA_E_INVALID", 2: "SSA_E_NOMEM", 3: "SSA_E_DEVICE", 4: "SSA_E_OVE
           5: "SSA_E_EVENT_LIMIT", 6: "SSA_E_UNSUPPORTED"}
 
 EXPORTS = ["ssa_model_create", "ssa_model_destroy", "ssa_run", "ssa_run_device", "ssa_backward_device",
+           "ssa_run_jacobian_device", "ssa_jacobian_vjp",
            "ssa_record", "ssa_batch_create", "ssa_batch_run", "ssa_batch_destroy", "ssa_last_error"]
 
 
@@ -61,6 +62,8 @@ def load(path=None):
     L.ssa_run.argtypes = [vp, i64, dbl, vp, i32, u64, vp, vp, vp]
     L.ssa_run_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
     L.ssa_backward_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
+    L.ssa_run_jacobian_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
+    L.ssa_jacobian_vjp.argtypes = [vp, vp, i32, i32, i32, vp, vp]
     L.ssa_record.argtypes = [vp, vp, i64, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
     L.ssa_batch_create.argtypes = [i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
     L.ssa_batch_run.argtypes = [vp, vp, vp, vp, vp]
@@ -178,6 +181,35 @@ def backward_device(model, n_traj, t_end, grid, seed, w, mhat, rates=None, max_e
     return grad, (st.as_dict() if st is not None else None)
 
 
+def run_jacobian_device(model, n_traj, t_end, grid, seed, rates=None, max_events=0, stream=None,
+                        with_stats=False, out=None):
+    """Forward pass with the likelihood-ratio Jacobian (ssa_run_jacobian_device); returns
+    (mean (G,S), var (G,S), jac (G,S,M), stats or None)."""
+    import torch
+    G = grid.shape[0]
+    if out is None:
+        mean = torch.empty((G, model.S), dtype=torch.float64, device=grid.device)
+        var = torch.empty_like(mean)
+        jac = torch.empty((G, model.S, model.M), dtype=torch.float64, device=grid.device)
+    else:
+        mean, var, jac = out
+    st = Stats() if with_stats else None
+    _check(load().ssa_run_jacobian_device(model.handle, _tp(rates), int(n_traj), float(t_end), _tp(grid), G,
+                                          int(seed), int(max_events), _tp(mean), _tp(var), _tp(jac),
+                                          _stream(stream), ctypes.byref(st) if st is not None else None))
+    return mean, var, jac, (st.as_dict() if st is not None else None)
+
+
+def jacobian_vjp(jac, w, stream=None, out=None):
+    """grad[j] = sum_{g,s} w[g,s] jac[g,s,j] on the device (ssa_jacobian_vjp)."""
+    import torch
+    G, S, M = jac.shape
+    grad = torch.empty(M, dtype=torch.float64, device=jac.device) if out is None else out
+    _check(load().ssa_jacobian_vjp(_tp(jac.contiguous()), _tp(w.contiguous()), G, S, M, _tp(grad),
+                                   _stream(stream)))
+    return grad
+
+
 def record(model, traj_begin, count, t_end, grid, seed, rates=None, max_events=0):
     """Per-trajectory record (ssa_record), host arrays; returns (status, dict) like the oracle's."""
     grid = np.ascontiguousarray(grid, dtype=np.float64)
@@ -247,24 +279,34 @@ def _make_function():
     class SSAMean(torch.autograd.Function):
         """mean = E[X(t_g)] over n_traj trajectories, differentiable in log rate constants.
 
-        forward: ssa_run_device with rates = exp(log_rates); backward: the likelihood-ratio
-        kernel (ssa_backward_device) re-simulates the same trajectories, centred on the
-        forward mean."""
+        mode "resim": forward ssa_run_device with rates = exp(log_rates); backward the
+        likelihood-ratio kernel (ssa_backward_device) re-simulates the same trajectories,
+        centred on the forward mean.  mode "jacobian": the forward pass also forms the
+        likelihood-ratio Jacobian (ssa_run_jacobian_device) and the backward is its
+        vector-Jacobian product (ssa_jacobian_vjp): one simulation pass in all."""
 
         @staticmethod
-        def forward(ctx, log_rates, model, n_traj, t_end, grid, seed):
+        def forward(ctx, log_rates, model, n_traj, t_end, grid, seed, mode):
             rates = torch.exp(log_rates.detach()).contiguous()
-            mean, _, _, _ = run_device(model, n_traj, t_end, grid, seed, rates=rates)
-            ctx.save_for_backward(rates, mean)
-            ctx.cfg = (model, n_traj, t_end, grid, seed)
+            if mode == "jacobian":
+                mean, _, jac, _ = run_jacobian_device(model, n_traj, t_end, grid, seed, rates=rates)
+                ctx.save_for_backward(jac)
+            else:
+                mean, _, _, _ = run_device(model, n_traj, t_end, grid, seed, rates=rates)
+                ctx.save_for_backward(rates, mean)
+            ctx.cfg = (model, n_traj, t_end, grid, seed, mode)
             return mean
 
         @staticmethod
         def backward(ctx, grad_mean):
-            rates, mean = ctx.saved_tensors
-            model, n_traj, t_end, grid, seed = ctx.cfg
-            g, _ = backward_device(model, n_traj, t_end, grid, seed, grad_mean.contiguous(), mean, rates=rates)
-            return g, None, None, None, None, None
+            model, n_traj, t_end, grid, seed, mode = ctx.cfg
+            if mode == "jacobian":
+                (jac,) = ctx.saved_tensors
+                g = jacobian_vjp(jac, grad_mean.contiguous())
+            else:
+                rates, mean = ctx.saved_tensors
+                g, _ = backward_device(model, n_traj, t_end, grid, seed, grad_mean.contiguous(), mean, rates=rates)
+            return g, None, None, None, None, None, None
 
     return SSAMean
 
@@ -272,9 +314,12 @@ def _make_function():
 _fn = None
 
 
-def ssa_mean(log_rates, model, n_traj, t_end, grid, seed):
-    """Differentiable grid means (torch.autograd.Function over the HIP forward/backward)."""
+def ssa_mean(log_rates, model, n_traj, t_end, grid, seed, mode="resim"):
+    """Differentiable grid means (torch.autograd.Function over the HIP kernels); mode
+    "resim" (re-simulating backward) or "jacobian" (Jacobian formed in the forward pass)."""
     global _fn
     if _fn is None:
         _fn = _make_function()
-    return _fn.apply(log_rates, model, n_traj, t_end, grid, seed)
+    if mode not in ("resim", "jacobian"):
+        raise ValueError("mode must be 'resim' or 'jacobian'")
+    return _fn.apply(log_rates, model, n_traj, t_end, grid, seed, mode)
