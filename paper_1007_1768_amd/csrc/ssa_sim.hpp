@@ -610,26 +610,25 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
                         sel = min(sel, M - 1);
                     }
                     const int32_t bin = binp;
+                    const bool inb = bin < G;
+                    long long *wrow = win + (bin & (W - 1)) * row_words;
                     p.apply(n, sel, [&](int32_t sp, int32_t xo, int32_t xn) {
+                        // unchanged species and events past the last grid point add zeros
                         ovf |= (uint32_t)xn;
-                        if (bin < G) {
-                            const int32_t dl = xn - xo;
-                            const long long d2 = (2ll * xo + dl) * (long long)dl;
-                            long long *w = win + (bin & (W - 1)) * row_words + sp * 2;
-                            atomicAdd((unsigned long long *)w, (unsigned long long)(long long)dl);
-                            if (d2 > -kSmallD2 && d2 < kSmallD2) {
-                                atomicAdd((unsigned long long *)(w + 1), (unsigned long long)d2);
-                            } else {
-                                atomicAdd((unsigned long long *)(w + 1), (unsigned long long)(d2 & ((1ll << 24) - 1)));
-                                atomicAdd(n.Dhi + (size_t)bin * S + sp, (unsigned long long)(d2 >> 24));
-                            }
-                            if (n.Hd && sp == n.h_species) {
-                                const int32_t bo = xo < n.h_lo ? 0 : min((xo - n.h_lo) / n.h_width, n.nb_hist - 1);
-                                const int32_t bn = xn < n.h_lo ? 0 : min((xn - n.h_lo) / n.h_width, n.nb_hist - 1);
-                                if (bo != bn) {
-                                    atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bo, -1);
-                                    atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bn, 1);
-                                }
+                        const int32_t dl = inb ? xn - xo : 0;
+                        const long long d2 = (2ll * xo + dl) * (long long)dl;
+                        long long *w = wrow + sp * 2;
+                        const bool small = d2 > -kSmallD2 && d2 < kSmallD2;
+                        atomicAdd((unsigned long long *)w, (unsigned long long)(long long)dl);
+                        atomicAdd((unsigned long long *)(w + 1),
+                                  (unsigned long long)(small ? d2 : (d2 & ((1ll << 24) - 1))));
+                        if (!small) atomicAdd(n.Dhi + (size_t)bin * S + sp, (unsigned long long)(d2 >> 24));
+                        if (n.Hd && sp == n.h_species && dl != 0) {
+                            const int32_t bo = xo < n.h_lo ? 0 : min((xo - n.h_lo) / n.h_width, n.nb_hist - 1);
+                            const int32_t bn = xn < n.h_lo ? 0 : min((xn - n.h_lo) / n.h_width, n.nb_hist - 1);
+                            if (bo != bn) {
+                                atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bo, -1);
+                                atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bn, 1);
                             }
                         }
                     });
