@@ -358,20 +358,23 @@ hipError_t launch_generic(int mm, const WorkList &wl, int64_t n_items, int dev, 
 // Forward launches (selective-memory windows, see ssa_sim.hpp)
 // ---------------------------------------------------------------------------------------
 
-// Bytes of LDS per window (SSA_WIN_BYTES overrides; 512 .. 16384).  8 KB measured best on
-// the 4-species network (4 KB: +5 % forward time, 2 KB: +20 % on the 10^4-point grid).
-size_t window_budget() {
-    size_t b = 8192;
+// Bytes of LDS per window (SSA_WIN_BYTES overrides; 512 .. 16384).  The specialised
+// kernels (one window per wave, state in registers) do best with 8 KB on the 4-species
+// network (4 KB: +5 % forward time, 2 KB: +20 % on the 10^4-point grid); the table-driven
+// kernel holds two windows next to its LDS state columns, where 4 KB keeps two blocks per
+// CU (8 KB slowed the batched workload by half).
+size_t window_budget(bool generic) {
+    size_t b = generic ? 4096 : 8192;
     if (const char *e = std::getenv("SSA_WIN_BYTES")) b = (size_t)std::strtoull(e, nullptr, 10);
     return std::min<size_t>(std::max<size_t>(b, 512), 16384);
 }
 
 // Window length in bins: the largest power of two whose S x 2 int64 words per bin fit the
 // budget, capped at 1024 and at the grid length rounded up to a power of two.
-int32_t window_bins(int32_t S, int32_t G) {
+int32_t window_bins(int32_t S, int32_t G, bool generic) {
     const size_t per_bin = (size_t)S * 2 * sizeof(long long);
     int32_t W = 1;
-    while (W < 1024 && (size_t)(2 * W) * per_bin <= window_budget() && W < G) W *= 2;
+    while (W < 1024 && (size_t)(2 * W) * per_bin <= window_budget(generic) && W < G) W *= 2;
     return W;
 }
 
@@ -586,7 +589,7 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
         return SSA_OK;
     }
     FwdKernel k;
-    wl.win_bins = window_bins(S, G);
+    wl.win_bins = window_bins(S, G, !jit_eligible(m));
     wl.win_words = wl.win_bins * S * 2;
     // the specialised kernels run generations with one window per wave, the table-driven
     // kernel cohorts with kCohorts windows
@@ -1177,7 +1180,7 @@ ssa_status batch_enqueue(ssa_batch *bt, hipStream_t st) {
     wl.stats = bt->d_stats;
     int32_t gmax = 0;
     for (int32_t g : bt->G) gmax = std::max(gmax, g);
-    wl.win_bins = window_bins(bt->s_rows, gmax);
+    wl.win_bins = window_bins(bt->s_rows, gmax, true);
     wl.win_words = wl.win_bins * bt->s_rows * 2;
     FwdKernel k;
     if (!pick_generic_fwd<true>(bt->mm, k)) return fail(SSA_E_UNSUPPORTED, "no kernel");
