@@ -116,7 +116,8 @@ bool prefer_generic() {
 // ---------------------------------------------------------------------------------------
 struct JitKernels {
     hipModule_t module = nullptr;
-    hipFunction_t fwd = nullptr, fwd_atomic = nullptr, fwd_jac = nullptr, rec = nullptr, bwd = nullptr;
+    hipFunction_t fwd = nullptr, fwd_atomic = nullptr, fwd_hist = nullptr, fwd_slab_hist = nullptr, fwd_jac = nullptr,
+                  rec = nullptr, bwd = nullptr;
 };
 
 std::mutex g_jit_mu;
@@ -276,6 +277,8 @@ ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out
     HIP_TRY(hipModuleLoadData(&k->module, code.data()));
     HIP_TRY(hipModuleGetFunction(&k->fwd, k->module, "ssa_jit_fwd"));
     HIP_TRY(hipModuleGetFunction(&k->fwd_atomic, k->module, "ssa_jit_fwd_atomic"));
+    HIP_TRY(hipModuleGetFunction(&k->fwd_hist, k->module, "ssa_jit_fwd_hist"));
+    HIP_TRY(hipModuleGetFunction(&k->fwd_slab_hist, k->module, "ssa_jit_fwd_slab_hist"));
     HIP_TRY(hipModuleGetFunction(&k->fwd_jac, k->module, "ssa_jit_fwd_jac"));
     HIP_TRY(hipModuleGetFunction(&k->rec, k->module, "ssa_jit_rec"));
     HIP_TRY(hipModuleGetFunction(&k->bwd, k->module, "ssa_jit_bwd"));
@@ -599,8 +602,9 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
         ssa_status s = get_jit(m, dev, jk);
         if (s) return s;
         k.jit = true;
-        k.f_slab = jk->fwd;
-        k.f_atomic = jk->fwd_atomic;
+        const bool hist = wl.net0.Hd != nullptr;
+        k.f_slab = hist ? jk->fwd_slab_hist : jk->fwd;
+        k.f_atomic = hist ? jk->fwd_hist : jk->fwd_atomic;
         k.lds = win_bytes;
     } else {
         if (m->max_changes > kChg)

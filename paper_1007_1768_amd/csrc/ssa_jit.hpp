@@ -15,17 +15,27 @@ namespace ssa {
 struct RegPolicy {
     using Net = ssa_gen::Net;
     int32_t x[Net::S];
+    double c[Net::M];     // rate constants, held in vector registers for the whole launch
 
-    __device__ __forceinline__ void switch_net(const NetDev &) {}
+    // The rates are loaded once and pinned in VGPRs: read through the scalar cache at every
+    // event they put a load and its wait (which also waits for the outstanding LDS
+    // atomics) on each event's critical path.
+    __device__ __forceinline__ void switch_net(const NetDev &n) {
+#pragma unroll
+        for (int j = 0; j < Net::M; ++j) {
+            c[j] = n.rate[j];
+            asm volatile("" : "+v"(c[j]));
+        }
+    }
     __device__ __forceinline__ void reset(const NetDev &) { Net::init(x); }
     template <int MM>
-    __device__ __forceinline__ void eval(const NetDev &n, double (&a)[MM]) const {
+    __device__ __forceinline__ void eval(const NetDev &, double (&a)[MM]) const {
         static_assert(MM == Net::M, "one propensity slot per reaction");
-        Net::props(x, (const SSA_CONST double *)n.rate, a);
+        Net::props(x, c, a);
     }
-    __device__ double one(const NetDev &n, int32_t j) const {
+    __device__ double one(const NetDev &, int32_t j) const {
         double a[Net::M];
-        Net::props(x, (const SSA_CONST double *)n.rate, a);
+        Net::props(x, c, a);
         double v = 0.0;
 #pragma unroll
         for (int q = 0; q < Net::M; ++q) v = (q == j) ? a[q] : v;
@@ -62,13 +72,30 @@ struct RegPolicy {
 extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd(ssa::WorkList wl) {
     extern __shared__ long long ssa_win[];
     ssa::RegPolicy p;
-    ssa::sim_fwd_gen<ssa_gen::Net::M, false, true>(wl, p, ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
+    ssa::sim_fwd_gen<ssa_gen::Net::M, false, true, false>(wl, p,
+                                                          ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
 }
 
 extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd_atomic(ssa::WorkList wl) {
     extern __shared__ long long ssa_win[];
     ssa::RegPolicy p;
-    ssa::sim_fwd_gen<ssa_gen::Net::M, false, false>(wl, p, ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
+    ssa::sim_fwd_gen<ssa_gen::Net::M, false, false, false>(wl, p,
+                                                           ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
+}
+
+// The same with the per-grid-point histogram of one species.
+extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd_hist(ssa::WorkList wl) {
+    extern __shared__ long long ssa_win[];
+    ssa::RegPolicy p;
+    ssa::sim_fwd_gen<ssa_gen::Net::M, false, false, true>(wl, p,
+                                                          ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
+}
+
+extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd_slab_hist(ssa::WorkList wl) {
+    extern __shared__ long long ssa_win[];
+    ssa::RegPolicy p;
+    ssa::sim_fwd_gen<ssa_gen::Net::M, false, true, true>(wl, p,
+                                                         ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
 }
 
 // Forward pass with the likelihood-ratio Jacobian: per wave, the moment window

@@ -493,8 +493,9 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 // its (up to) 64 trajectories to the end with one window that follows the slowest lane,
 // then takes the next item.  The loop is tighter than the cohort form below, which pays
 // off for networks compiled into registers.  win: the wave's LDS window, wl.win_bins bins
-// x S species x (sum nu, sum (2x+nu)nu) as int64.
-template <int MM, bool BATCH, bool SLAB, class Policy>
+// x S species x (sum nu, sum (2x+nu)nu) as int64.  HIST: with the per-grid-point histogram
+// (a separate instantiation, so runs without one carry none of its code).
+template <int MM, bool BATCH, bool SLAB, bool HIST, class Policy>
 __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long long *win) {
     constexpr int MR = MM > 0 ? MM : 1;
     const uint32_t lane = __lane_id();
@@ -603,11 +604,13 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
                     } else {
                         sel = p.select(n, u);
                     }
-                    if (sel >= M) {
-                        for (int32_t j = M - 1; j >= 0; --j) {
-                            if (p.one(n, j) > 0.0) { sel = j; break; }
+                    if (__ballot(sel >= M)) {          // rare: rounding left no S_j > u
+                        if (sel >= M) {
+                            for (int32_t j = M - 1; j >= 0; --j) {
+                                if (p.one(n, j) > 0.0) { sel = j; break; }
+                            }
+                            sel = min(sel, M - 1);
                         }
-                        sel = min(sel, M - 1);
                     }
                     const int32_t bin = binp;
                     const bool inb = bin < G;
@@ -622,8 +625,10 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
                         atomicAdd((unsigned long long *)w, (unsigned long long)(long long)dl);
                         atomicAdd((unsigned long long *)(w + 1),
                                   (unsigned long long)(small ? d2 : (d2 & ((1ll << 24) - 1))));
-                        if (!small) atomicAdd(n.Dhi + (size_t)bin * S + sp, (unsigned long long)(d2 >> 24));
-                        if (n.Hd && sp == n.h_species && dl != 0) {
+                        if (__ballot(!small)) {             // rare: |(2x+nu)nu| >= 2^24
+                            if (!small) atomicAdd(n.Dhi + (size_t)bin * S + sp, (unsigned long long)(d2 >> 24));
+                        }
+                        if (HIST && sp == n.h_species && dl != 0) {
                             const int32_t bo = xo < n.h_lo ? 0 : min((xo - n.h_lo) / n.h_width, n.nb_hist - 1);
                             const int32_t bn = xn < n.h_lo ? 0 : min((xn - n.h_lo) / n.h_width, n.nb_hist - 1);
                             if (bo != bn) {
@@ -740,6 +745,7 @@ __device__ __forceinline__ void sim_fwd_jac(const WorkList &wl, Policy &p, long 
     uint32_t flags = 0;
     unsigned long long tot_events = 0, max_steps = 0;
     double a[MM], Ssum[MM], B[MM];
+    p.switch_net(n);
 
     for (;;) {
         int32_t item = 0;
