@@ -574,122 +574,117 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
             __builtin_amdgcn_wave_barrier();
         };
 
-        // lane state
+        // lane state; every active lane holds a drawn event at t_next (bin binp) to apply
         bool active = (int64_t)lane < count;
         const int64_t traj = begin + lane;
         double t = 0.0, t_next = 0.0, u = 0.0;
         double tg_next = gv.uniform ? 0.0 : ((const SSA_CONST double *)gv.grid)[0];
         uint64_t k = 0, ev = 0;
         int32_t g = 0, binp = G;
-        bool pend = false;
         uint32_t ovf = 0;
         if (active) p.reset(n0);
 
+        // draw the event after t from the exponential variate En and the uniform r2n; a lane
+        // whose state is absorbing, whose event lies beyond t_end or that reached the event
+        // limit ends here (predicated, no branches but the grid search)
+        auto draw = [&](const NetDev &n, double En, double r2n) {
+            double acc;
+            if constexpr (MM > 0) {
+                p.template eval<MM>(n, a);
+                acc = a[0];
+                Ssum[0] = acc;
+#pragma unroll
+                for (int j = 1; j < MM; ++j) {
+                    acc = acc + a[j];
+                    Ssum[j] = acc;
+                }
+            } else {
+                acc = p.total(n);
+            }
+            const bool absorb = acc == 0.0;                 // no draw: the state holds to t_end
+            t_next = t + En / acc;
+            const bool beyond = !absorb && t_next > n.t_end; // drawn, not applied
+            const bool limit = !absorb && !beyond && ev >= n.max_events;
+            k = absorb ? k : k + 1;
+            flags |= limit ? (uint32_t)kFlagEventLimit : 0u;
+            u = r2n * acc;
+            const bool go = !(absorb || beyond || limit);
+            binp = g;
+            if (go && g < G && t_next > tg_next) binp = gv.next_bin(g, t_next, tg_next);
+            tot_events += go ? 0ull : (unsigned long long)ev;
+            max_steps = go ? max_steps : max(max_steps, (unsigned long long)ev);
+            active = go;
+        };
+        if (active) {
+            const NetDev n = current_net<BATCH>(wl, cur);
+            const u32x4 o = philox4x32_10(0u, 0u, (uint32_t)traj, (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
+            draw(n, neg_log(uniform_open0(o.v0, o.v1)), uniform_open1(o.v2, o.v3));
+        }
+
         for (;;) {
-            const bool blocked = active && pend && binp < G && binp >= base + W;
+            const bool blocked = active && binp < G && binp >= base + W;
             if (active && !blocked) {
                 const NetDev n = current_net<BATCH>(wl, cur);
-                // the next draw does not depend on the state: start it before the update.  A
-                // pending event has consumed draw k - 1, so the next one is draw k either way.
+                // the next draw does not depend on the state: start it before the update (the
+                // pending event consumed draw k - 1)
                 const u32x4 o = philox4x32_10((uint32_t)k, (uint32_t)(k >> 32), (uint32_t)traj,
                                               (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
                 const double r2n = uniform_open1(o.v2, o.v3);
                 const double En = neg_log(uniform_open0(o.v0, o.v1));
-                if (pend) {
-                    // apply the pending event at t_next (state unchanged since it was drawn)
-                    int32_t sel = 0;
-                    if constexpr (MM > 0) {
+                // apply the pending event at t_next (state unchanged since it was drawn)
+                int32_t sel = 0;
+                if constexpr (MM > 0) {
 #pragma unroll
-                        for (int j = 0; j < MM; ++j) sel += (Ssum[j] <= u) ? 1 : 0;
-                    } else {
-                        sel = p.select(n, u);
-                    }
-                    if (__ballot(sel >= M)) {          // rare: rounding left no S_j > u
-                        if (sel >= M) {
-                            for (int32_t j = M - 1; j >= 0; --j) {
-                                if (p.one(n, j) > 0.0) { sel = j; break; }
-                            }
-                            sel = min(sel, M - 1);
+                    for (int j = 0; j < MM; ++j) sel += (Ssum[j] <= u) ? 1 : 0;
+                } else {
+                    sel = p.select(n, u);
+                }
+                if (__ballot(sel >= M)) {          // rare: rounding left no S_j > u
+                    if (sel >= M) {
+                        for (int32_t j = M - 1; j >= 0; --j) {
+                            if (p.one(n, j) > 0.0) { sel = j; break; }
                         }
-                    }
-                    const int32_t bin = binp;
-                    const bool inb = bin < G;
-                    long long *wrow = win + (bin & (W - 1)) * row_words;
-                    p.apply(n, sel, [&](int32_t sp, int32_t xo, int32_t xn) {
-                        // unchanged species and events past the last grid point add zeros
-                        ovf |= (uint32_t)xn;
-                        const int32_t dl = inb ? xn - xo : 0;
-                        const long long d2 = (2ll * xo + dl) * (long long)dl;
-                        long long *w = wrow + sp * 2;
-                        const bool small = d2 > -kSmallD2 && d2 < kSmallD2;
-                        atomicAdd((unsigned long long *)w, (unsigned long long)(long long)dl);
-                        atomicAdd((unsigned long long *)(w + 1),
-                                  (unsigned long long)(small ? d2 : (d2 & ((1ll << 24) - 1))));
-                        if (__ballot(!small)) {             // rare: |(2x+nu)nu| >= 2^24
-                            if (!small) atomicAdd(n.Dhi + (size_t)bin * S + sp, (unsigned long long)(d2 >> 24));
-                        }
-                        if (HIST && sp == n.h_species && dl != 0) {
-                            const int32_t bo = xo < n.h_lo ? 0 : min((xo - n.h_lo) / n.h_width, n.nb_hist - 1);
-                            const int32_t bn = xn < n.h_lo ? 0 : min((xn - n.h_lo) / n.h_width, n.nb_hist - 1);
-                            if (bo != bn) {
-                                atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bo, -1);
-                                atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bn, 1);
-                            }
-                        }
-                    });
-                    pend = false;
-                    if ((int32_t)ovf < 0) {
-                        flags |= kFlagOverflow;
-                        active = false;
-                    } else {
-                        t = t_next;
-                        ev = ev + 1;
-                        g = bin;
+                        sel = min(sel, M - 1);
                     }
                 }
-                if (active) {
-                    // draw the next event
-                    double acc;
-                    if constexpr (MM > 0) {
-                        p.template eval<MM>(n, a);
-                        acc = a[0];
-                        Ssum[0] = acc;
-#pragma unroll
-                        for (int j = 1; j < MM; ++j) {
-                            acc = acc + a[j];
-                            Ssum[j] = acc;
-                        }
-                    } else {
-                        acc = p.total(n);
+                const int32_t bin = binp;
+                const bool inb = bin < G;
+                long long *wrow = win + (bin & (W - 1)) * row_words;
+                p.apply(n, sel, [&](int32_t sp, int32_t xo, int32_t xn) {
+                    // events past the last grid point add zeros
+                    ovf |= (uint32_t)xn;
+                    const int32_t dl = inb ? xn - xo : 0;
+                    const long long d2 = (2ll * xo + dl) * (long long)dl;
+                    long long *w = wrow + sp * 2;
+                    const bool small = d2 > -kSmallD2 && d2 < kSmallD2;
+                    atomicAdd((unsigned long long *)w, (unsigned long long)(long long)dl);
+                    atomicAdd((unsigned long long *)(w + 1),
+                              (unsigned long long)(small ? d2 : (d2 & ((1ll << 24) - 1))));
+                    if (__ballot(!small)) {             // rare: |(2x+nu)nu| >= 2^24
+                        if (!small) atomicAdd(n.Dhi + (size_t)bin * S + sp, (unsigned long long)(d2 >> 24));
                     }
-                    if (acc == 0.0) {
-                        active = false;                // absorbing: the state holds to t_end
-                    } else {
-                        const double r2 = r2n;
-                        t_next = t + En / acc;
-                        k = k + 1;
-                        if (t_next > n.t_end) {
-                            active = false;            // beyond the horizon: not applied
-                        } else if (ev >= n.max_events) {
-                            flags |= kFlagEventLimit;
-                            active = false;
-                        } else {
-                            u = r2 * acc;
-                            binp = g;
-                            if (g < G && t_next > tg_next) binp = gv.next_bin(g, t_next, tg_next);
-                            pend = true;
+                    if (HIST && sp == n.h_species && dl != 0) {
+                        const int32_t bo = xo < n.h_lo ? 0 : min((xo - n.h_lo) / n.h_width, n.nb_hist - 1);
+                        const int32_t bn = xn < n.h_lo ? 0 : min((xn - n.h_lo) / n.h_width, n.nb_hist - 1);
+                        if (bo != bn) {
+                            atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bo, -1);
+                            atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bn, 1);
                         }
                     }
-                    if (!active) {
-                        tot_events += ev;
-                        max_steps = max(max_steps, (unsigned long long)ev);
-                    }
-                }
+                });
+                // a count that left the int32 range ends the lane with an error
+                const bool bad = (int32_t)ovf < 0;
+                flags |= bad ? (uint32_t)kFlagOverflow : 0u;
+                t = t_next;
+                ev = ev + 1;
+                g = bin;
+                draw(n, En, r2n);
+                active = active && !bad;
             }
             // window upkeep: slide when a lane is waiting beyond it
             if (__ballot(active) == 0) break;
-            if (__ballot(active && pend && binp < G && binp >= base + W)) {
-                const int32_t m = wave_min(active && pend ? binp : G);
+            if (__ballot(active && binp < G && binp >= base + W)) {
+                const int32_t m = wave_min(active ? binp : G);
                 if (m > base) {
                     flush(base, min(m, base + W));
                     base = m;
