@@ -280,7 +280,8 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
     for (;;) {
         // ---------------- refill idle lanes ----------------
         const uint64_t idle = __ballot(!active);
-        if (idle) {
+        // (once the work is exhausted, idle lanes cost nothing per event)
+        if (idle && !(exhausted && pending < 0 && pool_next >= pool_end)) {
             if (pool_next >= pool_end && !exhausted && pending < 0) {
                 int32_t item = 0;
                 if (lane == 0) item = (int32_t)atomicAdd(wl.counter, 1u);
@@ -414,12 +415,14 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
             finish = true;
         }
         if (!finish) {
-            if (sel >= M) {
-                // rounding left no S_j > u: the largest j with a_j > 0
-                for (int32_t j = M - 1; j >= 0; --j) {
-                    if (p.one(n, j) > 0.0) { sel = j; break; }
+            if (__ballot(sel >= M)) {
+                // rare: rounding left no S_j > u; take the largest j with a_j > 0
+                if (sel >= M) {
+                    for (int32_t j = M - 1; j >= 0; --j) {
+                        if (p.one(n, j) > 0.0) { sel = j; break; }
+                    }
+                    sel = min(sel, M - 1);   // a0 > 0 guarantees some a_j > 0; keeps the index in range
                 }
-                sel = min(sel, M - 1);   // a0 > 0 guarantees some a_j > 0; keeps the index in range
             }
             p.apply(n, sel, [&](int32_t, int32_t, int32_t xn) { ovf |= (uint32_t)xn; });
             if ((int32_t)ovf < 0) {
