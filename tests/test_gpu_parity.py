@@ -182,3 +182,18 @@ def test_results_do_not_depend_on_launch_history(ssa):
     a = _fwd(ssa, m, 3000, 20.0, grid, 5)
     b = _fwd(ssa, m, 3000, 20.0, grid, 5)
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_forward_many_reactions(ssa):
+    """Networks above 32 reactions run the table-driven kernel whose selection uses block
+    checkpoints of the partial sums; their moments equal the oracle's."""
+    nets = [n for n in inputs.random_networks(count=20) if n["reac"].shape[0] > 32][:4]
+    assert any(n["reac"].shape[0] > 64 for n in nets)
+    for n in nets:
+        t_end = min(n["t_end"], 0.3)
+        grid = inputs.uniform_grid(t_end, 37)
+        mean, var, _, stats = _fwd(ssa, n, 333, t_end, grid, n["seed"])
+        st, ref = orc.run(n, 333, t_end, grid, n["seed"])
+        assert st == 0
+        assert np.array_equal(mean, ref["mean"]) and np.array_equal(var, ref["var"]), n["name"]
+        assert stats["events"] == ref["events"]
