@@ -145,6 +145,25 @@ ssa_status ssa_backward_device(const ssa_model *model, const double *rates, int6
                                const double *w, const double *mhat, double *grad, void *stream,
                                ssa_stats *stats);
 
+/* Autotuning of the forward launch for this model and problem size: every candidate
+ * configuration (LDS window bytes 2048 .. 16384, flush by atomics or through wave-private
+ * slabs) is timed on the caller's problem (grid [n_grid] device, the same outputs for all:
+ * results never depend on the configuration); the fastest is remembered for (device
+ * architecture, kernel kind, network, G and N rounded up to powers of two) and used by
+ * later ssa_run_device / ssa_run calls in this process, and written to the JSON file named
+ * by SSA_TUNE_FILE when set (read back at the first lookup of a later process).  result may
+ * be NULL.  Synchronous.  win_bytes 0 / slab -1 denote the built-in defaults. */
+typedef struct {
+    int32_t win_bytes;
+    int32_t slab;
+    float best_ms;      /* forward kernel time of the chosen configuration */
+    float default_ms;   /* forward kernel time with the defaults */
+} ssa_tune_result;
+
+ssa_status ssa_autotune_forward(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
+                                const double *grid, int32_t n_grid, uint64_t seed, void *stream,
+                                ssa_tune_result *result);
+
 /* Forward pass that also returns the likelihood-ratio Jacobian of the grid means with
  * respect to theta_j = ln c_j, from the same single simulation pass:
  *   jac[g][s][j] = (1/N) sum_i (X^i_s(t_g) - mean_{g,s}) (n^i_j(t_g) - A^i_j(t_g))

@@ -366,18 +366,19 @@ hipError_t launch_generic(int mm, const WorkList &wl, int64_t n_items, int dev, 
 // network (4 KB: +5 % forward time, 2 KB: +20 % on the 10^4-point grid); the table-driven
 // kernel holds two windows next to its LDS state columns, where 4 KB keeps two blocks per
 // CU (8 KB slowed the batched workload by half).
-size_t window_budget(bool generic) {
+size_t window_budget(bool generic, int32_t tuned = 0) {
     size_t b = generic ? 4096 : 8192;
     if (const char *e = std::getenv("SSA_WIN_BYTES")) b = (size_t)std::strtoull(e, nullptr, 10);
+    if (tuned > 0) b = (size_t)tuned;
     return std::min<size_t>(std::max<size_t>(b, 512), 16384);
 }
 
 // Window length in bins: the largest power of two whose S x 2 int64 words per bin fit the
 // budget, capped at 1024 and at the grid length rounded up to a power of two.
-int32_t window_bins(int32_t S, int32_t G, bool generic) {
+int32_t window_bins(int32_t S, int32_t G, bool generic, int32_t tuned = 0) {
     const size_t per_bin = (size_t)S * 2 * sizeof(long long);
     int32_t W = 1;
-    while (W < 1024 && (size_t)(2 * W) * per_bin <= window_budget(generic) && W < G) W *= 2;
+    while (W < 1024 && (size_t)(2 * W) * per_bin <= window_budget(generic, tuned) && W < G) W *= 2;
     return W;
 }
 
@@ -385,9 +386,10 @@ int32_t window_bins(int32_t S, int32_t G, bool generic) {
 // private slabs summed by a reduction kernel afterwards (SSA_FWD_FLUSH=slab, when the slabs
 // fit in SSA_SLAB_BYTES, default 1 GiB).  Both give identical sums; on the 4-species
 // workloads they run at the same speed, and the atomic form needs no slab memory.
-bool want_slabs(size_t slab_bytes) {
+bool want_slabs(size_t slab_bytes, int32_t tuned = -1) {
     const char *e = std::getenv("SSA_FWD_FLUSH");
-    if (!e || std::strcmp(e, "slab") != 0) return false;
+    const bool asked = tuned >= 0 ? tuned == 1 : (e && std::strcmp(e, "slab") == 0);
+    if (!asked) return false;
     size_t b = (size_t)1 << 30;
     if (const char *q = std::getenv("SSA_SLAB_BYTES")) b = (size_t)std::strtoull(q, nullptr, 10);
     return slab_bytes <= b;
@@ -573,11 +575,95 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
     return SSA_OK;
 }
 
+// ---------------------------------------------------------------------------------------
+// Autotuning of the forward launch.  A tuned configuration (window bytes, flush target)
+// is kept per (device architecture, kernel kind, S, M, network source hash, G and N rounded
+// up to powers of two), in memory and, when SSA_TUNE_FILE names a file, in that JSON file
+// (read at the first lookup, rewritten after each tuning).  Every configuration gives the
+// same bits, so tuning only changes speed.
+// ---------------------------------------------------------------------------------------
+struct FwdTune {
+    int32_t win_bytes = 0;   // 0: default
+    int32_t slab = -1;       // -1: default
+    float ms = 0.f;
+};
+
+std::mutex g_tune_mu;
+std::map<std::string, FwdTune> g_tune;
+bool g_tune_loaded = false;
+
+uint64_t next_pow2(uint64_t v) {
+    uint64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+}
+
+std::string tune_key(const ssa_model *m, int64_t n_traj, int32_t G, int dev) {
+    uint64_t h = 1469598103934665603ull;
+    for (unsigned char c : m->jit_src) h = (h ^ c) * 1099511628211ull;
+    char buf[256];
+    snprintf(buf, sizeof buf, "%s|%s|S%d|M%d|G%llu|N%llu|h%016llx", device_arch(dev).c_str(),
+             m->order == SSA_SUM_BLOCK64 ? "wave" : (jit_eligible(m) ? "jit" : "table"), m->S, m->M,
+             (unsigned long long)next_pow2((uint64_t)G), (unsigned long long)next_pow2((uint64_t)n_traj),
+             (unsigned long long)h);
+    return buf;
+}
+
+// The cache file holds one entry per line inside the "entries" object:
+//   "<key>": {"win_bytes": <int>, "slab": <int>, "ms": <float>}
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char *path = std::getenv("SSA_TUNE_FILE");
+    if (!path) return;
+    FILE *f = std::fopen(path, "r");
+    if (!f) return;
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        char key[512];
+        int wb = 0, sl = -1;
+        float ms = 0.f;
+        if (std::sscanf(line, " \"%511[^\"]\": {\"win_bytes\": %d, \"slab\": %d, \"ms\": %f}", key, &wb, &sl, &ms) == 4) {
+            FwdTune t;
+            t.win_bytes = wb;
+            t.slab = sl;
+            t.ms = ms;
+            g_tune[key] = t;
+        }
+    }
+    std::fclose(f);
+}
+
+void tune_save_locked() {
+    const char *path = std::getenv("SSA_TUNE_FILE");
+    if (!path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\n  \"format\": \"ssa forward tuning, one entry per line\",\n  \"entries\": {\n");
+    size_t i = 0;
+    for (const auto &kv : g_tune) {
+        std::fprintf(f, "    \"%s\": {\"win_bytes\": %d, \"slab\": %d, \"ms\": %.4f}%s\n", kv.first.c_str(),
+                     kv.second.win_bytes, kv.second.slab, kv.second.ms, ++i < g_tune.size() ? "," : "");
+    }
+    std::fprintf(f, "  }\n}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
+
+FwdTune tune_lookup(const ssa_model *m, int64_t n_traj, int32_t G, int dev) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    auto it = g_tune.find(tune_key(m, n_traj, G, dev));
+    return it == g_tune.end() ? FwdTune() : it->second;
+}
+
 // Forward launch of one network.  D receives the [G][S][2] difference sums, by atomic
 // flushes of the windows into D directly or through wave-private slabs and a reduction
 // (see want_slabs).  Dhi ([G][S], high parts) must be zero on entry.
 ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int dev, hipStream_t st,
-                          const double *user_rates, StreamScratch &scr, unsigned long long *D, float *kernel_ms) {
+                          const double *user_rates, StreamScratch &scr, unsigned long long *D, float *kernel_ms,
+                          const FwdTune &tune) {
     const int32_t G = wl.net0.G, S = m->S;
     if (m->order == SSA_SUM_BLOCK64) {
         HIP_TRY(launch_zero(D, (size_t)G * S * 2 * sizeof(unsigned long long), st));
@@ -592,7 +678,7 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
         return SSA_OK;
     }
     FwdKernel k;
-    wl.win_bins = window_bins(S, G, !jit_eligible(m));
+    wl.win_bins = window_bins(S, G, !jit_eligible(m), tune.win_bytes);
     wl.win_words = wl.win_bins * S * 2;
     // the specialised kernels run generations with one window per wave, the table-driven
     // kernel cohorts with kCohorts windows
@@ -625,7 +711,7 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
     int64_t blocks = 0;
     HIP_TRY(fwd_blocks(k, true, dev, n_items, blocks));
     const size_t slab_bytes = (size_t)blocks * (kBlock / kWave) * cell_words * sizeof(unsigned long long);
-    const bool slab = want_slabs(slab_bytes);
+    const bool slab = want_slabs(slab_bytes, tune.slab);
     if (slab) {
         void *sl = nullptr;
         HIP_TRY(scr.alloc(&sl, slab_bytes));
@@ -743,9 +829,14 @@ void ssa_model_destroy(ssa_model *m) {
     delete m;
 }
 
-ssa_status ssa_run_device(const ssa_model *m, const double *rates, int64_t n_traj, double t_end, const double *grid,
-                          int32_t G, uint64_t seed, uint64_t max_events, double *mean, double *var,
-                          const ssa_hist_spec *hist, uint32_t *d_hist, void *stream, ssa_stats *stats) {
+namespace {
+
+// The forward pass with a given launch configuration (tune == nullptr: the cached tuned
+// one, else the defaults).
+ssa_status run_device_impl(const ssa_model *m, const double *rates, int64_t n_traj, double t_end, const double *grid,
+                           int32_t G, uint64_t seed, uint64_t max_events, double *mean, double *var,
+                           const ssa_hist_spec *hist, uint32_t *d_hist, void *stream, ssa_stats *stats,
+                           const FwdTune *tune) {
     if (!m) return fail(SSA_E_INVALID, "model is NULL");
     if (n_traj <= 0) return fail(SSA_E_INVALID, "n_traj must be > 0");
     if (G <= 0 || !grid || !mean || !var) return fail(SSA_E_INVALID, "grid / mean / var missing");
@@ -794,7 +885,8 @@ ssa_status ssa_run_device(const ssa_model *m, const double *rates, int64_t n_tra
     wl.stats = (unsigned long long *)((char *)ctl + 32);
 
     float kms = 0.f;
-    ssa_status s = launch_forward(m, wl, n_items, dev, st, rates, scr, n.D, stats ? &kms : nullptr);
+    const FwdTune cfg = tune ? *tune : tune_lookup(m, n_traj, G, dev);
+    ssa_status s = launch_forward(m, wl, n_items, dev, st, rates, scr, n.D, stats ? &kms : nullptr, cfg);
     if (s) return s;
     HIP_TRY(launch_finalize(n.D, n.Dhi, G, m->S, m->d_x0, n_traj, mean, var, st));
     if (hist) {
@@ -808,6 +900,74 @@ ssa_status ssa_run_device(const ssa_model *m, const double *rates, int64_t n_tra
         s = collect_stats(wl.stats, st, nullptr, nullptr, stats);
         stats->kernel_ms = kms;
         return s;
+    }
+    return SSA_OK;
+}
+
+}  // namespace
+
+ssa_status ssa_run_device(const ssa_model *m, const double *rates, int64_t n_traj, double t_end, const double *grid,
+                          int32_t G, uint64_t seed, uint64_t max_events, double *mean, double *var,
+                          const ssa_hist_spec *hist, uint32_t *d_hist, void *stream, ssa_stats *stats) {
+    return run_device_impl(m, rates, n_traj, t_end, grid, G, seed, max_events, mean, var, hist, d_hist, stream, stats,
+                           nullptr);
+}
+
+ssa_status ssa_autotune_forward(const ssa_model *m, const double *rates, int64_t n_traj, double t_end,
+                                const double *grid, int32_t G, uint64_t seed, void *stream, ssa_tune_result *result) {
+    if (!m || !grid || G <= 0 || n_traj <= 0) return fail(SSA_E_INVALID, "bad argument");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipStream_t st = (hipStream_t)stream;
+    const size_t cells = (size_t)G * m->S;
+    double *mean = nullptr, *var = nullptr;
+    HIP_TRY(hipMallocAsync((void **)&mean, sizeof(double) * cells, st));
+    HIP_TRY(hipMallocAsync((void **)&var, sizeof(double) * cells, st));
+    // candidates: the default first, then the window sizes, with and without slabs
+    std::vector<FwdTune> cand(1);
+    if (m->order != SSA_SUM_BLOCK64) {
+        for (int32_t wb : {2048, 4096, 8192, 16384}) {
+            FwdTune t;
+            t.win_bytes = wb;
+            t.slab = 0;
+            cand.push_back(t);
+            t.slab = 1;
+            cand.push_back(t);
+        }
+    }
+    FwdTune best;
+    float best_ms = 0.f, default_ms = 0.f;
+    ssa_status status = SSA_OK;
+    for (size_t c = 0; c < cand.size() && status == SSA_OK; ++c) {
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && status == SSA_OK; ++rep) {     // the first run warms up
+            ssa_stats stt;
+            status = run_device_impl(m, rates, n_traj, t_end, grid, G, seed, 0, mean, var, nullptr, nullptr, stream,
+                                     &stt, &cand[c]);
+            ms = rep ? std::min(ms, stt.kernel_ms) : stt.kernel_ms;
+        }
+        if (status) break;
+        if (c == 0) default_ms = ms;
+        if (c == 0 || ms < best_ms) {
+            best_ms = ms;
+            best = cand[c];
+        }
+    }
+    (void)hipFreeAsync(mean, st);
+    (void)hipFreeAsync(var, st);
+    if (status) return status;
+    best.ms = best_ms;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        g_tune[tune_key(m, n_traj, G, dev)] = best;
+        tune_save_locked();
+    }
+    if (result) {
+        result->win_bytes = best.win_bytes;
+        result->slab = best.slab;
+        result->best_ms = best_ms;
+        result->default_ms = default_ms;
     }
     return SSA_OK;
 }

@@ -19,7 +19,7 @@ _NAMES = {1: "SSA_E_INVALID", 2: "SSA_E_NOMEM", 3: "SSA_E_DEVICE", 4: "SSA_E_OVE
           5: "SSA_E_EVENT_LIMIT", 6: "SSA_E_UNSUPPORTED"}
 
 EXPORTS = ["ssa_model_create", "ssa_model_destroy", "ssa_run", "ssa_run_device", "ssa_backward_device",
-           "ssa_run_jacobian_device", "ssa_jacobian_vjp",
+           "ssa_run_jacobian_device", "ssa_jacobian_vjp", "ssa_autotune_forward",
            "ssa_record", "ssa_batch_create", "ssa_batch_run", "ssa_batch_destroy", "ssa_last_error"]
 
 
@@ -62,6 +62,7 @@ def load(path=None):
     L.ssa_run.argtypes = [vp, i64, dbl, vp, i32, u64, vp, vp, vp]
     L.ssa_run_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
     L.ssa_backward_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
+    L.ssa_autotune_forward.argtypes = [vp, vp, i64, dbl, vp, i32, u64, vp, vp]
     L.ssa_run_jacobian_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
     L.ssa_jacobian_vjp.argtypes = [vp, vp, i32, i32, i32, vp, vp]
     L.ssa_record.argtypes = [vp, vp, i64, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
@@ -179,6 +180,20 @@ def backward_device(model, n_traj, t_end, grid, seed, w, mhat, rates=None, max_e
                                       _tp(mhat.contiguous()), _tp(grad), _stream(stream),
                                       ctypes.byref(st) if st is not None else None))
     return grad, (st.as_dict() if st is not None else None)
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("win_bytes", ctypes.c_int32), ("slab", ctypes.c_int32), ("best_ms", ctypes.c_float),
+                ("default_ms", ctypes.c_float)]
+
+
+def autotune_forward(model, n_traj, t_end, grid, seed, rates=None, stream=None):
+    """Time the forward launch configurations on this problem and keep the fastest
+    (ssa_autotune_forward); returns the chosen configuration and the two kernel times."""
+    r = TuneResult()
+    _check(load().ssa_autotune_forward(model.handle, _tp(rates), int(n_traj), float(t_end), _tp(grid), grid.shape[0],
+                                       int(seed), _stream(stream), ctypes.byref(r)))
+    return dict(win_bytes=r.win_bytes, slab=r.slab, best_ms=r.best_ms, default_ms=r.default_ms)
 
 
 def run_jacobian_device(model, n_traj, t_end, grid, seed, rates=None, max_events=0, stream=None,
