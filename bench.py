@@ -38,7 +38,7 @@ PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9     # full-rate VALU lane operations per se
 HBM_PEAK = 8.0e12
 
 # Algorithmic VALU work per SSA event, in full-rate lane operations (a 32x32->64-bit
-# multiply and a reciprocal count 4, as quarter-rate instructions).  See the design doc.
+# multiply and a reciprocal count 4, as quarter-rate instructions).
 W_PHILOX = 10 * (2 * 4 + 2)        # per round: two 32x32->64 products, two 3-way xors
 W_UNIFORMS = 2 * 7                 # two 53-bit conversions
 W_NEGLOG = 37                      # exponent split, (m-1)/(m+1), 10-term Horner, recombination
@@ -173,8 +173,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
-              "(the sharding design is in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path; trajectory "
+              "ranges would shard across GPUs with one all-reduce of the exact integer sums",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -60,7 +60,7 @@ typedef enum {
     SSA_E_DEVICE = 3,       /* a HIP call failed (message in ssa_last_error) */
     SSA_E_OVERFLOW = 4,     /* a species count left the int32 range in some trajectory */
     SSA_E_EVENT_LIMIT = 5,  /* a trajectory reached max_events before t_end */
-    SSA_E_UNSUPPORTED = 6   /* valid request outside what this build implements */
+    SSA_E_UNSUPPORTED = 6   /* valid request outside what the library implements */
 } ssa_status;
 
 typedef struct ssa_model ssa_model;
