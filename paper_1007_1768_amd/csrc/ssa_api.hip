@@ -1111,17 +1111,16 @@ ssa_status ssa_backward_device(const ssa_model *m, const double *rates, int64_t 
     void *gt = nullptr, *gt2 = nullptr, *ctl = nullptr, *bp = nullptr;
     const size_t rows_bytes = sizeof(double) * (size_t)n_traj * m->M;
     const int32_t ncol = 2 * m->S + 2;
-    HIP_TRY(scr.alloc(&bp, sizeof(double) * 2 * ncol * ((size_t)G + 1)));
+    HIP_TRY(scr.alloc(&bp, (size_t)12 * ncol * ((size_t)G + 1)));
     HIP_TRY(scr.alloc(&gt, rows_bytes));
     HIP_TRY(scr.alloc(&gt2, rows_bytes / 2 + sizeof(double) * m->M));
     HIP_TRY(scr.alloc(&ctl, 64 + sizeof(GridInfo)));
     HIP_TRY(launch_zero(ctl, 64, st));
     n.ginfo = (const GridInfo *)((char *)ctl + 64);
     HIP_TRY(launch_grid_info(grid, G, t_end, (GridInfo *)n.ginfo, st));
-    hipLaunchKernelGGL(bwd_prefix_kernel, dim3((unsigned)ncol), dim3(256), 0, st, w, mhat, grid, G, m->S,
-                       (double *)bp);
+    hipLaunchKernelGGL(bwd_prefix_kernel, dim3((unsigned)ncol), dim3(256), 0, st, w, mhat, grid, G, m->S, bp);
     HIP_TRY(hipGetLastError());
-    n.bp = (const double *)bp;
+    n.bp = bp;
     n.gtraj = (double *)gt;
     WorkList wl;
     std::memset(&wl, 0, sizeof wl);

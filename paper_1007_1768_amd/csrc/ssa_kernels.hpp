@@ -143,7 +143,7 @@ __global__ void __launch_bounds__(kBlock) fwd_kernel(WorkList wl) {
 //   W_s = w_gs,  WT_s = w_gs t_g,  C = c_g,  CT = c_g t_g.
 // The prefixes are kept as unevaluated double-double sums (hi + lo), so a difference of
 // two rows loses nothing to cancellation.  Row g (0 <= g <= G) holds the hi parts of the
-// 2S + 2 columns followed by their lo parts.
+// 2S + 2 columns (binary64) followed by their lo parts (binary32), see PrefixRow.
 __device__ __forceinline__ double bwd_column(const double *w, const double *mhat, const double *grid, int32_t S,
                                              int32_t g, int32_t k) {
     if (k < 2 * S) {
@@ -161,8 +161,10 @@ __device__ __forceinline__ double bwd_column(const double *w, const double *mhat
 __global__ void __launch_bounds__(256) bwd_prefix_kernel(const double *__restrict__ w,
                                                          const double *__restrict__ mhat,
                                                          const double *__restrict__ grid, int32_t G, int32_t S,
-                                                         double *__restrict__ P) {
-    const int32_t k = blockIdx.x, ncol = 2 * S + 2, row = 2 * ncol;
+                                                         void *__restrict__ P) {
+    const int32_t k = blockIdx.x, ncol = 2 * S + 2;
+    auto hi = [&](int32_t g) { return (double *)((char *)P + (size_t)g * 12 * ncol); };
+    auto lo = [&](int32_t g) { return (float *)((char *)P + (size_t)g * 12 * ncol + 8 * (size_t)ncol); };
     const int32_t nt = blockDim.x, per = (G + nt - 1) / nt;
     const int32_t g0 = min(G, (int32_t)threadIdx.x * per), g1 = min(G, g0 + per);
     double h = 0.0, l = 0.0;
@@ -190,13 +192,13 @@ __global__ void __launch_bounds__(256) bwd_prefix_kernel(const double *__restric
     h = threadIdx.x ? sh[0][threadIdx.x - 1] : 0.0;
     l = threadIdx.x ? sh[1][threadIdx.x - 1] : 0.0;
     if (threadIdx.x == 0) {
-        P[k] = 0.0;
-        P[ncol + k] = 0.0;
+        hi(0)[k] = 0.0;
+        lo(0)[k] = 0.0f;
     }
     for (int32_t g = g0; g < g1; ++g) {
         dd_add(h, l, bwd_column(w, mhat, grid, S, g, k), 0.0);
-        P[(size_t)(g + 1) * row + k] = h;
-        P[(size_t)(g + 1) * row + ncol + k] = l;
+        hi(g + 1)[k] = h;
+        lo(g + 1)[k] = (float)l;
     }
 }
 

@@ -100,8 +100,8 @@ struct NetDev {
     double *rec_tlast;
     int64_t *rec_nf;
     double *rec_aint;
-    // backward: prefix rows [G+1][2 (2S+2)] (see bwd_prefix_kernel), per-trajectory rows [n_traj][M]
-    const double *bp;
+    // backward: prefix rows [G+1] (see PrefixRow), per-trajectory rows [n_traj][M]
+    const void *bp;
     double *gtraj;
 };
 
@@ -148,22 +148,40 @@ __device__ __forceinline__ double dd_diff(double ah, double al, double bh, doubl
     return s + (e + (bl - al));
 }
 
+// Backward prefix rows (built by bwd_prefix_kernel): row g holds the ncol = 2S + 2 binary64
+// hi parts followed by the ncol lo parts stored as binary32 (a double-double's lo part is
+// below half an ulp of its hi part, so binary32 keeps the pair to 2^-77 relative),
+// 12 ncol bytes per row.
+struct PrefixRow {
+    const double *hi;
+    const float *lo;
+    __device__ __forceinline__ PrefixRow(const void *table, int32_t ncol, int32_t g) {
+        const char *r = (const char *)table + (size_t)g * 12 * ncol;
+        hi = (const double *)r;
+        lo = (const float *)(r + 8 * (size_t)ncol);
+    }
+    // (column c of row b) - (column c of this row)
+    __device__ __forceinline__ double diff_to(const PrefixRow &b, int32_t c) const {
+        return dd_diff(hi[c], (double)lo[c], b.hi[c], (double)b.lo[c]);
+    }
+};
+
 // Backward sums over the crossings g in [ga, gb) of one inter-event interval starting at t
 // (state x): alpha = sum_g phi_g, beta = sum_g phi_g (t_g - t), from two prefix rows.
 template <class Policy>
-__device__ __forceinline__ void interval_sums(const Policy &p, const double *P, int32_t S, int32_t ga, int32_t gb,
+__device__ __forceinline__ void interval_sums(const Policy &p, const void *P, int32_t S, int32_t ga, int32_t gb,
                                               double t, double &alpha, double &beta) {
-    const int32_t ncol = 2 * S + 2, row = 2 * ncol;
-    const double *ra = P + (size_t)ga * row, *rb = P + (size_t)gb * row;
+    const int32_t ncol = 2 * S + 2;
+    const PrefixRow ra(P, ncol, ga), rb(P, ncol, gb);
     double sw = 0.0, swt = 0.0;
     p.for_each_species([&](int32_t s, int32_t xs) {
-        const double dW = dd_diff(ra[s], ra[ncol + s], rb[s], rb[ncol + s]);
-        const double dWT = dd_diff(ra[S + s], ra[ncol + S + s], rb[S + s], rb[ncol + S + s]);
+        const double dW = ra.diff_to(rb, s);
+        const double dWT = ra.diff_to(rb, S + s);
         sw = sw + (double)xs * dW;
         swt = swt + (double)xs * (dWT - t * dW);
     });
-    const double dC = dd_diff(ra[2 * S], ra[ncol + 2 * S], rb[2 * S], rb[ncol + 2 * S]);
-    const double dCT = dd_diff(ra[2 * S + 1], ra[ncol + 2 * S + 1], rb[2 * S + 1], rb[ncol + 2 * S + 1]);
+    const double dC = ra.diff_to(rb, 2 * S);
+    const double dCT = ra.diff_to(rb, 2 * S + 1);
     alpha = sw - dC;
     beta = swt - (dCT - t * dC);
 }

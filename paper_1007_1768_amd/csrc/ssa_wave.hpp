@@ -147,21 +147,20 @@ __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
                 if (g < G && tg_next < t_next) {
                     double tb;
                     const int32_t gb = gv.next_bin(g, t_next, tb);
-                    const int32_t ncol = 2 * S + 2, rowl = 2 * ncol;
-                    const double *ra = n.bp + (size_t)g * rowl, *rb = n.bp + (size_t)gb * rowl;
+                    const int32_t ncol = 2 * S + 2;
+                    const PrefixRow ra(n.bp, ncol, g), rb(n.bp, ncol, gb);
                     double sw = 0.0, swt = 0.0;
                     for (int32_t s = lane; s < S; s += kWave) {
                         const double xs = (double)xl[s + 1];
-                        const double dW = dd_diff(ra[s], ra[ncol + s], rb[s], rb[ncol + s]);
-                        const double dWT = dd_diff(ra[S + s], ra[ncol + S + s], rb[S + s], rb[ncol + S + s]);
+                        const double dW = ra.diff_to(rb, s);
+                        const double dWT = ra.diff_to(rb, S + s);
                         sw = sw + xs * dW;
                         swt = swt + xs * (dWT - t * dW);
                     }
                     sw = wave_sum_f64(sw);
                     swt = wave_sum_f64(swt);
-                    const double dC = dd_diff(ra[2 * S], ra[ncol + 2 * S], rb[2 * S], rb[ncol + 2 * S]);
-                    const double dCT =
-                        dd_diff(ra[2 * S + 1], ra[ncol + 2 * S + 1], rb[2 * S + 1], rb[ncol + 2 * S + 1]);
+                    const double dC = ra.diff_to(rb, 2 * S);
+                    const double dCT = ra.diff_to(rb, 2 * S + 1);
                     const double alpha = sw - dC;
                     const double beta = swt - (dCT - t * dC);
 #pragma unroll
