@@ -177,6 +177,16 @@ ssa_status ssa_run_jacobian_device(const ssa_model *model, const double *rates, 
                                    const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events,
                                    double *mean, double *var, double *jac, void *stream, ssa_stats *stats);
 
+/* Forward pass returning the species covariance matrix at every grid point (a further
+ * recombining function over the time-aligned states): cov [G*S*S] device,
+ *   cov[g][s][r] = (N sum X_s X_r - sum X_s sum X_r) / (N (N - 1))   (0 when N == 1)
+ * from exact integer sums, rounded once, so cov[g][s][s] is the variance of ssa_run_device;
+ * mean [G*S] device.  Arguments as ssa_run_device (no histogram).  Needs a SSA_SUM_SEQ
+ * model with M <= 32 and S <= 64 (SSA_E_UNSUPPORTED otherwise). */
+ssa_status ssa_run_cov_device(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
+                              const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events, double *mean,
+                              double *cov, void *stream, ssa_stats *stats);
+
 /* grad[j] = sum_{g,s} w[g][s] jac[g][s][j] on the device (fixed summation order): the
  * vector-Jacobian product that turns the forward Jacobian into d loss / d ln c for
  * w = d loss / d mean.  jac [G*S*M], w [G*S], grad [M], all device; asynchronous on stream. */

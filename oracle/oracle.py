@@ -53,6 +53,9 @@ def lib():
         L.orc_jacobian.argtypes = [ctypes.POINTER(_Net), ctypes.c_int64, ctypes.c_double, vp, ctypes.c_int32,
                                    ctypes.c_uint64, ctypes.c_uint64, vp, vp, vp, ctypes.c_int]
         L.orc_jacobian.restype = ctypes.c_int
+        L.orc_covariance.argtypes = [ctypes.POINTER(_Net), ctypes.c_int64, ctypes.c_double, vp, ctypes.c_int32,
+                                     ctypes.c_uint64, ctypes.c_uint64, vp, vp, ctypes.c_int]
+        L.orc_covariance.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -181,3 +184,15 @@ def jacobian(model, N, t_end, grid, seed, mhat, max_events=2**62, rates=None, th
     st = lib().orc_jacobian(ctypes.byref(net.c), int(N), float(t_end), _ptr(grid), G, int(seed), int(max_events),
                             _ptr(mh), _ptr(jac), _ptr(l1), int(threads or default_threads()))
     return st, jac, l1
+
+
+def covariance(model, N, t_end, grid, seed, max_events=2**62, rates=None, threads=None):
+    """Grid means (G, S) and species covariance matrices (G, S, S) from exact sums."""
+    net = as_net(model, rates)
+    grid = np.ascontiguousarray(grid, dtype=np.float64)
+    G = grid.shape[0]
+    mean = np.zeros((G, net.S))
+    cov = np.zeros((G, net.S, net.S))
+    st = lib().orc_covariance(ctypes.byref(net.c), int(N), float(t_end), _ptr(grid), G, int(seed), int(max_events),
+                              _ptr(mean), _ptr(cov), int(threads or default_threads()))
+    return st, mean, cov

@@ -707,3 +707,90 @@ int orc_jacobian(const orc_net *net, int64_t N, double t_end, const double *grid
     free(info); free(tot); free(totl1);
     return status;
 }
+
+/* ------------------------------------------------------------------------------------
+ * Covariance between species at every grid point (a further associative, commutative
+ * recombining function over the time-aligned states): exact 128-bit sums of X_s and
+ * X_s X_r over the N trajectories, then
+ *   cov_{g,s,r} = fl(N sum X_s X_r - sum X_s sum X_r) / (N (N - 1))   (0 when N = 1),
+ * the variance formula with two species; cov_{g,s,s} is the variance.  Layout [G][S][S].
+ * ---------------------------------------------------------------------------------- */
+typedef struct {
+    int S;
+    i128 *sx, *sxx;   /* [G*S], [G*S*S] */
+} cov_ctx;
+
+static void cov_visit(void *c, int g, const traj_state *st, double tg)
+{
+    (void)tg;
+    cov_ctx *cc = (cov_ctx *)c;
+    const int S = cc->S;
+    for (int s = 0; s < S; ++s) {
+        cc->sx[(size_t)g * S + s] += (i128)st->x[s];
+        for (int r = 0; r < S; ++r)
+            cc->sxx[((size_t)g * S + s) * S + r] += (i128)st->x[s] * (i128)st->x[r];
+    }
+}
+
+int orc_covariance(const orc_net *net, int64_t N, double t_end, const double *grid, int32_t G,
+                   uint64_t seed, uint64_t max_events, double *mean, double *cov, int nthreads)
+{
+    int st0 = check_net(net);
+    if (st0) return st0;
+    if (check_grid(grid, G, t_end)) return ORC_INVALID;
+    if (N <= 0 || N > ((int64_t)1 << 30) || !mean || !cov) return ORC_INVALID;
+    const int S = net->S, M = net->M;
+    const size_t GS = (size_t)G * S, GSS = GS * S;
+    rxn_info *info = (rxn_info *)malloc(sizeof(rxn_info) * M);
+    i128 *sx = (i128 *)calloc(GS, sizeof(i128));
+    i128 *sxx = (i128 *)calloc(GSS, sizeof(i128));
+    if (!info || !sx || !sxx) { free(info); free(sx); free(sxx); return ORC_NOMEM; }
+    build_info(net, info);
+    int status = ORC_OK;
+    if (nthreads <= 0) nthreads = 1;
+#pragma omp parallel num_threads(nthreads)
+    {
+        cov_ctx cc;
+        cc.S = S;
+        cc.sx = (i128 *)calloc(GS, sizeof(i128));
+        cc.sxx = (i128 *)calloc(GSS, sizeof(i128));
+        traj_state st;
+        int ok = cc.sx && cc.sxx && alloc_state(net, &st, info) == ORC_OK;
+        int my_status = ok ? ORC_OK : ORC_NOMEM;
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < N; ++i) {
+            if (my_status != ORC_OK) continue;
+            int r = run_trajectory(net, info, seed, (uint64_t)i, t_end, grid, G, max_events, &st, NULL, NULL,
+                                   cov_visit, &cc);
+            if (r != ORC_OK) my_status = r;
+        }
+#pragma omp critical
+        {
+            if (my_status != ORC_OK && status == ORC_OK) status = my_status;
+            if (ok) {
+                for (size_t q = 0; q < GS; ++q) sx[q] += cc.sx[q];
+                for (size_t q = 0; q < GSS; ++q) sxx[q] += cc.sxx[q];
+            }
+        }
+        if (ok) free_state(&st);
+        free(cc.sx); free(cc.sxx);
+    }
+    if (status == ORC_OK) {
+        for (int g = 0; g < G; ++g)
+            for (int s = 0; s < S; ++s) {
+                const size_t q = (size_t)g * S + s;
+                mean[q] = (double)sx[q] / (double)N;
+                for (int r = 0; r < S; ++r) {
+                    const size_t qq = q * S + r;
+                    if (N == 1) {
+                        cov[qq] = 0.0;
+                    } else {
+                        i128 num = (i128)N * sxx[qq] - sx[q] * sx[(size_t)g * S + r];
+                        cov[qq] = (double)num / ((double)N * (double)(N - 1));
+                    }
+                }
+            }
+    }
+    free(info); free(sx); free(sxx);
+    return status;
+}

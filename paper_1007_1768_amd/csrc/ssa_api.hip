@@ -117,6 +117,7 @@ bool prefer_generic() {
 struct JitKernels {
     hipModule_t module = nullptr;
     hipFunction_t fwd = nullptr, fwd_atomic = nullptr, fwd_hist = nullptr, fwd_slab_hist = nullptr, fwd_jac = nullptr,
+                  fwd_cov = nullptr,
                   rec = nullptr, bwd = nullptr;
 };
 
@@ -280,6 +281,7 @@ ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out
     HIP_TRY(hipModuleGetFunction(&k->fwd_hist, k->module, "ssa_jit_fwd_hist"));
     HIP_TRY(hipModuleGetFunction(&k->fwd_slab_hist, k->module, "ssa_jit_fwd_slab_hist"));
     HIP_TRY(hipModuleGetFunction(&k->fwd_jac, k->module, "ssa_jit_fwd_jac"));
+    HIP_TRY(hipModuleGetFunction(&k->fwd_cov, k->module, "ssa_jit_fwd_cov"));
     HIP_TRY(hipModuleGetFunction(&k->rec, k->module, "ssa_jit_rec"));
     HIP_TRY(hipModuleGetFunction(&k->bwd, k->module, "ssa_jit_bwd"));
     std::lock_guard<std::mutex> lk(g_jit_mu);
@@ -1048,6 +1050,77 @@ ssa_status ssa_run_jacobian_device(const ssa_model *m, const double *rates, int6
                            (const double *)slabs, n_items, G, m->S, m->M, n_traj, (const double *)mean, jac);
         HIP_TRY(hipGetLastError());
     }
+    if (stats) return collect_stats(wl.stats, st, ev.a, ev.b, stats);
+    return SSA_OK;
+}
+
+ssa_status ssa_run_cov_device(const ssa_model *m, const double *rates, int64_t n_traj, double t_end,
+                              const double *grid, int32_t G, uint64_t seed, uint64_t max_events, double *mean,
+                              double *cov, void *stream, ssa_stats *stats) {
+    if (!m) return fail(SSA_E_INVALID, "model is NULL");
+    if (n_traj <= 0) return fail(SSA_E_INVALID, "n_traj must be > 0");
+    if (G <= 0 || !grid || !mean || !cov) return fail(SSA_E_INVALID, "grid / mean / cov missing");
+    if (!(t_end >= 0.0) || !std::isfinite(t_end)) return fail(SSA_E_INVALID, "t_end must be finite and >= 0");
+    if (n_traj > ((int64_t)1 << 31) * kChunk) return fail(SSA_E_INVALID, "n_traj too large");
+    if (m->order != SSA_SUM_SEQ || m->M > kJitMaxReactions || m->S > kJitMaxSpecies)
+        return fail(SSA_E_UNSUPPORTED, "the covariance pass needs a sequential-order network with at most %d "
+                    "reactions and %d species", kJitMaxReactions, kJitMaxSpecies);
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    keep_pool(dev);
+    StreamScratch scr(st);
+    std::shared_ptr<JitKernels> jk;
+    ssa_status s = get_jit(m, dev, jk);
+    if (s) return s;
+    const int32_t S = m->S, npairs = S * (S - 1) / 2;
+    const size_t row = (size_t)2 * S + npairs, hrow = (size_t)S + npairs;
+    NetDev n = base_net(m, rates, n_traj, t_end, grid, G, seed, max_events);
+    void *D = nullptr, *Dhi = nullptr, *ctl = nullptr, *sx = nullptr, *sxx = nullptr;
+    HIP_TRY(scr.alloc(&D, sizeof(unsigned long long) * row * G));
+    HIP_TRY(scr.alloc(&Dhi, sizeof(unsigned long long) * hrow * G));
+    HIP_TRY(scr.alloc(&ctl, 64 + sizeof(GridInfo)));
+    HIP_TRY(scr.alloc(&sx, sizeof(int64_t) * (size_t)G * S));
+    HIP_TRY(scr.alloc(&sxx, sizeof(i128s) * hrow * G));
+    HIP_TRY(launch_zero(D, sizeof(unsigned long long) * row * G, st));
+    HIP_TRY(launch_zero(Dhi, sizeof(unsigned long long) * hrow * G, st));
+    HIP_TRY(launch_zero(ctl, 64, st));
+    n.ginfo = (const GridInfo *)((char *)ctl + 64);
+    HIP_TRY(launch_grid_info(grid, G, t_end, (GridInfo *)n.ginfo, st));
+    n.D = (unsigned long long *)D;
+    n.Dhi = (unsigned long long *)Dhi;
+    WorkList wl;
+    std::memset(&wl, 0, sizeof wl);
+    wl.net0 = n;
+    wl.range_begin = 0;
+    wl.range_end = n_traj;
+    const int64_t n_items = (n_traj + kChunk - 1) / kChunk;
+    wl.n_items = (int32_t)n_items;
+    wl.counter = (unsigned int *)ctl;
+    wl.stats = (unsigned long long *)((char *)ctl + 32);
+    int32_t W = 1;
+    while (W < 1024 && (size_t)(2 * W) * row * 8 <= window_budget(false) && W < G) W *= 2;
+    wl.win_bins = W;
+    wl.win_words = (int32_t)(W * row);
+    const size_t lds = (size_t)(kBlock / kWave) * wl.win_words * sizeof(long long);
+    int per_cu = 0;
+    HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, jk->fwd_cov, kBlock, lds));
+    const int64_t blocks = grid_blocks(per_cu, dev, n_items);
+    EventPair ev;
+    if (stats && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
+    {
+        void *args[] = {&wl};
+        HIP_TRY(hipModuleLaunchKernel(jk->fwd_cov, (unsigned)blocks, 1, 1, kBlock, 1, 1, (unsigned)lds, st, args,
+                                      nullptr));
+    }
+    if (stats && ev.b) HIP_TRY(hipEventRecord(ev.b, st));
+    hipLaunchKernelGGL(cov_prefix_kernel, dim3((unsigned)hrow), dim3(1024), 0, st, (const unsigned long long *)D,
+                       (const unsigned long long *)Dhi, G, S, m->d_x0, n_traj, (int64_t *)sx, (i128s *)sxx);
+    HIP_TRY(hipGetLastError());
+    const int64_t cells = (int64_t)G * S * S;
+    hipLaunchKernelGGL(cov_final_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st,
+                       (const int64_t *)sx, (const i128s *)sxx, G, S, n_traj, mean, cov);
+    HIP_TRY(hipGetLastError());
     if (stats) return collect_stats(wl.stats, st, ev.a, ev.b, stats);
     return SSA_OK;
 }

@@ -98,6 +98,14 @@ extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd_slab_hist(
                                                          ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
 }
 
+// Forward pass with the species cross products (covariance matrices per grid point).
+extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd_cov(ssa::WorkList wl) {
+    extern __shared__ long long ssa_win[];
+    ssa::RegPolicy p;
+    ssa::sim_fwd_gen<ssa_gen::Net::M, false, false, false, ssa::RegPolicy, true>(
+        wl, p, ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
+}
+
 // Forward pass with the likelihood-ratio Jacobian: per wave, the moment window
 // (win_bins x S x 2 int64) followed by the Jacobian window (win_bins x (S+1) x M doubles);
 // wl.win_words is their total in 8-byte words.

@@ -378,6 +378,93 @@ __global__ void __launch_bounds__(1024) moment_final_kernel(const unsigned long 
     moment_final_body(D, Dhi, G, S, blockIdx.x, x0, n_traj, mean, var, sums);
 }
 
+// Covariance finalize, step 1: one block per column c of the cross-product rows
+// (c < S: species c, its sum of nu, low and high parts of (2x+nu)nu; c >= S: pair c - S,
+// low and high parts of the x_s x_r differences); exact inclusive prefixes over the grid
+// plus the initial-state terms give sx[g][s] (int64) and sxx[g][c] (128-bit).
+__global__ void __launch_bounds__(1024) cov_prefix_kernel(const unsigned long long *__restrict__ D,
+                                                          const unsigned long long *__restrict__ Dhi, int32_t G,
+                                                          int32_t S, const int32_t *__restrict__ x0, int64_t n_traj,
+                                                          int64_t *__restrict__ sx, i128s *__restrict__ sxx) {
+    const int32_t c = blockIdx.x, npairs = S * (S - 1) / 2, row = 2 * S + npairs, hrow = S + npairs;
+    int32_t ps = c, pr = c;             // the pair's species (for the initial-state term)
+    if (c >= S) {
+        int32_t q = c - S, a = 0;
+        while (q >= S - a - 1) { q -= S - a - 1; ++a; }
+        ps = a;
+        pr = a + 1 + q;
+    }
+    const int32_t lo_col = c < S ? 2 * c + 1 : 2 * S + (c - S);
+    const int32_t nt = blockDim.x, per = (G + nt - 1) / nt;
+    const int32_t g0 = min(G, (int32_t)threadIdx.x * per), g1 = min(G, g0 + per);
+    int64_t s1 = 0, s2 = 0, s3 = 0;
+    for (int32_t g = g0; g < g1; ++g) {
+        if (c < S) s1 += (int64_t)D[(size_t)g * row + 2 * c];
+        s2 += (int64_t)D[(size_t)g * row + lo_col];
+        s3 += (int64_t)Dhi[(size_t)g * hrow + c];
+    }
+    __shared__ int64_t sh[3][1024];
+    sh[0][threadIdx.x] = s1;
+    sh[1][threadIdx.x] = s2;
+    sh[2][threadIdx.x] = s3;
+    __syncthreads();
+    for (int off = 1; off < nt; off <<= 1) {
+        int64_t v1 = 0, v2 = 0, v3 = 0;
+        if ((int)threadIdx.x >= off) {
+            v1 = sh[0][threadIdx.x - off];
+            v2 = sh[1][threadIdx.x - off];
+            v3 = sh[2][threadIdx.x - off];
+        }
+        __syncthreads();
+        sh[0][threadIdx.x] += v1;
+        sh[1][threadIdx.x] += v2;
+        sh[2][threadIdx.x] += v3;
+        __syncthreads();
+    }
+    int64_t c1 = sh[0][threadIdx.x] - s1, c2 = sh[1][threadIdx.x] - s2, c3 = sh[2][threadIdx.x] - s3;
+    const int64_t xs = x0[ps], xr = x0[pr];
+    i128s init = i128_from(xs * xr);                     // |x0| < 2^31: the product fits int64
+    init = i128_mul_u64(init, (uint64_t)n_traj);
+    for (int32_t g = g0; g < g1; ++g) {
+        if (c < S) c1 += (int64_t)D[(size_t)g * row + 2 * c];
+        c2 += (int64_t)D[(size_t)g * row + lo_col];
+        c3 += (int64_t)Dhi[(size_t)g * hrow + c];
+        if (c < S) sx[(size_t)g * S + c] = n_traj * xs + c1;
+        sxx[(size_t)g * hrow + c] = i128_add(i128_add(init, i128_from(c2)), i128_mul_u64(i128_from(c3), 1ull << 24));
+    }
+}
+
+// Covariance finalize, step 2: one thread per (g, s, r):
+//   cov = fl(N sxx - sx_s sx_r) / (N (N - 1)),  0 when N == 1; mean[g][s] from sx.
+__global__ void cov_final_kernel(const int64_t *__restrict__ sx, const i128s *__restrict__ sxx, int32_t G, int32_t S,
+                                 int64_t n_traj, double *__restrict__ mean, double *__restrict__ cov) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)G * S * S) return;
+    const int32_t r = (int32_t)(idx % S), s = (int32_t)((idx / S) % S);
+    const int64_t g = idx / ((int64_t)S * S);
+    const int32_t npairs = S * (S - 1) / 2, hrow = S + npairs;
+    int32_t c = s;
+    if (s != r) {
+        const int32_t lo = min(s, r), hi = max(s, r);
+        c = S + lo * (2 * S - lo - 1) / 2 + (hi - lo - 1);
+    }
+    const int64_t a = sx[g * S + s], b = sx[g * S + r];
+    if (s == r) mean[g * S + s] = (double)a / (double)n_traj;
+    if (n_traj == 1) {
+        cov[idx] = 0.0;
+        return;
+    }
+    // N sxx - a b in 128 bits: a b as a signed 128-bit product
+    const bool neg = (a < 0) != (b < 0);
+    const uint64_t ua = (uint64_t)(a < 0 ? -a : a), ub = (uint64_t)(b < 0 ? -b : b);
+    i128s ab;
+    ab.lo = ua * ub;
+    ab.hi = (int64_t)__umul64hi(ua, ub);
+    if (neg) ab = i128_neg(ab);
+    const i128s num = i128_add(i128_mul_u64(sxx[g * hrow + c], (uint64_t)n_traj), i128_neg(ab));
+    cov[idx] = i128_to_double(num) / ((double)n_traj * (double)(n_traj - 1));
+}
+
 // Finalize of every network of a batch in one launch: block i handles species
 // block_species[i] of network block_net[i].
 struct FinalNet {

@@ -515,8 +515,9 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 // then takes the next item.  The loop is tighter than the cohort form below, which pays
 // off for networks compiled into registers.  win: the wave's LDS window, wl.win_bins bins
 // x S species x (sum nu, sum (2x+nu)nu) as int64.  HIST: with the per-grid-point histogram
-// (a separate instantiation, so runs without one carry none of its code).
-template <int MM, bool BATCH, bool SLAB, bool HIST, class Policy>
+// (a separate instantiation, so runs without one carry none of its code).  COV: also the
+// difference sums of the cross products x_s x_r for the species covariance matrix.
+template <int MM, bool BATCH, bool SLAB, bool HIST, class Policy, bool COV = false>
 __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long long *win) {
     constexpr int MR = MM > 0 ? MM : 1;
     const uint32_t lane = __lane_id();
@@ -565,7 +566,12 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
         }
         const NetDev n0 = current_net<BATCH>(wl, cur);
         const int32_t S = n0.S, G = n0.G, M = n0.M;
-        const int32_t row_words = S * 2;
+        // window / D row per bin: (sum nu, sum of low parts of (2x+nu)nu) per species, then
+        // with COV the low parts of the cross products x_s x_r (s < r); Dhi rows hold the
+        // matching high parts
+        const int32_t npairs = COV ? S * (S - 1) / 2 : 0;
+        const int32_t row_words = S * 2 + npairs;
+        const int32_t hi_words = S + npairs;
         unsigned long long *slab =
             SLAB ? wl.slabs + (size_t)wave_slot * (size_t)G * row_words : n0.D;
         for (int32_t q = lane; q < W * row_words; q += kWave) win[q] = 0;
@@ -682,7 +688,24 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
                     atomicAdd((unsigned long long *)(w + 1),
                               (unsigned long long)(small ? d2 : (d2 & ((1ll << 24) - 1))));
                     if (__ballot(!small)) {             // rare: |(2x+nu)nu| >= 2^24
-                        if (!small) atomicAdd(n.Dhi + (size_t)bin * S + sp, (unsigned long long)(d2 >> 24));
+                        if (!small) atomicAdd(n.Dhi + (size_t)bin * hi_words + sp, (unsigned long long)(d2 >> 24));
+                    }
+                    if (COV) {
+                        // x_s x_r changes by dl x_r (the other species at their current
+                        // values: applied one species at a time, the changes telescope)
+                        p.for_each_species([&](int32_t r, int32_t xr) {
+                            if (r == sp) return;
+                            const int32_t lo_s = min(sp, r), hi_s = max(sp, r);
+                            const int32_t pair = lo_s * (2 * S - lo_s - 1) / 2 + (hi_s - lo_s - 1);
+                            const long long c = (long long)dl * (long long)xr;
+                            const bool csmall = c > -kSmallD2 && c < kSmallD2;
+                            atomicAdd((unsigned long long *)(wrow + 2 * S + pair),
+                                      (unsigned long long)(csmall ? c : (c & ((1ll << 24) - 1))));
+                            if (__ballot(!csmall)) {
+                                if (!csmall)
+                                    atomicAdd(n.Dhi + (size_t)bin * hi_words + S + pair, (unsigned long long)(c >> 24));
+                            }
+                        });
                     }
                     if (HIST && sp == n.h_species && dl != 0) {
                         const int32_t bo = xo < n.h_lo ? 0 : min((xo - n.h_lo) / n.h_width, n.nb_hist - 1);

@@ -19,7 +19,7 @@ _NAMES = {1: "SSA_E_INVALID", 2: "SSA_E_NOMEM", 3: "SSA_E_DEVICE", 4: "SSA_E_OVE
           5: "SSA_E_EVENT_LIMIT", 6: "SSA_E_UNSUPPORTED"}
 
 EXPORTS = ["ssa_model_create", "ssa_model_destroy", "ssa_run", "ssa_run_device", "ssa_backward_device",
-           "ssa_run_jacobian_device", "ssa_jacobian_vjp", "ssa_autotune_forward",
+           "ssa_run_jacobian_device", "ssa_jacobian_vjp", "ssa_autotune_forward", "ssa_run_cov_device",
            "ssa_record", "ssa_batch_create", "ssa_batch_run", "ssa_batch_destroy", "ssa_last_error"]
 
 
@@ -63,6 +63,7 @@ def load(path=None):
     L.ssa_run_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
     L.ssa_backward_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
     L.ssa_autotune_forward.argtypes = [vp, vp, i64, dbl, vp, i32, u64, vp, vp]
+    L.ssa_run_cov_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp]
     L.ssa_run_jacobian_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
     L.ssa_jacobian_vjp.argtypes = [vp, vp, i32, i32, i32, vp, vp]
     L.ssa_record.argtypes = [vp, vp, i64, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
@@ -213,6 +214,19 @@ def run_jacobian_device(model, n_traj, t_end, grid, seed, rates=None, max_events
                                           int(seed), int(max_events), _tp(mean), _tp(var), _tp(jac),
                                           _stream(stream), ctypes.byref(st) if st is not None else None))
     return mean, var, jac, (st.as_dict() if st is not None else None)
+
+
+def run_cov_device(model, n_traj, t_end, grid, seed, rates=None, max_events=0, stream=None, with_stats=False):
+    """Grid means (G, S) and species covariance matrices (G, S, S) (ssa_run_cov_device)."""
+    import torch
+    G = grid.shape[0]
+    mean = torch.empty((G, model.S), dtype=torch.float64, device=grid.device)
+    cov = torch.empty((G, model.S, model.S), dtype=torch.float64, device=grid.device)
+    st = Stats() if with_stats else None
+    _check(load().ssa_run_cov_device(model.handle, _tp(rates), int(n_traj), float(t_end), _tp(grid), G, int(seed),
+                                     int(max_events), _tp(mean), _tp(cov), _stream(stream),
+                                     ctypes.byref(st) if st is not None else None))
+    return mean, cov, (st.as_dict() if st is not None else None)
 
 
 def jacobian_vjp(jac, w, stream=None, out=None):

@@ -179,3 +179,26 @@ def test_against_master_equation(case):
             p[:len(probs)] = probs[:nb]
             ok, chi, df = _chi2_ok(out["hist"][g], p, N)
             assert ok, (name, s, g, chi, df)
+
+
+def test_covariance_pins():
+    """Species covariance: its diagonal is the pinned variance; a conserved total makes
+    cov(A, B) = -var(A) exactly (every trajectory has A + B = n); two decoupled
+    birth-death species have covariance zero within sampling error; symmetry."""
+    n = 20
+    iso = inputs._model("iso", ["A", "B"], [({"A": 1}, {"B": 1}, 1.0), ({"B": 1}, {"A": 1}, 0.5)], [n, 0])
+    grid = inputs.uniform_grid(4.0, 9)
+    st, mean, cov = orc.covariance(iso, 3000, 4.0, grid, seed=5)
+    assert st == orc.OK
+    st, ref = orc.run(iso, 3000, 4.0, grid, seed=5)
+    assert np.array_equal(mean, ref["mean"])
+    assert np.array_equal(cov[:, 0, 0], ref["var"][:, 0]) and np.array_equal(cov[:, 1, 1], ref["var"][:, 1])
+    assert np.array_equal(cov[:, 0, 1], -cov[:, 0, 0]) and np.array_equal(cov[:, 0, 1], cov[:, 1, 0])
+    two = inputs._model("two", ["X", "Y"], [({}, {"X": 1}, 5.0), ({"X": 1}, {}, 0.5),
+                                            ({}, {"Y": 1}, 3.0), ({"Y": 1}, {}, 0.2)], [0, 0])
+    N = 20000
+    st, mean, cov = orc.covariance(two, N, 10.0, np.array([10.0]), seed=6)
+    assert st == orc.OK
+    # sample covariance of independent variables: standard error sqrt(var_x var_y / N)
+    se = math.sqrt(cov[0, 0, 0] * cov[0, 1, 1] / N)
+    assert abs(cov[0, 0, 1]) < 5 * se
