@@ -187,6 +187,14 @@ ssa_status ssa_run_cov_device(const ssa_model *model, const double *rates, int64
                               const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events, double *mean,
                               double *cov, void *stream, ssa_stats *stats);
 
+/* Quantiles per grid point from a histogram of ssa_run_device (spec as used there):
+ * for each q in qs (0 < q <= 1) the rank k = max(1, ceil(q N)) in binary64 and the result
+ * is lo + b width for the first bin b whose cumulative count reaches k (with width 1 and
+ * no clamping in the top bin, the k-th smallest count).  hist [G*nbins], qs [nq], out
+ * [G*nq] int32, all device; asynchronous on stream. */
+ssa_status ssa_hist_quantiles(const uint32_t *hist, int32_t n_grid, const ssa_hist_spec *spec, int64_t n_traj,
+                              const double *qs, int32_t nq, int32_t *out, void *stream);
+
 /* grad[j] = sum_{g,s} w[g][s] jac[g][s][j] on the device (fixed summation order): the
  * vector-Jacobian product that turns the forward Jacobian into d loss / d ln c for
  * w = d loss / d mean.  jac [G*S*M], w [G*S], grad [M], all device; asynchronous on stream. */

@@ -1125,6 +1125,17 @@ ssa_status ssa_run_cov_device(const ssa_model *m, const double *rates, int64_t n
     return SSA_OK;
 }
 
+ssa_status ssa_hist_quantiles(const uint32_t *hist, int32_t G, const ssa_hist_spec *spec, int64_t n_traj,
+                              const double *qs, int32_t nq, int32_t *out, void *stream) {
+    if (!hist || !spec || !qs || !out || G <= 0 || nq <= 0 || n_traj <= 0 || spec->nbins <= 0 || spec->width <= 0)
+        return fail(SSA_E_INVALID, "bad argument");
+    const int64_t cells = (int64_t)G * nq;
+    hipLaunchKernelGGL(hist_quantile_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0,
+                       (hipStream_t)stream, hist, G, spec->nbins, spec->lo, spec->width, n_traj, qs, nq, out);
+    HIP_TRY(hipGetLastError());
+    return SSA_OK;
+}
+
 ssa_status ssa_jacobian_vjp(const double *jac, const double *w, int32_t G, int32_t S, int32_t M, double *grad,
                             void *stream) {
     if (!jac || !w || !grad || G <= 0 || S <= 0 || M <= 0) return fail(SSA_E_INVALID, "bad argument");

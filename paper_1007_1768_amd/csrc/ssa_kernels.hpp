@@ -548,6 +548,31 @@ __global__ void hist_prefix_kernel(const int32_t *__restrict__ Hd, int32_t G, in
     }
 }
 
+// Quantiles of the binned distribution at every grid point: for q in (0, 1] the rank is
+// k = max(1, ceil(q N)) and the result is the lower edge lo + b width of the first bin b
+// whose cumulative count reaches k (with width 1 and no clamping in the top bin, the k-th
+// smallest count).  One thread per (grid point, quantile).
+__global__ void hist_quantile_kernel(const uint32_t *__restrict__ hist, int32_t G, int32_t nb, int32_t lo,
+                                     int32_t width, int64_t n_traj, const double *__restrict__ qs, int32_t nq,
+                                     int32_t *__restrict__ out) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)G * nq) return;
+    const int64_t g = idx / nq;
+    const double q = qs[idx % nq];
+    int64_t k = (int64_t)ceil(q * (double)n_traj);
+    k = max(k, (int64_t)1);
+    int64_t cum = 0;
+    int32_t b = nb - 1;
+    for (int32_t i = 0; i < nb; ++i) {
+        cum += hist[g * nb + i];
+        if (cum >= k) {
+            b = i;
+            break;
+        }
+    }
+    out[idx] = lo + b * width;
+}
+
 // Fixed-order pairwise sum of the per-trajectory gradient rows, then the 1/N scale.
 // Stage: out[r][j] = in[2r][j] + in[2r+1][j] (odd tail copied).
 __global__ void pair_sum_kernel(const double *__restrict__ in, int64_t rows, int32_t M, double *__restrict__ out) {

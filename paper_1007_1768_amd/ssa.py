@@ -20,6 +20,7 @@ _NAMES = {1: "SSA_E_INVALID", 2: "SSA_E_NOMEM", 3: "SSA_E_DEVICE", 4: "SSA_E_OVE
 
 EXPORTS = ["ssa_model_create", "ssa_model_destroy", "ssa_run", "ssa_run_device", "ssa_backward_device",
            "ssa_run_jacobian_device", "ssa_jacobian_vjp", "ssa_autotune_forward", "ssa_run_cov_device",
+           "ssa_hist_quantiles",
            "ssa_record", "ssa_batch_create", "ssa_batch_run", "ssa_batch_destroy", "ssa_last_error"]
 
 
@@ -64,6 +65,7 @@ def load(path=None):
     L.ssa_backward_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
     L.ssa_autotune_forward.argtypes = [vp, vp, i64, dbl, vp, i32, u64, vp, vp]
     L.ssa_run_cov_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp]
+    L.ssa_hist_quantiles.argtypes = [vp, i32, vp, i64, vp, i32, vp, vp]
     L.ssa_run_jacobian_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
     L.ssa_jacobian_vjp.argtypes = [vp, vp, i32, i32, i32, vp, vp]
     L.ssa_record.argtypes = [vp, vp, i64, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
@@ -227,6 +229,19 @@ def run_cov_device(model, n_traj, t_end, grid, seed, rates=None, max_events=0, s
                                      int(max_events), _tp(mean), _tp(cov), _stream(stream),
                                      ctypes.byref(st) if st is not None else None))
     return mean, cov, (st.as_dict() if st is not None else None)
+
+
+def hist_quantiles(hist, spec, n_traj, qs, stream=None):
+    """Per-grid-point quantiles from a histogram of run_device (ssa_hist_quantiles);
+    hist (G, nbins) int32/uint32 device tensor, spec = (species, lo, width, nbins), qs a
+    float64 device tensor; returns (G, len(qs)) int32."""
+    import torch
+    G = hist.shape[0]
+    out = torch.empty((G, qs.shape[0]), dtype=torch.int32, device=hist.device)
+    sp = HistSpec(*[int(v) for v in spec])
+    _check(load().ssa_hist_quantiles(_tp(hist.contiguous()), G, ctypes.byref(sp), int(n_traj), _tp(qs.contiguous()),
+                                     qs.shape[0], _tp(out), _stream(stream)))
+    return out
 
 
 def jacobian_vjp(jac, w, stream=None, out=None):

@@ -48,3 +48,29 @@ def test_covariance_matches_oracle(ssa, case):
     if case == "isomerisation":
         c = cov.cpu().numpy()
         assert np.array_equal(c[:, 0, 1], -c[:, 0, 0])
+
+
+def test_quantiles_are_order_statistics(ssa):
+    """With width 1 and a top bin above every count, the q-quantile of the histogram is the
+    k-th smallest count, k = max(1, ceil(q N)): compared with the sorted grid states of the
+    oracle's own trajectories and with the cumulative oracle histogram."""
+    m = inputs.immigration_death()
+    N, t_end, G, seed = 700, 30.0, 7, 9
+    spec = (0, 0, 1, 400)
+    grid = inputs.uniform_grid(t_end, G)
+    model = ssa.Model.from_dict(m)
+    mean, var, h, _ = ssa.run_device(model, N, t_end, torch.tensor(grid, device=DEV), seed, hist=spec)
+    qs = np.array([1e-9, 0.1, 0.25, 0.5, 0.75, 0.9, 1.0])
+    out = ssa.hist_quantiles(h, spec, N, torch.tensor(qs, device=DEV)).cpu().numpy()
+    torch.cuda.synchronize()
+    model.close()
+    states = np.zeros((N, G), dtype=np.int64)
+    for i in range(N):
+        st, r = orc.trajectory(m, seed, i, t_end, grid)
+        assert st == 0
+        states[i] = r["states"][:, 0]
+    assert states.max() < 399
+    srt = np.sort(states, axis=0)
+    for iq, q in enumerate(qs):
+        k = max(1, int(np.ceil(q * N)))
+        assert np.array_equal(out[:, iq], srt[k - 1]), q
