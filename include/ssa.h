@@ -97,14 +97,17 @@ typedef struct {
  *   products  [M*S] host: coefficients >= 0 (e.g. 200), each <= 2^19 - 4
  *   rates     [M]   host: stochastic rate constants c_j, finite, >= 0
  *   x0        [S]   host: initial counts >= 0
- *   sum_order ssa_sum_order (SSA_SUM_BLOCK64 needs M <= 512)
+ *   sum_order ssa_sum_order (either for any M up to 4096)
  * What runs where:
  *   SEQ, M <= 32 and S <= 64: kernels specialised to the network at first use (run-time
  *     compilation, cached per device), every entry point;
  *   SEQ otherwise: the table-driven kernel, which changes at most 4 species per reaction;
  *     record and backward need M <= 32 (SSA_E_UNSUPPORTED beyond);
- *   BLOCK64: the one-trajectory-per-wave kernel, at most 4 changed species per reaction;
- *     not accepted by ssa_batch_create.
+ *   BLOCK64: one trajectory per wave, at most 4 changed species per reaction; up to 512
+ *     reactions the chunk lives in registers, above that in LDS, where an event
+ *     re-evaluates only the propensities that read a species it changed (a dependency
+ *     graph built here; same results as re-evaluating all, which SSA_WIDE_DEPG=0 selects);
+ *     backward needs M <= 512 (SSA_E_UNSUPPORTED beyond); not accepted by ssa_batch_create.
  * The arrays are copied (to the current device); the handle is immutable and may be shared
  * by threads that use the same device.  Errors: SSA_E_INVALID, SSA_E_UNSUPPORTED,
  * SSA_E_NOMEM, SSA_E_DEVICE. */
@@ -139,7 +142,8 @@ ssa_status ssa_run_device(const ssa_model *model, const double *rates, int64_t n
  * rates [M] (NULL = model's), grid [G], w [G*S] (dL/dmean), mhat [G*S] (centring, usually
  * the forward mean), grad [M] output.  The per-trajectory sums are reduced in a fixed
  * pairwise order, so the result is deterministic.  Same status codes as ssa_run_device
- * (SSA_E_UNSUPPORTED for a SEQ model with more than 32 reactions). */
+ * (SSA_E_UNSUPPORTED for a SEQ model with more than 32 reactions or a BLOCK64 model with
+ * more than 512). */
 ssa_status ssa_backward_device(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
                                const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events,
                                const double *w, const double *mhat, double *grad, void *stream,

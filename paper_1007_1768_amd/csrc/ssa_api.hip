@@ -64,7 +64,8 @@ constexpr int32_t kMaxProduct = (1 << 19) - 4;
 constexpr uint64_t kDefaultMaxEvents = 1ull << 62;
 constexpr int32_t kJitMaxReactions = 32;     // specialised kernels keep a_j, S_j in registers
 constexpr int32_t kJitMaxSpecies = 64;
-constexpr int32_t kWaveMaxQ = 8;            // 64-chunk order: at most 8 reactions per lane
+constexpr int32_t kWaveMaxQ = 8;            // 64-chunk order: reactions per lane held in registers
+constexpr int64_t kMaxDepEntries = (int64_t)1 << 24;   // dependency lists beyond this: full re-evaluation
 
 // Device allocations made by one call, released on the stream in reverse order.
 struct StreamScratch {
@@ -101,6 +102,14 @@ int cu_count(int dev) {
     if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
     if (dev >= 0 && dev < 64) cache[dev] = n;
     return n;
+}
+
+// LDS one block may use (bytes).
+size_t lds_max(int dev) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || n <= 0)
+        n = 64 * 1024;
+    return (size_t)n;
 }
 
 // Kernel choice for single-network launches: the kernel specialised to the network
@@ -147,6 +156,9 @@ struct ssa_model {
     double *d_rate = nullptr;         // [m_pad] zero-padded rates
     int32_t *d_chg = nullptr;         // [M * kChg] packed changes
     int32_t *d_x0 = nullptr;          // [S]
+    int2 *d_dep = nullptr;            // 64-chunk order above kWaveMaxQ per lane: dependency lists
+    int32_t *d_dep_ptr = nullptr;     // [M + 1]
+    int64_t dep_nnz = 0;
     std::string jit_src;              // generated network description for specialisation
 };
 
@@ -323,6 +335,8 @@ NetDev base_net(const ssa_model *m, const double *rates, int64_t n_traj, double 
     n.x0 = m->d_x0;
     n.grid = grid;
     n.q = m->q;
+    n.dep = m->d_dep;
+    n.dep_ptr = m->d_dep_ptr;
     return n;
 }
 
@@ -512,8 +526,45 @@ struct EventPair {
 };
 
 // One-trajectory-per-wave kernels (64-chunk sum order).
+// Above kWaveMaxQ reactions per lane: one wave per block, chunk slots in LDS; the
+// dependency-graph update unless SSA_WIDE_DEPG=0 (or no graph was built) asks for the full
+// re-evaluation.  Both give the same bits.
+template <int MODE, bool DEPG>
+const void *wide_for(int32_t q) {
+    if (q <= 16) return (const void *)wide_kernel<16, MODE, DEPG>;
+    if (q <= 32) return (const void *)wide_kernel<32, MODE, DEPG>;
+    if (q <= 64) return (const void *)wide_kernel<64, MODE, DEPG>;
+    return nullptr;
+}
+
+bool wide_depg(const ssa_model *m) {
+    const char *e = std::getenv("SSA_WIDE_DEPG");
+    return m->d_dep_ptr != nullptr && !(e && e[0] == '0');
+}
+
+template <int MODE>
+hipError_t launch_wide(const ssa_model *m, const WorkList &wl, int dev, hipStream_t st) {
+    const bool depg = wide_depg(m);
+    const void *kern = depg ? wide_for<MODE, true>(m->q) : wide_for<MODE, false>(m->q);
+    if (!kern) return hipErrorInvalidValue;
+    const int32_t Q = m->q <= 16 ? 16 : (m->q <= 32 ? 32 : 64);
+    const size_t lds = (size_t)Q * kWave * (depg ? 8 : 12) + ((size_t)m->S + 1) * sizeof(int32_t);
+    int per_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave, lds);
+    if (e != hipSuccess) return e;
+    const int64_t n_traj = wl.range_end - wl.range_begin;
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(per_cu, 1) * cu_count(dev), n_traj));
+    WorkList w = wl;
+    void *args[] = {&w};
+    return hipLaunchKernel(kern, dim3((unsigned)blocks), dim3(kWave), args, lds, st);
+}
+
 template <int MODE>
 hipError_t launch_wave(const ssa_model *m, const WorkList &wl, int dev, hipStream_t st) {
+    if (m->q > kWaveMaxQ) {
+        if constexpr (MODE == kBwd) return hipErrorInvalidValue;
+        else return launch_wide<MODE>(m, wl, dev, st);
+    }
     const void *kern = nullptr;
     if (m->q <= 1) kern = (const void *)wave_kernel<1, MODE>;
     else if (m->q <= 2) kern = (const void *)wave_kernel<2, MODE>;
@@ -708,6 +759,11 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
         wl.s_rows = S;
         wl.m_rows = m->M;
         k.lds = generic_int_words(wl.s_rows, wl.m_rows) * sizeof(int32_t) + kCohorts * win_bytes;
+        if (k.lds > lds_max(dev))
+            return fail(SSA_E_UNSUPPORTED,
+                        "the sequential-order kernel needs %zu bytes of LDS for %d species and %d reactions "
+                        "(limit %zu); the 64-chunk order runs such networks",
+                        k.lds, S, m->M, lds_max(dev));
     }
     const size_t cell_words = (size_t)G * S * 2;
     int64_t blocks = 0;
@@ -760,8 +816,6 @@ ssa_status ssa_model_create(int32_t S, int32_t M, const int32_t *reac, const int
     m->M = M;
     m->order = sum_order;
     m->q = (M + kWave - 1) / kWave;
-    if (sum_order == SSA_SUM_BLOCK64 && m->q > kWaveMaxQ)
-        return fail(SSA_E_UNSUPPORTED, "the 64-chunk sum order supports at most %d reactions", kWaveMaxQ * kWave);
     m->reac.assign(reac, reac + (size_t)M * S);
     m->prod.assign(prod, prod + (size_t)M * S);
     m->rate.assign(rates, rates + M);
@@ -805,6 +859,44 @@ ssa_status ssa_model_create(int32_t S, int32_t M, const int32_t *reac, const int
         return fail(SSA_E_UNSUPPORTED, "a reaction changes more than %d species in a network run by a table-driven kernel",
                     kChg);
     m->jit_src = generate_net_source(m.get());
+    // dependency lists for the LDS-resident 64-chunk kernel: for each reaction, the
+    // reactions (as LDS slot and reactant code) with a reactant among its changed species
+    std::vector<int32_t> dep_ptr;
+    std::vector<int2> dep;
+    if (sum_order == SSA_SUM_BLOCK64 && m->q > kWaveMaxQ) {
+        std::vector<std::vector<int32_t>> readers(S);
+        for (int32_t k = 0; k < M; ++k) {
+            const uint32_t code = rx[k];
+            const int32_t ra = (int32_t)(code & 0xfffu), rb = (int32_t)((code >> 12) & 0xfffu);
+            if (ra) readers[ra - 1].push_back(k);
+            if (rb && rb != ra) readers[rb - 1].push_back(k);
+        }
+        dep_ptr.assign((size_t)M + 1, 0);
+        std::vector<int32_t> mark(M, -1);
+        bool too_big = false;
+        for (int32_t j = 0; j < M && !too_big; ++j) {
+            std::vector<int32_t> ks;
+            for (int32_t s = 0; s < S; ++s) {
+                if (prod[(size_t)j * S + s] == reac[(size_t)j * S + s]) continue;
+                for (int32_t k : readers[s])
+                    if (mark[k] != j) {
+                        mark[k] = j;
+                        ks.push_back(k);
+                    }
+            }
+            std::sort(ks.begin(), ks.end());
+            for (int32_t k : ks) {
+                const int32_t slot = (k % m->q) * kWave + k / m->q;
+                dep.push_back(make_int2(slot, (int)rx[k]));
+            }
+            dep_ptr[j + 1] = (int32_t)dep.size();
+            too_big = (int64_t)dep.size() > kMaxDepEntries;
+        }
+        if (too_big) {
+            dep.clear();
+            dep_ptr.clear();
+        }
+    }
     hipError_t e = hipGetDevice(&m->device);
     if (e == hipSuccess) e = hipMalloc(&m->d_rx, sizeof(uint32_t) * m->m_pad);
     if (e == hipSuccess) e = hipMalloc(&m->d_rate, sizeof(double) * m->m_pad);
@@ -814,6 +906,15 @@ ssa_status ssa_model_create(int32_t S, int32_t M, const int32_t *reac, const int
     if (e == hipSuccess) e = hipMemcpy(m->d_rate, rpad.data(), sizeof(double) * m->m_pad, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->d_chg, chg.data(), sizeof(int32_t) * M * kChg, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(m->d_x0, m->x0.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !dep_ptr.empty()) {
+        m->dep_nnz = (int64_t)dep.size();
+        e = hipMalloc(&m->d_dep_ptr, sizeof(int32_t) * dep_ptr.size());
+        if (e == hipSuccess) e = hipMalloc(&m->d_dep, sizeof(int2) * std::max<size_t>(dep.size(), 1));
+        if (e == hipSuccess)
+            e = hipMemcpy(m->d_dep_ptr, dep_ptr.data(), sizeof(int32_t) * dep_ptr.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !dep.empty())
+            e = hipMemcpy(m->d_dep, dep.data(), sizeof(int2) * dep.size(), hipMemcpyHostToDevice);
+    }
     if (e != hipSuccess) {
         ssa_model_destroy(m.release());
         return fail(e == hipErrorOutOfMemory ? SSA_E_NOMEM : SSA_E_DEVICE, "model upload: %s", hipGetErrorString(e));
@@ -828,6 +929,8 @@ void ssa_model_destroy(ssa_model *m) {
     if (m->d_rate) (void)hipFree(m->d_rate);
     if (m->d_chg) (void)hipFree(m->d_chg);
     if (m->d_x0) (void)hipFree(m->d_x0);
+    if (m->d_dep) (void)hipFree(m->d_dep);
+    if (m->d_dep_ptr) (void)hipFree(m->d_dep_ptr);
     delete m;
 }
 
@@ -1185,6 +1288,9 @@ ssa_status ssa_backward_device(const ssa_model *m, const double *rates, int64_t 
     if (!(t_end >= 0.0) || !std::isfinite(t_end)) return fail(SSA_E_INVALID, "t_end must be finite and >= 0");
     if (m->order == SSA_SUM_SEQ && m->M > kJitMaxReactions)
         return fail(SSA_E_UNSUPPORTED, "backward supports at most %d reactions", kJitMaxReactions);
+    if (m->order == SSA_SUM_BLOCK64 && m->q > kWaveMaxQ)
+        return fail(SSA_E_UNSUPPORTED, "backward in the 64-chunk order supports at most %d reactions",
+                    kWaveMaxQ * kWave);
     if (n_traj > ((int64_t)1 << 31) * kChunk) return fail(SSA_E_INVALID, "n_traj too large");
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
@@ -1433,6 +1539,9 @@ ssa_status batch_enqueue(ssa_batch *bt, hipStream_t st) {
     if (!pick_generic_fwd<true>(bt->mm, k)) return fail(SSA_E_UNSUPPORTED, "no kernel");
     k.lds = generic_int_words(wl.s_rows, wl.m_rows) * sizeof(int32_t) +
             (size_t)(kBlock / kWave) * kCohorts * wl.win_words * sizeof(long long);
+    if (k.lds > lds_max(bt->device))
+        return fail(SSA_E_UNSUPPORTED, "the batch needs %zu bytes of LDS per block (limit %zu)", k.lds,
+                    lds_max(bt->device));
     int64_t blocks = 0;
     HIP_TRY(fwd_blocks(k, false, bt->device, bt->n_items, blocks));
     HIP_TRY(fwd_launch(k, false, blocks, wl, st));

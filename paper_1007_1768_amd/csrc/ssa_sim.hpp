@@ -93,6 +93,10 @@ struct NetDev {
     int32_t *Hd;
     int32_t h_species, h_lo, h_width;
     int32_t q;               // 64-chunk sum order: reactions per lane (one trajectory per wave)
+    // 64-chunk order above 8 reactions per lane: dependency lists of the fired reaction,
+    // entries (LDS slot i * 64 + l of reaction l q + i, packed reactant code), [M + 1] offsets
+    const int2 *dep;
+    const int32_t *dep_ptr;
     // record
     int64_t rec_begin;
     int32_t *rec_states;

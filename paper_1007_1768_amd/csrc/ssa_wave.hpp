@@ -286,4 +286,269 @@ __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
     }
 }
 
+// Networks with more than 8 reactions per lane (q up to 64, M up to 4096), same sum order.
+// One wave per block; the chunk values live in LDS, slot i of lane l at word i * 64 + l,
+// so a row of slots is one conflict-free access.
+//
+// DEPG: the LDS slots hold the propensities themselves.  After an event only the
+// propensities that read a species the event changed are evaluated again, from the
+// dependency list of the fired reaction (slot and reactant code of each reaction whose
+// reactants intersect the changed species); every other slot keeps its value.  Without
+// DEPG the slots hold the rate constants and the reactant codes, and every lane
+// re-evaluates its whole chunk each event.  Both re-add the chunk's local sums in order
+// from the current values, so the partial sums, the selected reaction and the trajectory
+// are those of the full recomputation, bit for bit: the graph changes how much work an
+// event costs (the propensity evaluations of the reactions it touches instead of M), not
+// what is computed.
+//
+// Modes: forward (moment differences and histogram straight into the network totals, as
+// above) and record (per-trajectory grid states; the n_j and A_j rows accumulate in the
+// caller's output arrays).
+template <int Q, int MODE, bool DEPG>
+__global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
+    static_assert(MODE == kFwd || MODE == kRec, "forward and record only");
+    extern __shared__ double lds_d[];
+    const uint32_t lane = __lane_id();
+    const NetDev n = wl.net0;
+    const int32_t S = n.S, M = n.M, G = n.G, q = n.q;
+    double *av = lds_d;                                             // [Q][64] propensities | rates
+    uint32_t *cw = (uint32_t *)(lds_d + Q * kWave);                 // [Q][64] codes (without DEPG)
+    int32_t *xl = (int32_t *)(lds_d + Q * kWave) + (DEPG ? 0 : Q * kWave);
+    // real slots of this lane: reactions lane q .. lane q + nreal - 1
+    const int32_t nreal = max(0, min(q, M - (int32_t)lane * q));
+    const int32_t last_lane = (M - 1) / q;
+
+    if (!DEPG) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int32_t j = (int32_t)lane * q + i;
+            av[i * kWave + lane] = i < nreal ? n.rate[j] : 0.0;
+            cw[i * kWave + lane] = i < nreal ? n.rx[j] : 0u;
+        }
+    }
+
+    const GridInfo gi = *(const SSA_CONST GridInfo *)n.ginfo;
+    GridView gv;
+    gv.grid = n.grid;
+    gv.T = gi.T;
+    gv.D = gi.D;
+    gv.lo = gi.lo;
+    gv.scale = gi.scale;
+    gv.G = G;
+    gv.uniform = gi.uniform;
+
+    uint32_t flags = 0;
+    unsigned long long tot_events = 0, max_steps = 0;
+
+    for (;;) {
+        int32_t item = 0;
+        if (lane == 0) item = (int32_t)atomicAdd(wl.counter, 1u);
+        item = wave_uniform(__shfl(item, 0));
+        if ((int64_t)item >= wl.range_end - wl.range_begin) break;
+        const int64_t traj = wl.range_begin + item;
+        const int64_t r = traj - n.rec_begin;
+
+        if (lane == 0) xl[0] = 1;
+        for (int32_t s = lane; s < S; s += kWave) xl[s + 1] = n.x0[s];
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        if (DEPG) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int32_t j = (int32_t)lane * q + i;
+                av[i * kWave + lane] = i < nreal ? wave_propensity(n.rx[j], n.rate[j], xl) : 0.0;
+            }
+        }
+        if (MODE == kRec) {
+            for (int32_t i = 0; i < nreal; ++i) {
+                const int32_t j = (int32_t)lane * q + i;
+                if (n.rec_nf) n.rec_nf[r * M + j] = 0;
+                if (n.rec_aint) n.rec_aint[r * M + j] = 0.0;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+
+        double t = 0.0;
+        uint64_t k = 0, ev = 0;
+        int32_t g = 0;
+        double tg_next = G > 0 ? gv.at(0) : 0.0;
+        bool overflow = false;
+
+        for (;;) {
+            // local sums of this lane's chunk, in slot order
+            double L[Q];
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const double ai = DEPG ? av[i * kWave + lane]
+                                       : wave_propensity(cw[i * kWave + lane], av[i * kWave + lane], xl);
+                L[i] = i == 0 ? ai : L[i - 1] + ai;    // empty slots add +0
+            }
+            double v = L[Q - 1];
+#pragma unroll
+            for (int d = 1; d < kWave; d <<= 1) {
+                const double up = shfl_up_f64(v, d);
+                if ((int)lane >= d) v = v + up;
+            }
+            double E = shfl_up_f64(v, 1);
+            if (lane == 0) E = 0.0;
+            const double a0 = wave_uniform(__shfl(E + L[Q - 1], last_lane, kWave));
+
+            double tau = __builtin_inf(), r2 = 0.0;
+            if (a0 != 0.0) {
+                const u32x4 o = philox4x32_10((uint32_t)k, (uint32_t)(k >> 32), (uint32_t)traj,
+                                              (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
+                const double r1 = uniform_open0(o.v0, o.v1);
+                r2 = uniform_open1(o.v2, o.v3);
+                tau = neg_log(r1) / a0;
+                k = k + 1;
+            }
+            const double t_next = t + tau;
+
+            if (MODE == kRec) {
+                int32_t *rows = n.rec_states + (size_t)r * G * S;
+                while (g < G && gv.at(g) < t_next) {
+                    for (int32_t s = lane; s < S; s += kWave) rows[(size_t)g * S + s] = xl[s + 1];
+                    ++g;
+                }
+            }
+            if (t_next > n.t_end) break;
+            if (ev >= n.max_events) {
+                flags |= kFlagEventLimit;
+                break;
+            }
+
+            // selection: smallest j with S_j > u (the local sums are non-decreasing, so the
+            // first slot that passes is the lane's candidate), else the largest j with a_j > 0
+            const double u = r2 * a0;
+            int32_t first = -1;
+#pragma unroll
+            for (int i = Q - 1; i >= 0; --i)
+                if (E + L[i] > u) first = i;
+            if (nreal == 0) first = -1;
+            int32_t sel, sel_lane;
+            const uint64_t hit = __ballot(first >= 0);
+            if (hit) {
+                sel_lane = __ffsll((unsigned long long)hit) - 1;
+                sel = sel_lane * q + __shfl(first, sel_lane, kWave);
+            } else {
+                int32_t lastpos = -1;
+                for (int32_t i = 0; i < nreal; ++i) {
+                    const double ai = DEPG ? av[i * kWave + lane]
+                                           : wave_propensity(cw[i * kWave + lane], av[i * kWave + lane], xl);
+                    if (ai > 0.0) lastpos = i;
+                }
+                const uint64_t pos = __ballot(lastpos >= 0);
+                if (pos) {
+                    sel_lane = 63 - __clzll((unsigned long long)pos);
+                    sel = sel_lane * q + __shfl(lastpos, sel_lane, kWave);
+                } else {
+                    sel_lane = last_lane;
+                    sel = M - 1;
+                }
+            }
+            sel = wave_uniform(sel);
+            sel_lane = wave_uniform(sel_lane);
+
+            if (MODE == kRec) {
+                // A_j += a_j tau with the propensities of the state before the event
+                if (n.rec_aint) {
+                    for (int32_t i = 0; i < nreal; ++i) {
+                        const double ai = DEPG ? av[i * kWave + lane]
+                                               : wave_propensity(cw[i * kWave + lane], av[i * kWave + lane], xl);
+                        double *pa = n.rec_aint + r * M + (int32_t)lane * q + i;
+                        *pa = *pa + ai * tau;
+                    }
+                }
+                // the lane that owns the fired reaction counts it (it also zeroed the slot)
+                if (n.rec_nf && (int32_t)lane == sel_lane) n.rec_nf[r * M + sel] += 1;
+            }
+
+            int32_t bin = G;
+            if (MODE == kFwd) {
+                bin = g;
+                if (g < G && t_next > tg_next) bin = gv.next_bin(g, t_next, tg_next);
+            }
+            if ((int)lane < kChg) {
+                const int32_t cv = n.chg[sel * kChg + lane];
+                const int32_t rr = chg_row(cv), dl = chg_delta(cv);
+                if (dl != 0) {
+                    const int32_t xo = xl[rr];
+                    const int64_t xw = (int64_t)xo + dl;
+                    overflow = xw > 2147483647ll || xw < -2147483647ll - 1;
+                    const int32_t xn = (int32_t)xw;
+                    xl[rr] = xn;
+                    if (MODE == kFwd && bin < G && !overflow) {
+                        const int32_t sp = rr - 1;
+                        unsigned long long *dd = n.D + ((size_t)bin * S + sp) * 2;
+                        const long long d2 = (2ll * xo + dl) * (long long)dl;
+                        atomicAdd(dd, (unsigned long long)(long long)dl);
+                        if (d2 > -kSmallD2 && d2 < kSmallD2) {
+                            atomicAdd(dd + 1, (unsigned long long)d2);
+                        } else {
+                            atomicAdd(dd + 1, (unsigned long long)(d2 & ((1ll << 24) - 1)));
+                            atomicAdd(n.Dhi + (size_t)bin * S + sp, (unsigned long long)(d2 >> 24));
+                        }
+                        if (n.Hd && sp == n.h_species) {
+                            const int32_t bo = xo < n.h_lo ? 0 : min((xo - n.h_lo) / n.h_width, n.nb_hist - 1);
+                            const int32_t bn = xn < n.h_lo ? 0 : min((xn - n.h_lo) / n.h_width, n.nb_hist - 1);
+                            if (bo != bn) {
+                                atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bo, -1);
+                                atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bn, 1);
+                            }
+                        }
+                    }
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            if (__ballot(overflow)) {
+                flags |= kFlagOverflow;
+                break;
+            }
+            if (DEPG) {
+                // re-evaluate the propensities that read a changed species
+                const int32_t p0 = n.dep_ptr[sel], p1 = n.dep_ptr[sel + 1];
+                for (int32_t p = p0 + (int32_t)lane; p < p1; p += kWave) {
+                    const int2 e = n.dep[p];
+                    const int32_t j = (e.x & (kWave - 1)) * q + (e.x >> 6);
+                    av[e.x] = wave_propensity((uint32_t)e.y, n.rate[j], xl);
+                }
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+            t = t_next;
+            ev = ev + 1;
+            if (MODE == kFwd) g = bin;
+        }
+
+        if (MODE == kRec) {
+            if (lane == 0) {
+                n.rec_events[r] = ev;
+                n.rec_draws[r] = k;
+                n.rec_tlast[r] = t;
+            }
+            // the last partial interval of A_j, with the final state's propensities
+            if (n.rec_aint) {
+                const double tail = n.t_end - t;
+                for (int32_t i = 0; i < nreal; ++i) {
+                    const double ai = DEPG ? av[i * kWave + lane]
+                                           : wave_propensity(cw[i * kWave + lane], av[i * kWave + lane], xl);
+                    double *pa = n.rec_aint + r * M + (int32_t)lane * q + i;
+                    *pa = *pa + ai * tail;
+                }
+            }
+        }
+        tot_events += ev;
+        max_steps = max(max_steps, (unsigned long long)ev);
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (lane == 0) {
+        if (tot_events) atomicAdd(wl.stats + 0, tot_events);
+        atomicMax(wl.stats + 1, max_steps);
+        if (flags) atomicOr(wl.stats + 2, (unsigned long long)flags);
+    }
+}
+
 }  // namespace ssa

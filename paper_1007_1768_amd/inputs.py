@@ -17,7 +17,9 @@ for it, with the shapes named in the workload list of the design notes):
   * differentiated: the viral network at 10^5 trajectories with a squared-error loss
     against the means of the same model run with log-rates perturbed by N(0, 0.1^2);
   * large: the viral network, 10^6 trajectories, 10^4-point grid, 64-bin histogram of
-    I per grid point, with the gradient.
+    I per grid point, with the gradient;
+  * wide networks (wide_network): 512-4096 reactions summed in the 64-chunk order, for
+    the one-trajectory-per-wave kernels.
 """
 import numpy as np
 
@@ -128,6 +130,59 @@ def random_networks(seed=20100701, count=64, G=200):
                          rates=rates, x0=x0, t_end=t_end, n_traj=n_traj, grid=uniform_grid(t_end, G),
                          seed=net_seed))
     return nets
+
+
+def wide_network(M, seed=20100702, S=None):
+    """A mass-action network with many reactions (hundreds to 4096) for the 64-chunk order.
+
+    S = min(1024, max(8, M // 4)) species unless given.  Every species degrades (the first
+    S reactions); the rest are drawn as inflows (8 %), conversions X -> Y (30 %),
+    bindings X + Y -> Z (25 %), dimerisations 2X -> Y (12 %), catalysed degradations
+    X + Y -> X (15 %) and annihilations X + Y -> 0 (10 %).  Rates are log-uniform in
+    [1e-2, 1]; bimolecular rates are divided by 20 (about the mean initial count, so
+    first- and second-order reactions fire at comparable rates).  Initial counts are
+    uniform in [5, 40].  Only inflows add molecules, so trajectories stay short.
+    """
+    rng = np.random.default_rng(seed + M)
+    if S is None:
+        S = min(1024, max(8, M // 4))
+    reac = np.zeros((M, S), dtype=np.int32)
+    prod = np.zeros((M, S), dtype=np.int32)
+    bimol = np.zeros(M, dtype=bool)
+    j = 0
+    for s in range(min(S, M)):
+        reac[j, s] = 1
+        j += 1
+    kinds = ["inflow", "conv", "bind", "dimer", "catdeg", "annih"]
+    probs = [0.08, 0.30, 0.25, 0.12, 0.15, 0.10]
+    while j < M:
+        k = kinds[int(rng.choice(len(kinds), p=probs))]
+        a, b, z = (int(v) for v in rng.integers(0, S, size=3))
+        if b == a:
+            b = (a + 1) % S
+        if k == "inflow":
+            prod[j, a] = 1
+        elif k == "conv":
+            reac[j, a] = 1
+            prod[j, b] = 1
+        elif k == "dimer":
+            reac[j, a] = 2
+            prod[j, z] = 1
+            bimol[j] = True
+        else:
+            reac[j, a] = 1
+            reac[j, b] = 1
+            bimol[j] = True
+            if k == "bind":
+                prod[j, z] = 1
+            elif k == "catdeg":
+                prod[j, a] = 1
+        j += 1
+    rates = 10.0 ** rng.uniform(-2.0, 0.0, size=M)
+    rates[bimol] /= 20.0
+    x0 = rng.integers(5, 41, size=S).astype(np.int32)
+    return dict(name="wide%d" % M, species=["S%d" % s for s in range(S)], reac=reac, prod=prod, rates=rates,
+                x0=x0, sum_order="block64")
 
 
 def perturbed_rates(model, seed, sigma=0.1):

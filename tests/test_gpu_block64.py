@@ -133,10 +133,10 @@ def test_backward_block64(ssa, case):
 
 
 def test_block64_limits(ssa):
-    m = _chain_network(520, 8, 3)
+    m = _chain_network(4100, 8, 3)
     with pytest.raises(ssa.SSAError) as e:
         ssa.Model.from_dict(m)
-    assert e.value.status == ssa.E_UNSUPPORTED
+    assert e.value.status == ssa.E_INVALID
     ok = ssa.Model.from_dict(_b64(inputs.viral()))
     with pytest.raises(ssa.SSAError) as e:
         ssa.Batch([ok], [64], [1.0], [np.array([0.0, 1.0])], [1])
