@@ -154,6 +154,60 @@ def batched_vs_plain(ssa, torch, dev):
             "speedup": round(plain_s / batched_s, 3), "identical": identical}
 
 
+def wide_sweep(ssa, torch, dev):
+    """Networks with many reactions: the sequential order (one trajectory per lane) against
+    the 64-chunk order (one trajectory per wave), and above 512 reactions the 64-chunk
+    kernel with its dependency-graph update against full re-evaluation.  Forward
+    (mean/variance) kernel time, best of two launches, t_end 0.5, 50-point grid, seed 9."""
+    def run(m, N):
+        grid = torch.tensor(inputs.uniform_grid(0.5, 50), dtype=torch.float64, device=dev)
+        model = ssa.Model.from_dict(m)
+        best = None
+        try:
+            for _ in range(2):
+                _, _, _, st = ssa.run_device(model, N, 0.5, grid, 9, with_stats=True)
+                torch.cuda.synchronize()
+                if best is None or st["kernel_ms"] < best["kernel_ms"]:
+                    best = st
+        except ssa.SSAError as e:
+            return {"error": str(e).split(":")[0]}
+        finally:
+            model.close()
+        return {"events": best["events"], "kernel_ms": round(best["kernel_ms"], 3),
+                "events_per_s": round(best["events"] / best["kernel_ms"] * 1e3, 1)}
+
+    old = os.environ.get("SSA_WIDE_DEPG")
+    rows = []
+    try:
+        for M in (32, 64, 128, 256, 512, 1024, 2048, 4096):
+            S = min(48, M // 2)
+            base = inputs.wide_network(M, S=S)
+            for N in (1024, 16384, 131072):
+                if M >= 2048 and N > 16384:
+                    continue
+                for order in ("seq", "block64"):
+                    m = dict(base)
+                    m["sum_order"] = order
+                    variants = [("-", None)] if (order == "seq" or M <= 512) else [("depg", "1"), ("full", "0")]
+                    for vname, env in variants:
+                        if env is not None:
+                            os.environ["SSA_WIDE_DEPG"] = env
+                        rows.append(dict(set="few_species", M=M, S=S, N=N, order=order, update=vname, **run(m, N)))
+        for M in (600, 1024, 2048, 4096):
+            m = inputs.wide_network(M)
+            for N in (1024, 16384, 65536):
+                for vname, env in (("depg", "1"), ("full", "0")):
+                    os.environ["SSA_WIDE_DEPG"] = env
+                    rows.append(dict(set="sparse", M=M, S=int(m["reac"].shape[1]), N=N, order="block64",
+                                     update=vname, **run(m, N)))
+    finally:
+        if old is None:
+            os.environ.pop("SSA_WIDE_DEPG", None)
+        else:
+            os.environ["SSA_WIDE_DEPG"] = old
+    return rows
+
+
 def workload(name):
     w = dict(inputs.WORKLOADS[name])
     m = w["model"]()
@@ -170,6 +224,8 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched / plain comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter calibration)")
+    ap.add_argument("--wide-sweep", action="store_true",
+                    help="only run the many-reaction sweep (sum orders, dependency graph) and print it")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -192,6 +248,10 @@ def main():
             y.copy_(x)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8}))
+        return
+    if args.wide_sweep:
+        print(json.dumps({"sweep": "wide networks, forward events/s", "rows": wide_sweep(ssa, torch, dev)}),
+              flush=True)
         return
 
     m, w = workload(args.workload)

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "ssa_api.hip")
 DEPS = [os.path.join(HERE, "csrc", f) for f in ("ssa_api.hip", "ssa_kernels.hpp", "ssa_sim.hpp", "ssa_jit.hpp",
-                                                "ssa_device.hpp")] + \
+                                                "ssa_device.hpp", "ssa_wave.hpp")] + \
     [os.path.join(ROOT, "include", "ssa.h")]
 LIB = os.path.join(HERE, "libssa.so")
 ARCH = os.environ.get("SSA_OFFLOAD_ARCH", "gfx950")

@@ -157,6 +157,7 @@ struct ssa_model {
     int32_t *d_chg = nullptr;         // [M * kChg] packed changes
     int32_t *d_x0 = nullptr;          // [S]
     int2 *d_dep = nullptr;            // 64-chunk order above kWaveMaxQ per lane: dependency lists
+    double *d_dep_rate = nullptr;     // [dep_nnz] the model's rate of each entry's reaction
     int32_t *d_dep_ptr = nullptr;     // [M + 1]
     int64_t dep_nnz = 0;
     std::string jit_src;              // generated network description for specialisation
@@ -336,6 +337,7 @@ NetDev base_net(const ssa_model *m, const double *rates, int64_t n_traj, double 
     n.grid = grid;
     n.q = m->q;
     n.dep = m->d_dep;
+    n.dep_rate = m->d_dep_rate;
     n.dep_ptr = m->d_dep_ptr;
     return n;
 }
@@ -543,8 +545,21 @@ bool wide_depg(const ssa_model *m) {
 }
 
 template <int MODE>
-hipError_t launch_wide(const ssa_model *m, const WorkList &wl, int dev, hipStream_t st) {
+hipError_t launch_wide(const ssa_model *m, const WorkList &wl, int dev, hipStream_t st, StreamScratch &scr) {
     const bool depg = wide_depg(m);
+    WorkList w = wl;
+    if (depg && m->dep_nnz > 0 && w.net0.rate != m->d_rate) {
+        // rates given for this run: gather them into the dependency entries' order
+        void *dr = nullptr;
+        hipError_t e = scr.alloc(&dr, sizeof(double) * (size_t)m->dep_nnz);
+        if (e != hipSuccess) return e;
+        const unsigned blocks = (unsigned)std::min<int64_t>((m->dep_nnz + 255) / 256, 65535);
+        hipLaunchKernelGGL(dep_rate_kernel, dim3(blocks), dim3(256), 0, st, (const int2 *)m->d_dep, m->q,
+                           w.net0.rate, m->dep_nnz, (double *)dr);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        w.net0.dep_rate = (const double *)dr;
+    }
     const void *kern = depg ? wide_for<MODE, true>(m->q) : wide_for<MODE, false>(m->q);
     if (!kern) return hipErrorInvalidValue;
     const int32_t Q = m->q <= 16 ? 16 : (m->q <= 32 ? 32 : 64);
@@ -554,16 +569,15 @@ hipError_t launch_wide(const ssa_model *m, const WorkList &wl, int dev, hipStrea
     if (e != hipSuccess) return e;
     const int64_t n_traj = wl.range_end - wl.range_begin;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(per_cu, 1) * cu_count(dev), n_traj));
-    WorkList w = wl;
     void *args[] = {&w};
     return hipLaunchKernel(kern, dim3((unsigned)blocks), dim3(kWave), args, lds, st);
 }
 
 template <int MODE>
-hipError_t launch_wave(const ssa_model *m, const WorkList &wl, int dev, hipStream_t st) {
+hipError_t launch_wave(const ssa_model *m, const WorkList &wl, int dev, hipStream_t st, StreamScratch &scr) {
     if (m->q > kWaveMaxQ) {
         if constexpr (MODE == kBwd) return hipErrorInvalidValue;
-        else return launch_wide<MODE>(m, wl, dev, st);
+        else return launch_wide<MODE>(m, wl, dev, st, scr);
     }
     const void *kern = nullptr;
     if (m->q <= 1) kern = (const void *)wave_kernel<1, MODE>;
@@ -598,7 +612,7 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
                          const double *user_rates, StreamScratch &scr) {
     (void)n_items;
     if (m->order == SSA_SUM_BLOCK64) {
-        HIP_TRY(mode == kRec ? launch_wave<kRec>(m, wl, dev, st) : launch_wave<kBwd>(m, wl, dev, st));
+        HIP_TRY(mode == kRec ? launch_wave<kRec>(m, wl, dev, st, scr) : launch_wave<kBwd>(m, wl, dev, st, scr));
         return SSA_OK;
     }
     if (jit_eligible(m)) {
@@ -722,7 +736,7 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
         HIP_TRY(launch_zero(D, (size_t)G * S * 2 * sizeof(unsigned long long), st));
         EventPair ev;
         if (kernel_ms && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
-        HIP_TRY(launch_wave<kFwd>(m, wl, dev, st));
+        HIP_TRY(launch_wave<kFwd>(m, wl, dev, st, scr));
         if (kernel_ms && ev.b) {
             HIP_TRY(hipEventRecord(ev.b, st));
             HIP_TRY(hipEventSynchronize(ev.b));
@@ -908,12 +922,19 @@ ssa_status ssa_model_create(int32_t S, int32_t M, const int32_t *reac, const int
     if (e == hipSuccess) e = hipMemcpy(m->d_x0, m->x0.data(), sizeof(int32_t) * S, hipMemcpyHostToDevice);
     if (e == hipSuccess && !dep_ptr.empty()) {
         m->dep_nnz = (int64_t)dep.size();
+        std::vector<double> dep_rate(dep.size());
+        for (size_t p = 0; p < dep.size(); ++p)
+            dep_rate[p] = rates[(dep[p].x & (kWave - 1)) * m->q + (dep[p].x >> 6)];
+        const size_t nd = std::max<size_t>(dep.size(), 1);
         e = hipMalloc(&m->d_dep_ptr, sizeof(int32_t) * dep_ptr.size());
-        if (e == hipSuccess) e = hipMalloc(&m->d_dep, sizeof(int2) * std::max<size_t>(dep.size(), 1));
+        if (e == hipSuccess) e = hipMalloc(&m->d_dep, sizeof(int2) * nd);
+        if (e == hipSuccess) e = hipMalloc(&m->d_dep_rate, sizeof(double) * nd);
         if (e == hipSuccess)
             e = hipMemcpy(m->d_dep_ptr, dep_ptr.data(), sizeof(int32_t) * dep_ptr.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess && !dep.empty())
             e = hipMemcpy(m->d_dep, dep.data(), sizeof(int2) * dep.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess && !dep.empty())
+            e = hipMemcpy(m->d_dep_rate, dep_rate.data(), sizeof(double) * dep.size(), hipMemcpyHostToDevice);
     }
     if (e != hipSuccess) {
         ssa_model_destroy(m.release());
@@ -930,6 +951,7 @@ void ssa_model_destroy(ssa_model *m) {
     if (m->d_chg) (void)hipFree(m->d_chg);
     if (m->d_x0) (void)hipFree(m->d_x0);
     if (m->d_dep) (void)hipFree(m->d_dep);
+    if (m->d_dep_rate) (void)hipFree(m->d_dep_rate);
     if (m->d_dep_ptr) (void)hipFree(m->d_dep_ptr);
     delete m;
 }

@@ -96,6 +96,7 @@ struct NetDev {
     // 64-chunk order above 8 reactions per lane: dependency lists of the fired reaction,
     // entries (LDS slot i * 64 + l of reaction l q + i, packed reactant code), [M + 1] offsets
     const int2 *dep;
+    const double *dep_rate;  // rate constant of each entry's reaction (this run's rates)
     const int32_t *dep_ptr;
     // record
     int64_t rec_begin;

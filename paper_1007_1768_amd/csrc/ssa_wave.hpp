@@ -286,6 +286,14 @@ __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
     }
 }
 
+// Rate constants in dependency-entry order: out[p] = rate[reaction of entry p].
+__global__ void dep_rate_kernel(const int2 *dep, int32_t q, const double *rate, int64_t nnz, double *out) {
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t slot = dep[p].x;
+        out[p] = rate[(slot & (kWave - 1)) * q + (slot >> 6)];
+    }
+}
+
 // Networks with more than 8 reactions per lane (q up to 64, M up to 4096), same sum order.
 // One wave per block; the chunk values live in LDS, slot i of lane l at word i * 64 + l,
 // so a row of slots is one conflict-free access.
@@ -293,7 +301,8 @@ __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
 // DEPG: the LDS slots hold the propensities themselves.  After an event only the
 // propensities that read a species the event changed are evaluated again, from the
 // dependency list of the fired reaction (slot and reactant code of each reaction whose
-// reactants intersect the changed species); every other slot keeps its value.  Without
+// reactants intersect the changed species, with its rate constant in a parallel array);
+// every other slot keeps its value.  Without
 // DEPG the slots hold the rate constants and the reactant codes, and every lane
 // re-evaluates its whole chunk each event.  Both re-add the chunk's local sums in order
 // from the current values, so the partial sums, the selected reaction and the trajectory
@@ -374,6 +383,14 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
         int32_t g = 0;
         double tg_next = G > 0 ? gv.at(0) : 0.0;
         bool overflow = false;
+        // draw k's uniforms and -ln r1, prepared one event ahead (they depend on k only;
+        // an absorbing state leaves them unused)
+        double r2n, nl;
+        {
+            const u32x4 o = philox4x32_10(0u, 0u, (uint32_t)traj, (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
+            r2n = uniform_open1(o.v2, o.v3);
+            nl = neg_log(uniform_open0(o.v0, o.v1));
+        }
 
         for (;;) {
             // local sums of this lane's chunk, in slot order
@@ -396,11 +413,8 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
 
             double tau = __builtin_inf(), r2 = 0.0;
             if (a0 != 0.0) {
-                const u32x4 o = philox4x32_10((uint32_t)k, (uint32_t)(k >> 32), (uint32_t)traj,
-                                              (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
-                const double r1 = uniform_open0(o.v0, o.v1);
-                r2 = uniform_open1(o.v2, o.v3);
-                tau = neg_log(r1) / a0;
+                r2 = r2n;
+                tau = nl / a0;
                 k = k + 1;
             }
             const double t_next = t + tau;
@@ -507,15 +521,33 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
                 break;
             }
             if (DEPG) {
-                // re-evaluate the propensities that read a changed species
+                // re-evaluate the propensities that read a changed species; the first 64
+                // entries are loaded before the next draw is prepared, so their latency
+                // overlaps it
                 const int32_t p0 = n.dep_ptr[sel], p1 = n.dep_ptr[sel + 1];
-                for (int32_t p = p0 + (int32_t)lane; p < p1; p += kWave) {
-                    const int2 e = n.dep[p];
-                    const int32_t j = (e.x & (kWave - 1)) * q + (e.x >> 6);
-                    av[e.x] = wave_propensity((uint32_t)e.y, n.rate[j], xl);
+                const int32_t pf = p0 + (int32_t)lane;
+                int2 e = make_int2(0, 0);
+                double ce = 0.0;
+                if (pf < p1) {
+                    e = n.dep[pf];
+                    ce = n.dep_rate[pf];
+                }
+                const u32x4 o = philox4x32_10((uint32_t)k, (uint32_t)(k >> 32), (uint32_t)traj,
+                                              (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
+                r2n = uniform_open1(o.v2, o.v3);
+                nl = neg_log(uniform_open0(o.v0, o.v1));
+                if (pf < p1) av[e.x] = wave_propensity((uint32_t)e.y, ce, xl);
+                for (int32_t p = pf + kWave; p < p1; p += kWave) {
+                    const int2 e2 = n.dep[p];
+                    av[e2.x] = wave_propensity((uint32_t)e2.y, n.dep_rate[p], xl);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
                 __builtin_amdgcn_wave_barrier();
+            } else {
+                const u32x4 o = philox4x32_10((uint32_t)k, (uint32_t)(k >> 32), (uint32_t)traj,
+                                              (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
+                r2n = uniform_open1(o.v2, o.v3);
+                nl = neg_log(uniform_open0(o.v0, o.v1));
             }
             t = t_next;
             ev = ev + 1;
