@@ -56,6 +56,10 @@ def lib():
         L.orc_covariance.argtypes = [ctypes.POINTER(_Net), ctypes.c_int64, ctypes.c_double, vp, ctypes.c_int32,
                                      ctypes.c_uint64, ctypes.c_uint64, vp, vp, ctypes.c_int]
         L.orc_covariance.restype = ctypes.c_int
+        L.orc_adaptive.argtypes = [ctypes.POINTER(_Net), ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
+                                   ctypes.c_uint64, ctypes.c_int64,
+                                   ctypes.c_int64, vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp, ctypes.c_int]
+        L.orc_adaptive.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -196,3 +200,28 @@ def covariance(model, N, t_end, grid, seed, max_events=2**62, rates=None, thread
     st = lib().orc_covariance(ctypes.byref(net.c), int(N), float(t_end), _ptr(grid), G, int(seed), int(max_events),
                               _ptr(mean), _ptr(cov), int(threads or default_threads()))
     return st, mean, cov
+
+
+def adaptive(model, N, t_end, seed, k, max_events=2**62, rates=None, threads=None):
+    """Adaptive selective memory: Avg-Y over {0} and every distinct event time, Avg-XY over
+    groups of k successive Avg-Y points.  Returns (status, dict(y_time (U,), y_mean (U,S),
+    y_var (U,S), xy_time (P,), xy_mean (P,S), xy_var (P,S), events))."""
+    net = as_net(model, rates)
+    st, r = run(model, N, t_end, np.array([float(t_end)]), seed, max_events=max_events, rates=rates,
+                threads=threads)
+    if st != 0:
+        return st, None
+    cap = r["events"] + 1
+    capxy = (cap + k - 1) // k
+    S = net.S
+    yt, ym, yv = np.zeros(cap), np.zeros((cap, S)), np.zeros((cap, S))
+    xt, xm, xv = np.zeros(capxy), np.zeros((capxy, S)), np.zeros((capxy, S))
+    ny, nxy = np.zeros(1, np.int64), np.zeros(1, np.int64)
+    st = lib().orc_adaptive(ctypes.byref(net.c), int(N), float(t_end), int(seed), int(max_events), int(k),
+                            cap, _ptr(ny), _ptr(yt), _ptr(ym), _ptr(yv), capxy, _ptr(nxy), _ptr(xt), _ptr(xm),
+                            _ptr(xv), int(threads or default_threads()))
+    if st != 0:
+        return st, None
+    U, P = int(ny[0]), int(nxy[0])
+    return st, dict(y_time=yt[:U], y_mean=ym[:U], y_var=yv[:U], xy_time=xt[:P], xy_mean=xm[:P], xy_var=xv[:P],
+                    events=r["events"])

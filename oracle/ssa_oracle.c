@@ -286,7 +286,7 @@ static int check_grid(const double *grid, int32_t G, double t_end)
  *
  * visit(g) is called at each grid crossing with the current state.
  * ---------------------------------------------------------------------------------- */
-typedef struct {
+typedef struct traj_state_ {
     const orc_net *net;
     const rxn_info *info;
     int32_t *x;      /* [S] */
@@ -295,6 +295,9 @@ typedef struct {
     int64_t *nf;     /* [M] fired counts */
     double *A;       /* [M] integrated propensities */
     double t;
+    /* called after every applied event (t and x already updated), or NULL */
+    void (*on_event)(void *ctx, const struct traj_state_ *st);
+    void *ev_ctx;
 } traj_state;
 
 typedef void (*visit_fn)(void *ctx, int g, const traj_state *st, double tg);
@@ -348,6 +351,7 @@ static int run_trajectory(const orc_net *net, const rxn_info *info, uint64_t see
         for (int j = 0; j < M; ++j) st->A[j] = st->A[j] + st->a[j] * tau;
         st->t = t_next;
         events = events + 1;
+        if (st->on_event) st->on_event(st->ev_ctx, st);
     }
     if (events_out) *events_out = events;
     if (draws_out) *draws_out = k;
@@ -357,6 +361,7 @@ static int run_trajectory(const orc_net *net, const rxn_info *info, uint64_t see
 static int alloc_state(const orc_net *net, traj_state *st, const rxn_info *info)
 {
     st->net = net; st->info = info;
+    st->on_event = NULL; st->ev_ctx = NULL;
     st->x = (int32_t *)malloc(sizeof(int32_t) * net->S);
     st->a = (double *)malloc(sizeof(double) * net->M);
     st->Ssum = (double *)malloc(sizeof(double) * net->M);
@@ -792,5 +797,136 @@ int orc_covariance(const orc_net *net, int64_t N, double t_end, const double *gr
             }
     }
     free(info); free(sx); free(sxx);
+    return status;
+}
+
+/* ------------------------------------------------------------------------------------
+ * Adaptive selective memory (Section 3.2.1, Figure 3): the two curves of the figure,
+ * computed for N trajectories without a caller grid.
+ *   Avg-Y, the oversampled time-aligned average: its points are time 0 and every distinct
+ *     time at which some trajectory applies an event (t <= t_end).  At a point every
+ *     trajectory contributes its state after all of its own events up to and including
+ *     that time (sample and hold), so the values are exactly orc_run's on a grid made of
+ *     the point times -- and orc_run computes them.
+ *   Avg-XY, the average along time: consecutive groups of k Avg-Y points, the last group
+ *     possibly shorter (k' points), each give one point
+ *       time = (t_1 + ... + t_k') / k',  mean = (m_1 + ... + m_k') / k',
+ *       var  = (v_1 + ... + v_k') / k',
+ *     every sum taken left to right in binary64, then one division.
+ * The figure fixes the idea, not the arithmetic; the definitions above are this oracle's
+ * reading.  Output sizes: U Avg-Y points, P = ceil(U / k) Avg-XY points; when a capacity is
+ * too small the sizes are still returned, with ORC_INVALID.
+ * ---------------------------------------------------------------------------------- */
+typedef struct { double *t; int64_t n, cap; int fail; } time_log;
+
+static void log_event_time(void *c, const traj_state *st)
+{
+    time_log *lg = (time_log *)c;
+    if (lg->fail) return;
+    if (lg->n == lg->cap) {
+        int64_t nc = lg->cap ? 2 * lg->cap : 4096;
+        double *nt = (double *)realloc(lg->t, sizeof(double) * (size_t)nc);
+        if (!nt) { lg->fail = 1; return; }
+        lg->t = nt;
+        lg->cap = nc;
+    }
+    lg->t[lg->n++] = st->t;
+}
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+int orc_adaptive(const orc_net *net, int64_t N, double t_end, uint64_t seed, uint64_t max_events, int64_t k,
+                 int64_t cap_y, int64_t *n_y, double *y_time, double *y_mean, double *y_var,
+                 int64_t cap_xy, int64_t *n_xy, double *xy_time, double *xy_mean, double *xy_var, int nthreads)
+{
+    int st0 = check_net(net);
+    if (st0) return st0;
+    if (N <= 0 || N > ((int64_t)1 << 30) || k <= 0 || !(t_end >= 0.0) || !isfinite(t_end)) return ORC_INVALID;
+    const int S = net->S, M = net->M;
+    rxn_info *info = (rxn_info *)malloc(sizeof(rxn_info) * M);
+    if (!info) return ORC_NOMEM;
+    build_info(net, info);
+    if (nthreads <= 0) nthreads = 1;
+
+    /* 1. every applied event's time, from every trajectory */
+    time_log all = { NULL, 0, 0, 0 };
+    int status = ORC_OK;
+#pragma omp parallel num_threads(nthreads)
+    {
+        time_log lg = { NULL, 0, 0, 0 };
+        traj_state st;
+        int ok = alloc_state(net, &st, info) == ORC_OK;
+        int my_status = ok ? ORC_OK : ORC_NOMEM;
+        if (ok) { st.on_event = log_event_time; st.ev_ctx = &lg; }
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t i = 0; i < N; ++i) {
+            if (my_status != ORC_OK) continue;
+            int r = run_trajectory(net, info, seed, (uint64_t)i, t_end, NULL, 0, max_events, &st, NULL, NULL,
+                                   NULL, NULL);
+            if (r != ORC_OK) my_status = r;
+            if (lg.fail) my_status = ORC_NOMEM;
+        }
+#pragma omp critical
+        {
+            if (my_status != ORC_OK && status == ORC_OK) status = my_status;
+            if (status == ORC_OK && lg.n > 0) {
+                double *nt = (double *)realloc(all.t, sizeof(double) * (size_t)(all.n + lg.n + 1));
+                if (!nt) {
+                    status = ORC_NOMEM;
+                } else {
+                    all.t = nt;
+                    memcpy(all.t + all.n, lg.t, sizeof(double) * (size_t)lg.n);
+                    all.n += lg.n;
+                }
+            }
+        }
+        if (ok) free_state(&st);
+        free(lg.t);
+    }
+    if (status != ORC_OK) { free(all.t); free(info); return status; }
+
+    /* 2. the Avg-Y points: {0} and the distinct event times, ascending */
+    double *pts = (double *)malloc(sizeof(double) * (size_t)(all.n + 1));
+    if (!pts) { free(all.t); free(info); return ORC_NOMEM; }
+    if (all.n > 0) qsort(all.t, (size_t)all.n, sizeof(double), cmp_double);
+    int64_t U = 0;
+    pts[U++] = 0.0;
+    for (int64_t e = 0; e < all.n; ++e)
+        if (all.t[e] != pts[U - 1]) pts[U++] = all.t[e];
+    free(all.t);
+    const int64_t P = (U + k - 1) / k;
+    if (n_y) *n_y = U;
+    if (n_xy) *n_xy = P;
+    if (U > cap_y || P > cap_xy || U > INT32_MAX) { free(pts); free(info); return ORC_INVALID; }
+
+    /* 3. Avg-Y: the grid reduction at the point times */
+    status = orc_run(net, N, t_end, pts, (int32_t)U, seed, max_events, 0, 0, 1, 1, y_mean, y_var, NULL, NULL, NULL,
+                     nthreads);
+    if (status == ORC_OK) {
+        memcpy(y_time, pts, sizeof(double) * (size_t)U);
+        /* 4. Avg-XY */
+        for (int64_t p = 0; p < P; ++p) {
+            const int64_t u0 = p * k, u1 = (u0 + k < U) ? u0 + k : U;
+            const double kk = (double)(u1 - u0);
+            double ts = 0.0;
+            for (int64_t u = u0; u < u1; ++u) ts = ts + pts[u];
+            xy_time[p] = ts / kk;
+            for (int s = 0; s < S; ++s) {
+                double ms = 0.0, vs = 0.0;
+                for (int64_t u = u0; u < u1; ++u) {
+                    ms = ms + y_mean[(size_t)u * S + s];
+                    vs = vs + y_var[(size_t)u * S + s];
+                }
+                xy_mean[(size_t)p * S + s] = ms / kk;
+                xy_var[(size_t)p * S + s] = vs / kk;
+            }
+        }
+    }
+    free(pts);
+    free(info);
     return status;
 }
