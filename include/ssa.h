@@ -191,6 +191,31 @@ ssa_status ssa_run_cov_device(const ssa_model *model, const double *rates, int64
                               const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events, double *mean,
                               double *cov, void *stream, ssa_stats *stats);
 
+/* Adaptive selective memory (Section 3.2.1, Figure 3): the time alignment without a caller
+ * grid.
+ *   Avg-Y: the points are time 0 and every distinct time at which some trajectory applies an
+ *     event (t <= t_end); at each point every trajectory contributes its state after its
+ *     own events up to that time (sample and hold).  Mean and variance per species from
+ *     exact integer sums, rounded once (the formulas of ssa_run_device).
+ *   Avg-XY: consecutive groups of k Avg-Y points (the last may be shorter, k' points) each
+ *     give one point: time = (t_1 + ... + t_k') / k', and likewise the means and the
+ *     variances (sums left to right in binary64, one division).
+ * Every applied event is logged (time, species, change, previous count), the log is sorted
+ * by time on the device, and the moments are prefix sums over the distinct times.
+ * Arguments: rates [M] device or NULL; k >= 1; outputs device: xy_time [xy_cap],
+ * xy_mean / xy_var [xy_cap*S]; optional Avg-Y y_time [y_cap], y_mean / y_var [y_cap*S]
+ * (NULL to skip).  n_points (host, [2]) receives U (Avg-Y points) and P = ceil(U / k).
+ * With xy_time and y_time both NULL the call only sizes (the simulation still runs).
+ * Capacities below U / P give SSA_E_INVALID with n_points filled.  Scratch: about
+ * 40 bytes per logged species change plus 40 S bytes per Avg-Y point.  Synchronises the
+ * stream.  Needs a SSA_SUM_SEQ model with M <= 32 and at most 4 changed species per
+ * reaction (SSA_E_UNSUPPORTED otherwise), n_traj <= 2^30 and fewer than 2^31 logged
+ * changes. */
+ssa_status ssa_adaptive_device(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
+                               uint64_t seed, uint64_t max_events, int64_t k, double *xy_time, double *xy_mean,
+                               double *xy_var, int64_t xy_cap, double *y_time, double *y_mean, double *y_var,
+                               int64_t y_cap, int64_t *n_points, void *stream, ssa_stats *stats);
+
 /* Quantiles per grid point from a histogram of ssa_run_device (spec as used there):
  * for each q in qs (0 < q <= 1) the rank k = max(1, ceil(q N)) in binary64 and the result
  * is lo + b width for the first bin b whose cumulative count reaches k (with width 1 and

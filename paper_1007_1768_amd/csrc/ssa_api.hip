@@ -3,6 +3,7 @@
 // finalize and error reporting.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
+#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -127,7 +128,7 @@ struct JitKernels {
     hipModule_t module = nullptr;
     hipFunction_t fwd = nullptr, fwd_atomic = nullptr, fwd_hist = nullptr, fwd_slab_hist = nullptr, fwd_jac = nullptr,
                   fwd_cov = nullptr,
-                  rec = nullptr, bwd = nullptr;
+                  rec = nullptr, bwd = nullptr, evt = nullptr;
 };
 
 std::mutex g_jit_mu;
@@ -296,6 +297,7 @@ ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out
     HIP_TRY(hipModuleGetFunction(&k->fwd_jac, k->module, "ssa_jit_fwd_jac"));
     HIP_TRY(hipModuleGetFunction(&k->fwd_cov, k->module, "ssa_jit_fwd_cov"));
     HIP_TRY(hipModuleGetFunction(&k->rec, k->module, "ssa_jit_rec"));
+    HIP_TRY(hipModuleGetFunction(&k->evt, k->module, "ssa_jit_evt"));
     HIP_TRY(hipModuleGetFunction(&k->bwd, k->module, "ssa_jit_bwd"));
     std::lock_guard<std::mutex> lk(g_jit_mu);
     auto ins = g_jit_cache.emplace(key, k);
@@ -612,6 +614,7 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
                          const double *user_rates, StreamScratch &scr) {
     (void)n_items;
     if (m->order == SSA_SUM_BLOCK64) {
+        if (mode == kEvt) return fail(SSA_E_UNSUPPORTED, "the event log runs the sequential sum order");
         HIP_TRY(mode == kRec ? launch_wave<kRec>(m, wl, dev, st, scr) : launch_wave<kBwd>(m, wl, dev, st, scr));
         return SSA_OK;
     }
@@ -619,7 +622,7 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
         std::shared_ptr<JitKernels> k;
         ssa_status s = get_jit(m, dev, k);
         if (s) return s;
-        hipFunction_t f = mode == kRec ? k->rec : k->bwd;
+        hipFunction_t f = mode == kRec ? k->rec : (mode == kEvt ? k->evt : k->bwd);
         HIP_TRY(launch_jit(f, wl, n_items, dev, st));
         return SSA_OK;
     }
@@ -636,8 +639,9 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
     }
     wl.s_rows = m->S;
     wl.m_rows = m->M;
-    hipError_t e = mode == kRec ? launch_generic<kRec, false>(mm, wl, n_items, dev, st)
-                                : launch_generic<kBwd, false>(mm, wl, n_items, dev, st);
+    hipError_t e = mode == kRec   ? launch_generic<kRec, false>(mm, wl, n_items, dev, st)
+                   : mode == kEvt ? launch_generic<kEvt, false>(mm, wl, n_items, dev, st)
+                                  : launch_generic<kBwd, false>(mm, wl, n_items, dev, st);
     HIP_TRY(e);
     return SSA_OK;
 }
@@ -1430,6 +1434,173 @@ ssa_status ssa_record(const ssa_model *m, const double *rates, int64_t traj_begi
     HIP_TRY(hipMemcpy(h, (char *)ctl + 32, sizeof h, hipMemcpyDeviceToHost));
     if (h[2] & kFlagOverflow) return fail(SSA_E_OVERFLOW, "a species count left the int32 range");
     if (h[2] & kFlagEventLimit) return fail(SSA_E_EVENT_LIMIT, "a trajectory reached max_events before t_end");
+    return SSA_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// Adaptive selective memory: event log -> sort by time -> moments at every distinct event
+// time (Avg-Y) -> averages of k successive points (Avg-XY).
+// ------------------------------------------------------------------------------------------
+ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t n_traj, double t_end, uint64_t seed,
+                               uint64_t max_events, int64_t k, double *xy_time, double *xy_mean, double *xy_var,
+                               int64_t xy_cap, double *y_time, double *y_mean, double *y_var, int64_t y_cap,
+                               int64_t *n_points, void *stream, ssa_stats *stats) {
+    if (!m || !n_points) return fail(SSA_E_INVALID, "NULL argument");
+    n_points[0] = n_points[1] = 0;
+    if (n_traj <= 0 || n_traj > ((int64_t)1 << 30)) return fail(SSA_E_INVALID, "need 1 <= n_traj <= 2^30");
+    if (k <= 0) return fail(SSA_E_INVALID, "k must be >= 1");
+    if (!(t_end >= 0.0) || !std::isfinite(t_end)) return fail(SSA_E_INVALID, "t_end must be finite and >= 0");
+    if (m->order != SSA_SUM_SEQ) return fail(SSA_E_UNSUPPORTED, "the event log runs the sequential sum order");
+    if (m->M > kJitMaxReactions)
+        return fail(SSA_E_UNSUPPORTED, "the event log supports at most %d reactions", kJitMaxReactions);
+    if (m->max_changes > kChg)
+        return fail(SSA_E_UNSUPPORTED, "the event log records at most %d changed species per event", kChg);
+    if (xy_time && (!xy_mean || !xy_var)) return fail(SSA_E_INVALID, "Avg-XY outputs need time, mean and variance");
+    if (y_time && (!y_mean || !y_var)) return fail(SSA_E_INVALID, "Avg-Y outputs need time, mean and variance");
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    keep_pool(dev);
+    StreamScratch scr(st);
+    EventPair evp;
+    const bool timed = stats && evp.make();
+
+    // one-point grid at t_end (the event loop reads a grid view; nothing is aligned to it)
+    const double h_grid[1] = {t_end};
+    void *d_grid = nullptr, *ctl = nullptr, *cur = nullptr;
+    HIP_TRY(scr.alloc(&d_grid, sizeof(double)));
+    HIP_TRY(scr.alloc(&ctl, 64 + sizeof(GridInfo)));
+    HIP_TRY(scr.alloc(&cur, sizeof(unsigned long long)));
+    HIP_TRY(hipMemcpyAsync(d_grid, h_grid, sizeof(double), hipMemcpyHostToDevice, st));
+    const GridInfo hgi = host_grid_info(h_grid, 1, t_end);
+    HIP_TRY(hipMemcpyAsync((char *)ctl + 64, &hgi, sizeof hgi, hipMemcpyHostToDevice, st));
+    NetDev n = base_net(m, rates, n_traj, t_end, (const double *)d_grid, 1, seed, max_events);
+    n.ginfo = (const GridInfo *)((char *)ctl + 64);
+    n.ev_cursor = (unsigned long long *)cur;
+    WorkList wl;
+    std::memset(&wl, 0, sizeof wl);
+    wl.range_begin = 0;
+    wl.range_end = n_traj;
+    const int64_t n_items = (n_traj + kChunk - 1) / kChunk;
+    if (n_items > INT32_MAX) return fail(SSA_E_INVALID, "n_traj too large");
+    wl.n_items = (int32_t)n_items;
+    wl.counter = (unsigned int *)ctl;
+    wl.stats = (unsigned long long *)((char *)ctl + 32);
+
+    // pass 1 counts the records, pass 2 writes them (same trajectories, same order of draws)
+    if (timed) HIP_TRY(hipEventRecord(evp.a, st));
+    HIP_TRY(launch_zero(ctl, 64, st));
+    HIP_TRY(launch_zero(cur, sizeof(unsigned long long), st));
+    wl.net0 = n;
+    ssa_status s = launch_single(kEvt, m, wl, n_items, dev, st, rates, scr);
+    if (s) return s;
+    unsigned long long R = 0, h[3] = {0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(&R, cur, sizeof R, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(h, (char *)ctl + 32, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h[2] & kFlagOverflow) return fail(SSA_E_OVERFLOW, "a species count left the int32 range");
+    if (h[2] & kFlagEventLimit) return fail(SSA_E_EVENT_LIMIT, "a trajectory reached max_events before t_end");
+    if (R >= (unsigned long long)INT32_MAX) return fail(SSA_E_UNSUPPORTED, "more than 2^31 - 1 event records");
+    const int32_t nR = (int32_t)R;
+    void *k0 = nullptr, *k1 = nullptr, *v0 = nullptr, *v1 = nullptr, *stf = nullptr, *rk = nullptr;
+    const size_t rb = sizeof(unsigned long long) * std::max<size_t>(R, 1);
+    HIP_TRY(scr.alloc(&k0, rb));
+    HIP_TRY(scr.alloc(&k1, rb));
+    HIP_TRY(scr.alloc(&v0, rb));
+    HIP_TRY(scr.alloc(&v1, rb));
+    HIP_TRY(scr.alloc(&stf, sizeof(int32_t) * std::max<size_t>(R, 1)));
+    HIP_TRY(scr.alloc(&rk, sizeof(int32_t) * std::max<size_t>(R, 1)));
+    if (R > 0) {
+        n.ev_key = (unsigned long long *)k0;
+        n.ev_val = (unsigned long long *)v0;
+        n.ev_cap = (int64_t)R;
+        wl.net0 = n;
+        HIP_TRY(launch_zero(ctl, 64, st));
+        HIP_TRY(launch_zero(cur, sizeof(unsigned long long), st));
+        s = launch_single(kEvt, m, wl, n_items, dev, st, rates, scr);
+        if (s) return s;
+        size_t tb = 0;
+        HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (const unsigned long long *)k0,
+                                                   (unsigned long long *)k1, (const unsigned long long *)v0,
+                                                   (unsigned long long *)v1, nR, 0, 64, st));
+        size_t tb2 = 0;
+        HIP_TRY(hipcub::DeviceScan::InclusiveSum(nullptr, tb2, (const int32_t *)stf, (int32_t *)rk, nR, st));
+        void *tmp = nullptr;
+        HIP_TRY(scr.alloc(&tmp, std::max(tb, tb2)));
+        tb = std::max(tb, tb2);
+        HIP_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tb, (const unsigned long long *)k0, (unsigned long long *)k1,
+                                                   (const unsigned long long *)v0, (unsigned long long *)v1, nR, 0, 64,
+                                                   st));
+        const unsigned gb = (unsigned)std::min<int64_t>(((int64_t)R + 255) / 256, 65535);
+        hipLaunchKernelGGL(evt_start_kernel, dim3(gb), dim3(256), 0, st, (const unsigned long long *)k1,
+                           (int64_t)R, (int32_t *)stf);
+        HIP_TRY(hipGetLastError());
+        tb2 = tb;
+        HIP_TRY(hipcub::DeviceScan::InclusiveSum(tmp, tb2, (const int32_t *)stf, (int32_t *)rk, nR, st));
+    }
+    // sizes: U = distinct event times (+ the point at time 0 unless an event happened there)
+    int32_t n_distinct = 0;
+    unsigned long long first_key = 0, h2[3] = {0, 0, 0};
+    if (R > 0) {
+        HIP_TRY(hipMemcpyAsync(&n_distinct, (int32_t *)rk + (R - 1), sizeof n_distinct, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&first_key, k1, sizeof first_key, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(h2, (char *)ctl + 32, sizeof h2, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if ((h2[2] & kFlagRecordsFull) || h2[0] != h[0])
+            return fail(SSA_E_DEVICE, "the second pass logged a different number of events");
+    }
+    const int32_t off = (R > 0 && first_key == 0ull) ? 0 : 1;
+    const int64_t U = (int64_t)n_distinct + off;
+    const int64_t P = (U + k - 1) / k;
+    n_points[0] = U;
+    n_points[1] = P;
+    if (U > INT32_MAX) return fail(SSA_E_UNSUPPORTED, "more than 2^31 - 1 Avg-Y points");
+    if (!xy_time && !y_time) return SSA_OK;   // size query
+    if (xy_time && xy_cap < P) return fail(SSA_E_INVALID, "Avg-XY needs %lld points (capacity %lld)", (long long)P,
+                                           (long long)xy_cap);
+    if (y_time && y_cap < U)
+        return fail(SSA_E_INVALID, "Avg-Y needs %lld points (capacity %lld)", (long long)U, (long long)y_cap);
+
+    // Avg-Y: exact difference sums per point, prefix over the points, moments
+    const int32_t S = m->S;
+    void *D = nullptr, *Dhi = nullptr, *yt = y_time, *ym = y_mean, *yv = y_var;
+    HIP_TRY(scr.alloc(&D, sizeof(unsigned long long) * (size_t)U * S * 2));
+    HIP_TRY(scr.alloc(&Dhi, sizeof(unsigned long long) * (size_t)U * S));
+    if (!y_time) {
+        HIP_TRY(scr.alloc(&yt, sizeof(double) * (size_t)U));
+        HIP_TRY(scr.alloc(&ym, sizeof(double) * (size_t)U * S));
+        HIP_TRY(scr.alloc(&yv, sizeof(double) * (size_t)U * S));
+    }
+    HIP_TRY(launch_zero(D, sizeof(unsigned long long) * (size_t)U * S * 2, st));
+    HIP_TRY(launch_zero(Dhi, sizeof(unsigned long long) * (size_t)U * S, st));
+    HIP_TRY(launch_zero(yt, sizeof(double), st));   // time 0 (overwritten if an event happened there)
+    if (R > 0) {
+        const unsigned gb = (unsigned)std::min<int64_t>(((int64_t)R + 255) / 256, 65535);
+        hipLaunchKernelGGL(evt_diff_kernel, dim3(gb), dim3(256), 0, st, (const unsigned long long *)k1,
+                           (const unsigned long long *)v1, (const int32_t *)stf, (const int32_t *)rk, (int64_t)R, off,
+                           S, (unsigned long long *)D, (unsigned long long *)Dhi, (double *)yt);
+        HIP_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(moment_final_kernel, dim3(S), dim3(1024), 0, st, (const unsigned long long *)D,
+                       (const unsigned long long *)Dhi, (int32_t)U, S, (const int32_t *)m->d_x0, n_traj, (double *)ym,
+                       (double *)yv, (int64_t *)nullptr);
+    HIP_TRY(hipGetLastError());
+    if (xy_time) {
+        const int64_t work = P * ((int64_t)S + 1);
+        const unsigned gb = (unsigned)std::min<int64_t>((work + 255) / 256, 65535);
+        hipLaunchKernelGGL(xy_kernel, dim3(gb), dim3(256), 0, st, (const double *)yt, (const double *)ym,
+                           (const double *)yv, U, S, k, P, xy_time, xy_mean, xy_var);
+        HIP_TRY(hipGetLastError());
+    }
+    if (timed) HIP_TRY(hipEventRecord(evp.b, st));
+    if (stats) {
+        HIP_TRY(hipStreamSynchronize(st));
+        stats->events = h[0];
+        stats->max_steps = h[1];
+        stats->flags = (uint32_t)h[2];
+        stats->kernel_ms = 0.0f;
+        if (timed) (void)hipEventElapsedTime(&stats->kernel_ms, evp.a, evp.b);
+    }
     return SSA_OK;
 }
 

@@ -121,6 +121,11 @@ extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_rec(ssa::WorkL
     ssa::sim_loop<ssa::kRec, ssa_gen::Net::M, false>(wl, p);
 }
 
+extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_evt(ssa::WorkList wl) {
+    ssa::RegPolicy p;
+    ssa::sim_loop<ssa::kEvt, ssa_gen::Net::M, false>(wl, p);
+}
+
 extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_bwd(ssa::WorkList wl) {
     ssa::RegPolicy p;
     ssa::sim_loop<ssa::kBwd, ssa_gen::Net::M, false>(wl, p);

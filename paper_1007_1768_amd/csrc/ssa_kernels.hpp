@@ -22,7 +22,6 @@
 
 namespace ssa {
 
-constexpr int kChg = 4;
 constexpr int32_t kRowBits = 12;
 constexpr int kPadReactions = 32;    // generic tables are padded to a multiple of this
 
@@ -595,6 +594,73 @@ __global__ void scale_kernel(const double *__restrict__ in, int32_t M, double sc
 __global__ void zero_kernel(unsigned long long *__restrict__ p, size_t n_words) {
     for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += (size_t)gridDim.x * blockDim.x)
         p[i] = 0ull;
+}
+
+
+// ---------------------------------------------------------------------------------------
+// Adaptive selective memory (Section 3.2.1, Figure 3) from the time-sorted event log:
+// Avg-Y's points are time 0 and the distinct event times; a record starts a point when its
+// time differs from the previous record's.
+// ---------------------------------------------------------------------------------------
+__global__ void evt_start_kernel(const unsigned long long *__restrict__ key, int64_t R, int32_t *__restrict__ start) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x)
+        start[r] = (r == 0 || key[r] != key[r - 1]) ? 1 : 0;
+}
+
+// Each record's moment differences at its point u = (rank of its time among the distinct
+// times, from 1) - 1 + off (off = 1 when no event happens at time 0, whose point then
+// holds the initial state), in the forward kernels' split (whole (2x+nu)nu below 2^24,
+// else its low 24 bits and the rest >> 24); the first record of a point writes its time.
+__global__ void evt_diff_kernel(const unsigned long long *__restrict__ key, const unsigned long long *__restrict__ val,
+                                const int32_t *__restrict__ start, const int32_t *__restrict__ rank1, int64_t R,
+                                int32_t off, int32_t S, unsigned long long *__restrict__ D,
+                                unsigned long long *__restrict__ Dhi, double *__restrict__ y_time) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t u = (int64_t)rank1[r] - 1 + off;
+        const unsigned long long v = val[r];
+        const int32_t s = (int32_t)(v & 0xfffu);
+        const int32_t dl = ((int32_t)(((uint32_t)(v >> 12) & 0xfffffu) << 12)) >> 12;
+        const int32_t xo = (int32_t)(uint32_t)(v >> 32);
+        unsigned long long *dd = D + ((size_t)u * S + s) * 2;
+        atomicAdd(dd, (unsigned long long)(long long)dl);
+        const long long d2 = (2ll * xo + dl) * (long long)dl;
+        if (d2 > -kSmallD2 && d2 < kSmallD2) {
+            atomicAdd(dd + 1, (unsigned long long)d2);
+        } else {
+            atomicAdd(dd + 1, (unsigned long long)(d2 & ((1ll << 24) - 1)));
+            atomicAdd(Dhi + (size_t)u * S + s, (unsigned long long)(d2 >> 24));
+        }
+        if (start[r]) y_time[u] = __longlong_as_double((long long)key[r]);
+    }
+}
+
+// Avg-XY: groups of k successive Avg-Y points (the last one may be shorter); one thread per
+// (group, column), column S being the time.  Each sum runs left to right, then one division
+// by the group's size.
+__global__ void xy_kernel(const double *__restrict__ y_time, const double *__restrict__ y_mean,
+                          const double *__restrict__ y_var, int64_t U, int32_t S, int64_t k, int64_t P,
+                          double *__restrict__ xy_time, double *__restrict__ xy_mean, double *__restrict__ xy_var) {
+    const int64_t cols = (int64_t)S + 1;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P * cols;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t p = i / cols;
+        const int32_t c = (int32_t)(i - p * cols);
+        const int64_t u0 = p * k, u1 = min(u0 + k, U);
+        const double kk = (double)(u1 - u0);
+        if (c == S) {
+            double ts = 0.0;
+            for (int64_t u = u0; u < u1; ++u) ts = ts + y_time[u];
+            xy_time[p] = ts / kk;
+        } else {
+            double ms = 0.0, vs = 0.0;
+            for (int64_t u = u0; u < u1; ++u) {
+                ms = ms + y_mean[(size_t)u * S + c];
+                vs = vs + y_var[(size_t)u * S + c];
+            }
+            xy_mean[(size_t)p * S + c] = ms / kk;
+            xy_var[(size_t)p * S + c] = vs / kk;
+        }
+    }
 }
 
 }  // namespace ssa

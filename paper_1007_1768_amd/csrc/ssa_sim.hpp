@@ -53,13 +53,14 @@ namespace ssa {
 constexpr int kBlock = 256;
 constexpr int kWave = 64;
 constexpr int kChunk = 64;         // trajectory indices per work item
+constexpr int kChg = 4;            // changed species per reaction in the packed tables and the event log
 constexpr int kSmallD2 = 1 << 24;  // |(2x+nu)nu| below this goes whole to the low accumulator;
                                    // larger values add their low 24 bits there and value >> 24
                                    // to the high accumulator, so low words grow by < 2^24 per event
 
-enum Mode : int { kFwd = 0, kRec = 1, kBwd = 2 };
+enum Mode : int { kFwd = 0, kRec = 1, kBwd = 2, kEvt = 3 };
 
-enum Flags : uint32_t { kFlagOverflow = 1u, kFlagEventLimit = 2u };
+enum Flags : uint32_t { kFlagOverflow = 1u, kFlagEventLimit = 2u, kFlagRecordsFull = 4u };
 
 // Time grid description.  A grid with t_g = fl(fl(T g) / D) for every g (the uniform grid
 // of the workloads) is "uniform": its points are recomputed exactly from (T, D) instead of
@@ -108,7 +109,19 @@ struct NetDev {
     // backward: prefix rows [G+1] (see PrefixRow), per-trajectory rows [n_traj][M]
     const void *bp;
     double *gtraj;
+    // event log: one record per changed species of every applied event, appended at
+    // ev_cursor (key: the event time's bits; value: packed species, change, old count);
+    // with ev_key == nullptr only the cursor counts
+    unsigned long long *ev_key, *ev_val, *ev_cursor;
+    int64_t ev_cap;
 };
+
+// Event-log record value: species (12 bits) | change (20-bit two's complement) << 12 |
+// count before the event << 32.
+__host__ __device__ __forceinline__ unsigned long long ev_pack(int32_t s, int32_t dl, int32_t xo) {
+    return ((unsigned long long)(uint32_t)xo << 32) | ((unsigned long long)((uint32_t)dl & 0xfffffu) << 12) |
+           (unsigned long long)(uint32_t)s;
+}
 
 // Work description.  A single-network launch passes its network by value (net0) and the
 // trajectory range [range_begin, range_end) cut into chunks of kChunk; a batched launch
@@ -266,7 +279,7 @@ struct GridView {
 // Record and backward passes: lanes are refilled as soon as their trajectory ends.
 template <int MODE, int MM, bool BATCH, class Policy>
 __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
-    static_assert(MODE != kFwd && MM > 0, "record and backward need the per-reaction registers");
+    static_assert(MODE != kFwd && MM > 0, "record, backward and the event log need the per-reaction registers");
     constexpr int MR = MM > 0 ? MM : 1;
     const uint32_t lane = __lane_id();
 
@@ -447,7 +460,22 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
                     sel = min(sel, M - 1);   // a0 > 0 guarantees some a_j > 0; keeps the index in range
                 }
             }
-            p.apply(n, sel, [&](int32_t, int32_t, int32_t xn) { ovf |= (uint32_t)xn; });
+            // event log: the changed species of this event (at most kChg), kept in registers
+            int32_t nrec = 0;
+            int32_t rs[kChg], rd[kChg], rx[kChg];
+            p.apply(n, sel, [&](int32_t sp, int32_t xo, int32_t xn) {
+                ovf |= (uint32_t)xn;
+                if (MODE == kEvt) {
+#pragma unroll
+                    for (int i = 0; i < kChg; ++i)
+                        if (nrec == i) {
+                            rs[i] = sp;
+                            rd[i] = xn - xo;
+                            rx[i] = xo;
+                        }
+                    ++nrec;
+                }
+            });
             if ((int32_t)ovf < 0) {
                 flags |= kFlagOverflow;
                 finish = true;
@@ -462,6 +490,37 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
                 if (MODE == kBwd) {
 #pragma unroll
                     for (int j = 0; j < MM; ++j) B[j] = B[j] + ((j == sel ? 1.0 : 0.0) - a[j] * tau);
+                }
+                if (MODE == kEvt) {
+                    // one cursor bump per wave for the records of all its lanes
+                    nrec = min(nrec, kChg);
+                    uint32_t before = 0, total = 0;
+#pragma unroll
+                    for (int i = 0; i < kChg; ++i) {
+                        const uint64_t m = __ballot(nrec > i);
+                        before += __popcll(m & lanemask_lt());
+                        total += __popcll(m);
+                    }
+                    const int32_t leader = __ffsll((unsigned long long)__ballot(1)) - 1;
+                    unsigned long long base = 0;
+                    if ((int32_t)lane == leader) base = atomicAdd(n.ev_cursor, (unsigned long long)total);
+                    const uint32_t blo = (uint32_t)__shfl((int)(uint32_t)base, leader);
+                    const uint32_t bhi = (uint32_t)__shfl((int)(uint32_t)(base >> 32), leader);
+                    const int64_t at = (int64_t)(((unsigned long long)bhi << 32) | blo) + before;
+                    if (n.ev_key) {
+                        const unsigned long long key = (unsigned long long)__double_as_longlong(t_next);
+#pragma unroll
+                        for (int i = 0; i < kChg; ++i) {
+                            if (i < nrec) {
+                                if (at + i < n.ev_cap) {
+                                    n.ev_key[at + i] = key;
+                                    n.ev_val[at + i] = ev_pack(rs[i], rd[i], rx[i]);
+                                } else {
+                                    flags |= kFlagRecordsFull;
+                                }
+                            }
+                        }
+                    }
                 }
                 t = t_next;
                 ev = ev + 1;

@@ -20,7 +20,7 @@ _NAMES = {1: "SSA_E_INVALID", 2: "SSA_E_NOMEM", 3: "SSA_E_DEVICE", 4: "SSA_E_OVE
 
 EXPORTS = ["ssa_model_create", "ssa_model_destroy", "ssa_run", "ssa_run_device", "ssa_backward_device",
            "ssa_run_jacobian_device", "ssa_jacobian_vjp", "ssa_autotune_forward", "ssa_run_cov_device",
-           "ssa_hist_quantiles",
+           "ssa_hist_quantiles", "ssa_adaptive_device",
            "ssa_record", "ssa_batch_create", "ssa_batch_run", "ssa_batch_destroy", "ssa_last_error"]
 
 
@@ -66,6 +66,7 @@ def load(path=None):
     L.ssa_autotune_forward.argtypes = [vp, vp, i64, dbl, vp, i32, u64, vp, vp]
     L.ssa_run_cov_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp]
     L.ssa_hist_quantiles.argtypes = [vp, i32, vp, i64, vp, i32, vp, vp]
+    L.ssa_adaptive_device.argtypes = [vp, vp, i64, dbl, u64, u64, i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
     L.ssa_run_jacobian_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
     L.ssa_jacobian_vjp.argtypes = [vp, vp, i32, i32, i32, vp, vp]
     L.ssa_record.argtypes = [vp, vp, i64, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
@@ -229,6 +230,35 @@ def run_cov_device(model, n_traj, t_end, grid, seed, rates=None, max_events=0, s
                                      int(max_events), _tp(mean), _tp(cov), _stream(stream),
                                      ctypes.byref(st) if st is not None else None))
     return mean, cov, (st.as_dict() if st is not None else None)
+
+
+def adaptive_device(model, n_traj, t_end, seed, k, rates=None, max_events=0, stream=None, with_y=False,
+                    with_stats=False, device="cuda:0"):
+    """Adaptive selective memory (ssa_adaptive_device): Avg-XY points (time (P,), mean and
+    variance (P, S)) and, with with_y, the Avg-Y points (time (U,), mean, var (U, S)).
+    Sizes come from a first call that only counts (the simulation runs twice)."""
+    import torch
+    dev = rates.device if rates is not None else torch.device(device)
+    L = load()
+    npts = (ctypes.c_int64 * 2)()
+    _check(L.ssa_adaptive_device(model.handle, _tp(rates), int(n_traj), float(t_end), int(seed), int(max_events),
+                                 int(k), None, None, None, 0, None, None, None, 0, npts, _stream(stream), None))
+    U, P = int(npts[0]), int(npts[1])
+    f64 = dict(dtype=torch.float64, device=dev)
+    xt, xm, xv = torch.empty(P, **f64), torch.empty((P, model.S), **f64), torch.empty((P, model.S), **f64)
+    yt = ym = yv = None
+    if with_y:
+        yt, ym, yv = torch.empty(U, **f64), torch.empty((U, model.S), **f64), torch.empty((U, model.S), **f64)
+    st = Stats() if with_stats else None
+    _check(L.ssa_adaptive_device(model.handle, _tp(rates), int(n_traj), float(t_end), int(seed), int(max_events),
+                                 int(k), _tp(xt), _tp(xm), _tp(xv), P, _tp(yt), _tp(ym), _tp(yv), U if with_y else 0,
+                                 npts, _stream(stream), ctypes.byref(st) if st is not None else None))
+    out = dict(xy_time=xt, xy_mean=xm, xy_var=xv)
+    if with_y:
+        out.update(y_time=yt, y_mean=ym, y_var=yv)
+    if st is not None:
+        out["stats"] = st.as_dict()
+    return out
 
 
 def hist_quantiles(hist, spec, n_traj, qs, stream=None):
