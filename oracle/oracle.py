@@ -60,6 +60,10 @@ def lib():
                                    ctypes.c_uint64, ctypes.c_int64,
                                    ctypes.c_int64, vp, vp, vp, vp, ctypes.c_int64, vp, vp, vp, vp, ctypes.c_int]
         L.orc_adaptive.restype = ctypes.c_int
+        L.orc_adaptive_groups.argtypes = [ctypes.POINTER(_Net), ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
+                                          ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, vp, ctypes.c_int64, vp, vp,
+                                          vp, vp, vp, ctypes.c_int]
+        L.orc_adaptive_groups.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -225,3 +229,26 @@ def adaptive(model, N, t_end, seed, k, max_events=2**62, rates=None, threads=Non
     U, P = int(ny[0]), int(nxy[0])
     return st, dict(y_time=yt[:U], y_mean=ym[:U], y_var=yv[:U], xy_time=xt[:P], xy_mean=xm[:P], xy_var=xv[:P],
                     events=r["events"])
+
+
+def adaptive_groups(model, N, t_end, seed, k, groups, max_events=2**62, rates=None, threads=None):
+    """All Avg-Y point times and the Avg-XY points of the chosen groups only (each from the
+    grid reduction at its own points).  Returns (status, dict(y_time (U,), xy_time (n,),
+    xy_mean (n,S), xy_var (n,S), events))."""
+    net = as_net(model, rates)
+    st, r = run(model, N, t_end, np.array([float(t_end)]), seed, max_events=max_events, rates=rates,
+                threads=threads)
+    if st != 0:
+        return st, None
+    cap = r["events"] + 1
+    g = np.ascontiguousarray(groups, dtype=np.int64)
+    S = net.S
+    yt = np.zeros(cap)
+    gt, gm, gv = np.zeros(len(g)), np.zeros((len(g), S)), np.zeros((len(g), S))
+    ny = np.zeros(1, np.int64)
+    st = lib().orc_adaptive_groups(ctypes.byref(net.c), int(N), float(t_end), int(seed), int(max_events), int(k),
+                                   len(g), _ptr(g), cap, _ptr(ny), _ptr(yt), _ptr(gt), _ptr(gm), _ptr(gv),
+                                   int(threads or default_threads()))
+    if st != 0:
+        return st, None
+    return st, dict(y_time=yt[:int(ny[0])], xy_time=gt, xy_mean=gm, xy_var=gv, events=r["events"])

@@ -839,20 +839,11 @@ static int cmp_double(const void *a, const void *b)
     return (x > y) - (x < y);
 }
 
-int orc_adaptive(const orc_net *net, int64_t N, double t_end, uint64_t seed, uint64_t max_events, int64_t k,
-                 int64_t cap_y, int64_t *n_y, double *y_time, double *y_mean, double *y_var,
-                 int64_t cap_xy, int64_t *n_xy, double *xy_time, double *xy_mean, double *xy_var, int nthreads)
+/* The Avg-Y points of N trajectories: {0} and every distinct applied-event time, ascending.
+ * *pts is malloc'ed (caller frees); *U its length. */
+static int union_times(const orc_net *net, const rxn_info *info, int64_t N, double t_end, uint64_t seed,
+                       uint64_t max_events, int nthreads, double **pts_out, int64_t *U_out)
 {
-    int st0 = check_net(net);
-    if (st0) return st0;
-    if (N <= 0 || N > ((int64_t)1 << 30) || k <= 0 || !(t_end >= 0.0) || !isfinite(t_end)) return ORC_INVALID;
-    const int S = net->S, M = net->M;
-    rxn_info *info = (rxn_info *)malloc(sizeof(rxn_info) * M);
-    if (!info) return ORC_NOMEM;
-    build_info(net, info);
-    if (nthreads <= 0) nthreads = 1;
-
-    /* 1. every applied event's time, from every trajectory */
     time_log all = { NULL, 0, 0, 0 };
     int status = ORC_OK;
 #pragma omp parallel num_threads(nthreads)
@@ -887,44 +878,112 @@ int orc_adaptive(const orc_net *net, int64_t N, double t_end, uint64_t seed, uin
         if (ok) free_state(&st);
         free(lg.t);
     }
-    if (status != ORC_OK) { free(all.t); free(info); return status; }
-
-    /* 2. the Avg-Y points: {0} and the distinct event times, ascending */
+    if (status != ORC_OK) { free(all.t); return status; }
     double *pts = (double *)malloc(sizeof(double) * (size_t)(all.n + 1));
-    if (!pts) { free(all.t); free(info); return ORC_NOMEM; }
+    if (!pts) { free(all.t); return ORC_NOMEM; }
     if (all.n > 0) qsort(all.t, (size_t)all.n, sizeof(double), cmp_double);
     int64_t U = 0;
     pts[U++] = 0.0;
     for (int64_t e = 0; e < all.n; ++e)
         if (all.t[e] != pts[U - 1]) pts[U++] = all.t[e];
     free(all.t);
+    *pts_out = pts;
+    *U_out = U;
+    return ORC_OK;
+}
+
+/* One Avg-XY point from the Avg-Y values of its group (m, v: [k'][S], t: [k']). */
+static void xy_point(const double *t, const double *m, const double *v, int64_t kk, int S,
+                     double *xt, double *xm, double *xv)
+{
+    double ts = 0.0;
+    for (int64_t u = 0; u < kk; ++u) ts = ts + t[u];
+    *xt = ts / (double)kk;
+    for (int s = 0; s < S; ++s) {
+        double ms = 0.0, vs = 0.0;
+        for (int64_t u = 0; u < kk; ++u) {
+            ms = ms + m[(size_t)u * S + s];
+            vs = vs + v[(size_t)u * S + s];
+        }
+        xm[s] = ms / (double)kk;
+        xv[s] = vs / (double)kk;
+    }
+}
+
+int orc_adaptive(const orc_net *net, int64_t N, double t_end, uint64_t seed, uint64_t max_events, int64_t k,
+                 int64_t cap_y, int64_t *n_y, double *y_time, double *y_mean, double *y_var,
+                 int64_t cap_xy, int64_t *n_xy, double *xy_time, double *xy_mean, double *xy_var, int nthreads)
+{
+    int st0 = check_net(net);
+    if (st0) return st0;
+    if (N <= 0 || N > ((int64_t)1 << 30) || k <= 0 || !(t_end >= 0.0) || !isfinite(t_end)) return ORC_INVALID;
+    const int S = net->S, M = net->M;
+    rxn_info *info = (rxn_info *)malloc(sizeof(rxn_info) * M);
+    if (!info) return ORC_NOMEM;
+    build_info(net, info);
+    if (nthreads <= 0) nthreads = 1;
+    double *pts = NULL;
+    int64_t U = 0;
+    int status = union_times(net, info, N, t_end, seed, max_events, nthreads, &pts, &U);
+    if (status != ORC_OK) { free(info); return status; }
     const int64_t P = (U + k - 1) / k;
     if (n_y) *n_y = U;
     if (n_xy) *n_xy = P;
     if (U > cap_y || P > cap_xy || U > INT32_MAX) { free(pts); free(info); return ORC_INVALID; }
-
-    /* 3. Avg-Y: the grid reduction at the point times */
+    /* Avg-Y: the grid reduction at the point times */
     status = orc_run(net, N, t_end, pts, (int32_t)U, seed, max_events, 0, 0, 1, 1, y_mean, y_var, NULL, NULL, NULL,
                      nthreads);
     if (status == ORC_OK) {
         memcpy(y_time, pts, sizeof(double) * (size_t)U);
-        /* 4. Avg-XY */
         for (int64_t p = 0; p < P; ++p) {
             const int64_t u0 = p * k, u1 = (u0 + k < U) ? u0 + k : U;
-            const double kk = (double)(u1 - u0);
-            double ts = 0.0;
-            for (int64_t u = u0; u < u1; ++u) ts = ts + pts[u];
-            xy_time[p] = ts / kk;
-            for (int s = 0; s < S; ++s) {
-                double ms = 0.0, vs = 0.0;
-                for (int64_t u = u0; u < u1; ++u) {
-                    ms = ms + y_mean[(size_t)u * S + s];
-                    vs = vs + y_var[(size_t)u * S + s];
-                }
-                xy_mean[(size_t)p * S + s] = ms / kk;
-                xy_var[(size_t)p * S + s] = vs / kk;
-            }
+            xy_point(pts + u0, y_mean + (size_t)u0 * S, y_var + (size_t)u0 * S, u1 - u0, S, xy_time + p,
+                     xy_mean + (size_t)p * S, xy_var + (size_t)p * S);
         }
+    }
+    free(pts);
+    free(info);
+    return status;
+}
+
+/* The same reduction for chosen Avg-XY groups only (for runs whose Avg-Y is too long to
+ * evaluate whole): all Avg-Y point times (times [cap], U), and for each group in groups
+ * [n_groups] its Avg-XY point (g_time [n], g_mean / g_var [n][S]) from the grid reduction
+ * at that group's points alone. */
+int orc_adaptive_groups(const orc_net *net, int64_t N, double t_end, uint64_t seed, uint64_t max_events, int64_t k,
+                        int64_t n_groups, const int64_t *groups, int64_t cap, int64_t *n_y, double *times,
+                        double *g_time, double *g_mean, double *g_var, int nthreads)
+{
+    int st0 = check_net(net);
+    if (st0) return st0;
+    if (N <= 0 || N > ((int64_t)1 << 30) || k <= 0 || !(t_end >= 0.0) || !isfinite(t_end)) return ORC_INVALID;
+    const int S = net->S, M = net->M;
+    rxn_info *info = (rxn_info *)malloc(sizeof(rxn_info) * M);
+    if (!info) return ORC_NOMEM;
+    build_info(net, info);
+    if (nthreads <= 0) nthreads = 1;
+    double *pts = NULL;
+    int64_t U = 0;
+    int status = union_times(net, info, N, t_end, seed, max_events, nthreads, &pts, &U);
+    if (status != ORC_OK) { free(info); return status; }
+    if (n_y) *n_y = U;
+    const int64_t P = (U + k - 1) / k;
+    if (U > cap) { free(pts); free(info); return ORC_INVALID; }
+    memcpy(times, pts, sizeof(double) * (size_t)U);
+    for (int64_t q = 0; q < n_groups && status == ORC_OK; ++q) {
+        const int64_t p = groups[q];
+        if (p < 0 || p >= P || k > INT32_MAX) { status = ORC_INVALID; break; }
+        const int64_t u0 = p * k, u1 = (u0 + k < U) ? u0 + k : U;
+        const int64_t kk = u1 - u0;
+        double *m = (double *)malloc(sizeof(double) * (size_t)kk * S);
+        double *v = (double *)malloc(sizeof(double) * (size_t)kk * S);
+        if (!m || !v) { free(m); free(v); status = ORC_NOMEM; break; }
+        status = orc_run(net, N, t_end, pts + u0, (int32_t)kk, seed, max_events, 0, 0, 1, 1, m, v, NULL, NULL, NULL,
+                         nthreads);
+        if (status == ORC_OK)
+            xy_point(pts + u0, m, v, kk, S, g_time + q, g_mean + (size_t)q * S, g_var + (size_t)q * S);
+        free(m);
+        free(v);
     }
     free(pts);
     free(info);

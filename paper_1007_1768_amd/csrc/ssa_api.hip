@@ -1581,10 +1581,22 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
                            S, (unsigned long long *)D, (unsigned long long *)Dhi, (double *)yt);
         HIP_TRY(hipGetLastError());
     }
-    hipLaunchKernelGGL(moment_final_kernel, dim3(S), dim3(1024), 0, st, (const unsigned long long *)D,
-                       (const unsigned long long *)Dhi, (int32_t)U, S, (const int32_t *)m->d_x0, n_traj, (double *)ym,
-                       (double *)yv, (int64_t *)nullptr);
-    HIP_TRY(hipGetLastError());
+    {
+        // exact prefix over the points in chunks, then the moments
+        const int64_t n_chunks = (U + kFinChunk - 1) / kFinChunk;
+        if (n_chunks > 65535 * 2048ll) return fail(SSA_E_UNSUPPORTED, "too many Avg-Y points");
+        void *T = nullptr;
+        HIP_TRY(scr.alloc(&T, sizeof(long long) * (size_t)n_chunks * S * 3));
+        hipLaunchKernelGGL(chunk_total_kernel, dim3((unsigned)n_chunks, (unsigned)S), dim3(256), 0, st,
+                           (const unsigned long long *)D, (const unsigned long long *)Dhi, U, S, (long long *)T);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(chunk_scan_kernel, dim3((unsigned)S), dim3(1024), 0, st, (long long *)T, n_chunks, S);
+        HIP_TRY(hipGetLastError());
+        hipLaunchKernelGGL(chunk_final_kernel, dim3((unsigned)n_chunks, (unsigned)S), dim3(256), 0, st,
+                           (const unsigned long long *)D, (const unsigned long long *)Dhi, U, S, (const long long *)T,
+                           (const int32_t *)m->d_x0, n_traj, (double *)ym, (double *)yv);
+        HIP_TRY(hipGetLastError());
+    }
     if (xy_time) {
         const int64_t work = P * ((int64_t)S + 1);
         const unsigned gb = (unsigned)std::min<int64_t>((work + 255) / 256, 65535);

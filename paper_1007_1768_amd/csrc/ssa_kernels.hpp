@@ -307,6 +307,18 @@ __global__ void slab_reduce_kernel(const unsigned long long *__restrict__ slabs,
 // and from them the moments with one rounding each:
 //   mean = Sx / N,   var = (N Sx2 - Sx^2) / (N (N - 1))  (0 when N == 1).
 // Optionally also writes the totals as (Sx hi, Sx lo, Sx2 hi, Sx2 lo) 128-bit pairs.
+// Mean and variance of one (point, species) from its exact totals, one rounding each.
+__device__ __forceinline__ void moment_point(int64_t sx, const i128s &sx2, int64_t n_traj, double dn, double dd,
+                                             double *mean, double *var) {
+    *mean = (double)sx / dn;
+    if (n_traj == 1) {
+        *var = 0.0;
+    } else {
+        const i128s num = i128_add(i128_mul_u64(sx2, (uint64_t)n_traj), i128_neg(i128_sq(sx)));
+        *var = i128_to_double(num) / dd;
+    }
+}
+
 __device__ __forceinline__ void moment_final_body(const unsigned long long *__restrict__ D,
                                                   const unsigned long long *__restrict__ Dhi, int32_t G, int32_t S,
                                                   int32_t s, const int32_t *__restrict__ x0, int64_t n_traj,
@@ -352,13 +364,7 @@ __device__ __forceinline__ void moment_final_body(const unsigned long long *__re
         const int64_t sx = base1 + c1;
         const i128s sx2 = i128_add(i128_add(base2, i128_from(c2)), i128_mul_u64(i128_from(c3), 1ull << 24));
         const size_t q = (size_t)g * S + s;
-        mean[q] = (double)sx / dn;
-        if (n_traj == 1) {
-            var[q] = 0.0;
-        } else {
-            const i128s num = i128_add(i128_mul_u64(sx2, (uint64_t)n_traj), i128_neg(i128_sq(sx)));
-            var[q] = i128_to_double(num) / dd;
-        }
+        moment_point(sx, sx2, n_traj, dn, dd, mean + q, var + q);
         if (sums) {
             sums[4 * q + 0] = sx < 0 ? -1 : 0;
             sums[4 * q + 1] = sx;
@@ -375,6 +381,130 @@ __global__ void __launch_bounds__(1024) moment_final_kernel(const unsigned long 
                                                             int64_t n_traj, double *__restrict__ mean,
                                                             double *__restrict__ var, int64_t *__restrict__ sums) {
     moment_final_body(D, Dhi, G, S, blockIdx.x, x0, n_traj, mean, var, sums);
+}
+
+// The same finalize for long point sequences (the adaptive selective memory's Avg-Y), over
+// many blocks: chunks of kFinChunk points per (chunk, species) block.
+// Step 1: the chunk totals of the three difference sums.
+constexpr int kFinChunk = 1024;
+__global__ void __launch_bounds__(256) chunk_total_kernel(const unsigned long long *__restrict__ D,
+                                                          const unsigned long long *__restrict__ Dhi, int64_t G,
+                                                          int32_t S, long long *__restrict__ T) {
+    const int64_t c = blockIdx.x;
+    const int32_t s = blockIdx.y;
+    const int64_t g0 = c * kFinChunk, g1 = min(g0 + kFinChunk, G);
+    int64_t a1 = 0, a2 = 0, a3 = 0;
+    for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+        a1 += (int64_t)D[((size_t)g * S + s) * 2];
+        a2 += (int64_t)D[((size_t)g * S + s) * 2 + 1];
+        a3 += (int64_t)Dhi[(size_t)g * S + s];
+    }
+    __shared__ int64_t sh[3][256];
+    sh[0][threadIdx.x] = a1;
+    sh[1][threadIdx.x] = a2;
+    sh[2][threadIdx.x] = a3;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + off];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + off];
+            sh[2][threadIdx.x] += sh[2][threadIdx.x + off];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 3) T[((size_t)c * S + s) * 3 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// Step 2: exclusive prefix of the chunk totals per species (one block per species).
+__global__ void __launch_bounds__(1024) chunk_scan_kernel(long long *__restrict__ T, int64_t n_chunks, int32_t S) {
+    const int32_t s = blockIdx.x;
+    const int64_t per = (n_chunks + blockDim.x - 1) / blockDim.x;
+    const int64_t c0 = min(n_chunks, (int64_t)threadIdx.x * per), c1 = min(n_chunks, c0 + per);
+    int64_t a[3] = {0, 0, 0};
+    for (int64_t c = c0; c < c1; ++c)
+        for (int i = 0; i < 3; ++i) a[i] += T[((size_t)c * S + s) * 3 + i];
+    __shared__ int64_t sh[3][1024];
+    for (int i = 0; i < 3; ++i) sh[i][threadIdx.x] = a[i];
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        int64_t v[3] = {0, 0, 0};
+        if ((int)threadIdx.x >= off)
+            for (int i = 0; i < 3; ++i) v[i] = sh[i][threadIdx.x - off];
+        __syncthreads();
+        for (int i = 0; i < 3; ++i) sh[i][threadIdx.x] += v[i];
+        __syncthreads();
+    }
+    int64_t run[3];
+    for (int i = 0; i < 3; ++i) run[i] = sh[i][threadIdx.x] - a[i];
+    for (int64_t c = c0; c < c1; ++c)
+        for (int i = 0; i < 3; ++i) {
+            const int64_t v = T[((size_t)c * S + s) * 3 + i];
+            T[((size_t)c * S + s) * 3 + i] = run[i];
+            run[i] += v;
+        }
+}
+
+// Step 3: within each chunk, the inclusive prefix (4 points per thread, then a block scan)
+// plus the chunk's offset and the initial-state terms, then the moments per point.
+__global__ void __launch_bounds__(256) chunk_final_kernel(const unsigned long long *__restrict__ D,
+                                                          const unsigned long long *__restrict__ Dhi, int64_t G,
+                                                          int32_t S, const long long *__restrict__ T,
+                                                          const int32_t *__restrict__ x0, int64_t n_traj,
+                                                          double *__restrict__ mean, double *__restrict__ var) {
+    static_assert(kFinChunk == 4 * 256, "four points per thread");
+    const int64_t c = blockIdx.x;
+    const int32_t s = blockIdx.y;
+    const int64_t g0 = c * kFinChunk + 4 * (int64_t)threadIdx.x;
+    int64_t v1[4], v2[4], v3[4];
+    int64_t a1 = 0, a2 = 0, a3 = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t g = g0 + i;
+        v1[i] = g < G ? (int64_t)D[((size_t)g * S + s) * 2] : 0;
+        v2[i] = g < G ? (int64_t)D[((size_t)g * S + s) * 2 + 1] : 0;
+        v3[i] = g < G ? (int64_t)Dhi[(size_t)g * S + s] : 0;
+        a1 += v1[i];
+        a2 += v2[i];
+        a3 += v3[i];
+    }
+    __shared__ int64_t sh[3][256];
+    sh[0][threadIdx.x] = a1;
+    sh[1][threadIdx.x] = a2;
+    sh[2][threadIdx.x] = a3;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        int64_t u1 = 0, u2 = 0, u3 = 0;
+        if ((int)threadIdx.x >= off) {
+            u1 = sh[0][threadIdx.x - off];
+            u2 = sh[1][threadIdx.x - off];
+            u3 = sh[2][threadIdx.x - off];
+        }
+        __syncthreads();
+        sh[0][threadIdx.x] += u1;
+        sh[1][threadIdx.x] += u2;
+        sh[2][threadIdx.x] += u3;
+        __syncthreads();
+    }
+    int64_t c1 = T[((size_t)c * S + s) * 3 + 0] + sh[0][threadIdx.x] - a1;
+    int64_t c2 = T[((size_t)c * S + s) * 3 + 1] + sh[1][threadIdx.x] - a2;
+    int64_t c3 = T[((size_t)c * S + s) * 3 + 2] + sh[2][threadIdx.x] - a3;
+    const int64_t xs = x0[s];
+    const int64_t base1 = n_traj * xs;
+    const i128s base2 = i128_mul_u64(i128_sq(xs), (uint64_t)n_traj);
+    const double dn = (double)n_traj;
+    const double dd = dn * (double)(n_traj - 1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t g = g0 + i;
+        c1 += v1[i];
+        c2 += v2[i];
+        c3 += v3[i];
+        if (g < G) {
+            const int64_t sx = base1 + c1;
+            const i128s sx2 = i128_add(i128_add(base2, i128_from(c2)), i128_mul_u64(i128_from(c3), 1ull << 24));
+            moment_point(sx, sx2, n_traj, dn, dd, mean + (size_t)g * S + s, var + (size_t)g * S + s);
+        }
+    }
 }
 
 // Covariance finalize, step 1: one block per column c of the cross-product rows
@@ -647,13 +777,37 @@ __global__ void xy_kernel(const double *__restrict__ y_time, const double *__res
         const int32_t c = (int32_t)(i - p * cols);
         const int64_t u0 = p * k, u1 = min(u0 + k, U);
         const double kk = (double)(u1 - u0);
+        // values are loaded 16 at a time so their latencies overlap; the sums stay sequential
+        constexpr int kB = 16;
         if (c == S) {
             double ts = 0.0;
-            for (int64_t u = u0; u < u1; ++u) ts = ts + y_time[u];
+            int64_t u = u0;
+            for (; u + kB <= u1; u += kB) {
+                double b[kB];
+#pragma unroll
+                for (int i = 0; i < kB; ++i) b[i] = y_time[u + i];
+#pragma unroll
+                for (int i = 0; i < kB; ++i) ts = ts + b[i];
+            }
+            for (; u < u1; ++u) ts = ts + y_time[u];
             xy_time[p] = ts / kk;
         } else {
             double ms = 0.0, vs = 0.0;
-            for (int64_t u = u0; u < u1; ++u) {
+            int64_t u = u0;
+            for (; u + kB <= u1; u += kB) {
+                double bm[kB], bv[kB];
+#pragma unroll
+                for (int i = 0; i < kB; ++i) {
+                    bm[i] = y_mean[(size_t)(u + i) * S + c];
+                    bv[i] = y_var[(size_t)(u + i) * S + c];
+                }
+#pragma unroll
+                for (int i = 0; i < kB; ++i) {
+                    ms = ms + bm[i];
+                    vs = vs + bv[i];
+                }
+            }
+            for (; u < u1; ++u) {
                 ms = ms + y_mean[(size_t)u * S + c];
                 vs = vs + y_var[(size_t)u * S + c];
             }

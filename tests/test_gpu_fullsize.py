@@ -88,3 +88,27 @@ def test_batched_workload_full_size_sampled_networks(ssa):
     batch.close()
     for mo in models:
         mo.close()
+
+
+def test_adaptive_viral_full_size(ssa):
+    """Adaptive selective memory on the viral workload (10^4 trajectories, t_end 50, groups
+    of k = 10^4 points): every Avg-Y point time equal to the oracle's union of event times,
+    and the Avg-XY points of the first, a middle and the last group bit-identical to the
+    oracle's evaluation of those groups."""
+    w = inputs.WORKLOADS["viral"]
+    m = w["model"]()
+    N, t_end, seed, k = w["n_traj"], w["t_end"], w["seed"], w["n_traj"]
+    model = ssa.Model.from_dict(m)
+    out = ssa.adaptive_device(model, N, t_end, seed, k, with_y=True, with_stats=True)
+    torch.cuda.synchronize()
+    model.close()
+    P = out["xy_time"].shape[0]
+    groups = [0, P // 2, P - 1]
+    st, ref = orc.adaptive_groups(m, N, t_end, seed, k, groups)
+    assert st == 0
+    assert out["stats"]["events"] == ref["events"]
+    assert np.array_equal(out["y_time"].cpu().numpy(), ref["y_time"])
+    assert P == -(-ref["y_time"].shape[0] // k)
+    assert np.array_equal(out["xy_time"].cpu().numpy()[groups], ref["xy_time"])
+    assert np.array_equal(out["xy_mean"].cpu().numpy()[groups], ref["xy_mean"])
+    assert np.array_equal(out["xy_var"].cpu().numpy()[groups], ref["xy_var"])

@@ -91,3 +91,18 @@ def test_immigration_death_follows_the_exact_mean():
         exact = np.mean((b / d) * (1.0 - np.exp(-d * seg)))     # exact mean at the group's times
         sd = math.sqrt(max(exact, 1.0) / N)                        # Poisson: var = mean
         assert abs(r["xy_mean"][p, 0] - exact) <= 5.0 * sd, (p, r["xy_mean"][p, 0], exact)
+
+
+def test_groups_equal_whole_reduction():
+    """The per-group evaluation (used at sizes where Avg-Y is too long to evaluate whole)
+    gives the whole reduction's Avg-XY points bit for bit."""
+    m = inputs.viral()
+    N, t_end, seed, k = 30, 1.0, 4, 9
+    st, r = orc.adaptive(m, N, t_end, seed, k)
+    P = len(r["xy_time"])
+    groups = [0, 1, P // 2, P - 1]
+    st, g = orc.adaptive_groups(m, N, t_end, seed, k, groups)
+    assert st == 0
+    assert np.array_equal(g["y_time"], r["y_time"])
+    assert np.array_equal(g["xy_time"], r["xy_time"][groups])
+    assert np.array_equal(g["xy_mean"], r["xy_mean"][groups]) and np.array_equal(g["xy_var"], r["xy_var"][groups])
