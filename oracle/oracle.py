@@ -19,7 +19,9 @@ _lib = None
 class _Net(ctypes.Structure):
     _fields_ = [("S", ctypes.c_int32), ("M", ctypes.c_int32),
                 ("reac", ctypes.c_void_p), ("prod", ctypes.c_void_p),
-                ("rate", ctypes.c_void_p), ("x0", ctypes.c_void_p), ("sum_order", ctypes.c_int32)]
+                ("rate", ctypes.c_void_p), ("x0", ctypes.c_void_p), ("sum_order", ctypes.c_int32),
+                ("law_species", ctypes.c_void_p), ("law_slope", ctypes.c_void_p), ("law_lo", ctypes.c_void_p),
+                ("law_hi", ctypes.c_void_p)]
 
 SUM_ORDERS = {"seq": 0, "block64": 1}
 
@@ -75,20 +77,28 @@ def _ptr(a):
 class Net:
     """Holds contiguous copies of a network's arrays and the ctypes struct that points at them."""
 
-    def __init__(self, reac, prod, rates, x0, sum_order="seq"):
+    def __init__(self, reac, prod, rates, x0, sum_order="seq", laws=None):
         self.reac = np.ascontiguousarray(reac, dtype=np.int32)
         self.prod = np.ascontiguousarray(prod, dtype=np.int32)
         self.rates = np.ascontiguousarray(rates, dtype=np.float64)
         self.x0 = np.ascontiguousarray(x0, dtype=np.int32)
         self.M, self.S = self.reac.shape
+        ptrs = [None, None, None, None]
+        if laws is not None:
+            self.law_species = np.ascontiguousarray(laws["species"], dtype=np.int32)
+            self.law_slope = np.ascontiguousarray(laws["slope"], dtype=np.float64)
+            self.law_lo = np.ascontiguousarray(laws["lo"], dtype=np.float64)
+            self.law_hi = np.ascontiguousarray(laws["hi"], dtype=np.float64)
+            ptrs = [self.law_species.ctypes.data, self.law_slope.ctypes.data, self.law_lo.ctypes.data,
+                    self.law_hi.ctypes.data]
         self.c = _Net(self.S, self.M, self.reac.ctypes.data, self.prod.ctypes.data,
-                      self.rates.ctypes.data, self.x0.ctypes.data, SUM_ORDERS[sum_order])
+                      self.rates.ctypes.data, self.x0.ctypes.data, SUM_ORDERS[sum_order], *ptrs)
 
 
 def as_net(model, rates=None):
     """model: dict with reac, prod, rates, x0 and optionally sum_order ("seq" or "block64")."""
     return Net(model["reac"], model["prod"], model["rates"] if rates is None else rates, model["x0"],
-               model.get("sum_order", "seq"))
+               model.get("sum_order", "seq"), model.get("laws"))
 
 
 def default_threads():

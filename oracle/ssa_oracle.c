@@ -48,6 +48,14 @@ typedef struct {
     const double *rate;   /* [M]   */
     const int32_t *x0;    /* [S]   */
     int32_t sum_order;    /* ORC_SUM_SEQ or ORC_SUM_BLOCK64 */
+    /* Optional rate laws (NULL: mass action throughout).  For reaction j with
+     * law_species[j] = m >= 0 the rate constant is not c_j but
+     *   c_j(x) = min(max(c_j + law_slope[j] * x_m, law_lo[j]), law_hi[j])
+     * -- the infectivities of Section 2.1, beta -/+ K F clamped to [0, beta] -- evaluated as
+     * one product, one sum (binary64) and the two exact bounds, before the one product with
+     * the mass-action count. */
+    const int32_t *law_species;  /* [M] or NULL */
+    const double *law_slope, *law_lo, *law_hi;  /* [M] */
 } orc_net;
 
 /* ------------------------------------------------------------------------------------
@@ -174,6 +182,11 @@ static int check_net(const orc_net *n)
             if (order > 2) return ORC_INVALID;
         }
         if (!(n->rate[j] >= 0.0) || !isfinite(n->rate[j])) return ORC_INVALID;
+        if (n->law_species && n->law_species[j] >= 0) {
+            if (n->law_species[j] >= n->S || !isfinite(n->law_slope[j]) || !(n->law_lo[j] >= 0.0) ||
+                !(n->law_hi[j] >= n->law_lo[j]))
+                return ORC_INVALID;
+        }
     }
     for (int s = 0; s < n->S; ++s)
         if (n->x0[s] < 0) return ORC_INVALID;
@@ -207,7 +220,12 @@ static double propensity(const orc_net *n, const rxn_info *ri, int j, const int3
     } else {
         h = (int64_t)x[ri->sa] * (int64_t)x[ri->sb];
     }
-    return n->rate[j] * (double)h;
+    double c = n->rate[j];
+    if (n->law_species && n->law_species[j] >= 0) {
+        double v = c + n->law_slope[j] * (double)x[n->law_species[j]];
+        c = fmin(fmax(v, n->law_lo[j]), n->law_hi[j]);
+    }
+    return c * (double)h;
 }
 
 /* ------------------------------------------------------------------------------------

@@ -67,6 +67,61 @@ def viral(rates=None):
     return m
 
 
+HIV_SPECIES = ["U0", "U", "T", "F", "Z4", "Z5", "I4", "I5", "V4", "V5"]
+
+
+def hiv(delta_v=2.0):
+    """The HIV network of the paper's Table 1 (27 reactions over 10 species) with the rates
+    and initial state of Section 2.1 (time in days).  The infectivities depend on the
+    tumour necrosis factor F: beta_R5 = clamp(beta - K F, 0, beta), beta_X4 = beta + K F,
+    and gamma likewise (K = 1e-7); they are given as rate laws (species, slope, lo, hi) on
+    top of the base constants beta = 4e-5 and gamma = 2e-5.  Bursting (I -> 200 V) consumes
+    the infected cell; the V5 -> V4 mutation is the mass-action reaction of Table 1 (the
+    paper's additional time trigger is not specified and not modelled)."""
+    lam, d_uf, d_ut, d_uz, d_t, d_tf = 200.0, 1e-5, 0.129, 0.005, 0.01, 1e-5
+    beta, gamma, K = 4e-5, 2e-5, 1e-7
+    s1, s2, s3, d_iz, mu, pi_, d_i, d_z = 1e-4, 1e-3, 1e-4, 0.06, 2.5e-3, 200.0, 0.33, 0.01
+    R = [
+        ({"U0": 1}, {"U0": 1, "U": 1}, lam),
+        ({"U": 1, "F": 1}, {"F": 1}, d_uf),
+        ({"U": 1}, {"T": 1}, d_ut),
+        ({"U": 1}, {"Z4": 1}, d_uz),
+        ({"U": 1}, {"Z5": 1}, d_uz),
+        ({"T": 1}, {}, d_t),
+        ({"T": 1, "F": 1}, {"F": 1}, d_tf),
+        ({"T": 1, "V5": 1}, {"I5": 1}, beta),            # 7: beta_R5
+        ({"T": 1, "V4": 1}, {"I4": 1}, beta),            # 8: beta_X4
+        ({"Z5": 1, "V5": 1}, {"I5": 1}, gamma),          # 9: gamma_R5
+        ({"Z4": 1, "V4": 1}, {"I4": 1}, gamma),          # 10: gamma_X4
+        ({"I5": 1}, {"I5": 1, "Z5": 1}, s2),
+        ({"I4": 1}, {"I4": 1, "Z4": 1}, s2),
+        ({"I5": 1, "Z5": 1}, {"U": 1, "I5": 1, "Z5": 1}, s1),
+        ({"I4": 1, "Z4": 1}, {"U": 1, "I4": 1, "Z4": 1}, s1),
+        ({"I5": 1, "Z5": 1}, {"Z5": 1}, d_iz),
+        ({"I4": 1, "Z4": 1}, {"Z4": 1}, d_iz),
+        ({"V5": 1}, {"V4": 1}, mu),
+        ({"I5": 1}, {"V5": 200}, pi_),
+        ({"I4": 1}, {"V4": 200}, pi_),
+        ({"V4": 1}, {"F": 1, "V4": 1}, s3),
+        ({"I5": 1}, {}, d_i),
+        ({"I4": 1}, {}, d_i),
+        ({"Z5": 1}, {}, d_z),
+        ({"Z4": 1}, {}, d_z),
+        ({"V5": 1}, {}, delta_v),
+        ({"V4": 1}, {}, delta_v),
+    ]
+    x0 = [1, 200, 1000, 0, 250, 250, 0, 0, 0, 100]
+    m = _model("hiv", HIV_SPECIES, R, x0)
+    M = len(R)
+    F = HIV_SPECIES.index("F")
+    sp = np.full(M, -1, dtype=np.int32)
+    slope, lo, hi = np.zeros(M), np.zeros(M), np.full(M, np.inf)
+    for j, sign, cap in ((7, -1.0, beta), (8, 1.0, np.inf), (9, -1.0, gamma), (10, 1.0, np.inf)):
+        sp[j], slope[j], lo[j], hi[j] = F, sign * K, 0.0, cap
+    m["laws"] = dict(species=sp, slope=slope, lo=lo, hi=hi)
+    return m
+
+
 def uniform_grid(t_end, G):
     """t_g = (t_end * g) / (G - 1): one product, then one quotient, in binary64; the last
     point is t_end itself (the two roundings can otherwise put it one ulp above t_end)."""
