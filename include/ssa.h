@@ -114,6 +114,27 @@ typedef struct {
 ssa_status ssa_model_create(int32_t n_species, int32_t n_reactions, const int32_t *reactants,
                             const int32_t *products, const double *rates, const int32_t *x0,
                             int32_t sum_order, ssa_model **out);
+
+/* Rate law of one reaction (Section 2.1's infectivities beta_R5 = beta - K F with
+ * 0 <= beta_R5 <= beta, beta_X4 = beta + K F, gamma likewise): with species >= 0 the rate
+ * constant of reaction j is
+ *     c_j(x) = min(max(c_j + slope * x_species, lo), hi)
+ * (one product and one sum in binary64, then the bounds), c_j being the model's or the
+ * run's rate; species < 0 keeps mass action.  lo >= 0, lo <= hi (hi may be +inf). */
+typedef struct {
+    int32_t species;
+    double slope;
+    double lo;
+    double hi;
+} ssa_rate_law;
+
+/* ssa_model_create with optional rate laws (laws: host [M], NULL = mass action).  Networks
+ * with a rate law run only in the specialised kernels: SSA_SUM_SEQ, M <= 32, S <= 64
+ * (SSA_E_UNSUPPORTED otherwise); the gradient, the Jacobian and batches refuse them (the
+ * score of a modulated rate is not n_j - A_j). */
+ssa_status ssa_model_create_laws(int32_t n_species, int32_t n_reactions, const int32_t *reactants,
+                                 const int32_t *products, const double *rates, const int32_t *x0,
+                                 int32_t sum_order, const ssa_rate_law *laws, ssa_model **out);
 void ssa_model_destroy(ssa_model *model);
 
 /* Host convenience (synchronous): n_traj trajectories 0..n_traj-1 on [0, t_end], grid

@@ -162,6 +162,8 @@ struct ssa_model {
     int32_t *d_dep_ptr = nullptr;     // [M + 1]
     int64_t dep_nnz = 0;
     std::string jit_src;              // generated network description for specialisation
+    bool has_laws = false;            // some rate constant depends on a species (ssa_rate_law)
+    std::vector<ssa_rate_law> laws;   // [M] when has_laws
 };
 
 struct ssa_batch {
@@ -229,15 +231,28 @@ std::string generate_net_source(const ssa_model *m) {
             for (int32_t t = 0; t < r; ++t) (sa < 0 ? sa : sb) = q;
             order += r;
         }
+        // the rate constant: c_j, or its rate law min(max(c_j + slope x_m, lo), hi)
+        std::string cj = "c[" + std::to_string(j) + "]";
+        if (m->has_laws && m->laws[j].species >= 0) {
+            const ssa_rate_law &L = m->laws[j];
+            snprintf(buf, sizeof buf, "(%s + %a * (double)x[%d])", cj.c_str(), L.slope, L.species);
+            cj = buf;
+            snprintf(buf, sizeof buf, "fmax(%s, %a)", cj.c_str(), L.lo);
+            cj = buf;
+            if (std::isfinite(L.hi)) {
+                snprintf(buf, sizeof buf, "fmin(%s, %a)", cj.c_str(), L.hi);
+                cj = buf;
+            }
+        }
         if (order == 0)
-            snprintf(buf, sizeof buf, "        a[%d] = c[%d] * 1.0;\n", j, j);
+            snprintf(buf, sizeof buf, "        a[%d] = %s * 1.0;\n", j, cj.c_str());
         else if (order == 1)
-            snprintf(buf, sizeof buf, "        a[%d] = c[%d] * (double)x[%d];\n", j, j, sa);
+            snprintf(buf, sizeof buf, "        a[%d] = %s * (double)x[%d];\n", j, cj.c_str(), sa);
         else if (sa != sb)
-            snprintf(buf, sizeof buf, "        a[%d] = c[%d] * ((double)x[%d] * (double)x[%d]);\n", j, j, sa, sb);
+            snprintf(buf, sizeof buf, "        a[%d] = %s * ((double)x[%d] * (double)x[%d]);\n", j, cj.c_str(), sa, sb);
         else
-            snprintf(buf, sizeof buf,
-                     "        a[%d] = c[%d] * (((double)x[%d] * (double)max(x[%d] - 1, 0)) * 0.5);\n", j, j, sa, sa);
+            snprintf(buf, sizeof buf, "        a[%d] = %s * (((double)x[%d] * (double)max(x[%d] - 1, 0)) * 0.5);\n", j,
+                     cj.c_str(), sa, sa);
         s += buf;
     }
     s += "    }\n";
@@ -306,7 +321,8 @@ ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out
 }
 
 bool jit_eligible(const ssa_model *m) {
-    return !prefer_generic() && m->M <= kJitMaxReactions && m->S <= kJitMaxSpecies;
+    // networks with rate laws exist only in specialised form
+    return (m->has_laws || !prefer_generic()) && m->M <= kJitMaxReactions && m->S <= kJitMaxSpecies;
 }
 
 ssa_status validate_grid_host(const double *grid, int32_t G, double t_end) {
@@ -822,6 +838,12 @@ const char *ssa_last_error(void) { return g_err.c_str(); }
 
 ssa_status ssa_model_create(int32_t S, int32_t M, const int32_t *reac, const int32_t *prod, const double *rates,
                             const int32_t *x0, int32_t sum_order, ssa_model **out) {
+    return ssa_model_create_laws(S, M, reac, prod, rates, x0, sum_order, nullptr, out);
+}
+
+ssa_status ssa_model_create_laws(int32_t S, int32_t M, const int32_t *reac, const int32_t *prod,
+                                 const double *rates, const int32_t *x0, int32_t sum_order, const ssa_rate_law *laws,
+                                 ssa_model **out) {
     if (!out) return fail(SSA_E_INVALID, "out is NULL");
     *out = nullptr;
     if (sum_order != SSA_SUM_SEQ && sum_order != SSA_SUM_BLOCK64) return fail(SSA_E_INVALID, "unknown sum order");
@@ -834,6 +856,22 @@ ssa_status ssa_model_create(int32_t S, int32_t M, const int32_t *reac, const int
     m->M = M;
     m->order = sum_order;
     m->q = (M + kWave - 1) / kWave;
+    if (laws) {
+        for (int32_t j = 0; j < M; ++j) {
+            const ssa_rate_law &L = laws[j];
+            if (L.species < 0) continue;
+            if (L.species >= S || !std::isfinite(L.slope) || !(L.lo >= 0.0) || !(L.hi >= L.lo) || std::isnan(L.hi))
+                return fail(SSA_E_INVALID, "rate law of reaction %d: need 0 <= species < S, finite slope, "
+                                           "0 <= lo <= hi", j);
+            m->has_laws = true;
+        }
+        if (m->has_laws) {
+            if (sum_order != SSA_SUM_SEQ || M > kJitMaxReactions || S > kJitMaxSpecies)
+                return fail(SSA_E_UNSUPPORTED, "rate laws need the sequential order, M <= %d and S <= %d",
+                            kJitMaxReactions, kJitMaxSpecies);
+            m->laws.assign(laws, laws + M);
+        }
+    }
     m->reac.assign(reac, reac + (size_t)M * S);
     m->prod.assign(prod, prod + (size_t)M * S);
     m->rate.assign(rates, rates + M);
@@ -1114,6 +1152,7 @@ ssa_status ssa_run_jacobian_device(const ssa_model *m, const double *rates, int6
     if (m->order != SSA_SUM_SEQ || m->M > kJitMaxReactions || m->S > kJitMaxSpecies)
         return fail(SSA_E_UNSUPPORTED, "the forward Jacobian needs a sequential-order network with at most %d "
                     "reactions and %d species", kJitMaxReactions, kJitMaxSpecies);
+    if (m->has_laws) return fail(SSA_E_UNSUPPORTED, "the score of a rate law is not n_j - A_j: no Jacobian");
     const int64_t n_items = (n_traj + kChunk - 1) / kChunk;
     const size_t jrow = (size_t)(m->S + 1) * m->M;
     const size_t slab_bytes = (size_t)n_items * G * jrow * sizeof(double);
@@ -1317,6 +1356,7 @@ ssa_status ssa_backward_device(const ssa_model *m, const double *rates, int64_t 
     if (m->order == SSA_SUM_BLOCK64 && m->q > kWaveMaxQ)
         return fail(SSA_E_UNSUPPORTED, "backward in the 64-chunk order supports at most %d reactions",
                     kWaveMaxQ * kWave);
+    if (m->has_laws) return fail(SSA_E_UNSUPPORTED, "the score of a rate law is not n_j - A_j: no backward");
     if (n_traj > ((int64_t)1 << 31) * kChunk) return fail(SSA_E_INVALID, "n_traj too large");
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
@@ -1644,6 +1684,7 @@ ssa_status ssa_batch_create(int32_t B, const ssa_model *const *models, const int
         if (m->max_changes > kChg)
             return fail(SSA_E_UNSUPPORTED, "batched networks may change at most %d species per reaction", kChg);
         if (m->order != SSA_SUM_SEQ) return fail(SSA_E_UNSUPPORTED, "batched networks use the sequential sum order");
+        if (m->has_laws) return fail(SSA_E_UNSUPPORTED, "batched networks are mass action");
         mmax = std::max(mmax, m->M);
         bt->s_rows = std::max(bt->s_rows, m->S);
         bt->m_rows = std::max(bt->m_rows, m->M);

@@ -18,7 +18,7 @@ OK, E_INVALID, E_NOMEM, E_DEVICE, E_OVERFLOW, E_EVENT_LIMIT, E_UNSUPPORTED = ran
 _NAMES = {1: "SSA_E_INVALID", 2: "SSA_E_NOMEM", 3: "SSA_E_DEVICE", 4: "SSA_E_OVERFLOW",
           5: "SSA_E_EVENT_LIMIT", 6: "SSA_E_UNSUPPORTED"}
 
-EXPORTS = ["ssa_model_create", "ssa_model_destroy", "ssa_run", "ssa_run_device", "ssa_backward_device",
+EXPORTS = ["ssa_model_create", "ssa_model_create_laws", "ssa_model_destroy", "ssa_run", "ssa_run_device", "ssa_backward_device",
            "ssa_run_jacobian_device", "ssa_jacobian_vjp", "ssa_autotune_forward", "ssa_run_cov_device",
            "ssa_hist_quantiles", "ssa_adaptive_device",
            "ssa_record", "ssa_batch_create", "ssa_batch_run", "ssa_batch_destroy", "ssa_last_error"]
@@ -58,6 +58,7 @@ def load(path=None):
     L = ctypes.CDLL(path)
     vp, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
     L.ssa_model_create.argtypes = [i32, i32, vp, vp, vp, vp, i32, ctypes.POINTER(vp)]
+    L.ssa_model_create_laws.argtypes = [i32, i32, vp, vp, vp, vp, i32, vp, ctypes.POINTER(vp)]
     L.ssa_model_destroy.argtypes = [vp]
     L.ssa_model_destroy.restype = None
     L.ssa_run.argtypes = [vp, i64, dbl, vp, i32, u64, vp, vp, vp]
@@ -106,12 +107,18 @@ def _stream(stream):
 SUM_ORDERS = {"seq": 0, "block64": 1}
 
 
-class Model:
-    """A mass-action network on the current device (ssa_model_create).  sum_order: "seq"
-    (left-to-right propensity sums, one trajectory per lane) or "block64" (64-chunk sums,
-    one trajectory per wave)."""
+class RateLaw(ctypes.Structure):
+    _fields_ = [("species", ctypes.c_int32), ("slope", ctypes.c_double), ("lo", ctypes.c_double),
+                ("hi", ctypes.c_double)]
 
-    def __init__(self, reac, prod, rates, x0, sum_order="seq"):
+
+class Model:
+    """A network on the current device (ssa_model_create / ssa_model_create_laws).
+    sum_order: "seq" (left-to-right propensity sums, one trajectory per lane) or "block64"
+    (64-chunk sums, one trajectory per wave).  laws: optional dict of [M] arrays species,
+    slope, lo, hi (species -1 = mass action) for species-dependent rate constants."""
+
+    def __init__(self, reac, prod, rates, x0, sum_order="seq", laws=None):
         L = load()
         self.reac = np.ascontiguousarray(reac, dtype=np.int32)
         self.prod = np.ascontiguousarray(prod, dtype=np.int32)
@@ -120,13 +127,21 @@ class Model:
         self.M, self.S = self.reac.shape
         h = ctypes.c_void_p()
         self.sum_order = sum_order
-        _check(L.ssa_model_create(self.S, self.M, _p(self.reac), _p(self.prod), _p(self.rates), _p(self.x0),
-                                  SUM_ORDERS[sum_order], ctypes.byref(h)))
+        if laws is None:
+            _check(L.ssa_model_create(self.S, self.M, _p(self.reac), _p(self.prod), _p(self.rates), _p(self.x0),
+                                      SUM_ORDERS[sum_order], ctypes.byref(h)))
+        else:
+            arr = (RateLaw * self.M)()
+            for j in range(self.M):
+                arr[j] = RateLaw(int(laws["species"][j]), float(laws["slope"][j]), float(laws["lo"][j]),
+                                 float(laws["hi"][j]))
+            _check(L.ssa_model_create_laws(self.S, self.M, _p(self.reac), _p(self.prod), _p(self.rates),
+                                           _p(self.x0), SUM_ORDERS[sum_order], arr, ctypes.byref(h)))
         self.handle = h
 
     @classmethod
     def from_dict(cls, m):
-        return cls(m["reac"], m["prod"], m["rates"], m["x0"], m.get("sum_order", "seq"))
+        return cls(m["reac"], m["prod"], m["rates"], m["x0"], m.get("sum_order", "seq"), m.get("laws"))
 
     def close(self):
         if getattr(self, "handle", None):
