@@ -52,6 +52,9 @@ def lib():
         L.orc_grad.argtypes = [ctypes.POINTER(_Net), ctypes.c_int64, ctypes.c_double, vp, ctypes.c_int32,
                                ctypes.c_uint64, ctypes.c_uint64, vp, vp, vp, vp, ctypes.c_int]
         L.orc_grad.restype = ctypes.c_int
+        L.orc_grad_moments.argtypes = [ctypes.POINTER(_Net), ctypes.c_int64, ctypes.c_double, vp, ctypes.c_int32,
+                                       ctypes.c_uint64, ctypes.c_uint64, vp, vp, vp, vp, vp, vp, ctypes.c_int]
+        L.orc_grad_moments.restype = ctypes.c_int
         L.orc_jacobian.argtypes = [ctypes.POINTER(_Net), ctypes.c_int64, ctypes.c_double, vp, ctypes.c_int32,
                                    ctypes.c_uint64, ctypes.c_uint64, vp, vp, vp, ctypes.c_int]
         L.orc_jacobian.restype = ctypes.c_int
@@ -177,17 +180,23 @@ def run(model, N, t_end, grid, seed, hist=None, max_events=2**62, rates=None, th
     return st, out
 
 
-def grad(model, N, t_end, grid, seed, w, mhat, max_events=2**62, rates=None, threads=None):
-    """Likelihood-ratio gradient wrt log rate constants.  Returns (status, grad (M,), l1 (M,))."""
+def grad(model, N, t_end, grid, seed, w, mhat, max_events=2**62, rates=None, threads=None, wv=None, vhat=None):
+    """Likelihood-ratio gradient wrt log rate constants of a loss on the grid means (weights
+    w = dL/dmean, centring mhat) and optionally the variances (wv = dL/dvar, centring vhat).
+    Returns (status, grad (M,), l1 (M,))."""
     net = as_net(model, rates)
     grid = np.ascontiguousarray(grid, dtype=np.float64)
     G = grid.shape[0]
     w = np.ascontiguousarray(w, dtype=np.float64).reshape(G, net.S)
     mhat = np.ascontiguousarray(mhat, dtype=np.float64).reshape(G, net.S)
+    if wv is not None:
+        wv = np.ascontiguousarray(wv, dtype=np.float64).reshape(G, net.S)
+        vhat = np.ascontiguousarray(vhat, dtype=np.float64).reshape(G, net.S)
     g_out = np.zeros(net.M)
     l1 = np.zeros(net.M)
-    st = lib().orc_grad(ctypes.byref(net.c), int(N), float(t_end), _ptr(grid), G, seed, max_events,
-                        _ptr(w), _ptr(mhat), _ptr(g_out), _ptr(l1), threads or default_threads())
+    st = lib().orc_grad_moments(ctypes.byref(net.c), int(N), float(t_end), _ptr(grid), G, seed, max_events,
+                                _ptr(w), _ptr(mhat), _ptr(wv), _ptr(vhat), _ptr(g_out), _ptr(l1),
+                                threads or default_threads())
     return st, g_out, l1
 
 

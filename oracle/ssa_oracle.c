@@ -570,6 +570,7 @@ int orc_run(const orc_net *net, int64_t N, double t_end, const double *grid, int
 typedef struct {
     int S, M;
     const double *w, *mhat;
+    const double *wv, *vhat; /* variance weights and centring, or NULL */
     long double *acc, *l1;   /* [M] for the current trajectory */
     double *z;               /* [M] scratch */
 } grad_ctx;
@@ -589,13 +590,43 @@ static void grad_visit(void *c, int g, const traj_state *st, double tg)
             gc->acc[j] += (long double)term;
             gc->l1[j] += (long double)fabs(term);
         }
+        if (gc->wv) {
+            /* variance term: wv ((X - mhat)^2 - vhat) z_j, in long double; its scale is the
+             * size of the expanded terms wv (X^2 + 2|X mhat| + mhat^2 + |vhat|) |z_j| */
+            const long double x = (long double)st->x[s], m = (long double)gc->mhat[(size_t)g * gc->S + s];
+            const long double v = (long double)gc->vhat[(size_t)g * gc->S + s];
+            const long double wv = (long double)gc->wv[(size_t)g * gc->S + s];
+            const long double q = wv * ((x - m) * (x - m) - v);
+            const long double qs = fabsl(wv) * (x * x + 2.0L * fabsl(x * m) + m * m + fabsl(v));
+            for (int j = 0; j < gc->M; ++j) {
+                gc->acc[j] += q * (long double)gc->z[j];
+                gc->l1[j] += qs * fabsl((long double)gc->z[j]);
+            }
+        }
     }
 }
+
+int orc_grad_moments(const orc_net *net, int64_t N, double t_end, const double *grid, int32_t G,
+                     uint64_t seed, uint64_t max_events, const double *w, const double *mhat, const double *wv,
+                     const double *vhat, double *grad, double *l1, int nthreads);
 
 int orc_grad(const orc_net *net, int64_t N, double t_end, const double *grid, int32_t G,
              uint64_t seed, uint64_t max_events, const double *w, const double *mhat,
              double *grad, double *l1, int nthreads)
 {
+    return orc_grad_moments(net, N, t_end, grid, G, seed, max_events, w, mhat, NULL, NULL, grad, l1, nthreads);
+}
+
+/* The same gradient for a loss on the grid means and variances: with wv = dL/dvar and the
+ * centring vhat (usually the forward variance) each crossing adds
+ *   wv_{g,s} ((X_s(t_g) - mhat_{g,s})^2 - vhat_{g,s}) z_j(t_g),
+ * the score-function derivative of the variance: d/dtheta E[(X - mu)^2] = E[(X - mu)^2 z]
+ * because E[X - mu] = 0, and E[z] = 0 makes the centring by vhat unbiased. */
+int orc_grad_moments(const orc_net *net, int64_t N, double t_end, const double *grid, int32_t G,
+                     uint64_t seed, uint64_t max_events, const double *w, const double *mhat, const double *wv,
+                     const double *vhat, double *grad, double *l1, int nthreads)
+{
+    if (wv && !vhat) return ORC_INVALID;
     int st0 = check_net(net);
     if (st0) return st0;
     if (check_grid(grid, G, t_end)) return ORC_INVALID;
@@ -611,7 +642,7 @@ int orc_grad(const orc_net *net, int64_t N, double t_end, const double *grid, in
 #pragma omp parallel num_threads(nthreads)
     {
         grad_ctx gc;
-        gc.S = S; gc.M = M; gc.w = w; gc.mhat = mhat;
+        gc.S = S; gc.M = M; gc.w = w; gc.mhat = mhat; gc.wv = wv; gc.vhat = vhat;
         gc.acc = (long double *)calloc(M, sizeof(long double));
         gc.l1 = (long double *)calloc(M, sizeof(long double));
         gc.z = (double *)calloc(M, sizeof(double));

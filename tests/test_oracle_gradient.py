@@ -126,3 +126,32 @@ def test_jacobian_contracts_to_the_gradient():
     assert np.allclose(np.einsum("gs,gsj->j", w, J), g, rtol=0, atol=1e-12 * gl1.max())
     # the L1 scales are consistent too
     assert np.all(np.einsum("gs,gsj->j", np.abs(w), l1) >= gl1 * (1 - 1e-12))
+
+
+def test_immigration_death_variance_gradient_closed_form():
+    """Poisson marginals: var(t) = m(t), so d var / d ln k has the mean's closed form.  The
+    variance estimator (1/N) sum_i ((X_i - m_hat)^2 - v_hat) z_ij lands within 5 standard
+    errors, and the oracle's gradient routine with wv = 1 (w = 0) computes that sum."""
+    k1, k2 = 10.0, 0.1
+    m = inputs.immigration_death(k1, k2)
+    N = 8000
+    for t in (5.0, 20.0, 60.0):
+        X, Z = _records(m, 23, N, t)
+        x = X[:, 0]
+        mhat, vhat = x.mean(), x.var(ddof=1)
+        terms = ((x - mhat) ** 2 - vhat)[:, None] * Z
+        est = terms.mean(axis=0)
+        se = terms.std(axis=0, ddof=1) / math.sqrt(N)
+        mt = (k1 / k2) * (1 - math.exp(-k2 * t))
+        exact = [mt, -mt + k1 * t * math.exp(-k2 * t)]
+        for j in range(2):
+            assert abs(est[j] - exact[j]) < 5 * se[j], (t, j, est[j], exact[j], se[j])
+        st, g, l1 = orc.grad(m, N, t, np.array([t]), 23, np.array([0.0]), np.array([mhat]),
+                             wv=np.array([1.0]), vhat=np.array([vhat]))
+        assert st == orc.OK
+        assert np.allclose(g, est, rtol=0, atol=1e-12 * l1.max())
+        # the variance and mean parts add
+        _, gm, _ = orc.grad(m, N, t, np.array([t]), 23, np.array([0.7]), np.array([mhat]))
+        _, gb, lb = orc.grad(m, N, t, np.array([t]), 23, np.array([0.7]), np.array([mhat]),
+                             wv=np.array([1.0]), vhat=np.array([vhat]))
+        assert np.allclose(gb, gm + g, rtol=0, atol=1e-12 * lb.max())
