@@ -170,6 +170,20 @@ ssa_status ssa_backward_device(const ssa_model *model, const double *rates, int6
                                const double *w, const double *mhat, double *grad, void *stream,
                                ssa_stats *stats);
 
+/* The same gradient for a loss on the grid means and variances: with wv [G*S] = dL/dvar and
+ * the centring vhat [G*S] (usually the forward variance; both device) every crossing adds
+ *   wv_{g,s} ((X_s(t_g) - mhat_{g,s})^2 - vhat_{g,s}) z_j(t_g)
+ * to the mean term, the score-function derivative of the variance (d E[(X - mu)^2] / d theta
+ * = E[(X - mu)^2 z] since E[X - mu] = 0; E[z] = 0 makes the centring unbiased).  The weights
+ * are folded into prefix tables of w - 2 wv mhat, wv and their constants, evaluated as a
+ * polynomial in x per interval, so the rounding error scales with wv (x^2 + mhat^2 + |vhat|)
+ * rather than with the centred square.  wv == NULL gives ssa_backward_device.  SSA_SUM_SEQ
+ * models only (SSA_E_UNSUPPORTED otherwise); other limits and codes as ssa_backward_device. */
+ssa_status ssa_backward_moments_device(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
+                                       const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events,
+                                       const double *w, const double *mhat, const double *wv, const double *vhat,
+                                       double *grad, void *stream, ssa_stats *stats);
+
 /* Autotuning of the forward launch for this model and problem size: every candidate
  * configuration (LDS window bytes 2048 .. 16384, flush by atomics or through wave-private
  * slabs) is timed on the caller's problem (grid [n_grid] device, the same outputs for all:

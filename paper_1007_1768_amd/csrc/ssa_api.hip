@@ -128,7 +128,7 @@ struct JitKernels {
     hipModule_t module = nullptr;
     hipFunction_t fwd = nullptr, fwd_atomic = nullptr, fwd_hist = nullptr, fwd_slab_hist = nullptr, fwd_jac = nullptr,
                   fwd_cov = nullptr,
-                  rec = nullptr, bwd = nullptr, evt = nullptr;
+                  rec = nullptr, bwd = nullptr, bwd_var = nullptr, evt = nullptr;
 };
 
 std::mutex g_jit_mu;
@@ -313,6 +313,7 @@ ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out
     HIP_TRY(hipModuleGetFunction(&k->fwd_cov, k->module, "ssa_jit_fwd_cov"));
     HIP_TRY(hipModuleGetFunction(&k->rec, k->module, "ssa_jit_rec"));
     HIP_TRY(hipModuleGetFunction(&k->evt, k->module, "ssa_jit_evt"));
+    HIP_TRY(hipModuleGetFunction(&k->bwd_var, k->module, "ssa_jit_bwd_var"));
     HIP_TRY(hipModuleGetFunction(&k->bwd, k->module, "ssa_jit_bwd"));
     std::lock_guard<std::mutex> lk(g_jit_mu);
     auto ins = g_jit_cache.emplace(key, k);
@@ -374,9 +375,9 @@ size_t generic_lds(const WorkList &wl) {
            (size_t)(kBlock / kWave) * wl.m_rows * kChg * sizeof(int32_t);
 }
 
-template <int MODE, int MM, bool BATCH>
+template <int MODE, int MM, bool BATCH, bool QUAD = false>
 hipError_t launch_generic_mm(const WorkList &wl, int64_t n_items, int dev, hipStream_t st) {
-    auto kern = sim_kernel<MODE, MM, BATCH>;
+    auto kern = sim_kernel<MODE, MM, BATCH, QUAD>;
     const size_t lds = generic_lds(wl);
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, lds);
@@ -385,11 +386,11 @@ hipError_t launch_generic_mm(const WorkList &wl, int64_t n_items, int dev, hipSt
     return hipGetLastError();
 }
 
-template <int MODE, bool BATCH>
+template <int MODE, bool BATCH, bool QUAD = false>
 hipError_t launch_generic(int mm, const WorkList &wl, int64_t n_items, int dev, hipStream_t st) {
-    if (mm == 8) return launch_generic_mm<MODE, 8, BATCH>(wl, n_items, dev, st);
-    if (mm == 16) return launch_generic_mm<MODE, 16, BATCH>(wl, n_items, dev, st);
-    if (mm == 32) return launch_generic_mm<MODE, 32, BATCH>(wl, n_items, dev, st);
+    if (mm == 8) return launch_generic_mm<MODE, 8, BATCH, QUAD>(wl, n_items, dev, st);
+    if (mm == 16) return launch_generic_mm<MODE, 16, BATCH, QUAD>(wl, n_items, dev, st);
+    if (mm == 32) return launch_generic_mm<MODE, 32, BATCH, QUAD>(wl, n_items, dev, st);
     return hipErrorInvalidValue;
 }
 
@@ -627,10 +628,11 @@ hipError_t launch_finalize(const unsigned long long *D, const unsigned long long
 // network, or the generic one (which reads rates in zero-padded slots: a caller's rates
 // array is copied into a padded buffer first).
 ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_items, int dev, hipStream_t st,
-                         const double *user_rates, StreamScratch &scr) {
+                         const double *user_rates, StreamScratch &scr, bool quad = false) {
     (void)n_items;
     if (m->order == SSA_SUM_BLOCK64) {
         if (mode == kEvt) return fail(SSA_E_UNSUPPORTED, "the event log runs the sequential sum order");
+        if (quad) return fail(SSA_E_UNSUPPORTED, "variance weights need the sequential sum order");
         HIP_TRY(mode == kRec ? launch_wave<kRec>(m, wl, dev, st, scr) : launch_wave<kBwd>(m, wl, dev, st, scr));
         return SSA_OK;
     }
@@ -638,7 +640,7 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
         std::shared_ptr<JitKernels> k;
         ssa_status s = get_jit(m, dev, k);
         if (s) return s;
-        hipFunction_t f = mode == kRec ? k->rec : (mode == kEvt ? k->evt : k->bwd);
+        hipFunction_t f = mode == kRec ? k->rec : (mode == kEvt ? k->evt : (quad ? k->bwd_var : k->bwd));
         HIP_TRY(launch_jit(f, wl, n_items, dev, st));
         return SSA_OK;
     }
@@ -657,6 +659,7 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
     wl.m_rows = m->M;
     hipError_t e = mode == kRec   ? launch_generic<kRec, false>(mm, wl, n_items, dev, st)
                    : mode == kEvt ? launch_generic<kEvt, false>(mm, wl, n_items, dev, st)
+                   : quad         ? launch_generic<kBwd, false, true>(mm, wl, n_items, dev, st)
                                   : launch_generic<kBwd, false>(mm, wl, n_items, dev, st);
     HIP_TRY(e);
     return SSA_OK;
@@ -1348,8 +1351,18 @@ ssa_status ssa_run(const ssa_model *m, int64_t n_traj, double t_end, const doubl
 ssa_status ssa_backward_device(const ssa_model *m, const double *rates, int64_t n_traj, double t_end,
                                const double *grid, int32_t G, uint64_t seed, uint64_t max_events, const double *w,
                                const double *mhat, double *grad, void *stream, ssa_stats *stats) {
+    return ssa_backward_moments_device(m, rates, n_traj, t_end, grid, G, seed, max_events, w, mhat, nullptr, nullptr,
+                                       grad, stream, stats);
+}
+
+ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, int64_t n_traj, double t_end,
+                                       const double *grid, int32_t G, uint64_t seed, uint64_t max_events,
+                                       const double *w, const double *mhat, const double *wv, const double *vhat,
+                                       double *grad, void *stream, ssa_stats *stats) {
     if (!m) return fail(SSA_E_INVALID, "model is NULL");
     if (n_traj <= 0 || G <= 0 || !grid || !w || !mhat || !grad) return fail(SSA_E_INVALID, "bad argument");
+    if ((wv == nullptr) != (vhat == nullptr)) return fail(SSA_E_INVALID, "wv and vhat go together");
+    const bool quad = wv != nullptr;
     if (!(t_end >= 0.0) || !std::isfinite(t_end)) return fail(SSA_E_INVALID, "t_end must be finite and >= 0");
     if (m->order == SSA_SUM_SEQ && m->M > kJitMaxReactions)
         return fail(SSA_E_UNSUPPORTED, "backward supports at most %d reactions", kJitMaxReactions);
@@ -1366,7 +1379,7 @@ ssa_status ssa_backward_device(const ssa_model *m, const double *rates, int64_t 
     NetDev n = base_net(m, rates, n_traj, t_end, grid, G, seed, max_events);
     void *gt = nullptr, *gt2 = nullptr, *ctl = nullptr, *bp = nullptr;
     const size_t rows_bytes = sizeof(double) * (size_t)n_traj * m->M;
-    const int32_t ncol = 2 * m->S + 2;
+    const int32_t ncol = quad ? 4 * m->S + 2 : 2 * m->S + 2;
     HIP_TRY(scr.alloc(&bp, (size_t)12 * ncol * ((size_t)G + 1)));
     HIP_TRY(scr.alloc(&gt, rows_bytes));
     HIP_TRY(scr.alloc(&gt2, rows_bytes / 2 + sizeof(double) * m->M));
@@ -1374,7 +1387,8 @@ ssa_status ssa_backward_device(const ssa_model *m, const double *rates, int64_t 
     HIP_TRY(launch_zero(ctl, 64, st));
     n.ginfo = (const GridInfo *)((char *)ctl + 64);
     HIP_TRY(launch_grid_info(grid, G, t_end, (GridInfo *)n.ginfo, st));
-    hipLaunchKernelGGL(bwd_prefix_kernel, dim3((unsigned)ncol), dim3(256), 0, st, w, mhat, grid, G, m->S, bp);
+    hipLaunchKernelGGL(bwd_prefix_kernel, dim3((unsigned)ncol), dim3(256), 0, st, w, mhat, wv, vhat, grid, G, m->S,
+                       bp);
     HIP_TRY(hipGetLastError());
     n.bp = bp;
     n.gtraj = (double *)gt;
@@ -1389,7 +1403,7 @@ ssa_status ssa_backward_device(const ssa_model *m, const double *rates, int64_t 
     wl.stats = (unsigned long long *)((char *)ctl + 32);
     EventPair ev;
     if (stats && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
-    ssa_status s = launch_single(kBwd, m, wl, n_items, dev, st, rates, scr);
+    ssa_status s = launch_single(kBwd, m, wl, n_items, dev, st, rates, scr, quad);
     if (s) return s;
     if (stats && ev.b) HIP_TRY(hipEventRecord(ev.b, st));
     // fixed-order pairwise reduction of the per-trajectory rows

@@ -130,3 +130,9 @@ extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_bwd(ssa::WorkL
     ssa::RegPolicy p;
     ssa::sim_loop<ssa::kBwd, ssa_gen::Net::M, false>(wl, p);
 }
+
+// Backward with variance weights (prefix table with the quadratic columns).
+extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_bwd_var(ssa::WorkList wl) {
+    ssa::RegPolicy p;
+    ssa::sim_loop<ssa::kBwd, ssa_gen::Net::M, false, ssa::RegPolicy, true>(wl, p);
+}

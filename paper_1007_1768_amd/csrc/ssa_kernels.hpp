@@ -115,12 +115,12 @@ __host__ __device__ __forceinline__ size_t generic_int_words(int32_t s_rows, int
     return (w + 1) & ~(size_t)1;   // 8-byte alignment of the windows that follow
 }
 
-template <int MODE, int MM, bool BATCH>
+template <int MODE, int MM, bool BATCH, bool QUAD = false>
 __global__ void __launch_bounds__(kBlock) sim_kernel(WorkList wl) {
     extern __shared__ int32_t lds_x[];
     LdsPolicy p;
     generic_setup(wl, lds_x, p);
-    sim_loop<MODE, MM, BATCH>(wl, p);
+    sim_loop<MODE, MM, BATCH, LdsPolicy, QUAD>(wl, p);
 }
 
 template <int MM, bool BATCH, bool SLAB>
@@ -140,18 +140,34 @@ __global__ void __launch_bounds__(kBlock) fwd_kernel(WorkList wl) {
 //   beta  = sum phi_g (t_g - t) = sum_s x_s (dWT_s - t dW_s) - (dCT - t dC),
 // come from differences of prefix sums (over g' < g) of the 2S + 2 columns
 //   W_s = w_gs,  WT_s = w_gs t_g,  C = c_g,  CT = c_g t_g.
+// With variance weights wv and centring vhat the weight is quadratic in x,
+//   phi_g = sum_s [w (x - mhat) + wv ((x - mhat)^2 - vhat)]
+//         = sum_s [(w - 2 wv mhat) x + wv x^2] - sum_s [w mhat + wv (vhat - mhat^2)],
+// so W_s becomes w - 2 wv mhat, c_g the second sum, and 2S more columns follow:
+//   Q_s = wv_gs,  QT_s = wv_gs t_g   (4S + 2 in all).
 // The prefixes are kept as unevaluated double-double sums (hi + lo), so a difference of
 // two rows loses nothing to cancellation.  Row g (0 <= g <= G) holds the hi parts of the
-// 2S + 2 columns (binary64) followed by their lo parts (binary32), see PrefixRow.
-__device__ __forceinline__ double bwd_column(const double *w, const double *mhat, const double *grid, int32_t S,
-                                             int32_t g, int32_t k) {
+// columns (binary64) followed by their lo parts (binary32), see PrefixRow.
+__device__ __forceinline__ double bwd_column(const double *w, const double *mhat, const double *wv,
+                                             const double *vhat, const double *grid, int32_t S, int32_t g,
+                                             int32_t k) {
     if (k < 2 * S) {
         const int32_t s = k < S ? k : k - S;
-        const double v = w[(size_t)g * S + s];
+        double v = w[(size_t)g * S + s];
+        if (wv) v = v - 2.0 * wv[(size_t)g * S + s] * mhat[(size_t)g * S + s];
         return k < S ? v : v * grid[g];
     }
+    if (k >= 2 * S + 2) {
+        const int32_t s = k < 3 * S + 2 ? k - (2 * S + 2) : k - (3 * S + 2);
+        const double v = wv[(size_t)g * S + s];
+        return k < 3 * S + 2 ? v : v * grid[g];
+    }
     double c = 0.0;
-    for (int32_t s = 0; s < S; ++s) c = c + w[(size_t)g * S + s] * mhat[(size_t)g * S + s];
+    for (int32_t s = 0; s < S; ++s) {
+        const double m = mhat[(size_t)g * S + s];
+        c = c + w[(size_t)g * S + s] * m;
+        if (wv) c = c + wv[(size_t)g * S + s] * (vhat[(size_t)g * S + s] - m * m);
+    }
     return k == 2 * S ? c : c * grid[g];
 }
 
@@ -159,15 +175,17 @@ __device__ __forceinline__ double bwd_column(const double *w, const double *mhat
 // totals, then the prefix rows.
 __global__ void __launch_bounds__(256) bwd_prefix_kernel(const double *__restrict__ w,
                                                          const double *__restrict__ mhat,
+                                                         const double *__restrict__ wv,
+                                                         const double *__restrict__ vhat,
                                                          const double *__restrict__ grid, int32_t G, int32_t S,
                                                          void *__restrict__ P) {
-    const int32_t k = blockIdx.x, ncol = 2 * S + 2;
+    const int32_t k = blockIdx.x, ncol = wv ? 4 * S + 2 : 2 * S + 2;
     auto hi = [&](int32_t g) { return (double *)((char *)P + (size_t)g * 12 * ncol); };
     auto lo = [&](int32_t g) { return (float *)((char *)P + (size_t)g * 12 * ncol + 8 * (size_t)ncol); };
     const int32_t nt = blockDim.x, per = (G + nt - 1) / nt;
     const int32_t g0 = min(G, (int32_t)threadIdx.x * per), g1 = min(G, g0 + per);
     double h = 0.0, l = 0.0;
-    for (int32_t g = g0; g < g1; ++g) dd_add(h, l, bwd_column(w, mhat, grid, S, g, k), 0.0);
+    for (int32_t g = g0; g < g1; ++g) dd_add(h, l, bwd_column(w, mhat, wv, vhat, grid, S, g, k), 0.0);
     __shared__ double sh[2][256];
     sh[0][threadIdx.x] = h;
     sh[1][threadIdx.x] = l;
@@ -195,7 +213,7 @@ __global__ void __launch_bounds__(256) bwd_prefix_kernel(const double *__restric
         lo(0)[k] = 0.0f;
     }
     for (int32_t g = g0; g < g1; ++g) {
-        dd_add(h, l, bwd_column(w, mhat, grid, S, g, k), 0.0);
+        dd_add(h, l, bwd_column(w, mhat, wv, vhat, grid, S, g, k), 0.0);
         hi(g + 1)[k] = h;
         lo(g + 1)[k] = (float)l;
     }

@@ -186,17 +186,26 @@ struct PrefixRow {
 
 // Backward sums over the crossings g in [ga, gb) of one inter-event interval starting at t
 // (state x): alpha = sum_g phi_g, beta = sum_g phi_g (t_g - t), from two prefix rows.
-template <class Policy>
+// QUAD: the table also holds the variance columns Q, QT (weights quadratic in x).
+template <bool QUAD = false, class Policy>
 __device__ __forceinline__ void interval_sums(const Policy &p, const void *P, int32_t S, int32_t ga, int32_t gb,
                                               double t, double &alpha, double &beta) {
-    const int32_t ncol = 2 * S + 2;
+    const int32_t ncol = QUAD ? 4 * S + 2 : 2 * S + 2;
     const PrefixRow ra(P, ncol, ga), rb(P, ncol, gb);
     double sw = 0.0, swt = 0.0;
     p.for_each_species([&](int32_t s, int32_t xs) {
+        const double x = (double)xs;
         const double dW = ra.diff_to(rb, s);
         const double dWT = ra.diff_to(rb, S + s);
-        sw = sw + (double)xs * dW;
-        swt = swt + (double)xs * (dWT - t * dW);
+        sw = sw + x * dW;
+        swt = swt + x * (dWT - t * dW);
+        if (QUAD) {
+            const double x2 = x * x;
+            const double dQ = ra.diff_to(rb, 2 * S + 2 + s);
+            const double dQT = ra.diff_to(rb, 3 * S + 2 + s);
+            sw = sw + x2 * dQ;
+            swt = swt + x2 * (dQT - t * dQ);
+        }
     });
     const double dC = ra.diff_to(rb, 2 * S);
     const double dCT = ra.diff_to(rb, 2 * S + 1);
@@ -277,7 +286,7 @@ struct GridView {
 // The event loop.  MM is the number of propensity slots the policy evaluates (>= M), or 0
 // for networks too large to keep a_j and S_j in registers (forward only).
 // Record and backward passes: lanes are refilled as soon as their trajectory ends.
-template <int MODE, int MM, bool BATCH, class Policy>
+template <int MODE, int MM, bool BATCH, class Policy, bool QUAD = false>
 __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
     static_assert(MODE != kFwd && MM > 0, "record, backward and the event log need the per-reaction registers");
     constexpr int MR = MM > 0 ? MM : 1;
@@ -437,7 +446,7 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
                 double tb;
                 const int32_t gb = gv.next_bin(g, t_next, tb);
                 double alpha, beta;
-                interval_sums(p, n.bp, n.S, g, gb, t, alpha, beta);
+                interval_sums<QUAD>(p, n.bp, n.S, g, gb, t, alpha, beta);
 #pragma unroll
                 for (int j = 0; j < MM; ++j) gacc[j] = gacc[j] + (B[j] * alpha - a[j] * beta);
                 g = gb;

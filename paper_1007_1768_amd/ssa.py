@@ -18,7 +18,8 @@ OK, E_INVALID, E_NOMEM, E_DEVICE, E_OVERFLOW, E_EVENT_LIMIT, E_UNSUPPORTED = ran
 _NAMES = {1: "SSA_E_INVALID", 2: "SSA_E_NOMEM", 3: "SSA_E_DEVICE", 4: "SSA_E_OVERFLOW",
           5: "SSA_E_EVENT_LIMIT", 6: "SSA_E_UNSUPPORTED"}
 
-EXPORTS = ["ssa_model_create", "ssa_model_create_laws", "ssa_model_destroy", "ssa_run", "ssa_run_device", "ssa_backward_device",
+EXPORTS = ["ssa_model_create", "ssa_model_create_laws", "ssa_model_destroy", "ssa_run", "ssa_run_device",
+           "ssa_backward_device", "ssa_backward_moments_device",
            "ssa_run_jacobian_device", "ssa_jacobian_vjp", "ssa_autotune_forward", "ssa_run_cov_device",
            "ssa_hist_quantiles", "ssa_adaptive_device",
            "ssa_record", "ssa_batch_create", "ssa_batch_run", "ssa_batch_destroy", "ssa_last_error"]
@@ -64,6 +65,7 @@ def load(path=None):
     L.ssa_run.argtypes = [vp, i64, dbl, vp, i32, u64, vp, vp, vp]
     L.ssa_run_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
     L.ssa_backward_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
+    L.ssa_backward_moments_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp, vp]
     L.ssa_autotune_forward.argtypes = [vp, vp, i64, dbl, vp, i32, u64, vp, vp]
     L.ssa_run_cov_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp]
     L.ssa_hist_quantiles.argtypes = [vp, i32, vp, i64, vp, i32, vp, vp]
@@ -189,15 +191,24 @@ def run_device(model, n_traj, t_end, grid, seed, rates=None, hist=None, max_even
 
 
 def backward_device(model, n_traj, t_end, grid, seed, w, mhat, rates=None, max_events=0, stream=None,
-                    with_stats=False, out=None):
-    """LR gradient d loss / d log c (ssa_backward_device); returns (grad (M,), stats or None)."""
+                    with_stats=False, out=None, wv=None, vhat=None):
+    """LR gradient d loss / d log c (ssa_backward_device; with variance weights wv = dL/dvar
+    and centring vhat, ssa_backward_moments_device); returns (grad (M,), stats or None)."""
     import torch
     grad = torch.empty(model.M, dtype=torch.float64, device=grid.device) if out is None else out
     st = Stats() if with_stats else None
-    _check(load().ssa_backward_device(model.handle, _tp(rates), int(n_traj), float(t_end), _tp(grid),
-                                      grid.shape[0], int(seed), int(max_events), _tp(w.contiguous()),
-                                      _tp(mhat.contiguous()), _tp(grad), _stream(stream),
-                                      ctypes.byref(st) if st is not None else None))
+    L = load()
+    if wv is None:
+        _check(L.ssa_backward_device(model.handle, _tp(rates), int(n_traj), float(t_end), _tp(grid),
+                                     grid.shape[0], int(seed), int(max_events), _tp(w.contiguous()),
+                                     _tp(mhat.contiguous()), _tp(grad), _stream(stream),
+                                     ctypes.byref(st) if st is not None else None))
+    else:
+        _check(L.ssa_backward_moments_device(model.handle, _tp(rates), int(n_traj), float(t_end), _tp(grid),
+                                             grid.shape[0], int(seed), int(max_events), _tp(w.contiguous()),
+                                             _tp(mhat.contiguous()), _tp(wv.contiguous()), _tp(vhat.contiguous()),
+                                             _tp(grad), _stream(stream),
+                                             ctypes.byref(st) if st is not None else None))
     return grad, (st.as_dict() if st is not None else None)
 
 
@@ -397,10 +408,48 @@ def _make_function():
                 g, _ = backward_device(model, n_traj, t_end, grid, seed, grad_mean.contiguous(), mean, rates=rates)
             return g, None, None, None, None, None, None
 
+    class SSAMoments(torch.autograd.Function):
+        """(mean, var) = E[X(t_g)], Var[X(t_g)] over n_traj trajectories, differentiable in log
+        rate constants.  Forward ssa_run_device with rates = exp(log_rates); backward one
+        re-simulation (ssa_backward_moments_device) with both weight tensors, centred on the
+        forward mean and variance."""
+
+        @staticmethod
+        def forward(ctx, log_rates, model, n_traj, t_end, grid, seed):
+            rates = torch.exp(log_rates.detach()).contiguous()
+            mean, var, _, _ = run_device(model, n_traj, t_end, grid, seed, rates=rates)
+            ctx.save_for_backward(rates, mean, var)
+            ctx.cfg = (model, n_traj, t_end, grid, seed)
+            return mean, var
+
+        @staticmethod
+        def backward(ctx, grad_mean, grad_var):
+            model, n_traj, t_end, grid, seed = ctx.cfg
+            rates, mean, var = ctx.saved_tensors
+            if grad_mean is None:
+                grad_mean = torch.zeros_like(mean)
+            if grad_var is None:
+                g, _ = backward_device(model, n_traj, t_end, grid, seed, grad_mean.contiguous(), mean, rates=rates)
+            else:
+                g, _ = backward_device(model, n_traj, t_end, grid, seed, grad_mean.contiguous(), mean, rates=rates,
+                                       wv=grad_var.contiguous(), vhat=var)
+            return g, None, None, None, None, None
+
+    SSAMean.moments = SSAMoments
     return SSAMean
 
 
 _fn = None
+
+
+def ssa_moments(log_rates, model, n_traj, t_end, grid, seed):
+    """Differentiable grid means and variances (torch.autograd.Function over the HIP
+    kernels): returns (mean, var); gradients of a loss on either or both reach log_rates
+    through one re-simulating backward."""
+    global _fn
+    if _fn is None:
+        _fn = _make_function()
+    return _fn.moments.apply(log_rates, model, n_traj, t_end, grid, seed)
 
 
 def ssa_mean(log_rates, model, n_traj, t_end, grid, seed, mode="resim"):
