@@ -127,6 +127,14 @@ def batched_vs_plain(ssa, torch, dev):
     _, _, st = batch.run(dev, outs=(means, vars_), with_stats=True)
     torch.cuda.synchronize()
     batched_s = time.perf_counter() - t0
+    # the batch's own autotuner (window sizes timed on this batch), then the tuned replay
+    tune = batch.autotune()
+    batch.run(dev, outs=(means, vars_))                       # re-capture with the chosen window
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, st_t = batch.run(dev, outs=(means, vars_), with_stats=True)
+    torch.cuda.synchronize()
+    tuned_s = time.perf_counter() - t0
     saved = os.environ.get("SSA_KERNEL")
     os.environ["SSA_KERNEL"] = "generic"                      # the batched kernel's code path
     identical = True
@@ -151,7 +159,9 @@ def batched_vs_plain(ssa, torch, dev):
                         % sum(n["n_traj"] for n in nets),
             "events": st["events"], "batched_ms": round(batched_s * 1e3, 3), "plain_ms": round(plain_s * 1e3, 3),
             "batched_events_per_s": round(st["events"] / batched_s, 1),
-            "speedup": round(plain_s / batched_s, 3), "identical": identical}
+            "speedup": round(plain_s / batched_s, 3), "identical": identical,
+            "tuned": {"win_bytes": tune["win_bytes"], "batched_ms": round(tuned_s * 1e3, 3),
+                      "events": st_t["events"], "speedup": round(plain_s / tuned_s, 3)}}
 
 
 def wide_sweep(ssa, torch, dev):

@@ -290,6 +290,13 @@ ssa_status ssa_batch_run(ssa_batch *batch, double *const *means, double *const *
                          ssa_stats *stats);
 void ssa_batch_destroy(ssa_batch *batch);
 
+/* Autotuning of a batch: times the batched launch with each LDS window size (the
+ * built-in default, 2048 .. 16384 bytes; sizes that do not fit the LDS are skipped; results
+ * never depend on the choice) and keeps the fastest for this handle's later runs (the
+ * captured graph is rebuilt).  The trial runs write scratch outputs, not the caller's.
+ * result may be NULL (slab is always -1).  Synchronous. */
+ssa_status ssa_batch_autotune(ssa_batch *batch, void *stream, ssa_tune_result *result);
+
 /* Thread-local description of the last failure on this thread ("" if none). */
 const char *ssa_last_error(void);
 

@@ -192,6 +192,7 @@ struct ssa_batch {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int32_t win_bytes = 0;            // LDS window bytes per cohort (0: built-in default), see ssa_batch_autotune
 };
 
 namespace {
@@ -1793,7 +1794,7 @@ ssa_status batch_enqueue(ssa_batch *bt, hipStream_t st) {
     wl.stats = bt->d_stats;
     int32_t gmax = 0;
     for (int32_t g : bt->G) gmax = std::max(gmax, g);
-    wl.win_bins = window_bins(bt->s_rows, gmax, true);
+    wl.win_bins = window_bins(bt->s_rows, gmax, true, bt->win_bytes);
     wl.win_words = wl.win_bins * bt->s_rows * 2;
     FwdKernel k;
     if (!pick_generic_fwd<true>(bt->mm, k)) return fail(SSA_E_UNSUPPORTED, "no kernel");
@@ -1862,6 +1863,76 @@ ssa_status ssa_batch_run(ssa_batch *bt, double *const *means, double *const *var
     }
     if (stats && ev.b) HIP_TRY(hipEventRecord(ev.b, st));
     if (stats) return collect_stats(bt->d_stats, st, ev.a, ev.b, stats);
+    return SSA_OK;
+}
+
+ssa_status ssa_batch_autotune(ssa_batch *bt, void *stream, ssa_tune_result *result) {
+    if (!bt) return fail(SSA_E_INVALID, "batch is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    // the trial runs finalize into scratch outputs; the caller's are put back afterwards
+    HIP_TRY(hipStreamSynchronize(st));
+    StreamScratch scr(st);
+    std::vector<FinalNet> trial = bt->fin;
+    for (int32_t b = 0; b < bt->B; ++b) {
+        void *mp = nullptr, *vp = nullptr;
+        const size_t bytes = sizeof(double) * (size_t)bt->G[b] * bt->models[b]->S;
+        HIP_TRY(scr.alloc(&mp, bytes));
+        HIP_TRY(scr.alloc(&vp, bytes));
+        trial[b].mean = (double *)mp;
+        trial[b].var = (double *)vp;
+    }
+    HIP_TRY(hipMemcpyAsync(bt->d_fin, trial.data(), sizeof(FinalNet) * bt->B, hipMemcpyHostToDevice, st));
+    struct Restore {
+        ssa_batch *bt;
+        hipStream_t st;
+        ~Restore() {
+            (void)hipStreamSynchronize(st);
+            (void)hipMemcpy(bt->d_fin, bt->fin.data(), sizeof(FinalNet) * bt->B, hipMemcpyHostToDevice);
+        }
+    } restore{bt, st};
+    EventPair ev;
+    if (!ev.make()) return fail(SSA_E_DEVICE, "hipEventCreate failed");
+    const int32_t saved = bt->win_bytes;
+    float best_ms = 0.0f, default_ms = 0.0f;
+    int32_t best = -1;
+    for (int32_t wb : {0, 2048, 4096, 8192, 16384}) {
+        bt->win_bytes = wb;
+        float ms = 0.0f;
+        bool ok = true;
+        for (int rep = 0; rep < 2 && ok; ++rep) {   // the first run warms up, the second is timed
+            HIP_TRY(hipEventRecord(ev.a, st));
+            const ssa_status s = batch_enqueue(bt, st);
+            if (s == SSA_E_UNSUPPORTED) {
+                ok = false;   // window too large for the LDS: skip the candidate
+                break;
+            }
+            if (s) {
+                bt->win_bytes = saved;
+                return s;
+            }
+            HIP_TRY(hipEventRecord(ev.b, st));
+            HIP_TRY(hipEventSynchronize(ev.b));
+            HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+        }
+        if (!ok) continue;
+        if (wb == 0) default_ms = ms;
+        if (best < 0 || ms < best_ms) {
+            best = wb;
+            best_ms = ms;
+        }
+    }
+    bt->win_bytes = best < 0 ? saved : best;
+    // the captured graph holds the old window: capture again at the next run
+    if (bt->exec) (void)hipGraphExecDestroy(bt->exec);
+    if (bt->graph) (void)hipGraphDestroy(bt->graph);
+    bt->exec = nullptr;
+    bt->graph = nullptr;
+    if (result) {
+        result->win_bytes = bt->win_bytes;
+        result->slab = -1;
+        result->best_ms = best_ms;
+        result->default_ms = default_ms;
+    }
     return SSA_OK;
 }
 

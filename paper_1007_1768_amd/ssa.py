@@ -22,7 +22,8 @@ EXPORTS = ["ssa_model_create", "ssa_model_create_laws", "ssa_model_destroy", "ss
            "ssa_backward_device", "ssa_backward_moments_device",
            "ssa_run_jacobian_device", "ssa_jacobian_vjp", "ssa_autotune_forward", "ssa_run_cov_device",
            "ssa_hist_quantiles", "ssa_adaptive_device",
-           "ssa_record", "ssa_batch_create", "ssa_batch_run", "ssa_batch_destroy", "ssa_last_error"]
+           "ssa_record", "ssa_batch_create", "ssa_batch_run", "ssa_batch_autotune", "ssa_batch_destroy",
+           "ssa_last_error"]
 
 
 class SSAError(RuntimeError):
@@ -76,6 +77,7 @@ def load(path=None):
     L.ssa_batch_create.argtypes = [i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
     L.ssa_batch_run.argtypes = [vp, vp, vp, vp, vp]
     L.ssa_batch_destroy.argtypes = [vp]
+    L.ssa_batch_autotune.argtypes = [vp, vp, vp]
     L.ssa_batch_destroy.restype = None
     L.ssa_last_error.argtypes = []
     L.ssa_last_error.restype = ctypes.c_char_p
@@ -360,6 +362,12 @@ class Batch:
         st = Stats() if with_stats else None
         _check(load().ssa_batch_run(self.handle, mp, vp, _stream(stream), ctypes.byref(st) if st is not None else None))
         return means, vars_, (st.as_dict() if st is not None else None)
+
+    def autotune(self, stream=None):
+        """Time the LDS window sizes on this batch and keep the fastest (ssa_batch_autotune)."""
+        r = TuneResult()
+        _check(load().ssa_batch_autotune(self.handle, _stream(stream), ctypes.byref(r)))
+        return dict(win_bytes=r.win_bytes, best_ms=r.best_ms, default_ms=r.default_ms)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -45,3 +45,28 @@ def test_autotune_keeps_results_and_writes_cache(ssa, tmp_path, monkeypatch, gen
     assert len(keys) == 1
     assert entries[keys[0]]["win_bytes"] == r["win_bytes"] and entries[keys[0]]["slab"] == r["slab"]
     model.close()
+
+
+def test_batch_autotune_keeps_results(ssa):
+    """Batch autotuning times the window sizes on scratch outputs (the caller's last outputs
+    stay as they were), rebuilds the graph with the fastest and changes no result."""
+    nets = inputs.random_networks(count=8, G=100)
+    models = [ssa.Model.from_dict(n) for n in nets]
+    n_traj = [min(n["n_traj"], 2048) for n in nets]
+    bt = ssa.Batch(models, n_traj, [n["t_end"] for n in nets], [n["grid"] for n in nets],
+                   [n["seed"] for n in nets])
+    m1, v1, _ = bt.run(DEV)
+    torch.cuda.synchronize()
+    keep = [m.clone() for m in m1]
+    r = bt.autotune()
+    torch.cuda.synchronize()
+    assert r["win_bytes"] in (0, 2048, 4096, 8192, 16384)
+    assert r["best_ms"] > 0 and r["best_ms"] <= r["default_ms"] * 1.0001
+    assert all(torch.equal(a, b) for a, b in zip(m1, keep))
+    m2, v2, _ = bt.run(DEV)
+    torch.cuda.synchronize()
+    assert all(torch.equal(a, b) for a, b in zip(m1, m2))
+    assert all(torch.equal(a, b) for a, b in zip(v1, v2))
+    bt.close()
+    for m in models:
+        m.close()
