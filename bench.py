@@ -421,6 +421,9 @@ def main():
 
     if not args.no_batched:
         out["batched_vs_plain"] = batched_vs_plain(ssa, torch, dev)
+        # the other forms, each timed on its own workload (see --adaptive, --hiv)
+        out["adaptive_memory"] = adaptive_measure(ssa, torch, dev)
+        out["hiv_stress"] = hiv_stress(ssa, torch, dev)
 
     if not args.no_cpu_baseline:
         from oracle import oracle as orc
