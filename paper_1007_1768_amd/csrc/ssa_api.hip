@@ -1496,6 +1496,13 @@ ssa_status ssa_record(const ssa_model *m, const double *rates, int64_t traj_begi
 // Adaptive selective memory: event log -> sort by time -> moments at every distinct event
 // time (Avg-Y) -> averages of k successive points (Avg-XY).
 // ------------------------------------------------------------------------------------------
+// Records per epoch of the event log (SSA_ADAPTIVE_RECORDS overrides; at least 4096).
+int64_t adaptive_budget() {
+    int64_t b = (int64_t)1 << 26;
+    if (const char *e = std::getenv("SSA_ADAPTIVE_RECORDS")) b = std::strtoll(e, nullptr, 10);
+    return std::max<int64_t>(std::min<int64_t>(b, (int64_t)INT32_MAX - 1), 4096);
+}
+
 ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t n_traj, double t_end, uint64_t seed,
                                uint64_t max_events, int64_t k, double *xy_time, double *xy_mean, double *xy_var,
                                int64_t xy_cap, double *y_time, double *y_mean, double *y_var, int64_t y_cap,
@@ -1519,19 +1526,24 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
     StreamScratch scr(st);
     EventPair evp;
     const bool timed = stats && evp.make();
+    const int32_t S = m->S;
+    const bool sizing = !xy_time && !y_time;
 
     // one-point grid at t_end (the event loop reads a grid view; nothing is aligned to it)
     const double h_grid[1] = {t_end};
-    void *d_grid = nullptr, *ctl = nullptr, *cur = nullptr;
+    void *d_grid = nullptr, *ctl = nullptr, *cur = nullptr, *carry = nullptr;
     HIP_TRY(scr.alloc(&d_grid, sizeof(double)));
     HIP_TRY(scr.alloc(&ctl, 64 + sizeof(GridInfo)));
     HIP_TRY(scr.alloc(&cur, sizeof(unsigned long long)));
+    HIP_TRY(scr.alloc(&carry, sizeof(long long) * 3 * (size_t)S));
     HIP_TRY(hipMemcpyAsync(d_grid, h_grid, sizeof(double), hipMemcpyHostToDevice, st));
     const GridInfo hgi = host_grid_info(h_grid, 1, t_end);
     HIP_TRY(hipMemcpyAsync((char *)ctl + 64, &hgi, sizeof hgi, hipMemcpyHostToDevice, st));
-    NetDev n = base_net(m, rates, n_traj, t_end, (const double *)d_grid, 1, seed, max_events);
-    n.ginfo = (const GridInfo *)((char *)ctl + 64);
-    n.ev_cursor = (unsigned long long *)cur;
+    HIP_TRY(launch_zero(carry, sizeof(long long) * 3 * (size_t)S, st));
+    NetDev n0 = base_net(m, rates, n_traj, t_end, (const double *)d_grid, 1, seed, max_events);
+    n0.ginfo = (const GridInfo *)((char *)ctl + 64);
+    n0.ev_cursor = (unsigned long long *)cur;
+    n0.t_pause = t_end;
     WorkList wl;
     std::memset(&wl, 0, sizeof wl);
     wl.range_begin = 0;
@@ -1541,133 +1553,229 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
     wl.n_items = (int32_t)n_items;
     wl.counter = (unsigned int *)ctl;
     wl.stats = (unsigned long long *)((char *)ctl + 32);
+    unsigned long long tot_events = 0, max_steps = 0;
+    uint32_t all_flags = 0;
 
-    // pass 1 counts the records, pass 2 writes them (same trajectories, same order of draws)
-    if (timed) HIP_TRY(hipEventRecord(evp.a, st));
-    HIP_TRY(launch_zero(ctl, 64, st));
-    HIP_TRY(launch_zero(cur, sizeof(unsigned long long), st));
-    wl.net0 = n;
-    ssa_status s = launch_single(kEvt, m, wl, n_items, dev, st, rates, scr);
-    if (s) return s;
-    unsigned long long R = 0, h[3] = {0, 0, 0};
-    HIP_TRY(hipMemcpyAsync(&R, cur, sizeof R, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(h, (char *)ctl + 32, sizeof h, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipStreamSynchronize(st));
-    if (h[2] & kFlagOverflow) return fail(SSA_E_OVERFLOW, "a species count left the int32 range");
-    if (h[2] & kFlagEventLimit) return fail(SSA_E_EVENT_LIMIT, "a trajectory reached max_events before t_end");
-    if (R >= (unsigned long long)INT32_MAX) return fail(SSA_E_UNSUPPORTED, "more than 2^31 - 1 event records");
-    const int32_t nR = (int32_t)R;
-    void *k0 = nullptr, *k1 = nullptr, *v0 = nullptr, *v1 = nullptr, *stf = nullptr, *rk = nullptr;
-    const size_t rb = sizeof(unsigned long long) * std::max<size_t>(R, 1);
-    HIP_TRY(scr.alloc(&k0, rb));
-    HIP_TRY(scr.alloc(&k1, rb));
-    HIP_TRY(scr.alloc(&v0, rb));
-    HIP_TRY(scr.alloc(&v1, rb));
-    HIP_TRY(scr.alloc(&stf, sizeof(int32_t) * std::max<size_t>(R, 1)));
-    HIP_TRY(scr.alloc(&rk, sizeof(int32_t) * std::max<size_t>(R, 1)));
-    if (R > 0) {
-        n.ev_key = (unsigned long long *)k0;
-        n.ev_val = (unsigned long long *)v0;
-        n.ev_cap = (int64_t)R;
-        wl.net0 = n;
+    // One pass of the event log over the epoch (t0, t1] (the whole run when rs is NULL and
+    // t1 == t_end); R receives the records (counted even when they did not fit).
+    auto log_pass = [&](NetDev n, unsigned long long &R, unsigned long long (&h)[3]) -> ssa_status {
         HIP_TRY(launch_zero(ctl, 64, st));
         HIP_TRY(launch_zero(cur, sizeof(unsigned long long), st));
-        s = launch_single(kEvt, m, wl, n_items, dev, st, rates, scr);
+        wl.net0 = n;
+        ssa_status s = launch_single(kEvt, m, wl, n_items, dev, st, rates, scr);
         if (s) return s;
-        size_t tb = 0;
-        HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (const unsigned long long *)k0,
-                                                   (unsigned long long *)k1, (const unsigned long long *)v0,
-                                                   (unsigned long long *)v1, nR, 0, 64, st));
-        size_t tb2 = 0;
-        HIP_TRY(hipcub::DeviceScan::InclusiveSum(nullptr, tb2, (const int32_t *)stf, (int32_t *)rk, nR, st));
-        void *tmp = nullptr;
-        HIP_TRY(scr.alloc(&tmp, std::max(tb, tb2)));
-        tb = std::max(tb, tb2);
-        HIP_TRY(hipcub::DeviceRadixSort::SortPairs(tmp, tb, (const unsigned long long *)k0, (unsigned long long *)k1,
-                                                   (const unsigned long long *)v0, (unsigned long long *)v1, nR, 0, 64,
-                                                   st));
-        const unsigned gb = (unsigned)std::min<int64_t>(((int64_t)R + 255) / 256, 65535);
-        hipLaunchKernelGGL(evt_start_kernel, dim3(gb), dim3(256), 0, st, (const unsigned long long *)k1,
-                           (int64_t)R, (int32_t *)stf);
-        HIP_TRY(hipGetLastError());
-        tb2 = tb;
-        HIP_TRY(hipcub::DeviceScan::InclusiveSum(tmp, tb2, (const int32_t *)stf, (int32_t *)rk, nR, st));
-    }
-    // sizes: U = distinct event times (+ the point at time 0 unless an event happened there)
-    int32_t n_distinct = 0;
-    unsigned long long first_key = 0, h2[3] = {0, 0, 0};
-    if (R > 0) {
-        HIP_TRY(hipMemcpyAsync(&n_distinct, (int32_t *)rk + (R - 1), sizeof n_distinct, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(&first_key, k1, sizeof first_key, hipMemcpyDeviceToHost, st));
-        HIP_TRY(hipMemcpyAsync(h2, (char *)ctl + 32, sizeof h2, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&R, cur, sizeof R, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(h, (char *)ctl + 32, sizeof h, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
-        if ((h2[2] & kFlagRecordsFull) || h2[0] != h[0])
-            return fail(SSA_E_DEVICE, "the second pass logged a different number of events");
-    }
-    const int32_t off = (R > 0 && first_key == 0ull) ? 0 : 1;
-    const int64_t U = (int64_t)n_distinct + off;
-    const int64_t P = (U + k - 1) / k;
-    n_points[0] = U;
-    n_points[1] = P;
-    if (U > INT32_MAX) return fail(SSA_E_UNSUPPORTED, "more than 2^31 - 1 Avg-Y points");
-    if (!xy_time && !y_time) return SSA_OK;   // size query
-    if (xy_time && xy_cap < P) return fail(SSA_E_INVALID, "Avg-XY needs %lld points (capacity %lld)", (long long)P,
-                                           (long long)xy_cap);
-    if (y_time && y_cap < U)
-        return fail(SSA_E_INVALID, "Avg-Y needs %lld points (capacity %lld)", (long long)U, (long long)y_cap);
+        if (h[2] & kFlagOverflow) return fail(SSA_E_OVERFLOW, "a species count left the int32 range");
+        if (h[2] & kFlagEventLimit) return fail(SSA_E_EVENT_LIMIT, "a trajectory reached max_events before t_end");
+        return SSA_OK;
+    };
 
-    // Avg-Y: exact difference sums per point, prefix over the points, moments
-    const int32_t S = m->S;
-    void *D = nullptr, *Dhi = nullptr, *yt = y_time, *ym = y_mean, *yv = y_var;
-    HIP_TRY(scr.alloc(&D, sizeof(unsigned long long) * (size_t)U * S * 2));
-    HIP_TRY(scr.alloc(&Dhi, sizeof(unsigned long long) * (size_t)U * S));
-    if (!y_time) {
-        HIP_TRY(scr.alloc(&yt, sizeof(double) * (size_t)U));
-        HIP_TRY(scr.alloc(&ym, sizeof(double) * (size_t)U * S));
-        HIP_TRY(scr.alloc(&yv, sizeof(double) * (size_t)U * S));
-    }
-    HIP_TRY(launch_zero(D, sizeof(unsigned long long) * (size_t)U * S * 2, st));
-    HIP_TRY(launch_zero(Dhi, sizeof(unsigned long long) * (size_t)U * S, st));
-    HIP_TRY(launch_zero(yt, sizeof(double), st));   // time 0 (overwritten if an event happened there)
-    if (R > 0) {
-        const unsigned gb = (unsigned)std::min<int64_t>(((int64_t)R + 255) / 256, 65535);
-        hipLaunchKernelGGL(evt_diff_kernel, dim3(gb), dim3(256), 0, st, (const unsigned long long *)k1,
-                           (const unsigned long long *)v1, (const int32_t *)stf, (const int32_t *)rk, (int64_t)R, off,
-                           S, (unsigned long long *)D, (unsigned long long *)Dhi, (double *)yt);
-        HIP_TRY(hipGetLastError());
-    }
+    if (timed) HIP_TRY(hipEventRecord(evp.a, st));
+    // count the whole run's records once: a run that fits the budget is one epoch
+    unsigned long long R_all = 0, h0[3] = {0, 0, 0};
+    ssa_status s = log_pass(n0, R_all, h0);
+    if (s) return s;
+    const int64_t budget = adaptive_budget();
+    const bool epochs = (int64_t)R_all > budget;
+    void *keys0 = nullptr, *keys1 = nullptr, *vals0 = nullptr, *vals1 = nullptr, *stf = nullptr, *rk = nullptr;
+    const int64_t cap = std::max<int64_t>(1, std::min<int64_t>((int64_t)R_all, budget));
+    HIP_TRY(scr.alloc(&keys0, sizeof(unsigned long long) * (size_t)cap));
+    HIP_TRY(scr.alloc(&keys1, sizeof(unsigned long long) * (size_t)cap));
+    HIP_TRY(scr.alloc(&vals0, sizeof(unsigned long long) * (size_t)cap));
+    HIP_TRY(scr.alloc(&vals1, sizeof(unsigned long long) * (size_t)cap));
+    HIP_TRY(scr.alloc(&stf, sizeof(int32_t) * (size_t)cap));
+    HIP_TRY(scr.alloc(&rk, sizeof(int32_t) * (size_t)cap));
+    void *sort_tmp = nullptr;
+    size_t sort_tmp_bytes = 0;
     {
-        // exact prefix over the points in chunks, then the moments
-        const int64_t n_chunks = (U + kFinChunk - 1) / kFinChunk;
-        if (n_chunks > 65535 * 2048ll) return fail(SSA_E_UNSUPPORTED, "too many Avg-Y points");
-        void *T = nullptr;
-        HIP_TRY(scr.alloc(&T, sizeof(long long) * (size_t)n_chunks * S * 3));
-        hipLaunchKernelGGL(chunk_total_kernel, dim3((unsigned)n_chunks, (unsigned)S), dim3(256), 0, st,
-                           (const unsigned long long *)D, (const unsigned long long *)Dhi, U, S, (long long *)T);
-        HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(chunk_scan_kernel, dim3((unsigned)S), dim3(1024), 0, st, (long long *)T, n_chunks, S);
-        HIP_TRY(hipGetLastError());
-        hipLaunchKernelGGL(chunk_final_kernel, dim3((unsigned)n_chunks, (unsigned)S), dim3(256), 0, st,
-                           (const unsigned long long *)D, (const unsigned long long *)Dhi, U, S, (const long long *)T,
-                           (const int32_t *)m->d_x0, n_traj, (double *)ym, (double *)yv);
-        HIP_TRY(hipGetLastError());
+        size_t tb = 0, tb2 = 0;
+        HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (const unsigned long long *)keys0,
+                                                   (unsigned long long *)keys1, (const unsigned long long *)vals0,
+                                                   (unsigned long long *)vals1, (int)cap, 0, 64, st));
+        HIP_TRY(hipcub::DeviceScan::InclusiveSum(nullptr, tb2, (const int32_t *)stf, (int32_t *)rk, (int)cap, st));
+        sort_tmp_bytes = std::max(tb, tb2);
+        HIP_TRY(scr.alloc(&sort_tmp, sort_tmp_bytes));
     }
-    if (xy_time) {
-        const int64_t work = P * ((int64_t)S + 1);
-        const unsigned gb = (unsigned)std::min<int64_t>((work + 255) / 256, 65535);
-        hipLaunchKernelGGL(xy_kernel, dim3(gb), dim3(256), 0, st, (const double *)yt, (const double *)ym,
-                           (const double *)yv, U, S, k, P, xy_time, xy_mean, xy_var);
-        HIP_TRY(hipGetLastError());
+    // epochs: saved trajectory states, double-buffered
+    void *sx[2] = {nullptr, nullptr}, *stt[2] = {nullptr, nullptr}, *skk[2] = {nullptr, nullptr},
+         *sev[2] = {nullptr, nullptr};
+    if (epochs) {
+        for (int b = 0; b < 2; ++b) {
+            HIP_TRY(scr.alloc(&sx[b], sizeof(int32_t) * (size_t)n_traj * S));
+            HIP_TRY(scr.alloc(&stt[b], sizeof(double) * (size_t)n_traj));
+            HIP_TRY(scr.alloc(&skk[b], sizeof(uint64_t) * (size_t)n_traj));
+            HIP_TRY(scr.alloc(&sev[b], sizeof(uint64_t) * (size_t)n_traj));
+        }
     }
+
+    // Avg-XY across epochs: the points of a group not yet complete wait in front of the
+    // next epoch's points (work arrays: pending points, then this epoch's)
+    int64_t U_tot = 0, P_done = 0, n_pend = 0;
+    void *pend_t = nullptr, *pend_m = nullptr, *pend_v = nullptr;
+    if (epochs && !sizing) {
+        HIP_TRY(scr.alloc(&pend_t, sizeof(double) * (size_t)k));
+        HIP_TRY(scr.alloc(&pend_m, sizeof(double) * (size_t)k * S));
+        HIP_TRY(scr.alloc(&pend_v, sizeof(double) * (size_t)k * S));
+    }
+    double t0 = 0.0, span = epochs ? t_end * (double)budget / (1.25 * (double)R_all) : t_end;
+    int sb = 0;          // state buffer holding the current states (epochs)
+    bool first = true;
+    for (;;) {
+        const double t1 = (!epochs || t0 + span >= t_end) ? t_end : t0 + span;
+        NetDev n = n0;
+        n.t_pause = t1;
+        n.ev_key = (unsigned long long *)keys0;
+        n.ev_val = (unsigned long long *)vals0;
+        n.ev_cap = cap;
+        if (epochs) {
+            if (!first) {
+                n.rs_x = (const int32_t *)sx[sb];
+                n.rs_t = (const double *)stt[sb];
+                n.rs_k = (const uint64_t *)skk[sb];
+                n.rs_ev = (const uint64_t *)sev[sb];
+            }
+            n.ws_x = (int32_t *)sx[1 - sb];
+            n.ws_t = (double *)stt[1 - sb];
+            n.ws_k = (uint64_t *)skk[1 - sb];
+            n.ws_ev = (uint64_t *)sev[1 - sb];
+        }
+        unsigned long long R = 0, h[3] = {0, 0, 0};
+        s = log_pass(n, R, h);
+        if (s) return s;
+        if ((int64_t)R > cap) {
+            // the epoch did not fit: shorten it and run it again from the same states
+            if (!epochs) return fail(SSA_E_DEVICE, "the event log changed between passes");
+            span = (t1 - t0) * 0.8 * (double)cap / (double)R;
+            if (!(span > 0.0) || t0 + span <= t0) return fail(SSA_E_UNSUPPORTED, "too many events at one time");
+            continue;
+        }
+        tot_events += h[0];
+        max_steps = std::max(max_steps, h[1]);
+        all_flags |= (uint32_t)h[2];
+
+        // time order and the distinct-time ranks of this epoch's records
+        const int32_t nR = (int32_t)R;
+        int32_t n_distinct = 0;
+        unsigned long long first_key = 0;
+        if (R > 0) {
+            size_t tb = sort_tmp_bytes;
+            HIP_TRY(hipcub::DeviceRadixSort::SortPairs(sort_tmp, tb, (const unsigned long long *)keys0,
+                                                       (unsigned long long *)keys1, (const unsigned long long *)vals0,
+                                                       (unsigned long long *)vals1, nR, 0, 64, st));
+            const unsigned gb = (unsigned)std::min<int64_t>(((int64_t)R + 255) / 256, 65535);
+            hipLaunchKernelGGL(evt_start_kernel, dim3(gb), dim3(256), 0, st, (const unsigned long long *)keys1,
+                               (int64_t)R, (int32_t *)stf);
+            HIP_TRY(hipGetLastError());
+            tb = sort_tmp_bytes;
+            HIP_TRY(hipcub::DeviceScan::InclusiveSum(sort_tmp, tb, (const int32_t *)stf, (int32_t *)rk, nR, st));
+            HIP_TRY(hipMemcpyAsync(&n_distinct, (int32_t *)rk + (R - 1), sizeof n_distinct, hipMemcpyDeviceToHost,
+                                   st));
+            HIP_TRY(hipMemcpyAsync(&first_key, keys1, sizeof first_key, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+        }
+        // the point at time 0 (initial state) unless an event happened exactly then
+        const int32_t off = (first && (R == 0 || first_key != 0ull)) ? 1 : 0;
+        const int64_t U_e = (int64_t)n_distinct + off;
+        if (U_tot + U_e > INT32_MAX) return fail(SSA_E_UNSUPPORTED, "more than 2^31 - 1 Avg-Y points");
+
+        const bool last = t1 >= t_end;
+        if (!sizing && (U_e > 0 || (last && n_pend > 0))) {
+            // Avg-Y of this epoch's points into the work arrays, after the pending ones
+            // (scratch of this epoch only: returned to the pool at the end of the block)
+            StreamScratch escr(st);
+            const int64_t W = n_pend + U_e;
+            void *D = nullptr, *Dhi = nullptr, *wt = nullptr, *wm = nullptr, *wv = nullptr, *T = nullptr;
+            HIP_TRY(escr.alloc(&wt, sizeof(double) * (size_t)W));
+            HIP_TRY(escr.alloc(&wm, sizeof(double) * (size_t)W * S));
+            HIP_TRY(escr.alloc(&wv, sizeof(double) * (size_t)W * S));
+            double *et = (double *)wt + n_pend, *em = (double *)wm + n_pend * S, *evv = (double *)wv + n_pend * S;
+            if (U_e > 0) {
+                HIP_TRY(escr.alloc(&D, sizeof(unsigned long long) * (size_t)U_e * S * 2));
+                HIP_TRY(escr.alloc(&Dhi, sizeof(unsigned long long) * (size_t)U_e * S));
+                HIP_TRY(launch_zero(D, sizeof(unsigned long long) * (size_t)U_e * S * 2, st));
+                HIP_TRY(launch_zero(Dhi, sizeof(unsigned long long) * (size_t)U_e * S, st));
+                HIP_TRY(launch_zero(et, sizeof(double), st));   // time 0 (overwritten if an event happened there)
+                if (R > 0) {
+                    const unsigned gb = (unsigned)std::min<int64_t>(((int64_t)R + 255) / 256, 65535);
+                    hipLaunchKernelGGL(evt_diff_kernel, dim3(gb), dim3(256), 0, st, (const unsigned long long *)keys1,
+                                       (const unsigned long long *)vals1, (const int32_t *)stf, (const int32_t *)rk,
+                                       (int64_t)R, off, S, (unsigned long long *)D, (unsigned long long *)Dhi, et);
+                    HIP_TRY(hipGetLastError());
+                }
+                const int64_t n_chunks = (U_e + kFinChunk - 1) / kFinChunk;
+                HIP_TRY(escr.alloc(&T, sizeof(long long) * (size_t)n_chunks * S * 3));
+                hipLaunchKernelGGL(chunk_total_kernel, dim3((unsigned)n_chunks, (unsigned)S), dim3(256), 0, st,
+                                   (const unsigned long long *)D, (const unsigned long long *)Dhi, U_e, S, (long long *)T);
+                HIP_TRY(hipGetLastError());
+                hipLaunchKernelGGL(chunk_scan_kernel, dim3((unsigned)S), dim3(1024), 0, st, (long long *)T, n_chunks, S,
+                                   (long long *)carry);
+                HIP_TRY(hipGetLastError());
+                hipLaunchKernelGGL(chunk_final_kernel, dim3((unsigned)n_chunks, (unsigned)S), dim3(256), 0, st,
+                                   (const unsigned long long *)D, (const unsigned long long *)Dhi, U_e, S,
+                                   (const long long *)T, (const int32_t *)m->d_x0, n_traj, em, evv);
+                HIP_TRY(hipGetLastError());
+                if (y_time && U_tot + U_e <= y_cap) {
+                    HIP_TRY(hipMemcpyAsync(y_time + U_tot, et, sizeof(double) * (size_t)U_e, hipMemcpyDeviceToDevice, st));
+                    HIP_TRY(hipMemcpyAsync(y_mean + U_tot * S, em, sizeof(double) * (size_t)U_e * S,
+                                           hipMemcpyDeviceToDevice, st));
+                    HIP_TRY(hipMemcpyAsync(y_var + U_tot * S, evv, sizeof(double) * (size_t)U_e * S,
+                                           hipMemcpyDeviceToDevice, st));
+                }
+            }
+            if (n_pend > 0) {
+                HIP_TRY(hipMemcpyAsync(wt, pend_t, sizeof(double) * (size_t)n_pend, hipMemcpyDeviceToDevice, st));
+                HIP_TRY(hipMemcpyAsync(wm, pend_m, sizeof(double) * (size_t)n_pend * S, hipMemcpyDeviceToDevice, st));
+                HIP_TRY(hipMemcpyAsync(wv, pend_v, sizeof(double) * (size_t)n_pend * S, hipMemcpyDeviceToDevice, st));
+            }
+            // the complete groups (all of them after the last epoch)
+            const int64_t P_e = last ? (W + k - 1) / k : W / k;
+            if (xy_time && P_e > 0 && P_done + P_e <= xy_cap) {
+                const int64_t work = P_e * ((int64_t)S + 1);
+                const unsigned gb = (unsigned)std::min<int64_t>((work + 255) / 256, 65535);
+                hipLaunchKernelGGL(xy_kernel, dim3(gb), dim3(256), 0, st, (const double *)wt, (const double *)wm,
+                                   (const double *)wv, W, S, k, P_e, xy_time + P_done, xy_mean + P_done * S,
+                                   xy_var + P_done * S);
+                HIP_TRY(hipGetLastError());
+            }
+            const int64_t rest = W - P_e * k;
+            if (rest > 0 && epochs) {
+                HIP_TRY(hipMemcpyAsync(pend_t, (double *)wt + P_e * k, sizeof(double) * (size_t)rest,
+                                       hipMemcpyDeviceToDevice, st));
+                HIP_TRY(hipMemcpyAsync(pend_m, (double *)wm + P_e * k * S, sizeof(double) * (size_t)rest * S,
+                                       hipMemcpyDeviceToDevice, st));
+                HIP_TRY(hipMemcpyAsync(pend_v, (double *)wv + P_e * k * S, sizeof(double) * (size_t)rest * S,
+                                       hipMemcpyDeviceToDevice, st));
+            }
+            P_done += P_e;
+            n_pend = rest;
+            HIP_TRY(hipStreamSynchronize(st));   // the epoch's scratch is reused by the next one
+        }
+        U_tot += U_e;
+        first = false;
+        if (t1 >= t_end) break;
+        t0 = t1;
+        sb = 1 - sb;
+        span = std::min(span * 1.25, t_end);  // let a quiet stretch take a longer epoch
+    }
+    const int64_t P = (U_tot + k - 1) / k;
+    n_points[0] = U_tot;
+    n_points[1] = P;
     if (timed) HIP_TRY(hipEventRecord(evp.b, st));
     if (stats) {
         HIP_TRY(hipStreamSynchronize(st));
-        stats->events = h[0];
-        stats->max_steps = h[1];
-        stats->flags = (uint32_t)h[2];
+        stats->events = epochs ? tot_events : h0[0];
+        stats->max_steps = epochs ? max_steps : h0[1];
+        stats->flags = epochs ? all_flags : (uint32_t)h0[2];
         stats->kernel_ms = 0.0f;
         if (timed) (void)hipEventElapsedTime(&stats->kernel_ms, evp.a, evp.b);
     }
+    if (sizing) return SSA_OK;
+    if (xy_time && xy_cap < P) return fail(SSA_E_INVALID, "Avg-XY needs %lld points (capacity %lld)", (long long)P,
+                                           (long long)xy_cap);
+    if (y_time && y_cap < U_tot)
+        return fail(SSA_E_INVALID, "Avg-Y needs %lld points (capacity %lld)", (long long)U_tot, (long long)y_cap);
     return SSA_OK;
 }
 

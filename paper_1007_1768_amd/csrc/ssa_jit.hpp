@@ -28,6 +28,10 @@ struct RegPolicy {
         }
     }
     __device__ __forceinline__ void reset(const NetDev &) { Net::init(x); }
+    __device__ __forceinline__ void load_state(const int32_t *src) {
+#pragma unroll
+        for (int s = 0; s < Net::S; ++s) x[s] = src[s];
+    }
     template <int MM>
     __device__ __forceinline__ void eval(const NetDev &, double (&a)[MM]) const {
         static_assert(MM == Net::M, "one propensity slot per reaction");

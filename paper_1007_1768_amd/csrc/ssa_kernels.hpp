@@ -51,6 +51,9 @@ struct LdsPolicy {
         const SSA_CONST int32_t *x0 = (const SSA_CONST int32_t *)n.x0;
         for (int32_t s = 0; s < S; ++s) xc[(s + 1) * kBlock] = x0[s];
     }
+    __device__ void load_state(const int32_t *src) {
+        for (int32_t s = 0; s < S; ++s) xc[(s + 1) * kBlock] = src[s];
+    }
     template <int MM>
     __device__ __forceinline__ void eval(const NetDev &n, double (&a)[MM]) const {
         const SSA_CONST uint32_t *rx = (const SSA_CONST uint32_t *)n.rx;
@@ -433,8 +436,11 @@ __global__ void __launch_bounds__(256) chunk_total_kernel(const unsigned long lo
     if (threadIdx.x < 3) T[((size_t)c * S + s) * 3 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-// Step 2: exclusive prefix of the chunk totals per species (one block per species).
-__global__ void __launch_bounds__(1024) chunk_scan_kernel(long long *__restrict__ T, int64_t n_chunks, int32_t S) {
+// Step 2: exclusive prefix of the chunk totals per species (one block per species),
+// starting from carry[s][3] (the sums of earlier epochs; NULL = 0), whose entries are then
+// advanced to include this call's totals.
+__global__ void __launch_bounds__(1024) chunk_scan_kernel(long long *__restrict__ T, int64_t n_chunks, int32_t S,
+                                                          long long *__restrict__ carry) {
     const int32_t s = blockIdx.x;
     const int64_t per = (n_chunks + blockDim.x - 1) / blockDim.x;
     const int64_t c0 = min(n_chunks, (int64_t)threadIdx.x * per), c1 = min(n_chunks, c0 + per);
@@ -452,14 +458,20 @@ __global__ void __launch_bounds__(1024) chunk_scan_kernel(long long *__restrict_
         for (int i = 0; i < 3; ++i) sh[i][threadIdx.x] += v[i];
         __syncthreads();
     }
+    int64_t base[3] = {0, 0, 0};
+    if (carry)
+        for (int i = 0; i < 3; ++i) base[i] = carry[(size_t)s * 3 + i];
     int64_t run[3];
-    for (int i = 0; i < 3; ++i) run[i] = sh[i][threadIdx.x] - a[i];
+    for (int i = 0; i < 3; ++i) run[i] = base[i] + sh[i][threadIdx.x] - a[i];
     for (int64_t c = c0; c < c1; ++c)
         for (int i = 0; i < 3; ++i) {
             const int64_t v = T[((size_t)c * S + s) * 3 + i];
             T[((size_t)c * S + s) * 3 + i] = run[i];
             run[i] += v;
         }
+    __syncthreads();   // every thread has read base before the carry moves on
+    if (carry && threadIdx.x == blockDim.x - 1)
+        for (int i = 0; i < 3; ++i) carry[(size_t)s * 3 + i] = base[i] + sh[i][threadIdx.x];
 }
 
 // Step 3: within each chunk, the inclusive prefix (4 points per thread, then a block scan)

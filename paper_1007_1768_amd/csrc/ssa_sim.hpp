@@ -114,6 +114,17 @@ struct NetDev {
     // with ev_key == nullptr only the cursor counts
     unsigned long long *ev_key, *ev_val, *ev_cursor;
     int64_t ev_cap;
+    // event log in epochs: each trajectory starts from a saved state (rs_*, or the initial
+    // state when rs_t is NULL) and stops before its first event beyond t_pause, saving its
+    // state to ws_*: counts [n_traj][S], time (-1 once the trajectory has ended), the next
+    // draw's index and the events applied so far
+    const int32_t *rs_x;
+    const double *rs_t;
+    const uint64_t *rs_k, *rs_ev;
+    int32_t *ws_x;
+    double *ws_t;
+    uint64_t *ws_k, *ws_ev;
+    double t_pause;
 };
 
 // Event-log record value: species (12 bits) | change (20-bit two's complement) << 12 |
@@ -313,6 +324,8 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
     uint32_t ovf = 0;
     uint32_t flags = 0;
     unsigned long long tot_events = 0, max_steps = 0;
+    uint64_t ev_start = 0;     // event log in epochs: events before this epoch
+    bool gone = false;         // event log in epochs: the trajectory ended in an earlier epoch
     double a[MR];
     double Ssum[MR];
     // record: A_j and n_j; backward: the score B_j = n_j - A_j at the current event time
@@ -376,6 +389,18 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
                     tg_cur = gv.uniform ? 0.0 : ((const SSA_CONST double *)gv.grid)[0];
                     ovf = 0;
                     p.reset(n);
+                    ev_start = 0;
+                    if (MODE == kEvt && n.rs_t) {
+                        t = n.rs_t[traj];
+                        k = n.rs_k[traj];
+                        ev = n.rs_ev[traj];
+                        p.load_state(n.rs_x + (size_t)traj * n.S);
+                        ev_start = ev;
+                        if (t < 0.0) {            // ended in an earlier epoch
+                            t = n.t_end;
+                            gone = true;
+                        }
+                    }
                     if (MODE == kRec) {
 #pragma unroll
                         for (int j = 0; j < MM; ++j) { A[j] = 0.0; nf[j] = 0; }
@@ -455,6 +480,18 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
         }
 
         bool finish = t_next > n.t_end;
+        bool pause = false;
+        if (MODE == kEvt && n.ws_t) {
+            // epochs: an ended trajectory stays ended; an event beyond the epoch waits for the
+            // next one, which redraws the same Philox block from the same state
+            if (gone) {
+                finish = true;
+            } else if (!finish && t_next > n.t_pause) {
+                finish = true;
+                pause = true;
+                if (acc != 0.0) k = k - 1;
+            }
+        }
         if (!finish && ev >= n.max_events) {
             flags |= kFlagEventLimit;
             finish = true;
@@ -558,9 +595,17 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
                 for (int j = 0; j < MM; ++j)
                     if (j < M) n.gtraj[(size_t)traj * M + j] = gacc[j];
             }
-            tot_events += ev;
+            if (MODE == kEvt && n.ws_t) {
+                int32_t *wx = n.ws_x + (size_t)traj * n.S;
+                p.for_each_species([&](int32_t s, int32_t xs) { wx[s] = xs; });
+                n.ws_t[traj] = pause ? t : -1.0;
+                n.ws_k[traj] = k;
+                n.ws_ev[traj] = ev;
+            }
+            tot_events += ev - ev_start;
             max_steps = max(max_steps, (unsigned long long)ev);
             active = false;
+            gone = false;
         }
     }
 

@@ -90,11 +90,15 @@ def test_batched_workload_full_size_sampled_networks(ssa):
         mo.close()
 
 
-def test_adaptive_viral_full_size(ssa):
+@pytest.mark.parametrize("budget", [None, "3000000"])
+def test_adaptive_viral_full_size(ssa, monkeypatch, budget):
     """Adaptive selective memory on the viral workload (10^4 trajectories, t_end 50, groups
-    of k = 10^4 points): every Avg-Y point time equal to the oracle's union of event times,
-    and the Avg-XY points of the first, a middle and the last group bit-identical to the
-    oracle's evaluation of those groups."""
+    of k = 10^4 points), in one pass and in epochs of at most 3·10^6 records: every Avg-Y
+    point time equal to the oracle's union of event times, and the Avg-XY points of the
+    first, a middle and the last group bit-identical to the oracle's evaluation of those
+    groups."""
+    if budget:
+        monkeypatch.setenv("SSA_ADAPTIVE_RECORDS", budget)
     w = inputs.WORKLOADS["viral"]
     m = w["model"]()
     N, t_end, seed, k = w["n_traj"], w["t_end"], w["seed"], w["n_traj"]
