@@ -1496,9 +1496,10 @@ ssa_status ssa_record(const ssa_model *m, const double *rates, int64_t traj_begi
 // Adaptive selective memory: event log -> sort by time -> moments at every distinct event
 // time (Avg-Y) -> averages of k successive points (Avg-XY).
 // ------------------------------------------------------------------------------------------
-// Records per epoch of the event log (SSA_ADAPTIVE_RECORDS overrides; at least 4096).
+// Records per epoch of the event log (SSA_ADAPTIVE_RECORDS overrides; at least 4096).  At
+// 2^27 records an epoch holds about 17 GB of log, sums and points.
 int64_t adaptive_budget() {
-    int64_t b = (int64_t)1 << 26;
+    int64_t b = (int64_t)1 << 27;
     if (const char *e = std::getenv("SSA_ADAPTIVE_RECORDS")) b = std::strtoll(e, nullptr, 10);
     return std::max<int64_t>(std::min<int64_t>(b, (int64_t)INT32_MAX - 1), 4096);
 }
@@ -1732,11 +1733,9 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
             // the complete groups (all of them after the last epoch)
             const int64_t P_e = last ? (W + k - 1) / k : W / k;
             if (xy_time && P_e > 0 && P_done + P_e <= xy_cap) {
-                const int64_t work = P_e * ((int64_t)S + 1);
-                const unsigned gb = (unsigned)std::min<int64_t>((work + 255) / 256, 65535);
-                hipLaunchKernelGGL(xy_kernel, dim3(gb), dim3(256), 0, st, (const double *)wt, (const double *)wm,
-                                   (const double *)wv, W, S, k, P_e, xy_time + P_done, xy_mean + P_done * S,
-                                   xy_var + P_done * S);
+                hipLaunchKernelGGL(xy_kernel, dim3((unsigned)P_e, (unsigned)(S + 1)), dim3(kWave), 0, st,
+                                   (const double *)wt, (const double *)wm, (const double *)wv, W, S, k, P_e,
+                                   xy_time + P_done, xy_mean + P_done * S, xy_var + P_done * S);
                 HIP_TRY(hipGetLastError());
             }
             const int64_t rest = W - P_e * k;
@@ -1755,9 +1754,11 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
         U_tot += U_e;
         first = false;
         if (t1 >= t_end) break;
+        // the next epoch's length from this one's fill (records are not uniform in time)
+        const double fill = 0.85 * (double)cap / (double)std::max<unsigned long long>(R, 1ull);
+        span = std::min((t1 - t0) * std::min(std::max(fill, 0.5), 4.0), t_end);
         t0 = t1;
         sb = 1 - sb;
-        span = std::min(span * 1.25, t_end);  // let a quiet stretch take a longer epoch
     }
     const int64_t P = (U_tot + k - 1) / k;
     n_points[0] = U_tot;

@@ -794,55 +794,67 @@ __global__ void evt_diff_kernel(const unsigned long long *__restrict__ key, cons
     }
 }
 
-// Avg-XY: groups of k successive Avg-Y points (the last one may be shorter); one thread per
-// (group, column), column S being the time.  Each sum runs left to right, then one division
-// by the group's size.
-__global__ void xy_kernel(const double *__restrict__ y_time, const double *__restrict__ y_mean,
-                          const double *__restrict__ y_var, int64_t U, int32_t S, int64_t k, int64_t P,
-                          double *__restrict__ xy_time, double *__restrict__ xy_mean, double *__restrict__ xy_var) {
-    const int64_t cols = (int64_t)S + 1;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < P * cols;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t p = i / cols;
-        const int32_t c = (int32_t)(i - p * cols);
-        const int64_t u0 = p * k, u1 = min(u0 + k, U);
-        const double kk = (double)(u1 - u0);
-        // values are loaded 16 at a time so their latencies overlap; the sums stay sequential
-        constexpr int kB = 16;
-        if (c == S) {
-            double ts = 0.0;
-            int64_t u = u0;
-            for (; u + kB <= u1; u += kB) {
-                double b[kB];
-#pragma unroll
-                for (int i = 0; i < kB; ++i) b[i] = y_time[u + i];
-#pragma unroll
-                for (int i = 0; i < kB; ++i) ts = ts + b[i];
+// Avg-XY: groups of k successive Avg-Y points (the last one may be shorter).  One wave per
+// (group, column), column S being the time: the wave loads 64 consecutive points at a time
+// and adds them in order through lane broadcasts, so each sum is the plain left-to-right
+// binary64 sum (then one division by the group's size), while the next 64 loads are in
+// flight -- a single thread per group was bound by load latency at k = 10^6.
+__device__ __forceinline__ double readlane_f64(double v, int32_t l) {
+    const long long b = __double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((unsigned long long)b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__global__ void __launch_bounds__(64) xy_kernel(const double *__restrict__ y_time, const double *__restrict__ y_mean,
+                                                const double *__restrict__ y_var, int64_t U, int32_t S, int64_t k,
+                                                int64_t P, double *__restrict__ xy_time,
+                                                double *__restrict__ xy_mean, double *__restrict__ xy_var) {
+    const int64_t p = blockIdx.x;
+    const int32_t c = blockIdx.y;
+    const int32_t lane = (int32_t)threadIdx.x;
+    if (p >= P) return;
+    const int64_t u0 = p * k, u1 = min(u0 + k, U);
+    const double kk = (double)(u1 - u0);
+    const bool tcol = c == S;
+    auto load = [&](int64_t u, double &a, double &b) {
+        a = 0.0;
+        b = 0.0;
+        if (u < u1) {
+            if (tcol) {
+                a = y_time[u];
+            } else {
+                a = y_mean[(size_t)u * S + c];
+                b = y_var[(size_t)u * S + c];
             }
-            for (; u < u1; ++u) ts = ts + y_time[u];
-            xy_time[p] = ts / kk;
+        }
+    };
+    double s1 = 0.0, s2 = 0.0;
+    double a, b;
+    load(u0 + lane, a, b);
+    for (int64_t base = u0; base < u1; base += kWave) {
+        const double ca = a, cb = b;
+        load(base + kWave + lane, a, b);     // the next 64 points
+        const int64_t nb = min((int64_t)kWave, u1 - base);
+        if (nb == kWave) {
+#pragma unroll
+            for (int32_t i = 0; i < kWave; ++i) {
+                s1 = s1 + readlane_f64(ca, i);
+                if (!tcol) s2 = s2 + readlane_f64(cb, i);
+            }
         } else {
-            double ms = 0.0, vs = 0.0;
-            int64_t u = u0;
-            for (; u + kB <= u1; u += kB) {
-                double bm[kB], bv[kB];
-#pragma unroll
-                for (int i = 0; i < kB; ++i) {
-                    bm[i] = y_mean[(size_t)(u + i) * S + c];
-                    bv[i] = y_var[(size_t)(u + i) * S + c];
-                }
-#pragma unroll
-                for (int i = 0; i < kB; ++i) {
-                    ms = ms + bm[i];
-                    vs = vs + bv[i];
-                }
+            for (int32_t i = 0; i < (int32_t)nb; ++i) {
+                s1 = s1 + readlane_f64(ca, i);
+                if (!tcol) s2 = s2 + readlane_f64(cb, i);
             }
-            for (; u < u1; ++u) {
-                ms = ms + y_mean[(size_t)u * S + c];
-                vs = vs + y_var[(size_t)u * S + c];
-            }
-            xy_mean[(size_t)p * S + c] = ms / kk;
-            xy_var[(size_t)p * S + c] = vs / kk;
+        }
+    }
+    if (lane == 0) {
+        if (tcol) {
+            xy_time[p] = s1 / kk;
+        } else {
+            xy_mean[(size_t)p * S + c] = s1 / kk;
+            xy_var[(size_t)p * S + c] = s2 / kk;
         }
     }
 }
