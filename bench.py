@@ -263,6 +263,38 @@ def hiv_stress(ssa, torch, dev, N=16384, t_end=5.0, G=101, seed=7, reps=2):
             "events_per_s": round(best["events"] / best["kernel_ms"] * 1e3, 1)}
 
 
+def throughput_case(ssa, torch, dev, name="large", steps=3, warmup=1):
+    """The same step (forward mean/var + LR backward) on a workload that fills the chip
+    (large: 10^6 trajectories, 10^4-point grid, histogram): kernel times and the
+    roofline fraction of both kernels, for comparison with the latency-bound default."""
+    m, w = workload(name)
+    N, t_end, G, seed = w["n_traj"], w["t_end"], w["G"], w["seed"]
+    grid = torch.tensor(inputs.uniform_grid(t_end, G), dtype=torch.float64, device=dev)
+    model = ssa.Model.from_dict(m)
+    hist = w.get("hist")
+    prates = torch.tensor(inputs.perturbed_rates(m, w.get("perturb_seed", 404)), device=dev)
+    target, _, _, _ = ssa.run_device(model, N, t_end, grid, w.get("target_seed", 44), rates=prates)
+    fw, bw = [], []
+    for i in range(warmup + steps):
+        mean, var, _, sf = ssa.run_device(model, N, t_end, grid, seed, hist=hist, with_stats=True)
+        _, sb = ssa.backward_device(model, N, t_end, grid, seed, 2.0 * (mean - target), mean, with_stats=True)
+        if i >= warmup:
+            fw.append(sf["kernel_ms"])
+            bw.append(sb["kernel_ms"])
+    torch.cuda.synchronize()
+    model.close()
+    S = m["reac"].shape[1]
+    crossings = G * N / max(sf["events"], 1)
+    f_ms, b_ms = float(np.mean(fw)), float(np.mean(bw))
+    f_ops = w_forward(m, min(1.0, crossings), mean_changes(m)) * sf["events"] / (f_ms * 1e-3)
+    b_ops = w_backward(m, crossings) * sf["events"] / (b_ms * 1e-3)
+    return {"workload": "%s: %d trajectories, t_end %g, %d-point grid%s, forward mean/var + LR backward"
+                        % (name, N, t_end, G, ", histogram" if hist else ""),
+            "events": sf["events"], "fwd_kernel_ms": round(f_ms, 3), "bwd_kernel_ms": round(b_ms, 3),
+            "events_per_s": round(sf["events"] / ((f_ms + b_ms) * 1e-3), 1),
+            "fwd_valu_frac": round(f_ops / PEAK_LANE_OPS, 4), "bwd_valu_frac": round(b_ops / PEAK_LANE_OPS, 4)}
+
+
 def workload(name):
     w = dict(inputs.WORKLOADS[name])
     m = w["model"]()
@@ -428,6 +460,7 @@ def main():
     if not args.no_batched:
         out["batched_vs_plain"] = batched_vs_plain(ssa, torch, dev)
         # the other forms, each timed on its own workload (see --adaptive, --hiv)
+        out["throughput_case"] = throughput_case(ssa, torch, dev)
         out["adaptive_memory"] = adaptive_measure(ssa, torch, dev)
         out["hiv_stress"] = hiv_stress(ssa, torch, dev)
 
