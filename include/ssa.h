@@ -107,7 +107,7 @@ typedef struct {
  *     reactions the chunk lives in registers, above that in LDS, where an event
  *     re-evaluates only the propensities that read a species it changed (a dependency
  *     graph built here; same results as re-evaluating all, which SSA_WIDE_DEPG=0 selects);
- *     backward needs M <= 512 (SSA_E_UNSUPPORTED beyond); not accepted by ssa_batch_create.
+ *     not accepted by ssa_batch_create.
  * The arrays are copied (to the current device); the handle is immutable and may be shared
  * by threads that use the same device.  Errors: SSA_E_INVALID, SSA_E_UNSUPPORTED,
  * SSA_E_NOMEM, SSA_E_DEVICE. */
@@ -163,8 +163,7 @@ ssa_status ssa_run_device(const ssa_model *model, const double *rates, int64_t n
  * rates [M] (NULL = model's), grid [G], w [G*S] (dL/dmean), mhat [G*S] (centring, usually
  * the forward mean), grad [M] output.  The per-trajectory sums are reduced in a fixed
  * pairwise order, so the result is deterministic.  Same status codes as ssa_run_device
- * (SSA_E_UNSUPPORTED for a SEQ model with more than 32 reactions or a BLOCK64 model with
- * more than 512). */
+ * (SSA_E_UNSUPPORTED for a SEQ model with more than 32 reactions). */
 ssa_status ssa_backward_device(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
                                const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events,
                                const double *w, const double *mhat, double *grad, void *stream,

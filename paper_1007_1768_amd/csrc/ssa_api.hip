@@ -583,9 +583,12 @@ hipError_t launch_wide(const ssa_model *m, const WorkList &wl, int dev, hipStrea
     const void *kern = depg ? wide_for<MODE, true>(m->q) : wide_for<MODE, false>(m->q);
     if (!kern) return hipErrorInvalidValue;
     const int32_t Q = m->q <= 16 ? 16 : (m->q <= 32 ? 32 : 64);
-    const size_t lds = (size_t)Q * kWave * (depg ? 8 : 12) + ((size_t)m->S + 1) * sizeof(int32_t);
+    const size_t lds = (size_t)Q * kWave * ((depg ? 8 : 12) + (MODE == kBwd ? 16 : 0)) +
+                       ((size_t)m->S + 1) * sizeof(int32_t);
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave, lds);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kWave, lds);
     if (e != hipSuccess) return e;
     const int64_t n_traj = wl.range_end - wl.range_begin;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(per_cu, 1) * cu_count(dev), n_traj));
@@ -595,10 +598,7 @@ hipError_t launch_wide(const ssa_model *m, const WorkList &wl, int dev, hipStrea
 
 template <int MODE>
 hipError_t launch_wave(const ssa_model *m, const WorkList &wl, int dev, hipStream_t st, StreamScratch &scr) {
-    if (m->q > kWaveMaxQ) {
-        if constexpr (MODE == kBwd) return hipErrorInvalidValue;
-        else return launch_wide<MODE>(m, wl, dev, st, scr);
-    }
+    if (m->q > kWaveMaxQ) return launch_wide<MODE>(m, wl, dev, st, scr);
     const void *kern = nullptr;
     if (m->q <= 1) kern = (const void *)wave_kernel<1, MODE>;
     else if (m->q <= 2) kern = (const void *)wave_kernel<2, MODE>;
@@ -1367,9 +1367,6 @@ ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, 
     if (!(t_end >= 0.0) || !std::isfinite(t_end)) return fail(SSA_E_INVALID, "t_end must be finite and >= 0");
     if (m->order == SSA_SUM_SEQ && m->M > kJitMaxReactions)
         return fail(SSA_E_UNSUPPORTED, "backward supports at most %d reactions", kJitMaxReactions);
-    if (m->order == SSA_SUM_BLOCK64 && m->q > kWaveMaxQ)
-        return fail(SSA_E_UNSUPPORTED, "backward in the 64-chunk order supports at most %d reactions",
-                    kWaveMaxQ * kWave);
     if (m->has_laws) return fail(SSA_E_UNSUPPORTED, "the score of a rate law is not n_j - A_j: no backward");
     if (n_traj > ((int64_t)1 << 31) * kChunk) return fail(SSA_E_INVALID, "n_traj too large");
     hipStream_t st = (hipStream_t)stream;
@@ -1419,7 +1416,7 @@ ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, 
         std::swap(src, dst);
         rows = orows;
     }
-    hipLaunchKernelGGL(scale_kernel, dim3(1), dim3(std::max(64, ((m->M + 63) / 64) * 64)), 0, st, src, m->M,
+    hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((m->M + 255) / 256)), dim3(256), 0, st, src, m->M,
                        1.0 / (double)n_traj, grad);
     HIP_TRY(hipGetLastError());
     if (stats) return collect_stats(wl.stats, st, ev.a, ev.b, stats);

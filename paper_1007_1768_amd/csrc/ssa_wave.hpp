@@ -311,18 +311,22 @@ __global__ void dep_rate_kernel(const int2 *dep, int32_t q, const double *rate, 
 // what is computed.
 //
 // Modes: forward (moment differences and histogram straight into the network totals, as
-// above) and record (per-trajectory grid states; the n_j and A_j rows accumulate in the
-// caller's output arrays).
+// above), record (per-trajectory grid states; the n_j and A_j rows accumulate in the
+// caller's output arrays) and backward (the score B_j and the gradient accumulator of every
+// slot in two more LDS rows each, updated as in the register kernel; the crossings'
+// alpha, beta from the prefix rows with the species spread over the lanes).
 template <int Q, int MODE, bool DEPG>
 __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
-    static_assert(MODE == kFwd || MODE == kRec, "forward and record only");
     extern __shared__ double lds_d[];
     const uint32_t lane = __lane_id();
     const NetDev n = wl.net0;
     const int32_t S = n.S, M = n.M, G = n.G, q = n.q;
     double *av = lds_d;                                             // [Q][64] propensities | rates
-    uint32_t *cw = (uint32_t *)(lds_d + Q * kWave);                 // [Q][64] codes (without DEPG)
-    int32_t *xl = (int32_t *)(lds_d + Q * kWave) + (DEPG ? 0 : Q * kWave);
+    double *bsc = lds_d + Q * kWave;                                // backward: [Q][64] scores B_j
+    double *gac = bsc + (MODE == kBwd ? Q * kWave : 0);             // backward: [Q][64] accumulators
+    double *after = gac + (MODE == kBwd ? Q * kWave : 0);
+    uint32_t *cw = (uint32_t *)after;                               // [Q][64] codes (without DEPG)
+    int32_t *xl = (int32_t *)after + (DEPG ? 0 : Q * kWave);
     // real slots of this lane: reactions lane q .. lane q + nreal - 1
     const int32_t nreal = max(0, min(q, M - (int32_t)lane * q));
     const int32_t last_lane = (M - 1) / q;
@@ -375,6 +379,13 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
                 if (n.rec_aint) n.rec_aint[r * M + j] = 0.0;
             }
         }
+        if (MODE == kBwd) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                bsc[i * kWave + lane] = 0.0;
+                gac[i * kWave + lane] = 0.0;
+            }
+        }
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
 
@@ -425,6 +436,37 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
                     for (int32_t s = lane; s < S; s += kWave) rows[(size_t)g * S + s] = xl[s + 1];
                     ++g;
                 }
+            } else if (MODE == kBwd) {
+                // crossings [g, gb) of this interval from two prefix rows; the species are
+                // spread over the lanes, every slot's accumulator takes B_j alpha - a_j beta
+                if (g < G && tg_next < t_next) {
+                    double tb;
+                    const int32_t gb = gv.next_bin(g, t_next, tb);
+                    const int32_t ncol = 2 * S + 2;
+                    const PrefixRow ra(n.bp, ncol, g), rb(n.bp, ncol, gb);
+                    double sw = 0.0, swt = 0.0;
+                    for (int32_t s = lane; s < S; s += kWave) {
+                        const double xs = (double)xl[s + 1];
+                        const double dW = ra.diff_to(rb, s);
+                        const double dWT = ra.diff_to(rb, S + s);
+                        sw = sw + xs * dW;
+                        swt = swt + xs * (dWT - t * dW);
+                    }
+                    sw = wave_sum_f64(sw);
+                    swt = wave_sum_f64(swt);
+                    const double dC = ra.diff_to(rb, 2 * S);
+                    const double dCT = ra.diff_to(rb, 2 * S + 1);
+                    const double alpha = sw - dC;
+                    const double beta = swt - (dCT - t * dC);
+                    for (int32_t i = 0; i < nreal; ++i) {
+                        const double ai = DEPG ? av[i * kWave + lane]
+                                               : wave_propensity(cw[i * kWave + lane], av[i * kWave + lane], xl);
+                        double &gi = gac[i * kWave + lane];
+                        gi = gi + (bsc[i * kWave + lane] * alpha - ai * beta);
+                    }
+                    g = gb;
+                    tg_next = tb;
+                }
             }
             if (t_next > n.t_end) break;
             if (ev >= n.max_events) {
@@ -464,6 +506,16 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
             sel = wave_uniform(sel);
             sel_lane = wave_uniform(sel_lane);
 
+            if (MODE == kBwd) {
+                // B_j += [j fired] - a_j tau with the propensities before the event
+                for (int32_t i = 0; i < nreal; ++i) {
+                    const double ai = DEPG ? av[i * kWave + lane]
+                                           : wave_propensity(cw[i * kWave + lane], av[i * kWave + lane], xl);
+                    const int32_t j = (int32_t)lane * q + i;
+                    double &bi = bsc[i * kWave + lane];
+                    bi = bi + ((j == sel ? 1.0 : 0.0) - ai * tau);
+                }
+            }
             if (MODE == kRec) {
                 // A_j += a_j tau with the propensities of the state before the event
                 if (n.rec_aint) {
@@ -570,6 +622,10 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
                     *pa = *pa + ai * tail;
                 }
             }
+        }
+        if (MODE == kBwd) {
+            for (int32_t i = 0; i < nreal; ++i)
+                n.gtraj[(size_t)traj * M + (int32_t)lane * q + i] = gac[i * kWave + lane];
         }
         tot_events += ev;
         max_steps = max(max_steps, (unsigned long long)ev);

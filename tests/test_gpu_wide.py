@@ -4,7 +4,8 @@ Networks of 600 (10 per lane), 1500 (24, ragged last chunk) and 4096 reactions (
 lane, the limit).  Both the dependency-graph update (default) and the full re-evaluation
 (SSA_WIDE_DEPG=0) must reproduce the oracle's 64-chunk trajectories bit for bit: record
 mode (grid states, events, draws, last event time, n_j, A_j) and forward moments with a
-histogram; rates passed at run time override the model's in both.
+histogram; rates passed at run time override the model's in both.  The backward keeps the
+scores and accumulators in LDS and matches the oracle's gradient within 1e-12 of its scale.
 """
 import os
 
@@ -109,12 +110,36 @@ def test_wide_rates_override(ssa, update):
         assert np.array_equal(rec["a_int"][i], r["a_int"]), i
 
 
-def test_wide_backward_unsupported(ssa):
+@pytest.mark.parametrize("M", [600, 1500])
+def test_wide_backward_matches_oracle(ssa, update, M):
+    """The backward of the LDS-resident kernel (scores and accumulators in LDS rows) against
+    the oracle's gradient in the same sum order, within 1e-12 of its L1 scale."""
+    m = inputs.wide_network(M)
+    N, t_end, G, seed = 96, 0.5, 11, 13
+    grid = inputs.uniform_grid(t_end, G)
+    st, ref = orc.run(m, N, t_end, grid, seed)
+    assert st == 0
+    w = np.random.default_rng(M).normal(size=ref["mean"].shape)
+    model = ssa.Model.from_dict(m)
+    g, stats = ssa.backward_device(model, N, t_end, torch.tensor(grid, device=DEV), seed,
+                                   torch.tensor(w, device=DEV), torch.tensor(ref["mean"], device=DEV),
+                                   with_stats=True)
+    torch.cuda.synchronize()
+    model.close()
+    st, gref, l1 = orc.grad(m, N, t_end, grid, seed, w, ref["mean"])
+    assert st == 0
+    d = np.abs(g.cpu().numpy() - gref)
+    assert np.all(d <= 1e-12 * l1 + 1e-300), (d / np.maximum(l1, 1e-300)).max()
+    assert stats["events"] == ref["events"]
+
+
+def test_wide_variance_weights_unsupported(ssa):
     m = inputs.wide_network(600)
     grid = inputs.uniform_grid(1.0, 5)
     model = ssa.Model.from_dict(m)
-    w = torch.zeros(5 * m["reac"].shape[1], dtype=torch.float64, device=DEV)
+    S = m["reac"].shape[1]
+    w = torch.zeros((5, S), dtype=torch.float64, device=DEV)
     with pytest.raises(ssa.SSAError) as e:
-        ssa.backward_device(model, 64, 1.0, torch.tensor(grid, device=DEV), 1, w, w)
+        ssa.backward_device(model, 64, 1.0, torch.tensor(grid, device=DEV), 1, w, w, wv=w, vhat=w)
     assert e.value.status == ssa.E_UNSUPPORTED
     model.close()
