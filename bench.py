@@ -82,14 +82,14 @@ def w_backward(model, crossings_per_event):
 
 
 def kernel_sources_hash():
-    """FNV-1a 64 over the device sources (the .hpp headers every kernel is built from), to tie
-    stored counter readings to the kernels they came from."""
+    """FNV-1a 64 over the sources of the network-specialised kernels (the headers they are
+    compiled from at run time), to tie stored counter readings of those kernels to the code
+    they came from."""
     h = 0xcbf29ce484222325
     d = os.path.join(ROOT, "paper_1007_1768_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith(".hpp"):
-            for byte in open(os.path.join(d, f), "rb").read():
-                h = ((h ^ byte) * 0x100000001b3) & 0xffffffffffffffff
+    for f in ("ssa_device.hpp", "ssa_jit.hpp", "ssa_sim.hpp"):
+        for byte in open(os.path.join(d, f), "rb").read():
+            h = ((h ^ byte) * 0x100000001b3) & 0xffffffffffffffff
     return "%016x" % h
 
 
