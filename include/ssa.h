@@ -176,8 +176,8 @@ ssa_status ssa_backward_device(const ssa_model *model, const double *rates, int6
  * = E[(X - mu)^2 z] since E[X - mu] = 0; E[z] = 0 makes the centring unbiased).  The weights
  * are folded into prefix tables of w - 2 wv mhat, wv and their constants, evaluated as a
  * polynomial in x per interval, so the rounding error scales with wv (x^2 + mhat^2 + |vhat|)
- * rather than with the centred square.  wv == NULL gives ssa_backward_device.  SSA_SUM_SEQ
- * models only (SSA_E_UNSUPPORTED otherwise); other limits and codes as ssa_backward_device. */
+ * rather than with the centred square.  wv == NULL gives ssa_backward_device.  Limits and
+ * codes as ssa_backward_device. */
 ssa_status ssa_backward_moments_device(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
                                        const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events,
                                        const double *w, const double *mhat, const double *wv, const double *vhat,

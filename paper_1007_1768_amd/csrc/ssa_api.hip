@@ -633,7 +633,6 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
     (void)n_items;
     if (m->order == SSA_SUM_BLOCK64) {
         if (mode == kEvt) return fail(SSA_E_UNSUPPORTED, "the event log runs the sequential sum order");
-        if (quad) return fail(SSA_E_UNSUPPORTED, "variance weights need the sequential sum order");
         HIP_TRY(mode == kRec ? launch_wave<kRec>(m, wl, dev, st, scr) : launch_wave<kBwd>(m, wl, dev, st, scr));
         return SSA_OK;
     }
@@ -1389,6 +1388,7 @@ ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, 
                        bp);
     HIP_TRY(hipGetLastError());
     n.bp = bp;
+    n.bp_quad = quad ? 1 : 0;
     n.gtraj = (double *)gt;
     WorkList wl;
     std::memset(&wl, 0, sizeof wl);

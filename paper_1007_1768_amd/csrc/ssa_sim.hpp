@@ -106,9 +106,12 @@ struct NetDev {
     double *rec_tlast;
     int64_t *rec_nf;
     double *rec_aint;
-    // backward: prefix rows [G+1] (see PrefixRow), per-trajectory rows [n_traj][M]
+    // backward: prefix rows [G+1] (see PrefixRow), per-trajectory rows [n_traj][M]; bp_quad:
+    // the rows carry the variance columns (one-trajectory-per-wave kernels read it; the
+    // lane kernels are instantiated per layout)
     const void *bp;
     double *gtraj;
+    int32_t bp_quad;
     // event log: one record per changed species of every applied event, appended at
     // ev_cursor (key: the event time's bits; value: packed species, change, old count);
     // with ev_key == nullptr only the cursor counts

@@ -37,6 +37,38 @@ __device__ __forceinline__ double wave_sum_f64(double v) {
     return v;
 }
 
+// Backward sums alpha, beta over the crossings [ga, gb) of an interval starting at t (see
+// interval_sums), one trajectory per wave: the species are spread over the lanes and summed
+// across the wave.  With n.bp_quad the table carries the variance columns (weights
+// quadratic in x).
+__device__ __forceinline__ void wave_interval_sums(const NetDev &n, const int32_t *xl, int32_t ga, int32_t gb,
+                                                   double t, uint32_t lane, double &alpha, double &beta) {
+    const int32_t S = n.S;
+    const int32_t ncol = n.bp_quad ? 4 * S + 2 : 2 * S + 2;
+    const PrefixRow ra(n.bp, ncol, ga), rb(n.bp, ncol, gb);
+    double sw = 0.0, swt = 0.0;
+    for (int32_t s = lane; s < S; s += kWave) {
+        const double xs = (double)xl[s + 1];
+        const double dW = ra.diff_to(rb, s);
+        const double dWT = ra.diff_to(rb, S + s);
+        sw = sw + xs * dW;
+        swt = swt + xs * (dWT - t * dW);
+        if (n.bp_quad) {
+            const double x2 = xs * xs;
+            const double dQ = ra.diff_to(rb, 2 * S + 2 + s);
+            const double dQT = ra.diff_to(rb, 3 * S + 2 + s);
+            sw = sw + x2 * dQ;
+            swt = swt + x2 * (dQT - t * dQ);
+        }
+    }
+    sw = wave_sum_f64(sw);
+    swt = wave_sum_f64(swt);
+    const double dC = ra.diff_to(rb, 2 * S);
+    const double dCT = ra.diff_to(rb, 2 * S + 1);
+    alpha = sw - dC;
+    beta = swt - (dCT - t * dC);
+}
+
 // LDS: one row of (S + 1) int32 per wave.
 template <int Q, int MODE>
 __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
@@ -147,22 +179,8 @@ __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
                 if (g < G && tg_next < t_next) {
                     double tb;
                     const int32_t gb = gv.next_bin(g, t_next, tb);
-                    const int32_t ncol = 2 * S + 2;
-                    const PrefixRow ra(n.bp, ncol, g), rb(n.bp, ncol, gb);
-                    double sw = 0.0, swt = 0.0;
-                    for (int32_t s = lane; s < S; s += kWave) {
-                        const double xs = (double)xl[s + 1];
-                        const double dW = ra.diff_to(rb, s);
-                        const double dWT = ra.diff_to(rb, S + s);
-                        sw = sw + xs * dW;
-                        swt = swt + xs * (dWT - t * dW);
-                    }
-                    sw = wave_sum_f64(sw);
-                    swt = wave_sum_f64(swt);
-                    const double dC = ra.diff_to(rb, 2 * S);
-                    const double dCT = ra.diff_to(rb, 2 * S + 1);
-                    const double alpha = sw - dC;
-                    const double beta = swt - (dCT - t * dC);
+                    double alpha, beta;
+                    wave_interval_sums(n, xl, g, gb, t, lane, alpha, beta);
 #pragma unroll
                     for (int i = 0; i < Q; ++i) gacc[i] = gacc[i] + (B[i] * alpha - a[i] * beta);
                     g = gb;
@@ -442,22 +460,8 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
                 if (g < G && tg_next < t_next) {
                     double tb;
                     const int32_t gb = gv.next_bin(g, t_next, tb);
-                    const int32_t ncol = 2 * S + 2;
-                    const PrefixRow ra(n.bp, ncol, g), rb(n.bp, ncol, gb);
-                    double sw = 0.0, swt = 0.0;
-                    for (int32_t s = lane; s < S; s += kWave) {
-                        const double xs = (double)xl[s + 1];
-                        const double dW = ra.diff_to(rb, s);
-                        const double dWT = ra.diff_to(rb, S + s);
-                        sw = sw + xs * dW;
-                        swt = swt + xs * (dWT - t * dW);
-                    }
-                    sw = wave_sum_f64(sw);
-                    swt = wave_sum_f64(swt);
-                    const double dC = ra.diff_to(rb, 2 * S);
-                    const double dCT = ra.diff_to(rb, 2 * S + 1);
-                    const double alpha = sw - dC;
-                    const double beta = swt - (dCT - t * dC);
+                    double alpha, beta;
+                    wave_interval_sums(n, xl, g, gb, t, lane, alpha, beta);
                     for (int32_t i = 0; i < nreal; ++i) {
                         const double ai = DEPG ? av[i * kWave + lane]
                                                : wave_propensity(cw[i * kWave + lane], av[i * kWave + lane], xl);

@@ -105,13 +105,29 @@ def test_moments_autograd(ssa):
     assert torch.equal(lr.grad, g)
 
 
-def test_variance_weights_need_sequential_order(ssa):
-    m = dict(inputs.viral())
-    m["sum_order"] = "block64"
+@pytest.mark.parametrize("M", [9, 600])
+def test_variance_gradient_64_chunk_order(ssa, M):
+    """The one-trajectory-per-wave backward (registers up to 8 reactions per lane, LDS rows
+    above) with variance weights, against the oracle in the same sum order."""
+    if M == 9:
+        m = dict(inputs.viral())
+        m["sum_order"] = "block64"
+        N, t_end, G, seed = 200, 4.0, 13, 8
+    else:
+        m = inputs.wide_network(M)
+        N, t_end, G, seed = 96, 0.5, 11, 13
+    grid = inputs.uniform_grid(t_end, G)
+    st, ref = orc.run(m, N, t_end, grid, seed)
+    assert st == 0
+    rng = np.random.default_rng(M)
+    w = rng.normal(size=ref["mean"].shape)
+    wv = rng.normal(size=ref["mean"].shape) / (1.0 + ref["var"])
     model = ssa.Model.from_dict(m)
-    grid = _t(inputs.uniform_grid(1.0, 3))
-    z = torch.zeros((3, 4), dtype=torch.float64, device=DEV)
-    with pytest.raises(ssa.SSAError) as e:
-        ssa.backward_device(model, 64, 1.0, grid, 1, z, z, wv=z, vhat=z)
-    assert e.value.status == ssa.E_UNSUPPORTED
+    g, _ = ssa.backward_device(model, N, t_end, _t(grid), seed, _t(w), _t(ref["mean"]), wv=_t(wv),
+                               vhat=_t(ref["var"]))
+    torch.cuda.synchronize()
     model.close()
+    st, gref, l1 = orc.grad(m, N, t_end, grid, seed, w, ref["mean"], wv=wv, vhat=ref["var"])
+    assert st == 0
+    d = np.abs(g.cpu().numpy() - gref)
+    assert np.all(d <= 1e-12 * l1 + 1e-300), (d / np.maximum(l1, 1e-300)).max()

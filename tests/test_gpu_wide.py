@@ -131,15 +131,3 @@ def test_wide_backward_matches_oracle(ssa, update, M):
     d = np.abs(g.cpu().numpy() - gref)
     assert np.all(d <= 1e-12 * l1 + 1e-300), (d / np.maximum(l1, 1e-300)).max()
     assert stats["events"] == ref["events"]
-
-
-def test_wide_variance_weights_unsupported(ssa):
-    m = inputs.wide_network(600)
-    grid = inputs.uniform_grid(1.0, 5)
-    model = ssa.Model.from_dict(m)
-    S = m["reac"].shape[1]
-    w = torch.zeros((5, S), dtype=torch.float64, device=DEV)
-    with pytest.raises(ssa.SSAError) as e:
-        ssa.backward_device(model, 64, 1.0, torch.tensor(grid, device=DEV), 1, w, w, wv=w, vhat=w)
-    assert e.value.status == ssa.E_UNSUPPORTED
-    model.close()
