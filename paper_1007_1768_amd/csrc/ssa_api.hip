@@ -1377,7 +1377,9 @@ ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, 
     void *gt = nullptr, *gt2 = nullptr, *ctl = nullptr, *bp = nullptr;
     const size_t rows_bytes = sizeof(double) * (size_t)n_traj * m->M;
     const int32_t ncol = quad ? 4 * m->S + 2 : 2 * m->S + 2;
+    void *bpt = nullptr;
     HIP_TRY(scr.alloc(&bp, (size_t)12 * ncol * ((size_t)G + 1)));
+    HIP_TRY(scr.alloc(&bpt, sizeof(double) * ncol * (size_t)G));
     HIP_TRY(scr.alloc(&gt, rows_bytes));
     HIP_TRY(scr.alloc(&gt2, rows_bytes / 2 + sizeof(double) * m->M));
     HIP_TRY(scr.alloc(&ctl, 64 + sizeof(GridInfo)));
@@ -1385,9 +1387,10 @@ ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, 
     n.ginfo = (const GridInfo *)((char *)ctl + 64);
     HIP_TRY(launch_grid_info(grid, G, t_end, (GridInfo *)n.ginfo, st));
     hipLaunchKernelGGL(bwd_prefix_kernel, dim3((unsigned)ncol), dim3(256), 0, st, w, mhat, wv, vhat, grid, G, m->S,
-                       bp);
+                       bp, (double *)bpt);
     HIP_TRY(hipGetLastError());
     n.bp = bp;
+    n.bpt = (const double *)bpt;
     n.bp_quad = quad ? 1 : 0;
     n.gtraj = (double *)gt;
     WorkList wl;

@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(256) bwd_prefix_kernel(const double *__restric
                                                          const double *__restrict__ wv,
                                                          const double *__restrict__ vhat,
                                                          const double *__restrict__ grid, int32_t G, int32_t S,
-                                                         void *__restrict__ P) {
+                                                         void *__restrict__ P, double *__restrict__ PT) {
     const int32_t k = blockIdx.x, ncol = wv ? 4 * S + 2 : 2 * S + 2;
     auto hi = [&](int32_t g) { return (double *)((char *)P + (size_t)g * 12 * ncol); };
     auto lo = [&](int32_t g) { return (float *)((char *)P + (size_t)g * 12 * ncol + 8 * (size_t)ncol); };
@@ -216,7 +216,9 @@ __global__ void __launch_bounds__(256) bwd_prefix_kernel(const double *__restric
         lo(0)[k] = 0.0f;
     }
     for (int32_t g = g0; g < g1; ++g) {
-        dd_add(h, l, bwd_column(w, mhat, wv, vhat, grid, S, g, k), 0.0);
+        const double v = bwd_column(w, mhat, wv, vhat, grid, S, g, k);
+        if (PT) PT[(size_t)g * ncol + k] = v;    // the point's own row, for one-crossing intervals
+        dd_add(h, l, v, 0.0);
         hi(g + 1)[k] = h;
         lo(g + 1)[k] = (float)l;
     }

@@ -110,6 +110,7 @@ struct NetDev {
     // the rows carry the variance columns (one-trajectory-per-wave kernels read it; the
     // lane kernels are instantiated per layout)
     const void *bp;
+    const double *bpt;       // the column values of each grid point [G][ncol] (one-crossing intervals)
     double *gtraj;
     int32_t bp_quad;
     // event log: one record per changed species of every applied event, appended at
@@ -199,13 +200,12 @@ struct PrefixRow {
 };
 
 // Backward sums over the crossings g in [ga, gb) of one inter-event interval starting at t
-// (state x): alpha = sum_g phi_g, beta = sum_g phi_g (t_g - t), from two prefix rows.
-// QUAD: the table also holds the variance columns Q, QT (weights quadratic in x).
-template <bool QUAD = false, class Policy>
-__device__ __forceinline__ void interval_sums(const Policy &p, const void *P, int32_t S, int32_t ga, int32_t gb,
-                                              double t, double &alpha, double &beta) {
-    const int32_t ncol = QUAD ? 4 * S + 2 : 2 * S + 2;
-    const PrefixRow ra(P, ncol, ga), rb(P, ncol, gb);
+// (state x): alpha = sum_g phi_g, beta = sum_g phi_g (t_g - t), from two rows: prefix rows
+// (their differences) or, for a single crossing, the point's own row.  QUAD: the rows also
+// hold the variance columns Q, QT (weights quadratic in x).
+template <bool QUAD, class Policy, class Row>
+__device__ __forceinline__ void interval_sums_rows(const Policy &p, const Row &ra, const Row &rb, int32_t S, double t,
+                                                   double &alpha, double &beta) {
     double sw = 0.0, swt = 0.0;
     p.for_each_species([&](int32_t s, int32_t xs) {
         const double x = (double)xs;
@@ -225,6 +225,26 @@ __device__ __forceinline__ void interval_sums(const Policy &p, const void *P, in
     const double dCT = ra.diff_to(rb, 2 * S + 1);
     alpha = sw - dC;
     beta = swt - (dCT - t * dC);
+}
+
+// A grid point's own column values: an interval with one crossing needs no prefix
+// difference (alpha = phi_g, beta = phi_g (t_g - t)).
+struct PointRow {
+    const double *v;
+    __device__ __forceinline__ double diff_to(const PointRow &, int32_t c) const { return v[c]; }
+};
+
+template <bool QUAD = false, class Policy>
+__device__ __forceinline__ void interval_sums(const Policy &p, const void *P, const double *PT, int32_t S,
+                                              int32_t ga, int32_t gb, double t, double &alpha, double &beta) {
+    const int32_t ncol = QUAD ? 4 * S + 2 : 2 * S + 2;
+    if (PT && gb == ga + 1) {
+        const PointRow r{PT + (size_t)ga * ncol};
+        interval_sums_rows<QUAD>(p, r, r, S, t, alpha, beta);
+    } else {
+        const PrefixRow ra(P, ncol, ga), rb(P, ncol, gb);
+        interval_sums_rows<QUAD>(p, ra, rb, S, t, alpha, beta);
+    }
 }
 
 // Wave-uniform copies (scalar registers) of values every lane holds identically.
@@ -474,7 +494,7 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
                 double tb;
                 const int32_t gb = gv.next_bin(g, t_next, tb);
                 double alpha, beta;
-                interval_sums<QUAD>(p, n.bp, n.S, g, gb, t, alpha, beta);
+                interval_sums<QUAD>(p, n.bp, n.bpt, n.S, g, gb, t, alpha, beta);
 #pragma unroll
                 for (int j = 0; j < MM; ++j) gacc[j] = gacc[j] + (B[j] * alpha - a[j] * beta);
                 g = gb;
