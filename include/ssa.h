@@ -242,9 +242,8 @@ ssa_status ssa_run_cov_device(const ssa_model *model, const double *rates, int64
  * With xy_time and y_time both NULL the call only sizes (the simulation still runs).
  * Capacities below U / P give SSA_E_INVALID with n_points filled.  Scratch: about
  * 40 bytes per logged species change plus 40 S bytes per Avg-Y point.  Synchronises the
- * stream.  Needs a SSA_SUM_SEQ model with M <= 32 and at most 4 changed species per
- * reaction (SSA_E_UNSUPPORTED otherwise), n_traj <= 2^30 and fewer than 2^31 logged
- * changes. */
+ * stream.  Needs at most 4 changed species per reaction and, in the sequential order,
+ * M <= 32 (SSA_E_UNSUPPORTED otherwise); n_traj <= 2^30. */
 ssa_status ssa_adaptive_device(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
                                uint64_t seed, uint64_t max_events, int64_t k, double *xy_time, double *xy_mean,
                                double *xy_var, int64_t xy_cap, double *y_time, double *y_mean, double *y_var,

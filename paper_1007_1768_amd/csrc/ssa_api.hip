@@ -632,8 +632,9 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
                          const double *user_rates, StreamScratch &scr, bool quad = false) {
     (void)n_items;
     if (m->order == SSA_SUM_BLOCK64) {
-        if (mode == kEvt) return fail(SSA_E_UNSUPPORTED, "the event log runs the sequential sum order");
-        HIP_TRY(mode == kRec ? launch_wave<kRec>(m, wl, dev, st, scr) : launch_wave<kBwd>(m, wl, dev, st, scr));
+        HIP_TRY(mode == kRec   ? launch_wave<kRec>(m, wl, dev, st, scr)
+                : mode == kEvt ? launch_wave<kEvt>(m, wl, dev, st, scr)
+                               : launch_wave<kBwd>(m, wl, dev, st, scr));
         return SSA_OK;
     }
     if (jit_eligible(m)) {
@@ -1513,9 +1514,9 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
     if (n_traj <= 0 || n_traj > ((int64_t)1 << 30)) return fail(SSA_E_INVALID, "need 1 <= n_traj <= 2^30");
     if (k <= 0) return fail(SSA_E_INVALID, "k must be >= 1");
     if (!(t_end >= 0.0) || !std::isfinite(t_end)) return fail(SSA_E_INVALID, "t_end must be finite and >= 0");
-    if (m->order != SSA_SUM_SEQ) return fail(SSA_E_UNSUPPORTED, "the event log runs the sequential sum order");
-    if (m->M > kJitMaxReactions)
-        return fail(SSA_E_UNSUPPORTED, "the event log supports at most %d reactions", kJitMaxReactions);
+    if (m->order == SSA_SUM_SEQ && m->M > kJitMaxReactions)
+        return fail(SSA_E_UNSUPPORTED, "the event log in the sequential order supports at most %d reactions",
+                    kJitMaxReactions);
     if (m->max_changes > kChg)
         return fail(SSA_E_UNSUPPORTED, "the event log records at most %d changed species per event", kChg);
     if (xy_time && (!xy_mean || !xy_var)) return fail(SSA_E_INVALID, "Avg-XY outputs need time, mean and variance");

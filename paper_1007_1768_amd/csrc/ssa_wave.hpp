@@ -69,6 +69,53 @@ __device__ __forceinline__ void wave_interval_sums(const NetDev &n, const int32_
     beta = swt - (dCT - t * dC);
 }
 
+// Event log, one trajectory per wave: the lanes that applied a change (has) append its
+// record (time bits; species, change, previous count) through one cursor bump for the wave.
+// Returns true if a record did not fit (the host then runs the epoch again shorter).
+__device__ __forceinline__ bool wave_log_event(const NetDev &n, bool has, double t_next, int32_t sp, int32_t dl,
+                                               int32_t xo, uint32_t lane) {
+    const uint64_t mk = __ballot(has);
+    if (!mk) return false;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(n.ev_cursor, (unsigned long long)__popcll(mk));
+    const uint32_t blo = (uint32_t)__shfl((int)(uint32_t)base, 0);
+    const uint32_t bhi = (uint32_t)__shfl((int)(uint32_t)(base >> 32), 0);
+    const int64_t at = (int64_t)(((unsigned long long)bhi << 32) | blo) + __popcll(mk & lanemask_lt());
+    bool full = false;
+    if (has && n.ev_key) {
+        if (at < n.ev_cap) {
+            n.ev_key[at] = (unsigned long long)__double_as_longlong(t_next);
+            n.ev_val[at] = ev_pack(sp, dl, xo);
+        } else {
+            full = true;
+        }
+    }
+    return __ballot(full) != 0;
+}
+
+// Event log in epochs (NetDev::rs_*, ws_*), one trajectory per wave: load the saved state
+// into the LDS row, or save it (time -1 once the trajectory has ended).
+__device__ __forceinline__ void wave_evt_resume(const NetDev &n, int64_t traj, int32_t *xl, uint32_t lane, double &t,
+                                                uint64_t &k, uint64_t &ev, uint64_t &ev_start, bool &gone) {
+    for (int32_t s = lane; s < n.S; s += kWave) xl[s + 1] = n.rs_x[(size_t)traj * n.S + s];
+    t = n.rs_t[traj];
+    k = n.rs_k[traj];
+    ev = n.rs_ev[traj];
+    ev_start = ev;
+    gone = t < 0.0;
+    if (gone) t = n.t_end;
+}
+
+__device__ __forceinline__ void wave_evt_save(const NetDev &n, int64_t traj, const int32_t *xl, uint32_t lane,
+                                              bool pause, double t, uint64_t k, uint64_t ev) {
+    for (int32_t s = lane; s < n.S; s += kWave) n.ws_x[(size_t)traj * n.S + s] = xl[s + 1];
+    if (lane == 0) {
+        n.ws_t[traj] = pause ? t : -1.0;
+        n.ws_k[traj] = k;
+        n.ws_ev[traj] = ev;
+    }
+}
+
 // LDS: one row of (S + 1) int32 per wave.
 template <int Q, int MODE>
 __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
@@ -114,11 +161,13 @@ __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
 
         if (lane == 0) xl[0] = 1;
         for (int32_t s = lane; s < S; s += kWave) xl[s + 1] = n.x0[s];
+        double t = 0.0;
+        uint64_t k = 0, ev = 0, ev_start = 0;
+        bool gone = false, pause = false;
+        if (MODE == kEvt && n.rs_t) wave_evt_resume(n, traj, xl, lane, t, k, ev, ev_start, gone);
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
 
-        double t = 0.0;
-        uint64_t k = 0, ev = 0;
         int32_t g = 0;
         double tg_next = G > 0 ? gv.at(0) : 0.0;
         // record: A_j and n_j; backward: the score B_j = n_j - A_j and the accumulator
@@ -188,6 +237,16 @@ __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
                 }
             }
 
+            if (MODE == kEvt && n.ws_t) {
+                // epochs: an ended trajectory stays ended; an event beyond the epoch waits for
+                // the next one, which redraws the same Philox block from the same state
+                if (gone) break;
+                if (t_next <= n.t_end && t_next > n.t_pause) {
+                    pause = true;
+                    if (a0 != 0.0) k = k - 1;
+                    break;
+                }
+            }
             if (t_next > n.t_end) break;
             if (ev >= n.max_events) {
                 flags |= kFlagEventLimit;
@@ -218,6 +277,7 @@ __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
                 if (g < G && t_next > tg_next) bin = gv.next_bin(g, t_next, tg_next);
             }
             // apply: lanes 0 .. kChg-1 take one change slot each (distinct species)
+            int32_t log_sp = 0, log_dl = 0, log_xo = 0;   // event log: this lane's change
             if ((int)lane < kChg) {
                 const int32_t cv = n.chg[sel * kChg + lane];
                 const int32_t r = chg_row(cv), dl = chg_delta(cv);
@@ -227,6 +287,9 @@ __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
                     overflow = xw > 2147483647ll || xw < -2147483647ll - 1;
                     const int32_t xn = (int32_t)xw;
                     xl[r] = xn;
+                    log_sp = r - 1;
+                    log_dl = dl;
+                    log_xo = xo;
                     if (MODE == kFwd && bin < G && !overflow) {
                         const int32_t sp = r - 1;
                         unsigned long long *dd = n.D + ((size_t)bin * S + sp) * 2;
@@ -254,6 +317,10 @@ __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
             if (__ballot(overflow)) {
                 flags |= kFlagOverflow;
                 break;
+            }
+            if (MODE == kEvt) {
+                const bool has = (int)lane < kChg && log_dl != 0;
+                if (wave_log_event(n, has, t_next, log_sp, log_dl, log_xo, lane)) flags |= kFlagRecordsFull;
             }
             if (MODE == kRec) {
 #pragma unroll
@@ -292,7 +359,8 @@ __global__ void __launch_bounds__(kBlock) wave_kernel(WorkList wl) {
             for (int i = 0; i < Q; ++i)
                 if (jr[i] >= 0) n.gtraj[(size_t)traj * M + jr[i]] = gacc[i];
         }
-        tot_events += ev;
+        if (MODE == kEvt && n.ws_t) wave_evt_save(n, traj, xl, lane, pause, t, k, ev);
+        tot_events += ev - ev_start;
         max_steps = max(max_steps, (unsigned long long)ev);
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -381,6 +449,10 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
 
         if (lane == 0) xl[0] = 1;
         for (int32_t s = lane; s < S; s += kWave) xl[s + 1] = n.x0[s];
+        double t = 0.0;
+        uint64_t k = 0, ev = 0, ev_start = 0;
+        bool gone = false, pause = false;
+        if (MODE == kEvt && n.rs_t) wave_evt_resume(n, traj, xl, lane, t, k, ev, ev_start, gone);
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
         if (DEPG) {
@@ -407,8 +479,6 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
 
-        double t = 0.0;
-        uint64_t k = 0, ev = 0;
         int32_t g = 0;
         double tg_next = G > 0 ? gv.at(0) : 0.0;
         bool overflow = false;
@@ -416,7 +486,8 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
         // an absorbing state leaves them unused)
         double r2n, nl;
         {
-            const u32x4 o = philox4x32_10(0u, 0u, (uint32_t)traj, (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
+            const u32x4 o = philox4x32_10((uint32_t)k, (uint32_t)(k >> 32), (uint32_t)traj,
+                                          (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
             r2n = uniform_open1(o.v2, o.v3);
             nl = neg_log(uniform_open0(o.v0, o.v1));
         }
@@ -470,6 +541,16 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
                     }
                     g = gb;
                     tg_next = tb;
+                }
+            }
+            if (MODE == kEvt && n.ws_t) {
+                // epochs: an ended trajectory stays ended; an event beyond the epoch waits for
+                // the next one, which redraws the same Philox block from the same state
+                if (gone) break;
+                if (t_next <= n.t_end && t_next > n.t_pause) {
+                    pause = true;
+                    if (a0 != 0.0) k = k - 1;
+                    break;
                 }
             }
             if (t_next > n.t_end) break;
@@ -539,6 +620,7 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
                 bin = g;
                 if (g < G && t_next > tg_next) bin = gv.next_bin(g, t_next, tg_next);
             }
+            int32_t log_sp = 0, log_dl = 0, log_xo = 0;   // event log: this lane's change
             if ((int)lane < kChg) {
                 const int32_t cv = n.chg[sel * kChg + lane];
                 const int32_t rr = chg_row(cv), dl = chg_delta(cv);
@@ -548,6 +630,9 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
                     overflow = xw > 2147483647ll || xw < -2147483647ll - 1;
                     const int32_t xn = (int32_t)xw;
                     xl[rr] = xn;
+                    log_sp = rr - 1;
+                    log_dl = dl;
+                    log_xo = xo;
                     if (MODE == kFwd && bin < G && !overflow) {
                         const int32_t sp = rr - 1;
                         unsigned long long *dd = n.D + ((size_t)bin * S + sp) * 2;
@@ -575,6 +660,10 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
             if (__ballot(overflow)) {
                 flags |= kFlagOverflow;
                 break;
+            }
+            if (MODE == kEvt) {
+                const bool has = (int)lane < kChg && log_dl != 0;
+                if (wave_log_event(n, has, t_next, log_sp, log_dl, log_xo, lane)) flags |= kFlagRecordsFull;
             }
             if (DEPG) {
                 // re-evaluate the propensities that read a changed species; the first 64
@@ -631,7 +720,8 @@ __global__ void __launch_bounds__(kWave) wide_kernel(WorkList wl) {
             for (int32_t i = 0; i < nreal; ++i)
                 n.gtraj[(size_t)traj * M + (int32_t)lane * q + i] = gac[i * kWave + lane];
         }
-        tot_events += ev;
+        if (MODE == kEvt && n.ws_t) wave_evt_save(n, traj, xl, lane, pause, t, k, ev);
+        tot_events += ev - ev_start;
         max_steps = max(max_steps, (unsigned long long)ev);
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();

@@ -163,3 +163,29 @@ def test_adaptive_epochs_hiv(ssa, small_epochs):
     st, ref = orc.adaptive(m, 16, 0.3, 2, 16)
     assert st == 0
     _compare(out, ref)
+
+
+def _viral_b64():
+    m = dict(inputs.viral())
+    m["sum_order"] = "block64"
+    return m
+
+
+@pytest.mark.parametrize("make,N,t_end,seed,k", [(_viral_b64, 100, 3.0, 3, 40),
+                                                  (lambda: inputs.wide_network(600), 32, 0.3, 5, 64),
+                                                  (lambda: inputs.wide_network(1500), 16, 0.2, 7, 100)])
+@pytest.mark.parametrize("epochs", [False, True])
+def test_adaptive_64_chunk_order(ssa, monkeypatch, make, N, t_end, seed, k, epochs):
+    """The event log of the one-trajectory-per-wave kernels (registers, and LDS rows with the
+    dependency graph) in one pass and in epochs."""
+    if epochs:
+        monkeypatch.setenv("SSA_ADAPTIVE_RECORDS", "4096")
+    m = make()
+    model = ssa.Model.from_dict(m)
+    out = ssa.adaptive_device(model, N, t_end, seed, k, with_y=True, with_stats=True)
+    torch.cuda.synchronize()
+    model.close()
+    st, ref = orc.adaptive(m, N, t_end, seed, k)
+    assert st == 0
+    _compare(out, ref)
+    assert out["stats"]["events"] == ref["events"]
