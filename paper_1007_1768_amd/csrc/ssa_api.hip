@@ -16,6 +16,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/ssa.h"
@@ -132,7 +133,7 @@ struct JitKernels {
 };
 
 std::mutex g_jit_mu;
-std::map<std::pair<int, std::string>, std::shared_ptr<JitKernels>> g_jit_cache;
+std::map<std::tuple<int, std::string, bool>, std::shared_ptr<JitKernels>> g_jit_cache;
 
 std::string device_arch(int dev) {
     hipDeviceProp_t p;
@@ -257,23 +258,63 @@ std::string generate_net_source(const ssa_model *m) {
         s += buf;
     }
     s += "    }\n";
+    // the change of species q by reaction j: a 4-bit field (delta + 8) of one or two
+    // 64-bit constants when every delta lies in [-8, 7] (no branches on the divergent j),
+    // else a select chain
+    std::string changed;
     s += "    __device__ static __forceinline__ void deltas(int32_t j, int32_t (&d)[S]) {\n";
     for (int32_t q = 0; q < S; ++q) {
-        std::string e = "0";
-        for (int32_t j = M - 1; j >= 0; --j) {
+        bool any = false, small = M <= 32;
+        uint64_t K[2] = {0, 0};
+        for (int32_t j = 0; j < M; ++j) {
             const int32_t dl = m->prod[(size_t)j * S + q] - m->reac[(size_t)j * S + q];
-            if (!dl) continue;
-            snprintf(buf, sizeof buf, "(j == %d ? %d : %s)", j, dl, e.c_str());
+            any = any || dl != 0;
+            small = small && dl >= -8 && dl <= 7;
+            if (small) K[j / 16] |= (uint64_t)(dl + 8) << (4 * (j % 16));
+        }
+        for (int32_t j = M; j < 32; ++j) K[j / 16] |= (uint64_t)8 << (4 * (j % 16));
+        changed += any ? (q ? ", true" : "true") : (q ? ", false" : "false");
+        std::string e;
+        if (!any) {
+            e = "0";
+        } else if (small && M <= 16) {
+            snprintf(buf, sizeof buf, "(int32_t)((0x%016llxull >> (4 * j)) & 15ull) - 8", (unsigned long long)K[0]);
             e = buf;
+        } else if (small) {
+            snprintf(buf, sizeof buf,
+                     "(int32_t)(((j < 16 ? 0x%016llxull : 0x%016llxull) >> (4 * (j & 15))) & 15ull) - 8",
+                     (unsigned long long)K[0], (unsigned long long)K[1]);
+            e = buf;
+        } else {
+            e = "0";
+            for (int32_t j = M - 1; j >= 0; --j) {
+                const int32_t dl = m->prod[(size_t)j * S + q] - m->reac[(size_t)j * S + q];
+                if (!dl) continue;
+                snprintf(buf, sizeof buf, "(j == %d ? %d : %s)", j, dl, e.c_str());
+                e = buf;
+            }
         }
         s += "        d[" + std::to_string(q) + "] = " + e + ";\n";
     }
-    s += "    }\n};\n}  // namespace ssa_gen\n#include \"ssa_jit.hpp\"\n";
+    s += "    }\n";
+    // species that some reaction changes (the others are never touched)
+    s += "    __device__ static constexpr bool changes(int q) {\n";
+    s += "        constexpr bool c[S] = {" + changed + "};\n";
+    s += "        return c[q];\n    }\n";
+    s += "};\n}  // namespace ssa_gen\n#include \"ssa_jit.hpp\"\n";
     return s;
 }
 
-ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out) {
-    const auto key = std::make_pair(dev, m->jit_src);
+// A launch of n_items work items (64 trajectories each, one wave apiece) that leaves most
+// SIMDs with at most two waves runs at the latency of a wave's dependency chains rather
+// than at the chip's issue rate.
+bool latency_bound(int64_t n_items, int dev) { return n_items <= (int64_t)2 * 4 * cu_count(dev); }
+
+// The network's kernels compiled at run time; ilp: scheduled for latency-bound launches
+// (independent chains interleaved), else for throughput (the default scheduler, which
+// measured faster once several waves share a SIMD).
+ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out, bool ilp = false) {
+    const auto key = std::make_tuple(dev, m->jit_src, ilp);
     {
         std::lock_guard<std::mutex> lk(g_jit_mu);
         auto it = g_jit_cache.find(key);
@@ -288,9 +329,14 @@ ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out
     if (hiprtcCreateProgram(&prog, m->jit_src.c_str(), "ssa_net.hip", 3, hdrs, names) != HIPRTC_SUCCESS)
         return fail(SSA_E_DEVICE, "hiprtcCreateProgram failed");
     const std::string arch = "--offload-arch=" + device_arch(dev);
+    // ilp: the instruction scheduler that interleaves independent chains.  A lone wave per
+    // SIMD runs the event loop at the latency of its dependency chains, and the loop carries
+    // two of them (the next draw's variates; the propensities and the division).
     const char *opts[] = {arch.c_str(), "-O3", "-std=c++17", "-ffp-contract=off", "-fno-fast-math",
-                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"};
-    const hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+                          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                          "-mllvm", "-amdgpu-sched-strategy=max-ilp"};
+    const int n_opts = (int)(sizeof opts / sizeof opts[0]) - (ilp ? 0 : 2);
+    const hiprtcResult rc = hiprtcCompileProgram(prog, n_opts, opts);
     if (rc != HIPRTC_SUCCESS) {
         size_t ls = 0;
         hiprtcGetProgramLogSize(prog, &ls);
@@ -639,7 +685,7 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
     }
     if (jit_eligible(m)) {
         std::shared_ptr<JitKernels> k;
-        ssa_status s = get_jit(m, dev, k);
+        ssa_status s = get_jit(m, dev, k, latency_bound(n_items, dev));
         if (s) return s;
         hipFunction_t f = mode == kRec ? k->rec : (mode == kEvt ? k->evt : (quad ? k->bwd_var : k->bwd));
         HIP_TRY(launch_jit(f, wl, n_items, dev, st));
@@ -776,7 +822,7 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
     const size_t win_bytes = (size_t)(kBlock / kWave) * wl.win_words * sizeof(long long);
     if (jit_eligible(m)) {
         std::shared_ptr<JitKernels> jk;
-        ssa_status s = get_jit(m, dev, jk);
+        ssa_status s = get_jit(m, dev, jk, latency_bound(n_items, dev));
         if (s) return s;
         k.jit = true;
         const bool hist = wl.net0.Hd != nullptr;

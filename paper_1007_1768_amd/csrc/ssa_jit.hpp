@@ -52,19 +52,32 @@ struct RegPolicy {
 #pragma unroll
         for (int s = 0; s < Net::S; ++s) f(s, x[s]);
     }
+    // Up to 8 species every species that some reaction changes is updated on every event
+    // (f may then see x_new == x_old), so the update has no branches on the divergent
+    // selection; larger networks skip the species the reaction leaves alone.
+    static constexpr bool kDense = Net::S <= 8;
     template <class F>
     __device__ __forceinline__ void apply(const NetDev &, int32_t sel, F f) {
         int32_t dx[Net::S];
         Net::deltas(sel, dx);
 #pragma unroll
         for (int s = 0; s < Net::S; ++s) {
-            if (dx[s] != 0) {
+            if (Net::changes(s) && (kDense || dx[s] != 0)) {
                 const int32_t xo = x[s];
                 const int32_t xn = xo + dx[s];
                 x[s] = xn;
                 f(s, xo, xn);
             }
         }
+    }
+    // f(s, x_old, x_new) for the species reaction sel changed, after apply(n, sel, ...)
+    template <class F>
+    __device__ __forceinline__ void replay(const NetDev &, int32_t sel, F f) const {
+        int32_t dx[Net::S];
+        Net::deltas(sel, dx);
+#pragma unroll
+        for (int s = 0; s < Net::S; ++s)
+            if (Net::changes(s) && dx[s] != 0) f(s, x[s] - dx[s], x[s]);
     }
 };
 

@@ -19,6 +19,7 @@
 //                                   sums <= u, each from a fresh pass over the reactions
 //   for_each_species(f)             f(s, x_s) for every species
 //   apply(n, sel, f)                apply reaction sel: f(s, x_old, x_new) per changed species
+//                                   (a policy may also call f with x_new == x_old)
 //
 // Selective memory (Section 3.2.1) in difference form: the grid value x(t_g) of a
 // trajectory is x0 plus every change with t_e <= t_g, so an event at t_e contributes its
@@ -227,24 +228,20 @@ __device__ __forceinline__ void interval_sums_rows(const Policy &p, const Row &r
     beta = swt - (dCT - t * dC);
 }
 
-// A grid point's own column values: an interval with one crossing needs no prefix
-// difference (alpha = phi_g, beta = phi_g (t_g - t)).
-struct PointRow {
-    const double *v;
-    __device__ __forceinline__ double diff_to(const PointRow &, int32_t c) const { return v[c]; }
-};
-
 template <bool QUAD = false, class Policy>
 __device__ __forceinline__ void interval_sums(const Policy &p, const void *P, const double *PT, int32_t S,
                                               int32_t ga, int32_t gb, double t, double &alpha, double &beta) {
     const int32_t ncol = QUAD ? 4 * S + 2 : 2 * S + 2;
-    if (PT && gb == ga + 1) {
-        const PointRow r{PT + (size_t)ga * ncol};
-        interval_sums_rows<QUAD>(p, r, r, S, t, alpha, beta);
-    } else {
-        const PrefixRow ra(P, ncol, ga), rb(P, ncol, gb);
-        interval_sums_rows<QUAD>(p, ra, rb, S, t, alpha, beta);
+    // A single crossing reads its point's row against the zero row 0 of the prefix table
+    // (dd_diff(0, 0, v, 0) = v), so both kinds of interval run the same code without a
+    // divergent branch.
+    const bool one = PT && gb == ga + 1;
+    PrefixRow ra(P, ncol, one ? 0 : ga), rb(P, ncol, gb);
+    if (one) {
+        rb.hi = PT + (size_t)ga * ncol;
+        rb.lo = ra.lo;
     }
+    interval_sums_rows<QUAD>(p, ra, rb, S, t, alpha, beta);
 }
 
 // Wave-uniform copies (scalar registers) of values every lane holds identically.
@@ -314,6 +311,29 @@ struct GridView {
     }
     __device__ __forceinline__ int32_t next_bin(int32_t g0, double t, double &tb) const {
         return uniform ? next_bin_impl<true>(g0, t, tb) : next_bin_impl<false>(g0, t, tb);
+    }
+
+    // Division-free form for the event loops: the first index b >= g with t_b >= t (G if
+    // none), for a t past t_{g-1}; tg holds t_g on a grid read from memory and moves to t_b
+    // (it is ignored on a uniform grid).  On a uniform grid lo = 0, f = fl(t * scale) is
+    // t D / T within a relative 5 ulp and t_g = fl(fl(T g) / D) is T g / D within 2 ulp, so
+    // when f lies farther than 2^-40 (f + 1) from every integer, ceil(f) is b.  Only a t
+    // that close to a grid point (or t = inf) takes the exact search, as a rare
+    // wave-uniform branch.
+    __device__ __forceinline__ int32_t bin_of(int32_t g, double t, double &tg) const {
+        if (!uniform) return (g < G && t > tg) ? next_bin_impl<false>(g, t, tg) : g;
+        const double f = (t - lo) * scale;
+        const double gf = ceil(f);
+        const double m = 0x1p-40 * (f + 1.0);
+        const bool near = !(gf - f > m) || !(f - (gf - 1.0) > m);
+        int32_t b = gf <= (double)g ? g : (gf >= (double)G ? G : (int32_t)gf);
+        if (__ballot(near)) {
+            if (near) {
+                double tu;
+                b = (g < G && t > (T * (double)g) / D) ? next_bin_impl<true>(g, t, tu) : g;
+            }
+        }
+        return b;
     }
 };
 
@@ -490,15 +510,13 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
             // z_j(t_g) = (n_j - A_j) - a_j (t_g - t): fold them into
             //   alpha = sum_g phi_g,  beta = sum_g phi_g (t_g - t),  phi_g = sum_s w_gs (x_s - mhat_gs)
             // (two rows of the prefix table) and update the M accumulators once per interval.
-            if (g < n.G && tg_cur < t_next) {
-                double tb;
-                const int32_t gb = gv.next_bin(g, t_next, tb);
+            const int32_t gb = gv.bin_of(g, t_next, tg_cur);
+            if (gb > g) {
                 double alpha, beta;
                 interval_sums<QUAD>(p, n.bp, n.bpt, n.S, g, gb, t, alpha, beta);
 #pragma unroll
                 for (int j = 0; j < MM; ++j) gacc[j] = gacc[j] + (B[j] * alpha - a[j] * beta);
                 g = gb;
-                tg_cur = tb;
             }
         }
 
@@ -534,7 +552,7 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
             int32_t rs[kChg], rd[kChg], rx[kChg];
             p.apply(n, sel, [&](int32_t sp, int32_t xo, int32_t xn) {
                 ovf |= (uint32_t)xn;
-                if (MODE == kEvt) {
+                if (MODE == kEvt && xn != xo) {
 #pragma unroll
                     for (int i = 0; i < kChg; ++i)
                         if (nrec == i) {
@@ -777,28 +795,38 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
             flags |= limit ? (uint32_t)kFlagEventLimit : 0u;
             u = r2n * acc;
             const bool go = !(absorb || beyond || limit);
-            binp = g;
-            if (go && g < G && t_next > tg_next) binp = gv.next_bin(g, t_next, tg_next);
             tot_events += go ? 0ull : (unsigned long long)ev;
             max_steps = go ? max_steps : max(max_steps, (unsigned long long)ev);
             active = go;
         };
+        // the grid bin of the drawn event
+        auto place = [&]() {
+            const int32_t bq = gv.bin_of(g, t_next, tg_next);
+            binp = active ? bq : g;
+        };
+        // the variates of draw kk (they do not depend on the state)
+        double E_pre = 0.0, r2_pre = 0.0;
+        auto prepare = [&](const NetDev &n, uint64_t kk) {
+            const u32x4 o = philox4x32_10((uint32_t)kk, (uint32_t)(kk >> 32), (uint32_t)traj,
+                                          (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
+            r2_pre = uniform_open1(o.v2, o.v3);
+            E_pre = neg_log(uniform_open0(o.v0, o.v1));
+        };
         if (active) {
             const NetDev n = current_net<BATCH>(wl, cur);
-            const u32x4 o = philox4x32_10(0u, 0u, (uint32_t)traj, (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
-            draw(n, neg_log(uniform_open0(o.v0, o.v1)), uniform_open1(o.v2, o.v3));
+            prepare(n, 0);
+            draw(n, E_pre, r2_pre);
+            place();
+            prepare(n, k);
         }
 
         for (;;) {
             const bool blocked = active && binp < G && binp >= base + W;
             if (active && !blocked) {
                 const NetDev n = current_net<BATCH>(wl, cur);
-                // the next draw does not depend on the state: start it before the update (the
-                // pending event consumed draw k - 1)
-                const u32x4 o = philox4x32_10((uint32_t)k, (uint32_t)(k >> 32), (uint32_t)traj,
-                                              (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
-                const double r2n = uniform_open1(o.v2, o.v3);
-                const double En = neg_log(uniform_open0(o.v0, o.v1));
+                // the variates of draw k were prepared one event ahead
+                const double r2n = r2_pre, En = E_pre;
+                const uint64_t k_after = k + 1;
                 // apply the pending event at t_next (state unchanged since it was drawn)
                 int32_t sel = 0;
                 if constexpr (MM > 0) {
@@ -818,6 +846,7 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
                 const int32_t bin = binp;
                 const bool inb = bin < G;
                 long long *wrow = win + (bin & (W - 1)) * row_words;
+                bool big = false;
                 p.apply(n, sel, [&](int32_t sp, int32_t xo, int32_t xn) {
                     // events past the last grid point add zeros
                     ovf |= (uint32_t)xn;
@@ -825,12 +854,10 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
                     const long long d2 = (2ll * xo + dl) * (long long)dl;
                     long long *w = wrow + sp * 2;
                     const bool small = d2 > -kSmallD2 && d2 < kSmallD2;
+                    big = big || !small;
                     atomicAdd((unsigned long long *)w, (unsigned long long)(long long)dl);
                     atomicAdd((unsigned long long *)(w + 1),
                               (unsigned long long)(small ? d2 : (d2 & ((1ll << 24) - 1))));
-                    if (__ballot(!small)) {             // rare: |(2x+nu)nu| >= 2^24
-                        if (!small) atomicAdd(n.Dhi + (size_t)bin * hi_words + sp, (unsigned long long)(d2 >> 24));
-                    }
                     if (COV) {
                         // x_s x_r changes by dl x_r (the other species at their current
                         // values: applied one species at a time, the changes telescope)
@@ -857,6 +884,16 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
                         }
                     }
                 });
+                if (__ballot(big)) {                    // rare: |(2x+nu)nu| >= 2^24
+                    if (big) {
+                        p.replay(n, sel, [&](int32_t sp, int32_t xo, int32_t xn) {
+                            const int32_t dl = inb ? xn - xo : 0;
+                            const long long d2 = (2ll * xo + dl) * (long long)dl;
+                            if (!(d2 > -kSmallD2 && d2 < kSmallD2))
+                                atomicAdd(n.Dhi + (size_t)bin * hi_words + sp, (unsigned long long)(d2 >> 24));
+                        });
+                    }
+                }
                 // a count that left the int32 range ends the lane with an error
                 const bool bad = (int32_t)ovf < 0;
                 flags |= bad ? (uint32_t)kFlagOverflow : 0u;
@@ -864,6 +901,11 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
                 ev = ev + 1;
                 g = bin;
                 draw(n, En, r2n);
+                // the next variates (unused when the state turned absorbing), computed here
+                // so that their chain overlaps the propensities and the division above
+                prepare(n, k_after);
+                asm volatile("" : "+v"(E_pre), "+v"(r2_pre));
+                place();
                 active = active && !bad;
             }
             // window upkeep: slide when a lane is waiting beyond it
@@ -1360,8 +1402,7 @@ __device__ __forceinline__ void sim_fwd(const WorkList &wl, Policy &p, long long
                     k = k + 1;
                 } else {
                     u = r2 * acc;
-                    binp = g;
-                    if (g < G && t_next > tg_next) binp = gv.next_bin(g, t_next, tg_next);
+                    binp = gv.bin_of(g, t_next, tg_next);
                     pend = true;
                 }
             }
