@@ -43,6 +43,7 @@ W_PHILOX = 10 * (2 * 4 + 2)        # per round: two 32x32->64 products, two 3-wa
 W_UNIFORMS = 2 * 7                 # two 53-bit conversions
 W_NEGLOG = 37                      # exponent split, (m-1)/(m+1), 10-term Horner, recombination
 W_DIV = 13                         # one IEEE binary64 division (reciprocal + refinement + fixup)
+W_ALIGN = 4                        # grid bin of an event time on a uniform grid: scale, ceil, test, convert
 
 
 def propensity_ops(model):
@@ -72,13 +73,13 @@ def mean_changes(model, n_fired_share=None):
 def w_forward(model, crossing_frac, changes):
     M = model["reac"].shape[0]
     return (W_PHILOX + W_UNIFORMS + W_NEGLOG + W_DIV + 1 + propensity_ops(model) + (M - 1) + 2 * M
-            + changes * 6 + crossing_frac * 2 * W_DIV)
+            + changes * 6 + crossing_frac * W_ALIGN)
 
 
 def w_backward(model, crossings_per_event):
     M, S = model["reac"].shape
     return (W_PHILOX + W_UNIFORMS + W_NEGLOG + W_DIV + 1 + propensity_ops(model) + (M - 1) + 2 * M
-            + 4 * M + crossings_per_event * (2 * S + 4 * M + W_DIV))
+            + 4 * M + min(1.0, crossings_per_event) * W_ALIGN + crossings_per_event * (2 * S + 4 * M))
 
 
 def kernel_sources_hash():
@@ -420,8 +421,12 @@ def main():
     fwd_avg = float(np.mean(fwd_ms))
     bwd_avg = float(np.mean(bwd_ms))
     jit = os.environ.get("SSA_KERNEL") != "generic" and M <= 32 and S <= 64
+    # the library runs the backward in generations when the launch has at most two waves
+    # per SIMD (items of 64 trajectories)
+    lat = (N + 63) // 64 <= 2 * 4 * torch.cuda.get_device_properties(0).multi_processor_count
     if bwd_avg >= fwd_avg:
-        kname, kms, wop = ("ssa_jit_bwd" if jit else "sim_kernel_bwd"), bwd_avg, w_backward(m, crossings)
+        kname = ("ssa_jit_bwd_gen" if lat else "ssa_jit_bwd") if jit else "sim_kernel_bwd"
+        kms, wop = bwd_avg, w_backward(m, crossings)
     else:
         kname, kms, wop = ("ssa_jit_fwd_atomic" if jit else "fwd_kernel"), fwd_avg, w_forward(m, cross_frac, changes)
     achieved = wop * stats_f["events"] / (kms * 1e-3) / 1e12

@@ -129,7 +129,8 @@ struct JitKernels {
     hipModule_t module = nullptr;
     hipFunction_t fwd = nullptr, fwd_atomic = nullptr, fwd_hist = nullptr, fwd_slab_hist = nullptr, fwd_jac = nullptr,
                   fwd_cov = nullptr,
-                  rec = nullptr, bwd = nullptr, bwd_var = nullptr, evt = nullptr;
+                  rec = nullptr, bwd = nullptr, bwd_var = nullptr, evt = nullptr, bwd_gen = nullptr,
+                  bwd_var_gen = nullptr;
 };
 
 std::mutex g_jit_mu;
@@ -362,6 +363,8 @@ ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out
     HIP_TRY(hipModuleGetFunction(&k->evt, k->module, "ssa_jit_evt"));
     HIP_TRY(hipModuleGetFunction(&k->bwd_var, k->module, "ssa_jit_bwd_var"));
     HIP_TRY(hipModuleGetFunction(&k->bwd, k->module, "ssa_jit_bwd"));
+    HIP_TRY(hipModuleGetFunction(&k->bwd_gen, k->module, "ssa_jit_bwd_gen"));
+    HIP_TRY(hipModuleGetFunction(&k->bwd_var_gen, k->module, "ssa_jit_bwd_var_gen"));
     std::lock_guard<std::mutex> lk(g_jit_mu);
     auto ins = g_jit_cache.emplace(key, k);
     out = ins.first->second;
@@ -685,9 +688,14 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
     }
     if (jit_eligible(m)) {
         std::shared_ptr<JitKernels> k;
-        ssa_status s = get_jit(m, dev, k, latency_bound(n_items, dev));
+        const bool lat = latency_bound(n_items, dev);
+        ssa_status s = get_jit(m, dev, k, lat);
         if (s) return s;
-        hipFunction_t f = mode == kRec ? k->rec : (mode == kEvt ? k->evt : (quad ? k->bwd_var : k->bwd));
+        // latency-bound backward: generations (no per-event refill logic)
+        hipFunction_t f = mode == kRec   ? k->rec
+                          : mode == kEvt ? k->evt
+                          : quad         ? (lat ? k->bwd_var_gen : k->bwd_var)
+                                         : (lat ? k->bwd_gen : k->bwd);
         HIP_TRY(launch_jit(f, wl, n_items, dev, st));
         return SSA_OK;
     }

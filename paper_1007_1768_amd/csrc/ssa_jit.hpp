@@ -153,3 +153,15 @@ extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_bwd_var(ssa::W
     ssa::RegPolicy p;
     ssa::sim_loop<ssa::kBwd, ssa_gen::Net::M, false, ssa::RegPolicy, true>(wl, p);
 }
+
+// The backward in generations (lanes refilled only once the whole wave is idle), for
+// launches of about one wave per SIMD.
+extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_bwd_gen(ssa::WorkList wl) {
+    ssa::RegPolicy p;
+    ssa::sim_loop<ssa::kBwd, ssa_gen::Net::M, false, ssa::RegPolicy, false, true>(wl, p);
+}
+
+extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_bwd_var_gen(ssa::WorkList wl) {
+    ssa::RegPolicy p;
+    ssa::sim_loop<ssa::kBwd, ssa_gen::Net::M, false, ssa::RegPolicy, true, true>(wl, p);
+}

@@ -175,11 +175,12 @@ __device__ __forceinline__ void dd_add(double &h, double &l, double bh, double b
     l = e - (h - s);
 }
 
-// (bh + bl) - (ah + al), rounded once at the end.
+// (bh + bl) - (ah + al) within about 1 ulp of the result: bh - ah is exact when the two
+// lie within a factor of 2 (Sterbenz) and otherwise the result is at least |bh| / 2, so
+// its one rounding costs at most half an ulp of the result either way; the lo parts'
+// difference is then added.
 __device__ __forceinline__ double dd_diff(double ah, double al, double bh, double bl) {
-    double s, e;
-    two_sum(bh, -ah, s, e);
-    return s + (e + (bl - al));
+    return (bh - ah) + (bl - al);
 }
 
 // Backward prefix rows (built by bwd_prefix_kernel): row g holds the ncol = 2S + 2 binary64
@@ -326,7 +327,7 @@ struct GridView {
         const double gf = ceil(f);
         const double m = 0x1p-40 * (f + 1.0);
         const bool near = !(gf - f > m) || !(f - (gf - 1.0) > m);
-        int32_t b = gf <= (double)g ? g : (gf >= (double)G ? G : (int32_t)gf);
+        int32_t b = (int32_t)fmin(fmax(gf, (double)g), (double)G);   // in [g, G]: converts exactly
         if (__ballot(near)) {
             if (near) {
                 double tu;
@@ -339,8 +340,11 @@ struct GridView {
 
 // The event loop.  MM is the number of propensity slots the policy evaluates (>= M), or 0
 // for networks too large to keep a_j and S_j in registers (forward only).
-// Record and backward passes: lanes are refilled as soon as their trajectory ends.
-template <int MODE, int MM, bool BATCH, class Policy, bool QUAD = false>
+// Record and backward passes: lanes are refilled as soon as their trajectory ends, or, with
+// GEN, only once every lane of the wave is idle (generations of 64 trajectories: for
+// launches of about one wave per SIMD, where the longest trajectory sets the time anyway
+// and the simpler loop runs each event faster).
+template <int MODE, int MM, bool BATCH, class Policy, bool QUAD = false, bool GEN = false>
 __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
     static_assert(MODE != kFwd && MM > 0, "record, backward and the event log need the per-reaction registers");
     constexpr int MR = MM > 0 ? MM : 1;
@@ -382,7 +386,7 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
         // ---------------- refill idle lanes ----------------
         const uint64_t idle = __ballot(!active);
         // (once the work is exhausted, idle lanes cost nothing per event)
-        if (idle && !(exhausted && pending < 0 && pool_next >= pool_end)) {
+        if (GEN ? idle == ~0ull && !exhausted : idle && !(exhausted && pending < 0 && pool_next >= pool_end)) {
             if (pool_next >= pool_end && !exhausted && pending < 0) {
                 int32_t item = 0;
                 if (lane == 0) item = (int32_t)atomicAdd(wl.counter, 1u);
@@ -478,16 +482,15 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
         } else {
             acc = p.total(n);
         }
-        double tau = __builtin_inf();
-        double r2 = 0.0;
-        if (acc != 0.0) {
-            const u32x4 o = philox4x32_10((uint32_t)k, (uint32_t)(k >> 32), (uint32_t)traj,
-                                          (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
-            const double r1 = uniform_open0(o.v0, o.v1);
-            r2 = uniform_open1(o.v2, o.v3);
-            tau = neg_log(r1) / acc;
-            k = k + 1;
-        }
+        // the draw (not consumed when the state is absorbing), computed without a branch so
+        // that its chain interleaves with the propensities
+        const u32x4 o = philox4x32_10((uint32_t)k, (uint32_t)(k >> 32), (uint32_t)traj,
+                                      (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
+        const double En = neg_log(uniform_open0(o.v0, o.v1));
+        const bool drawn = acc != 0.0;
+        const double r2 = drawn ? uniform_open1(o.v2, o.v3) : 0.0;
+        const double tau = drawn ? En / acc : __builtin_inf();
+        k = drawn ? k + 1 : k;
         const double t_next = t + tau;
         // the count of partial sums <= u (the smallest j with S_j > u), taken now so the
         // partial sums are dead before the grid work below
