@@ -421,14 +421,18 @@ def main():
     fwd_avg = float(np.mean(fwd_ms))
     bwd_avg = float(np.mean(bwd_ms))
     jit = os.environ.get("SSA_KERNEL") != "generic" and M <= 32 and S <= 64
-    # the library runs the backward in generations when the launch has at most two waves
-    # per SIMD (items of 64 trajectories)
-    lat = (N + 63) // 64 <= 2 * 4 * torch.cuda.get_device_properties(0).multi_processor_count
+    # the kernels the library picks by work items (64 trajectories each) per CU: up to 2,
+    # two-wave blocks (a drawing wave beside each simulating one); up to 8, the backward in
+    # generations; beyond, the refilling backward
+    items_per_cu = ((N + 63) // 64) / torch.cuda.get_device_properties(0).multi_processor_count
     if bwd_avg >= fwd_avg:
-        kname = ("ssa_jit_bwd_gen" if lat else "ssa_jit_bwd") if jit else "sim_kernel_bwd"
+        kname = (("ssa_jit_bwd_pc" if items_per_cu <= 2 else "ssa_jit_bwd_gen" if items_per_cu <= 8
+                  else "ssa_jit_bwd") if jit else "sim_kernel_bwd")
         kms, wop = bwd_avg, w_backward(m, crossings)
     else:
-        kname, kms, wop = ("ssa_jit_fwd_atomic" if jit else "fwd_kernel"), fwd_avg, w_forward(m, cross_frac, changes)
+        kname = ((("ssa_jit_fwd_hist_pc" if hist else "ssa_jit_fwd_pc") if items_per_cu <= 2
+                  else "ssa_jit_fwd_atomic") if jit else "fwd_kernel")
+        kms, wop = fwd_avg, w_forward(m, cross_frac, changes)
     achieved = wop * stats_f["events"] / (kms * 1e-3) / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_LANE_OPS / 1e12, 3),
                 "unit": "Tlane-op/s", "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 5),

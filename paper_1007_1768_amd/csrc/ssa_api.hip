@@ -130,7 +130,8 @@ struct JitKernels {
     hipFunction_t fwd = nullptr, fwd_atomic = nullptr, fwd_hist = nullptr, fwd_slab_hist = nullptr, fwd_jac = nullptr,
                   fwd_cov = nullptr,
                   rec = nullptr, bwd = nullptr, bwd_var = nullptr, evt = nullptr, bwd_gen = nullptr,
-                  bwd_var_gen = nullptr;
+                  bwd_var_gen = nullptr, bwd_pc = nullptr, bwd_var_pc = nullptr, fwd_pc = nullptr,
+                  fwd_hist_pc = nullptr;
 };
 
 std::mutex g_jit_mu;
@@ -311,6 +312,15 @@ std::string generate_net_source(const ssa_model *m) {
 // than at the chip's issue rate.
 bool latency_bound(int64_t n_items, int dev) { return n_items <= (int64_t)2 * 4 * cu_count(dev); }
 
+// Launches of at most two work items per CU run the specialised forward and backward in
+// blocks of two waves, one simulating and one computing the draws (each wave on its own
+// SIMD); SSA_DRAW_WAVE=0 turns this off.
+bool pc_launch(int64_t n_items, int dev) {
+    const char *e = std::getenv("SSA_DRAW_WAVE");
+    if (e && std::strcmp(e, "0") == 0) return false;
+    return n_items <= (int64_t)2 * cu_count(dev);
+}
+
 // The network's kernels compiled at run time; ilp: scheduled for latency-bound launches
 // (independent chains interleaved), else for throughput (the default scheduler, which
 // measured faster once several waves share a SIMD).
@@ -365,6 +375,10 @@ ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out
     HIP_TRY(hipModuleGetFunction(&k->bwd, k->module, "ssa_jit_bwd"));
     HIP_TRY(hipModuleGetFunction(&k->bwd_gen, k->module, "ssa_jit_bwd_gen"));
     HIP_TRY(hipModuleGetFunction(&k->bwd_var_gen, k->module, "ssa_jit_bwd_var_gen"));
+    HIP_TRY(hipModuleGetFunction(&k->bwd_pc, k->module, "ssa_jit_bwd_pc"));
+    HIP_TRY(hipModuleGetFunction(&k->bwd_var_pc, k->module, "ssa_jit_bwd_var_pc"));
+    HIP_TRY(hipModuleGetFunction(&k->fwd_pc, k->module, "ssa_jit_fwd_pc"));
+    HIP_TRY(hipModuleGetFunction(&k->fwd_hist_pc, k->module, "ssa_jit_fwd_hist_pc"));
     std::lock_guard<std::mutex> lk(g_jit_mu);
     auto ins = g_jit_cache.emplace(key, k);
     out = ins.first->second;
@@ -535,6 +549,17 @@ hipError_t launch_jit(hipFunction_t f, WorkList &wl, int64_t n_items, int dev, h
                                  nullptr);
 }
 
+// Two-wave blocks (simulating wave + drawing wave), one work item at a time per block.
+// SSA_DRAW_WAVE_BLOCKS caps the block count (blocks then run several generations each).
+hipError_t launch_jit_pc(hipFunction_t f, WorkList &wl, int64_t n_items, int dev, hipStream_t st,
+                         size_t dyn_lds = 0) {
+    int64_t cap = (int64_t)8 * cu_count(dev);
+    if (const char *e = std::getenv("SSA_DRAW_WAVE_BLOCKS")) cap = std::max<int64_t>(1, std::strtoll(e, nullptr, 10));
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(n_items, cap));
+    void *args[] = {&wl};
+    return hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, 2 * kWave, 1, 1, (unsigned)dyn_lds, st, args, nullptr);
+}
+
 hipError_t launch_grid_info(const double *grid, int32_t G, double t_end, GridInfo *out, hipStream_t st) {
     hipLaunchKernelGGL(grid_info_kernel, dim3(1), dim3(256), 0, st, grid, G, t_end, out);
     return hipGetLastError();
@@ -691,7 +716,11 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
         const bool lat = latency_bound(n_items, dev);
         ssa_status s = get_jit(m, dev, k, lat);
         if (s) return s;
-        // latency-bound backward: generations (no per-event refill logic)
+        // latency-bound backward: generations with a drawing wave beside each simulating one
+        if (mode == kBwd && pc_launch(n_items, dev)) {
+            HIP_TRY(launch_jit_pc(quad ? k->bwd_var_pc : k->bwd_pc, wl, n_items, dev, st));
+            return SSA_OK;
+        }
         hipFunction_t f = mode == kRec   ? k->rec
                           : mode == kEvt ? k->evt
                           : quad         ? (lat ? k->bwd_var_gen : k->bwd_var)
@@ -837,6 +866,20 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
         k.f_slab = hist ? jk->fwd_slab_hist : jk->fwd;
         k.f_atomic = hist ? jk->fwd_hist : jk->fwd_atomic;
         k.lds = win_bytes;
+        if (pc_launch(n_items, dev)) {
+            // one simulating wave per block: one window, flushed atomically into D
+            HIP_TRY(launch_zero(D, (size_t)G * S * 2 * sizeof(unsigned long long), st));
+            EventPair ev;
+            if (kernel_ms && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
+            HIP_TRY(launch_jit_pc(hist ? jk->fwd_hist_pc : jk->fwd_pc, wl, n_items, dev, st,
+                                  (size_t)wl.win_words * sizeof(long long)));
+            if (kernel_ms && ev.b) {
+                HIP_TRY(hipEventRecord(ev.b, st));
+                HIP_TRY(hipEventSynchronize(ev.b));
+                (void)hipEventElapsedTime(kernel_ms, ev.a, ev.b);
+            }
+            return SSA_OK;
+        }
     } else {
         if (m->max_changes > kChg)
             return fail(SSA_E_UNSUPPORTED, "the generic kernel handles at most %d changed species per reaction", kChg);

@@ -165,3 +165,39 @@ extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_bwd_var_gen(ss
     ssa::RegPolicy p;
     ssa::sim_loop<ssa::kBwd, ssa_gen::Net::M, false, ssa::RegPolicy, true, true>(wl, p);
 }
+
+// The backward in generations with a second wave computing the draws (blocks of two
+// waves), for launches of about one block per CU.
+extern "C" __global__ void __launch_bounds__(2 * ssa::kWave) ssa_jit_bwd_pc(ssa::WorkList wl) {
+    __shared__ double ring[2 * 2 * ssa::kPcRows * ssa::kWave];
+    __shared__ int32_t ctl[4];
+    ssa::RegPolicy p;
+    ssa::sim_bwd_pc<ssa_gen::Net::M, ssa::RegPolicy>(wl, p, ring, ctl);
+}
+
+extern "C" __global__ void __launch_bounds__(2 * ssa::kWave) ssa_jit_bwd_var_pc(ssa::WorkList wl) {
+    __shared__ double ring[2 * 2 * ssa::kPcRows * ssa::kWave];
+    __shared__ int32_t ctl[4];
+    ssa::RegPolicy p;
+    ssa::sim_bwd_pc<ssa_gen::Net::M, ssa::RegPolicy, true>(wl, p, ring, ctl);
+}
+
+// The forward in generations with a drawing wave (blocks of two waves; dynamic LDS: the
+// simulating wave's window), for launches of about one block per CU.
+extern "C" __global__ void __launch_bounds__(2 * ssa::kWave) ssa_jit_fwd_pc(ssa::WorkList wl) {
+    extern __shared__ long long ssa_win[];
+    __shared__ double ring[2 * 2 * ssa::kPcRows * ssa::kWave];
+    __shared__ unsigned long long kl[2 * ssa::kWave];
+    __shared__ int32_t ctl[4];
+    ssa::RegPolicy p;
+    ssa::sim_fwd_gen<ssa_gen::Net::M, false, false, false, ssa::RegPolicy, false, true>(wl, p, ssa_win, ring, kl, ctl);
+}
+
+extern "C" __global__ void __launch_bounds__(2 * ssa::kWave) ssa_jit_fwd_hist_pc(ssa::WorkList wl) {
+    extern __shared__ long long ssa_win[];
+    __shared__ double ring[2 * 2 * ssa::kPcRows * ssa::kWave];
+    __shared__ unsigned long long kl[2 * ssa::kWave];
+    __shared__ int32_t ctl[4];
+    ssa::RegPolicy p;
+    ssa::sim_fwd_gen<ssa_gen::Net::M, false, false, true, ssa::RegPolicy, false, true>(wl, p, ssa_win, ring, kl, ctl);
+}

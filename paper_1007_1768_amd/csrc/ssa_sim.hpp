@@ -666,6 +666,166 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
     }
 }
 
+// Backward in generations with a second wave drawing the random numbers.  A block is two
+// waves: wave 0 simulates a generation of up to 64 trajectories as sim_loop<kBwd> does,
+// wave 1 computes the Philox blocks and variates (-ln r1, r2) of the next kPcRows steps of
+// every lane into an LDS ring of two halves, one barrier per kPcRows steps.  In a
+// generation every active lane applies one event per step, so step n consumes draw n of
+// every lane; the simulating wave's event chain loses the Philox rounds and the logarithm,
+// which the other wave computes on its own SIMD.  For launches of about one block per CU,
+// where the simulating waves run alone and their chains set the time.  ring: [2][2][kPcRows]
+// [64] doubles (half, E / r2, step, lane); ctl: 3 ints.  Every decision that ends a loop
+// around a barrier is read from LDS after a barrier, so both waves take the same path.
+constexpr int kPcRows = 16;
+
+template <int MM, class Policy, bool QUAD = false>
+__device__ __forceinline__ void sim_bwd_pc(const WorkList &wl, Policy &p, double *ring, int32_t *ctl) {
+    const uint32_t lane = __lane_id();
+    const bool drawer = __builtin_amdgcn_readfirstlane(threadIdx.x) >= (unsigned)kWave;   // wave-uniform
+    const NetDev n = wl.net0;
+    const int32_t M = n.M;
+    const GridInfo gi = *(const SSA_CONST GridInfo *)n.ginfo;
+    GridView gv;
+    gv.grid = wave_uniform(n.grid);
+    gv.T = wave_uniform(gi.T);
+    gv.D = wave_uniform(gi.D);
+    gv.lo = wave_uniform(gi.lo);
+    gv.scale = wave_uniform(gi.scale);
+    gv.G = wave_uniform(n.G);
+    gv.uniform = wave_uniform(gi.uniform);
+    if (!drawer) p.switch_net(n);
+    uint32_t flags = 0;
+    unsigned long long tot_events = 0, max_steps = 0;
+    double a[MM], Ssum[MM], B[MM], gacc[MM];
+
+    for (;;) {
+        if (!drawer && lane == 0) ctl[0] = (int32_t)atomicAdd(wl.counter, 1u);
+        __syncthreads();
+        const int32_t item = ctl[0];
+        if (item >= wl.n_items) break;
+        const int64_t begin = wl.range_begin + (int64_t)item * kChunk;
+        const int64_t count = min((int64_t)kChunk, wl.range_end - begin);
+        const int64_t traj = begin + lane;
+        const bool mine = (int64_t)lane < count;
+
+        // draws [row0, row0 + kPcRows) of this lane's trajectory into ring half h
+        auto fill = [&](int32_t h, uint64_t row0) {
+            if (!mine) return;
+            double *e = ring + (size_t)(2 * h) * kPcRows * kWave + lane;
+            double *r = e + kPcRows * kWave;
+#pragma unroll 4
+            for (int i = 0; i < kPcRows; ++i) {
+                const uint64_t kk = row0 + (uint64_t)i;
+                const u32x4 o = philox4x32_10((uint32_t)kk, (uint32_t)(kk >> 32), (uint32_t)traj,
+                                              (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
+                e[i * kWave] = neg_log(uniform_open0(o.v0, o.v1));
+                r[i * kWave] = uniform_open1(o.v2, o.v3);
+            }
+        };
+        if (drawer) fill(0, 0);
+
+        // simulating lane state
+        bool active = !drawer && mine;
+        double t = 0.0, tg_cur = gv.uniform ? 0.0 : ((const SSA_CONST double *)gv.grid)[0];
+        uint64_t ev = 0;
+        int32_t g = 0;
+        uint32_t ovf = 0;
+        if (active) p.reset(n);
+#pragma unroll
+        for (int j = 0; j < MM; ++j) { B[j] = 0.0; gacc[j] = 0.0; }
+        __syncthreads();
+
+        for (int32_t c = 0;; ++c) {
+            if (drawer) {
+                fill((c + 1) & 1, (uint64_t)(c + 1) * kPcRows);
+            } else {
+                const double *Er = ring + (size_t)(2 * (c & 1)) * kPcRows * kWave + lane;
+                const double *Rr = Er + kPcRows * kWave;
+                for (int i = 0; i < kPcRows; ++i) {
+                    if (__ballot(active) == 0) break;
+                    if (!active) continue;
+                    p.template eval<MM>(n, a);
+                    double acc = a[0];
+                    Ssum[0] = acc;
+#pragma unroll
+                    for (int j = 1; j < MM; ++j) {
+                        acc = acc + a[j];
+                        Ssum[j] = acc;
+                    }
+                    const bool drawn = acc != 0.0;
+                    const double r2 = drawn ? Rr[i * kWave] : 0.0;
+                    const double tau = drawn ? Er[i * kWave] / acc : __builtin_inf();
+                    const double t_next = t + tau;
+                    int32_t sel = 0;
+                    {
+                        const double u = r2 * acc;
+#pragma unroll
+                        for (int j = 0; j < MM; ++j) sel += (Ssum[j] <= u) ? 1 : 0;
+                    }
+                    const int32_t gb = gv.bin_of(g, t_next, tg_cur);
+                    if (gb > g) {
+                        double alpha, beta;
+                        interval_sums<QUAD>(p, n.bp, n.bpt, n.S, g, gb, t, alpha, beta);
+#pragma unroll
+                        for (int j = 0; j < MM; ++j) gacc[j] = gacc[j] + (B[j] * alpha - a[j] * beta);
+                        g = gb;
+                    }
+                    bool finish = t_next > n.t_end;
+                    if (!finish && ev >= n.max_events) {
+                        flags |= kFlagEventLimit;
+                        finish = true;
+                    }
+                    if (!finish) {
+                        if (__ballot(sel >= M)) {
+                            if (sel >= M) {
+                                for (int32_t j = M - 1; j >= 0; --j) {
+                                    if (p.one(n, j) > 0.0) { sel = j; break; }
+                                }
+                                sel = min(sel, M - 1);
+                            }
+                        }
+                        p.apply(n, sel, [&](int32_t, int32_t, int32_t xn) { ovf |= (uint32_t)xn; });
+                        if ((int32_t)ovf < 0) {
+                            flags |= kFlagOverflow;
+                            finish = true;
+                        } else {
+#pragma unroll
+                            for (int j = 0; j < MM; ++j) B[j] = B[j] + ((j == sel ? 1.0 : 0.0) - a[j] * tau);
+                            t = t_next;
+                            ev = ev + 1;
+                        }
+                    }
+                    if (finish) {
+#pragma unroll
+                        for (int j = 0; j < MM; ++j)
+                            if (j < M) n.gtraj[(size_t)traj * M + j] = gacc[j];
+                        tot_events += ev;
+                        max_steps = max(max_steps, (unsigned long long)ev);
+                        active = false;
+                    }
+                }
+                const bool none = __ballot(active) == 0;
+                if (lane == 0) ctl[1 + (c & 1)] = none ? 1 : 0;
+            }
+            __syncthreads();
+            if (ctl[1 + (c & 1)]) break;
+        }
+    }
+
+    if (!drawer) {
+        for (int off = 32; off > 0; off >>= 1) {
+            tot_events += __shfl_xor(tot_events, off);
+            max_steps = max(max_steps, (unsigned long long)__shfl_xor(max_steps, off));
+            flags |= (uint32_t)__shfl_xor((int)flags, off);
+        }
+        if (lane == 0) {
+            if (tot_events) atomicAdd(wl.stats + 0, tot_events);
+            atomicMax(wl.stats + 1, max_steps);
+            if (flags) atomicOr(wl.stats + 2, (unsigned long long)flags);
+        }
+    }
+}
+
 // Smallest value over the wave's lanes (uniform result).
 __device__ __forceinline__ int32_t wave_min(int32_t v) {
     for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
@@ -679,10 +839,25 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 // x S species x (sum nu, sum (2x+nu)nu) as int64.  HIST: with the per-grid-point histogram
 // (a separate instantiation, so runs without one carry none of its code).  COV: also the
 // difference sums of the cross products x_s x_r for the species covariance matrix.
-template <int MM, bool BATCH, bool SLAB, bool HIST, class Policy, bool COV = false>
-__device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long long *win) {
+//
+// PC: blocks of two waves, the second computing the draws (see sim_bwd_pc) into an LDS ring
+// of 2 kPcRows draws per lane, indexed by draw number mod 2 kPcRows.  A lane whose next
+// event lies beyond the window does not draw, so lanes consume draws at their own pace: at
+// the barrier that ends each kPcRows steps the simulating wave publishes each lane's next
+// draw number K (kl, two halves by chunk parity), and during the next steps the drawing
+// wave fills draws up to K + 2 kPcRows.  A lane consumes at most one draw per step, so the
+// draws it needs before the next barrier, [K, K + kPcRows), are in the ring, and the slots
+// being refilled hold draws below K, already consumed.
+template <int MM, bool BATCH, bool SLAB, bool HIST, class Policy, bool COV = false, bool PC = false>
+__device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long long *win, double *ring = nullptr,
+                                            unsigned long long *kl = nullptr, int32_t *ctl = nullptr) {
+    static_assert(!PC || (!BATCH && !SLAB), "the drawing wave serves single-network atomic-flush launches");
     constexpr int MR = MM > 0 ? MM : 1;
+    constexpr uint64_t kRing = 2 * kPcRows;
     const uint32_t lane = __lane_id();
+    // wave-uniform (a scalar value): the two roles are separate code paths, each with its
+    // own barriers, which must not be compiled as one masked path for both waves
+    const bool drawer = PC && __builtin_amdgcn_readfirstlane(threadIdx.x) >= (unsigned)kWave;
     const int32_t W = wl.win_bins;
     const int32_t wave_slot = (int32_t)(blockIdx.x * (kBlock / kWave) + threadIdx.x / kWave);
 
@@ -700,8 +875,14 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
     for (;;) {
         // ---------------- next generation: one work item, one trajectory per lane ----------------
         int32_t item = 0;
-        if (lane == 0) item = (int32_t)atomicAdd(wl.counter, 1u);
-        item = wave_uniform(__shfl(item, 0));
+        if constexpr (PC) {
+            if (!drawer && lane == 0) ctl[0] = (int32_t)atomicAdd(wl.counter, 1u);
+            __syncthreads();
+            item = ctl[0];
+        } else {
+            if (lane == 0) item = (int32_t)atomicAdd(wl.counter, 1u);
+            item = wave_uniform(__shfl(item, 0));
+        }
         if (item >= wl.n_items) break;
         int32_t b = 0;
         int64_t begin, count;
@@ -728,6 +909,34 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
         }
         const NetDev n0 = current_net<BATCH>(wl, cur);
         const int32_t S = n0.S, G = n0.G, M = n0.M;
+        if constexpr (PC) {
+            if (drawer) {
+                // the drawing wave: draws [F, K + 2 kPcRows) of each lane's trajectory
+                const int64_t dtraj = begin + lane;
+                const bool mine = (int64_t)lane < count;
+                uint64_t F = 0;
+                auto fill_to = [&](uint64_t upto) {
+                    if (!mine) return;
+                    for (; F < upto; ++F) {
+                        const u32x4 o = philox4x32_10((uint32_t)F, (uint32_t)(F >> 32), (uint32_t)dtraj,
+                                                      (uint32_t)((uint64_t)dtraj >> 32), n0.key0, n0.key1);
+                        const uint32_t slot = (uint32_t)(F & (kRing - 1));
+                        ring[slot * kWave + lane] = neg_log(uniform_open0(o.v0, o.v1));
+                        ring[(kRing + slot) * kWave + lane] = uniform_open1(o.v2, o.v3);
+                    }
+                };
+                fill_to(kRing);
+                __syncthreads();
+                for (int32_t c = 0;; ++c) {
+                    // draw 0 is taken before the first step, so the first steps start at draw 1
+                    const uint64_t K = c == 0 ? 1 : kl[((c - 1) & 1) * kWave + lane];
+                    fill_to(K + kRing);
+                    __syncthreads();
+                    if (ctl[1 + (c & 1)]) break;
+                }
+                continue;
+            }
+        }
         // window / D row per bin: (sum nu, sum of low parts of (2x+nu)nu) per species, then
         // with COV the low parts of the cross products x_s x_r (s < r); Dhi rows hold the
         // matching high parts
@@ -820,15 +1029,28 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
             prepare(n, 0);
             draw(n, E_pre, r2_pre);
             place();
-            prepare(n, k);
+            if (!PC) prepare(n, k);
         }
+        if (PC) __syncthreads();    // the drawing wave has filled the ring
 
-        for (;;) {
+        for (int32_t c = 0, step = 0;; ++step) {
+            if (PC && step == kPcRows) {
+                // chunk boundary: publish each lane's next draw, then both waves meet
+                kl[(c & 1) * kWave + lane] = k;
+                const bool none = __ballot(active) == 0;     // over all lanes, taken before lane 0 alone writes
+                if (lane == 0) ctl[1 + (c & 1)] = none ? 1 : 0;
+                __syncthreads();
+                if (ctl[1 + (c & 1)]) break;
+                ++c;
+                step = 0;
+            }
             const bool blocked = active && binp < G && binp >= base + W;
             if (active && !blocked) {
                 const NetDev n = current_net<BATCH>(wl, cur);
-                // the variates of draw k were prepared one event ahead
-                const double r2n = r2_pre, En = E_pre;
+                // the variates of draw k: from the ring, or prepared one event ahead
+                const uint32_t slot = (uint32_t)(k & (kRing - 1));
+                const double r2n = PC ? ring[(kRing + slot) * kWave + lane] : r2_pre;
+                const double En = PC ? ring[slot * kWave + lane] : E_pre;
                 const uint64_t k_after = k + 1;
                 // apply the pending event at t_next (state unchanged since it was drawn)
                 int32_t sel = 0;
@@ -904,15 +1126,21 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
                 ev = ev + 1;
                 g = bin;
                 draw(n, En, r2n);
-                // the next variates (unused when the state turned absorbing), computed here
-                // so that their chain overlaps the propensities and the division above
-                prepare(n, k_after);
-                asm volatile("" : "+v"(E_pre), "+v"(r2_pre));
+                if (!PC) {
+                    // the next variates (unused when the state turned absorbing), computed here
+                    // so that their chain overlaps the propensities and the division above
+                    prepare(n, k_after);
+                    asm volatile("" : "+v"(E_pre), "+v"(r2_pre));
+                }
                 place();
                 active = active && !bad;
             }
             // window upkeep: slide when a lane is waiting beyond it
-            if (__ballot(active) == 0) break;
+            if (__ballot(active) == 0) {
+                if (!PC) break;
+                step = kPcRows - 1;     // the drawing wave leaves at the next chunk boundary
+                continue;
+            }
             if (__ballot(active && binp < G && binp >= base + W)) {
                 const int32_t m = wave_min(active ? binp : G);
                 if (m > base) {
