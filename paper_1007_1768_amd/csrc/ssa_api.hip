@@ -131,7 +131,7 @@ struct JitKernels {
                   fwd_cov = nullptr,
                   rec = nullptr, bwd = nullptr, bwd_var = nullptr, evt = nullptr, bwd_gen = nullptr,
                   bwd_var_gen = nullptr, bwd_pc = nullptr, bwd_var_pc = nullptr, fwd_pc = nullptr,
-                  fwd_hist_pc = nullptr;
+                  fwd_hist_pc = nullptr, evt_pc = nullptr;
 };
 
 std::mutex g_jit_mu;
@@ -379,6 +379,7 @@ ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out
     HIP_TRY(hipModuleGetFunction(&k->bwd_var_pc, k->module, "ssa_jit_bwd_var_pc"));
     HIP_TRY(hipModuleGetFunction(&k->fwd_pc, k->module, "ssa_jit_fwd_pc"));
     HIP_TRY(hipModuleGetFunction(&k->fwd_hist_pc, k->module, "ssa_jit_fwd_hist_pc"));
+    HIP_TRY(hipModuleGetFunction(&k->evt_pc, k->module, "ssa_jit_evt_pc"));
     std::lock_guard<std::mutex> lk(g_jit_mu);
     auto ins = g_jit_cache.emplace(key, k);
     out = ins.first->second;
@@ -717,8 +718,9 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
         ssa_status s = get_jit(m, dev, k, lat);
         if (s) return s;
         // latency-bound backward: generations with a drawing wave beside each simulating one
-        if (mode == kBwd && pc_launch(n_items, dev)) {
-            HIP_TRY(launch_jit_pc(quad ? k->bwd_var_pc : k->bwd_pc, wl, n_items, dev, st));
+        if ((mode == kBwd || mode == kEvt) && pc_launch(n_items, dev)) {
+            HIP_TRY(launch_jit_pc(mode == kEvt ? k->evt_pc : (quad ? k->bwd_var_pc : k->bwd_pc), wl, n_items, dev,
+                                  st));
             return SSA_OK;
         }
         hipFunction_t f = mode == kRec   ? k->rec

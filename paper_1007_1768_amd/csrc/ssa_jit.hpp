@@ -172,14 +172,14 @@ extern "C" __global__ void __launch_bounds__(2 * ssa::kWave) ssa_jit_bwd_pc(ssa:
     __shared__ double ring[2 * 2 * ssa::kPcRows * ssa::kWave];
     __shared__ int32_t ctl[4];
     ssa::RegPolicy p;
-    ssa::sim_bwd_pc<ssa_gen::Net::M, ssa::RegPolicy>(wl, p, ring, ctl);
+    ssa::sim_pc<ssa::kBwd, ssa_gen::Net::M, ssa::RegPolicy>(wl, p, ring, ctl);
 }
 
 extern "C" __global__ void __launch_bounds__(2 * ssa::kWave) ssa_jit_bwd_var_pc(ssa::WorkList wl) {
     __shared__ double ring[2 * 2 * ssa::kPcRows * ssa::kWave];
     __shared__ int32_t ctl[4];
     ssa::RegPolicy p;
-    ssa::sim_bwd_pc<ssa_gen::Net::M, ssa::RegPolicy, true>(wl, p, ring, ctl);
+    ssa::sim_pc<ssa::kBwd, ssa_gen::Net::M, ssa::RegPolicy, true>(wl, p, ring, ctl);
 }
 
 // The forward in generations with a drawing wave (blocks of two waves; dynamic LDS: the
@@ -200,4 +200,13 @@ extern "C" __global__ void __launch_bounds__(2 * ssa::kWave) ssa_jit_fwd_hist_pc
     __shared__ int32_t ctl[4];
     ssa::RegPolicy p;
     ssa::sim_fwd_gen<ssa_gen::Net::M, false, false, true, ssa::RegPolicy, false, true>(wl, p, ssa_win, ring, kl, ctl);
+}
+
+// The event log (adaptive memory) in generations with a drawing wave, for launches of about
+// one block per CU.
+extern "C" __global__ void __launch_bounds__(2 * ssa::kWave) ssa_jit_evt_pc(ssa::WorkList wl) {
+    __shared__ double ring[2 * 2 * ssa::kPcRows * ssa::kWave];
+    __shared__ int32_t ctl[4];
+    ssa::RegPolicy p;
+    ssa::sim_pc<ssa::kEvt, ssa_gen::Net::M, ssa::RegPolicy>(wl, p, ring, ctl);
 }

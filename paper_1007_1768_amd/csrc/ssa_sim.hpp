@@ -666,20 +666,22 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
     }
 }
 
-// Backward in generations with a second wave drawing the random numbers.  A block is two
-// waves: wave 0 simulates a generation of up to 64 trajectories as sim_loop<kBwd> does,
-// wave 1 computes the Philox blocks and variates (-ln r1, r2) of the next kPcRows steps of
-// every lane into an LDS ring of two halves, one barrier per kPcRows steps.  In a
-// generation every active lane applies one event per step, so step n consumes draw n of
-// every lane; the simulating wave's event chain loses the Philox rounds and the logarithm,
-// which the other wave computes on its own SIMD.  For launches of about one block per CU,
+// Backward and event log in generations with a second wave drawing the random numbers.  A
+// block is two waves: wave 0 simulates a generation of up to 64 trajectories as
+// sim_loop<kBwd> / sim_loop<kEvt> do, wave 1 computes the Philox blocks and variates
+// (-ln r1, r2) of the next kPcRows steps of every lane into an LDS ring of two halves, one
+// barrier per kPcRows steps.  In a generation every active lane applies one event per step,
+// so step n consumes draw K0 + n of every lane (K0: 0, or the draw an epoch of the event
+// log resumes at); the simulating wave's event chain loses the Philox rounds and the
+// logarithm, which the other wave computes on its own SIMD.  For launches of about one block per CU,
 // where the simulating waves run alone and their chains set the time.  ring: [2][2][kPcRows]
 // [64] doubles (half, E / r2, step, lane); ctl: 3 ints.  Every decision that ends a loop
 // around a barrier is read from LDS after a barrier, so both waves take the same path.
 constexpr int kPcRows = 16;
 
-template <int MM, class Policy, bool QUAD = false>
-__device__ __forceinline__ void sim_bwd_pc(const WorkList &wl, Policy &p, double *ring, int32_t *ctl) {
+template <int MODE, int MM, class Policy, bool QUAD = false>
+__device__ __forceinline__ void sim_pc(const WorkList &wl, Policy &p, double *ring, int32_t *ctl) {
+    static_assert(MODE == kBwd || MODE == kEvt, "backward or event log");
     const uint32_t lane = __lane_id();
     const bool drawer = __builtin_amdgcn_readfirstlane(threadIdx.x) >= (unsigned)kWave;   // wave-uniform
     const NetDev n = wl.net0;
@@ -707,15 +709,19 @@ __device__ __forceinline__ void sim_bwd_pc(const WorkList &wl, Policy &p, double
         const int64_t count = min((int64_t)kChunk, wl.range_end - begin);
         const int64_t traj = begin + lane;
         const bool mine = (int64_t)lane < count;
+        // event log in epochs: where this lane's trajectory resumes
+        const bool resume = MODE == kEvt && n.rs_t != nullptr;
+        const double t0 = mine && resume ? n.rs_t[traj] : 0.0;
+        const uint64_t K0 = mine && resume ? n.rs_k[traj] : 0;
 
-        // draws [row0, row0 + kPcRows) of this lane's trajectory into ring half h
+        // draws K0 + [row0, row0 + kPcRows) of this lane's trajectory into ring half h
         auto fill = [&](int32_t h, uint64_t row0) {
             if (!mine) return;
             double *e = ring + (size_t)(2 * h) * kPcRows * kWave + lane;
             double *r = e + kPcRows * kWave;
 #pragma unroll 4
             for (int i = 0; i < kPcRows; ++i) {
-                const uint64_t kk = row0 + (uint64_t)i;
+                const uint64_t kk = K0 + row0 + (uint64_t)i;
                 const u32x4 o = philox4x32_10((uint32_t)kk, (uint32_t)(kk >> 32), (uint32_t)traj,
                                               (uint32_t)((uint64_t)traj >> 32), n.key0, n.key1);
                 e[i * kWave] = neg_log(uniform_open0(o.v0, o.v1));
@@ -727,10 +733,23 @@ __device__ __forceinline__ void sim_bwd_pc(const WorkList &wl, Policy &p, double
         // simulating lane state
         bool active = !drawer && mine;
         double t = 0.0, tg_cur = gv.uniform ? 0.0 : ((const SSA_CONST double *)gv.grid)[0];
-        uint64_t ev = 0;
+        uint64_t ev = 0, ev_start = 0, k = K0;
+        bool gone = false;
         int32_t g = 0;
         uint32_t ovf = 0;
-        if (active) p.reset(n);
+        if (active) {
+            p.reset(n);
+            if (resume) {
+                t = t0;
+                ev = n.rs_ev[traj];
+                ev_start = ev;
+                p.load_state(n.rs_x + (size_t)traj * n.S);
+                if (t < 0.0) {          // ended in an earlier epoch
+                    t = n.t_end;
+                    gone = true;
+                }
+            }
+        }
 #pragma unroll
         for (int j = 0; j < MM; ++j) { B[j] = 0.0; gacc[j] = 0.0; }
         __syncthreads();
@@ -762,15 +781,30 @@ __device__ __forceinline__ void sim_bwd_pc(const WorkList &wl, Policy &p, double
 #pragma unroll
                         for (int j = 0; j < MM; ++j) sel += (Ssum[j] <= u) ? 1 : 0;
                     }
-                    const int32_t gb = gv.bin_of(g, t_next, tg_cur);
-                    if (gb > g) {
-                        double alpha, beta;
-                        interval_sums<QUAD>(p, n.bp, n.bpt, n.S, g, gb, t, alpha, beta);
+                    k = drawn ? k + 1 : k;
+                    if (MODE == kBwd) {
+                        const int32_t gb = gv.bin_of(g, t_next, tg_cur);
+                        if (gb > g) {
+                            double alpha, beta;
+                            interval_sums<QUAD>(p, n.bp, n.bpt, n.S, g, gb, t, alpha, beta);
 #pragma unroll
-                        for (int j = 0; j < MM; ++j) gacc[j] = gacc[j] + (B[j] * alpha - a[j] * beta);
-                        g = gb;
+                            for (int j = 0; j < MM; ++j) gacc[j] = gacc[j] + (B[j] * alpha - a[j] * beta);
+                            g = gb;
+                        }
                     }
                     bool finish = t_next > n.t_end;
+                    bool pause = false;
+                    if (MODE == kEvt && n.ws_t) {
+                        // an ended trajectory stays ended; an event beyond the epoch waits for
+                        // the next one, which redraws the same draw from the same state
+                        if (gone) {
+                            finish = true;
+                        } else if (!finish && t_next > n.t_pause) {
+                            finish = true;
+                            pause = true;
+                            if (drawn) k = k - 1;
+                        }
+                    }
                     if (!finish && ev >= n.max_events) {
                         flags |= kFlagEventLimit;
                         finish = true;
@@ -784,22 +818,78 @@ __device__ __forceinline__ void sim_bwd_pc(const WorkList &wl, Policy &p, double
                                 sel = min(sel, M - 1);
                             }
                         }
-                        p.apply(n, sel, [&](int32_t, int32_t, int32_t xn) { ovf |= (uint32_t)xn; });
+                        int32_t nrec = 0;
+                        int32_t rs[kChg], rd[kChg], rx[kChg];
+                        p.apply(n, sel, [&](int32_t sp, int32_t xo, int32_t xn) {
+                            ovf |= (uint32_t)xn;
+                            if (MODE == kEvt && xn != xo) {
+#pragma unroll
+                                for (int q = 0; q < kChg; ++q)
+                                    if (nrec == q) {
+                                        rs[q] = sp;
+                                        rd[q] = xn - xo;
+                                        rx[q] = xo;
+                                    }
+                                ++nrec;
+                            }
+                        });
                         if ((int32_t)ovf < 0) {
                             flags |= kFlagOverflow;
                             finish = true;
                         } else {
+                            if (MODE == kBwd) {
 #pragma unroll
-                            for (int j = 0; j < MM; ++j) B[j] = B[j] + ((j == sel ? 1.0 : 0.0) - a[j] * tau);
+                                for (int j = 0; j < MM; ++j) B[j] = B[j] + ((j == sel ? 1.0 : 0.0) - a[j] * tau);
+                            }
+                            if (MODE == kEvt) {
+                                // one cursor bump per wave for the records of all its lanes
+                                nrec = min(nrec, kChg);
+                                uint32_t before = 0, total = 0;
+#pragma unroll
+                                for (int q = 0; q < kChg; ++q) {
+                                    const uint64_t mq = __ballot(nrec > q);
+                                    before += __popcll(mq & lanemask_lt());
+                                    total += __popcll(mq);
+                                }
+                                const int32_t leader = __ffsll((unsigned long long)__ballot(1)) - 1;
+                                unsigned long long base = 0;
+                                if ((int32_t)lane == leader) base = atomicAdd(n.ev_cursor, (unsigned long long)total);
+                                const uint32_t blo = (uint32_t)__shfl((int)(uint32_t)base, leader);
+                                const uint32_t bhi = (uint32_t)__shfl((int)(uint32_t)(base >> 32), leader);
+                                const int64_t at = (int64_t)(((unsigned long long)bhi << 32) | blo) + before;
+                                if (n.ev_key) {
+                                    const unsigned long long key = (unsigned long long)__double_as_longlong(t_next);
+#pragma unroll
+                                    for (int q = 0; q < kChg; ++q) {
+                                        if (q < nrec) {
+                                            if (at + q < n.ev_cap) {
+                                                n.ev_key[at + q] = key;
+                                                n.ev_val[at + q] = ev_pack(rs[q], rd[q], rx[q]);
+                                            } else {
+                                                flags |= kFlagRecordsFull;
+                                            }
+                                        }
+                                    }
+                                }
+                            }
                             t = t_next;
                             ev = ev + 1;
                         }
                     }
                     if (finish) {
+                        if (MODE == kBwd) {
 #pragma unroll
-                        for (int j = 0; j < MM; ++j)
-                            if (j < M) n.gtraj[(size_t)traj * M + j] = gacc[j];
-                        tot_events += ev;
+                            for (int j = 0; j < MM; ++j)
+                                if (j < M) n.gtraj[(size_t)traj * M + j] = gacc[j];
+                        }
+                        if (MODE == kEvt && n.ws_t) {
+                            int32_t *wx = n.ws_x + (size_t)traj * n.S;
+                            p.for_each_species([&](int32_t sp, int32_t xs) { wx[sp] = xs; });
+                            n.ws_t[traj] = pause ? t : -1.0;
+                            n.ws_k[traj] = k;
+                            n.ws_ev[traj] = ev;
+                        }
+                        tot_events += ev - ev_start;
                         max_steps = max(max_steps, (unsigned long long)ev);
                         active = false;
                     }
@@ -840,7 +930,7 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 // (a separate instantiation, so runs without one carry none of its code).  COV: also the
 // difference sums of the cross products x_s x_r for the species covariance matrix.
 //
-// PC: blocks of two waves, the second computing the draws (see sim_bwd_pc) into an LDS ring
+// PC: blocks of two waves, the second computing the draws (see sim_pc) into an LDS ring
 // of 2 kPcRows draws per lane, indexed by draw number mod 2 kPcRows.  A lane whose next
 // event lies beyond the window does not draw, so lanes consume draws at their own pace: at
 // the barrier that ends each kPcRows steps the simulating wave publishes each lane's next

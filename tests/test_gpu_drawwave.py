@@ -1,8 +1,9 @@
 """The two-wave launches (one wave simulates a generation of 64 trajectories, the other
-computes its draws into an LDS ring): the forward and the backward give the same bits as
-the one-wave kernels, including when lanes wait on the selective-memory window (so they
-consume draws at different paces), when a block runs several generations, for ragged
-and tiny trajectory counts, with the histogram and with variance weights."""
+computes its draws into an LDS ring): the forward, the backward and the event log of the
+adaptive memory give the same bits as the one-wave kernels, including when lanes wait on
+the selective-memory window (so they consume draws at different paces), when a block runs
+several generations, when the event log runs in epochs (lanes resume at their own draws),
+for ragged and tiny trajectory counts, with the histogram and with variance weights."""
 import pytest
 
 from paper_1007_1768_amd import inputs
@@ -83,4 +84,27 @@ def test_backward_same_bits(ssa, monkeypatch, N, t_end, G, seed, win, cap):
         (g1, s1), (g2, s2) = _both(monkeypatch, run)
         assert s1["events"] == s2["events"] and s1["flags"] == s2["flags"]
         assert torch.equal(g1, g2), (g1 - g2).abs().max().item()
+    model.close()
+
+
+@pytest.mark.parametrize("N,t_end,seed,k,epochs,cap", [
+    (1500, 10.0, 21, 50, False, None),
+    (1500, 10.0, 22, 50, True, None),     # epochs of 4096 records: lanes resume at their own draws
+    (300, 6.0, 23, 7, True, 2),           # several generations per block, in epochs
+])
+def test_event_log_same_bits(ssa, monkeypatch, N, t_end, seed, k, epochs, cap):
+    if epochs:
+        monkeypatch.setenv("SSA_ADAPTIVE_RECORDS", "4096")
+    if cap:
+        monkeypatch.setenv("SSA_DRAW_WAVE_BLOCKS", str(cap))
+    model = ssa.Model.from_dict(inputs.viral())
+
+    def run():
+        out = ssa.adaptive_device(model, N, t_end, seed, k, with_y=True, with_stats=True)
+        torch.cuda.synchronize()
+        return out
+    a, b = _both(monkeypatch, run)
+    assert a["stats"]["events"] == b["stats"]["events"] and a["stats"]["flags"] == b["stats"]["flags"]
+    for key in ("xy_time", "xy_mean", "xy_var", "y_time", "y_mean", "y_var"):
+        assert torch.equal(a[key], b[key]), key
     model.close()
