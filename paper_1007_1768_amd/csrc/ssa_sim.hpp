@@ -1123,17 +1123,7 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
         }
         if (PC) __syncthreads();    // the drawing wave has filled the ring
 
-        for (int32_t c = 0, step = 0;; ++step) {
-            if (PC && step == kPcRows) {
-                // chunk boundary: publish each lane's next draw, then both waves meet
-                kl[(c & 1) * kWave + lane] = k;
-                const bool none = __ballot(active) == 0;     // over all lanes, taken before lane 0 alone writes
-                if (lane == 0) ctl[1 + (c & 1)] = none ? 1 : 0;
-                __syncthreads();
-                if (ctl[1 + (c & 1)]) break;
-                ++c;
-                step = 0;
-            }
+        for (int32_t c = 0, step = 0;;) {
             const bool blocked = active && binp < G && binp >= base + W;
             if (active && !blocked) {
                 const NetDev n = current_net<BATCH>(wl, cur);
@@ -1226,17 +1216,24 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
                 active = active && !bad;
             }
             // window upkeep: slide when a lane is waiting beyond it
-            if (__ballot(active) == 0) {
-                if (!PC) break;
-                step = kPcRows - 1;     // the drawing wave leaves at the next chunk boundary
-                continue;
-            }
-            if (__ballot(active && binp < G && binp >= base + W)) {
+            const bool none = __ballot(active) == 0;
+            if (!PC && none) break;
+            if (!none && __ballot(active && binp < G && binp >= base + W)) {
                 const int32_t m = wave_min(active ? binp : G);
                 if (m > base) {
                     flush(base, min(m, base + W));
                     base = m;
                 }
+            }
+            if (PC && (++step == kPcRows || none)) {
+                // chunk boundary (or no lane left: the drawing wave leaves at this one):
+                // publish each lane's next draw, then both waves meet
+                kl[(c & 1) * kWave + lane] = k;
+                if (lane == 0) ctl[1 + (c & 1)] = none ? 1 : 0;
+                __syncthreads();
+                if (ctl[1 + (c & 1)]) break;
+                ++c;
+                step = 0;
             }
         }
         flush(base, min(G, base + W));
