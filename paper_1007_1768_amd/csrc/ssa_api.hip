@@ -587,6 +587,13 @@ GridInfo host_grid_info(const double *grid, int32_t G, double t_end) {
     return gi;
 }
 
+hipError_t launch_fill(void *p, size_t words, unsigned long long v, hipStream_t st) {
+    if (!words) return hipSuccess;
+    const unsigned blocks = (unsigned)std::min<size_t>((words + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_kernel, dim3(blocks), dim3(256), 0, st, (unsigned long long *)p, words, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
     const size_t words = (bytes + 7) / 8;
     if (!words) return hipSuccess;
@@ -1635,7 +1642,7 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
     void *d_grid = nullptr, *ctl = nullptr, *cur = nullptr, *carry = nullptr;
     HIP_TRY(scr.alloc(&d_grid, sizeof(double)));
     HIP_TRY(scr.alloc(&ctl, 64 + sizeof(GridInfo)));
-    HIP_TRY(scr.alloc(&cur, sizeof(unsigned long long)));
+    HIP_TRY(scr.alloc(&cur, 2 * sizeof(unsigned long long)));    // record count, reserved slots
     HIP_TRY(scr.alloc(&carry, sizeof(long long) * 3 * (size_t)S));
     HIP_TRY(hipMemcpyAsync(d_grid, h_grid, sizeof(double), hipMemcpyHostToDevice, st));
     const GridInfo hgi = host_grid_info(h_grid, 1, t_end);
@@ -1644,6 +1651,7 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
     NetDev n0 = base_net(m, rates, n_traj, t_end, (const double *)d_grid, 1, seed, max_events);
     n0.ginfo = (const GridInfo *)((char *)ctl + 64);
     n0.ev_cursor = (unsigned long long *)cur;
+    n0.ev_resv = (unsigned long long *)cur + 1;
     n0.t_pause = t_end;
     WorkList wl;
     std::memset(&wl, 0, sizeof wl);
@@ -1658,14 +1666,18 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
     uint32_t all_flags = 0;
 
     // One pass of the event log over the epoch (t0, t1] (the whole run when rs is NULL and
-    // t1 == t_end); R receives the records (counted even when they did not fit).
+    // t1 == t_end); R receives the records (counted even when they did not fit), Rs the
+    // extent of the slots they occupy (R plus the unused ends of the waves' reservations;
+    // 0 for kernels that place records at the count).
+    unsigned long long Rs = 0;
     auto log_pass = [&](NetDev n, unsigned long long &R, unsigned long long (&h)[3]) -> ssa_status {
         HIP_TRY(launch_zero(ctl, 64, st));
-        HIP_TRY(launch_zero(cur, sizeof(unsigned long long), st));
+        HIP_TRY(launch_zero(cur, 2 * sizeof(unsigned long long), st));
         wl.net0 = n;
         ssa_status s = launch_single(kEvt, m, wl, n_items, dev, st, rates, scr);
         if (s) return s;
         HIP_TRY(hipMemcpyAsync(&R, cur, sizeof R, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&Rs, (unsigned long long *)cur + 1, sizeof Rs, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipMemcpyAsync(h, (char *)ctl + 32, sizeof h, hipMemcpyDeviceToHost, st));
         HIP_TRY(hipStreamSynchronize(st));
         if (h[2] & kFlagOverflow) return fail(SSA_E_OVERFLOW, "a species count left the int32 range");
@@ -1681,11 +1693,17 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
     const int64_t budget = adaptive_budget();
     const bool epochs = (int64_t)R_all > budget;
     void *keys0 = nullptr, *keys1 = nullptr, *vals0 = nullptr, *vals1 = nullptr, *stf = nullptr, *rk = nullptr;
-    const int64_t cap = std::max<int64_t>(1, std::min<int64_t>((int64_t)R_all, budget));
-    HIP_TRY(scr.alloc(&keys0, sizeof(unsigned long long) * (size_t)cap));
-    HIP_TRY(scr.alloc(&keys1, sizeof(unsigned long long) * (size_t)cap));
-    HIP_TRY(scr.alloc(&vals0, sizeof(unsigned long long) * (size_t)cap));
-    HIP_TRY(scr.alloc(&vals1, sizeof(unsigned long long) * (size_t)cap));
+    // slots: the records plus the unused ends of each wave's last two reservations (a wave
+    // reserves only while it holds work, so at most one wave per work item; a launch holds
+    // at most 8192 waves)
+    const int64_t waste = std::min<int64_t>(n_items, 8192) * 2 * (int64_t)kLogChunk;
+    const int64_t cap =
+        std::max<int64_t>(1, std::min<int64_t>(std::min<int64_t>((int64_t)R_all, budget), INT32_MAX - 1 - waste));
+    const int64_t slots = cap + waste;
+    HIP_TRY(scr.alloc(&keys0, sizeof(unsigned long long) * (size_t)slots));
+    HIP_TRY(scr.alloc(&keys1, sizeof(unsigned long long) * (size_t)slots));
+    HIP_TRY(scr.alloc(&vals0, sizeof(unsigned long long) * (size_t)slots));
+    HIP_TRY(scr.alloc(&vals1, sizeof(unsigned long long) * (size_t)slots));
     HIP_TRY(scr.alloc(&stf, sizeof(int32_t) * (size_t)cap));
     HIP_TRY(scr.alloc(&rk, sizeof(int32_t) * (size_t)cap));
     void *sort_tmp = nullptr;
@@ -1694,7 +1712,7 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
         size_t tb = 0, tb2 = 0;
         HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (const unsigned long long *)keys0,
                                                    (unsigned long long *)keys1, (const unsigned long long *)vals0,
-                                                   (unsigned long long *)vals1, (int)cap, 0, 64, st));
+                                                   (unsigned long long *)vals1, (int)slots, 0, 64, st));
         HIP_TRY(hipcub::DeviceScan::InclusiveSum(nullptr, tb2, (const int32_t *)stf, (int32_t *)rk, (int)cap, st));
         sort_tmp_bytes = std::max(tb, tb2);
         HIP_TRY(scr.alloc(&sort_tmp, sort_tmp_bytes));
@@ -1729,7 +1747,9 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
         n.t_pause = t1;
         n.ev_key = (unsigned long long *)keys0;
         n.ev_val = (unsigned long long *)vals0;
-        n.ev_cap = cap;
+        n.ev_cap = slots;
+        // slots no record takes keep the key ~0, which sorts after every event time
+        HIP_TRY(launch_fill(keys0, (size_t)slots, ~0ull, st));
         if (epochs) {
             if (!first) {
                 n.rs_x = (const int32_t *)sx[sb];
@@ -1756,15 +1776,18 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
         max_steps = std::max(max_steps, h[1]);
         all_flags |= (uint32_t)h[2];
 
-        // time order and the distinct-time ranks of this epoch's records
+        // time order and the distinct-time ranks of this epoch's records (the first R of
+        // the sorted slots)
         const int32_t nR = (int32_t)R;
+        const int32_t nSlots = (int32_t)std::max<unsigned long long>(R, Rs);
+        if (nSlots > slots) return fail(SSA_E_DEVICE, "event log slots beyond the reservation bound");
         int32_t n_distinct = 0;
         unsigned long long first_key = 0;
         if (R > 0) {
             size_t tb = sort_tmp_bytes;
             HIP_TRY(hipcub::DeviceRadixSort::SortPairs(sort_tmp, tb, (const unsigned long long *)keys0,
                                                        (unsigned long long *)keys1, (const unsigned long long *)vals0,
-                                                       (unsigned long long *)vals1, nR, 0, 64, st));
+                                                       (unsigned long long *)vals1, nSlots, 0, 64, st));
             const unsigned gb = (unsigned)std::min<int64_t>(((int64_t)R + 255) / 256, 65535);
             hipLaunchKernelGGL(evt_start_kernel, dim3(gb), dim3(256), 0, st, (const unsigned long long *)keys1,
                                (int64_t)R, (int32_t *)stf);

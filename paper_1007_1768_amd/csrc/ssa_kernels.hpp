@@ -758,6 +758,11 @@ __global__ void zero_kernel(unsigned long long *__restrict__ p, size_t n_words) 
         p[i] = 0ull;
 }
 
+__global__ void fill_kernel(unsigned long long *__restrict__ p, size_t n_words, unsigned long long v) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_words; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
 
 // ---------------------------------------------------------------------------------------
 // Adaptive selective memory (Section 3.2.1, Figure 3) from the time-sorted event log:

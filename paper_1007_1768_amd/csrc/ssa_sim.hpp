@@ -63,6 +63,37 @@ enum Mode : int { kFwd = 0, kRec = 1, kBwd = 2, kEvt = 3 };
 
 enum Flags : uint32_t { kFlagOverflow = 1u, kFlagEventLimit = 2u, kFlagRecordsFull = 4u };
 
+constexpr unsigned kLogChunk = 1024;   // event-log slots a wave reserves at a time (>= 64 kChg)
+
+// A wave's event-log slots: the rest of its current chunk [next, end) and, once that may
+// be too short for a step (64 kChg records), the following chunk nxt (~0: none yet).  All
+// fields change only where the wave is converged, so they are wave-uniform.
+struct LogSlots {
+    unsigned long long next = 0, end = 0, nxt = ~0ull;
+    // slot of the j-th record of this step
+    __device__ __forceinline__ unsigned long long at(unsigned long long j) const {
+        return next + j < end ? next + j : nxt + (next + j - end);
+    }
+    // after a step that took `used` slots; reserve ahead when a step might not fit (only a
+    // wave with an active lane, so only waves that hold work reserve)
+    __device__ __forceinline__ void advance(uint32_t used, bool busy, unsigned long long *resv, uint32_t lane) {
+        next += used;
+        if (next >= end && nxt != ~0ull) {
+            const unsigned long long over = next - end;
+            next = nxt + over;
+            end = nxt + kLogChunk;
+            nxt = ~0ull;
+        }
+        if (busy && nxt == ~0ull && end - next < (unsigned long long)(kWave * kChg)) {
+            unsigned long long b = 0;
+            if (lane == 0) b = atomicAdd(resv, (unsigned long long)kLogChunk);
+            const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, 0);
+            const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), 0);
+            nxt = ((unsigned long long)hi << 32) | lo;
+        }
+    }
+};
+
 // Time grid description.  A grid with t_g = fl(fl(T g) / D) for every g (the uniform grid
 // of the workloads) is "uniform": its points are recomputed exactly from (T, D) instead of
 // being loaded, which keeps the event loop free of vector-memory loads.  Any other
@@ -114,10 +145,17 @@ struct NetDev {
     const double *bpt;       // the column values of each grid point [G][ncol] (one-crossing intervals)
     double *gtraj;
     int32_t bp_quad;
-    // event log: one record per changed species of every applied event, appended at
-    // ev_cursor (key: the event time's bits; value: packed species, change, old count);
-    // with ev_key == nullptr only the cursor counts
+    // event log: one record per changed species of every applied event (key: the event
+    // time's bits; value: packed species, change, old count); ev_cursor counts the records;
+    // with ev_key == nullptr nothing else is written
     unsigned long long *ev_key, *ev_val, *ev_cursor;
+    // slot allocator of the lane kernels: a wave reserves kLogChunk slots at a time (the
+    // next chunk before the current one may run short, so no slot is skipped), so records
+    // land in [0, *ev_resv) with gaps only at the end of each wave's last two chunks (the
+    // caller fills the keys with ~0 first, which sorts after every event time); *ev_cursor
+    // still counts the records exactly.  The one-trajectory-per-wave kernels place records
+    // at the cursor.
+    unsigned long long *ev_resv;
     int64_t ev_cap;
     // event log in epochs: each trajectory starts from a saved state (rs_*, or the initial
     // state when rs_t is NULL) and stops before its first event beyond t_pause, saving its
@@ -373,6 +411,9 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
     unsigned long long tot_events = 0, max_steps = 0;
     uint64_t ev_start = 0;     // event log in epochs: events before this epoch
     bool gone = false;         // event log in epochs: the trajectory ended in an earlier epoch
+    unsigned long long rec_count = 0;   // event log: this lane's records (added to the cursor at the end)
+    LogSlots slots;             // event log: the wave's reserved slots
+    int32_t step_nrec = 0;      // event log: this lane's records of the last step
     double a[MR];
     double Ssum[MR];
     // record: A_j and n_j; backward: the score B_j = n_j - A_j at the current event time
@@ -459,6 +500,14 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
                 }
             }
             pool_next = min(pool_next + (int64_t)n_idle, pool_end);
+        }
+        if (MODE == kEvt && wl.net0.ev_key) {
+            // the last step's records took slots; make sure this step's fit
+            uint32_t used = 0;
+#pragma unroll
+            for (int q = 0; q < kChg; ++q) used += __popcll(__ballot(step_nrec > q));
+            step_nrec = 0;
+            slots.advance(used, __ballot(active) != 0, wl.net0.ev_resv, lane);
         }
         if (__ballot(active) == 0) {
             if (exhausted && pending < 0) break;
@@ -582,29 +631,24 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
                     for (int j = 0; j < MM; ++j) B[j] = B[j] + ((j == sel ? 1.0 : 0.0) - a[j] * tau);
                 }
                 if (MODE == kEvt) {
-                    // one cursor bump per wave for the records of all its lanes
                     nrec = min(nrec, kChg);
-                    uint32_t before = 0, total = 0;
+                    rec_count += (unsigned long long)nrec;
+                }
+                if (MODE == kEvt && n.ev_key) {
+                    // this step's records take consecutive slots of the wave's reservation
+                    step_nrec = nrec;
+                    uint32_t before = 0;
 #pragma unroll
-                    for (int i = 0; i < kChg; ++i) {
-                        const uint64_t m = __ballot(nrec > i);
-                        before += __popcll(m & lanemask_lt());
-                        total += __popcll(m);
-                    }
-                    const int32_t leader = __ffsll((unsigned long long)__ballot(1)) - 1;
-                    unsigned long long base = 0;
-                    if ((int32_t)lane == leader) base = atomicAdd(n.ev_cursor, (unsigned long long)total);
-                    const uint32_t blo = (uint32_t)__shfl((int)(uint32_t)base, leader);
-                    const uint32_t bhi = (uint32_t)__shfl((int)(uint32_t)(base >> 32), leader);
-                    const int64_t at = (int64_t)(((unsigned long long)bhi << 32) | blo) + before;
-                    if (n.ev_key) {
+                    for (int i = 0; i < kChg; ++i) before += __popcll(__ballot(nrec > i) & lanemask_lt());
+                    {
                         const unsigned long long key = (unsigned long long)__double_as_longlong(t_next);
 #pragma unroll
                         for (int i = 0; i < kChg; ++i) {
                             if (i < nrec) {
-                                if (at + i < n.ev_cap) {
-                                    n.ev_key[at + i] = key;
-                                    n.ev_val[at + i] = ev_pack(rs[i], rd[i], rx[i]);
+                                const int64_t at = (int64_t)slots.at((unsigned long long)(before + i));
+                                if (at < n.ev_cap) {
+                                    n.ev_key[at] = key;
+                                    n.ev_val[at] = ev_pack(rs[i], rd[i], rx[i]);
                                 } else {
                                     flags |= kFlagRecordsFull;
                                 }
@@ -658,11 +702,13 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
         tot_events += __shfl_xor(tot_events, off);
         max_steps = max(max_steps, (unsigned long long)__shfl_xor(max_steps, off));
         flags |= (uint32_t)__shfl_xor((int)flags, off);
+        if (MODE == kEvt) rec_count += __shfl_xor(rec_count, off);
     }
     if (lane == 0) {
         if (tot_events) atomicAdd(wl.stats + 0, tot_events);
         atomicMax(wl.stats + 1, max_steps);
         if (flags) atomicOr(wl.stats + 2, (unsigned long long)flags);
+        if (MODE == kEvt && rec_count) atomicAdd(wl.net0.ev_cursor, rec_count);
     }
 }
 
@@ -698,6 +744,9 @@ __device__ __forceinline__ void sim_pc(const WorkList &wl, Policy &p, double *ri
     if (!drawer) p.switch_net(n);
     uint32_t flags = 0;
     unsigned long long tot_events = 0, max_steps = 0;
+    unsigned long long rec_count = 0;   // event log: this lane's records (added to the cursor at the end)
+    LogSlots slots;             // event log: the wave's reserved slots
+    int32_t step_nrec = 0;      // event log: this lane's records of the last step
     double a[MM], Ssum[MM], B[MM], gacc[MM];
 
     for (;;) {
@@ -761,6 +810,14 @@ __device__ __forceinline__ void sim_pc(const WorkList &wl, Policy &p, double *ri
                 const double *Er = ring + (size_t)(2 * (c & 1)) * kPcRows * kWave + lane;
                 const double *Rr = Er + kPcRows * kWave;
                 for (int i = 0; i < kPcRows; ++i) {
+                    if (MODE == kEvt && n.ev_key) {
+                        // the last step's records took slots; make sure this step's fit
+                        uint32_t used = 0;
+#pragma unroll
+                        for (int q = 0; q < kChg; ++q) used += __popcll(__ballot(step_nrec > q));
+                        step_nrec = 0;
+                        slots.advance(used, __ballot(active) != 0, n.ev_resv, lane);
+                    }
                     if (__ballot(active) == 0) break;
                     if (!active) continue;
                     p.template eval<MM>(n, a);
@@ -842,29 +899,24 @@ __device__ __forceinline__ void sim_pc(const WorkList &wl, Policy &p, double *ri
                                 for (int j = 0; j < MM; ++j) B[j] = B[j] + ((j == sel ? 1.0 : 0.0) - a[j] * tau);
                             }
                             if (MODE == kEvt) {
-                                // one cursor bump per wave for the records of all its lanes
                                 nrec = min(nrec, kChg);
-                                uint32_t before = 0, total = 0;
+                                rec_count += (unsigned long long)nrec;
+                            }
+                            if (MODE == kEvt && n.ev_key) {
+                                // this step's records take consecutive slots of the wave's reservation
+                                step_nrec = nrec;
+                                uint32_t before = 0;
 #pragma unroll
-                                for (int q = 0; q < kChg; ++q) {
-                                    const uint64_t mq = __ballot(nrec > q);
-                                    before += __popcll(mq & lanemask_lt());
-                                    total += __popcll(mq);
-                                }
-                                const int32_t leader = __ffsll((unsigned long long)__ballot(1)) - 1;
-                                unsigned long long base = 0;
-                                if ((int32_t)lane == leader) base = atomicAdd(n.ev_cursor, (unsigned long long)total);
-                                const uint32_t blo = (uint32_t)__shfl((int)(uint32_t)base, leader);
-                                const uint32_t bhi = (uint32_t)__shfl((int)(uint32_t)(base >> 32), leader);
-                                const int64_t at = (int64_t)(((unsigned long long)bhi << 32) | blo) + before;
-                                if (n.ev_key) {
+                                for (int q = 0; q < kChg; ++q) before += __popcll(__ballot(nrec > q) & lanemask_lt());
+                                {
                                     const unsigned long long key = (unsigned long long)__double_as_longlong(t_next);
 #pragma unroll
                                     for (int q = 0; q < kChg; ++q) {
                                         if (q < nrec) {
-                                            if (at + q < n.ev_cap) {
-                                                n.ev_key[at + q] = key;
-                                                n.ev_val[at + q] = ev_pack(rs[q], rd[q], rx[q]);
+                                            const int64_t at = (int64_t)slots.at((unsigned long long)(before + q));
+                                            if (at < n.ev_cap) {
+                                                n.ev_key[at] = key;
+                                                n.ev_val[at] = ev_pack(rs[q], rd[q], rx[q]);
                                             } else {
                                                 flags |= kFlagRecordsFull;
                                             }
@@ -907,11 +959,13 @@ __device__ __forceinline__ void sim_pc(const WorkList &wl, Policy &p, double *ri
             tot_events += __shfl_xor(tot_events, off);
             max_steps = max(max_steps, (unsigned long long)__shfl_xor(max_steps, off));
             flags |= (uint32_t)__shfl_xor((int)flags, off);
+            if (MODE == kEvt) rec_count += __shfl_xor(rec_count, off);
         }
         if (lane == 0) {
             if (tot_events) atomicAdd(wl.stats + 0, tot_events);
             atomicMax(wl.stats + 1, max_steps);
             if (flags) atomicOr(wl.stats + 2, (unsigned long long)flags);
+            if (MODE == kEvt && rec_count) atomicAdd(wl.net0.ev_cursor, rec_count);
         }
     }
 }
