@@ -376,43 +376,50 @@ def main():
     hbuf = torch.empty((G, hist[3]), dtype=torch.int32, device=dev) if hist else None
     gbuf = torch.empty(M, dtype=torch.float64, device=dev)
 
-    def step():
+    def step(with_stats):
         _, _, _, sf = ssa.run_device(model, N, t_end, grid, seed, hist=hist, out=(mean, var, hbuf),
-                                     with_stats=True)
+                                     with_stats=with_stats)
         wts = 2.0 * (mean - target)
-        _, sb = ssa.backward_device(model, N, t_end, grid, seed, wts, mean, out=gbuf, with_stats=True)
+        _, sb = ssa.backward_device(model, N, t_end, grid, seed, wts, mean, out=gbuf, with_stats=with_stats)
         return sf, sb
 
-    for _ in range(args.warmup):
-        step()
+    # warm-up with statistics: event counts (the same every step), status checks and the
+    # kernels' own times
+    fwd_ms, bwd_ms = [], []
+    stats_f = stats_b = None
+    for _ in range(max(args.warmup, 3)):
+        stats_f, stats_b = step(True)
+        assert stats_f["flags"] == 0 and stats_b["flags"] == 0, (stats_f, stats_b)
+        fwd_ms.append(stats_f["kernel_ms"])
+        bwd_ms.append(stats_b["kernel_ms"])
+    fwd_ms, bwd_ms = fwd_ms[-3:], bwd_ms[-3:]
     torch.cuda.synchronize()
 
+    # timed steps: the calls are asynchronous on the stream (no statistics, so no host wait
+    # inside a step), as a training loop issues them
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    fwd_ms, bwd_ms, events = [], [], 0
-    stats_f = stats_b = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
     for _ in range(args.steps):
-        stats_f, stats_b = step()
-        fwd_ms.append(stats_f["kernel_ms"])
-        bwd_ms.append(stats_b["kernel_ms"])
-        events += stats_f["events"] + stats_b["events"]
+        step(False)
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     step_ms = e0.elapsed_time(e1) / args.steps
+    events = args.steps * (stats_f["events"] + stats_b["events"])
     value = stats_f["events"] / (step_ms * 1e-3)
 
-    # forward-only timing (same kernels, no backward), for the grad / plain ratio
-    f_only = []
-    for _ in range(3):
-        torch.cuda.synchronize()
-        a0 = time.perf_counter()
-        ssa.run_device(model, N, t_end, grid, seed, hist=hist, out=(mean, var, hbuf), with_stats=True)
-        torch.cuda.synchronize()
-        f_only.append(time.perf_counter() - a0)
-    fwd_only_ms = 1e3 * float(np.median(f_only))
+    # forward-only timing (same kernels, no backward, issued like the steps), for the
+    # grad / plain ratio
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    f0.record(stream)
+    for _ in range(args.steps):
+        ssa.run_device(model, N, t_end, grid, seed, hist=hist, out=(mean, var, hbuf))
+    f1.record(stream)
+    torch.cuda.synchronize()
+    fwd_only_ms = f0.elapsed_time(f1) / args.steps
 
     # roofline of the dominant kernel (algorithmic lane-ops per launch / mean launch time)
     crossings = G * N / max(stats_f["events"], 1)                 # grid points passed per event
