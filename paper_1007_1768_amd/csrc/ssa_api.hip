@@ -1518,13 +1518,14 @@ ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, 
     double *src = (double *)gt, *dst = (double *)gt2;
     int64_t rows = n_traj;
     while (rows > 1) {
-        const int64_t orows = (rows + 1) / 2;
-        const int64_t cells = orows * m->M;
-        hipLaunchKernelGGL(pair_sum_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st, src, rows,
-                           m->M, dst);
+        int32_t L = 0;          // up to 8 levels per launch (tiles of 256 rows)
+        while (L < 8 && ((int64_t)1 << L) < rows) ++L;
+        const int64_t tiles = (rows + ((int64_t)1 << L) - 1) >> L;
+        hipLaunchKernelGGL(pair_sum_kernel, dim3((unsigned)tiles, (unsigned)m->M), dim3(256), 0, st, src, rows,
+                           m->M, L, dst);
         HIP_TRY(hipGetLastError());
         std::swap(src, dst);
-        rows = orows;
+        rows = tiles;
     }
     hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((m->M + 255) / 256)), dim3(256), 0, st, src, m->M,
                        1.0 / (double)n_traj, grad);

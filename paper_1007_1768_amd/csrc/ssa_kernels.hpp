@@ -734,16 +734,31 @@ __global__ void hist_quantile_kernel(const uint32_t *__restrict__ hist, int32_t 
     out[idx] = lo + b * width;
 }
 
-// Fixed-order pairwise sum of the per-trajectory gradient rows, then the 1/N scale.
-// Stage: out[r][j] = in[2r][j] + in[2r+1][j] (odd tail copied).
-__global__ void pair_sum_kernel(const double *__restrict__ in, int64_t rows, int32_t M, double *__restrict__ out) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t orows = (rows + 1) / 2;
-    if (idx >= orows * M) return;
-    const int64_t r = idx / M;
-    const int32_t j = (int32_t)(idx % M);
-    const double v0 = in[(2 * r) * M + j];
-    out[idx] = (2 * r + 1 < rows) ? v0 + in[(2 * r + 1) * M + j] : v0;
+// Fixed-order pairwise sum of the per-trajectory gradient rows, then the 1/N scale.  One
+// level: out[r][j] = in[2r][j] + in[2r+1][j], an odd last row copied.  A launch applies L
+// such levels at once to tiles of 2^L rows in LDS (block (tile, column)): tiles start at
+// multiples of 2^L, so no pair crosses a tile and only the last tile sees the odd tails,
+// which gives the same sums, in the same order, as L one-level passes.
+__global__ void __launch_bounds__(256) pair_sum_kernel(const double *__restrict__ in, int64_t rows, int32_t M,
+                                                       int32_t L, double *__restrict__ out) {
+    __shared__ double v[256];
+    const int64_t t = blockIdx.x;
+    const int32_t j = (int32_t)blockIdx.y;
+    const int32_t i = (int32_t)threadIdx.x;
+    const int64_t r0 = t << L;
+    int64_t valid = min((int64_t)1 << L, rows - r0);
+    if (i < valid) v[i] = in[(r0 + i) * M + j];
+    __syncthreads();
+    for (int32_t l = 0; l < L; ++l) {
+        const int64_t ov = (valid + 1) / 2;
+        double x = 0.0;
+        if (i < ov) x = (2 * i + 1 < valid) ? v[2 * i] + v[2 * i + 1] : v[2 * i];
+        __syncthreads();
+        if (i < ov) v[i] = x;
+        __syncthreads();
+        valid = ov;
+    }
+    if (i == 0) out[t * M + j] = v[0];
 }
 
 __global__ void scale_kernel(const double *__restrict__ in, int32_t M, double scale, double *__restrict__ out) {
