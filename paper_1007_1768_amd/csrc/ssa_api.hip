@@ -61,6 +61,7 @@ ssa_status fail(ssa_status st, const char *fmt, ...) {
     } while (0)
 
 constexpr int32_t kMaxSpecies = 1024;
+static_assert(2 * kMaxSpecies + 1 <= kXyTile, "an Avg-XY tile must hold one point of every chain");
 constexpr int32_t kMaxReactions = 4096;
 constexpr int32_t kMaxProduct = (1 << 19) - 4;
 constexpr uint64_t kDefaultMaxEvents = 1ull << 62;
@@ -1857,7 +1858,8 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
             // the complete groups (all of them after the last epoch)
             const int64_t P_e = last ? (W + k - 1) / k : W / k;
             if (xy_time && P_e > 0 && P_done + P_e <= xy_cap) {
-                hipLaunchKernelGGL(xy_kernel, dim3((unsigned)P_e, (unsigned)(S + 1)), dim3(kWave), 0, st,
+                hipLaunchKernelGGL(xy_kernel, dim3((unsigned)P_e, (unsigned)((2 * S + 1 + kWave - 1) / kWave)),
+                                   dim3(kWave), 0, st,
                                    (const double *)wt, (const double *)wm, (const double *)wv, W, S, k, P_e,
                                    xy_time + P_done, xy_mean + P_done * S, xy_var + P_done * S);
                 HIP_TRY(hipGetLastError());

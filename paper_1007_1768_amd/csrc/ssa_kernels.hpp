@@ -816,67 +816,108 @@ __global__ void evt_diff_kernel(const unsigned long long *__restrict__ key, cons
     }
 }
 
-// Avg-XY: groups of k successive Avg-Y points (the last one may be shorter).  One wave per
-// (group, column), column S being the time: the wave loads 64 consecutive points at a time
-// and adds them in order through lane broadcasts, so each sum is the plain left-to-right
-// binary64 sum (then one division by the group's size), while the next 64 loads are in
-// flight -- a single thread per group was bound by load latency at k = 10^6.
-__device__ __forceinline__ double readlane_f64(double v, int32_t l) {
-    const long long b = __double_as_longlong(v);
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, l);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)((unsigned long long)b >> 32), l);
-    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
+// Avg-XY: groups of k successive Avg-Y points (the last one may be shorter).  A group has
+// C = 2S + 1 chains -- the time, S means and S variances -- each summed left to right in
+// binary64 and then divided once by the group's size.  One wave per group (and per 64
+// chains): the wave copies the group's points tile by tile into LDS with coalesced loads of
+// whole rows, and lane j adds chain j of the tile in order while the loads of the next tile
+// are in flight.  A wave per chain, adding 64 lane broadcasts in a row, spent most of the
+// adaptive run at k = 10^6 on that serial chain.
+constexpr int kXyRegs = 36;                 // doubles per lane staged for the next tile
+constexpr int kXyTile = kXyRegs * kWave;    // doubles per tile: T points of C values
+constexpr int kXyBatch = 16;                // LDS reads of a chain in flight together
 
 __global__ void __launch_bounds__(64) xy_kernel(const double *__restrict__ y_time, const double *__restrict__ y_mean,
                                                 const double *__restrict__ y_var, int64_t U, int32_t S, int64_t k,
                                                 int64_t P, double *__restrict__ xy_time,
                                                 double *__restrict__ xy_mean, double *__restrict__ xy_var) {
+    __shared__ double tile[kXyTile];
     const int64_t p = blockIdx.x;
-    const int32_t c = blockIdx.y;
     const int32_t lane = (int32_t)threadIdx.x;
     if (p >= P) return;
+    const int32_t C = 2 * S + 1;
+    const int32_t T = kXyTile / C;          // points per tile, >= 1 for S <= 1151
+    const int32_t TS = T * S;
     const int64_t u0 = p * k, u1 = min(u0 + k, U);
-    const double kk = (double)(u1 - u0);
-    const bool tcol = c == S;
-    auto load = [&](int64_t u, double &a, double &b) {
-        a = 0.0;
-        b = 0.0;
-        if (u < u1) {
-            if (tcol) {
-                a = y_time[u];
-            } else {
-                a = y_mean[(size_t)u * S + c];
-                b = y_var[(size_t)u * S + c];
-            }
-        }
-    };
-    double s1 = 0.0, s2 = 0.0;
-    double a, b;
-    load(u0 + lane, a, b);
-    for (int64_t base = u0; base < u1; base += kWave) {
-        const double ca = a, cb = b;
-        load(base + kWave + lane, a, b);     // the next 64 points
-        const int64_t nb = min((int64_t)kWave, u1 - base);
-        if (nb == kWave) {
+    // tile layout: times at [0, T), means at [T, T + T*S), variances at [T + T*S, T*C),
+    // each in the row-major order of the source arrays
+    // staged slot r of this lane: its source (time row, or a mean or variance entry) is the
+    // same for every tile; only the tile's first point and its point count change
+    const double *pb[kXyRegs];
+    int32_t po[kXyRegs];
+    bool pt[kXyRegs];
 #pragma unroll
-            for (int32_t i = 0; i < kWave; ++i) {
-                s1 = s1 + readlane_f64(ca, i);
-                if (!tcol) s2 = s2 + readlane_f64(cb, i);
-            }
+    for (int32_t r = 0; r < kXyRegs; ++r) {
+        const int32_t f = lane + r * kWave;
+        pt[r] = f < T;
+        if (f < T) {
+            pb[r] = y_time + f;
+            po[r] = f;
+        } else if (f < T + TS) {
+            pb[r] = y_mean + (f - T);
+            po[r] = f - T;
+        } else if (f < T * C) {
+            pb[r] = y_var + (f - T - TS);
+            po[r] = f - T - TS;
         } else {
-            for (int32_t i = 0; i < (int32_t)nb; ++i) {
-                s1 = s1 + readlane_f64(ca, i);
-                if (!tcol) s2 = s2 + readlane_f64(cb, i);
-            }
+            pb[r] = y_time;
+            po[r] = INT32_MAX;   // never loaded
         }
     }
-    if (lane == 0) {
-        if (tcol) {
-            xy_time[p] = s1 / kk;
+    double nx[kXyRegs];
+    // every lane loads (slots past the tile's points read y_time[0] and keep 0), so the loads
+    // stay unconditional and all of them are in flight together
+    auto fetch = [&](int64_t base) {
+        const int32_t n = (int32_t)min((int64_t)T, u1 - base), nS = n * S;
+        const int64_t bS = base * S;
+#pragma unroll
+        for (int32_t r = 0; r < kXyRegs; ++r) {
+            const bool ok = po[r] < (pt[r] ? n : nS);
+            const double v = *(ok ? pb[r] + (pt[r] ? base : bS) : y_time);
+            nx[r] = ok ? v : 0.0;
+        }
+    };
+    const int32_t j = (int32_t)blockIdx.y * kWave + lane;   // this lane's chain
+    const bool act = j < C;
+    int32_t off = 0, stride = 1;
+    if (j >= 1 && j <= S) {
+        off = T + (j - 1);
+        stride = S;
+    } else if (j > S) {
+        off = T + TS + (j - S - 1);
+        stride = S;
+    }
+    double s = 0.0;
+    fetch(u0);
+    for (int64_t base = u0; base < u1; base += T) {
+        __syncthreads();                    // every chain is done with the previous tile
+#pragma unroll
+        for (int32_t r = 0; r < kXyRegs; ++r) tile[lane + r * kWave] = nx[r];
+        __syncthreads();
+        if (base + T < u1) fetch(base + T);
+        const int32_t n = (int32_t)min((int64_t)T, u1 - base);
+        if (act) {
+            // reads issued kXyBatch at a time, so one LDS latency covers kXyBatch adds
+            const double *c = tile + off;
+            int32_t i = 0;
+            for (; i + kXyBatch <= n; i += kXyBatch) {
+                double v[kXyBatch];
+#pragma unroll
+                for (int32_t q = 0; q < kXyBatch; ++q) v[q] = c[(i + q) * stride];
+#pragma unroll
+                for (int32_t q = 0; q < kXyBatch; ++q) s = s + v[q];
+            }
+            for (; i < n; ++i) s = s + c[i * stride];
+        }
+    }
+    if (act) {
+        const double kk = (double)(u1 - u0);
+        if (j == 0) {
+            xy_time[p] = s / kk;
+        } else if (j <= S) {
+            xy_mean[(size_t)p * S + (j - 1)] = s / kk;
         } else {
-            xy_mean[(size_t)p * S + c] = s1 / kk;
-            xy_var[(size_t)p * S + c] = s2 / kk;
+            xy_var[(size_t)p * S + (j - S - 1)] = s / kk;
         }
     }
 }
