@@ -228,16 +228,18 @@ def adaptive_measure(ssa, torch, dev, reps=3, workload="viral"):
     m = w["model"]()
     N, t_end, seed = w["n_traj"], w["t_end"], w["seed"]
     model = ssa.Model.from_dict(m)
-    best = None
+    best, best_wall = None, float("inf")
     for _ in range(reps):
         torch.cuda.synchronize()
         a0 = time.perf_counter()
         out = ssa.adaptive_device(model, N, t_end, seed, N, with_stats=True)
         torch.cuda.synchronize()
         wall = time.perf_counter() - a0
+        best_wall = min(best_wall, wall)        # the first call also compiles the network's kernels
         st = out["stats"]
         if best is None or st["kernel_ms"] < best["kernel_ms"]:
-            best = dict(st, wall_ms=1e3 * wall, P=int(out["xy_time"].shape[0]))
+            best = dict(st, P=int(out["xy_time"].shape[0]))
+    best["wall_ms"] = 1e3 * best_wall
     model.close()
     return {"workload": "%s: %d trajectories, t_end %g, Avg-XY groups of %d points" % (workload, N, t_end, N),
             "events": best["events"], "avg_xy_points": best["P"], "device_ms": round(best["kernel_ms"], 3),

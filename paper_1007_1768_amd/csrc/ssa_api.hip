@@ -1832,13 +1832,13 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
                 }
                 const int64_t n_chunks = (U_e + kFinChunk - 1) / kFinChunk;
                 HIP_TRY(escr.alloc(&T, sizeof(long long) * (size_t)n_chunks * S * 3));
-                hipLaunchKernelGGL(chunk_total_kernel, dim3((unsigned)n_chunks, (unsigned)S), dim3(256), 0, st,
+                hipLaunchKernelGGL(chunk_total_kernel, dim3((unsigned)n_chunks), dim3(256), 0, st,
                                    (const unsigned long long *)D, (const unsigned long long *)Dhi, U_e, S, (long long *)T);
                 HIP_TRY(hipGetLastError());
                 hipLaunchKernelGGL(chunk_scan_kernel, dim3((unsigned)S), dim3(1024), 0, st, (long long *)T, n_chunks, S,
                                    (long long *)carry);
                 HIP_TRY(hipGetLastError());
-                hipLaunchKernelGGL(chunk_final_kernel, dim3((unsigned)n_chunks, (unsigned)S), dim3(256), 0, st,
+                hipLaunchKernelGGL(chunk_final_kernel, dim3((unsigned)n_chunks), dim3(256), 0, st,
                                    (const unsigned long long *)D, (const unsigned long long *)Dhi, U_e, S,
                                    (const long long *)T, (const int32_t *)m->d_x0, n_traj, em, evv);
                 HIP_TRY(hipGetLastError());

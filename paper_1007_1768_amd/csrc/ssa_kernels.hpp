@@ -407,14 +407,14 @@ __global__ void __launch_bounds__(1024) moment_final_kernel(const unsigned long 
 }
 
 // The same finalize for long point sequences (the adaptive selective memory's Avg-Y), over
-// many blocks: chunks of kFinChunk points per (chunk, species) block.
+// many blocks: chunks of kFinChunk points per block, which takes the species one after the
+// other (a point's S entries share cache lines, so the later species read them from L2
+// instead of fetching them again from HBM as blocks of one species each did).
 // Step 1: the chunk totals of the three difference sums.
 constexpr int kFinChunk = 1024;
-__global__ void __launch_bounds__(256) chunk_total_kernel(const unsigned long long *__restrict__ D,
-                                                          const unsigned long long *__restrict__ Dhi, int64_t G,
-                                                          int32_t S, long long *__restrict__ T) {
-    const int64_t c = blockIdx.x;
-    const int32_t s = blockIdx.y;
+__device__ __forceinline__ void chunk_total_one(const unsigned long long *__restrict__ D,
+                                                const unsigned long long *__restrict__ Dhi, int64_t G, int32_t S,
+                                                long long *__restrict__ T, int64_t c, int32_t s) {
     const int64_t g0 = c * kFinChunk, g1 = min(g0 + kFinChunk, G);
     int64_t a1 = 0, a2 = 0, a3 = 0;
     for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
@@ -436,6 +436,15 @@ __global__ void __launch_bounds__(256) chunk_total_kernel(const unsigned long lo
         __syncthreads();
     }
     if (threadIdx.x < 3) T[((size_t)c * S + s) * 3 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void __launch_bounds__(256) chunk_total_kernel(const unsigned long long *__restrict__ D,
+                                                          const unsigned long long *__restrict__ Dhi, int64_t G,
+                                                          int32_t S, long long *__restrict__ T) {
+    for (int32_t s = 0; s < S; ++s) {
+        chunk_total_one(D, Dhi, G, S, T, blockIdx.x, s);
+        __syncthreads();                // the shared sums are reused by the next species
+    }
 }
 
 // Step 2: exclusive prefix of the chunk totals per species (one block per species),
@@ -478,14 +487,12 @@ __global__ void __launch_bounds__(1024) chunk_scan_kernel(long long *__restrict_
 
 // Step 3: within each chunk, the inclusive prefix (4 points per thread, then a block scan)
 // plus the chunk's offset and the initial-state terms, then the moments per point.
-__global__ void __launch_bounds__(256) chunk_final_kernel(const unsigned long long *__restrict__ D,
-                                                          const unsigned long long *__restrict__ Dhi, int64_t G,
-                                                          int32_t S, const long long *__restrict__ T,
-                                                          const int32_t *__restrict__ x0, int64_t n_traj,
-                                                          double *__restrict__ mean, double *__restrict__ var) {
+__device__ __forceinline__ void chunk_final_one(const unsigned long long *__restrict__ D,
+                                                const unsigned long long *__restrict__ Dhi, int64_t G, int32_t S,
+                                                const long long *__restrict__ T, const int32_t *__restrict__ x0,
+                                                int64_t n_traj, double *__restrict__ mean, double *__restrict__ var,
+                                                int64_t c, int32_t s) {
     static_assert(kFinChunk == 4 * 256, "four points per thread");
-    const int64_t c = blockIdx.x;
-    const int32_t s = blockIdx.y;
     const int64_t g0 = c * kFinChunk + 4 * (int64_t)threadIdx.x;
     int64_t v1[4], v2[4], v3[4];
     int64_t a1 = 0, a2 = 0, a3 = 0;
@@ -536,6 +543,17 @@ __global__ void __launch_bounds__(256) chunk_final_kernel(const unsigned long lo
             const i128s sx2 = i128_add(i128_add(base2, i128_from(c2)), i128_mul_u64(i128_from(c3), 1ull << 24));
             moment_point(sx, sx2, n_traj, dn, dd, mean + (size_t)g * S + s, var + (size_t)g * S + s);
         }
+    }
+}
+
+__global__ void __launch_bounds__(256) chunk_final_kernel(const unsigned long long *__restrict__ D,
+                                                          const unsigned long long *__restrict__ Dhi, int64_t G,
+                                                          int32_t S, const long long *__restrict__ T,
+                                                          const int32_t *__restrict__ x0, int64_t n_traj,
+                                                          double *__restrict__ mean, double *__restrict__ var) {
+    for (int32_t s = 0; s < S; ++s) {
+        chunk_final_one(D, Dhi, G, S, T, x0, n_traj, mean, var, blockIdx.x, s);
+        __syncthreads();                // the shared scan is reused by the next species
     }
 }
 
