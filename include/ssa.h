@@ -83,12 +83,28 @@ typedef struct {
     int32_t nbins;   /* 1..4096 */
 } ssa_hist_spec;
 
+/* How the simulation kernel of a call was launched (reported in ssa_stats.form).  Every
+ * form gives the same bits; they differ in how lanes get their next trajectory. */
+typedef enum {
+    SSA_FORM_NONE = 0,
+    SSA_FORM_TWO_WAVE = 1,     /* blocks of a simulating wave and a wave computing its draws,
+                                  one generation of 64 trajectories at a time */
+    SSA_FORM_GENERATIONS = 2,  /* persistent blocks; a wave takes its next 64 trajectories once
+                                  all of its lanes are done */
+    SSA_FORM_REFILL = 3,       /* persistent blocks; a lane takes the next trajectory as soon as
+                                  its own ends */
+    SSA_FORM_TABLE = 4,        /* the table-driven kernel (sequential order, any network) */
+    SSA_FORM_WAVE = 5          /* one trajectory per wave (64-chunk order) */
+} ssa_launch_form;
+
 /* Filled when a non-NULL pointer is passed (the call then synchronises). */
 typedef struct {
     uint64_t events;      /* events applied with t <= t_end, summed over trajectories */
     uint64_t max_steps;   /* largest per-trajectory event count */
     uint32_t flags;       /* bit 0: overflow seen, bit 1: event limit reached */
     float kernel_ms;      /* device time of the simulation kernel(s) */
+    uint32_t form;        /* ssa_launch_form of the simulation kernel */
+    uint32_t blocks;      /* its grid size in blocks */
 } ssa_stats;
 
 /* Model (Section 3.2 model format).
@@ -135,55 +151,84 @@ typedef struct {
 ssa_status ssa_model_create_laws(int32_t n_species, int32_t n_reactions, const int32_t *reactants,
                                  const int32_t *products, const double *rates, const int32_t *x0,
                                  int32_t sum_order, const ssa_rate_law *laws, ssa_model **out);
+/* Releases a model handle and its device copies (NULL is ignored). */
 void ssa_model_destroy(ssa_model *model);
 
-/* Host convenience (synchronous): n_traj trajectories 0..n_traj-1 on [0, t_end], grid
- * [n_grid] host (non-decreasing, inside [0, t_end]), outputs mean and var [G*S] host.
- * stats may be NULL.  Errors: SSA_E_INVALID, SSA_E_NOMEM, SSA_E_DEVICE, SSA_E_OVERFLOW,
- * SSA_E_EVENT_LIMIT (outputs undefined on error). */
+/* Host convenience (synchronous).  Section 2: n_traj independent Gillespie trajectories
+ * 0..n_traj-1 of the model on [0, t_end]; Section 3.2.1: their states aligned on the time
+ * grid and reduced across trajectories; Section 4: mean and variance at every grid point.
+ *   grid [n_grid] host: non-decreasing, inside [0, t_end] (checked: SSA_E_INVALID)
+ *   mean, var [G*S] host outputs (caller-owned); stats may be NULL.
+ * Errors: SSA_E_INVALID, SSA_E_NOMEM, SSA_E_DEVICE, SSA_E_OVERFLOW, SSA_E_EVENT_LIMIT
+ * (outputs undefined on error). */
 ssa_status ssa_run(const ssa_model *model, int64_t n_traj, double t_end, const double *grid,
                    int32_t n_grid, uint64_t seed, double *mean, double *var, ssa_stats *stats);
 
-/* Device form.  rates: [M] device, overrides the model's rate constants (NULL = model's).
- * grid [G] device; mean, var [G*S] device; hist + d_hist [G*nbins] device (both NULL for
- * none).  max_events: per-trajectory cap (0 = 2^62).  Asynchronous on stream when stats is
- * NULL: an overflow or event-limit condition is then only reported by a later call with
- * stats, so pass stats when the model may overflow.  The grid is validated on the device
- * side only in the sense that a non-monotone grid gives undefined results; use ssa_run for
- * checked host grids. */
-ssa_status ssa_run_device(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
-                          const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events,
-                          double *mean, double *var, const ssa_hist_spec *hist, uint32_t *d_hist,
-                          void *stream, ssa_stats *stats);
+/* Rate constants from log rate constants (the parameters theta_j = ln c_j of the gradient
+ * below; Section 4's sensitivity analysis varies such parameters): rates[j] = e^theta_j for
+ * j < n, both device arrays, asynchronous on stream, with fixed roundings the CPU oracle
+ * reproduces bit for bit:
+ *   theta < -708 (also -inf): 0;   theta > 709 or NaN: NaN (an invalid rate);
+ *   else k = rint(fl(theta * INV_LN2)) (ties to even, INV_LN2 = 0x1.71547652b82fep0),
+ *   r = fma(-k, LN2_LO, fma(-k, LN2_HI, theta)) (LN2_HI = 0x1.62e42fee00000p-1,
+ *   LN2_LO = 0x1.a39ef35793c76p-33), p = E_13 then p = fma(p, r, E_n) for n = 12 .. 0 with
+ *   E_n = fl(1/n!), and the result p * 2^k (exact).  Within 2 ulp of e^theta. */
+ssa_status ssa_rates_from_log(const double *log_rates, int32_t n, double *rates, void *stream);
 
-/* Likelihood-ratio gradient of a loss L(mean) with respect to theta_j = ln c_j, by
- * re-simulating the same trajectories (same seed, same Philox counters):
+/* Device form of ssa_run (Sections 2, 3.2.1 and 4 as above), with an optional histogram
+ * of one species at every grid point (a further recombining function, Section 5).
+ *   rates [M] device: rate constants for this run (NULL = the model's), or
+ *   log_rates [M] device: theta_j = ln c_j, turned into c_j by ssa_rates_from_log's formula
+ *     on the device (NULL = none); at most one of the two.
+ *   grid [G] device; mean, var [G*S] device outputs; hist + d_hist [G*nbins] device (both
+ *   NULL for none).  max_events: per-trajectory cap (0 = 2^62).
+ * Device inputs are checked on the device: a grid that is not non-decreasing inside
+ * [0, t_end] (NaN included) or a log rate that is NaN or above 709 refuses the run -- no
+ * trajectory is simulated, mean and var are NaN and the histogram counts 0xffffffff -- and
+ * the call returns SSA_E_INVALID when stats is given.  Asynchronous on stream when stats is
+ * NULL: a refusal, an overflow or an event-limit condition is then not reported by the
+ * status, so pass stats when the inputs or the model may fail.
+ * Errors: SSA_E_INVALID, SSA_E_NOMEM, SSA_E_DEVICE, SSA_E_OVERFLOW, SSA_E_EVENT_LIMIT,
+ * SSA_E_UNSUPPORTED. */
+ssa_status ssa_run_device(const ssa_model *model, const double *rates, const double *log_rates,
+                          int64_t n_traj, double t_end, const double *grid, int32_t n_grid,
+                          uint64_t seed, uint64_t max_events, double *mean, double *var,
+                          const ssa_hist_spec *hist, uint32_t *d_hist, void *stream, ssa_stats *stats);
+
+/* Likelihood-ratio gradient of a loss L(mean) with respect to theta_j = ln c_j (the local
+ * form of Section 4's sensitivity analysis of the mean trajectories), by re-simulating the
+ * same trajectories (same seed, same Philox counters):
  *   grad_j = sum_{g,s} w_{g,s} (1/N) sum_i (X^i_s(t_g) - mhat_{g,s}) (n^i_j(t_g) - A^i_j(t_g))
  * with n_j the firing count and A_j the integrated propensity.  All pointers device:
- * rates [M] (NULL = model's), grid [G], w [G*S] (dL/dmean), mhat [G*S] (centring, usually
- * the forward mean), grad [M] output.  The per-trajectory sums are reduced in a fixed
- * pairwise order, so the result is deterministic.  Same status codes as ssa_run_device
- * (SSA_E_UNSUPPORTED for a SEQ model with more than 32 reactions). */
-ssa_status ssa_backward_device(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
-                               const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events,
-                               const double *w, const double *mhat, double *grad, void *stream,
-                               ssa_stats *stats);
+ * rates or log_rates [M] as in ssa_run_device (the forward's), grid [G], w [G*S]
+ * (dL/dmean), mhat [G*S] (centring, usually the forward mean), grad [M] output.  The
+ * per-trajectory sums are reduced in a fixed pairwise order, so the result is
+ * deterministic.  Device inputs are checked as in ssa_run_device (a refused run gives a
+ * NaN gradient and, with stats, SSA_E_INVALID).  Same status codes as ssa_run_device
+ * (SSA_E_UNSUPPORTED for a SEQ model with more than 32 reactions or with rate laws). */
+ssa_status ssa_backward_device(const ssa_model *model, const double *rates, const double *log_rates,
+                               int64_t n_traj, double t_end, const double *grid, int32_t n_grid,
+                               uint64_t seed, uint64_t max_events, const double *w, const double *mhat,
+                               double *grad, void *stream, ssa_stats *stats);
 
-/* The same gradient for a loss on the grid means and variances: with wv [G*S] = dL/dvar and
- * the centring vhat [G*S] (usually the forward variance; both device) every crossing adds
+/* The same gradient for a loss on the grid means and variances (Section 4 reduces runs to
+ * average and variance): with wv [G*S] = dL/dvar and the centring vhat [G*S] (usually the
+ * forward variance; both device) every crossing adds
  *   wv_{g,s} ((X_s(t_g) - mhat_{g,s})^2 - vhat_{g,s}) z_j(t_g)
  * to the mean term, the score-function derivative of the variance (d E[(X - mu)^2] / d theta
  * = E[(X - mu)^2 z] since E[X - mu] = 0; E[z] = 0 makes the centring unbiased).  The weights
  * are folded into prefix tables of w - 2 wv mhat, wv and their constants, evaluated as a
  * polynomial in x per interval, so the rounding error scales with wv (x^2 + mhat^2 + |vhat|)
- * rather than with the centred square.  wv == NULL gives ssa_backward_device.  Limits and
- * codes as ssa_backward_device. */
-ssa_status ssa_backward_moments_device(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
-                                       const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events,
-                                       const double *w, const double *mhat, const double *wv, const double *vhat,
-                                       double *grad, void *stream, ssa_stats *stats);
+ * rather than with the centred square.  wv == NULL gives ssa_backward_device.  Arguments,
+ * limits and codes as ssa_backward_device. */
+ssa_status ssa_backward_moments_device(const ssa_model *model, const double *rates, const double *log_rates,
+                                       int64_t n_traj, double t_end, const double *grid, int32_t n_grid,
+                                       uint64_t seed, uint64_t max_events, const double *w, const double *mhat,
+                                       const double *wv, const double *vhat, double *grad, void *stream,
+                                       ssa_stats *stats);
 
-/* Autotuning of the forward launch for this model and problem size: every candidate
+/* Autotuning of the forward launch (the forward of ssa_run_device, Sections 2 and 3.2.1;
+ * the search itself is no step of the paper's method) for this model and problem size: every candidate
  * configuration (LDS window bytes 2048 .. 16384, flush by atomics or through wave-private
  * slabs) is timed on the caller's problem (grid [n_grid] device, the same outputs for all:
  * results never depend on the configuration); the fastest is remembered for (device
@@ -203,20 +248,22 @@ ssa_status ssa_autotune_forward(const ssa_model *model, const double *rates, int
                                 ssa_tune_result *result);
 
 /* Forward pass that also returns the likelihood-ratio Jacobian of the grid means with
- * respect to theta_j = ln c_j, from the same single simulation pass:
+ * respect to theta_j = ln c_j (every local sensitivity of Section 4's mean trajectories),
+ * from the same single simulation pass:
  *   jac[g][s][j] = (1/N) sum_i (X^i_s(t_g) - mean_{g,s}) (n^i_j(t_g) - A^i_j(t_g))
  * (the estimator of ssa_backward_device before it is contracted with w, centred on this
- * run's own mean).  Arguments as ssa_run_device (no histogram); jac [G*S*M] device.  The
+ * run's own mean).  Arguments as ssa_run_device (rates or log_rates, no histogram); jac [G*S*M] device.  The
  * item sums are reduced in a fixed order, so the Jacobian is deterministic.  Needs a
  * SSA_SUM_SEQ model with M <= 32 and S <= 64 and ceil(N/64) * G * (S+1) * M * 8 bytes of
  * scratch (at most 4 GiB, or SSA_JAC_BYTES); SSA_E_UNSUPPORTED otherwise (use
  * ssa_backward_device). */
-ssa_status ssa_run_jacobian_device(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
-                                   const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events,
-                                   double *mean, double *var, double *jac, void *stream, ssa_stats *stats);
+ssa_status ssa_run_jacobian_device(const ssa_model *model, const double *rates, const double *log_rates,
+                                   int64_t n_traj, double t_end, const double *grid, int32_t n_grid,
+                                   uint64_t seed, uint64_t max_events, double *mean, double *var, double *jac,
+                                   void *stream, ssa_stats *stats);
 
 /* Forward pass returning the species covariance matrix at every grid point (a further
- * recombining function over the time-aligned states): cov [G*S*S] device,
+ * recombining function over the time-aligned states, Sections 3.2.1 and 5): cov [G*S*S] device,
  *   cov[g][s][r] = (N sum X_s X_r - sum X_s sum X_r) / (N (N - 1))   (0 when N == 1)
  * from exact integer sums, rounded once, so cov[g][s][s] is the variance of ssa_run_device;
  * mean [G*S] device.  Arguments as ssa_run_device (no histogram).  Needs a SSA_SUM_SEQ
@@ -249,7 +296,8 @@ ssa_status ssa_adaptive_device(const ssa_model *model, const double *rates, int6
                                double *xy_var, int64_t xy_cap, double *y_time, double *y_mean, double *y_var,
                                int64_t y_cap, int64_t *n_points, void *stream, ssa_stats *stats);
 
-/* Quantiles per grid point from a histogram of ssa_run_device (spec as used there):
+/* Quantiles per grid point (one of the more informative recombining functions Section 5
+ * asks for) from a histogram of ssa_run_device (spec as used there):
  * for each q in qs (0 < q <= 1) the rank k = max(1, ceil(q N)) in binary64 and the result
  * is lo + b width for the first bin b whose cumulative count reaches k (with width 1 and
  * no clamping in the top bin, the k-th smallest count).  hist [G*nbins], qs [nq], out
@@ -257,13 +305,15 @@ ssa_status ssa_adaptive_device(const ssa_model *model, const double *rates, int6
 ssa_status ssa_hist_quantiles(const uint32_t *hist, int32_t n_grid, const ssa_hist_spec *spec, int64_t n_traj,
                               const double *qs, int32_t nq, int32_t *out, void *stream);
 
-/* grad[j] = sum_{g,s} w[g][s] jac[g][s][j] on the device (fixed summation order): the
+/* grad[j] = sum_{g,s} w[g][s] jac[g][s][j] on the device (fixed summation order; Section 4's
+ * sensitivity of the means, contracted with a loss gradient): the
  * vector-Jacobian product that turns the forward Jacobian into d loss / d ln c for
  * w = d loss / d mean.  jac [G*S*M], w [G*S], grad [M], all device; asynchronous on stream. */
 ssa_status ssa_jacobian_vjp(const double *jac, const double *w, int32_t n_grid, int32_t n_species,
                             int32_t n_reactions, double *grad, void *stream);
 
-/* Per-trajectory record of trajectories traj_begin .. traj_begin+count-1 (synchronous, all
+/* Per-trajectory record (Section 2: one trajectory, one realisation of the CTMC; Section
+ * 3.2's workers can write whole trajectories out) of trajectories traj_begin .. traj_begin+count-1 (synchronous, all
  * pointers host): states [count*G*S] int32 at the grid points, events [count], draws
  * [count] (Philox blocks consumed), t_last [count] (time of the last applied event, 0 if
  * none), n_fired [count*M] and a_int [count*M] (integral of a_j over [0, t_end]) may be
@@ -283,12 +333,16 @@ ssa_status ssa_record(const ssa_model *model, const double *rates, int64_t traj_
 ssa_status ssa_batch_create(int32_t n_models, const ssa_model *const *models, const int64_t *n_traj,
                             const double *t_end, const double *const *grids, const int32_t *n_grid,
                             const uint64_t *seeds, ssa_batch **out);
-/* means[b], vars[b]: device pointers [G_b * S_b].  Asynchronous unless stats != NULL. */
+/* One run of a batch (Section 3.2's parameter-swept simulations, reduced per network as in
+ * Sections 3.2.1 and 4): means[b], vars[b]: device pointers [G_b * S_b] (caller-owned);
+ * the launch sequence is captured as a hipGraph at the first call and replayed after.
+ * Asynchronous unless stats != NULL.  Errors: SSA_E_INVALID, SSA_E_DEVICE, SSA_E_OVERFLOW,
+ * SSA_E_EVENT_LIMIT. */
 ssa_status ssa_batch_run(ssa_batch *batch, double *const *means, double *const *vars, void *stream,
                          ssa_stats *stats);
 void ssa_batch_destroy(ssa_batch *batch);
 
-/* Autotuning of a batch: times the batched launch with each LDS window size (the
+/* Autotuning of a batch (the launch of ssa_batch_run; no step of the paper's method): times the batched launch with each LDS window size (the
  * built-in default, 2048 .. 16384 bytes; sizes that do not fit the LDS are skipped; results
  * never depend on the choice) and keeps the fastest for this handle's later runs (the
  * captured graph is rebuilt).  The trial runs write scratch outputs, not the caller's.

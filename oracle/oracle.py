@@ -36,6 +36,8 @@ def lib():
         L.orc_philox4x32_10.restype = None
         L.orc_neglog.argtypes = [ctypes.c_double]
         L.orc_neglog.restype = ctypes.c_double
+        L.orc_exp.argtypes = [ctypes.c_double]
+        L.orc_exp.restype = ctypes.c_double
         L.orc_uniforms.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
         L.orc_uniforms.restype = None
@@ -124,6 +126,12 @@ def philox(ctr, key):
 
 def neglog(r):
     return lib().orc_neglog(float(r))
+
+
+def exp_rates(theta):
+    """Rate constants c = e^theta from log rate constants, element by element (orc_exp)."""
+    th = np.asarray(theta, dtype=np.float64)
+    return np.array([lib().orc_exp(float(v)) for v in th.ravel()], dtype=np.float64).reshape(th.shape)
 
 
 def uniforms(seed, traj, k):

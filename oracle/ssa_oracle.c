@@ -156,6 +156,43 @@ double orc_neglog(double r)
 }
 
 /* ------------------------------------------------------------------------------------
+ * e^theta for the log rate constants theta = ln c (the parameters of the gradient; Section
+ * 4's sensitivity analysis varies rate parameters).  The paper fixes no arithmetic, so the
+ * reading is a plain argument reduction and a Taylor polynomial with stated roundings:
+ *   theta < -708 (below the normal range of c): 0;  theta > 709 or NaN: invalid (NaN);
+ *   k = nearest integer (ties to even) to fl(theta * (1/ln 2)), 1/ln 2 rounded to binary64;
+ *   r = theta - k ln 2 in two fused steps, first with LN2_HI, then with LN2_LO;
+ *   e^r by Horner over the Taylor coefficients 1/n!, n = 13 down to 0, each step one
+ *   fused multiply-add, the coefficients being the binary64 quotients 1/n! (n! is an exact
+ *   integer in binary64 up to 13!);
+ *   c = e^r * 2^k (a power-of-two scaling, exact for k >= -1021).
+ * |r| <= ln2/2 + |k| 2^-60, so the Taylor remainder |r|^14/14! < 2^-57 relative.
+ * ---------------------------------------------------------------------------------- */
+static const double ORC_INV_LN2 = 0x1.71547652b82fep+0;
+
+double orc_exp(double theta)
+{
+    if (theta < -708.0)
+        return 0.0;
+    if (!(theta <= 709.0))
+        return NAN;
+    double k = nearbyint(theta * ORC_INV_LN2);
+    double r = fma(-k, ORC_LN2_HI, theta);
+    r = fma(-k, ORC_LN2_LO, r);
+    double coef[14];
+    double fact = 1.0;
+    for (int n = 0; n < 14; ++n) {
+        if (n > 0)
+            fact = fact * (double)n;
+        coef[n] = 1.0 / fact;
+    }
+    double p = coef[13];
+    for (int n = 12; n >= 0; --n)
+        p = fma(p, r, coef[n]);
+    return ldexp(p, (int)k);
+}
+
+/* ------------------------------------------------------------------------------------
  * Model checks and mass-action propensities (Section 3.2: integer state, integer
  * stoichiometry, propensity from reactant amounts and the rate).
  *   order 0:           h = 1

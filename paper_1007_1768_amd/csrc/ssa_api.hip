@@ -115,6 +115,31 @@ size_t lds_max(int dev) {
     return (size_t)n;
 }
 
+// Launch form and grid size of the last simulation kernel this thread launched (copied into
+// ssa_stats.form / ssa_stats.blocks).
+struct LaunchRec {
+    uint32_t form = SSA_FORM_NONE;
+    uint32_t blocks = 0;
+};
+thread_local LaunchRec g_launch;
+
+void note_launch(uint32_t form, int64_t blocks) {
+    g_launch.form = form;
+    g_launch.blocks = (uint32_t)blocks;
+}
+
+// Launch form requested for the specialised kernels by SSA_LAUNCH_FORM (two_wave,
+// generations or refill; SSA_FORM_NONE when unset).  Forms a kernel kind does not have are
+// ignored there (the forward has no refill form).  Every form gives the same bits.
+uint32_t forced_form() {
+    const char *e = std::getenv("SSA_LAUNCH_FORM");
+    if (!e) return SSA_FORM_NONE;
+    if (std::strcmp(e, "two_wave") == 0) return SSA_FORM_TWO_WAVE;
+    if (std::strcmp(e, "generations") == 0) return SSA_FORM_GENERATIONS;
+    if (std::strcmp(e, "refill") == 0) return SSA_FORM_REFILL;
+    return SSA_FORM_NONE;
+}
+
 // Kernel choice for single-network launches: the kernel specialised to the network
 // (default) or the compiled table-driven one (SSA_KERNEL=generic).  Both give bit-identical
 // results; the variable only selects the implementation.
@@ -197,6 +222,7 @@ struct ssa_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     int32_t win_bytes = 0;            // LDS window bytes per cohort (0: built-in default), see ssa_batch_autotune
+    LaunchRec launch;                 // form and grid of the captured simulation launch
 };
 
 namespace {
@@ -448,7 +474,9 @@ hipError_t launch_generic_mm(const WorkList &wl, int64_t n_items, int dev, hipSt
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid_blocks(per_cu, dev, n_items)), dim3(kBlock), lds, st, wl);
+    const int64_t blocks = grid_blocks(per_cu, dev, n_items);
+    note_launch(SSA_FORM_TABLE, blocks);
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kBlock), lds, st, wl);
     return hipGetLastError();
 }
 
@@ -533,6 +561,7 @@ hipError_t fwd_blocks(const FwdKernel &k, bool slab, int dev, int64_t n_items, i
 }
 
 hipError_t fwd_launch(const FwdKernel &k, bool slab, int64_t blocks, WorkList &wl, hipStream_t st) {
+    note_launch(k.jit ? SSA_FORM_GENERATIONS : SSA_FORM_TABLE, blocks);
     if (k.jit) {
         void *args[] = {&wl};
         return hipModuleLaunchKernel(slab ? k.f_slab : k.f_atomic, (unsigned)blocks, 1, 1, kBlock, 1, 1,
@@ -542,13 +571,14 @@ hipError_t fwd_launch(const FwdKernel &k, bool slab, int64_t blocks, WorkList &w
     return hipLaunchKernel(slab ? k.g_slab : k.g_atomic, dim3((unsigned)blocks), dim3(kBlock), args, k.lds, st);
 }
 
-hipError_t launch_jit(hipFunction_t f, WorkList &wl, int64_t n_items, int dev, hipStream_t st) {
+hipError_t launch_jit(hipFunction_t f, WorkList &wl, int64_t n_items, int dev, hipStream_t st, uint32_t form) {
     int per_cu = 0;
     hipError_t e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBlock, 0);
     if (e != hipSuccess) return e;
+    const int64_t blocks = grid_blocks(per_cu, dev, n_items);
+    note_launch(form, blocks);
     void *args[] = {&wl};
-    return hipModuleLaunchKernel(f, (unsigned)grid_blocks(per_cu, dev, n_items), 1, 1, kBlock, 1, 1, 0, st, args,
-                                 nullptr);
+    return hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, kBlock, 1, 1, 0, st, args, nullptr);
 }
 
 // Two-wave blocks (simulating wave + drawing wave), one work item at a time per block.
@@ -558,14 +588,27 @@ hipError_t launch_jit_pc(hipFunction_t f, WorkList &wl, int64_t n_items, int dev
     int64_t cap = (int64_t)8 * cu_count(dev);
     if (const char *e = std::getenv("SSA_DRAW_WAVE_BLOCKS")) cap = std::max<int64_t>(1, std::strtoll(e, nullptr, 10));
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(n_items, cap));
+    note_launch(SSA_FORM_TWO_WAVE, blocks);
     void *args[] = {&wl};
     return hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, 2 * kWave, 1, 1, (unsigned)dyn_lds, st, args, nullptr);
 }
 
-hipError_t launch_grid_info(const double *grid, int32_t G, double t_end, GridInfo *out, hipStream_t st) {
-    hipLaunchKernelGGL(grid_info_kernel, dim3(1), dim3(256), 0, st, grid, G, t_end, out);
+// The control block of a single-network run: work counter at byte 0, status words
+// (events, largest step count, flags) at byte 32, the grid description at byte 64.
+constexpr size_t kCtlBytes = 64 + sizeof(GridInfo);
+unsigned long long *ctl_flags(void *ctl) { return (unsigned long long *)((char *)ctl + 48); }
+
+// Describes a device grid and checks it (a grid that is not non-decreasing inside
+// [0, t_end] refuses the run on the device; see grid_info_kernel).  ctl must be zeroed.
+hipError_t launch_grid_info(const double *grid, int32_t G, double t_end, void *ctl, hipStream_t st) {
+    hipLaunchKernelGGL(grid_info_kernel, dim3(1), dim3(256), 0, st, grid, G, t_end, (GridInfo *)((char *)ctl + 64),
+                       (unsigned int *)ctl, ctl_flags(ctl));
     return hipGetLastError();
 }
+
+// Largest trajectory count a single-network call accepts: work items of 64 trajectories
+// (one trajectory each in the 64-chunk order) stay below the refused-run sentinel.
+int64_t max_traj(const ssa_model *m) { return m->order == SSA_SUM_BLOCK64 ? ((int64_t)1 << 30) : ((int64_t)1 << 36); }
 
 // Host twin of grid_info_kernel for host grids.
 GridInfo host_grid_info(const double *grid, int32_t G, double t_end) {
@@ -615,7 +658,12 @@ ssa_status collect_stats(unsigned long long *d_stats, hipStream_t st, hipEvent_t
         float ms = 0.f;
         if (e0 && e1) (void)hipEventElapsedTime(&ms, e0, e1);
         stats->kernel_ms = ms;
+        stats->form = g_launch.form;
+        stats->blocks = g_launch.blocks;
     }
+    if (h[2] & kFlagRefused)
+        return fail(SSA_E_INVALID, "refused on the device: the grid is not non-decreasing inside [0, t_end], or a "
+                                   "log rate is NaN or above 709 (outputs are NaN)");
     if (h[2] & kFlagOverflow) return fail(SSA_E_OVERFLOW, "a species count left the int32 range");
     if (h[2] & kFlagEventLimit) return fail(SSA_E_EVENT_LIMIT, "a trajectory reached max_events before t_end");
     return SSA_OK;
@@ -675,6 +723,7 @@ hipError_t launch_wide(const ssa_model *m, const WorkList &wl, int dev, hipStrea
     if (e != hipSuccess) return e;
     const int64_t n_traj = wl.range_end - wl.range_begin;
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(per_cu, 1) * cu_count(dev), n_traj));
+    note_launch(SSA_FORM_WAVE, blocks);
     void *args[] = {&w};
     return hipLaunchKernel(kern, dim3((unsigned)blocks), dim3(kWave), args, lds, st);
 }
@@ -695,6 +744,7 @@ hipError_t launch_wave(const ssa_model *m, const WorkList &wl, int dev, hipStrea
     const int64_t n_traj = wl.range_end - wl.range_begin;
     const int64_t blocks =
         std::max<int64_t>(1, std::min<int64_t>((int64_t)std::max(per_cu, 1) * cu_count(dev), (n_traj + 3) / 4));
+    note_launch(SSA_FORM_WAVE, blocks);
     WorkList w = wl;
     void *args[] = {&w};
     return hipLaunchKernel(kern, dim3((unsigned)blocks), dim3(kBlock), args, lds, st);
@@ -702,9 +752,10 @@ hipError_t launch_wave(const ssa_model *m, const WorkList &wl, int dev, hipStrea
 
 // Finalize of one network: exact prefix over the grid and the moments.
 hipError_t launch_finalize(const unsigned long long *D, const unsigned long long *Dhi, int32_t G, int32_t S,
-                           const int32_t *d_x0, int64_t n_traj, double *mean, double *var, hipStream_t st) {
+                           const int32_t *d_x0, int64_t n_traj, double *mean, double *var,
+                           const unsigned long long *flags, hipStream_t st) {
     hipLaunchKernelGGL(moment_final_kernel, dim3(S), dim3(1024), 0, st, D, Dhi, G, S, d_x0, n_traj, mean, var,
-                       (int64_t *)nullptr);
+                       (int64_t *)nullptr, flags);
     return hipGetLastError();
 }
 
@@ -725,17 +776,26 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
         const bool lat = latency_bound(n_items, dev);
         ssa_status s = get_jit(m, dev, k, lat);
         if (s) return s;
-        // latency-bound backward: generations with a drawing wave beside each simulating one
-        if ((mode == kBwd || mode == kEvt) && pc_launch(n_items, dev)) {
+        // backward: two-wave blocks for launches of up to two work items per CU,
+        // generations up to eight, lanes refilled beyond; the event log: two-wave blocks or
+        // refill; the record always refills
+        uint32_t form = SSA_FORM_REFILL;
+        if (mode == kBwd) form = pc_launch(n_items, dev) ? SSA_FORM_TWO_WAVE : lat ? SSA_FORM_GENERATIONS : form;
+        if (mode == kEvt && pc_launch(n_items, dev)) form = SSA_FORM_TWO_WAVE;
+        const uint32_t forced = forced_form();
+        if (forced != SSA_FORM_NONE && mode != kRec && !(mode == kEvt && forced == SSA_FORM_GENERATIONS))
+            form = forced;
+        if (form == SSA_FORM_TWO_WAVE) {
             HIP_TRY(launch_jit_pc(mode == kEvt ? k->evt_pc : (quad ? k->bwd_var_pc : k->bwd_pc), wl, n_items, dev,
                                   st));
             return SSA_OK;
         }
+        const bool gen = form == SSA_FORM_GENERATIONS;
         hipFunction_t f = mode == kRec   ? k->rec
                           : mode == kEvt ? k->evt
-                          : quad         ? (lat ? k->bwd_var_gen : k->bwd_var)
-                                         : (lat ? k->bwd_gen : k->bwd);
-        HIP_TRY(launch_jit(f, wl, n_items, dev, st));
+                          : quad         ? (gen ? k->bwd_var_gen : k->bwd_var)
+                                         : (gen ? k->bwd_gen : k->bwd);
+        HIP_TRY(launch_jit(f, wl, n_items, dev, st, form));
         return SSA_OK;
     }
     const int mm = generic_mm(m->M);
@@ -876,7 +936,10 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
         k.f_slab = hist ? jk->fwd_slab_hist : jk->fwd;
         k.f_atomic = hist ? jk->fwd_hist : jk->fwd_atomic;
         k.lds = win_bytes;
-        if (pc_launch(n_items, dev)) {
+        const uint32_t forced = forced_form();
+        const bool two_wave = forced == SSA_FORM_TWO_WAVE ||
+                              (forced != SSA_FORM_GENERATIONS && forced != SSA_FORM_REFILL && pc_launch(n_items, dev));
+        if (two_wave) {
             // one simulating wave per block: one window, flushed atomically into D
             HIP_TRY(launch_zero(D, (size_t)G * S * 2 * sizeof(unsigned long long), st));
             EventPair ev;
@@ -1111,12 +1174,28 @@ void ssa_model_destroy(ssa_model *m) {
 
 namespace {
 
+// Rate constants of a run: the caller's rates, or c = e^theta of the caller's log rates
+// formed on the device (zero-padded to the model's table width; an invalid theta refuses the
+// run), or NULL for the model's own.  ctl must be zeroed.
+ssa_status run_rates(const ssa_model *m, const double *rates, const double *log_rates, void *ctl,
+                     StreamScratch &scr, hipStream_t st, const double **out) {
+    *out = rates;
+    if (!log_rates) return SSA_OK;
+    void *p = nullptr;
+    HIP_TRY(scr.alloc(&p, sizeof(double) * (size_t)m->m_pad));
+    hipLaunchKernelGGL(rates_from_log_kernel, dim3((unsigned)((m->m_pad + 255) / 256)), dim3(256), 0, st, log_rates,
+                       m->M, m->m_pad, (double *)p, (unsigned int *)ctl, ctl_flags(ctl));
+    HIP_TRY(hipGetLastError());
+    *out = (const double *)p;
+    return SSA_OK;
+}
+
 // The forward pass with a given launch configuration (tune == nullptr: the cached tuned
 // one, else the defaults).
-ssa_status run_device_impl(const ssa_model *m, const double *rates, int64_t n_traj, double t_end, const double *grid,
-                           int32_t G, uint64_t seed, uint64_t max_events, double *mean, double *var,
-                           const ssa_hist_spec *hist, uint32_t *d_hist, void *stream, ssa_stats *stats,
-                           const FwdTune *tune) {
+ssa_status run_device_impl(const ssa_model *m, const double *rates, const double *log_rates, int64_t n_traj,
+                           double t_end, const double *grid, int32_t G, uint64_t seed, uint64_t max_events,
+                           double *mean, double *var, const ssa_hist_spec *hist, uint32_t *d_hist, void *stream,
+                           ssa_stats *stats, const FwdTune *tune) {
     if (!m) return fail(SSA_E_INVALID, "model is NULL");
     if (n_traj <= 0) return fail(SSA_E_INVALID, "n_traj must be > 0");
     if (G <= 0 || !grid || !mean || !var) return fail(SSA_E_INVALID, "grid / mean / var missing");
@@ -1125,26 +1204,29 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, int64_t n_tr
     if (hist && (hist->species < 0 || hist->species >= m->S || hist->width <= 0 || hist->nbins <= 0 ||
                  hist->nbins > 4096))
         return fail(SSA_E_INVALID, "bad histogram spec");
-    if (n_traj > ((int64_t)1 << 31) * kChunk) return fail(SSA_E_INVALID, "n_traj too large");
+    if (rates && log_rates) return fail(SSA_E_INVALID, "rates and log_rates are alternatives");
+    if (n_traj > max_traj(m)) return fail(SSA_E_INVALID, "n_traj above %lld", (long long)max_traj(m));
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     keep_pool(dev);
     StreamScratch scr(st);
 
-    NetDev n = base_net(m, rates, n_traj, t_end, grid, G, seed, max_events);
     const size_t cells = (size_t)G * m->S;
     const size_t H_bytes = hist ? sizeof(int32_t) * (size_t)G * hist->nbins : 0;
     void *D = nullptr, *Dhi = nullptr, *Hd = nullptr, *ctl = nullptr;
     HIP_TRY(scr.alloc(&D, sizeof(unsigned long long) * 2 * cells));
     HIP_TRY(scr.alloc(&Dhi, sizeof(unsigned long long) * cells));
-    HIP_TRY(scr.alloc(&ctl, 64 + sizeof(GridInfo)));
+    HIP_TRY(scr.alloc(&ctl, kCtlBytes));
     if (hist) HIP_TRY(scr.alloc(&Hd, H_bytes));
     HIP_TRY(launch_zero(Dhi, sizeof(unsigned long long) * cells, st));
     HIP_TRY(launch_zero(ctl, 64, st));
     if (hist) HIP_TRY(launch_zero(Hd, H_bytes, st));
+    ssa_status s = run_rates(m, rates, log_rates, ctl, scr, st, &rates);
+    if (s) return s;
+    NetDev n = base_net(m, rates, n_traj, t_end, grid, G, seed, max_events);
     n.ginfo = (const GridInfo *)((char *)ctl + 64);
-    HIP_TRY(launch_grid_info(grid, G, t_end, (GridInfo *)n.ginfo, st));
+    HIP_TRY(launch_grid_info(grid, G, t_end, ctl, st));
     n.D = (unsigned long long *)D;
     n.Dhi = (unsigned long long *)Dhi;
     if (hist) {
@@ -1166,14 +1248,14 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, int64_t n_tr
 
     float kms = 0.f;
     const FwdTune cfg = tune ? *tune : tune_lookup(m, n_traj, G, dev);
-    ssa_status s = launch_forward(m, wl, n_items, dev, st, rates, scr, n.D, stats ? &kms : nullptr, cfg);
+    s = launch_forward(m, wl, n_items, dev, st, rates, scr, n.D, stats ? &kms : nullptr, cfg);
     if (s) return s;
-    HIP_TRY(launch_finalize(n.D, n.Dhi, G, m->S, m->d_x0, n_traj, mean, var, st));
+    HIP_TRY(launch_finalize(n.D, n.Dhi, G, m->S, m->d_x0, n_traj, mean, var, ctl_flags(ctl), st));
     if (hist) {
         const int32_t xv = m->x0[hist->species];
         const int32_t ib = xv < hist->lo ? 0 : std::min((xv - hist->lo) / hist->width, hist->nbins - 1);
         hipLaunchKernelGGL(hist_prefix_kernel, dim3(hist->nbins), dim3(1024), 0, st, (const int32_t *)Hd, G,
-                           hist->nbins, ib, n_traj, d_hist);
+                           hist->nbins, ib, n_traj, d_hist, (const unsigned long long *)ctl_flags(ctl));
         HIP_TRY(hipGetLastError());
     }
     if (stats) {
@@ -1186,11 +1268,12 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, int64_t n_tr
 
 }  // namespace
 
-ssa_status ssa_run_device(const ssa_model *m, const double *rates, int64_t n_traj, double t_end, const double *grid,
-                          int32_t G, uint64_t seed, uint64_t max_events, double *mean, double *var,
-                          const ssa_hist_spec *hist, uint32_t *d_hist, void *stream, ssa_stats *stats) {
-    return run_device_impl(m, rates, n_traj, t_end, grid, G, seed, max_events, mean, var, hist, d_hist, stream, stats,
-                           nullptr);
+ssa_status ssa_run_device(const ssa_model *m, const double *rates, const double *log_rates, int64_t n_traj,
+                          double t_end, const double *grid, int32_t G, uint64_t seed, uint64_t max_events,
+                          double *mean, double *var, const ssa_hist_spec *hist, uint32_t *d_hist, void *stream,
+                          ssa_stats *stats) {
+    return run_device_impl(m, rates, log_rates, n_traj, t_end, grid, G, seed, max_events, mean, var, hist, d_hist,
+                           stream, stats, nullptr);
 }
 
 ssa_status ssa_autotune_forward(const ssa_model *m, const double *rates, int64_t n_traj, double t_end,
@@ -1222,7 +1305,7 @@ ssa_status ssa_autotune_forward(const ssa_model *m, const double *rates, int64_t
         float ms = 0.f;
         for (int rep = 0; rep < 2 && status == SSA_OK; ++rep) {     // the first run warms up
             ssa_stats stt;
-            status = run_device_impl(m, rates, n_traj, t_end, grid, G, seed, 0, mean, var, nullptr, nullptr, stream,
+            status = run_device_impl(m, rates, nullptr, n_traj, t_end, grid, G, seed, 0, mean, var, nullptr, nullptr, stream,
                                      &stt, &cand[c]);
             ms = rep ? std::min(ms, stt.kernel_ms) : stt.kernel_ms;
         }
@@ -1252,14 +1335,15 @@ ssa_status ssa_autotune_forward(const ssa_model *m, const double *rates, int64_t
     return SSA_OK;
 }
 
-ssa_status ssa_run_jacobian_device(const ssa_model *m, const double *rates, int64_t n_traj, double t_end,
-                                   const double *grid, int32_t G, uint64_t seed, uint64_t max_events, double *mean,
-                                   double *var, double *jac, void *stream, ssa_stats *stats) {
+ssa_status ssa_run_jacobian_device(const ssa_model *m, const double *rates, const double *log_rates, int64_t n_traj,
+                                   double t_end, const double *grid, int32_t G, uint64_t seed, uint64_t max_events,
+                                   double *mean, double *var, double *jac, void *stream, ssa_stats *stats) {
     if (!m) return fail(SSA_E_INVALID, "model is NULL");
     if (n_traj <= 0) return fail(SSA_E_INVALID, "n_traj must be > 0");
     if (G <= 0 || !grid || !mean || !var || !jac) return fail(SSA_E_INVALID, "grid / mean / var / jac missing");
     if (!(t_end >= 0.0) || !std::isfinite(t_end)) return fail(SSA_E_INVALID, "t_end must be finite and >= 0");
-    if (n_traj > ((int64_t)1 << 31) * kChunk) return fail(SSA_E_INVALID, "n_traj too large");
+    if (rates && log_rates) return fail(SSA_E_INVALID, "rates and log_rates are alternatives");
+    if (n_traj > max_traj(m)) return fail(SSA_E_INVALID, "n_traj above %lld", (long long)max_traj(m));
     if (m->order != SSA_SUM_SEQ || m->M > kJitMaxReactions || m->S > kJitMaxSpecies)
         return fail(SSA_E_UNSUPPORTED, "the forward Jacobian needs a sequential-order network with at most %d "
                     "reactions and %d species", kJitMaxReactions, kJitMaxSpecies);
@@ -1281,18 +1365,20 @@ ssa_status ssa_run_jacobian_device(const ssa_model *m, const double *rates, int6
     ssa_status s = get_jit(m, dev, jk);
     if (s) return s;
 
-    NetDev n = base_net(m, rates, n_traj, t_end, grid, G, seed, max_events);
     const size_t cells = (size_t)G * m->S;
     void *D = nullptr, *Dhi = nullptr, *ctl = nullptr, *slabs = nullptr;
     HIP_TRY(scr.alloc(&D, sizeof(unsigned long long) * 2 * cells));
     HIP_TRY(scr.alloc(&Dhi, sizeof(unsigned long long) * cells));
-    HIP_TRY(scr.alloc(&ctl, 64 + sizeof(GridInfo)));
+    HIP_TRY(scr.alloc(&ctl, kCtlBytes));
     HIP_TRY(scr.alloc(&slabs, slab_bytes));
     HIP_TRY(launch_zero(D, sizeof(unsigned long long) * 2 * cells, st));
     HIP_TRY(launch_zero(Dhi, sizeof(unsigned long long) * cells, st));
     HIP_TRY(launch_zero(ctl, 64, st));
+    s = run_rates(m, rates, log_rates, ctl, scr, st, &rates);
+    if (s) return s;
+    NetDev n = base_net(m, rates, n_traj, t_end, grid, G, seed, max_events);
     n.ginfo = (const GridInfo *)((char *)ctl + 64);
-    HIP_TRY(launch_grid_info(grid, G, t_end, (GridInfo *)n.ginfo, st));
+    HIP_TRY(launch_grid_info(grid, G, t_end, ctl, st));
     n.D = (unsigned long long *)D;
     n.Dhi = (unsigned long long *)Dhi;
     WorkList wl;
@@ -1318,15 +1404,17 @@ ssa_status ssa_run_jacobian_device(const ssa_model *m, const double *rates, int6
     if (stats && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
     {
         void *args[] = {&wl};
+        note_launch(SSA_FORM_GENERATIONS, blocks);
         HIP_TRY(hipModuleLaunchKernel(jk->fwd_jac, (unsigned)blocks, 1, 1, kBlock, 1, 1, (unsigned)lds, st, args,
                                       nullptr));
     }
     if (stats && ev.b) HIP_TRY(hipEventRecord(ev.b, st));
-    HIP_TRY(launch_finalize(n.D, n.Dhi, G, m->S, m->d_x0, n_traj, mean, var, st));
+    HIP_TRY(launch_finalize(n.D, n.Dhi, G, m->S, m->d_x0, n_traj, mean, var, ctl_flags(ctl), st));
     {
         const int64_t jc = (int64_t)cells * m->M;
         hipLaunchKernelGGL(jacobian_final_kernel, dim3((unsigned)((jc + 255) / 256)), dim3(256), 0, st,
-                           (const double *)slabs, n_items, G, m->S, m->M, n_traj, (const double *)mean, jac);
+                           (const double *)slabs, n_items, G, m->S, m->M, n_traj, (const double *)mean, jac,
+                           (const unsigned long long *)ctl_flags(ctl));
         HIP_TRY(hipGetLastError());
     }
     if (stats) return collect_stats(wl.stats, st, ev.a, ev.b, stats);
@@ -1340,7 +1428,7 @@ ssa_status ssa_run_cov_device(const ssa_model *m, const double *rates, int64_t n
     if (n_traj <= 0) return fail(SSA_E_INVALID, "n_traj must be > 0");
     if (G <= 0 || !grid || !mean || !cov) return fail(SSA_E_INVALID, "grid / mean / cov missing");
     if (!(t_end >= 0.0) || !std::isfinite(t_end)) return fail(SSA_E_INVALID, "t_end must be finite and >= 0");
-    if (n_traj > ((int64_t)1 << 31) * kChunk) return fail(SSA_E_INVALID, "n_traj too large");
+    if (n_traj > max_traj(m)) return fail(SSA_E_INVALID, "n_traj above %lld", (long long)max_traj(m));
     if (m->order != SSA_SUM_SEQ || m->M > kJitMaxReactions || m->S > kJitMaxSpecies)
         return fail(SSA_E_UNSUPPORTED, "the covariance pass needs a sequential-order network with at most %d "
                     "reactions and %d species", kJitMaxReactions, kJitMaxSpecies);
@@ -1358,14 +1446,14 @@ ssa_status ssa_run_cov_device(const ssa_model *m, const double *rates, int64_t n
     void *D = nullptr, *Dhi = nullptr, *ctl = nullptr, *sx = nullptr, *sxx = nullptr;
     HIP_TRY(scr.alloc(&D, sizeof(unsigned long long) * row * G));
     HIP_TRY(scr.alloc(&Dhi, sizeof(unsigned long long) * hrow * G));
-    HIP_TRY(scr.alloc(&ctl, 64 + sizeof(GridInfo)));
+    HIP_TRY(scr.alloc(&ctl, kCtlBytes));
     HIP_TRY(scr.alloc(&sx, sizeof(int64_t) * (size_t)G * S));
     HIP_TRY(scr.alloc(&sxx, sizeof(i128s) * hrow * G));
     HIP_TRY(launch_zero(D, sizeof(unsigned long long) * row * G, st));
     HIP_TRY(launch_zero(Dhi, sizeof(unsigned long long) * hrow * G, st));
     HIP_TRY(launch_zero(ctl, 64, st));
     n.ginfo = (const GridInfo *)((char *)ctl + 64);
-    HIP_TRY(launch_grid_info(grid, G, t_end, (GridInfo *)n.ginfo, st));
+    HIP_TRY(launch_grid_info(grid, G, t_end, ctl, st));
     n.D = (unsigned long long *)D;
     n.Dhi = (unsigned long long *)Dhi;
     WorkList wl;
@@ -1389,6 +1477,7 @@ ssa_status ssa_run_cov_device(const ssa_model *m, const double *rates, int64_t n
     if (stats && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
     {
         void *args[] = {&wl};
+        note_launch(SSA_FORM_GENERATIONS, blocks);
         HIP_TRY(hipModuleLaunchKernel(jk->fwd_cov, (unsigned)blocks, 1, 1, kBlock, 1, 1, (unsigned)lds, st, args,
                                       nullptr));
     }
@@ -1398,7 +1487,8 @@ ssa_status ssa_run_cov_device(const ssa_model *m, const double *rates, int64_t n
     HIP_TRY(hipGetLastError());
     const int64_t cells = (int64_t)G * S * S;
     hipLaunchKernelGGL(cov_final_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st,
-                       (const int64_t *)sx, (const i128s *)sxx, G, S, n_traj, mean, cov);
+                       (const int64_t *)sx, (const i128s *)sxx, G, S, n_traj, mean, cov,
+                       (const unsigned long long *)ctl_flags(ctl));
     HIP_TRY(hipGetLastError());
     if (stats) return collect_stats(wl.stats, st, ev.a, ev.b, stats);
     return SSA_OK;
@@ -1424,6 +1514,14 @@ ssa_status ssa_jacobian_vjp(const double *jac, const double *w, int32_t G, int32
     return SSA_OK;
 }
 
+ssa_status ssa_rates_from_log(const double *log_rates, int32_t n, double *rates, void *stream) {
+    if (!log_rates || !rates || n <= 0) return fail(SSA_E_INVALID, "bad argument");
+    hipLaunchKernelGGL(rates_from_log_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       log_rates, n, n, rates, (unsigned int *)nullptr, (unsigned long long *)nullptr);
+    HIP_TRY(hipGetLastError());
+    return SSA_OK;
+}
+
 ssa_status ssa_run(const ssa_model *m, int64_t n_traj, double t_end, const double *grid, int32_t G, uint64_t seed,
                    double *mean, double *var, ssa_stats *stats) {
     if (!m || !mean || !var) return fail(SSA_E_INVALID, "NULL argument");
@@ -1445,7 +1543,7 @@ ssa_status ssa_run(const ssa_model *m, int64_t n_traj, double t_end, const doubl
         return fail(e == hipErrorOutOfMemory ? SSA_E_NOMEM : SSA_E_DEVICE, "%s", hipGetErrorString(e));
     }
     ssa_stats local;
-    s = ssa_run_device(m, nullptr, n_traj, t_end, dg, G, seed, 0, dm, dv, nullptr, nullptr, nullptr,
+    s = ssa_run_device(m, nullptr, nullptr, n_traj, t_end, dg, G, seed, 0, dm, dv, nullptr, nullptr, nullptr,
                        stats ? stats : &local);
     if (s == SSA_OK) {
         e = hipMemcpy(mean, dm, sizeof(double) * cells, hipMemcpyDeviceToHost);
@@ -1456,17 +1554,17 @@ ssa_status ssa_run(const ssa_model *m, int64_t n_traj, double t_end, const doubl
     return s;
 }
 
-ssa_status ssa_backward_device(const ssa_model *m, const double *rates, int64_t n_traj, double t_end,
-                               const double *grid, int32_t G, uint64_t seed, uint64_t max_events, const double *w,
-                               const double *mhat, double *grad, void *stream, ssa_stats *stats) {
-    return ssa_backward_moments_device(m, rates, n_traj, t_end, grid, G, seed, max_events, w, mhat, nullptr, nullptr,
-                                       grad, stream, stats);
+ssa_status ssa_backward_device(const ssa_model *m, const double *rates, const double *log_rates, int64_t n_traj,
+                               double t_end, const double *grid, int32_t G, uint64_t seed, uint64_t max_events,
+                               const double *w, const double *mhat, double *grad, void *stream, ssa_stats *stats) {
+    return ssa_backward_moments_device(m, rates, log_rates, n_traj, t_end, grid, G, seed, max_events, w, mhat, nullptr,
+                                       nullptr, grad, stream, stats);
 }
 
-ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, int64_t n_traj, double t_end,
-                                       const double *grid, int32_t G, uint64_t seed, uint64_t max_events,
-                                       const double *w, const double *mhat, const double *wv, const double *vhat,
-                                       double *grad, void *stream, ssa_stats *stats) {
+ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, const double *log_rates,
+                                       int64_t n_traj, double t_end, const double *grid, int32_t G, uint64_t seed,
+                                       uint64_t max_events, const double *w, const double *mhat, const double *wv,
+                                       const double *vhat, double *grad, void *stream, ssa_stats *stats) {
     if (!m) return fail(SSA_E_INVALID, "model is NULL");
     if (n_traj <= 0 || G <= 0 || !grid || !w || !mhat || !grad) return fail(SSA_E_INVALID, "bad argument");
     if ((wv == nullptr) != (vhat == nullptr)) return fail(SSA_E_INVALID, "wv and vhat go together");
@@ -1475,13 +1573,13 @@ ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, 
     if (m->order == SSA_SUM_SEQ && m->M > kJitMaxReactions)
         return fail(SSA_E_UNSUPPORTED, "backward supports at most %d reactions", kJitMaxReactions);
     if (m->has_laws) return fail(SSA_E_UNSUPPORTED, "the score of a rate law is not n_j - A_j: no backward");
-    if (n_traj > ((int64_t)1 << 31) * kChunk) return fail(SSA_E_INVALID, "n_traj too large");
+    if (rates && log_rates) return fail(SSA_E_INVALID, "rates and log_rates are alternatives");
+    if (n_traj > max_traj(m)) return fail(SSA_E_INVALID, "n_traj above %lld", (long long)max_traj(m));
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
     keep_pool(dev);
     StreamScratch scr(st);
-    NetDev n = base_net(m, rates, n_traj, t_end, grid, G, seed, max_events);
     void *gt = nullptr, *gt2 = nullptr, *ctl = nullptr, *bp = nullptr;
     const size_t rows_bytes = sizeof(double) * (size_t)n_traj * m->M;
     const int32_t ncol = quad ? 4 * m->S + 2 : 2 * m->S + 2;
@@ -1490,10 +1588,13 @@ ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, 
     HIP_TRY(scr.alloc(&bpt, sizeof(double) * ncol * (size_t)G));
     HIP_TRY(scr.alloc(&gt, rows_bytes));
     HIP_TRY(scr.alloc(&gt2, rows_bytes / 2 + sizeof(double) * m->M));
-    HIP_TRY(scr.alloc(&ctl, 64 + sizeof(GridInfo)));
+    HIP_TRY(scr.alloc(&ctl, kCtlBytes));
     HIP_TRY(launch_zero(ctl, 64, st));
+    ssa_status s = run_rates(m, rates, log_rates, ctl, scr, st, &rates);
+    if (s) return s;
+    NetDev n = base_net(m, rates, n_traj, t_end, grid, G, seed, max_events);
     n.ginfo = (const GridInfo *)((char *)ctl + 64);
-    HIP_TRY(launch_grid_info(grid, G, t_end, (GridInfo *)n.ginfo, st));
+    HIP_TRY(launch_grid_info(grid, G, t_end, ctl, st));
     hipLaunchKernelGGL(bwd_prefix_kernel, dim3((unsigned)ncol), dim3(256), 0, st, w, mhat, wv, vhat, grid, G, m->S,
                        bp, (double *)bpt);
     HIP_TRY(hipGetLastError());
@@ -1512,7 +1613,7 @@ ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, 
     wl.stats = (unsigned long long *)((char *)ctl + 32);
     EventPair ev;
     if (stats && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
-    ssa_status s = launch_single(kBwd, m, wl, n_items, dev, st, rates, scr, quad);
+    s = launch_single(kBwd, m, wl, n_items, dev, st, rates, scr, quad);
     if (s) return s;
     if (stats && ev.b) HIP_TRY(hipEventRecord(ev.b, st));
     // fixed-order pairwise reduction of the per-trajectory rows
@@ -1529,7 +1630,7 @@ ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, 
         rows = tiles;
     }
     hipLaunchKernelGGL(scale_kernel, dim3((unsigned)((m->M + 255) / 256)), dim3(256), 0, st, src, m->M,
-                       1.0 / (double)n_traj, grad);
+                       1.0 / (double)n_traj, grad, (const unsigned long long *)ctl_flags(ctl));
     HIP_TRY(hipGetLastError());
     if (stats) return collect_stats(wl.stats, st, ev.a, ev.b, stats);
     return SSA_OK;
@@ -1896,6 +1997,8 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
         stats->max_steps = epochs ? max_steps : h0[1];
         stats->flags = epochs ? all_flags : (uint32_t)h0[2];
         stats->kernel_ms = 0.0f;
+        stats->form = g_launch.form;
+        stats->blocks = g_launch.blocks;
         if (timed) (void)hipEventElapsedTime(&stats->kernel_ms, evp.a, evp.b);
     }
     if (sizing) return SSA_OK;
@@ -2041,6 +2144,7 @@ ssa_status batch_enqueue(ssa_batch *bt, hipStream_t st) {
     int64_t blocks = 0;
     HIP_TRY(fwd_blocks(k, false, bt->device, bt->n_items, blocks));
     HIP_TRY(fwd_launch(k, false, blocks, wl, st));
+    bt->launch = g_launch;
     hipLaunchKernelGGL(moment_final_batched_kernel, dim3((unsigned)bt->n_fin_blocks), dim3(1024), 0, st,
                        (const FinalNet *)bt->d_fin, (const int32_t *)bt->d_block_net,
                        (const int32_t *)bt->d_block_species);
@@ -2097,6 +2201,7 @@ ssa_status ssa_batch_run(ssa_batch *bt, double *const *means, double *const *var
         if (s) return s;
     }
     if (stats && ev.b) HIP_TRY(hipEventRecord(ev.b, st));
+    g_launch = bt->launch;     // a graph replay launches nothing through the host helpers
     if (stats) return collect_stats(bt->d_stats, st, ev.a, ev.b, stats);
     return SSA_OK;
 }

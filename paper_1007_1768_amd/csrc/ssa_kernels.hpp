@@ -224,13 +224,34 @@ __global__ void __launch_bounds__(256) bwd_prefix_kernel(const double *__restric
     }
 }
 
+// A run whose inputs fail the device-side checks (grid or log rates) is refused on the
+// device: the check sets this bit in the run's status word and moves the work counter to
+// kRefusedItem, so every simulation kernel finds no work item and exits through its normal
+// path, and the finalize kernels write NaN (all-ones histogram counts) instead of results.
+// The host reports SSA_E_INVALID when it reads the status word.
+constexpr uint32_t kFlagRefused = 8u;
+constexpr unsigned int kRefusedItem = 0x7f000000u;   // above any work-item count the library accepts
+
+__device__ __forceinline__ bool refused(const unsigned long long *flags) {
+    return flags && (*(const volatile unsigned long long *)flags & kFlagRefused);
+}
+
+__device__ __forceinline__ void refuse(unsigned int *counter, unsigned long long *flags) {
+    atomicOr(flags, (unsigned long long)kFlagRefused);
+    atomicMax(counter, kRefusedItem);
+}
+
 // Grid description of a device grid: uniform if t_g == fl(fl(T g) / D) for all g with
 // D = G - 1 and T either t_end or t_{G-1} (first that fits), else general; plus the affine
-// guess.  One block of 256 threads.
+// guess.  The grid must be non-decreasing inside [0, t_end] (Section 3.2.1's time
+// alignment is on increasing simulation times): any other grid, NaN included, refuses the
+// run (counter and flags: the run's work counter and status word).  One block of 256
+// threads.
 __global__ void __launch_bounds__(256) grid_info_kernel(const double *__restrict__ grid, int32_t G, double t_end,
-                                                        GridInfo *__restrict__ out) {
-    __shared__ int bad[2];
-    if (threadIdx.x < 2) bad[threadIdx.x] = 0;
+                                                        GridInfo *__restrict__ out, unsigned int *__restrict__ counter,
+                                                        unsigned long long *__restrict__ flags) {
+    __shared__ int bad[3];
+    if (threadIdx.x < 3) bad[threadIdx.x] = 0;
     __syncthreads();
     const double D = (double)(G - 1);
     const double Tc[2] = {t_end, grid[G - 1]};
@@ -240,6 +261,12 @@ __global__ void __launch_bounds__(256) grid_info_kernel(const double *__restrict
             if (grid[g] != (Tc[c] * (double)g) / D) mine = 1;
         if (mine) atomicOr(&bad[c], 1);
     }
+    int invalid = 0;
+    for (int32_t g = threadIdx.x; g < G && !invalid; g += blockDim.x) {
+        const double v = grid[g];
+        if (!(v >= 0.0 && v <= t_end) || (g > 0 && !(v >= grid[g - 1]))) invalid = 1;
+    }
+    if (invalid) atomicOr(&bad[2], 1);
     __syncthreads();
     if (threadIdx.x == 0) {
         GridInfo gi;
@@ -250,8 +277,69 @@ __global__ void __launch_bounds__(256) grid_info_kernel(const double *__restrict
         const double span = grid[G - 1] - grid[0];
         gi.scale = (G > 1 && span > 0.0) ? (double)(G - 1) / span : 0.0;
         gi.pad = 0;
+        if (bad[2]) {
+            gi.uniform = 1;            // harmless values; no work item runs
+            gi.T = 0.0;
+            gi.lo = 0.0;
+            gi.scale = 0.0;
+            if (counter && flags) refuse(counter, flags);
+        }
         *out = gi;
     }
+}
+
+// Rate constants from log rate constants (the parameters theta_j = ln c_j of the
+// likelihood-ratio gradient), c = e^theta with fixed roundings so that the CPU oracle can
+// form the same binary64 values:
+//   theta < -708 (also -inf): c = 0;  theta > 709 or NaN: invalid;
+//   otherwise k = rint(fl(theta * INV_LN2)) (ties to even), r = fma(-k, LN2_LO, fma(-k, LN2_HI, theta)),
+//   p = Horner with fma over the Taylor coefficients E_n = fl(1/n!), n = 13 down to 0
+//   (p = E_13, then p = fma(p, r, E_n)), and c = p 2^k (exact: k >= -1021, p > 0.7).
+// |r| <= ln 2 / 2 + 2^-40, so the degree-13 remainder is below 2^-57 of e^r.
+// LN2_HI keeps 32 significant bits (k LN2_HI is exact for |k| < 2^21).
+__device__ __forceinline__ double exp_contract(double theta, bool &invalid) {
+    invalid = false;
+    if (theta < -708.0) return 0.0;
+    if (!(theta <= 709.0)) {
+        invalid = true;
+        return __builtin_nan("");
+    }
+    constexpr double kInvLn2 = 0x1.71547652b82fep0;
+    constexpr double kLn2Hi = 0x1.62e42fee00000p-1;
+    constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
+    const double k = rint(theta * kInvLn2);
+    const double r = fma(-k, kLn2Lo, fma(-k, kLn2Hi, theta));
+    constexpr double E[14] = {1.0,
+                              1.0,
+                              1.0 / 2.0,
+                              1.0 / 6.0,
+                              1.0 / 24.0,
+                              1.0 / 120.0,
+                              1.0 / 720.0,
+                              1.0 / 5040.0,
+                              1.0 / 40320.0,
+                              1.0 / 362880.0,
+                              1.0 / 3628800.0,
+                              1.0 / 39916800.0,
+                              1.0 / 479001600.0,
+                              1.0 / 6227020800.0};
+    double p = E[13];
+#pragma unroll
+    for (int n = 12; n >= 0; --n) p = fma(p, r, E[n]);
+    return ldexp(p, (int)k);
+}
+
+// c[j] = exp_contract(theta[j]) for j < M and 0 for M <= j < m_pad (the table-driven kernels
+// read zero-padded rate tables); an invalid theta refuses the run.
+__global__ void rates_from_log_kernel(const double *__restrict__ theta, int32_t M, int32_t m_pad,
+                                      double *__restrict__ c, unsigned int *__restrict__ counter,
+                                      unsigned long long *__restrict__ flags) {
+    const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= m_pad) return;
+    bool invalid = false;
+    c[j] = j < M ? exp_contract(theta[j], invalid) : 0.0;
+    if (invalid && counter && flags) refuse(counter, flags);
+    if (invalid && flags && !counter) atomicOr(flags, (unsigned long long)kFlagRefused);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -402,7 +490,16 @@ __global__ void __launch_bounds__(1024) moment_final_kernel(const unsigned long 
                                                             const unsigned long long *__restrict__ Dhi, int32_t G,
                                                             int32_t S, const int32_t *__restrict__ x0,
                                                             int64_t n_traj, double *__restrict__ mean,
-                                                            double *__restrict__ var, int64_t *__restrict__ sums) {
+                                                            double *__restrict__ var, int64_t *__restrict__ sums,
+                                                            const unsigned long long *__restrict__ flags) {
+    if (refused(flags)) {
+        const int32_t s = blockIdx.x;
+        for (int32_t g = threadIdx.x; g < G; g += blockDim.x) {
+            mean[(size_t)g * S + s] = __builtin_nan("");
+            var[(size_t)g * S + s] = __builtin_nan("");
+        }
+        return;
+    }
     moment_final_body(D, Dhi, G, S, blockIdx.x, x0, n_traj, mean, var, sums);
 }
 
@@ -616,11 +713,17 @@ __global__ void __launch_bounds__(1024) cov_prefix_kernel(const unsigned long lo
 // Covariance finalize, step 2: one thread per (g, s, r):
 //   cov = fl(N sxx - sx_s sx_r) / (N (N - 1)),  0 when N == 1; mean[g][s] from sx.
 __global__ void cov_final_kernel(const int64_t *__restrict__ sx, const i128s *__restrict__ sxx, int32_t G, int32_t S,
-                                 int64_t n_traj, double *__restrict__ mean, double *__restrict__ cov) {
+                                 int64_t n_traj, double *__restrict__ mean, double *__restrict__ cov,
+                                 const unsigned long long *__restrict__ flags) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)G * S * S) return;
     const int32_t r = (int32_t)(idx % S), s = (int32_t)((idx / S) % S);
     const int64_t g = idx / ((int64_t)S * S);
+    if (refused(flags)) {
+        if (s == r) mean[g * S + s] = __builtin_nan("");
+        cov[idx] = __builtin_nan("");
+        return;
+    }
     const int32_t npairs = S * (S - 1) / 2, hrow = S + npairs;
     int32_t c = s;
     if (s != r) {
@@ -666,9 +769,13 @@ __global__ void __launch_bounds__(1024) moment_final_batched_kernel(const FinalN
 // order.  One thread per (g, s, j).
 __global__ void jacobian_final_kernel(const double *__restrict__ slabs, int64_t n_items, int32_t G, int32_t S,
                                       int32_t M, int64_t n_traj, const double *__restrict__ mean,
-                                      double *__restrict__ jac) {
+                                      double *__restrict__ jac, const unsigned long long *__restrict__ flags) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)G * S * M) return;
+    if (refused(flags)) {
+        jac[idx] = __builtin_nan("");
+        return;
+    }
     const int32_t j = (int32_t)(idx % M);
     const int64_t gs = idx / M;
     const int32_t s = (int32_t)(gs % S);
@@ -704,8 +811,13 @@ __global__ void __launch_bounds__(256) jacobian_vjp_kernel(const double *__restr
 
 // Histogram: inclusive prefix over g of the bin differences plus N in the initial bin.
 __global__ void hist_prefix_kernel(const int32_t *__restrict__ Hd, int32_t G, int32_t nb, int32_t init_bin,
-                                   int64_t n_traj, uint32_t *__restrict__ out) {
+                                   int64_t n_traj, uint32_t *__restrict__ out,
+                                   const unsigned long long *__restrict__ flags) {
     const int32_t bin = blockIdx.x;
+    if (refused(flags)) {
+        for (int32_t g = threadIdx.x; g < G; g += blockDim.x) out[(size_t)g * nb + bin] = 0xffffffffu;
+        return;
+    }
     const int32_t nt = blockDim.x;
     const int32_t per = (G + nt - 1) / nt;
     const int32_t g0 = min(G, (int32_t)threadIdx.x * per), g1 = min(G, g0 + per);
@@ -779,9 +891,10 @@ __global__ void __launch_bounds__(256) pair_sum_kernel(const double *__restrict_
     if (i == 0) out[t * M + j] = v[0];
 }
 
-__global__ void scale_kernel(const double *__restrict__ in, int32_t M, double scale, double *__restrict__ out) {
+__global__ void scale_kernel(const double *__restrict__ in, int32_t M, double scale, double *__restrict__ out,
+                             const unsigned long long *__restrict__ flags) {
     const int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < M) out[j] = in[j] * scale;
+    if (j < M) out[j] = refused(flags) ? __builtin_nan("") : in[j] * scale;
 }
 
 // Zero fill with plain stores (kept out of hipMemsetAsync so the launch sequence can be

@@ -18,7 +18,8 @@ OK, E_INVALID, E_NOMEM, E_DEVICE, E_OVERFLOW, E_EVENT_LIMIT, E_UNSUPPORTED = ran
 _NAMES = {1: "SSA_E_INVALID", 2: "SSA_E_NOMEM", 3: "SSA_E_DEVICE", 4: "SSA_E_OVERFLOW",
           5: "SSA_E_EVENT_LIMIT", 6: "SSA_E_UNSUPPORTED"}
 
-EXPORTS = ["ssa_model_create", "ssa_model_create_laws", "ssa_model_destroy", "ssa_run", "ssa_run_device",
+EXPORTS = ["ssa_model_create", "ssa_model_create_laws", "ssa_model_destroy", "ssa_run", "ssa_rates_from_log",
+           "ssa_run_device",
            "ssa_backward_device", "ssa_backward_moments_device",
            "ssa_run_jacobian_device", "ssa_jacobian_vjp", "ssa_autotune_forward", "ssa_run_cov_device",
            "ssa_hist_quantiles", "ssa_adaptive_device",
@@ -37,13 +38,17 @@ class HistSpec(ctypes.Structure):
                 ("nbins", ctypes.c_int32)]
 
 
+FORMS = {0: "none", 1: "two_wave", 2: "generations", 3: "refill", 4: "table", 5: "wave"}
+
+
 class Stats(ctypes.Structure):
     _fields_ = [("events", ctypes.c_uint64), ("max_steps", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("kernel_ms", ctypes.c_float)]
+                ("kernel_ms", ctypes.c_float), ("form", ctypes.c_uint32), ("blocks", ctypes.c_uint32)]
 
     def as_dict(self):
         return dict(events=int(self.events), max_steps=int(self.max_steps), flags=int(self.flags),
-                    kernel_ms=float(self.kernel_ms))
+                    kernel_ms=float(self.kernel_ms), form=FORMS.get(int(self.form), str(self.form)),
+                    blocks=int(self.blocks))
 
 
 _lib = None
@@ -64,14 +69,15 @@ def load(path=None):
     L.ssa_model_destroy.argtypes = [vp]
     L.ssa_model_destroy.restype = None
     L.ssa_run.argtypes = [vp, i64, dbl, vp, i32, u64, vp, vp, vp]
-    L.ssa_run_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
-    L.ssa_backward_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
-    L.ssa_backward_moments_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp, vp]
+    L.ssa_rates_from_log.argtypes = [vp, i32, vp, vp]
+    L.ssa_run_device.argtypes = [vp, vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
+    L.ssa_backward_device.argtypes = [vp, vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
+    L.ssa_backward_moments_device.argtypes = [vp, vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp, vp]
     L.ssa_autotune_forward.argtypes = [vp, vp, i64, dbl, vp, i32, u64, vp, vp]
     L.ssa_run_cov_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp]
     L.ssa_hist_quantiles.argtypes = [vp, i32, vp, i64, vp, i32, vp, vp]
     L.ssa_adaptive_device.argtypes = [vp, vp, i64, dbl, u64, u64, i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
-    L.ssa_run_jacobian_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
+    L.ssa_run_jacobian_device.argtypes = [vp, vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
     L.ssa_jacobian_vjp.argtypes = [vp, vp, i32, i32, i32, vp, vp]
     L.ssa_record.argtypes = [vp, vp, i64, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
     L.ssa_batch_create.argtypes = [i32, vp, vp, vp, vp, vp, vp, ctypes.POINTER(vp)]
@@ -171,10 +177,19 @@ def run(model, n_traj, t_end, grid, seed):
     return mean, var, st.as_dict()
 
 
+def rates_from_log(log_rates, stream=None, out=None):
+    """c = e^theta on the device with the library's fixed roundings (ssa_rates_from_log)."""
+    import torch
+    theta = log_rates.contiguous()
+    c = torch.empty_like(theta) if out is None else out
+    _check(load().ssa_rates_from_log(_tp(theta), theta.shape[0], _tp(c), _stream(stream)))
+    return c
+
+
 def run_device(model, n_traj, t_end, grid, seed, rates=None, hist=None, max_events=0, stream=None,
-               with_stats=False, out=None):
-    """Device form (ssa_run_device).  grid and rates are float64 CUDA tensors; returns
-    (mean, var, hist or None, stats or None) as tensors on grid's device."""
+               with_stats=False, out=None, log_rates=None):
+    """Device form (ssa_run_device).  grid and rates (or log_rates) are float64 CUDA tensors;
+    returns (mean, var, hist or None, stats or None) as tensors on grid's device."""
     import torch
     G = grid.shape[0]
     if out is None:
@@ -185,15 +200,15 @@ def run_device(model, n_traj, t_end, grid, seed, rates=None, hist=None, max_even
         mean, var, h = out
     spec = HistSpec(*[int(v) for v in hist]) if hist is not None else None
     st = Stats() if with_stats else None
-    _check(load().ssa_run_device(model.handle, _tp(rates), int(n_traj), float(t_end), _tp(grid), G, int(seed),
-                                 int(max_events), _tp(mean), _tp(var),
+    _check(load().ssa_run_device(model.handle, _tp(rates), _tp(log_rates), int(n_traj), float(t_end), _tp(grid), G,
+                                 int(seed), int(max_events), _tp(mean), _tp(var),
                                  ctypes.byref(spec) if spec is not None else None, _tp(h), _stream(stream),
                                  ctypes.byref(st) if st is not None else None))
     return mean, var, h, (st.as_dict() if st is not None else None)
 
 
 def backward_device(model, n_traj, t_end, grid, seed, w, mhat, rates=None, max_events=0, stream=None,
-                    with_stats=False, out=None, wv=None, vhat=None):
+                    with_stats=False, out=None, wv=None, vhat=None, log_rates=None):
     """LR gradient d loss / d log c (ssa_backward_device; with variance weights wv = dL/dvar
     and centring vhat, ssa_backward_moments_device); returns (grad (M,), stats or None)."""
     import torch
@@ -201,13 +216,13 @@ def backward_device(model, n_traj, t_end, grid, seed, w, mhat, rates=None, max_e
     st = Stats() if with_stats else None
     L = load()
     if wv is None:
-        _check(L.ssa_backward_device(model.handle, _tp(rates), int(n_traj), float(t_end), _tp(grid),
+        _check(L.ssa_backward_device(model.handle, _tp(rates), _tp(log_rates), int(n_traj), float(t_end), _tp(grid),
                                      grid.shape[0], int(seed), int(max_events), _tp(w.contiguous()),
                                      _tp(mhat.contiguous()), _tp(grad), _stream(stream),
                                      ctypes.byref(st) if st is not None else None))
     else:
-        _check(L.ssa_backward_moments_device(model.handle, _tp(rates), int(n_traj), float(t_end), _tp(grid),
-                                             grid.shape[0], int(seed), int(max_events), _tp(w.contiguous()),
+        _check(L.ssa_backward_moments_device(model.handle, _tp(rates), _tp(log_rates), int(n_traj), float(t_end),
+                                             _tp(grid), grid.shape[0], int(seed), int(max_events), _tp(w.contiguous()),
                                              _tp(mhat.contiguous()), _tp(wv.contiguous()), _tp(vhat.contiguous()),
                                              _tp(grad), _stream(stream),
                                              ctypes.byref(st) if st is not None else None))
@@ -229,7 +244,7 @@ def autotune_forward(model, n_traj, t_end, grid, seed, rates=None, stream=None):
 
 
 def run_jacobian_device(model, n_traj, t_end, grid, seed, rates=None, max_events=0, stream=None,
-                        with_stats=False, out=None):
+                        with_stats=False, out=None, log_rates=None):
     """Forward pass with the likelihood-ratio Jacobian (ssa_run_jacobian_device); returns
     (mean (G,S), var (G,S), jac (G,S,M), stats or None)."""
     import torch
@@ -241,8 +256,8 @@ def run_jacobian_device(model, n_traj, t_end, grid, seed, rates=None, max_events
     else:
         mean, var, jac = out
     st = Stats() if with_stats else None
-    _check(load().ssa_run_jacobian_device(model.handle, _tp(rates), int(n_traj), float(t_end), _tp(grid), G,
-                                          int(seed), int(max_events), _tp(mean), _tp(var), _tp(jac),
+    _check(load().ssa_run_jacobian_device(model.handle, _tp(rates), _tp(log_rates), int(n_traj), float(t_end),
+                                          _tp(grid), G, int(seed), int(max_events), _tp(mean), _tp(var), _tp(jac),
                                           _stream(stream), ctypes.byref(st) if st is not None else None))
     return mean, var, jac, (st.as_dict() if st is not None else None)
 
@@ -387,21 +402,21 @@ def _make_function():
     class SSAMean(torch.autograd.Function):
         """mean = E[X(t_g)] over n_traj trajectories, differentiable in log rate constants.
 
-        mode "resim": forward ssa_run_device with rates = exp(log_rates); backward the
-        likelihood-ratio kernel (ssa_backward_device) re-simulates the same trajectories,
-        centred on the forward mean.  mode "jacobian": the forward pass also forms the
+        mode "resim": forward ssa_run_device on the log rates (the library forms the rate
+        constants on the device); backward the likelihood-ratio kernel (ssa_backward_device)
+        re-simulates the same trajectories, centred on the forward mean.  mode "jacobian": the forward pass also forms the
         likelihood-ratio Jacobian (ssa_run_jacobian_device) and the backward is its
         vector-Jacobian product (ssa_jacobian_vjp): one simulation pass in all."""
 
         @staticmethod
         def forward(ctx, log_rates, model, n_traj, t_end, grid, seed, mode):
-            rates = torch.exp(log_rates.detach()).contiguous()
+            theta = log_rates.detach().contiguous()
             if mode == "jacobian":
-                mean, _, jac, _ = run_jacobian_device(model, n_traj, t_end, grid, seed, rates=rates)
+                mean, _, jac, _ = run_jacobian_device(model, n_traj, t_end, grid, seed, log_rates=theta)
                 ctx.save_for_backward(jac)
             else:
-                mean, _, _, _ = run_device(model, n_traj, t_end, grid, seed, rates=rates)
-                ctx.save_for_backward(rates, mean)
+                mean, _, _, _ = run_device(model, n_traj, t_end, grid, seed, log_rates=theta)
+                ctx.save_for_backward(theta, mean)
             ctx.cfg = (model, n_traj, t_end, grid, seed, mode)
             return mean
 
@@ -412,34 +427,34 @@ def _make_function():
                 (jac,) = ctx.saved_tensors
                 g = jacobian_vjp(jac, grad_mean.contiguous())
             else:
-                rates, mean = ctx.saved_tensors
-                g, _ = backward_device(model, n_traj, t_end, grid, seed, grad_mean.contiguous(), mean, rates=rates)
+                theta, mean = ctx.saved_tensors
+                g, _ = backward_device(model, n_traj, t_end, grid, seed, grad_mean.contiguous(), mean, log_rates=theta)
             return g, None, None, None, None, None, None
 
     class SSAMoments(torch.autograd.Function):
         """(mean, var) = E[X(t_g)], Var[X(t_g)] over n_traj trajectories, differentiable in log
-        rate constants.  Forward ssa_run_device with rates = exp(log_rates); backward one
+        rate constants.  Forward ssa_run_device on the log rates; backward one
         re-simulation (ssa_backward_moments_device) with both weight tensors, centred on the
         forward mean and variance."""
 
         @staticmethod
         def forward(ctx, log_rates, model, n_traj, t_end, grid, seed):
-            rates = torch.exp(log_rates.detach()).contiguous()
-            mean, var, _, _ = run_device(model, n_traj, t_end, grid, seed, rates=rates)
-            ctx.save_for_backward(rates, mean, var)
+            theta = log_rates.detach().contiguous()
+            mean, var, _, _ = run_device(model, n_traj, t_end, grid, seed, log_rates=theta)
+            ctx.save_for_backward(theta, mean, var)
             ctx.cfg = (model, n_traj, t_end, grid, seed)
             return mean, var
 
         @staticmethod
         def backward(ctx, grad_mean, grad_var):
             model, n_traj, t_end, grid, seed = ctx.cfg
-            rates, mean, var = ctx.saved_tensors
+            theta, mean, var = ctx.saved_tensors
             if grad_mean is None:
                 grad_mean = torch.zeros_like(mean)
             if grad_var is None:
-                g, _ = backward_device(model, n_traj, t_end, grid, seed, grad_mean.contiguous(), mean, rates=rates)
+                g, _ = backward_device(model, n_traj, t_end, grid, seed, grad_mean.contiguous(), mean, log_rates=theta)
             else:
-                g, _ = backward_device(model, n_traj, t_end, grid, seed, grad_mean.contiguous(), mean, rates=rates,
+                g, _ = backward_device(model, n_traj, t_end, grid, seed, grad_mean.contiguous(), mean, log_rates=theta,
                                        wv=grad_var.contiguous(), vhat=var)
             return g, None, None, None, None, None
 

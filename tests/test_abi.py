@@ -67,8 +67,11 @@ def test_null_arguments_rejected(lib):
     g = np.array([0.0, 1.0])
     mean = np.zeros(2)
     assert lib.ssa_run(None, 10, 1.0, g.ctypes.data, 2, 1, mean.ctypes.data, mean.ctypes.data, None) == ssa.E_INVALID
-    assert lib.ssa_run_device(None, None, 10, 1.0, None, 2, 1, 0, None, None, None, None, None, None) == ssa.E_INVALID
-    assert lib.ssa_backward_device(None, None, 10, 1.0, None, 2, 1, 0, None, None, None, None, None) == ssa.E_INVALID
+    assert lib.ssa_run_device(None, None, None, 10, 1.0, None, 2, 1, 0, None, None, None, None, None,
+                              None) == ssa.E_INVALID
+    assert lib.ssa_backward_device(None, None, None, 10, 1.0, None, 2, 1, 0, None, None, None, None,
+                                   None) == ssa.E_INVALID
+    assert lib.ssa_rates_from_log(None, 3, None, None) == ssa.E_INVALID
     assert lib.ssa_record(None, None, 0, 1, 1.0, None, 1, 1, 0, None, None, None, None, None, None) == ssa.E_INVALID
     out = ctypes.c_void_p()
     assert lib.ssa_batch_create(0, None, None, None, None, None, None, ctypes.byref(out)) == ssa.E_INVALID

@@ -56,14 +56,19 @@ def test_differentiated_workload_full_gradient(ssa):
     grid = inputs.uniform_grid(t_end, G)
     model = ssa.Model.from_dict(m)
     gd = torch.tensor(grid, device=DEV)
-    prates = torch.tensor(inputs.perturbed_rates(m, w["perturb_seed"]), device=DEV)
-    target, _, _, _ = ssa.run_device(model, N, t_end, gd, w["target_seed"], rates=prates)
-    mean, _, _, _ = ssa.run_device(model, N, t_end, gd, seed)
-    wts = 2.0 * (mean - target)
-    grad, st = ssa.backward_device(model, N, t_end, gd, seed, wts, mean, with_stats=True)
+    # the loss target and the centring mean come from the oracle, so no input of the
+    # comparison is a GPU result
+    s, tgt = orc.run(m, N, t_end, grid, w["target_seed"], rates=inputs.perturbed_rates(m, w["perturb_seed"]))
+    assert s == 0
+    s, ref = orc.run(m, N, t_end, grid, seed)
+    assert s == 0
+    wts = 2.0 * (ref["mean"] - tgt["mean"])
+    grad, st = ssa.backward_device(model, N, t_end, gd, seed, torch.tensor(wts, device=DEV),
+                                   torch.tensor(ref["mean"], device=DEV), with_stats=True)
     torch.cuda.synchronize()
     model.close()
-    s, gref, l1 = orc.grad(m, N, t_end, grid, seed, wts.cpu().numpy(), mean.cpu().numpy())
+    assert st["form"] == "generations" and st["events"] == ref["events"], st
+    s, gref, l1 = orc.grad(m, N, t_end, grid, seed, wts, ref["mean"])
     assert s == 0
     g = grad.cpu().numpy()
     assert np.all(np.abs(g - gref) <= 1e-12 * l1), np.max(np.abs(g - gref) / l1)

@@ -65,7 +65,7 @@ def test_autograd_function_matches_direct_call(ssa):
     loss = ((mean - target) ** 2).sum()
     loss.backward()
     w = 2.0 * (mean.detach() - target)
-    direct, _ = ssa.backward_device(model, N, t_end, grid, seed, w, mean.detach(), rates=torch.exp(log_rates.detach()))
+    direct, _ = ssa.backward_device(model, N, t_end, grid, seed, w, mean.detach(), log_rates=log_rates.detach())
     torch.cuda.synchronize()
     assert torch.equal(log_rates.grad, direct)
     model.close()

@@ -97,8 +97,7 @@ def test_moments_autograd(ssa):
     cm = torch.linspace(0.1, 1.0, G * 4, dtype=torch.float64, device=DEV).reshape(G, 4)
     cv = torch.linspace(-0.01, 0.02, G * 4, dtype=torch.float64, device=DEV).reshape(G, 4)
     (mean * cm).sum().add((var * cv).sum()).backward()
-    rates = torch.exp(lr.detach())
-    g, _ = ssa.backward_device(model, N, t_end, grid, seed, cm, mean.detach(), rates=rates, wv=cv,
+    g, _ = ssa.backward_device(model, N, t_end, grid, seed, cm, mean.detach(), log_rates=lr.detach(), wv=cv,
                                vhat=var.detach())
     torch.cuda.synchronize()
     model.close()

@@ -142,3 +142,41 @@ def test_neglog_oracle_matches_mirror_bitwise():
     for _ in range(2000):
         r = (rng.getrandbits(53) + 1) * 2.0**-53
         assert orc.neglog(r) == mirror.neglog(r)
+
+
+def test_exp_rates_accuracy_against_mpmath():
+    """Rate constants from log rate constants: within 2 ulp of e^theta (mpmath, 60 digits)
+    over the whole accepted range, densely near 0 and at the ends of the argument
+    reduction's intervals (theta near (k + 1/2) ln 2)."""
+    mpmath.mp.dps = 60
+    rng = np.random.default_rng(17)
+    thetas = list(rng.uniform(-708.0, 709.0, 4000)) + list(rng.normal(0.0, 3.0, 4000))
+    thetas += list(rng.uniform(-1e-6, 1e-6, 200)) + [0.0, 1.0, -1.0, 709.0, -708.0, 1e-300, -1e-300]
+    ln2 = float(mpmath.log(2))
+    for k in range(-1020, 1022, 7):
+        thetas += [(k + 0.5) * ln2, np.nextafter((k + 0.5) * ln2, np.inf), np.nextafter((k + 0.5) * ln2, -np.inf)]
+    thetas = [t for t in thetas if -708.0 <= t <= 709.0]
+    got = orc.exp_rates(np.array(thetas))
+    worst = 0.0
+    for t, v in zip(thetas, got):
+        exact = mpmath.exp(mpmath.mpf(float(t)))
+        err = abs(mpmath.mpf(float(v)) - exact) / mpmath.mpf(math.ulp(float(exact)))
+        worst = max(worst, float(err))
+    assert worst <= 2.0, worst
+
+
+def test_exp_rates_special_values():
+    assert orc.exp_rates([0.0])[0] == 1.0
+    # below the normal range of c the rate is zero; above 709 (and NaN) invalid
+    assert list(orc.exp_rates([-708.0000001, -1000.0, -np.inf])) == [0.0, 0.0, 0.0]
+    assert np.all(np.isnan(orc.exp_rates([709.0000001, 1000.0, np.inf, np.nan])))
+    # monotone on a sorted sample, and e^a e^-a within a few ulp of 1
+    t = np.sort(np.random.default_rng(3).uniform(-50, 50, 5000))
+    c = orc.exp_rates(t)
+    assert np.all(np.diff(c) >= 0)
+    assert np.all(np.abs(c * orc.exp_rates(-t) - 1.0) <= 4 * 2.0**-52)
+    # e^(fl(ln c)) returns c for the workload's rate constants, up to the rounding of ln c
+    # (half an ulp of theta, times c) and 2 ulp of c
+    for v in (10.0, 0.01, 2e-5, 0.5, 20.0, 3.0, 1e-3, 1e-4, 0.1):
+        th = math.log(v)
+        assert abs(orc.exp_rates([th])[0] - v) <= v * math.ulp(th) / 2 + 2 * math.ulp(v)
