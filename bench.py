@@ -2,22 +2,22 @@
 CPU oracle as a reported baseline.
 
 One step is the whole hot path over one batch of synthetic input: the forward pass
-(trajectories, grid alignment, cross-trajectory mean and variance) followed by the
-likelihood-ratio backward pass of a squared-error loss on the grid means (re-simulating
-the same trajectories).  Both run through the library's persistent work-stealing kernels.
-value = forward events per step / step time: the backward's re-simulated events are
-reported beside it, never added.
+(trajectories, grid alignment, cross-trajectory mean, variance and histogram) followed by
+the likelihood-ratio backward pass of a squared-error loss on the grid means
+(re-simulating the same trajectories).  value = forward events per step / step time, the
+step timed with HIP events on the launch stream around everything both calls launch and
+the loss weights between them; the backward's re-simulated events are reported beside
+it, never added.
 
-Beside the step, the line reports the batched form against plain launches: the 64 random
-networks of the batched workload (5-40 species, 10-120 reactions, 256-16384 trajectories
-each, 200-point grids) as one graph-replayed persistent launch, against one plain launch
-per network through the same table-driven kernel; the results are checked bit-identical.
+Default workload (large): the 4-species viral network, 10^6 trajectories, t_end = 50,
+10^4-point grid, 64-bin histogram of I at every grid point, gradient enabled; the loss
+target is the mean of the same network with log rates perturbed by N(0, 0.1^2) (computed
+once, outside the timed region).  The line also carries the same step on the viral
+workload (10^4 trajectories, 1000-point grid: a launch too small to fill the chip), the
+batched form against each network's plain launch, the adaptive selective memory, the HIV
+network stress case and the oracle on the host cores.
 
-Default workload: the 4-species viral network, 10^4 trajectories, t_end = 50, 1000-point
-grid; the loss target is the mean of the same network with log rates perturbed by
-N(0, 0.1^2) (computed once, outside the timed region).
-
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload viral|differentiated|large]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|viral|differentiated]
        [--no-cpu-baseline] [--no-batched] [--copy-calibration]
 """
 import argparse
@@ -77,9 +77,12 @@ def w_forward(model, crossing_frac, changes):
 
 
 def w_backward(model, crossings_per_event):
+    """The forward event's work, the score update of every reaction (4 per reaction:
+    compare, select, product, add) and, per grid point the interval crosses, the
+    contraction of the S centred states with the M scores (S x M lane operations)."""
     M, S = model["reac"].shape
     return (W_PHILOX + W_UNIFORMS + W_NEGLOG + W_DIV + 1 + propensity_ops(model) + (M - 1) + 2 * M
-            + 4 * M + min(1.0, crossings_per_event) * W_ALIGN + crossings_per_event * (2 * S + 4 * M))
+            + 4 * M + min(1.0, crossings_per_event) * W_ALIGN + crossings_per_event * S * M)
 
 
 def kernel_sources_hash():
@@ -113,56 +116,63 @@ def stored_traffic(kernel, workload_name):
         return None
 
 
-def batched_vs_plain(ssa, torch, dev):
-    """The batched workload as one graph-replayed launch and as one plain launch per network."""
+def _median_ms(torch, stream, fn, reps):
+    """Median over reps of fn()'s device time, HIP events on stream around each call."""
+    times = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        fn()
+        b.record(stream)
+        b.synchronize()
+        times.append(a.elapsed_time(b))
+    return float(np.median(times))
+
+
+def batched_vs_plain(ssa, torch, dev, replays=20, plain_passes=3):
+    """The batched workload as one graph-replayed launch (median of `replays` replays)
+    against one plain launch per network, each through that network's default kernel
+    (median of `plain_passes` passes over the 64 networks); the results must be equal bit
+    for bit."""
     nets = inputs.random_networks()
     models = [ssa.Model.from_dict(n) for n in nets]
     grids = [torch.tensor(n["grid"], device=dev) for n in nets]
     means = [torch.empty((len(n["grid"]), n["reac"].shape[1]), dtype=torch.float64, device=dev) for n in nets]
     vars_ = [torch.empty_like(v) for v in means]
+    stream = torch.cuda.current_stream()
     batch = ssa.Batch(models, [n["n_traj"] for n in nets], [n["t_end"] for n in nets], [n["grid"] for n in nets],
                       [n["seed"] for n in nets])
-    batch.run(dev, outs=(means, vars_))                       # capture + warm-up
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, _, st = batch.run(dev, outs=(means, vars_), with_stats=True)
-    torch.cuda.synchronize()
-    batched_s = time.perf_counter() - t0
-    # the batch's own autotuner (window sizes timed on this batch), then the tuned replay
+    _, _, st = batch.run(dev, outs=(means, vars_), with_stats=True)   # capture, warm-up, event count
+    for _ in range(2):
+        batch.run(dev, outs=(means, vars_))
+    batched_ms = _median_ms(torch, stream, lambda: batch.run(dev, outs=(means, vars_)), replays)
+    # the batch's own autotuner (window sizes timed on this batch), then the tuned replays
     tune = batch.autotune()
     batch.run(dev, outs=(means, vars_))                       # re-capture with the chosen window
+    tuned_ms = _median_ms(torch, stream, lambda: batch.run(dev, outs=(means, vars_)), replays)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    _, _, st_t = batch.run(dev, outs=(means, vars_), with_stats=True)
-    torch.cuda.synchronize()
-    tuned_s = time.perf_counter() - t0
-    saved = os.environ.get("SSA_KERNEL")
-    os.environ["SSA_KERNEL"] = "generic"                      # the batched kernel's code path
-    identical = True
-    try:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        plain = [ssa.run_device(models[b], n["n_traj"], n["t_end"], grids[b], n["seed"])[:2]
-                 for b, n in enumerate(nets)]
-        torch.cuda.synchronize()
-        plain_s = time.perf_counter() - t0
-        for b, (pm, pv) in enumerate(plain):
-            identical &= bool(torch.equal(pm, means[b]) and torch.equal(pv, vars_[b]))
-    finally:
-        if saved is None:
-            os.environ.pop("SSA_KERNEL", None)
-        else:
-            os.environ["SSA_KERNEL"] = saved
+    outs = [(torch.empty_like(means[b]), torch.empty_like(vars_[b])) for b in range(len(nets))]
+
+    def plain_pass():
+        for b, n in enumerate(nets):
+            ssa.run_device(models[b], n["n_traj"], n["t_end"], grids[b], n["seed"], out=(outs[b][0], outs[b][1], None))
+
+    plain_pass()                                              # compiles the specialised kernels
+    plain_ms = _median_ms(torch, stream, plain_pass, plain_passes)
+    identical = all(bool(torch.equal(outs[b][0], means[b]) and torch.equal(outs[b][1], vars_[b]))
+                    for b in range(len(nets)))
     batch.close()
     for mo in models:
         mo.close()
     return {"workload": "64 random networks, 5-40 species, 10-120 reactions, %d trajectories, 200-point grids"
                         % sum(n["n_traj"] for n in nets),
-            "events": st["events"], "batched_ms": round(batched_s * 1e3, 3), "plain_ms": round(plain_s * 1e3, 3),
-            "batched_events_per_s": round(st["events"] / batched_s, 1),
-            "speedup": round(plain_s / batched_s, 3), "identical": identical,
-            "tuned": {"win_bytes": tune["win_bytes"], "batched_ms": round(tuned_s * 1e3, 3),
-                      "events": st_t["events"], "speedup": round(plain_s / tuned_s, 3)}}
+            "events": st["events"], "batched_ms": round(batched_ms, 3), "plain_ms": round(plain_ms, 3),
+            "timing": "median of %d graph replays / of %d passes of 64 plain launches (each network's default "
+                      "kernel), HIP events" % (replays, plain_passes),
+            "batched_events_per_s": round(st["events"] / (batched_ms * 1e-3), 1),
+            "speedup": round(plain_ms / batched_ms, 3), "identical": identical,
+            "tuned": {"win_bytes": tune["win_bytes"], "batched_ms": round(tuned_ms, 3),
+                      "speedup": round(plain_ms / tuned_ms, 3)}}
 
 
 def wide_sweep(ssa, torch, dev):
@@ -266,42 +276,164 @@ def hiv_stress(ssa, torch, dev, N=16384, t_end=5.0, G=101, seed=7, reps=2):
             "events_per_s": round(best["events"] / best["kernel_ms"] * 1e3, 1)}
 
 
-def throughput_case(ssa, torch, dev, name="large", steps=3, warmup=1):
-    """The same step (forward mean/var + LR backward) on a workload that fills the chip
-    (large: 10^6 trajectories, 10^4-point grid, histogram): kernel times and the
-    roofline fraction of both kernels, for comparison with the latency-bound default."""
+def workload(name):
+    w = dict(inputs.WORKLOADS[name])
+    m = w["model"]()
+    return m, w
+
+
+KERNEL_NAMES = {
+    # (direction, launch form) -> name of the specialised kernel in the trace
+    ("fwd", "two_wave"): "ssa_jit_fwd_pc", ("fwd", "generations"): "ssa_jit_fwd_atomic",
+    ("bwd", "two_wave"): "ssa_jit_bwd_pc", ("bwd", "generations"): "ssa_jit_bwd_gen", ("bwd", "refill"): "ssa_jit_bwd",
+    ("fwd", "table"): "fwd_kernel", ("bwd", "table"): "sim_kernel_bwd",
+}
+
+
+def kernel_name(direction, form, hist):
+    k = KERNEL_NAMES.get((direction, form), "%s_%s" % (direction, form))
+    if hist and direction == "fwd" and k.startswith("ssa_jit_fwd"):
+        k = {"ssa_jit_fwd_pc": "ssa_jit_fwd_hist_pc", "ssa_jit_fwd_atomic": "ssa_jit_fwd_hist"}[k]
+    return k
+
+
+def measure_step(ssa, torch, dev, name, steps, warmup):
+    """The step (forward mean/var[/histogram] + loss weights + LR backward) on a named
+    workload: K steps timed with HIP events on the launch stream, each step's own time
+    too, every launch's statistics (events, launch form, simulation-kernel time by HIP
+    events around it) from the timed steps themselves; forward-only steps for the
+    grad / plain ratio; the roofline of the dominant simulation kernel."""
     m, w = workload(name)
     N, t_end, G, seed = w["n_traj"], w["t_end"], w["G"], w["seed"]
     grid = torch.tensor(inputs.uniform_grid(t_end, G), dtype=torch.float64, device=dev)
     model = ssa.Model.from_dict(m)
     hist = w.get("hist")
+    stream = torch.cuda.current_stream()
+    # target of the loss: the same network with perturbed log rates (untimed)
     prates = torch.tensor(inputs.perturbed_rates(m, w.get("perturb_seed", 404)), device=dev)
     target, _, _, _ = ssa.run_device(model, N, t_end, grid, w.get("target_seed", 44), rates=prates)
-    fw, bw = [], []
-    for i in range(warmup + steps):
-        mean, var, _, sf = ssa.run_device(model, N, t_end, grid, seed, hist=hist, with_stats=True)
-        _, sb = ssa.backward_device(model, N, t_end, grid, seed, 2.0 * (mean - target), mean, with_stats=True)
-        if i >= warmup:
-            fw.append(sf["kernel_ms"])
-            bw.append(sb["kernel_ms"])
+    S, M = m["reac"].shape[1], m["reac"].shape[0]
+    mean = torch.empty((G, S), dtype=torch.float64, device=dev)
+    var = torch.empty_like(mean)
+    hbuf = torch.empty((G, hist[3]), dtype=torch.int32, device=dev) if hist else None
+    gbuf = torch.empty(M, dtype=torch.float64, device=dev)
+    wts = torch.empty_like(mean)
+
+    def step():
+        _, _, _, sf = ssa.run_device(model, N, t_end, grid, seed, hist=hist, out=(mean, var, hbuf), with_stats=True)
+        torch.sub(mean, target, out=wts)
+        wts.mul_(2.0)
+        _, sb = ssa.backward_device(model, N, t_end, grid, seed, wts, mean, out=gbuf, with_stats=True)
+        return sf, sb
+
+    for _ in range(warmup):
+        sf, sb = step()
+        assert sf["flags"] == 0 and sb["flags"] == 0, (sf, sb)
     torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    fs, bs = [], []
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(steps):
+        sf, sb = step()
+        ev[i + 1].record(stream)
+        fs.append(sf)
+        bs.append(sb)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    step_ms = ev[0].elapsed_time(ev[-1]) / steps
+    per_step = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    assert all(f["events"] == fs[0]["events"] and f["flags"] == 0 for f in fs)
+    assert all(b["events"] == fs[0]["events"] and b["flags"] == 0 for b in bs)
+    events = fs[0]["events"]
+
+    # forward-only steps (same calls, no backward), for the grad / plain ratio
+    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    f0.record(stream)
+    for _ in range(steps):
+        ssa.run_device(model, N, t_end, grid, seed, hist=hist, out=(mean, var, hbuf))
+    f1.record(stream)
+    torch.cuda.synchronize()
+    fwd_only_ms = f0.elapsed_time(f1) / steps
     model.close()
-    S = m["reac"].shape[1]
-    crossings = G * N / max(sf["events"], 1)
-    f_ms, b_ms = float(np.mean(fw)), float(np.mean(bw))
-    f_ops = w_forward(m, min(1.0, crossings), mean_changes(m)) * sf["events"] / (f_ms * 1e-3)
-    b_ops = w_backward(m, crossings) * sf["events"] / (b_ms * 1e-3)
-    return {"workload": "%s: %d trajectories, t_end %g, %d-point grid%s, forward mean/var + LR backward"
-                        % (name, N, t_end, G, ", histogram" if hist else ""),
-            "events": sf["events"], "fwd_kernel_ms": round(f_ms, 3), "bwd_kernel_ms": round(b_ms, 3),
-            "events_per_s": round(sf["events"] / ((f_ms + b_ms) * 1e-3), 1),
-            "fwd_valu_frac": round(f_ops / PEAK_LANE_OPS, 4), "bwd_valu_frac": round(b_ops / PEAK_LANE_OPS, 4)}
+
+    # roofline of the dominant simulation kernel: algorithmic lane-ops per launch / its mean
+    # launch time over the timed steps
+    crossings = G * N / max(events, 1)                 # grid points passed per event
+    fwd_avg = float(np.mean([f["kernel_ms"] for f in fs]))
+    bwd_avg = float(np.mean([b["kernel_ms"] for b in bs]))
+    wf = w_forward(m, min(1.0, crossings), mean_changes(m))
+    wb = w_backward(m, crossings)
+    kf = kernel_name("fwd", fs[0]["form"], hist)
+    kb = kernel_name("bwd", bs[0]["form"], hist)
+    if bwd_avg >= fwd_avg:
+        kname, kms, wop, blocks = kb, bwd_avg, wb, bs[0]["blocks"]
+    else:
+        kname, kms, wop, blocks = kf, fwd_avg, wf, fs[0]["blocks"]
+    achieved = wop * events / (kms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_LANE_OPS / 1e12, 3),
+                "unit": "Tlane-op/s", "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 5),
+                "traffic": stored_traffic(kname, name),
+                "kernel": kname, "kernel_ms": round(kms, 4), "ops_per_event": round(wop, 1),
+                "events_per_launch": events, "blocks": blocks,
+                "other_kernel": {"kernel": kf if kname == kb else kb, "kernel_ms": round(fwd_avg if kname == kb
+                                                                                        else bwd_avg, 4),
+                                 "ops_per_event": round(wf if kname == kb else wb, 1),
+                                 "frac": round((wf * events / (fwd_avg * 1e-3) if kname == kb
+                                                else wb * events / (bwd_avg * 1e-3)) / PEAK_LANE_OPS, 5)}}
+    cfg = {"workload": "%s: %d trajectories, t_end %g, %d-point grid%s, forward mean/var%s + LR backward"
+                       % (name, N, t_end, G, ", histogram of I (%d bins)" % hist[3] if hist else "",
+                          "/histogram" if hist else ""),
+           "n_traj": N, "grid_points": G, "t_end": t_end, "species": S, "reactions": M,
+           "histogram": list(hist) if hist else None}
+    return dict(cfg=cfg, events=events, step_ms=step_ms, median_step_ms=float(np.median(per_step)),
+                fwd_ms=fwd_avg, bwd_ms=bwd_avg, fwd_only_ms=fwd_only_ms, wall=wall, roofline=roofline,
+                fwd_form=fs[0]["form"], bwd_form=bs[0]["form"], target=target.cpu().numpy(), model=m, w=w)
 
 
-def workload(name):
-    w = dict(inputs.WORKLOADS[name])
-    m = w["model"]()
-    return m, w
+def cpu_baseline(m, w, target):
+    """The oracle on the host cores over a bounded sample of the workload (trajectories
+    0..n-1, forward with the workload's histogram + gradient, as in a step), repeated for
+    at least 10 s on all threads and 5 s on one; forward events per second."""
+    from oracle import oracle as orc
+    N, t_end, G, seed, hist = w["n_traj"], w["t_end"], w["G"], w["seed"], w.get("hist")
+    grid_np = inputs.uniform_grid(t_end, G)
+
+    def rate(threads, n_cpu, min_s):
+        ev, reps = 0, 0
+        a0 = time.perf_counter()
+        while True:
+            st, ref = orc.run(m, n_cpu, t_end, grid_np, seed, hist=hist, threads=threads)
+            st2, _, _ = orc.grad(m, n_cpu, t_end, grid_np, seed, 2.0 * (ref["mean"] - target), ref["mean"],
+                                 threads=threads)
+            assert st == 0 and st2 == 0
+            ev += ref["events"]
+            reps += 1
+            if time.perf_counter() - a0 >= min_s:
+                break
+        return ev / (time.perf_counter() - a0), reps, time.perf_counter() - a0
+
+    thr = orc.default_threads()
+    scale = 1.0 if G <= 1000 else 0.2          # a 10^4-point grid makes the gradient ~10x dearer
+    n_all = min(N, max(256, int(20000 * scale)))
+    n_one = min(N, max(64, int(2000 * scale)))
+    v_all, r_all, s_all = rate(thr, n_all, 10.0)
+    v_one, r_one, s_one = rate(1, n_one, 5.0)
+    model_name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model_name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": round(v_all, 1), "unit": "events/s", "cores": thr, "kind": "oracle",
+            "sample": "%d x (trajectories 0..%d of %d, forward + gradient), %.1f s on %d threads"
+                      % (r_all, n_all - 1, N, s_all, thr),
+            "cpu_model": model_name,
+            "single_thread": {"value": round(v_one, 1), "unit": "events/s",
+                              "sample": "%d x (trajectories 0..%d), %.1f s" % (r_one, n_one - 1, s_one)}}
 
 
 def main():
@@ -309,7 +441,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="viral", choices=["viral", "differentiated", "large"])
+    ap.add_argument("--workload", default="large", choices=["large", "viral", "differentiated"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched / plain comparison")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -359,153 +491,51 @@ def main():
               flush=True)
         return
 
-    m, w = workload(args.workload)
-    N, t_end, G, seed = w["n_traj"], w["t_end"], w["G"], w["seed"]
-    grid_np = inputs.uniform_grid(t_end, G)
-    grid = torch.tensor(grid_np, dtype=torch.float64, device=dev)
-    model = ssa.Model.from_dict(m)
-    hist = w.get("hist")
-    stream = torch.cuda.current_stream()
-
-    # target of the loss: the same network with perturbed log rates (untimed)
-    prates = torch.tensor(inputs.perturbed_rates(m, w.get("perturb_seed", 404)), device=dev)
-    target, _, _, _ = ssa.run_device(model, N, t_end, grid, w.get("target_seed", 44), rates=prates)
-    torch.cuda.synchronize()
-
-    S, M = m["reac"].shape[1], m["reac"].shape[0]
-    mean = torch.empty((G, S), dtype=torch.float64, device=dev)
-    var = torch.empty_like(mean)
-    hbuf = torch.empty((G, hist[3]), dtype=torch.int32, device=dev) if hist else None
-    gbuf = torch.empty(M, dtype=torch.float64, device=dev)
-
-    def step(with_stats):
-        _, _, _, sf = ssa.run_device(model, N, t_end, grid, seed, hist=hist, out=(mean, var, hbuf),
-                                     with_stats=with_stats)
-        wts = 2.0 * (mean - target)
-        _, sb = ssa.backward_device(model, N, t_end, grid, seed, wts, mean, out=gbuf, with_stats=with_stats)
-        return sf, sb
-
-    # warm-up with statistics: event counts (the same every step), status checks and the
-    # kernels' own times
-    fwd_ms, bwd_ms = [], []
-    stats_f = stats_b = None
-    for _ in range(max(args.warmup, 3)):
-        stats_f, stats_b = step(True)
-        assert stats_f["flags"] == 0 and stats_b["flags"] == 0, (stats_f, stats_b)
-        fwd_ms.append(stats_f["kernel_ms"])
-        bwd_ms.append(stats_b["kernel_ms"])
-    fwd_ms, bwd_ms = fwd_ms[-3:], bwd_ms[-3:]
-    torch.cuda.synchronize()
-
-    # timed steps: the calls are asynchronous on the stream (no statistics, so no host wait
-    # inside a step), as a training loop issues them
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        step(False)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    step_ms = e0.elapsed_time(e1) / args.steps
-    events = args.steps * (stats_f["events"] + stats_b["events"])
-    value = stats_f["events"] / (step_ms * 1e-3)
-
-    # forward-only timing (same kernels, no backward, issued like the steps), for the
-    # grad / plain ratio
-    f0, f1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    f0.record(stream)
-    for _ in range(args.steps):
-        ssa.run_device(model, N, t_end, grid, seed, hist=hist, out=(mean, var, hbuf))
-    f1.record(stream)
-    torch.cuda.synchronize()
-    fwd_only_ms = f0.elapsed_time(f1) / args.steps
-
-    # roofline of the dominant kernel (algorithmic lane-ops per launch / mean launch time)
-    crossings = G * N / max(stats_f["events"], 1)                 # grid points passed per event
-    cross_frac = min(1.0, crossings)
-    changes = mean_changes(m)
-    fwd_avg = float(np.mean(fwd_ms))
-    bwd_avg = float(np.mean(bwd_ms))
-    jit = os.environ.get("SSA_KERNEL") != "generic" and M <= 32 and S <= 64
-    # the kernels the library picks by work items (64 trajectories each) per CU: up to 2,
-    # two-wave blocks (a drawing wave beside each simulating one); up to 8, the backward in
-    # generations; beyond, the refilling backward
-    items_per_cu = ((N + 63) // 64) / torch.cuda.get_device_properties(0).multi_processor_count
-    if bwd_avg >= fwd_avg:
-        kname = (("ssa_jit_bwd_pc" if items_per_cu <= 2 else "ssa_jit_bwd_gen" if items_per_cu <= 8
-                  else "ssa_jit_bwd") if jit else "sim_kernel_bwd")
-        kms, wop = bwd_avg, w_backward(m, crossings)
-    else:
-        kname = ((("ssa_jit_fwd_hist_pc" if hist else "ssa_jit_fwd_pc") if items_per_cu <= 2
-                  else "ssa_jit_fwd_atomic") if jit else "fwd_kernel")
-        kms, wop = fwd_avg, w_forward(m, cross_frac, changes)
-    achieved = wop * stats_f["events"] / (kms * 1e-3) / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 4), "peak": round(PEAK_LANE_OPS / 1e12, 3),
-                "unit": "Tlane-op/s", "frac": round(achieved * 1e12 / PEAK_LANE_OPS, 5),
-                "traffic": stored_traffic(kname, args.workload),
-                "kernel": kname, "kernel_ms": round(kms, 4), "ops_per_event": round(wop, 1)}
-
+    r = measure_step(ssa, torch, dev, args.workload, args.steps, args.warmup)
     out = {
         "metric": "SSA reaction events/sec on 1 MI355X (+ % VALU roofline); batched & grad vs plain",
-        "value": round(value, 1),
+        "value": round(r["events"] / (r["step_ms"] * 1e-3), 1),
         "unit": "events/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(step_ms, 4),
+        "ms_per_step": round(r["step_ms"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64+i32",
         "data": "synthetic",
-        "config": {"workload": "%s: %d trajectories, t_end %g, %d-point grid, forward mean/var + LR backward"
-                               % (args.workload, N, t_end, G),
-                   "n_traj": N, "grid_points": G, "t_end": t_end, "species": S, "reactions": M,
-                   "histogram": list(hist) if hist else None},
-        "fwd_events_per_step": stats_f["events"],
-        "bwd_events_per_step": stats_b["events"],
-        "fwd_kernel_ms": round(fwd_avg, 4),
-        "bwd_kernel_ms": round(bwd_avg, 4),
-        "fwd_only_ms": round(fwd_only_ms, 4),
-        "grad_vs_plain": round(step_ms / fwd_only_ms, 3),
-        "wall_s": round(wall, 3),
-        "roofline": roofline,
+        "config": r["cfg"],
+        "median_step_ms": round(r["median_step_ms"], 4),
+        "fwd_events_per_step": r["events"],
+        "bwd_events_per_step": r["events"],
+        "fwd_kernel_ms": round(r["fwd_ms"], 4),
+        "bwd_kernel_ms": round(r["bwd_ms"], 4),
+        "launch_forms": {"forward": r["fwd_form"], "backward": r["bwd_form"]},
+        "fwd_only_ms": round(r["fwd_only_ms"], 4),
+        "grad_vs_plain": round(r["step_ms"] / r["fwd_only_ms"], 3),
+        "wall_s": round(r["wall"], 3),
+        "roofline": r["roofline"],
     }
 
     if not args.no_batched:
-        out["batched_vs_plain"] = batched_vs_plain(ssa, torch, dev)
         # the other forms, each timed on its own workload (see --adaptive, --hiv)
-        out["throughput_case"] = throughput_case(ssa, torch, dev)
+        other = "viral" if args.workload != "viral" else "large"
+        o = measure_step(ssa, torch, dev, other, args.steps, args.warmup)
+        out["%s_case" % other] = {"workload": o["cfg"]["workload"], "events": o["events"],
+                                  "ms_per_step": round(o["step_ms"], 4),
+                                  "events_per_s": round(o["events"] / (o["step_ms"] * 1e-3), 1),
+                                  "fwd_kernel_ms": round(o["fwd_ms"], 4), "bwd_kernel_ms": round(o["bwd_ms"], 4),
+                                  "grad_vs_plain": round(o["step_ms"] / o["fwd_only_ms"], 3),
+                                  "launch_forms": {"forward": o["fwd_form"], "backward": o["bwd_form"]},
+                                  "roofline_frac": o["roofline"]["frac"], "roofline_kernel": o["roofline"]["kernel"]}
+        out["batched_vs_plain"] = batched_vs_plain(ssa, torch, dev)
         out["adaptive_memory"] = adaptive_measure(ssa, torch, dev)
         out["hiv_stress"] = hiv_stress(ssa, torch, dev)
 
     if not args.no_cpu_baseline:
-        from oracle import oracle as orc
-        thr = orc.default_threads()
-        # bounded sample of the same workload: a slice of its trajectories (forward + gradient,
-        # as in a step), repeated until at least 10 s of oracle time have passed
-        n_cpu = min(N, int(os.environ.get("BENCH_CPU_TRAJ", str(min(N, 20000)))))
-        tw = target.cpu().numpy()
-        cpu_events, reps = 0, 0
-        a0 = time.perf_counter()
-        while True:
-            st, ref = orc.run(m, n_cpu, t_end, grid_np, seed, hist=hist, threads=thr)
-            st2, g, _ = orc.grad(m, n_cpu, t_end, grid_np, seed, 2.0 * (ref["mean"] - tw), ref["mean"],
-                                 threads=thr)
-            cpu_events += ref["events"]
-            reps += 1
-            if time.perf_counter() - a0 >= 10.0:
-                break
-        cpu_s = time.perf_counter() - a0
-        out["cpu_baseline"] = {"value": round(cpu_events / cpu_s, 1), "unit": "events/s", "cores": thr,
-                               "kind": "oracle",
-                               "sample": "%d x (trajectories 0..%d of %d, forward + gradient), %.1f s"
-                                         % (reps, n_cpu - 1, N, cpu_s)}
+        out["cpu_baseline"] = cpu_baseline(r["model"], r["w"], r["target"])
     print(json.dumps(out), flush=True)
-    model.close()
 
 
 if __name__ == "__main__":
