@@ -195,6 +195,29 @@ ssa_status ssa_run_device(const ssa_model *model, const double *rates, const dou
                           uint64_t seed, uint64_t max_events, double *mean, double *var,
                           const ssa_hist_spec *hist, uint32_t *d_hist, void *stream, ssa_stats *stats);
 
+/* ssa_run_device for callers that cannot allocate device memory (code being captured into
+ * a HIP graph, tight serving loops, hosts that forbid allocation during a run): the same
+ * arguments, results and device-side checks, but every piece of scratch (the grid-point
+ * sums, the histogram differences, the status words, rates formed from log_rates) comes
+ * from one static device area of 8 MiB that the library holds on each GPU it runs on until
+ * the process ends, and the call makes no allocation of its own.  Limits:
+ *   about 24 G S + 4 G nbins bytes (256-byte pieces), plus 16 bytes per reaction when
+ *   rates or log_rates are given (8 per dependency-list entry for a 64-chunk network above
+ *   512 reactions), must fit in the 8 MiB (the large workload, 10^4 points x 4 species
+ *   with a 64-bin histogram, takes 3.5 MiB); larger calls get SSA_E_INVALID before anything
+ *   runs;
+ *   the network's specialised kernels are used only if this device has them compiled
+ *   already (by an earlier ssa_run_device call); otherwise the table-driven kernel runs,
+ *   with the same results (a network with rate laws then gets SSA_E_UNSUPPORTED);
+ *   stats->kernel_ms is 0 (no timing events).
+ * Calls on one GPU share its area and find the last call's contents (the call clears what
+ * must start at zero): two calls that overlap in time on one GPU, on different streams or
+ * threads, race and give undefined results. */
+ssa_status ssa_run_device_static(const ssa_model *model, const double *rates, const double *log_rates,
+                                 int64_t n_traj, double t_end, const double *grid, int32_t n_grid,
+                                 uint64_t seed, uint64_t max_events, double *mean, double *var,
+                                 const ssa_hist_spec *hist, uint32_t *d_hist, void *stream, ssa_stats *stats);
+
 /* Likelihood-ratio gradient of a loss L(mean) with respect to theta_j = ln c_j (the local
  * form of Section 4's sensitivity analysis of the mean trajectories), by re-simulating the
  * same trajectories (same seed, same Philox counters):

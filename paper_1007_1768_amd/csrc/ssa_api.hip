@@ -24,6 +24,13 @@
 
 using namespace ssa;
 
+// The scratch area of ssa_run_device_static: every GPU the library runs on holds its own
+// copy until the process ends.  Host code never uses the symbol itself (on the host it is
+// a stand-in, not a device address): it takes each device's address once, with that device
+// current, from hipGetSymbolAddress (static_scratch below).
+constexpr size_t kStaticScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
 namespace {
 
 // Device sources of the run-time specialised kernels, embedded at build time.
@@ -70,20 +77,59 @@ constexpr int32_t kJitMaxSpecies = 64;
 constexpr int32_t kWaveMaxQ = 8;            // 64-chunk order: reactions per lane held in registers
 constexpr int64_t kMaxDepEntries = (int64_t)1 << 24;   // dependency lists beyond this: full re-evaluation
 
-// Device allocations made by one call, released on the stream in reverse order.
-struct StreamScratch {
+// Device memory one call needs beyond its inputs and outputs.
+struct Scratch {
+    virtual ~Scratch() = default;
+    virtual hipError_t alloc(void **p, size_t bytes) = 0;
+};
+
+// Stream-ordered allocations of one call, released on the stream in reverse order.
+struct StreamScratch : Scratch {
     hipStream_t stream;
     std::vector<void *> ptrs;
     explicit StreamScratch(hipStream_t s) : stream(s) {}
-    hipError_t alloc(void **p, size_t bytes) {
+    hipError_t alloc(void **p, size_t bytes) override {
         hipError_t e = hipMallocAsync(p, std::max<size_t>(bytes, 256), stream);
         if (e == hipSuccess) ptrs.push_back(*p);
         return e;
     }
-    ~StreamScratch() {
+    ~StreamScratch() override {
         for (auto it = ptrs.rbegin(); it != ptrs.rend(); ++it) (void)hipFreeAsync(*it, stream);
     }
 };
+
+// Consecutive 256-byte aligned pieces of a fixed device area (no allocation call).
+struct FixedScratch : Scratch {
+    char *base;
+    size_t cap, used = 0;
+    FixedScratch(void *b, size_t c) : base((char *)b), cap(c) {}
+    static size_t piece(size_t bytes) { return (std::max<size_t>(bytes, 1) + 255) & ~(size_t)255; }
+    hipError_t alloc(void **p, size_t bytes) override {
+        const size_t b = piece(bytes);
+        if (used + b > cap) return hipErrorOutOfMemory;
+        *p = base + used;
+        used += b;
+        return hipSuccess;
+    }
+};
+
+std::mutex g_static_mu;
+void *g_static_ptr[64] = {};
+
+// The current device's address of the scratch area (looked up at the first call on the device).
+ssa_status static_scratch(int dev, void **out) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (dev < 0 || dev >= 64) return fail(SSA_E_UNSUPPORTED, "device index %d beyond 63", dev);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(SSA_E_DEVICE, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_static_ptr[dev] = p;
+    }
+    *out = g_static_ptr[dev];
+    return SSA_OK;
+}
 
 // Keep freed stream-ordered memory in the pool between calls instead of returning it.
 void keep_pool(int dev) {
@@ -351,6 +397,11 @@ bool pc_launch(int64_t n_items, int dev) {
 // The network's kernels compiled at run time; ilp: scheduled for latency-bound launches
 // (independent chains interleaved), else for throughput (the default scheduler, which
 // measured faster once several waves share a SIMD).
+bool jit_cached(const ssa_model *m, int dev, bool ilp) {
+    std::lock_guard<std::mutex> lk(g_jit_mu);
+    return g_jit_cache.count(std::make_tuple(dev, m->jit_src, ilp)) != 0;
+}
+
 ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out, bool ilp = false) {
     const auto key = std::make_tuple(dev, m->jit_src, ilp);
     {
@@ -696,7 +747,7 @@ bool wide_depg(const ssa_model *m) {
 }
 
 template <int MODE>
-hipError_t launch_wide(const ssa_model *m, const WorkList &wl, int dev, hipStream_t st, StreamScratch &scr) {
+hipError_t launch_wide(const ssa_model *m, const WorkList &wl, int dev, hipStream_t st, Scratch &scr) {
     const bool depg = wide_depg(m);
     WorkList w = wl;
     if (depg && m->dep_nnz > 0 && w.net0.rate != m->d_rate) {
@@ -729,7 +780,7 @@ hipError_t launch_wide(const ssa_model *m, const WorkList &wl, int dev, hipStrea
 }
 
 template <int MODE>
-hipError_t launch_wave(const ssa_model *m, const WorkList &wl, int dev, hipStream_t st, StreamScratch &scr) {
+hipError_t launch_wave(const ssa_model *m, const WorkList &wl, int dev, hipStream_t st, Scratch &scr) {
     if (m->q > kWaveMaxQ) return launch_wide<MODE>(m, wl, dev, st, scr);
     const void *kern = nullptr;
     if (m->q <= 1) kern = (const void *)wave_kernel<1, MODE>;
@@ -763,7 +814,7 @@ hipError_t launch_finalize(const unsigned long long *D, const unsigned long long
 // network, or the generic one (which reads rates in zero-padded slots: a caller's rates
 // array is copied into a padded buffer first).
 ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_items, int dev, hipStream_t st,
-                         const double *user_rates, StreamScratch &scr, bool quad = false) {
+                         const double *user_rates, Scratch &scr, bool quad = false) {
     (void)n_items;
     if (m->order == SSA_SUM_BLOCK64) {
         HIP_TRY(mode == kRec   ? launch_wave<kRec>(m, wl, dev, st, scr)
@@ -905,10 +956,16 @@ FwdTune tune_lookup(const ssa_model *m, int64_t n_traj, int32_t G, int dev) {
 // Forward launch of one network.  D receives the [G][S][2] difference sums, by atomic
 // flushes of the windows into D directly or through wave-private slabs and a reduction
 // (see want_slabs).  Dhi ([G][S], high parts) must be zero on entry.
+// may_compile false: the specialised kernels only if this device has them compiled already
+// (else the table-driven kernel, with the same results; networks with rate laws then fail).
 ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int dev, hipStream_t st,
-                          const double *user_rates, StreamScratch &scr, unsigned long long *D, float *kernel_ms,
-                          const FwdTune &tune) {
+                          const double *user_rates, Scratch &scr, unsigned long long *D, float *kernel_ms,
+                          const FwdTune &tune, bool may_compile = true) {
     const int32_t G = wl.net0.G, S = m->S;
+    const bool use_jit = jit_eligible(m) && (may_compile || jit_cached(m, dev, latency_bound(n_items, dev)));
+    if (m->has_laws && !use_jit)
+        return fail(SSA_E_UNSUPPORTED, "a network with rate laws needs its specialised kernels compiled on this "
+                                       "device first (one ssa_run_device call)");
     if (m->order == SSA_SUM_BLOCK64) {
         HIP_TRY(launch_zero(D, (size_t)G * S * 2 * sizeof(unsigned long long), st));
         EventPair ev;
@@ -922,12 +979,12 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
         return SSA_OK;
     }
     FwdKernel k;
-    wl.win_bins = window_bins(S, G, !jit_eligible(m), tune.win_bytes);
+    wl.win_bins = window_bins(S, G, !use_jit, tune.win_bytes);
     wl.win_words = wl.win_bins * S * 2;
     // the specialised kernels run generations with one window per wave, the table-driven
     // kernel cohorts with kCohorts windows
     const size_t win_bytes = (size_t)(kBlock / kWave) * wl.win_words * sizeof(long long);
-    if (jit_eligible(m)) {
+    if (use_jit) {
         std::shared_ptr<JitKernels> jk;
         ssa_status s = get_jit(m, dev, jk, latency_bound(n_items, dev));
         if (s) return s;
@@ -1178,7 +1235,7 @@ namespace {
 // formed on the device (zero-padded to the model's table width; an invalid theta refuses the
 // run), or NULL for the model's own.  ctl must be zeroed.
 ssa_status run_rates(const ssa_model *m, const double *rates, const double *log_rates, void *ctl,
-                     StreamScratch &scr, hipStream_t st, const double **out) {
+                     Scratch &scr, hipStream_t st, const double **out) {
     *out = rates;
     if (!log_rates) return SSA_OK;
     void *p = nullptr;
@@ -1192,10 +1249,13 @@ ssa_status run_rates(const ssa_model *m, const double *rates, const double *log_
 
 // The forward pass with a given launch configuration (tune == nullptr: the cached tuned
 // one, else the defaults).
+// fixed != nullptr: every piece of scratch comes from that area and the call allocates
+// nothing, compiles nothing (see launch_forward), flushes the windows by atomics and does
+// not time its kernel.
 ssa_status run_device_impl(const ssa_model *m, const double *rates, const double *log_rates, int64_t n_traj,
                            double t_end, const double *grid, int32_t G, uint64_t seed, uint64_t max_events,
                            double *mean, double *var, const ssa_hist_spec *hist, uint32_t *d_hist, void *stream,
-                           ssa_stats *stats, const FwdTune *tune) {
+                           ssa_stats *stats, const FwdTune *tune, Scratch *fixed = nullptr) {
     if (!m) return fail(SSA_E_INVALID, "model is NULL");
     if (n_traj <= 0) return fail(SSA_E_INVALID, "n_traj must be > 0");
     if (G <= 0 || !grid || !mean || !var) return fail(SSA_E_INVALID, "grid / mean / var missing");
@@ -1209,8 +1269,9 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, const double
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    keep_pool(dev);
-    StreamScratch scr(st);
+    if (!fixed) keep_pool(dev);
+    StreamScratch pooled(st);
+    Scratch &scr = fixed ? *fixed : (Scratch &)pooled;
 
     const size_t cells = (size_t)G * m->S;
     const size_t H_bytes = hist ? sizeof(int32_t) * (size_t)G * hist->nbins : 0;
@@ -1247,8 +1308,9 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, const double
     wl.stats = (unsigned long long *)((char *)ctl + 32);
 
     float kms = 0.f;
-    const FwdTune cfg = tune ? *tune : tune_lookup(m, n_traj, G, dev);
-    s = launch_forward(m, wl, n_items, dev, st, rates, scr, n.D, stats ? &kms : nullptr, cfg);
+    FwdTune cfg = tune ? *tune : (fixed ? FwdTune() : tune_lookup(m, n_traj, G, dev));
+    if (fixed) cfg.slab = 0;
+    s = launch_forward(m, wl, n_items, dev, st, rates, scr, n.D, (stats && !fixed) ? &kms : nullptr, cfg, !fixed);
     if (s) return s;
     HIP_TRY(launch_finalize(n.D, n.Dhi, G, m->S, m->d_x0, n_traj, mean, var, ctl_flags(ctl), st));
     if (hist) {
@@ -1274,6 +1336,34 @@ ssa_status ssa_run_device(const ssa_model *m, const double *rates, const double 
                           ssa_stats *stats) {
     return run_device_impl(m, rates, log_rates, n_traj, t_end, grid, G, seed, max_events, mean, var, hist, d_hist,
                            stream, stats, nullptr);
+}
+
+ssa_status ssa_run_device_static(const ssa_model *m, const double *rates, const double *log_rates, int64_t n_traj,
+                                 double t_end, const double *grid, int32_t G, uint64_t seed, uint64_t max_events,
+                                 double *mean, double *var, const ssa_hist_spec *hist, uint32_t *d_hist,
+                                 void *stream, ssa_stats *stats) {
+    if (!m) return fail(SSA_E_INVALID, "model is NULL");
+    if (G <= 0) return fail(SSA_E_INVALID, "grid must have at least one point");
+    // upper bound of the pieces run_device_impl and launch_forward take, in their order
+    const size_t cells = (size_t)G * m->S;
+    size_t need = FixedScratch::piece(16 * cells) + FixedScratch::piece(8 * cells) + FixedScratch::piece(kCtlBytes);
+    if (hist && hist->nbins > 0) need += FixedScratch::piece(sizeof(int32_t) * cells / m->S * (size_t)hist->nbins);
+    if (log_rates) need += FixedScratch::piece(sizeof(double) * (size_t)m->m_pad);
+    if (rates || log_rates)
+        need += FixedScratch::piece(sizeof(double) * std::max<size_t>((size_t)m->m_pad, (size_t)m->dep_nnz));
+    if (need > kStaticScratchBytes)
+        return fail(SSA_E_INVALID,
+                    "the call needs %zu bytes of scratch and the static area holds %zu: fewer grid points, species "
+                    "or histogram bins, or ssa_run_device",
+                    need, kStaticScratchBytes);
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    void *base = nullptr;
+    ssa_status s = static_scratch(dev, &base);
+    if (s) return s;
+    FixedScratch area(base, kStaticScratchBytes);
+    return run_device_impl(m, rates, log_rates, n_traj, t_end, grid, G, seed, max_events, mean, var, hist, d_hist,
+                           stream, stats, nullptr, &area);
 }
 
 ssa_status ssa_autotune_forward(const ssa_model *m, const double *rates, int64_t n_traj, double t_end,

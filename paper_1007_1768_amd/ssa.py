@@ -19,7 +19,7 @@ _NAMES = {1: "SSA_E_INVALID", 2: "SSA_E_NOMEM", 3: "SSA_E_DEVICE", 4: "SSA_E_OVE
           5: "SSA_E_EVENT_LIMIT", 6: "SSA_E_UNSUPPORTED"}
 
 EXPORTS = ["ssa_model_create", "ssa_model_create_laws", "ssa_model_destroy", "ssa_run", "ssa_rates_from_log",
-           "ssa_run_device",
+           "ssa_run_device", "ssa_run_device_static",
            "ssa_backward_device", "ssa_backward_moments_device",
            "ssa_run_jacobian_device", "ssa_jacobian_vjp", "ssa_autotune_forward", "ssa_run_cov_device",
            "ssa_hist_quantiles", "ssa_adaptive_device",
@@ -71,6 +71,7 @@ def load(path=None):
     L.ssa_run.argtypes = [vp, i64, dbl, vp, i32, u64, vp, vp, vp]
     L.ssa_rates_from_log.argtypes = [vp, i32, vp, vp]
     L.ssa_run_device.argtypes = [vp, vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
+    L.ssa_run_device_static.argtypes = [vp, vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
     L.ssa_backward_device.argtypes = [vp, vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
     L.ssa_backward_moments_device.argtypes = [vp, vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp, vp]
     L.ssa_autotune_forward.argtypes = [vp, vp, i64, dbl, vp, i32, u64, vp, vp]
@@ -205,6 +206,20 @@ def run_device(model, n_traj, t_end, grid, seed, rates=None, hist=None, max_even
                                  ctypes.byref(spec) if spec is not None else None, _tp(h), _stream(stream),
                                  ctypes.byref(st) if st is not None else None))
     return mean, var, h, (st.as_dict() if st is not None else None)
+
+
+def run_device_static(model, n_traj, t_end, grid, seed, out, rates=None, log_rates=None, hist=None, max_events=0,
+                      stream=None, with_stats=False):
+    """ssa_run_device_static: run_device into caller-given outputs out = (mean, var, hist or
+    None), with the library's static scratch area (no allocation); returns stats or None."""
+    mean, var, h = out
+    spec = HistSpec(*[int(v) for v in hist]) if hist is not None else None
+    st = Stats() if with_stats else None
+    _check(load().ssa_run_device_static(model.handle, _tp(rates), _tp(log_rates), int(n_traj), float(t_end),
+                                        _tp(grid), grid.shape[0], int(seed), int(max_events), _tp(mean), _tp(var),
+                                        ctypes.byref(spec) if spec is not None else None, _tp(h), _stream(stream),
+                                        ctypes.byref(st) if st is not None else None))
+    return st.as_dict() if st is not None else None
 
 
 def backward_device(model, n_traj, t_end, grid, seed, w, mhat, rates=None, max_events=0, stream=None,
