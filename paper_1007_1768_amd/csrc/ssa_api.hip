@@ -3,7 +3,6 @@
 // finalize and error reporting.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
-#include <hipcub/hipcub.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -1792,6 +1791,49 @@ ssa_status ssa_record(const ssa_model *m, const double *rates, int64_t traj_begi
     return SSA_OK;
 }
 
+// Inclusive prefix sum of n int32 values (in place allowed); sums holds n / kScanTile + 1
+// int32 of scratch.
+hipError_t launch_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *sums, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const int64_t tiles = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(scan_tile_sums_kernel, dim3((unsigned)tiles), dim3(256), 0, st, in, n, sums);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, st, sums, tiles);
+    hipLaunchKernelGGL(scan_apply_kernel, dim3((unsigned)tiles), dim3(256), 0, st, in, n, (const int32_t *)sums, out);
+    return hipGetLastError();
+}
+
+// Time order of one epoch's event log (see bin_count_kernel): the R records among the
+// first n_slots slots of (key, val), whose times lie in [t0, t1], end sorted by key in the
+// first R slots of (okey, oval).  Scratch: bins [>= B] and big [>= B] int32, n_big one
+// int32, sums as launch_scan's for n = B.  B: about R / 16 bins (SSA_SORT_BINS overrides).
+hipError_t sort_event_log(const unsigned long long *key, const unsigned long long *val, int64_t n_slots, int64_t R,
+                          double t0, double t1, unsigned long long *okey, unsigned long long *oval, int32_t *bins,
+                          int32_t *big, int32_t *n_big, int32_t *sums, int64_t max_bins, hipStream_t st) {
+    int64_t B = 1;
+    while (B < R / 16 && B < ((int64_t)1 << 25)) B <<= 1;
+    if (const char *e = std::getenv("SSA_SORT_BINS")) B = std::max<int64_t>(1, std::strtoll(e, nullptr, 10));
+    B = std::min(B, std::max<int64_t>(1, max_bins));
+    TimeBins tb;
+    tb.t0 = t0;
+    tb.scale = t1 > t0 ? (double)B / (t1 - t0) : 0.0;
+    tb.B = (int32_t)B;
+    tb.pad = 0;
+    hipError_t e = launch_zero(bins, sizeof(int32_t) * (size_t)B, st);
+    if (e == hipSuccess) e = launch_zero(n_big, sizeof(int32_t), st);
+    if (e != hipSuccess) return e;
+    const unsigned gs = (unsigned)std::min<int64_t>((n_slots + 255) / 256, 8192);
+    hipLaunchKernelGGL(bin_count_kernel, dim3(gs), dim3(256), 0, st, key, n_slots, tb, bins);
+    e = launch_scan(bins, bins, B, sums, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(bin_scatter_kernel, dim3(gs), dim3(256), 0, st, key, val, n_slots, tb, bins, okey, oval);
+    const unsigned gb = (unsigned)std::min<int64_t>((B + 3) / 4, 8192);
+    hipLaunchKernelGGL(bin_sort_small_kernel, dim3(gb), dim3(256), 0, st, okey, oval, (const int32_t *)bins,
+                       (int32_t)B, R, big, n_big);
+    hipLaunchKernelGGL(bin_sort_big_kernel, dim3(1024), dim3(256), 0, st, okey, oval, (const int32_t *)bins,
+                       (int32_t)B, R, (const int32_t *)big, (const int32_t *)n_big);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------------------------
 // Adaptive selective memory: event log -> sort by time -> moments at every distinct event
 // time (Avg-Y) -> averages of k successive points (Avg-XY).
@@ -1899,17 +1941,9 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
     HIP_TRY(scr.alloc(&vals1, sizeof(unsigned long long) * (size_t)slots));
     HIP_TRY(scr.alloc(&stf, sizeof(int32_t) * (size_t)cap));
     HIP_TRY(scr.alloc(&rk, sizeof(int32_t) * (size_t)cap));
-    void *sort_tmp = nullptr;
-    size_t sort_tmp_bytes = 0;
-    {
-        size_t tb = 0, tb2 = 0;
-        HIP_TRY(hipcub::DeviceRadixSort::SortPairs(nullptr, tb, (const unsigned long long *)keys0,
-                                                   (unsigned long long *)keys1, (const unsigned long long *)vals0,
-                                                   (unsigned long long *)vals1, (int)slots, 0, 64, st));
-        HIP_TRY(hipcub::DeviceScan::InclusiveSum(nullptr, tb2, (const int32_t *)stf, (int32_t *)rk, (int)cap, st));
-        sort_tmp_bytes = std::max(tb, tb2);
-        HIP_TRY(scr.alloc(&sort_tmp, sort_tmp_bytes));
-    }
+    void *scan_sums = nullptr, *n_big = nullptr;
+    HIP_TRY(scr.alloc(&scan_sums, sizeof(int32_t) * (size_t)(cap / kScanTile + 2)));
+    HIP_TRY(scr.alloc(&n_big, sizeof(int32_t)));
     // epochs: saved trajectory states, double-buffered
     void *sx[2] = {nullptr, nullptr}, *stt[2] = {nullptr, nullptr}, *skk[2] = {nullptr, nullptr},
          *sev[2] = {nullptr, nullptr};
@@ -1977,16 +2011,15 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
         int32_t n_distinct = 0;
         unsigned long long first_key = 0;
         if (R > 0) {
-            size_t tb = sort_tmp_bytes;
-            HIP_TRY(hipcub::DeviceRadixSort::SortPairs(sort_tmp, tb, (const unsigned long long *)keys0,
-                                                       (unsigned long long *)keys1, (const unsigned long long *)vals0,
-                                                       (unsigned long long *)vals1, nSlots, 0, 64, st));
+            // bins and the big-bin list borrow the rank arrays (both >= R >= the bin count)
+            HIP_TRY(sort_event_log((const unsigned long long *)keys0, (const unsigned long long *)vals0, nSlots,
+                                   (int64_t)R, t0, t1, (unsigned long long *)keys1, (unsigned long long *)vals1,
+                                   (int32_t *)rk, (int32_t *)stf, (int32_t *)n_big, (int32_t *)scan_sums, cap, st));
             const unsigned gb = (unsigned)std::min<int64_t>(((int64_t)R + 255) / 256, 65535);
             hipLaunchKernelGGL(evt_start_kernel, dim3(gb), dim3(256), 0, st, (const unsigned long long *)keys1,
                                (int64_t)R, (int32_t *)stf);
             HIP_TRY(hipGetLastError());
-            tb = sort_tmp_bytes;
-            HIP_TRY(hipcub::DeviceScan::InclusiveSum(sort_tmp, tb, (const int32_t *)stf, (int32_t *)rk, nR, st));
+            HIP_TRY(launch_scan((const int32_t *)stf, (int32_t *)rk, nR, (int32_t *)scan_sums, st));
             HIP_TRY(hipMemcpyAsync(&n_distinct, (int32_t *)rk + (R - 1), sizeof n_distinct, hipMemcpyDeviceToHost,
                                    st));
             HIP_TRY(hipMemcpyAsync(&first_key, keys1, sizeof first_key, hipMemcpyDeviceToHost, st));

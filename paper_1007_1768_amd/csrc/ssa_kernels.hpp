@@ -911,6 +911,248 @@ __global__ void fill_kernel(unsigned long long *__restrict__ p, size_t n_words, 
 
 
 // ---------------------------------------------------------------------------------------
+// Inclusive prefix sum of int32 values (n < 2^31, totals below 2^31), in place or not:
+// tiles of kScanTile values (16 per thread), the tile totals scanned by one block, then
+// every tile scanned with its offset.
+// ---------------------------------------------------------------------------------------
+constexpr int kScanPer = 16;
+constexpr int kScanTile = 256 * kScanPer;
+
+__device__ __forceinline__ int32_t block_excl_scan256(int32_t v, int32_t *sh, int32_t &total) {
+    const int t = threadIdx.x;
+    sh[t] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int32_t a = t >= off ? sh[t - off] : 0;
+        __syncthreads();
+        sh[t] += a;
+        __syncthreads();
+    }
+    total = sh[255];
+    const int32_t incl = sh[t];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ void __launch_bounds__(256) scan_tile_sums_kernel(const int32_t *__restrict__ in, int64_t n,
+                                                             int32_t *__restrict__ sums) {
+    __shared__ int32_t sh[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int32_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i)
+        if (base + i < n) acc += in[base + i];
+    int32_t total = 0;
+    block_excl_scan256(acc, sh, total);
+    if (threadIdx.x == 0) sums[blockIdx.x] = total;
+}
+
+// Exclusive scan of the tile totals in place (one block).
+__global__ void __launch_bounds__(256) scan_sums_kernel(int32_t *__restrict__ sums, int64_t n_tiles) {
+    __shared__ int32_t sh[256];
+    int32_t carry = 0;
+    for (int64_t base = 0; base < n_tiles; base += 256) {
+        const int64_t i = base + threadIdx.x;
+        const int32_t v = i < n_tiles ? sums[i] : 0;
+        int32_t total = 0;
+        const int32_t ex = block_excl_scan256(v, sh, total);
+        if (i < n_tiles) sums[i] = carry + ex;
+        carry += total;
+    }
+}
+
+__global__ void __launch_bounds__(256) scan_apply_kernel(const int32_t *in, int64_t n,
+                                                         const int32_t *__restrict__ sums, int32_t *out) {
+    __shared__ int32_t sh[256];
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanPer;
+    int32_t v[kScanPer];
+    int32_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        v[i] = base + i < n ? in[base + i] : 0;
+        acc += v[i];
+    }
+    int32_t total = 0;
+    int32_t run = sums[blockIdx.x] + block_excl_scan256(acc, sh, total);
+#pragma unroll
+    for (int i = 0; i < kScanPer; ++i) {
+        run += v[i];
+        if (base + i < n) out[base + i] = run;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Time order of the event log (adaptive selective memory, Section 3.2.1: the points of all
+// trajectories merged by simulation time).  The keys are the bit patterns of the event
+// times of one epoch, in [t0, t1] (non-negative binary64 values order like their bits), or
+// ~0 for a slot no record took.  A bucket sort by time: bin(t) = floor((t - t0) * scale),
+// clamped to [0, B - 1], is monotone in t, so every key of bin b is at most every key of
+// bin b + 1; the records are counted per bin, the counts scanned, each record scattered
+// into its bin's range (slots without a record are dropped), and then every bin is sorted
+// by key -- by one wave (rank by counting) up to 64 records, else by one block (bitonic
+// network with ascending comparators only, in LDS up to kBinLds records, in global memory
+// beyond).  Records with equal keys end in any order: only the distinct times and the
+// integer sums of their records are used.
+// ---------------------------------------------------------------------------------------
+struct TimeBins {
+    double t0, scale;
+    int32_t B, pad;
+};
+
+constexpr unsigned long long kNoRecord = ~0ull;
+constexpr int kBinLds = 2048;
+
+__device__ __forceinline__ int32_t time_bin(const TimeBins &tb, unsigned long long key) {
+    const double f = (__longlong_as_double((long long)key) - tb.t0) * tb.scale;
+    return f > 0.0 ? (f < (double)tb.B ? (int32_t)f : tb.B - 1) : 0;
+}
+
+__global__ void __launch_bounds__(256) bin_count_kernel(const unsigned long long *__restrict__ key, int64_t n,
+                                                        TimeBins tb, int32_t *__restrict__ cnt) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
+        const unsigned long long k = key[r];
+        if (k != kNoRecord) atomicAdd(cnt + time_bin(tb, k), 1);
+    }
+}
+
+// cur: the inclusive scan of the counts on entry; each record takes the slot below its
+// bin's cursor, so on exit cur[b] is the first slot of bin b.  A thread takes kScatterPer
+// records at once, so their cursor atomics are in flight together before the dependent
+// stores.
+constexpr int kScatterPer = 4;
+__global__ void __launch_bounds__(256) bin_scatter_kernel(const unsigned long long *__restrict__ key,
+                                                          const unsigned long long *__restrict__ val, int64_t n,
+                                                          TimeBins tb, int32_t *__restrict__ cur,
+                                                          unsigned long long *__restrict__ okey,
+                                                          unsigned long long *__restrict__ oval) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r0 < n; r0 += kScatterPer * stride) {
+        unsigned long long k[kScatterPer], v[kScatterPer];
+        int32_t p[kScatterPer];
+#pragma unroll
+        for (int i = 0; i < kScatterPer; ++i) {
+            const int64_t r = r0 + i * stride;
+            k[i] = r < n ? key[r] : kNoRecord;
+            v[i] = r < n ? val[r] : 0ull;
+        }
+#pragma unroll
+        for (int i = 0; i < kScatterPer; ++i)
+            p[i] = k[i] != kNoRecord ? atomicSub(cur + time_bin(tb, k[i]), 1) - 1 : -1;
+#pragma unroll
+        for (int i = 0; i < kScatterPer; ++i) {
+            if (p[i] >= 0) {
+                okey[p[i]] = k[i];
+                oval[p[i]] = v[i];
+            }
+        }
+    }
+}
+
+// Bins of at most 64 records, one wave each: lane i takes record i, its place is the number
+// of smaller keys plus the number of equal keys at lower lanes.  Larger bins are listed in
+// big[] for bin_sort_big_kernel.
+__global__ void __launch_bounds__(256) bin_sort_small_kernel(unsigned long long *__restrict__ key,
+                                                             unsigned long long *__restrict__ val,
+                                                             const int32_t *__restrict__ start, int32_t B, int64_t R,
+                                                             int32_t *__restrict__ big, int32_t *__restrict__ n_big) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave; b < B; b += waves) {
+        const int64_t s = start[b], e = b + 1 < B ? (int64_t)start[b + 1] : R;
+        const int32_t n = (int32_t)(e - s);
+        if (n <= 1) continue;
+        if (n > kWave) {
+            if (lane == 0) big[atomicAdd(n_big, 1)] = (int32_t)b;
+            continue;
+        }
+        const unsigned long long k = lane < n ? key[s + lane] : kNoRecord;
+        const unsigned long long v = lane < n ? val[s + lane] : 0ull;
+        int32_t rank = 0;
+        for (int32_t j = 0; j < n; ++j) {
+            const unsigned long long kj = __shfl(k, j);
+            rank += (kj < k || (kj == k && j < lane)) ? 1 : 0;
+        }
+        if (lane < n) {
+            key[s + rank] = k;
+            val[s + rank] = v;
+        }
+    }
+}
+
+// Ascending bitonic network over n elements at positions [0, P) (P = n rounded up to a power
+// of two; positions >= n act as +infinity and are never touched): for every merge size k,
+// first i against i ^ (k - 1), then i against i ^ d for d = k/4 .. 1, every comparator
+// putting the smaller key at the lower position.  ACC(i) is a reference to key i, SWP(i, j)
+// exchanges records i and j.
+template <class KeyAt, class Swap>
+__device__ __forceinline__ void bitonic_ascending(int64_t n, KeyAt key_at, Swap swp, bool lds) {
+    int64_t P = 1;
+    while (P < n) P <<= 1;
+    auto stage = [&](int64_t d, bool flip) {
+        for (int64_t q = threadIdx.x; q < P / 2; q += blockDim.x) {
+            // q-th pair: i has bit log2(d) clear (flip: the lower half of its k-block)
+            const int64_t i = ((q / d) * 2 * d) + (q % d);
+            const int64_t j = flip ? (i ^ (2 * d - 1)) : (i + d);
+            if (j < n && key_at(j) < key_at(i)) swp(i, j);
+        }
+        if (!lds) __threadfence_block();
+        __syncthreads();
+    };
+    for (int64_t k = 2; k <= P; k <<= 1) {
+        stage(k / 2, true);
+        for (int64_t d = k / 4; d >= 1; d >>= 1) stage(d, false);
+    }
+}
+
+__global__ void __launch_bounds__(256) bin_sort_big_kernel(unsigned long long *__restrict__ key,
+                                                           unsigned long long *__restrict__ val,
+                                                           const int32_t *__restrict__ start, int32_t B, int64_t R,
+                                                           const int32_t *__restrict__ big,
+                                                           const int32_t *__restrict__ n_big) {
+    __shared__ unsigned long long sk[kBinLds], sv[kBinLds];
+    const int32_t nb = *n_big;
+    for (int32_t i = blockIdx.x; i < nb; i += gridDim.x) {
+        const int64_t b = big[i];
+        const int64_t s = start[b], e = b + 1 < B ? (int64_t)start[b + 1] : R;
+        const int64_t n = e - s;
+        if (n <= kBinLds) {
+            for (int64_t q = threadIdx.x; q < n; q += blockDim.x) {
+                sk[q] = key[s + q];
+                sv[q] = val[s + q];
+            }
+            __syncthreads();
+            bitonic_ascending(
+                n, [&](int64_t q) { return sk[q]; },
+                [&](int64_t a, int64_t c) {
+                    const unsigned long long tk = sk[a], tv = sv[a];
+                    sk[a] = sk[c];
+                    sv[a] = sv[c];
+                    sk[c] = tk;
+                    sv[c] = tv;
+                },
+                true);
+            for (int64_t q = threadIdx.x; q < n; q += blockDim.x) {
+                key[s + q] = sk[q];
+                val[s + q] = sv[q];
+            }
+        } else {
+            unsigned long long *gk = key + s, *gv = val + s;
+            bitonic_ascending(
+                n, [&](int64_t q) { return gk[q]; },
+                [&](int64_t a, int64_t c) {
+                    const unsigned long long tk = gk[a], tv = gv[a];
+                    gk[a] = gk[c];
+                    gv[a] = gv[c];
+                    gk[c] = tk;
+                    gv[c] = tv;
+                },
+                false);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------
 // Adaptive selective memory (Section 3.2.1, Figure 3) from the time-sorted event log:
 // Avg-Y's points are time 0 and the distinct event times; a record starts a point when its
 // time differs from the previous record's.

@@ -189,3 +189,21 @@ def test_adaptive_64_chunk_order(ssa, monkeypatch, make, N, t_end, seed, k, epoc
     assert st == 0
     _compare(out, ref)
     assert out["stats"]["events"] == ref["events"]
+
+
+@pytest.mark.parametrize("bins", ["1", "5", "300"])
+@pytest.mark.parametrize("case", ["viral", "immigration_death", "closed"])
+def test_adaptive_time_order_paths(ssa, monkeypatch, bins, case):
+    """The time order of the event log with forced bin counts, so every path of the bucket
+    sort runs: one bin for the whole log (a block-wide network in global memory, beyond
+    2048 records), a few bins (networks in LDS), many bins (wave-sized bins)."""
+    monkeypatch.setenv("SSA_SORT_BINS", bins)
+    make, N, t_end, seed, k = CASES[case]
+    m = make()
+    model = ssa.Model.from_dict(m)
+    out = ssa.adaptive_device(model, N, t_end, seed, k, with_y=True, with_stats=True)
+    torch.cuda.synchronize()
+    model.close()
+    st, ref = orc.adaptive(m, N, t_end, seed, k)
+    assert st == 0
+    _compare(out, ref)
