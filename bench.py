@@ -389,7 +389,8 @@ def measure_step(ssa, torch, dev, name, steps, warmup):
            "histogram": list(hist) if hist else None}
     return dict(cfg=cfg, events=events, step_ms=step_ms, median_step_ms=float(np.median(per_step)),
                 fwd_ms=fwd_avg, bwd_ms=bwd_avg, fwd_only_ms=fwd_only_ms, wall=wall, roofline=roofline,
-                fwd_form=fs[0]["form"], bwd_form=bs[0]["form"], target=target.cpu().numpy(), model=m, w=w)
+                fwd_form=fs[0]["form"], bwd_form=bs[0]["form"], fwd_blocks=fs[0]["blocks"],
+                bwd_blocks=bs[0]["blocks"], target=target.cpu().numpy(), model=m, w=w)
 
 
 def cpu_baseline(m, w, target):
@@ -454,6 +455,9 @@ def main():
                     help="only time the adaptive selective memory at 10^6 trajectories (epochs) and print it")
     ap.add_argument("--hiv", action="store_true",
                     help="only run the HIV network stress case (forward) and print it")
+    ap.add_argument("--autotune", action="store_true",
+                    help="only run the forward and backward autotuners on the viral, differentiated and large "
+                         "workloads and print what they chose")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -486,6 +490,17 @@ def main():
     if args.adaptive:
         print(json.dumps({"adaptive": adaptive_measure(ssa, torch, dev)}), flush=True)
         return
+    if args.autotune:
+        for name in ("viral", "differentiated", "large"):
+            m, w = workload(name)
+            grid = torch.tensor(inputs.uniform_grid(w["t_end"], w["G"]), dtype=torch.float64, device=dev)
+            model = ssa.Model.from_dict(m)
+            f = ssa.autotune_forward(model, w["n_traj"], w["t_end"], grid, w["seed"])
+            b = ssa.autotune_backward(model, w["n_traj"], w["t_end"], grid, w["seed"])
+            model.close()
+            print(json.dumps({"autotune": name, "n_traj": w["n_traj"], "grid_points": w["G"],
+                              "forward": f, "backward": b}), flush=True)
+        return
     if args.wide_sweep:
         print(json.dumps({"sweep": "wide networks, forward events/s", "rows": wide_sweep(ssa, torch, dev)}),
               flush=True)
@@ -511,7 +526,8 @@ def main():
         "bwd_events_per_step": r["events"],
         "fwd_kernel_ms": round(r["fwd_ms"], 4),
         "bwd_kernel_ms": round(r["bwd_ms"], 4),
-        "launch_forms": {"forward": r["fwd_form"], "backward": r["bwd_form"]},
+        "launch_forms": {"forward": r["fwd_form"], "backward": r["bwd_form"], "forward_blocks": r["fwd_blocks"],
+                         "backward_blocks": r["bwd_blocks"]},
         "fwd_only_ms": round(r["fwd_only_ms"], 4),
         "grad_vs_plain": round(r["step_ms"] / r["fwd_only_ms"], 3),
         "wall_s": round(r["wall"], 3),

@@ -252,23 +252,40 @@ ssa_status ssa_backward_moments_device(const ssa_model *model, const double *rat
 
 /* Autotuning of the forward launch (the forward of ssa_run_device, Sections 2 and 3.2.1;
  * the search itself is no step of the paper's method) for this model and problem size: every candidate
- * configuration (LDS window bytes 2048 .. 16384, flush by atomics or through wave-private
- * slabs) is timed on the caller's problem (grid [n_grid] device, the same outputs for all:
- * results never depend on the configuration); the fastest is remembered for (device
+ * configuration is timed on the caller's problem (grid [n_grid] device, the same outputs for
+ * all: results never depend on the configuration): first the LDS window bytes 2048 .. 16384
+ * with the windows flushed by atomics or through wave-private slabs, then, with the best
+ * window, the launch form of the specialised kernels (two-wave blocks or generations) and
+ * its block count (the default and smaller grids).  The fastest is remembered for (device
  * architecture, kernel kind, network, G and N rounded up to powers of two) and used by
  * later ssa_run_device / ssa_run calls in this process, and written to the JSON file named
  * by SSA_TUNE_FILE when set (read back at the first lookup of a later process).  result may
- * be NULL.  Synchronous.  win_bytes 0 / slab -1 denote the built-in defaults. */
+ * be NULL.  Synchronous.  win_bytes 0 / slab -1 / form 0 / blocks 0 denote the built-in
+ * choices (form by launch size, grid at the occupancy limit). */
 typedef struct {
     int32_t win_bytes;
     int32_t slab;
-    float best_ms;      /* forward kernel time of the chosen configuration */
-    float default_ms;   /* forward kernel time with the defaults */
+    float best_ms;      /* kernel time of the chosen configuration */
+    float default_ms;   /* kernel time with the built-in choices */
+    int32_t form;       /* ssa_launch_form chosen (0: by launch size) */
+    int32_t blocks;     /* grid size chosen (0: the default) */
 } ssa_tune_result;
 
 ssa_status ssa_autotune_forward(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
                                 const double *grid, int32_t n_grid, uint64_t seed, void *stream,
                                 ssa_tune_result *result);
+
+/* Autotuning of the backward launch (the re-simulation of ssa_backward_device, the
+ * gradient of Section 4's sensitivity; no step of the paper's method itself): the launch
+ * forms of the specialised kernels (two-wave blocks, generations, refilled lanes) at their
+ * default grids and at smaller ones are timed on the caller's problem with unit weights
+ * (results never depend on the choice), and the fastest is remembered per (architecture,
+ * kernel kind, network, G and N rounded up to powers of two) for later ssa_backward_device
+ * / ssa_backward_moments_device calls, and in SSA_TUNE_FILE.  Other kernels keep their
+ * single form.  result may be NULL (win_bytes 0, slab -1).  Synchronous. */
+ssa_status ssa_autotune_backward(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
+                                 const double *grid, int32_t n_grid, uint64_t seed, void *stream,
+                                 ssa_tune_result *result);
 
 /* Forward pass that also returns the likelihood-ratio Jacobian of the grid means with
  * respect to theta_j = ln c_j (every local sensitivity of Section 4's mean trajectories),

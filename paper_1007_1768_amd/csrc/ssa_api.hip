@@ -621,21 +621,25 @@ hipError_t fwd_launch(const FwdKernel &k, bool slab, int64_t blocks, WorkList &w
     return hipLaunchKernel(slab ? k.g_slab : k.g_atomic, dim3((unsigned)blocks), dim3(kBlock), args, k.lds, st);
 }
 
-hipError_t launch_jit(hipFunction_t f, WorkList &wl, int64_t n_items, int dev, hipStream_t st, uint32_t form) {
+// max_blocks > 0 caps the persistent grid (a tuned launch), else the occupancy limit.
+hipError_t launch_jit(hipFunction_t f, WorkList &wl, int64_t n_items, int dev, hipStream_t st, uint32_t form,
+                      int64_t max_blocks = 0) {
     int per_cu = 0;
     hipError_t e = hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, kBlock, 0);
     if (e != hipSuccess) return e;
-    const int64_t blocks = grid_blocks(per_cu, dev, n_items);
+    int64_t blocks = grid_blocks(per_cu, dev, n_items);
+    if (max_blocks > 0) blocks = std::min(blocks, max_blocks);
     note_launch(form, blocks);
     void *args[] = {&wl};
     return hipModuleLaunchKernel(f, (unsigned)blocks, 1, 1, kBlock, 1, 1, 0, st, args, nullptr);
 }
 
 // Two-wave blocks (simulating wave + drawing wave), one work item at a time per block.
-// SSA_DRAW_WAVE_BLOCKS caps the block count (blocks then run several generations each).
+// The block count is at most 8 per CU, or max_blocks (a tuned launch), or
+// SSA_DRAW_WAVE_BLOCKS (tests); blocks then run several generations each.
 hipError_t launch_jit_pc(hipFunction_t f, WorkList &wl, int64_t n_items, int dev, hipStream_t st,
-                         size_t dyn_lds = 0) {
-    int64_t cap = (int64_t)8 * cu_count(dev);
+                         size_t dyn_lds = 0, int64_t max_blocks = 0) {
+    int64_t cap = max_blocks > 0 ? max_blocks : (int64_t)8 * cu_count(dev);
     if (const char *e = std::getenv("SSA_DRAW_WAVE_BLOCKS")) cap = std::max<int64_t>(1, std::strtoll(e, nullptr, 10));
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(n_items, cap));
     note_launch(SSA_FORM_TWO_WAVE, blocks);
@@ -647,6 +651,7 @@ hipError_t launch_jit_pc(hipFunction_t f, WorkList &wl, int64_t n_items, int dev
 // (events, largest step count, flags) at byte 32, the grid description at byte 64.
 constexpr size_t kCtlBytes = 64 + sizeof(GridInfo);
 unsigned long long *ctl_flags(void *ctl) { return (unsigned long long *)((char *)ctl + 48); }
+const unsigned long long *ctl_status(void *ctl) { return (const unsigned long long *)((char *)ctl + 32); }
 
 // Describes a device grid and checks it (a grid that is not non-decreasing inside
 // [0, t_end] refuses the run on the device; see grid_info_kernel).  ctl must be zeroed.
@@ -714,6 +719,10 @@ ssa_status collect_stats(unsigned long long *d_stats, hipStream_t st, hipEvent_t
     if (h[2] & kFlagRefused)
         return fail(SSA_E_INVALID, "refused on the device: the grid is not non-decreasing inside [0, t_end], or a "
                                    "log rate is NaN or above 709 (outputs are NaN)");
+    if (h[2] & kFlagTooManyEvents)
+        return fail(SSA_E_UNSUPPORTED, "%llu events in one run: the exact integer sums hold at most 2^39 "
+                                       "(outputs are NaN); split the trajectories over several calls",
+                    (unsigned long long)h[0]);
     if (h[2] & kFlagOverflow) return fail(SSA_E_OVERFLOW, "a species count left the int32 range");
     if (h[2] & kFlagEventLimit) return fail(SSA_E_EVENT_LIMIT, "a trajectory reached max_events before t_end");
     return SSA_OK;
@@ -801,19 +810,22 @@ hipError_t launch_wave(const ssa_model *m, const WorkList &wl, int dev, hipStrea
 }
 
 // Finalize of one network: exact prefix over the grid and the moments.
+// status: the run's status words (ctl_status), or NULL.
 hipError_t launch_finalize(const unsigned long long *D, const unsigned long long *Dhi, int32_t G, int32_t S,
                            const int32_t *d_x0, int64_t n_traj, double *mean, double *var,
-                           const unsigned long long *flags, hipStream_t st) {
+                           const unsigned long long *status, hipStream_t st) {
     hipLaunchKernelGGL(moment_final_kernel, dim3(S), dim3(1024), 0, st, D, Dhi, G, S, d_x0, n_traj, mean, var,
-                       (int64_t *)nullptr, flags);
+                       (int64_t *)nullptr, status);
     return hipGetLastError();
 }
 
 // Single-network launch of one simulation mode through the kernel specialised to the
 // network, or the generic one (which reads rates in zero-padded slots: a caller's rates
 // array is copied into a padded buffer first).
+// tuned_form / tuned_blocks: a tuned launch of the specialised backward (0: by launch size).
 ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_items, int dev, hipStream_t st,
-                         const double *user_rates, Scratch &scr, bool quad = false) {
+                         const double *user_rates, Scratch &scr, bool quad = false, int32_t tuned_form = 0,
+                         int32_t tuned_blocks = 0) {
     (void)n_items;
     if (m->order == SSA_SUM_BLOCK64) {
         HIP_TRY(mode == kRec   ? launch_wave<kRec>(m, wl, dev, st, scr)
@@ -826,18 +838,25 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
         const bool lat = latency_bound(n_items, dev);
         ssa_status s = get_jit(m, dev, k, lat);
         if (s) return s;
-        // backward: two-wave blocks for launches of up to two work items per CU,
-        // generations up to eight, lanes refilled beyond; the event log: two-wave blocks or
-        // refill; the record always refills
+        // backward: two-wave blocks for launches of up to two work items per CU, else
+        // generations (measured faster than refilling lanes at every size: 32.6 against
+        // 37.2 ms at 10^6 trajectories on a 10^4-point grid, where trajectories differ little
+        // in length and the simpler loop wins); the event log: two-wave blocks or refill; the
+        // record always refills
         uint32_t form = SSA_FORM_REFILL;
-        if (mode == kBwd) form = pc_launch(n_items, dev) ? SSA_FORM_TWO_WAVE : lat ? SSA_FORM_GENERATIONS : form;
+        if (mode == kBwd) form = pc_launch(n_items, dev) ? SSA_FORM_TWO_WAVE : SSA_FORM_GENERATIONS;
         if (mode == kEvt && pc_launch(n_items, dev)) form = SSA_FORM_TWO_WAVE;
+        int64_t max_blocks = 0;
+        if (mode == kBwd && tuned_form >= SSA_FORM_TWO_WAVE && tuned_form <= SSA_FORM_REFILL) {
+            form = (uint32_t)tuned_form;
+            max_blocks = tuned_blocks;
+        }
         const uint32_t forced = forced_form();
         if (forced != SSA_FORM_NONE && mode != kRec && !(mode == kEvt && forced == SSA_FORM_GENERATIONS))
             form = forced;
         if (form == SSA_FORM_TWO_WAVE) {
             HIP_TRY(launch_jit_pc(mode == kEvt ? k->evt_pc : (quad ? k->bwd_var_pc : k->bwd_pc), wl, n_items, dev,
-                                  st));
+                                  st, 0, max_blocks));
             return SSA_OK;
         }
         const bool gen = form == SSA_FORM_GENERATIONS;
@@ -845,7 +864,7 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
                           : mode == kEvt ? k->evt
                           : quad         ? (gen ? k->bwd_var_gen : k->bwd_var)
                                          : (gen ? k->bwd_gen : k->bwd);
-        HIP_TRY(launch_jit(f, wl, n_items, dev, st, form));
+        HIP_TRY(launch_jit(f, wl, n_items, dev, st, form, max_blocks));
         return SSA_OK;
     }
     const int mm = generic_mm(m->M);
@@ -870,15 +889,18 @@ ssa_status launch_single(int mode, const ssa_model *m, WorkList &wl, int64_t n_i
 }
 
 // ---------------------------------------------------------------------------------------
-// Autotuning of the forward launch.  A tuned configuration (window bytes, flush target)
-// is kept per (device architecture, kernel kind, S, M, network source hash, G and N rounded
-// up to powers of two), in memory and, when SSA_TUNE_FILE names a file, in that JSON file
-// (read at the first lookup, rewritten after each tuning).  Every configuration gives the
-// same bits, so tuning only changes speed.
+// Autotuning of the launches.  A tuned configuration (forward: window bytes, flush target;
+// forward and backward: launch form and block count) is kept per (direction, device
+// architecture, kernel kind, S, M, network source hash, G and N rounded up to powers of
+// two), in memory and, when SSA_TUNE_FILE names a file, in that JSON file (read at the
+// first lookup, rewritten after each tuning).  Every configuration gives the same bits, so
+// tuning only changes speed.
 // ---------------------------------------------------------------------------------------
 struct FwdTune {
     int32_t win_bytes = 0;   // 0: default
     int32_t slab = -1;       // -1: default
+    int32_t form = 0;        // ssa_launch_form of the specialised kernels; 0: by launch size
+    int32_t blocks = 0;      // grid size (persistent forms: at most the occupancy limit); 0: default
     float ms = 0.f;
 };
 
@@ -892,11 +914,12 @@ uint64_t next_pow2(uint64_t v) {
     return p;
 }
 
-std::string tune_key(const ssa_model *m, int64_t n_traj, int32_t G, int dev) {
+// Forward keys start with the architecture; backward keys with "bwd|".
+std::string tune_key(const ssa_model *m, int64_t n_traj, int32_t G, int dev, bool backward = false) {
     uint64_t h = 1469598103934665603ull;
     for (unsigned char c : m->jit_src) h = (h ^ c) * 1099511628211ull;
     char buf[256];
-    snprintf(buf, sizeof buf, "%s|%s|S%d|M%d|G%llu|N%llu|h%016llx", device_arch(dev).c_str(),
+    snprintf(buf, sizeof buf, "%s%s|%s|S%d|M%d|G%llu|N%llu|h%016llx", backward ? "bwd|" : "", device_arch(dev).c_str(),
              m->order == SSA_SUM_BLOCK64 ? "wave" : (jit_eligible(m) ? "jit" : "table"), m->S, m->M,
              (unsigned long long)next_pow2((uint64_t)G), (unsigned long long)next_pow2((uint64_t)n_traj),
              (unsigned long long)h);
@@ -904,7 +927,7 @@ std::string tune_key(const ssa_model *m, int64_t n_traj, int32_t G, int dev) {
 }
 
 // The cache file holds one entry per line inside the "entries" object:
-//   "<key>": {"win_bytes": <int>, "slab": <int>, "ms": <float>}
+//   "<key>": {"win_bytes": <int>, "slab": <int>, "form": <int>, "blocks": <int>, "ms": <float>}
 void tune_load_locked() {
     if (g_tune_loaded) return;
     g_tune_loaded = true;
@@ -915,12 +938,15 @@ void tune_load_locked() {
     char line[1024];
     while (std::fgets(line, sizeof line, f)) {
         char key[512];
-        int wb = 0, sl = -1;
+        int wb = 0, sl = -1, fo = 0, bl = 0;
         float ms = 0.f;
-        if (std::sscanf(line, " \"%511[^\"]\": {\"win_bytes\": %d, \"slab\": %d, \"ms\": %f}", key, &wb, &sl, &ms) == 4) {
+        if (std::sscanf(line, " \"%511[^\"]\": {\"win_bytes\": %d, \"slab\": %d, \"form\": %d, \"blocks\": %d, \"ms\": %f}",
+                        key, &wb, &sl, &fo, &bl, &ms) == 6) {
             FwdTune t;
             t.win_bytes = wb;
             t.slab = sl;
+            t.form = fo;
+            t.blocks = bl;
             t.ms = ms;
             g_tune[key] = t;
         }
@@ -934,22 +960,30 @@ void tune_save_locked() {
     const std::string tmp = std::string(path) + ".tmp";
     FILE *f = std::fopen(tmp.c_str(), "w");
     if (!f) return;
-    std::fprintf(f, "{\n  \"format\": \"ssa forward tuning, one entry per line\",\n  \"entries\": {\n");
+    std::fprintf(f, "{\n  \"format\": \"ssa launch tuning, one entry per line\",\n  \"entries\": {\n");
     size_t i = 0;
     for (const auto &kv : g_tune) {
-        std::fprintf(f, "    \"%s\": {\"win_bytes\": %d, \"slab\": %d, \"ms\": %.4f}%s\n", kv.first.c_str(),
-                     kv.second.win_bytes, kv.second.slab, kv.second.ms, ++i < g_tune.size() ? "," : "");
+        std::fprintf(f, "    \"%s\": {\"win_bytes\": %d, \"slab\": %d, \"form\": %d, \"blocks\": %d, \"ms\": %.4f}%s\n",
+                     kv.first.c_str(), kv.second.win_bytes, kv.second.slab, kv.second.form, kv.second.blocks,
+                     kv.second.ms, ++i < g_tune.size() ? "," : "");
     }
     std::fprintf(f, "  }\n}\n");
     std::fclose(f);
     std::rename(tmp.c_str(), path);
 }
 
-FwdTune tune_lookup(const ssa_model *m, int64_t n_traj, int32_t G, int dev) {
+FwdTune tune_lookup(const ssa_model *m, int64_t n_traj, int32_t G, int dev, bool backward = false) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_locked();
-    auto it = g_tune.find(tune_key(m, n_traj, G, dev));
+    auto it = g_tune.find(tune_key(m, n_traj, G, dev, backward));
     return it == g_tune.end() ? FwdTune() : it->second;
+}
+
+void tune_store(const ssa_model *m, int64_t n_traj, int32_t G, int dev, bool backward, const FwdTune &t) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_load_locked();
+    g_tune[tune_key(m, n_traj, G, dev, backward)] = t;
+    tune_save_locked();
 }
 
 // Forward launch of one network.  D receives the [G][S][2] difference sums, by atomic
@@ -992,16 +1026,18 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
         k.f_slab = hist ? jk->fwd_slab_hist : jk->fwd;
         k.f_atomic = hist ? jk->fwd_hist : jk->fwd_atomic;
         k.lds = win_bytes;
-        const uint32_t forced = forced_form();
-        const bool two_wave = forced == SSA_FORM_TWO_WAVE ||
-                              (forced != SSA_FORM_GENERATIONS && forced != SSA_FORM_REFILL && pc_launch(n_items, dev));
+        // the launch form: SSA_LAUNCH_FORM, else a tuned one, else by launch size
+        uint32_t want = forced_form();
+        if (want == SSA_FORM_NONE && (tune.form == SSA_FORM_TWO_WAVE || tune.form == SSA_FORM_GENERATIONS))
+            want = (uint32_t)tune.form;
+        const bool two_wave = want == SSA_FORM_TWO_WAVE || (want == SSA_FORM_NONE && pc_launch(n_items, dev));
         if (two_wave) {
             // one simulating wave per block: one window, flushed atomically into D
             HIP_TRY(launch_zero(D, (size_t)G * S * 2 * sizeof(unsigned long long), st));
             EventPair ev;
             if (kernel_ms && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
             HIP_TRY(launch_jit_pc(hist ? jk->fwd_hist_pc : jk->fwd_pc, wl, n_items, dev, st,
-                                  (size_t)wl.win_words * sizeof(long long)));
+                                  (size_t)wl.win_words * sizeof(long long), tune.blocks));
             if (kernel_ms && ev.b) {
                 HIP_TRY(hipEventRecord(ev.b, st));
                 HIP_TRY(hipEventSynchronize(ev.b));
@@ -1041,6 +1077,7 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
         wl.slabs = (unsigned long long *)sl;
     } else {
         HIP_TRY(fwd_blocks(k, false, dev, n_items, blocks));
+        if (tune.blocks > 0) blocks = std::min<int64_t>(blocks, tune.blocks);
         HIP_TRY(launch_zero(D, cell_words * sizeof(unsigned long long), st));
     }
     EventPair ev;
@@ -1311,7 +1348,7 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, const double
     if (fixed) cfg.slab = 0;
     s = launch_forward(m, wl, n_items, dev, st, rates, scr, n.D, (stats && !fixed) ? &kms : nullptr, cfg, !fixed);
     if (s) return s;
-    HIP_TRY(launch_finalize(n.D, n.Dhi, G, m->S, m->d_x0, n_traj, mean, var, ctl_flags(ctl), st));
+    HIP_TRY(launch_finalize(n.D, n.Dhi, G, m->S, m->d_x0, n_traj, mean, var, ctl_status(ctl), st));
     if (hist) {
         const int32_t xv = m->x0[hist->species];
         const int32_t ib = xv < hist->lo ? 0 : std::min((xv - hist->lo) / hist->width, hist->nbins - 1);
@@ -1405,21 +1442,50 @@ ssa_status ssa_autotune_forward(const ssa_model *m, const double *rates, int64_t
             best = cand[c];
         }
     }
+    // then, with the best window, the launch form of the specialised kernels (two-wave blocks
+    // at their default count and at 2 and 4 per CU; generations at the occupancy limit and at
+    // 1/2 and 1/4 of it); the table-driven and 64-chunk kernels have one form
+    if (status == SSA_OK && m->order == SSA_SUM_SEQ && jit_eligible(m)) {
+        const int64_t n_items = (n_traj + kChunk - 1) / kChunk;
+        const FwdTune win = best;
+        for (int32_t form : {(int32_t)SSA_FORM_TWO_WAVE, (int32_t)SSA_FORM_GENERATIONS}) {
+            int64_t b0 = 0;
+            for (int k2 : {1, 2, 4}) {
+                FwdTune c = win;
+                c.form = form;
+                c.blocks = k2 == 1 ? 0
+                                   : (form == SSA_FORM_TWO_WAVE ? k2 * cu_count(dev)
+                                                                : (int32_t)std::max<int64_t>(1, b0 / k2));
+                if (k2 > 1 && !(c.blocks < b0 && c.blocks < n_items)) continue;
+                if (form == SSA_FORM_TWO_WAVE && (c.slab == 1)) c.slab = 0;   // two-wave blocks flush atomically
+                float ms = 0.f;
+                for (int rep = 0; rep < 2 && status == SSA_OK; ++rep) {
+                    ssa_stats stt;
+                    status = run_device_impl(m, rates, nullptr, n_traj, t_end, grid, G, seed, 0, mean, var, nullptr,
+                                             nullptr, stream, &stt, &c);
+                    ms = rep ? std::min(ms, stt.kernel_ms) : stt.kernel_ms;
+                    if (k2 == 1) b0 = stt.blocks;
+                }
+                if (status) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = c;
+                }
+            }
+        }
+    }
     (void)hipFreeAsync(mean, st);
     (void)hipFreeAsync(var, st);
     if (status) return status;
     best.ms = best_ms;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        tune_load_locked();
-        g_tune[tune_key(m, n_traj, G, dev)] = best;
-        tune_save_locked();
-    }
+    tune_store(m, n_traj, G, dev, false, best);
     if (result) {
         result->win_bytes = best.win_bytes;
         result->slab = best.slab;
         result->best_ms = best_ms;
         result->default_ms = default_ms;
+        result->form = best.form;
+        result->blocks = best.blocks;
     }
     return SSA_OK;
 }
@@ -1498,7 +1564,7 @@ ssa_status ssa_run_jacobian_device(const ssa_model *m, const double *rates, cons
                                       nullptr));
     }
     if (stats && ev.b) HIP_TRY(hipEventRecord(ev.b, st));
-    HIP_TRY(launch_finalize(n.D, n.Dhi, G, m->S, m->d_x0, n_traj, mean, var, ctl_flags(ctl), st));
+    HIP_TRY(launch_finalize(n.D, n.Dhi, G, m->S, m->d_x0, n_traj, mean, var, ctl_status(ctl), st));
     {
         const int64_t jc = (int64_t)cells * m->M;
         hipLaunchKernelGGL(jacobian_final_kernel, dim3((unsigned)((jc + 255) / 256)), dim3(256), 0, st,
@@ -1576,8 +1642,7 @@ ssa_status ssa_run_cov_device(const ssa_model *m, const double *rates, int64_t n
     HIP_TRY(hipGetLastError());
     const int64_t cells = (int64_t)G * S * S;
     hipLaunchKernelGGL(cov_final_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st,
-                       (const int64_t *)sx, (const i128s *)sxx, G, S, n_traj, mean, cov,
-                       (const unsigned long long *)ctl_flags(ctl));
+                       (const int64_t *)sx, (const i128s *)sxx, G, S, n_traj, mean, cov, ctl_status(ctl));
     HIP_TRY(hipGetLastError());
     if (stats) return collect_stats(wl.stats, st, ev.a, ev.b, stats);
     return SSA_OK;
@@ -1650,10 +1715,13 @@ ssa_status ssa_backward_device(const ssa_model *m, const double *rates, const do
                                        nullptr, grad, stream, stats);
 }
 
-ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, const double *log_rates,
-                                       int64_t n_traj, double t_end, const double *grid, int32_t G, uint64_t seed,
-                                       uint64_t max_events, const double *w, const double *mhat, const double *wv,
-                                       const double *vhat, double *grad, void *stream, ssa_stats *stats) {
+namespace {
+
+// The backward with a given launch configuration (tune == nullptr: the cached tuned one).
+ssa_status backward_impl(const ssa_model *m, const double *rates, const double *log_rates, int64_t n_traj,
+                         double t_end, const double *grid, int32_t G, uint64_t seed, uint64_t max_events,
+                         const double *w, const double *mhat, const double *wv, const double *vhat, double *grad,
+                         void *stream, ssa_stats *stats, const FwdTune *tune) {
     if (!m) return fail(SSA_E_INVALID, "model is NULL");
     if (n_traj <= 0 || G <= 0 || !grid || !w || !mhat || !grad) return fail(SSA_E_INVALID, "bad argument");
     if ((wv == nullptr) != (vhat == nullptr)) return fail(SSA_E_INVALID, "wv and vhat go together");
@@ -1702,7 +1770,8 @@ ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, 
     wl.stats = (unsigned long long *)((char *)ctl + 32);
     EventPair ev;
     if (stats && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
-    s = launch_single(kBwd, m, wl, n_items, dev, st, rates, scr, quad);
+    const FwdTune cfg = tune ? *tune : tune_lookup(m, n_traj, G, dev, true);
+    s = launch_single(kBwd, m, wl, n_items, dev, st, rates, scr, quad, cfg.form, cfg.blocks);
     if (s) return s;
     if (stats && ev.b) HIP_TRY(hipEventRecord(ev.b, st));
     // fixed-order pairwise reduction of the per-trajectory rows
@@ -1722,6 +1791,91 @@ ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, 
                        1.0 / (double)n_traj, grad, (const unsigned long long *)ctl_flags(ctl));
     HIP_TRY(hipGetLastError());
     if (stats) return collect_stats(wl.stats, st, ev.a, ev.b, stats);
+    return SSA_OK;
+}
+
+}  // namespace
+
+ssa_status ssa_backward_moments_device(const ssa_model *m, const double *rates, const double *log_rates,
+                                       int64_t n_traj, double t_end, const double *grid, int32_t G, uint64_t seed,
+                                       uint64_t max_events, const double *w, const double *mhat, const double *wv,
+                                       const double *vhat, double *grad, void *stream, ssa_stats *stats) {
+    return backward_impl(m, rates, log_rates, n_traj, t_end, grid, G, seed, max_events, w, mhat, wv, vhat, grad,
+                         stream, stats, nullptr);
+}
+
+ssa_status ssa_autotune_backward(const ssa_model *m, const double *rates, int64_t n_traj, double t_end,
+                                 const double *grid, int32_t G, uint64_t seed, void *stream, ssa_tune_result *result) {
+    if (!m || !grid || G <= 0 || n_traj <= 0) return fail(SSA_E_INVALID, "bad argument");
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    hipStream_t st = (hipStream_t)stream;
+    const size_t cells = (size_t)G * m->S;
+    double *w = nullptr, *mhat = nullptr, *grad = nullptr;
+    HIP_TRY(hipMallocAsync((void **)&w, sizeof(double) * cells, st));
+    HIP_TRY(hipMallocAsync((void **)&mhat, sizeof(double) * cells, st));
+    HIP_TRY(hipMallocAsync((void **)&grad, sizeof(double) * (size_t)m->M, st));
+    double one = 1.0;
+    unsigned long long one_bits = 0;
+    std::memcpy(&one_bits, &one, sizeof one_bits);
+    HIP_TRY(launch_fill(w, cells, one_bits, st));      // weights and centring: any values time the same work
+    HIP_TRY(launch_zero(mhat, sizeof(double) * cells, st));
+    ssa_status status = SSA_OK;
+    // time one configuration: best of two runs after one warm-up
+    auto time_cfg = [&](const FwdTune &c, float &ms, ssa_stats &last) {
+        ms = 0.f;
+        for (int rep = 0; rep < 3 && status == SSA_OK; ++rep) {
+            status = backward_impl(m, rates, nullptr, n_traj, t_end, grid, G, seed, 0, w, mhat, nullptr, nullptr, grad,
+                                   stream, &last, &c);
+            if (rep == 1) ms = last.kernel_ms;
+            if (rep == 2) ms = std::min(ms, last.kernel_ms);
+        }
+    };
+    FwdTune base;
+    float default_ms = 0.f;
+    ssa_stats s0;
+    time_cfg(base, default_ms, s0);
+    FwdTune best = base;
+    float best_ms = default_ms;
+    // candidates (specialised kernels only): each form at its default grid and at 1/2 and
+    // 1/4 of it (the persistent forms), or at 2 and 4 blocks per CU (two-wave blocks)
+    auto consider = [&](const FwdTune &c, ssa_stats &sx) {
+        float ms = 0.f;
+        time_cfg(c, ms, sx);
+        if (status == SSA_OK && ms < best_ms) {
+            best_ms = ms;
+            best = c;
+        }
+    };
+    if (status == SSA_OK && m->order == SSA_SUM_SEQ && jit_eligible(m)) {
+        const int64_t n_items = (n_traj + kChunk - 1) / kChunk;
+        for (int32_t form : {(int32_t)SSA_FORM_TWO_WAVE, (int32_t)SSA_FORM_GENERATIONS, (int32_t)SSA_FORM_REFILL}) {
+            FwdTune c;
+            c.form = form;
+            ssa_stats sx;
+            consider(c, sx);
+            const int64_t b0 = sx.blocks;
+            for (int k2 : {2, 4}) {
+                if (status) break;
+                c.blocks = form == SSA_FORM_TWO_WAVE ? k2 * cu_count(dev) : (int32_t)std::max<int64_t>(1, b0 / k2);
+                if (c.blocks < b0 && c.blocks < n_items) consider(c, sx);
+            }
+        }
+    }
+    (void)hipFreeAsync(w, st);
+    (void)hipFreeAsync(mhat, st);
+    (void)hipFreeAsync(grad, st);
+    if (status) return status;
+    best.ms = best_ms;
+    tune_store(m, n_traj, G, dev, true, best);
+    if (result) {
+        result->win_bytes = 0;
+        result->slab = -1;
+        result->best_ms = best_ms;
+        result->default_ms = default_ms;
+        result->form = best.form;
+        result->blocks = best.blocks;
+    }
     return SSA_OK;
 }
 
@@ -2002,6 +2156,9 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
         tot_events += h[0];
         max_steps = std::max(max_steps, h[1]);
         all_flags |= (uint32_t)h[2];
+        if (tot_events >= kMaxExactEvents)
+            return fail(SSA_E_UNSUPPORTED, "%llu events in one run: the exact integer sums hold at most 2^39",
+                        (unsigned long long)tot_events);
 
         // time order and the distinct-time ranks of this epoch's records (the first R of
         // the sorted slots)
@@ -2394,6 +2551,8 @@ ssa_status ssa_batch_autotune(ssa_batch *bt, void *stream, ssa_tune_result *resu
         result->win_bytes = bt->win_bytes;
         result->slab = -1;
         result->best_ms = best_ms;
+        result->form = 0;
+        result->blocks = 0;
         result->default_ms = default_ms;
     }
     return SSA_OK;

@@ -236,6 +236,24 @@ __device__ __forceinline__ bool refused(const unsigned long long *flags) {
     return flags && (*(const volatile unsigned long long *)flags & kFlagRefused);
 }
 
+// The exact integer sums hold every event's change of x and its low part of (2x + nu) nu
+// (below 2^24) in int64 words and running prefixes, exact up to 2^39 events per run; a run
+// with more events is refused at its finalize (NaN moments, this bit in the status word).
+constexpr uint32_t kFlagTooManyEvents = 16u;
+constexpr unsigned long long kMaxExactEvents = 1ull << 39;
+
+// status: the run's words (events, largest step count, flags).  True when the finalize must
+// write NaN: the run was refused, or it applied too many events for exact sums (flagged here).
+__device__ __forceinline__ bool finalize_refused(const unsigned long long *status) {
+    if (!status) return false;
+    if (refused(status + 2)) return true;
+    if (*(const volatile unsigned long long *)status >= kMaxExactEvents) {
+        if (threadIdx.x == 0 && blockIdx.x == 0) atomicOr((unsigned long long *)status + 2, (unsigned long long)kFlagTooManyEvents);
+        return true;
+    }
+    return false;
+}
+
 __device__ __forceinline__ void refuse(unsigned int *counter, unsigned long long *flags) {
     atomicOr(flags, (unsigned long long)kFlagRefused);
     atomicMax(counter, kRefusedItem);
@@ -491,8 +509,8 @@ __global__ void __launch_bounds__(1024) moment_final_kernel(const unsigned long 
                                                             int32_t S, const int32_t *__restrict__ x0,
                                                             int64_t n_traj, double *__restrict__ mean,
                                                             double *__restrict__ var, int64_t *__restrict__ sums,
-                                                            const unsigned long long *__restrict__ flags) {
-    if (refused(flags)) {
+                                                            const unsigned long long *__restrict__ status) {
+    if (finalize_refused(status)) {
         const int32_t s = blockIdx.x;
         for (int32_t g = threadIdx.x; g < G; g += blockDim.x) {
             mean[(size_t)g * S + s] = __builtin_nan("");
@@ -714,12 +732,12 @@ __global__ void __launch_bounds__(1024) cov_prefix_kernel(const unsigned long lo
 //   cov = fl(N sxx - sx_s sx_r) / (N (N - 1)),  0 when N == 1; mean[g][s] from sx.
 __global__ void cov_final_kernel(const int64_t *__restrict__ sx, const i128s *__restrict__ sxx, int32_t G, int32_t S,
                                  int64_t n_traj, double *__restrict__ mean, double *__restrict__ cov,
-                                 const unsigned long long *__restrict__ flags) {
+                                 const unsigned long long *__restrict__ status) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)G * S * S) return;
     const int32_t r = (int32_t)(idx % S), s = (int32_t)((idx / S) % S);
     const int64_t g = idx / ((int64_t)S * S);
-    if (refused(flags)) {
+    if (finalize_refused(status)) {
         if (s == r) mean[g * S + s] = __builtin_nan("");
         cov[idx] = __builtin_nan("");
         return;

@@ -21,7 +21,8 @@ _NAMES = {1: "SSA_E_INVALID", 2: "SSA_E_NOMEM", 3: "SSA_E_DEVICE", 4: "SSA_E_OVE
 EXPORTS = ["ssa_model_create", "ssa_model_create_laws", "ssa_model_destroy", "ssa_run", "ssa_rates_from_log",
            "ssa_run_device", "ssa_run_device_static",
            "ssa_backward_device", "ssa_backward_moments_device",
-           "ssa_run_jacobian_device", "ssa_jacobian_vjp", "ssa_autotune_forward", "ssa_run_cov_device",
+           "ssa_run_jacobian_device", "ssa_jacobian_vjp", "ssa_autotune_forward", "ssa_autotune_backward",
+           "ssa_run_cov_device",
            "ssa_hist_quantiles", "ssa_adaptive_device",
            "ssa_record", "ssa_batch_create", "ssa_batch_run", "ssa_batch_autotune", "ssa_batch_destroy",
            "ssa_last_error"]
@@ -75,6 +76,7 @@ def load(path=None):
     L.ssa_backward_device.argtypes = [vp, vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
     L.ssa_backward_moments_device.argtypes = [vp, vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp, vp]
     L.ssa_autotune_forward.argtypes = [vp, vp, i64, dbl, vp, i32, u64, vp, vp]
+    L.ssa_autotune_backward.argtypes = [vp, vp, i64, dbl, vp, i32, u64, vp, vp]
     L.ssa_run_cov_device.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp]
     L.ssa_hist_quantiles.argtypes = [vp, i32, vp, i64, vp, i32, vp, vp]
     L.ssa_adaptive_device.argtypes = [vp, vp, i64, dbl, u64, u64, i64, vp, vp, vp, i64, vp, vp, vp, i64, vp, vp, vp]
@@ -246,7 +248,11 @@ def backward_device(model, n_traj, t_end, grid, seed, w, mhat, rates=None, max_e
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("win_bytes", ctypes.c_int32), ("slab", ctypes.c_int32), ("best_ms", ctypes.c_float),
-                ("default_ms", ctypes.c_float)]
+                ("default_ms", ctypes.c_float), ("form", ctypes.c_int32), ("blocks", ctypes.c_int32)]
+
+    def as_dict(self):
+        return dict(win_bytes=self.win_bytes, slab=self.slab, best_ms=self.best_ms, default_ms=self.default_ms,
+                    form=FORMS.get(int(self.form), str(self.form)), blocks=int(self.blocks))
 
 
 def autotune_forward(model, n_traj, t_end, grid, seed, rates=None, stream=None):
@@ -255,7 +261,16 @@ def autotune_forward(model, n_traj, t_end, grid, seed, rates=None, stream=None):
     r = TuneResult()
     _check(load().ssa_autotune_forward(model.handle, _tp(rates), int(n_traj), float(t_end), _tp(grid), grid.shape[0],
                                        int(seed), _stream(stream), ctypes.byref(r)))
-    return dict(win_bytes=r.win_bytes, slab=r.slab, best_ms=r.best_ms, default_ms=r.default_ms)
+    return r.as_dict()
+
+
+def autotune_backward(model, n_traj, t_end, grid, seed, rates=None, stream=None):
+    """Time the backward launch forms and grids on this problem and keep the fastest
+    (ssa_autotune_backward); returns the chosen form, grid and the two kernel times."""
+    r = TuneResult()
+    _check(load().ssa_autotune_backward(model.handle, _tp(rates), int(n_traj), float(t_end), _tp(grid),
+                                        grid.shape[0], int(seed), _stream(stream), ctypes.byref(r)))
+    return r.as_dict()
 
 
 def run_jacobian_device(model, n_traj, t_end, grid, seed, rates=None, max_events=0, stream=None,

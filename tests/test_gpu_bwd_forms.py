@@ -2,16 +2,17 @@
 
 The specialised backward runs in one of three forms, chosen by the launch size: blocks of
 a simulating and a drawing wave (up to two work items of 64 trajectories per CU), persistent
-blocks that refill a wave by generations (up to eight per CU), and persistent blocks that
-refill each lane as its trajectory ends (beyond; the form the large workload's gradient
-runs).  Every form must give the oracle's gradient within 1e-12 of its L1 scale, with mean
+blocks that refill a wave by generations (beyond: the form the large workload's gradient
+runs), and persistent blocks that refill each lane as its trajectory ends (by request or a
+tuned launch).  Every form must give the oracle's gradient within 1e-12 of its L1 scale, with mean
 weights and with mean and variance weights, and the call must report the form it ran.
 
 * forced forms (SSA_LAUNCH_FORM) at small sizes: a ragged count on a fine grid, grid points
   at, just below and duplicated on event times, and a network whose trajectories reach an
   absorbing state long before t_end;
-* the default form at the large workload's grid (10^4 points, t_end 50) with more than
-  2048 work items, so that the launch refills lanes exactly as the large workload's does.
+* the persistent forms (generations, the default beyond two-wave launches and the large
+  workload's own; refilled lanes) at the large workload's grid (10^4 points, t_end 50) with
+  more than 2048 work items.
 """
 import os
 
@@ -100,42 +101,48 @@ def test_backward_form_matches_oracle(ssa, form, case):
 
 
 # The large workload's network, horizon and grid with just over 2048 work items: the
-# default launch refills lanes (the large workload's own gradient form).
-N_REFILL, T_REFILL, G_REFILL, SEED_REFILL = 135000, 50.0, 10000, 55
+# persistent forms at the large workload's grid (generations by default, refilled lanes when
+# asked for), against the oracle's gradients computed once.
+N_BIG, T_BIG, G_BIG, SEED_BIG = 135000, 50.0, 10000, 55
 
 
 @pytest.fixture(scope="module")
-def refill_ref():
+def big_ref():
     m = inputs.viral()
-    grid = inputs.uniform_grid(T_REFILL, G_REFILL)
-    st, ref = orc.run(m, N_REFILL, T_REFILL, grid, SEED_REFILL)
+    grid = inputs.uniform_grid(T_BIG, G_BIG)
+    st, ref = orc.run(m, N_BIG, T_BIG, grid, SEED_BIG)
     assert st == 0
-    rng = np.random.default_rng(SEED_REFILL)
+    rng = np.random.default_rng(SEED_BIG)
     w = rng.normal(size=ref["mean"].shape)
     wv = rng.normal(size=ref["mean"].shape) / (1.0 + ref["var"])
-    return m, grid, ref, w, wv
+    grads = {}
+    st, grads["mean"], l1m = orc.grad(m, N_BIG, T_BIG, grid, SEED_BIG, w, ref["mean"])
+    assert st == 0
+    st, grads["mean_and_variance"], l1q = orc.grad(m, N_BIG, T_BIG, grid, SEED_BIG, w, ref["mean"], wv=wv,
+                                                   vhat=ref["var"])
+    assert st == 0
+    return m, grid, ref, w, wv, grads, {"mean": l1m, "mean_and_variance": l1q}
 
 
 @pytest.mark.parametrize("weights", ["mean", "mean_and_variance"])
-def test_refill_backward_at_large_grid(ssa, refill_ref, weights):
-    m, grid, ref, w, wv = refill_ref
-    assert os.environ.get("SSA_LAUNCH_FORM") is None
+@pytest.mark.parametrize("asked", [None, "refill"])
+def test_persistent_backward_at_large_grid(ssa, big_ref, monkeypatch, weights, asked):
+    m, grid, ref, w, wv, grads, l1 = big_ref
+    if asked:
+        monkeypatch.setenv("SSA_LAUNCH_FORM", asked)
+    else:
+        monkeypatch.delenv("SSA_LAUNCH_FORM", raising=False)
     model = ssa.Model.from_dict(m)
     gd = _t(grid)
-    print("refill backward N %d G %d weights %s" % (N_REFILL, G_REFILL, weights), flush=True)
-    mean, var, _, sf = ssa.run_device(model, N_REFILL, T_REFILL, gd, SEED_REFILL, with_stats=True)
+    print("persistent backward N %d G %d weights %s form %s" % (N_BIG, G_BIG, weights, asked), flush=True)
+    mean, var, _, sf = ssa.run_device(model, N_BIG, T_BIG, gd, SEED_BIG, with_stats=True)
     quad = weights == "mean_and_variance"
-    g, sb = ssa.backward_device(model, N_REFILL, T_REFILL, gd, SEED_REFILL, _t(w), _t(ref["mean"]),
+    g, sb = ssa.backward_device(model, N_BIG, T_BIG, gd, SEED_BIG, _t(w), _t(ref["mean"]),
                                 wv=_t(wv) if quad else None, vhat=_t(ref["var"]) if quad else None,
                                 with_stats=True)
     torch.cuda.synchronize()
     model.close()
-    assert sb["form"] == "refill", sb
+    assert sb["form"] == (asked or "generations"), sb
     assert sb["events"] == ref["events"] == sf["events"]
     assert np.array_equal(mean.cpu().numpy(), ref["mean"]) and np.array_equal(var.cpu().numpy(), ref["var"])
-    if quad:
-        st, gref, l1 = orc.grad(m, N_REFILL, T_REFILL, grid, SEED_REFILL, w, ref["mean"], wv=wv, vhat=ref["var"])
-    else:
-        st, gref, l1 = orc.grad(m, N_REFILL, T_REFILL, grid, SEED_REFILL, w, ref["mean"])
-    assert st == 0
-    assert np.all(np.abs(g.cpu().numpy() - gref) <= 1e-12 * l1), (g.cpu().numpy(), gref, l1)
+    assert np.all(np.abs(g.cpu().numpy() - grads[weights]) <= 1e-12 * l1[weights]), (g.cpu().numpy(), grads[weights])
