@@ -276,6 +276,36 @@ def hiv_stress(ssa, torch, dev, N=16384, t_end=5.0, G=101, seed=7, reps=2):
             "events_per_s": round(best["events"] / best["kernel_ms"] * 1e3, 1)}
 
 
+def hiv_long(ssa, torch, dev, N=2048, t_end=4000.0, G=101, seed=7, epoch_days=40.0):
+    """The HIV network of Table 1 over the paper's horizon of 4000 days (about 1.5e8 events per
+    trajectory), taken in epochs of simulation time (ssa_run_begin / advance / finish); one
+    progress line per epoch; mean and variance on a 101-point grid at the end."""
+    m = inputs.hiv()
+    model = ssa.Model.from_dict(m)
+    grid = inputs.uniform_grid(t_end, G)
+    run = ssa.Run(model, N, t_end, grid, seed)
+    t, events, kms = 0.0, 0, 0.0
+    a0 = time.perf_counter()
+    while t < t_end:
+        t = min(t_end, t + epoch_days)
+        st = run.advance(t)
+        events += st["events"]
+        kms += st["kernel_ms"]
+        print(json.dumps({"hiv_long_epoch_to_day": t, "events": events, "kernel_ms": round(kms, 1),
+                          "max_steps": st["max_steps"], "wall_s": round(time.perf_counter() - a0, 1)}), flush=True)
+    mean, var, _, st = run.finish()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - a0
+    run.close()
+    model.close()
+    mv = mean.cpu().numpy()
+    return {"workload": "hiv: %d trajectories, t_end %g days, %d-point grid, epochs of %g days"
+                        % (N, t_end, G, epoch_days),
+            "events": st["events"], "max_steps": st["max_steps"], "kernel_ms": round(st["kernel_ms"], 1),
+            "wall_s": round(wall, 1), "events_per_s": round(st["events"] / (st["kernel_ms"] * 1e-3), 1),
+            "mean_at_end": [round(float(v), 3) for v in mv[-1]]}
+
+
 def workload(name):
     w = dict(inputs.WORKLOADS[name])
     m = w["model"]()
@@ -455,6 +485,8 @@ def main():
                     help="only time the adaptive selective memory at 10^6 trajectories (epochs) and print it")
     ap.add_argument("--hiv", action="store_true",
                     help="only run the HIV network stress case (forward) and print it")
+    ap.add_argument("--hiv-long", action="store_true",
+                    help="only run the HIV network over 4000 days (2048 trajectories, epochs of 40 days) and print it")
     ap.add_argument("--autotune", action="store_true",
                     help="only run the forward and backward autotuners on the viral, differentiated and large "
                          "workloads and print what they chose")
@@ -486,6 +518,9 @@ def main():
         return
     if args.hiv:
         print(json.dumps({"hiv": hiv_stress(ssa, torch, dev)}), flush=True)
+        return
+    if args.hiv_long:
+        print(json.dumps({"hiv_long": hiv_long(ssa, torch, dev)}), flush=True)
         return
     if args.adaptive:
         print(json.dumps({"adaptive": adaptive_measure(ssa, torch, dev)}), flush=True)

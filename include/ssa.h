@@ -218,6 +218,34 @@ ssa_status ssa_run_device_static(const ssa_model *model, const double *rates, co
                                  uint64_t seed, uint64_t max_events, double *mean, double *var,
                                  const ssa_hist_spec *hist, uint32_t *d_hist, void *stream, ssa_stats *stats);
 
+/* A run taken in epochs of simulation time, for horizons too long for one launch (Section
+ * 4's HIV runs cover 4000 simulated days, about 1.5e8 events per trajectory): the same
+ * trajectories, alignment and reduction as ssa_run_device, with the same results bit for
+ * bit, but the caller advances the run to successive times and may act (report progress,
+ * stop) in between.  Each advance simulates every trajectory up to its last event at or
+ * before t_until and saves its state; the next one resumes from there with the draw the
+ * trajectory did not use.  The specialised kernels only (sequential order, M <= 32, S <= 64;
+ * SSA_E_UNSUPPORTED otherwise).
+ *   ssa_run_begin: grid [n_grid] host (checked as in ssa_run), rates [M] host or NULL (the
+ *     model's), hist as in ssa_run_device or NULL.  The handle owns its device memory
+ *     (about 2 x (4 S + 24) bytes per trajectory plus the grid sums).
+ *   ssa_run_advance: up to min(t_until, t_end) (a time at or before the last one does
+ *     nothing); synchronous; stats (may be NULL) receive this advance's events (those
+ *     applied in it), largest step count so far, flags and kernel time.  Errors as
+ *     ssa_run_device; a run past 2^39 events gets SSA_E_UNSUPPORTED.
+ *   ssa_run_finish: after the run reached t_end, mean, var [G*S] and d_hist [G*nbins] (iff
+ *     the run has a histogram) device outputs; stats receive the run's totals.
+ *     SSA_E_INVALID before t_end.
+ *   ssa_run_destroy: releases the handle (NULL is ignored). */
+typedef struct ssa_run_state ssa_run_state;
+ssa_status ssa_run_begin(const ssa_model *model, const double *rates, int64_t n_traj, double t_end,
+                         const double *grid, int32_t n_grid, uint64_t seed, uint64_t max_events,
+                         const ssa_hist_spec *hist, ssa_run_state **out);
+ssa_status ssa_run_advance(ssa_run_state *run, double t_until, void *stream, ssa_stats *stats);
+ssa_status ssa_run_finish(ssa_run_state *run, double *mean, double *var, uint32_t *d_hist, void *stream,
+                          ssa_stats *stats);
+void ssa_run_destroy(ssa_run_state *run);
+
 /* Likelihood-ratio gradient of a loss L(mean) with respect to theta_j = ln c_j (the local
  * form of Section 4's sensitivity analysis of the mean trajectories), by re-simulating the
  * same trajectories (same seed, same Philox counters):

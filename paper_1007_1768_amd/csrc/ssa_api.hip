@@ -270,6 +270,31 @@ struct ssa_batch {
     LaunchRec launch;                 // form and grid of the captured simulation launch
 };
 
+// A run taken in epochs of simulation time (ssa_run_begin / advance / finish): the device
+// copies of the grid and rates, the exact sums so far, the trajectories' saved states
+// (double-buffered: read one, write the other) and the host totals.
+struct ssa_run_state {
+    const ssa_model *m = nullptr;
+    int device = 0;
+    int64_t n_traj = 0;
+    double t_end = 0.0, t_done = 0.0;
+    int32_t G = 0;
+    uint64_t seed = 0, max_events = 0;
+    bool has_hist = false, started = false;
+    ssa_hist_spec hist{};
+    double *d_grid = nullptr, *d_rates = nullptr;
+    unsigned long long *D = nullptr, *Dhi = nullptr;
+    int32_t *Hd = nullptr;
+    void *ctl = nullptr;
+    int32_t *sx[2] = {nullptr, nullptr};
+    double *st[2] = {nullptr, nullptr};
+    uint64_t *sk[2] = {nullptr, nullptr}, *sev[2] = {nullptr, nullptr};
+    int cur = -1;                      // buffer holding the saved states (-1: none yet)
+    unsigned long long events = 0, max_steps = 0;
+    uint32_t flags = 0;
+    float kernel_ms = 0.f;
+};
+
 namespace {
 
 // FNV-1a over the embedded kernel sources.  Stamped into every generated program so a
@@ -991,10 +1016,15 @@ void tune_store(const ssa_model *m, int64_t n_traj, int32_t G, int dev, bool bac
 // (see want_slabs).  Dhi ([G][S], high parts) must be zero on entry.
 // may_compile false: the specialised kernels only if this device has them compiled already
 // (else the table-driven kernel, with the same results; networks with rate laws then fail).
+// epoch: one epoch of a resumable run (the generations form of the specialised kernels,
+// which saves and resumes trajectory states; D keeps the earlier epochs' sums).
 ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int dev, hipStream_t st,
                           const double *user_rates, Scratch &scr, unsigned long long *D, float *kernel_ms,
-                          const FwdTune &tune, bool may_compile = true) {
+                          const FwdTune &tune, bool may_compile = true, bool epoch = false) {
     const int32_t G = wl.net0.G, S = m->S;
+    if (epoch && (m->order != SSA_SUM_SEQ || !jit_eligible(m)))
+        return fail(SSA_E_UNSUPPORTED, "runs in epochs need the specialised kernels (sequential order, at most %d "
+                                       "reactions and %d species)", kJitMaxReactions, kJitMaxSpecies);
     const bool use_jit = jit_eligible(m) && (may_compile || jit_cached(m, dev, latency_bound(n_items, dev)));
     if (m->has_laws && !use_jit)
         return fail(SSA_E_UNSUPPORTED, "a network with rate laws needs its specialised kernels compiled on this "
@@ -1030,6 +1060,7 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
         uint32_t want = forced_form();
         if (want == SSA_FORM_NONE && (tune.form == SSA_FORM_TWO_WAVE || tune.form == SSA_FORM_GENERATIONS))
             want = (uint32_t)tune.form;
+        if (epoch) want = SSA_FORM_GENERATIONS;
         const bool two_wave = want == SSA_FORM_TWO_WAVE || (want == SSA_FORM_NONE && pc_launch(n_items, dev));
         if (two_wave) {
             // one simulating wave per block: one window, flushed atomically into D
@@ -1069,7 +1100,7 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
     int64_t blocks = 0;
     HIP_TRY(fwd_blocks(k, true, dev, n_items, blocks));
     const size_t slab_bytes = (size_t)blocks * (kBlock / kWave) * cell_words * sizeof(unsigned long long);
-    const bool slab = want_slabs(slab_bytes, tune.slab);
+    const bool slab = !epoch && want_slabs(slab_bytes, tune.slab);
     if (slab) {
         void *sl = nullptr;
         HIP_TRY(scr.alloc(&sl, slab_bytes));
@@ -1078,7 +1109,7 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
     } else {
         HIP_TRY(fwd_blocks(k, false, dev, n_items, blocks));
         if (tune.blocks > 0) blocks = std::min<int64_t>(blocks, tune.blocks);
-        HIP_TRY(launch_zero(D, cell_words * sizeof(unsigned long long), st));
+        if (!epoch) HIP_TRY(launch_zero(D, cell_words * sizeof(unsigned long long), st));
     }
     EventPair ev;
     if (kernel_ms && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
@@ -1400,6 +1431,184 @@ ssa_status ssa_run_device_static(const ssa_model *m, const double *rates, const 
     FixedScratch area(base, kStaticScratchBytes);
     return run_device_impl(m, rates, log_rates, n_traj, t_end, grid, G, seed, max_events, mean, var, hist, d_hist,
                            stream, stats, nullptr, &area);
+}
+
+void ssa_run_destroy(ssa_run_state *r) {
+    if (!r) return;
+    for (void *p : {(void *)r->d_grid, (void *)r->d_rates, (void *)r->D, (void *)r->Dhi, (void *)r->Hd, r->ctl,
+                    (void *)r->sx[0], (void *)r->sx[1], (void *)r->st[0], (void *)r->st[1], (void *)r->sk[0],
+                    (void *)r->sk[1], (void *)r->sev[0], (void *)r->sev[1]})
+        if (p) (void)hipFree(p);
+    delete r;
+}
+
+ssa_status ssa_run_begin(const ssa_model *m, const double *rates, int64_t n_traj, double t_end, const double *grid,
+                         int32_t G, uint64_t seed, uint64_t max_events, const ssa_hist_spec *hist, ssa_run_state **out) {
+    if (!out) return fail(SSA_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!m) return fail(SSA_E_INVALID, "model is NULL");
+    if (n_traj <= 0 || n_traj > max_traj(m)) return fail(SSA_E_INVALID, "n_traj must be in 1 .. %lld", (long long)max_traj(m));
+    ssa_status s = validate_grid_host(grid, G, t_end);
+    if (s) return s;
+    if (hist && (hist->species < 0 || hist->species >= m->S || hist->width <= 0 || hist->nbins <= 0 ||
+                 hist->nbins > 4096))
+        return fail(SSA_E_INVALID, "bad histogram spec");
+    if (rates)
+        for (int32_t j = 0; j < m->M; ++j)
+            if (!(rates[j] >= 0.0) || !std::isfinite(rates[j])) return fail(SSA_E_INVALID, "rates[%d] invalid", j);
+    if (m->order != SSA_SUM_SEQ || !jit_eligible(m))
+        return fail(SSA_E_UNSUPPORTED, "runs in epochs need the specialised kernels (sequential order, at most %d "
+                                       "reactions and %d species)", kJitMaxReactions, kJitMaxSpecies);
+    auto *r = new (std::nothrow) ssa_run_state;
+    if (!r) return fail(SSA_E_NOMEM, "host allocation failed");
+    r->m = m;
+    r->n_traj = n_traj;
+    r->t_end = t_end;
+    r->G = G;
+    r->seed = seed;
+    r->max_events = max_events;
+    r->has_hist = hist != nullptr;
+    if (hist) r->hist = *hist;
+    auto bad = [&](hipError_t e) {
+        ssa_run_destroy(r);
+        return fail(e == hipErrorOutOfMemory ? SSA_E_NOMEM : SSA_E_DEVICE, "%s", hipGetErrorString(e));
+    };
+    hipError_t e = hipGetDevice(&r->device);
+    const size_t cells = (size_t)G * m->S;
+    if (e == hipSuccess) e = hipMalloc(&r->d_grid, sizeof(double) * G);
+    if (e == hipSuccess) e = hipMemcpy(r->d_grid, grid, sizeof(double) * G, hipMemcpyHostToDevice);
+    if (e == hipSuccess && rates) e = hipMalloc(&r->d_rates, sizeof(double) * m->M);
+    if (e == hipSuccess && rates) e = hipMemcpy(r->d_rates, rates, sizeof(double) * m->M, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&r->D, sizeof(unsigned long long) * 2 * cells);
+    if (e == hipSuccess) e = hipMalloc(&r->Dhi, sizeof(unsigned long long) * cells);
+    if (e == hipSuccess && hist) e = hipMalloc(&r->Hd, sizeof(int32_t) * (size_t)G * hist->nbins);
+    if (e == hipSuccess) e = hipMalloc(&r->ctl, kCtlBytes);
+    for (int b = 0; b < 2 && e == hipSuccess; ++b) {
+        e = hipMalloc(&r->sx[b], sizeof(int32_t) * (size_t)n_traj * m->S);
+        if (e == hipSuccess) e = hipMalloc(&r->st[b], sizeof(double) * (size_t)n_traj);
+        if (e == hipSuccess) e = hipMalloc(&r->sk[b], sizeof(uint64_t) * (size_t)n_traj);
+        if (e == hipSuccess) e = hipMalloc(&r->sev[b], sizeof(uint64_t) * (size_t)n_traj);
+    }
+    if (e == hipSuccess) e = hipMemset(r->D, 0, sizeof(unsigned long long) * 2 * cells);
+    if (e == hipSuccess) e = hipMemset(r->Dhi, 0, sizeof(unsigned long long) * cells);
+    if (e == hipSuccess && hist) e = hipMemset(r->Hd, 0, sizeof(int32_t) * (size_t)G * hist->nbins);
+    if (e == hipSuccess) {
+        const GridInfo gi = host_grid_info(grid, G, t_end);
+        e = hipMemcpy((char *)r->ctl + 64, &gi, sizeof gi, hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return bad(e);
+    *out = r;
+    return SSA_OK;
+}
+
+ssa_status ssa_run_advance(ssa_run_state *r, double t_until, void *stream, ssa_stats *stats) {
+    if (!r) return fail(SSA_E_INVALID, "run is NULL");
+    if (std::isnan(t_until)) return fail(SSA_E_INVALID, "t_until is NaN");
+    const double t1 = std::min(t_until, r->t_end);
+    if (r->started && !(t1 > r->t_done)) {
+        if (stats) std::memset(stats, 0, sizeof *stats);
+        return SSA_OK;
+    }
+    const ssa_model *m = r->m;
+    hipStream_t st = (hipStream_t)stream;
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != r->device) return fail(SSA_E_INVALID, "the run was begun on device %d", r->device);
+    StreamScratch scr(st);
+    HIP_TRY(launch_zero(r->ctl, 64, st));
+    NetDev n = base_net(m, r->d_rates, r->n_traj, r->t_end, r->d_grid, r->G, r->seed, r->max_events);
+    n.ginfo = (const GridInfo *)((char *)r->ctl + 64);
+    n.D = r->D;
+    n.Dhi = r->Dhi;
+    if (r->has_hist) {
+        n.Hd = r->Hd;
+        n.nb_hist = r->hist.nbins;
+        n.h_species = r->hist.species;
+        n.h_lo = r->hist.lo;
+        n.h_width = r->hist.width;
+    }
+    const int wb = r->cur < 0 ? 0 : 1 - r->cur;
+    if (r->cur >= 0) {
+        n.rs_x = r->sx[r->cur];
+        n.rs_t = r->st[r->cur];
+        n.rs_k = r->sk[r->cur];
+        n.rs_ev = r->sev[r->cur];
+    }
+    n.ws_x = r->sx[wb];
+    n.ws_t = r->st[wb];
+    n.ws_k = r->sk[wb];
+    n.ws_ev = r->sev[wb];
+    n.t_pause = t1;
+    WorkList wl;
+    std::memset(&wl, 0, sizeof wl);
+    wl.net0 = n;
+    wl.range_begin = 0;
+    wl.range_end = r->n_traj;
+    const int64_t n_items = (r->n_traj + kChunk - 1) / kChunk;
+    wl.n_items = (int32_t)n_items;
+    wl.counter = (unsigned int *)r->ctl;
+    wl.stats = (unsigned long long *)((char *)r->ctl + 32);
+    FwdTune cfg = tune_lookup(m, r->n_traj, r->G, dev);
+    cfg.slab = 0;
+    float kms = 0.f;
+    ssa_status s = launch_forward(m, wl, n_items, dev, st, r->d_rates, scr, r->D, &kms, cfg, true, true);
+    if (s) return s;
+    unsigned long long h[3] = {0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(h, wl.stats, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    r->cur = wb;
+    r->started = true;
+    r->t_done = t1;
+    r->events += h[0];
+    r->max_steps = std::max(r->max_steps, h[1]);
+    r->flags |= (uint32_t)h[2];
+    r->kernel_ms += kms;
+    if (stats) {
+        stats->events = h[0];
+        stats->max_steps = h[1];
+        stats->flags = (uint32_t)h[2];
+        stats->kernel_ms = kms;
+        stats->form = g_launch.form;
+        stats->blocks = g_launch.blocks;
+    }
+    if (h[2] & kFlagOverflow) return fail(SSA_E_OVERFLOW, "a species count left the int32 range");
+    if (h[2] & kFlagEventLimit) return fail(SSA_E_EVENT_LIMIT, "a trajectory reached max_events before t_end");
+    if (r->events >= kMaxExactEvents)
+        return fail(SSA_E_UNSUPPORTED, "%llu events in one run: the exact integer sums hold at most 2^39",
+                    (unsigned long long)r->events);
+    return SSA_OK;
+}
+
+ssa_status ssa_run_finish(ssa_run_state *r, double *mean, double *var, uint32_t *d_hist, void *stream,
+                          ssa_stats *stats) {
+    if (!r || !mean || !var) return fail(SSA_E_INVALID, "NULL argument");
+    if (r->has_hist != (d_hist != nullptr)) return fail(SSA_E_INVALID, "the histogram buffer goes with the run's spec");
+    if (!r->started || r->t_done < r->t_end)
+        return fail(SSA_E_INVALID, "the run has reached t = %g of %g: advance it to t_end first", r->t_done, r->t_end);
+    if (r->events >= kMaxExactEvents || (r->flags & (kFlagOverflow | kFlagEventLimit)))
+        return fail(SSA_E_UNSUPPORTED, "the run did not complete with exact sums");
+    hipStream_t st = (hipStream_t)stream;
+    // the finalize reads the run's totals from the status words
+    const unsigned long long tot[3] = {r->events, r->max_steps, 0ull};
+    HIP_TRY(hipMemcpyAsync((char *)r->ctl + 32, tot, sizeof tot, hipMemcpyHostToDevice, st));
+    HIP_TRY(launch_finalize(r->D, r->Dhi, r->G, r->m->S, r->m->d_x0, r->n_traj, mean, var, ctl_status(r->ctl), st));
+    if (r->has_hist) {
+        const int32_t xv = r->m->x0[r->hist.species];
+        const int32_t ib = xv < r->hist.lo ? 0 : std::min((xv - r->hist.lo) / r->hist.width, r->hist.nbins - 1);
+        hipLaunchKernelGGL(hist_prefix_kernel, dim3(r->hist.nbins), dim3(1024), 0, st, (const int32_t *)r->Hd, r->G,
+                           r->hist.nbins, ib, r->n_traj, d_hist, (const unsigned long long *)ctl_flags(r->ctl));
+        HIP_TRY(hipGetLastError());
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    if (stats) {
+        stats->events = r->events;
+        stats->max_steps = r->max_steps;
+        stats->flags = r->flags;
+        stats->kernel_ms = r->kernel_ms;
+        stats->form = SSA_FORM_GENERATIONS;
+        stats->blocks = 0;
+    }
+    return SSA_OK;
 }
 
 ssa_status ssa_autotune_forward(const ssa_model *m, const double *rates, int64_t n_traj, double t_end,

@@ -1121,10 +1121,24 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
         const int64_t traj = begin + lane;
         double t = 0.0, t_next = 0.0, u = 0.0;
         double tg_next = gv.uniform ? 0.0 : ((const SSA_CONST double *)gv.grid)[0];
-        uint64_t k = 0, ev = 0;
+        uint64_t k = 0, ev = 0, ev_start = 0;
         int32_t g = 0, binp = G;
         uint32_t ovf = 0;
         if (active) p.reset(n0);
+        // a run in epochs of simulation time resumes every trajectory from its saved state
+        // (its next draw is the Philox block it did not use; the window follows its lanes
+        // from wherever they are)
+        if (!PC && active && n0.rs_t) {
+            const double ts = n0.rs_t[traj];
+            if (ts < 0.0) {
+                active = false;                 // ended in an earlier epoch
+            } else {
+                t = ts;
+                k = n0.rs_k[traj];
+                ev = ev_start = n0.rs_ev[traj];
+                p.load_state(n0.rs_x + (size_t)traj * S);
+            }
+        }
 
         // draw the event after t from the exponential variate En and the uniform r2n; a lane
         // whose state is absorbing, whose event lies beyond t_end or that reached the event
@@ -1146,13 +1160,24 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
             const bool absorb = acc == 0.0;                 // no draw: the state holds to t_end
             t_next = t + En / acc;
             const bool beyond = !absorb && t_next > n.t_end; // drawn, not applied
-            const bool limit = !absorb && !beyond && ev >= n.max_events;
+            // epochs: an event beyond the epoch's end waits for the next epoch
+            const bool pause = !PC && n.ws_t != nullptr && !absorb && !beyond && t_next > n.t_pause;
+            const bool limit = !absorb && !beyond && !pause && ev >= n.max_events;
             k = absorb ? k : k + 1;
             flags |= limit ? (uint32_t)kFlagEventLimit : 0u;
             u = r2n * acc;
-            const bool go = !(absorb || beyond || limit);
-            tot_events += go ? 0ull : (unsigned long long)ev;
+            const bool go = !(absorb || beyond || limit || pause);
+            tot_events += go ? 0ull : (unsigned long long)(ev - ev_start);
             max_steps = go ? max_steps : max(max_steps, (unsigned long long)ev);
+            if (!PC && !go && n.ws_t) {
+                // save the state for the next epoch: time -1 once the trajectory has ended;
+                // a paused lane redraws the block of the event it did not apply
+                int32_t *wx = n.ws_x + (size_t)traj * S;
+                p.for_each_species([&](int32_t s2, int32_t xs) { wx[s2] = xs; });
+                n.ws_t[traj] = pause ? t : -1.0;
+                n.ws_k[traj] = pause ? k - 1 : k;
+                n.ws_ev[traj] = ev;
+            }
             active = go;
         };
         // the grid bin of the drawn event
@@ -1170,7 +1195,7 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
         };
         if (active) {
             const NetDev n = current_net<BATCH>(wl, cur);
-            prepare(n, 0);
+            prepare(n, k);
             draw(n, E_pre, r2_pre);
             place();
             if (!PC) prepare(n, k);

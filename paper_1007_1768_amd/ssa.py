@@ -19,7 +19,8 @@ _NAMES = {1: "SSA_E_INVALID", 2: "SSA_E_NOMEM", 3: "SSA_E_DEVICE", 4: "SSA_E_OVE
           5: "SSA_E_EVENT_LIMIT", 6: "SSA_E_UNSUPPORTED"}
 
 EXPORTS = ["ssa_model_create", "ssa_model_create_laws", "ssa_model_destroy", "ssa_run", "ssa_rates_from_log",
-           "ssa_run_device", "ssa_run_device_static",
+           "ssa_run_device", "ssa_run_device_static", "ssa_run_begin", "ssa_run_advance", "ssa_run_finish",
+           "ssa_run_destroy",
            "ssa_backward_device", "ssa_backward_moments_device",
            "ssa_run_jacobian_device", "ssa_jacobian_vjp", "ssa_autotune_forward", "ssa_autotune_backward",
            "ssa_run_cov_device",
@@ -73,6 +74,11 @@ def load(path=None):
     L.ssa_rates_from_log.argtypes = [vp, i32, vp, vp]
     L.ssa_run_device.argtypes = [vp, vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
     L.ssa_run_device_static.argtypes = [vp, vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp]
+    L.ssa_run_begin.argtypes = [vp, vp, i64, dbl, vp, i32, u64, u64, vp, ctypes.POINTER(vp)]
+    L.ssa_run_advance.argtypes = [vp, dbl, vp, vp]
+    L.ssa_run_finish.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.ssa_run_destroy.argtypes = [vp]
+    L.ssa_run_destroy.restype = None
     L.ssa_backward_device.argtypes = [vp, vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp]
     L.ssa_backward_moments_device.argtypes = [vp, vp, vp, i64, dbl, vp, i32, u64, u64, vp, vp, vp, vp, vp, vp, vp]
     L.ssa_autotune_forward.argtypes = [vp, vp, i64, dbl, vp, i32, u64, vp, vp]
@@ -91,7 +97,7 @@ def load(path=None):
     L.ssa_last_error.argtypes = []
     L.ssa_last_error.restype = ctypes.c_char_p
     for f in EXPORTS:
-        if f not in ("ssa_model_destroy", "ssa_batch_destroy", "ssa_last_error"):
+        if f not in ("ssa_model_destroy", "ssa_batch_destroy", "ssa_run_destroy", "ssa_last_error"):
             getattr(L, f).restype = ctypes.c_int
     _lib = L
     return L
@@ -244,6 +250,49 @@ def backward_device(model, n_traj, t_end, grid, seed, w, mhat, rates=None, max_e
                                              _tp(grad), _stream(stream),
                                              ctypes.byref(st) if st is not None else None))
     return grad, (st.as_dict() if st is not None else None)
+
+
+class Run:
+    """A run taken in epochs of simulation time (ssa_run_begin / advance / finish): the same
+    results as run_device, with the caller advancing it to successive times."""
+
+    def __init__(self, model, n_traj, t_end, grid, seed, rates=None, hist=None, max_events=0):
+        self.model = model
+        self.grid = np.ascontiguousarray(grid, dtype=np.float64)
+        self.hist = hist
+        r = None if rates is None else np.ascontiguousarray(rates, dtype=np.float64)
+        spec = HistSpec(*[int(v) for v in hist]) if hist is not None else None
+        h = ctypes.c_void_p()
+        _check(load().ssa_run_begin(model.handle, _p(r), int(n_traj), float(t_end), _p(self.grid), self.grid.shape[0],
+                                    int(seed), int(max_events), ctypes.byref(spec) if spec is not None else None,
+                                    ctypes.byref(h)))
+        self.handle = h
+
+    def advance(self, t_until, stream=None):
+        st = Stats()
+        _check(load().ssa_run_advance(self.handle, float(t_until), _stream(stream), ctypes.byref(st)))
+        return st.as_dict()
+
+    def finish(self, device="cuda:0", stream=None):
+        import torch
+        G, S = self.grid.shape[0], self.model.S
+        mean = torch.empty((G, S), dtype=torch.float64, device=device)
+        var = torch.empty_like(mean)
+        h = torch.empty((G, self.hist[3]), dtype=torch.int32, device=device) if self.hist is not None else None
+        st = Stats()
+        _check(load().ssa_run_finish(self.handle, _tp(mean), _tp(var), _tp(h), _stream(stream), ctypes.byref(st)))
+        return mean, var, h, st.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            load().ssa_run_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class TuneResult(ctypes.Structure):

@@ -1,0 +1,105 @@
+"""GPU checks of runs taken in epochs of simulation time (ssa_run_begin / advance / finish).
+
+A run advanced to successive times must give ssa_run_device's results bit for bit (mean,
+variance, histogram, event count) and the oracle's: every trajectory pauses before its first
+event beyond the epoch's end and resumes with the draw it did not use.  Cases: epochs at
+arbitrary times (with repeated and backward times, which do nothing), an epoch ending
+exactly at an event time (the event belongs to that epoch), the HIV network of Table 1 with
+its rate laws, and the errors (finishing early, unsupported models).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1007_1768_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def ssa():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1007_1768_amd import ssa as s
+    s.load()
+    return s
+
+
+def _epochs_vs_single(ssa, m, N, t_end, grid, seed, times, hist=None):
+    model = ssa.Model.from_dict(m)
+    print("epochs N %d t_end %g G %d times %s" % (N, t_end, grid.shape[0], times), flush=True)
+    run = ssa.Run(model, N, t_end, grid, seed, hist=hist)
+    events = 0
+    for t in times:
+        events += run.advance(t)["events"]
+    mean, var, h, st = run.finish()
+    run.close()
+    m1, v1, h1, s1 = ssa.run_device(model, N, t_end, torch.tensor(grid, device=DEV), seed, hist=hist,
+                                    with_stats=True)
+    torch.cuda.synchronize()
+    model.close()
+    assert st["events"] == events == s1["events"], (st, events, s1)
+    assert torch.equal(mean, m1) and torch.equal(var, v1)
+    if hist is not None:
+        assert torch.equal(h, h1)
+    return mean, var, h, st
+
+
+def test_epochs_equal_single_run_and_oracle(ssa):
+    m = inputs.viral()
+    N, t_end, G, seed = 3000, 20.0, 200, 17
+    grid = inputs.uniform_grid(t_end, G)
+    hist = (1, 0, 1, 16)
+    mean, var, h, st = _epochs_vs_single(ssa, m, N, t_end, grid, seed, [3.3, 3.3, 2.0, 7.77, 12.0, 25.0], hist)
+    s, ref = orc.run(m, N, t_end, grid, seed, hist=hist)
+    assert s == 0 and ref["events"] == st["events"]
+    assert np.array_equal(mean.cpu().numpy(), ref["mean"]) and np.array_equal(var.cpu().numpy(), ref["var"])
+    assert np.array_equal(h.cpu().numpy().astype(np.int64), ref["hist"].astype(np.int64))
+
+
+def test_epoch_ending_at_an_event_time(ssa):
+    m = inputs.viral()
+    t_end = 4.0
+    s, r = orc.trajectory(m, 5, 0, 2.0, np.array([2.0]))
+    assert s == 0
+    tl = float(r["t_last"])                      # an event of trajectory 0 happens exactly then
+    grid = np.array(sorted([0.0, np.nextafter(tl, 0.0), tl, 3.0, t_end]))
+    _epochs_vs_single(ssa, m, 300, t_end, grid, 5, [tl, np.nextafter(tl, np.inf), t_end])
+
+
+def test_epochs_hiv_network(ssa):
+    m = inputs.hiv()
+    N, t_end, G, seed = 128, 1.0, 21, 7
+    grid = inputs.uniform_grid(t_end, G)
+    mean, var, _, st = _epochs_vs_single(ssa, m, N, t_end, grid, seed, [0.1, 0.35, 0.6, 1.0])
+    s, ref = orc.run(m, N, t_end, grid, seed)
+    assert s == 0 and ref["events"] == st["events"]
+    assert np.array_equal(mean.cpu().numpy(), ref["mean"]) and np.array_equal(var.cpu().numpy(), ref["var"])
+
+
+def test_epoch_errors(ssa):
+    m = inputs.viral()
+    model = ssa.Model.from_dict(m)
+    grid = inputs.uniform_grid(5.0, 11)
+    run = ssa.Run(model, 100, 5.0, grid, 1)
+    run.advance(2.0)
+    with pytest.raises(ssa.SSAError) as e:
+        run.finish()
+    assert e.value.status == ssa.E_INVALID
+    with pytest.raises(ssa.SSAError) as e:
+        run.advance(float("nan"))
+    assert e.value.status == ssa.E_INVALID
+    run.close()
+    with pytest.raises(ssa.SSAError) as e:
+        ssa.Run(model, 100, 5.0, grid[::-1].copy(), 1)
+    assert e.value.status == ssa.E_INVALID
+    model.close()
+    b = dict(inputs.viral())
+    b["sum_order"] = "block64"
+    mb = ssa.Model.from_dict(b)
+    with pytest.raises(ssa.SSAError) as e:
+        ssa.Run(mb, 100, 5.0, grid, 1)
+    assert e.value.status == ssa.E_UNSUPPORTED
+    mb.close()
