@@ -43,6 +43,19 @@
  *     the given hipStream_t (NULL = the null stream) unless stats is non-NULL, in which case
  *     the call waits for the stream and fills stats.
  *   - Layouts are row-major: [G*S] means index g*S + s.
+ *   - Graph capture: ssa_run_device, ssa_run_device_static, ssa_backward_device,
+ *     ssa_backward_moments_device, ssa_run_jacobian_device, ssa_run_cov_device,
+ *     ssa_rates_from_log and ssa_jacobian_vjp may be called on a stream that is being
+ *     captured into a HIP graph (hipStreamBeginCapture, torch.cuda.graph), and the graph
+ *     replayed any number of times with the results of the same call made directly.  Under
+ *     capture a call (1) takes no statistics (stats must be NULL, else SSA_E_INVALID);
+ *     (2) compiles nothing: the network's specialised kernels of that launch size must exist
+ *     from an earlier call on the device (else SSA_E_INVALID); (3) allocates its scratch with
+ *     hipMalloc, this thread's capture mode relaxed for the call, and hands it to the model,
+ *     which keeps it until ssa_model_destroy: replay graphs only while their model lives, and
+ *     expect each capture to hold its scratch until then.  A refused call returns before its
+ *     first stream operation, so the capture stays usable.  Replays of one graph on two
+ *     streams at once share that scratch and race.
  */
 #ifndef SSA_H
 #define SSA_H
@@ -151,7 +164,8 @@ typedef struct {
 ssa_status ssa_model_create_laws(int32_t n_species, int32_t n_reactions, const int32_t *reactants,
                                  const int32_t *products, const double *rates, const int32_t *x0,
                                  int32_t sum_order, const ssa_rate_law *laws, ssa_model **out);
-/* Releases a model handle and its device copies (NULL is ignored). */
+/* Releases a model handle, its device copies and the scratch of every call captured into a
+ * graph with it (NULL is ignored). */
 void ssa_model_destroy(ssa_model *model);
 
 /* Host convenience (synchronous).  Section 2: n_traj independent Gillespie trajectories

@@ -112,6 +112,16 @@ struct FixedScratch : Scratch {
     }
 };
 
+// Scratch of a call made while its stream is captured into a graph: each piece is a
+// hipMalloc of its own (taken with this thread's capture mode relaxed, since the caller may
+// capture in global mode), which the model keeps until ssa_model_destroy, so that every
+// replay of the graph finds its scratch in place and allocates nothing.
+struct CaptureScratch : Scratch {
+    const ssa_model *m;
+    explicit CaptureScratch(const ssa_model *model);
+    hipError_t alloc(void **p, size_t bytes) override;
+};
+
 std::mutex g_static_mu;
 void *g_static_ptr[64] = {};
 
@@ -202,7 +212,7 @@ struct JitKernels {
                   fwd_cov = nullptr,
                   rec = nullptr, bwd = nullptr, bwd_var = nullptr, evt = nullptr, bwd_gen = nullptr,
                   bwd_var_gen = nullptr, bwd_pc = nullptr, bwd_var_pc = nullptr, fwd_pc = nullptr,
-                  fwd_hist_pc = nullptr, evt_pc = nullptr;
+                  fwd_hist_pc = nullptr, evt_pc = nullptr, fwd_epoch = nullptr, fwd_hist_epoch = nullptr;
 };
 
 std::mutex g_jit_mu;
@@ -238,7 +248,27 @@ struct ssa_model {
     std::string jit_src;              // generated network description for specialisation
     bool has_laws = false;            // some rate constant depends on a species (ssa_rate_law)
     std::vector<ssa_rate_law> laws;   // [M] when has_laws
+    mutable std::mutex cap_mu;
+    mutable std::vector<void *> cap_mem;   // scratch of calls captured into graphs (freed with the model)
 };
+
+namespace {
+
+CaptureScratch::CaptureScratch(const ssa_model *model) : m(model) {}
+
+hipError_t CaptureScratch::alloc(void **p, size_t bytes) {
+    hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+    hipError_t e = hipThreadExchangeStreamCaptureMode(&mode);
+    if (e != hipSuccess) return e;
+    e = hipMalloc(p, std::max<size_t>(bytes, 256));
+    (void)hipThreadExchangeStreamCaptureMode(&mode);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(m->cap_mu);
+    m->cap_mem.push_back(*p);
+    return hipSuccess;
+}
+
+}  // namespace
 
 struct ssa_batch {
     int32_t B = 0, device = 0, s_rows = 0, m_rows = 0, mm = 0;
@@ -481,6 +511,8 @@ ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out
     HIP_TRY(hipModuleGetFunction(&k->bwd_var_pc, k->module, "ssa_jit_bwd_var_pc"));
     HIP_TRY(hipModuleGetFunction(&k->fwd_pc, k->module, "ssa_jit_fwd_pc"));
     HIP_TRY(hipModuleGetFunction(&k->fwd_hist_pc, k->module, "ssa_jit_fwd_hist_pc"));
+    HIP_TRY(hipModuleGetFunction(&k->fwd_epoch, k->module, "ssa_jit_fwd_epoch"));
+    HIP_TRY(hipModuleGetFunction(&k->fwd_hist_epoch, k->module, "ssa_jit_fwd_hist_epoch"));
     HIP_TRY(hipModuleGetFunction(&k->evt_pc, k->module, "ssa_jit_evt_pc"));
     std::lock_guard<std::mutex> lk(g_jit_mu);
     auto ins = g_jit_cache.emplace(key, k);
@@ -491,6 +523,28 @@ ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out
 bool jit_eligible(const ssa_model *m) {
     // networks with rate laws exist only in specialised form
     return (m->has_laws || !prefer_generic()) && m->M <= kJitMaxReactions && m->S <= kJitMaxSpecies;
+}
+
+// Whether the caller's stream is being captured into a graph.  A captured call takes its
+// scratch from CaptureScratch, compiles nothing (specialised: the call runs the network's
+// specialised kernels, whose form ilp must exist from an earlier call on this device) and
+// synchronises nothing (no statistics); every check comes before the call's first stream
+// operation, so a refused call leaves the capture as it was.
+ssa_status capture_check(const ssa_model *m, hipStream_t st, int dev, const ssa_stats *stats, bool specialised,
+                         bool ilp, bool *capturing) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    const hipError_t e = hipStreamIsCapturing(st, &cs);
+    if (e != hipSuccess) return fail(SSA_E_DEVICE, "hipStreamIsCapturing: %s", hipGetErrorString(e));
+    if (cs == hipStreamCaptureStatusInvalidated) return fail(SSA_E_INVALID, "the stream's capture is invalidated");
+    *capturing = cs == hipStreamCaptureStatusActive;
+    if (!*capturing) return SSA_OK;
+    if (stats)
+        return fail(SSA_E_INVALID, "statistics are read back with a synchronisation: pass none while the stream is "
+                                   "captured");
+    if (specialised && !jit_cached(m, dev, ilp))
+        return fail(SSA_E_INVALID, "the network's kernels are compiled by its first call on a device: make one "
+                                   "call of the same size before capturing");
+    return SSA_OK;
 }
 
 ssa_status validate_grid_host(const double *grid, int32_t G, double t_end) {
@@ -1054,7 +1108,7 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
         k.jit = true;
         const bool hist = wl.net0.Hd != nullptr;
         k.f_slab = hist ? jk->fwd_slab_hist : jk->fwd;
-        k.f_atomic = hist ? jk->fwd_hist : jk->fwd_atomic;
+        k.f_atomic = epoch ? (hist ? jk->fwd_hist_epoch : jk->fwd_epoch) : hist ? jk->fwd_hist : jk->fwd_atomic;
         k.lds = win_bytes;
         // the launch form: SSA_LAUNCH_FORM, else a tuned one, else by launch size
         uint32_t want = forced_form();
@@ -1293,6 +1347,7 @@ void ssa_model_destroy(ssa_model *m) {
     if (m->d_dep) (void)hipFree(m->d_dep);
     if (m->d_dep_rate) (void)hipFree(m->d_dep_rate);
     if (m->d_dep_ptr) (void)hipFree(m->d_dep_ptr);
+    for (void *p : m->cap_mem) (void)hipFree(p);
     delete m;
 }
 
@@ -1336,9 +1391,15 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, const double
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    if (!fixed) keep_pool(dev);
+    const int64_t n_items = (n_traj + kChunk - 1) / kChunk;
+    bool cap = false;
+    ssa_status s = capture_check(m, st, dev, stats, m->order == SSA_SUM_SEQ && jit_eligible(m),
+                                 latency_bound(n_items, dev), &cap);
+    if (s) return s;
+    if (!fixed && !cap) keep_pool(dev);
     StreamScratch pooled(st);
-    Scratch &scr = fixed ? *fixed : (Scratch &)pooled;
+    CaptureScratch kept(m);
+    Scratch &scr = fixed ? *fixed : cap ? (Scratch &)kept : (Scratch &)pooled;
 
     const size_t cells = (size_t)G * m->S;
     const size_t H_bytes = hist ? sizeof(int32_t) * (size_t)G * hist->nbins : 0;
@@ -1350,7 +1411,7 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, const double
     HIP_TRY(launch_zero(Dhi, sizeof(unsigned long long) * cells, st));
     HIP_TRY(launch_zero(ctl, 64, st));
     if (hist) HIP_TRY(launch_zero(Hd, H_bytes, st));
-    ssa_status s = run_rates(m, rates, log_rates, ctl, scr, st, &rates);
+    s = run_rates(m, rates, log_rates, ctl, scr, st, &rates);
     if (s) return s;
     NetDev n = base_net(m, rates, n_traj, t_end, grid, G, seed, max_events);
     n.ginfo = (const GridInfo *)((char *)ctl + 64);
@@ -1369,7 +1430,6 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, const double
     wl.net0 = n;
     wl.range_begin = 0;
     wl.range_end = n_traj;
-    const int64_t n_items = (n_traj + kChunk - 1) / kChunk;
     wl.n_items = (int32_t)n_items;
     wl.counter = (unsigned int *)ctl;
     wl.stats = (unsigned long long *)((char *)ctl + 32);
@@ -1377,7 +1437,8 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, const double
     float kms = 0.f;
     FwdTune cfg = tune ? *tune : (fixed ? FwdTune() : tune_lookup(m, n_traj, G, dev));
     if (fixed) cfg.slab = 0;
-    s = launch_forward(m, wl, n_items, dev, st, rates, scr, n.D, (stats && !fixed) ? &kms : nullptr, cfg, !fixed);
+    s = launch_forward(m, wl, n_items, dev, st, rates, scr, n.D, (stats && !fixed) ? &kms : nullptr, cfg,
+                       !fixed && !cap);
     if (s) return s;
     HIP_TRY(launch_finalize(n.D, n.Dhi, G, m->S, m->d_x0, n_traj, mean, var, ctl_status(ctl), st));
     if (hist) {
@@ -1723,10 +1784,15 @@ ssa_status ssa_run_jacobian_device(const ssa_model *m, const double *rates, cons
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    keep_pool(dev);
-    StreamScratch scr(st);
+    bool cap = false;
+    ssa_status s = capture_check(m, st, dev, stats, true, false, &cap);
+    if (s) return s;
+    if (!cap) keep_pool(dev);
+    StreamScratch pooled(st);
+    CaptureScratch kept(m);
+    Scratch &scr = cap ? (Scratch &)kept : (Scratch &)pooled;
     std::shared_ptr<JitKernels> jk;
-    ssa_status s = get_jit(m, dev, jk);
+    s = get_jit(m, dev, jk);
     if (s) return s;
 
     const size_t cells = (size_t)G * m->S;
@@ -1799,10 +1865,15 @@ ssa_status ssa_run_cov_device(const ssa_model *m, const double *rates, int64_t n
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    keep_pool(dev);
-    StreamScratch scr(st);
+    bool cap = false;
+    ssa_status s = capture_check(m, st, dev, stats, true, false, &cap);
+    if (s) return s;
+    if (!cap) keep_pool(dev);
+    StreamScratch pooled(st);
+    CaptureScratch kept(m);
+    Scratch &scr = cap ? (Scratch &)kept : (Scratch &)pooled;
     std::shared_ptr<JitKernels> jk;
-    ssa_status s = get_jit(m, dev, jk);
+    s = get_jit(m, dev, jk);
     if (s) return s;
     const int32_t S = m->S, npairs = S * (S - 1) / 2;
     const size_t row = (size_t)2 * S + npairs, hrow = (size_t)S + npairs;
@@ -1944,8 +2015,15 @@ ssa_status backward_impl(const ssa_model *m, const double *rates, const double *
     hipStream_t st = (hipStream_t)stream;
     int dev = 0;
     HIP_TRY(hipGetDevice(&dev));
-    keep_pool(dev);
-    StreamScratch scr(st);
+    const int64_t n_items = (n_traj + kChunk - 1) / kChunk;
+    bool cap = false;
+    ssa_status s = capture_check(m, st, dev, stats, m->order == SSA_SUM_SEQ && jit_eligible(m),
+                                 latency_bound(n_items, dev), &cap);
+    if (s) return s;
+    if (!cap) keep_pool(dev);
+    StreamScratch pooled(st);
+    CaptureScratch kept(m);
+    Scratch &scr = cap ? (Scratch &)kept : (Scratch &)pooled;
     void *gt = nullptr, *gt2 = nullptr, *ctl = nullptr, *bp = nullptr;
     const size_t rows_bytes = sizeof(double) * (size_t)n_traj * m->M;
     const int32_t ncol = quad ? 4 * m->S + 2 : 2 * m->S + 2;
@@ -1956,7 +2034,7 @@ ssa_status backward_impl(const ssa_model *m, const double *rates, const double *
     HIP_TRY(scr.alloc(&gt2, rows_bytes / 2 + sizeof(double) * m->M));
     HIP_TRY(scr.alloc(&ctl, kCtlBytes));
     HIP_TRY(launch_zero(ctl, 64, st));
-    ssa_status s = run_rates(m, rates, log_rates, ctl, scr, st, &rates);
+    s = run_rates(m, rates, log_rates, ctl, scr, st, &rates);
     if (s) return s;
     NetDev n = base_net(m, rates, n_traj, t_end, grid, G, seed, max_events);
     n.ginfo = (const GridInfo *)((char *)ctl + 64);
@@ -1973,7 +2051,6 @@ ssa_status backward_impl(const ssa_model *m, const double *rates, const double *
     wl.net0 = n;
     wl.range_begin = 0;
     wl.range_end = n_traj;
-    const int64_t n_items = (n_traj + kChunk - 1) / kChunk;
     wl.n_items = (int32_t)n_items;
     wl.counter = (unsigned int *)ctl;
     wl.stats = (unsigned long long *)((char *)ctl + 32);

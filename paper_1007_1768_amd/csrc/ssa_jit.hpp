@@ -115,6 +115,21 @@ extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd_slab_hist(
                                                          ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
 }
 
+// One epoch of a run in epochs of simulation time, without and with the histogram.
+extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd_epoch(ssa::WorkList wl) {
+    extern __shared__ long long ssa_win[];
+    ssa::RegPolicy p;
+    ssa::sim_fwd_gen<ssa_gen::Net::M, false, false, false, ssa::RegPolicy, false, false, true>(
+        wl, p, ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
+}
+
+extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd_hist_epoch(ssa::WorkList wl) {
+    extern __shared__ long long ssa_win[];
+    ssa::RegPolicy p;
+    ssa::sim_fwd_gen<ssa_gen::Net::M, false, false, true, ssa::RegPolicy, false, false, true>(
+        wl, p, ssa_win + (threadIdx.x / ssa::kWave) * wl.win_words);
+}
+
 // Forward pass with the species cross products (covariance matrices per grid point).
 extern "C" __global__ void __launch_bounds__(ssa::kBlock) ssa_jit_fwd_cov(ssa::WorkList wl) {
     extern __shared__ long long ssa_win[];

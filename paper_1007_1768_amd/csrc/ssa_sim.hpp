@@ -992,10 +992,15 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 // wave fills draws up to K + 2 kPcRows.  A lane consumes at most one draw per step, so the
 // draws it needs before the next barrier, [K, K + kPcRows), are in the ring, and the slots
 // being refilled hold draws below K, already consumed.
-template <int MM, bool BATCH, bool SLAB, bool HIST, class Policy, bool COV = false, bool PC = false>
+// EPOCH: one epoch of a run in epochs of simulation time (resume from n.rs_*, unless NULL,
+// pause before the first event beyond n.t_pause and save into n.ws_*); a template flag so
+// that the other launches carry none of it.
+template <int MM, bool BATCH, bool SLAB, bool HIST, class Policy, bool COV = false, bool PC = false,
+          bool EPOCH = false>
 __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long long *win, double *ring = nullptr,
                                             unsigned long long *kl = nullptr, int32_t *ctl = nullptr) {
     static_assert(!PC || (!BATCH && !SLAB), "the drawing wave serves single-network atomic-flush launches");
+    static_assert(!EPOCH || (!PC && !BATCH && !SLAB && !COV), "epochs run single-network atomic-flush launches");
     constexpr int MR = MM > 0 ? MM : 1;
     constexpr uint64_t kRing = 2 * kPcRows;
     const uint32_t lane = __lane_id();
@@ -1128,7 +1133,7 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
         // a run in epochs of simulation time resumes every trajectory from its saved state
         // (its next draw is the Philox block it did not use; the window follows its lanes
         // from wherever they are)
-        if (!PC && active && n0.rs_t) {
+        if (EPOCH && active && n0.rs_t) {
             const double ts = n0.rs_t[traj];
             if (ts < 0.0) {
                 active = false;                 // ended in an earlier epoch
@@ -1161,7 +1166,7 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
             t_next = t + En / acc;
             const bool beyond = !absorb && t_next > n.t_end; // drawn, not applied
             // epochs: an event beyond the epoch's end waits for the next epoch
-            const bool pause = !PC && n.ws_t != nullptr && !absorb && !beyond && t_next > n.t_pause;
+            const bool pause = EPOCH && !absorb && !beyond && t_next > n.t_pause;
             const bool limit = !absorb && !beyond && !pause && ev >= n.max_events;
             k = absorb ? k : k + 1;
             flags |= limit ? (uint32_t)kFlagEventLimit : 0u;
@@ -1169,7 +1174,7 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
             const bool go = !(absorb || beyond || limit || pause);
             tot_events += go ? 0ull : (unsigned long long)(ev - ev_start);
             max_steps = go ? max_steps : max(max_steps, (unsigned long long)ev);
-            if (!PC && !go && n.ws_t) {
+            if (EPOCH && !go) {
                 // save the state for the next epoch: time -1 once the trajectory has ended;
                 // a paused lane redraws the block of the event it did not apply
                 int32_t *wx = n.ws_x + (size_t)traj * S;
