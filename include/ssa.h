@@ -118,6 +118,8 @@ typedef struct {
     float kernel_ms;      /* device time of the simulation kernel(s) */
     uint32_t form;        /* ssa_launch_form of the simulation kernel */
     uint32_t blocks;      /* its grid size in blocks */
+    uint32_t ordered;     /* backward: 1 when its trajectories ran longest first, in the order of
+                             the event counts a forward over the same trajectories recorded */
 } ssa_stats;
 
 /* Model (Section 3.2 model format).

@@ -175,12 +175,14 @@ size_t lds_max(int dev) {
 struct LaunchRec {
     uint32_t form = SSA_FORM_NONE;
     uint32_t blocks = 0;
+    uint32_t ordered = 0;
 };
 thread_local LaunchRec g_launch;
 
-void note_launch(uint32_t form, int64_t blocks) {
+void note_launch(uint32_t form, int64_t blocks, bool ordered = false) {
     g_launch.form = form;
     g_launch.blocks = (uint32_t)blocks;
+    g_launch.ordered = ordered ? 1u : 0u;
 }
 
 // Launch form requested for the specialised kernels by SSA_LAUNCH_FORM (two_wave,
@@ -250,6 +252,19 @@ struct ssa_model {
     std::vector<ssa_rate_law> laws;   // [M] when has_laws
     mutable std::mutex cap_mu;
     mutable std::vector<void *> cap_mem;   // scratch of calls captured into graphs (freed with the model)
+    // the event count of every trajectory of the last forward in generations, and that
+    // run's identity: a backward over the same trajectories orders them by length
+    mutable std::mutex hint_mu;
+    mutable uint32_t *hint_len = nullptr;
+    mutable int64_t hint_cap = 0;
+    mutable bool hint_valid = false;
+    mutable int64_t hint_n = 0;
+    mutable double hint_t_end = 0.0;
+    mutable uint64_t hint_seed = 0, hint_max_events = 0;
+    mutable const double *hint_grid = nullptr, *hint_rates = nullptr, *hint_log_rates = nullptr;
+    mutable int32_t hint_G = 0;
+    mutable int hint_dev = -1;
+    mutable std::vector<void *> hint_old;  // replaced buffers (a launch may still read one)
 };
 
 namespace {
@@ -794,6 +809,7 @@ ssa_status collect_stats(unsigned long long *d_stats, hipStream_t st, hipEvent_t
         stats->kernel_ms = ms;
         stats->form = g_launch.form;
         stats->blocks = g_launch.blocks;
+        stats->ordered = g_launch.ordered;
     }
     if (h[2] & kFlagRefused)
         return fail(SSA_E_INVALID, "refused on the device: the grid is not non-decreasing inside [0, t_end], or a "
@@ -1348,10 +1364,106 @@ void ssa_model_destroy(ssa_model *m) {
     if (m->d_dep_rate) (void)hipFree(m->d_dep_rate);
     if (m->d_dep_ptr) (void)hipFree(m->d_dep_ptr);
     for (void *p : m->cap_mem) (void)hipFree(p);
+    for (void *p : m->hint_old) (void)hipFree(p);
+    if (m->hint_len) (void)hipFree(m->hint_len);
     delete m;
 }
 
 namespace {
+
+// ---------------------------------------------------------------------------------------
+// Length hints.  A forward in generations records the event count of every trajectory
+// into a buffer of the model, with the identity of its run; a backward of the same run
+// (same trajectory count, horizon, seed, event cap, grid and rate arrays) then takes its
+// trajectories longest first (len_max_kernel and after), so that the trajectories of one
+// generation end close together.  The record is only a hint: a backward whose arrays
+// changed contents since, or that overlaps a forward, still gets its exact results.
+// ---------------------------------------------------------------------------------------
+constexpr int64_t kMaxHintTraj = (int64_t)1 << 27;
+
+struct RunId {
+    int64_t n;
+    double t_end;
+    uint64_t seed, max_events;
+    const double *grid, *rates, *log_rates;
+    int32_t G;
+    int dev;
+};
+
+// The buffer the forward of run id records into, or NULL (no record for this run).  Under
+// graph capture the buffer is used only if it is large enough already, and the recorded
+// identity is left as it is.
+uint32_t *hint_begin(const ssa_model *m, const RunId &id, bool capturing) {
+    if (m->order != SSA_SUM_SEQ || !jit_eligible(m) || id.n > kMaxHintTraj) return nullptr;
+    std::lock_guard<std::mutex> lk(m->hint_mu);
+    if (capturing) return (m->hint_cap >= id.n && m->hint_dev == id.dev) ? m->hint_len : nullptr;
+    m->hint_valid = false;
+    if (m->hint_cap < id.n || m->hint_dev != id.dev) {
+        void *p = nullptr;
+        if (hipMalloc(&p, sizeof(uint32_t) * (size_t)id.n) != hipSuccess) return nullptr;
+        if (m->hint_len) m->hint_old.push_back(m->hint_len);
+        m->hint_len = (uint32_t *)p;
+        m->hint_cap = id.n;
+        m->hint_dev = id.dev;
+    }
+    return m->hint_len;
+}
+
+void hint_end(const ssa_model *m, const RunId &id, bool recorded) {
+    std::lock_guard<std::mutex> lk(m->hint_mu);
+    m->hint_valid = recorded;
+    m->hint_n = id.n;
+    m->hint_t_end = id.t_end;
+    m->hint_seed = id.seed;
+    m->hint_max_events = id.max_events;
+    m->hint_grid = id.grid;
+    m->hint_rates = id.rates;
+    m->hint_log_rates = id.log_rates;
+    m->hint_G = id.G;
+}
+
+// The order of the trajectories of a backward of run id (NULL: positions in order).
+// Scratch: a copy of the counts, the bucket counters and the order.
+ssa_status hint_order(const ssa_model *m, const RunId &id, Scratch &scr, hipStream_t st, const uint32_t **out) {
+    *out = nullptr;
+    const uint32_t *len = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(m->hint_mu);
+        const bool same = m->hint_valid && m->hint_n == id.n && m->hint_t_end == id.t_end && m->hint_seed == id.seed &&
+                          m->hint_max_events == id.max_events && m->hint_grid == id.grid &&
+                          m->hint_rates == id.rates && m->hint_log_rates == id.log_rates && m->hint_G == id.G &&
+                          m->hint_dev == id.dev;
+        if (!same) return SSA_OK;
+        len = m->hint_len;
+    }
+    const int64_t n = id.n;
+    void *snap = nullptr, *cnt = nullptr, *perm = nullptr;
+    HIP_TRY(scr.alloc(&snap, sizeof(uint32_t) * (size_t)n));
+    HIP_TRY(scr.alloc(&perm, sizeof(uint32_t) * (size_t)n));
+    HIP_TRY(scr.alloc(&cnt, sizeof(int32_t) * (kLenBuckets + 64)));
+    unsigned int *mx = (unsigned int *)((int32_t *)cnt + kLenBuckets);
+    HIP_TRY(launch_zero(cnt, sizeof(int32_t) * (kLenBuckets + 64), st));
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(len_max_kernel, dim3(blocks), dim3(256), 0, st, len, n, (uint32_t *)snap, mx);
+    hipLaunchKernelGGL(len_count_kernel, dim3(blocks), dim3(256), 0, st, (const uint32_t *)snap, n,
+                       (const unsigned int *)mx, (int32_t *)cnt);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, st, (int32_t *)cnt, (int64_t)kLenBuckets);
+    hipLaunchKernelGGL(len_scatter_kernel, dim3(blocks), dim3(256), 0, st, (const uint32_t *)snap, n,
+                       (const unsigned int *)mx, (int32_t *)cnt, (uint32_t *)perm);
+    HIP_TRY(hipGetLastError());
+    *out = (const uint32_t *)perm;
+    return SSA_OK;
+}
+
+// Launch form of the specialised backward: two-wave blocks up to two work items per CU,
+// else generations; a tuned form, then SSA_LAUNCH_FORM, replace it (as launch_single does).
+uint32_t bwd_form(int64_t n_items, int dev, int32_t tuned_form) {
+    uint32_t form = pc_launch(n_items, dev) ? SSA_FORM_TWO_WAVE : SSA_FORM_GENERATIONS;
+    if (tuned_form >= SSA_FORM_TWO_WAVE && tuned_form <= SSA_FORM_REFILL) form = (uint32_t)tuned_form;
+    const uint32_t forced = forced_form();
+    if (forced != SSA_FORM_NONE) form = forced;
+    return form;
+}
 
 // Rate constants of a run: the caller's rates, or c = e^theta of the caller's log rates
 // formed on the device (zero-padded to the model's table width; an invalid theta refuses the
@@ -1401,6 +1513,7 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, const double
     CaptureScratch kept(m);
     Scratch &scr = fixed ? *fixed : cap ? (Scratch &)kept : (Scratch &)pooled;
 
+    const RunId rid{n_traj, t_end, seed, max_events, grid, rates, log_rates, G, dev};
     const size_t cells = (size_t)G * m->S;
     const size_t H_bytes = hist ? sizeof(int32_t) * (size_t)G * hist->nbins : 0;
     void *D = nullptr, *Dhi = nullptr, *Hd = nullptr, *ctl = nullptr;
@@ -1425,6 +1538,7 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, const double
         n.h_lo = hist->lo;
         n.h_width = hist->width;
     }
+    n.len_out = fixed ? nullptr : hint_begin(m, rid, cap);
     WorkList wl;
     std::memset(&wl, 0, sizeof wl);
     wl.net0 = n;
@@ -1439,6 +1553,7 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, const double
     if (fixed) cfg.slab = 0;
     s = launch_forward(m, wl, n_items, dev, st, rates, scr, n.D, (stats && !fixed) ? &kms : nullptr, cfg,
                        !fixed && !cap);
+    if (n.len_out && !cap) hint_end(m, rid, s == SSA_OK && g_launch.form == SSA_FORM_GENERATIONS);
     if (s) return s;
     HIP_TRY(launch_finalize(n.D, n.Dhi, G, m->S, m->d_x0, n_traj, mean, var, ctl_status(ctl), st));
     if (hist) {
@@ -2024,6 +2139,7 @@ ssa_status backward_impl(const ssa_model *m, const double *rates, const double *
     StreamScratch pooled(st);
     CaptureScratch kept(m);
     Scratch &scr = cap ? (Scratch &)kept : (Scratch &)pooled;
+    const RunId rid{n_traj, t_end, seed, max_events, grid, rates, log_rates, G, dev};
     void *gt = nullptr, *gt2 = nullptr, *ctl = nullptr, *bp = nullptr;
     const size_t rows_bytes = sizeof(double) * (size_t)n_traj * m->M;
     const int32_t ncol = quad ? 4 * m->S + 2 : 2 * m->S + 2;
@@ -2054,11 +2170,18 @@ ssa_status backward_impl(const ssa_model *m, const double *rates, const double *
     wl.n_items = (int32_t)n_items;
     wl.counter = (unsigned int *)ctl;
     wl.stats = (unsigned long long *)((char *)ctl + 32);
+    const FwdTune cfg = tune ? *tune : tune_lookup(m, n_traj, G, dev, true);
+    // the lane kernels take the trajectories longest first when the forward of this run
+    // recorded their lengths
+    if (m->order == SSA_SUM_SEQ && (!jit_eligible(m) || bwd_form(n_items, dev, cfg.form) != SSA_FORM_TWO_WAVE)) {
+        s = hint_order(m, rid, scr, st, &wl.perm);
+        if (s) return s;
+    }
     EventPair ev;
     if (stats && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
-    const FwdTune cfg = tune ? *tune : tune_lookup(m, n_traj, G, dev, true);
     s = launch_single(kBwd, m, wl, n_items, dev, st, rates, scr, quad, cfg.form, cfg.blocks);
     if (s) return s;
+    g_launch.ordered = wl.perm ? 1u : 0u;
     if (stats && ev.b) HIP_TRY(hipEventRecord(ev.b, st));
     // fixed-order pairwise reduction of the per-trajectory rows
     double *src = (double *)gt, *dst = (double *)gt2;

@@ -1000,6 +1000,66 @@ __global__ void __launch_bounds__(256) scan_apply_kernel(const int32_t *in, int6
 }
 
 // ---------------------------------------------------------------------------------------
+// Trajectory order of a backward pass.  The backward re-simulates the forward's
+// trajectories; a forward in generations records each trajectory's event count, and the
+// backward then takes its trajectories longest first, in buckets of similar length
+// (len >> shift, shift the smallest that brings the longest below kLenBuckets), so that the
+// 64 trajectories of one generation end close together.  Any order gives the same results,
+// so the counts are only a hint: a stale one costs time, never bits.
+// ---------------------------------------------------------------------------------------
+constexpr int32_t kLenBuckets = 4096;
+
+// Copies the counts (the order is built from this private copy, so that a forward writing
+// the recorded counts at the same time cannot make it anything but a permutation) and takes
+// their maximum.
+__global__ void __launch_bounds__(256) len_max_kernel(const uint32_t *__restrict__ len, int64_t n,
+                                                      uint32_t *__restrict__ snap, unsigned int *__restrict__ mx) {
+    uint32_t m = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const uint32_t v = len[i];
+        snap[i] = v;
+        m = max(m, v);
+    }
+    for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(mx, m);
+}
+
+// Bucket of a length: longest first (bucket 0 holds the longest).
+__device__ __forceinline__ int32_t len_bucket(uint32_t v, int32_t shift) {
+    return kLenBuckets - 1 - (int32_t)min(v >> shift, (uint32_t)(kLenBuckets - 1));
+}
+
+__device__ __forceinline__ int32_t len_shift(uint32_t mx) {
+    int32_t s = 0;
+    while ((mx >> s) >= (uint32_t)kLenBuckets) ++s;
+    return s;
+}
+
+__global__ void __launch_bounds__(256) len_count_kernel(const uint32_t *__restrict__ len, int64_t n,
+                                                        const unsigned int *__restrict__ mx,
+                                                        int32_t *__restrict__ cnt) {
+    __shared__ int32_t loc[kLenBuckets];
+    for (int32_t b = threadIdx.x; b < kLenBuckets; b += blockDim.x) loc[b] = 0;
+    __syncthreads();
+    const int32_t sh = len_shift(*mx);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&loc[len_bucket(len[i], sh)], 1);
+    __syncthreads();
+    for (int32_t b = threadIdx.x; b < kLenBuckets; b += blockDim.x)
+        if (loc[b]) atomicAdd(cnt + b, loc[b]);
+}
+
+// cur: the exclusive scan of the counts; each trajectory takes the next position of its
+// bucket.
+__global__ void __launch_bounds__(256) len_scatter_kernel(const uint32_t *__restrict__ len, int64_t n,
+                                                          const unsigned int *__restrict__ mx,
+                                                          int32_t *__restrict__ cur, uint32_t *__restrict__ perm) {
+    const int32_t sh = len_shift(*mx);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        perm[atomicAdd(cur + len_bucket(len[i], sh), 1)] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------------------
 // Time order of the event log (adaptive selective memory, Section 3.2.1: the points of all
 // trajectories merged by simulation time).  The keys are the bit patterns of the event
 // times of one epoch, in [t0, t1] (non-negative binary64 values order like their bits), or

@@ -168,6 +168,8 @@ struct NetDev {
     double *ws_t;
     uint64_t *ws_k, *ws_ev;
     double t_pause;
+    // forward in generations: each trajectory's event count (saturated to 32 bits), or NULL
+    uint32_t *len_out;
 };
 
 // Event-log record value: species (12 bits) | change (20-bit two's complement) << 12 |
@@ -196,6 +198,10 @@ struct WorkList {
     double *jac_slabs;           // forward with Jacobian: [items][G][S+1][M] per-work-item sums
     unsigned int *counter;       // work-item counter (zeroed before launch)
     unsigned long long *stats;   // [0] events, [1] max steps, [2] flags
+    // single-network record / backward / event log: the trajectory at each position of
+    // [range_begin, range_end), or NULL for the positions themselves (any order gives the
+    // same results: a trajectory keeps its index, its random numbers and its output row)
+    const uint32_t *perm;
 };
 
 // Error-free transformations (Knuth's two-sum) for double-double prefix sums.
@@ -469,7 +475,7 @@ __device__ __forceinline__ void sim_loop(const WorkList &wl, Policy &p) {
                 if (mine < pool_end) {
                     const NetDev n = current_net<BATCH>(wl, cur);
                     active = true;
-                    traj = mine;
+                    traj = (!BATCH && wl.perm) ? (int64_t)wl.perm[mine] : mine;
                     t = 0.0;
                     k = 0;
                     ev = 0;
@@ -1321,6 +1327,8 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
             }
         }
         flush(base, min(G, base + W));
+        if (!BATCH && !PC && !EPOCH && n0.len_out && (int64_t)lane < count)
+            n0.len_out[traj] = (uint32_t)min(ev, (uint64_t)0xffffffffu);
     }
 
     // wave totals -> global statistics

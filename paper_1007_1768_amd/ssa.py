@@ -45,12 +45,13 @@ FORMS = {0: "none", 1: "two_wave", 2: "generations", 3: "refill", 4: "table", 5:
 
 class Stats(ctypes.Structure):
     _fields_ = [("events", ctypes.c_uint64), ("max_steps", ctypes.c_uint64), ("flags", ctypes.c_uint32),
-                ("kernel_ms", ctypes.c_float), ("form", ctypes.c_uint32), ("blocks", ctypes.c_uint32)]
+                ("kernel_ms", ctypes.c_float), ("form", ctypes.c_uint32), ("blocks", ctypes.c_uint32),
+                ("ordered", ctypes.c_uint32)]
 
     def as_dict(self):
         return dict(events=int(self.events), max_steps=int(self.max_steps), flags=int(self.flags),
                     kernel_ms=float(self.kernel_ms), form=FORMS.get(int(self.form), str(self.form)),
-                    blocks=int(self.blocks))
+                    blocks=int(self.blocks), ordered=bool(self.ordered))
 
 
 _lib = None

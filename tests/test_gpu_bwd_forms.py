@@ -12,7 +12,8 @@ weights and with mean and variance weights, and the call must report the form it
   absorbing state long before t_end;
 * the persistent forms (generations, the default beyond two-wave launches and the large
   workload's own; refilled lanes) at the large workload's grid (10^4 points, t_end 50) with
-  more than 2048 work items.
+  more than 2048 work items, after a forward of the same run (so their trajectories run
+  longest first, in the order of the lengths that forward recorded).
 """
 import os
 
@@ -143,6 +144,7 @@ def test_persistent_backward_at_large_grid(ssa, big_ref, monkeypatch, weights, a
     torch.cuda.synchronize()
     model.close()
     assert sb["form"] == (asked or "generations"), sb
+    assert sb["ordered"], sb        # longest first, from the lengths the forward above recorded
     assert sb["events"] == ref["events"] == sf["events"]
     assert np.array_equal(mean.cpu().numpy(), ref["mean"]) and np.array_equal(var.cpu().numpy(), ref["var"])
     assert np.all(np.abs(g.cpu().numpy() - grads[weights]) <= 1e-12 * l1[weights]), (g.cpu().numpy(), grads[weights])
