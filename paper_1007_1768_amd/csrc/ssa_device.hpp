@@ -68,6 +68,15 @@ __device__ __forceinline__ double uniform_open1(uint32_t lo, uint32_t hi) {
 //   P = C10, P = fma(P, s, Cn) for n = 9..1, Cn = 2/(2n+1) rounded once;
 //   ln m = fma(f, s P, f + f);  ln r = fma(E, LN2_HI, fma(E, LN2_LO, ln m)).
 // LN2_HI keeps 32 significant bits of ln 2, so E * LN2_HI is exact; LN2_LO is the rest.
+// p s + c rounded once, as the three-operand VOP3 instruction: for a loop-invariant c the
+// compiler otherwise copies c into the accumulator and uses the two-operand form, one more
+// instruction per term.
+__device__ __forceinline__ double fma3(double p, double s, double c) {
+    double out;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(out) : "v"(p), "v"(s), "v"(c));
+    return out;
+}
+
 __device__ __forceinline__ double neg_log(double r) {
     constexpr double kLn2Hi = 0x1.62e42fee00000p-1;
     constexpr double kLn2Lo = 0x1.a39ef35793c76p-33;
@@ -82,15 +91,15 @@ __device__ __forceinline__ double neg_log(double r) {
     const double f = (m - 1.0) / (m + 1.0);
     const double s = f * f;
     double P = 2.0 / 21.0;
-    P = __builtin_fma(P, s, 2.0 / 19.0);
-    P = __builtin_fma(P, s, 2.0 / 17.0);
-    P = __builtin_fma(P, s, 2.0 / 15.0);
-    P = __builtin_fma(P, s, 2.0 / 13.0);
-    P = __builtin_fma(P, s, 2.0 / 11.0);
-    P = __builtin_fma(P, s, 2.0 / 9.0);
-    P = __builtin_fma(P, s, 2.0 / 7.0);
-    P = __builtin_fma(P, s, 2.0 / 5.0);
-    P = __builtin_fma(P, s, 2.0 / 3.0);
+    P = fma3(P, s, 2.0 / 19.0);
+    P = fma3(P, s, 2.0 / 17.0);
+    P = fma3(P, s, 2.0 / 15.0);
+    P = fma3(P, s, 2.0 / 13.0);
+    P = fma3(P, s, 2.0 / 11.0);
+    P = fma3(P, s, 2.0 / 9.0);
+    P = fma3(P, s, 2.0 / 7.0);
+    P = fma3(P, s, 2.0 / 5.0);
+    P = fma3(P, s, 2.0 / 3.0);
     const double t = s * P;
     const double lnm = __builtin_fma(f, t, f + f);
     const double Ed = (double)E;

@@ -1242,17 +1242,20 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
                 const bool inb = bin < G;
                 long long *wrow = win + (bin & (W - 1)) * row_words;
                 bool big = false;
+                int32_t h_old = 0, h_new = 0;       // HIST: the histogram species before and after
                 p.apply(n, sel, [&](int32_t sp, int32_t xo, int32_t xn) {
                     // events past the last grid point add zeros
                     ovf |= (uint32_t)xn;
                     const int32_t dl = inb ? xn - xo : 0;
-                    const long long d2 = (2ll * xo + dl) * (long long)dl;
-                    long long *w = wrow + sp * 2;
-                    const bool small = d2 > -kSmallD2 && d2 < kSmallD2;
+                    // (2x + nu) nu as a 24-bit product when x < 2^19 and |nu| < 16 (its
+                    // magnitude then stays below 2^24); any other change goes whole through
+                    // the rare path below (low 24 bits to the window, the rest to Dhi)
+                    const bool small = (uint32_t)xo < (1u << 19) && (uint32_t)(dl + 15) < 31u;
+                    const int32_t d2 = small ? __mul24(2 * xo + dl, dl) : 0;
                     big = big || !small;
+                    long long *w = wrow + sp * 2;
                     atomicAdd((unsigned long long *)w, (unsigned long long)(long long)dl);
-                    atomicAdd((unsigned long long *)(w + 1),
-                              (unsigned long long)(small ? d2 : (d2 & ((1ll << 24) - 1))));
+                    atomicAdd((unsigned long long *)(w + 1), (unsigned long long)(long long)d2);
                     if (COV) {
                         // x_s x_r changes by dl x_r (the other species at their current
                         // values: applied one species at a time, the changes telescope)
@@ -1270,22 +1273,32 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
                             }
                         });
                     }
-                    if (HIST && sp == n.h_species && dl != 0) {
-                        const int32_t bo = xo < n.h_lo ? 0 : min((xo - n.h_lo) / n.h_width, n.nb_hist - 1);
-                        const int32_t bn = xn < n.h_lo ? 0 : min((xn - n.h_lo) / n.h_width, n.nb_hist - 1);
-                        if (bo != bn) {
-                            atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bo, -1);
-                            atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bn, 1);
-                        }
+                    if (HIST) {
+                        const bool h = sp == n.h_species;       // wave-uniform
+                        h_old = h ? xo : h_old;
+                        h_new = h ? xn : h_new;
                     }
                 });
-                if (__ballot(big)) {                    // rare: |(2x+nu)nu| >= 2^24
+                if (HIST && inb && h_old != h_new) {
+                    // unit-width bins (a wave-uniform test) need no division
+                    const int32_t lo = n.h_lo, top = n.nb_hist - 1;
+                    const int32_t bo = h_old < lo ? 0 : min(n.h_width == 1 ? h_old - lo : (h_old - lo) / n.h_width, top);
+                    const int32_t bn = h_new < lo ? 0 : min(n.h_width == 1 ? h_new - lo : (h_new - lo) / n.h_width, top);
+                    if (bo != bn) {
+                        atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bo, -1);
+                        atomicAdd(n.Hd + (size_t)bin * n.nb_hist + bn, 1);
+                    }
+                }
+                if (__ballot(big)) {                    // rare: a count of 2^19 or more, or |nu| >= 16
                     if (big) {
                         p.replay(n, sel, [&](int32_t sp, int32_t xo, int32_t xn) {
                             const int32_t dl = inb ? xn - xo : 0;
-                            const long long d2 = (2ll * xo + dl) * (long long)dl;
-                            if (!(d2 > -kSmallD2 && d2 < kSmallD2))
+                            if (!((uint32_t)xo < (1u << 19) && (uint32_t)(dl + 15) < 31u)) {
+                                const long long d2 = (2ll * xo + dl) * (long long)dl;
+                                atomicAdd((unsigned long long *)(wrow + sp * 2 + 1),
+                                          (unsigned long long)(d2 & ((1ll << 24) - 1)));
                                 atomicAdd(n.Dhi + (size_t)bin * hi_words + sp, (unsigned long long)(d2 >> 24));
+                            }
                         });
                     }
                 }
