@@ -1422,6 +1422,27 @@ void hint_end(const ssa_model *m, const RunId &id, bool recorded) {
     m->hint_G = id.G;
 }
 
+// Positions 0..n-1 ordered by key, largest first in buckets of similar keys (the bucket
+// sort of len_max_kernel and after).  Scratch: a copy of the keys, the counters, the order.
+ssa_status order_by_key(const uint32_t *key, int64_t n, Scratch &scr, hipStream_t st, const uint32_t **out) {
+    void *snap = nullptr, *cnt = nullptr, *perm = nullptr;
+    HIP_TRY(scr.alloc(&snap, sizeof(uint32_t) * (size_t)n));
+    HIP_TRY(scr.alloc(&perm, sizeof(uint32_t) * (size_t)n));
+    HIP_TRY(scr.alloc(&cnt, sizeof(int32_t) * (kLenBuckets + 64)));
+    unsigned int *mx = (unsigned int *)((int32_t *)cnt + kLenBuckets);
+    HIP_TRY(launch_zero(cnt, sizeof(int32_t) * (kLenBuckets + 64), st));
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(len_max_kernel, dim3(blocks), dim3(256), 0, st, key, n, (uint32_t *)snap, mx);
+    hipLaunchKernelGGL(len_count_kernel, dim3(blocks), dim3(256), 0, st, (const uint32_t *)snap, n,
+                       (const unsigned int *)mx, (int32_t *)cnt);
+    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, st, (int32_t *)cnt, (int64_t)kLenBuckets);
+    hipLaunchKernelGGL(len_scatter_kernel, dim3(blocks), dim3(256), 0, st, (const uint32_t *)snap, n,
+                       (const unsigned int *)mx, (int32_t *)cnt, (uint32_t *)perm);
+    HIP_TRY(hipGetLastError());
+    *out = (const uint32_t *)perm;
+    return SSA_OK;
+}
+
 // The order of the trajectories of a backward of run id (NULL: positions in order).
 // Scratch: a copy of the counts, the bucket counters and the order.
 ssa_status hint_order(const ssa_model *m, const RunId &id, Scratch &scr, hipStream_t st, const uint32_t **out) {
@@ -1436,23 +1457,7 @@ ssa_status hint_order(const ssa_model *m, const RunId &id, Scratch &scr, hipStre
         if (!same) return SSA_OK;
         len = m->hint_len;
     }
-    const int64_t n = id.n;
-    void *snap = nullptr, *cnt = nullptr, *perm = nullptr;
-    HIP_TRY(scr.alloc(&snap, sizeof(uint32_t) * (size_t)n));
-    HIP_TRY(scr.alloc(&perm, sizeof(uint32_t) * (size_t)n));
-    HIP_TRY(scr.alloc(&cnt, sizeof(int32_t) * (kLenBuckets + 64)));
-    unsigned int *mx = (unsigned int *)((int32_t *)cnt + kLenBuckets);
-    HIP_TRY(launch_zero(cnt, sizeof(int32_t) * (kLenBuckets + 64), st));
-    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
-    hipLaunchKernelGGL(len_max_kernel, dim3(blocks), dim3(256), 0, st, len, n, (uint32_t *)snap, mx);
-    hipLaunchKernelGGL(len_count_kernel, dim3(blocks), dim3(256), 0, st, (const uint32_t *)snap, n,
-                       (const unsigned int *)mx, (int32_t *)cnt);
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, st, (int32_t *)cnt, (int64_t)kLenBuckets);
-    hipLaunchKernelGGL(len_scatter_kernel, dim3(blocks), dim3(256), 0, st, (const uint32_t *)snap, n,
-                       (const unsigned int *)mx, (int32_t *)cnt, (uint32_t *)perm);
-    HIP_TRY(hipGetLastError());
-    *out = (const uint32_t *)perm;
-    return SSA_OK;
+    return order_by_key(len, id.n, scr, st, out);
 }
 
 // Launch form of the specialised backward: two-wave blocks up to two work items per CU,

@@ -1141,12 +1141,16 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
         // from wherever they are)
         if (EPOCH && active && n0.rs_t) {
             const double ts = n0.rs_t[traj];
+            ev = ev_start = n0.rs_ev[traj];
             if (ts < 0.0) {
-                active = false;                 // ended in an earlier epoch
+                // ended in an earlier epoch: it stays ended in this epoch's saved states too
+                // (the two state buffers alternate from epoch to epoch)
+                active = false;
+                n0.ws_t[traj] = -1.0;
+                n0.ws_ev[traj] = ev;
             } else {
                 t = ts;
                 k = n0.rs_k[traj];
-                ev = ev_start = n0.rs_ev[traj];
                 p.load_state(n0.rs_x + (size_t)traj * S);
             }
         }
@@ -1316,6 +1320,7 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
                     asm volatile("" : "+v"(E_pre), "+v"(r2_pre));
                 }
                 place();
+                if (EPOCH && bad) n.ws_t[traj] = -1.0;      // an overflow ends the trajectory
                 active = active && !bad;
             }
             // window upkeep: slide when a lane is waiting beyond it
@@ -1340,7 +1345,7 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
             }
         }
         flush(base, min(G, base + W));
-        if (!BATCH && !PC && !EPOCH && n0.len_out && (int64_t)lane < count)
+        if (!BATCH && !PC && n0.len_out && (int64_t)lane < count)
             n0.len_out[traj] = (uint32_t)min(ev, (uint64_t)0xffffffffu);
     }
 

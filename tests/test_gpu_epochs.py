@@ -5,7 +5,8 @@ variance, histogram, event count) and the oracle's: every trajectory pauses befo
 event beyond the epoch's end and resumes with the draw it did not use.  Cases: epochs at
 arbitrary times (with repeated and backward times, which do nothing), an epoch ending
 exactly at an event time (the event belongs to that epoch), the HIV network of Table 1 with
-its rate laws, and the errors (finishing early, unsupported models).
+its rate laws, trajectories absorbed many epochs before the last, and the errors (finishing
+early, unsupported models).
 """
 import numpy as np
 import pytest
@@ -76,6 +77,19 @@ def test_epochs_hiv_network(ssa):
     mean, var, _, st = _epochs_vs_single(ssa, m, N, t_end, grid, seed, [0.1, 0.35, 0.6, 1.0])
     s, ref = orc.run(m, N, t_end, grid, seed)
     assert s == 0 and ref["events"] == st["events"]
+    assert np.array_equal(mean.cpu().numpy(), ref["mean"]) and np.array_equal(var.cpu().numpy(), ref["var"])
+
+
+def test_trajectories_that_end_early_stay_ended(ssa):
+    # pure death from 5: every trajectory is absorbed within a few time units, long before
+    # the last of 40 epochs; an ended trajectory must stay ended in both alternating state
+    # buffers, whatever the number of epochs after its end
+    m = inputs._model("death", ["X"], [({"X": 1}, {}, 1.0)], [5])
+    N, t_end, G, seed = 3000, 20.0, 81, 12
+    grid = inputs.uniform_grid(t_end, G)
+    mean, var, _, st = _epochs_vs_single(ssa, m, N, t_end, grid, seed, list(np.arange(1, 41) * 0.5))
+    s, ref = orc.run(m, N, t_end, grid, seed)
+    assert s == 0 and ref["events"] == st["events"] == 5 * N
     assert np.array_equal(mean.cpu().numpy(), ref["mean"]) and np.array_equal(var.cpu().numpy(), ref["var"])
 
 
