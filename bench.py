@@ -329,7 +329,7 @@ def kernel_name(direction, form, hist):
     return k
 
 
-def measure_step(ssa, torch, dev, name, steps, warmup):
+def measure_step(ssa, torch, dev, name, steps, warmup, graph_steps=True):
     """The step (forward mean/var[/histogram] + loss weights + LR backward) on a named
     workload: K steps timed with HIP events on the launch stream, each step's own time
     too, every launch's statistics (events, launch form, simulation-kernel time by HIP
@@ -397,33 +397,35 @@ def measure_step(ssa, torch, dev, name, steps, warmup):
         wts.mul_(2.0)
         ssa.backward_device(model, N, t_end, grid, seed, wts, mean, out=gbuf)
 
-    outs = [mean, var, gbuf] + ([hbuf] if hist else [])
-    want = [x.clone() for x in outs]
-    side = torch.cuda.Stream()
-    side.wait_stream(stream)
-    with torch.cuda.stream(side):
-        step_graph()
-    stream.wait_stream(side)
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        step_graph()
-    torch.cuda.synchronize()
-    for _ in range(warmup):
-        graph.replay()
-    torch.cuda.synchronize()
-    gev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
-    g_t0 = time.perf_counter()
-    gev[0].record(stream)
-    for i in range(steps):
-        graph.replay()
-        gev[i + 1].record(stream)
-    torch.cuda.synchronize()
-    g_wall = time.perf_counter() - g_t0
-    graph_ms = gev[0].elapsed_time(gev[-1]) / steps
-    graph_per = [gev[i].elapsed_time(gev[i + 1]) for i in range(steps)]
-    assert all(torch.equal(a, b) for a, b in zip(outs, want)), "graph replay differs from the eager step"
-    del graph
+    graph_ms, graph_per, g_wall = step_ms, per_step, wall
+    if graph_steps:
+        outs = [mean, var, gbuf] + ([hbuf] if hist else [])
+        want = [x.clone() for x in outs]
+        side = torch.cuda.Stream()
+        side.wait_stream(stream)
+        with torch.cuda.stream(side):
+            step_graph()
+        stream.wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step_graph()
+        torch.cuda.synchronize()
+        for _ in range(warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        gev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+        g_t0 = time.perf_counter()
+        gev[0].record(stream)
+        for i in range(steps):
+            graph.replay()
+            gev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        g_wall = time.perf_counter() - g_t0
+        graph_ms = gev[0].elapsed_time(gev[-1]) / steps
+        graph_per = [gev[i].elapsed_time(gev[i + 1]) for i in range(steps)]
+        assert all(torch.equal(a, b) for a, b in zip(outs, want)), "graph replay differs from the eager step"
+        del graph
     torch.cuda.synchronize()
     model.close()
 
@@ -515,6 +517,8 @@ def main():
     ap.add_argument("--workload", default="large", choices=["large", "viral", "differentiated"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched / plain comparison")
+    ap.add_argument("--eager", action="store_true",
+                    help="time the K eager steps only, without the graph capture (for counter-collection runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter calibration)")
     ap.add_argument("--wide-sweep", action="store_true",
@@ -581,7 +585,7 @@ def main():
               flush=True)
         return
 
-    r = measure_step(ssa, torch, dev, args.workload, args.steps, args.warmup)
+    r = measure_step(ssa, torch, dev, args.workload, args.steps, args.warmup, graph_steps=not args.eager)
     out = {
         "metric": "SSA reaction events/sec on 1 MI355X (+ % VALU roofline); batched & grad vs plain",
         "value": round(r["events"] / (r["graph_ms"] * 1e-3), 1),
@@ -596,9 +600,10 @@ def main():
         "dtype": "f64+i32",
         "data": "synthetic",
         "config": r["cfg"],
-        "timing": "K replays of the step captured as one HIP graph (forward, loss weights, backward), HIP "
-                  "events on the replay stream; kernel times and launch forms from K eager steps with statistics "
-                  "timed in the same run",
+        "timing": ("K eager steps with statistics, HIP events on the launch stream" if args.eager else
+                   "K replays of the step captured as one HIP graph (forward, loss weights, backward), HIP "
+                   "events on the replay stream; kernel times and launch forms from K eager steps with "
+                   "statistics timed in the same run"),
         "median_step_ms": round(r["graph_median_ms"], 4),
         "eager_ms_per_step": round(r["step_ms"], 4),
         "eager_median_step_ms": round(r["median_step_ms"], 4),
@@ -618,7 +623,7 @@ def main():
     if not args.no_batched:
         # the other forms, each timed on its own workload (see --adaptive, --hiv)
         other = "viral" if args.workload != "viral" else "large"
-        o = measure_step(ssa, torch, dev, other, args.steps, args.warmup)
+        o = measure_step(ssa, torch, dev, other, args.steps, args.warmup, graph_steps=not args.eager)
         out["%s_case" % other] = {"workload": o["cfg"]["workload"], "events": o["events"],
                                   "ms_per_step": round(o["graph_ms"], 4),
                                   "events_per_s": round(o["events"] / (o["graph_ms"] * 1e-3), 1),

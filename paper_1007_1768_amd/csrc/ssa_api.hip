@@ -1200,7 +1200,8 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
 
 }  // namespace
 
-extern "C" {
+// The ssa_* definitions below take C linkage from their declarations in ssa.h; every
+// other function of this file has internal linkage (anonymous namespaces).
 
 const char *ssa_last_error(void) { return g_err.c_str(); }
 
@@ -1422,22 +1423,33 @@ void hint_end(const ssa_model *m, const RunId &id, bool recorded) {
     m->hint_G = id.G;
 }
 
-// Positions 0..n-1 ordered by key, largest first in buckets of similar keys (the bucket
-// sort of len_max_kernel and after).  Scratch: a copy of the keys, the counters, the order.
+hipError_t launch_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *sums, hipStream_t st);
+
+// Positions 0..n-1 ordered by key, largest first in buckets of similar keys (len_max_kernel,
+// len_count_kernel, the prefix sum of the counts, len_scatter_kernel).  Scratch: a copy of
+// the keys, the per-tile counts and their prefix sums, the order.
 ssa_status order_by_key(const uint32_t *key, int64_t n, Scratch &scr, hipStream_t st, const uint32_t **out) {
-    void *snap = nullptr, *cnt = nullptr, *perm = nullptr;
+    const int64_t tile = std::max<int64_t>(4096, (n + 255) / 256);
+    const int32_t n_tiles = (int32_t)((n + tile - 1) / tile);
+    const int64_t n_cnt = (int64_t)kLenBuckets * n_tiles;
+    void *snap = nullptr, *perm = nullptr, *cnt = nullptr, *incl = nullptr, *sums = nullptr, *mxw = nullptr;
     HIP_TRY(scr.alloc(&snap, sizeof(uint32_t) * (size_t)n));
     HIP_TRY(scr.alloc(&perm, sizeof(uint32_t) * (size_t)n));
-    HIP_TRY(scr.alloc(&cnt, sizeof(int32_t) * (kLenBuckets + 64)));
-    unsigned int *mx = (unsigned int *)((int32_t *)cnt + kLenBuckets);
-    HIP_TRY(launch_zero(cnt, sizeof(int32_t) * (kLenBuckets + 64), st));
+    HIP_TRY(scr.alloc(&cnt, sizeof(int32_t) * (size_t)n_cnt));
+    HIP_TRY(scr.alloc(&incl, sizeof(int32_t) * (size_t)n_cnt));
+    HIP_TRY(scr.alloc(&sums, sizeof(int32_t) * (size_t)(n_cnt / kScanTile + 2)));
+    HIP_TRY(scr.alloc(&mxw, 256));
+    unsigned int *mx = (unsigned int *)mxw;
+    HIP_TRY(launch_zero(mx, 8, st));
     const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
     hipLaunchKernelGGL(len_max_kernel, dim3(blocks), dim3(256), 0, st, key, n, (uint32_t *)snap, mx);
-    hipLaunchKernelGGL(len_count_kernel, dim3(blocks), dim3(256), 0, st, (const uint32_t *)snap, n,
-                       (const unsigned int *)mx, (int32_t *)cnt);
-    hipLaunchKernelGGL(scan_sums_kernel, dim3(1), dim3(256), 0, st, (int32_t *)cnt, (int64_t)kLenBuckets);
-    hipLaunchKernelGGL(len_scatter_kernel, dim3(blocks), dim3(256), 0, st, (const uint32_t *)snap, n,
-                       (const unsigned int *)mx, (int32_t *)cnt, (uint32_t *)perm);
+    hipLaunchKernelGGL(len_count_kernel, dim3((unsigned)n_tiles), dim3(256), 0, st, (const uint32_t *)snap, n, tile,
+                       (const unsigned int *)mx, (int32_t *)cnt, n_tiles);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(launch_scan((const int32_t *)cnt, (int32_t *)incl, n_cnt, (int32_t *)sums, st));
+    hipLaunchKernelGGL(len_scatter_kernel, dim3((unsigned)n_tiles), dim3(256), 0, st, (const uint32_t *)snap, n, tile,
+                       (const unsigned int *)mx, (const int32_t *)cnt, (const int32_t *)incl, n_tiles,
+                       (uint32_t *)perm);
     HIP_TRY(hipGetLastError());
     *out = (const uint32_t *)perm;
     return SSA_OK;
@@ -2359,6 +2371,8 @@ ssa_status ssa_record(const ssa_model *m, const double *rates, int64_t traj_begi
     return SSA_OK;
 }
 
+namespace {
+
 // Inclusive prefix sum of n int32 values (in place allowed); sums holds n / kScanTile + 1
 // int32 of scratch.
 hipError_t launch_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *sums, hipStream_t st) {
@@ -2401,6 +2415,8 @@ hipError_t sort_event_log(const unsigned long long *key, const unsigned long lon
                        (int32_t)B, R, (const int32_t *)big, (const int32_t *)n_big);
     return hipGetLastError();
 }
+
+}  // namespace
 
 // ------------------------------------------------------------------------------------------
 // Adaptive selective memory: event log -> sort by time -> moments at every distinct event
@@ -2990,5 +3006,3 @@ void ssa_batch_destroy(ssa_batch *bt) {
     if (bt->cap_stream) (void)hipStreamDestroy(bt->cap_stream);
     delete bt;
 }
-
-}  // extern "C"

@@ -1035,28 +1035,39 @@ __device__ __forceinline__ int32_t len_shift(uint32_t mx) {
     return s;
 }
 
-__global__ void __launch_bounds__(256) len_count_kernel(const uint32_t *__restrict__ len, int64_t n,
+// Counting sort by bucket without global atomics: block t takes positions
+// [t * tile, (t + 1) * tile) and counts them per bucket in LDS; the counts are stored
+// bucket-major (cnt[b * n_tiles + t]), so that their inclusive prefix sum less the count
+// is where tile t's positions of bucket b start; the scatter counts again in LDS, each
+// position taking the next rank of its bucket in its tile.
+__global__ void __launch_bounds__(256) len_count_kernel(const uint32_t *__restrict__ len, int64_t n, int64_t tile,
                                                         const unsigned int *__restrict__ mx,
-                                                        int32_t *__restrict__ cnt) {
+                                                        int32_t *__restrict__ cnt, int32_t n_tiles) {
     __shared__ int32_t loc[kLenBuckets];
     for (int32_t b = threadIdx.x; b < kLenBuckets; b += blockDim.x) loc[b] = 0;
     __syncthreads();
     const int32_t sh = len_shift(*mx);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        atomicAdd(&loc[len_bucket(len[i], sh)], 1);
+    const int64_t lo = (int64_t)blockIdx.x * tile, hi = min(n, lo + tile);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) atomicAdd(&loc[len_bucket(len[i], sh)], 1);
     __syncthreads();
-    for (int32_t b = threadIdx.x; b < kLenBuckets; b += blockDim.x)
-        if (loc[b]) atomicAdd(cnt + b, loc[b]);
+    for (int32_t b = threadIdx.x; b < kLenBuckets; b += blockDim.x) cnt[(int64_t)b * n_tiles + blockIdx.x] = loc[b];
 }
 
-// cur: the exclusive scan of the counts; each trajectory takes the next position of its
-// bucket.
-__global__ void __launch_bounds__(256) len_scatter_kernel(const uint32_t *__restrict__ len, int64_t n,
+__global__ void __launch_bounds__(256) len_scatter_kernel(const uint32_t *__restrict__ len, int64_t n, int64_t tile,
                                                           const unsigned int *__restrict__ mx,
-                                                          int32_t *__restrict__ cur, uint32_t *__restrict__ perm) {
+                                                          const int32_t *__restrict__ cnt,
+                                                          const int32_t *__restrict__ incl, int32_t n_tiles,
+                                                          uint32_t *__restrict__ perm) {
+    __shared__ int32_t loc[kLenBuckets];
+    for (int32_t b = threadIdx.x; b < kLenBuckets; b += blockDim.x) loc[b] = 0;
+    __syncthreads();
     const int32_t sh = len_shift(*mx);
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        perm[atomicAdd(cur + len_bucket(len[i], sh), 1)] = (uint32_t)i;
+    const int64_t lo = (int64_t)blockIdx.x * tile, hi = min(n, lo + tile);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+        const int32_t b = len_bucket(len[i], sh);
+        const int64_t j = (int64_t)b * n_tiles + blockIdx.x;
+        perm[incl[j] - cnt[j] + atomicAdd(&loc[b], 1)] = (uint32_t)i;
+    }
 }
 
 // ---------------------------------------------------------------------------------------
