@@ -1452,7 +1452,7 @@ ssa_status order_by_key(const uint32_t *key, int64_t n, Scratch &scr, hipStream_
     HIP_TRY(scr.alloc(&mxw, 256));
     unsigned int *mx = (unsigned int *)mxw;
     HIP_TRY(launch_zero(mx, 8, st));
-    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+    const unsigned blocks = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
     hipLaunchKernelGGL(len_max_kernel, dim3(blocks), dim3(256), 0, st, key, n, (uint32_t *)snap, mx);
     hipLaunchKernelGGL(len_count_kernel, dim3((unsigned)n_tiles), dim3(256), 0, st, (const uint32_t *)snap, n, tile,
                        (const unsigned int *)mx, (int32_t *)cnt, n_tiles);

@@ -1021,7 +1021,10 @@ __global__ void __launch_bounds__(256) len_max_kernel(const uint32_t *__restrict
         m = max(m, v);
     }
     for (int off = 32; off > 0; off >>= 1) m = max(m, (uint32_t)__shfl_xor((int)m, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(mx, m);
+    __shared__ uint32_t wm[4];
+    if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) atomicMax(mx, max(max(wm[0], wm[1]), max(wm[2], wm[3])));   // one atomic per block
 }
 
 // Bucket of a length: longest first (bucket 0 holds the longest).
