@@ -204,6 +204,9 @@ ssa_status ssa_rates_from_log(const double *log_rates, int32_t n, double *rates,
  * the call returns SSA_E_INVALID when stats is given.  Asynchronous on stream when stats is
  * NULL: a refusal, an overflow or an event-limit condition is then not reported by the
  * status, so pass stats when the inputs or the model may fail.
+ * A run of the specialised kernels (sequential order, M <= 32, S <= 64, n_traj <= 2^27) also
+ * records each trajectory's event count into a device buffer of the model (4 bytes per
+ * trajectory, grown as needed, released by ssa_model_destroy), for ssa_backward_device.
  * Errors: SSA_E_INVALID, SSA_E_NOMEM, SSA_E_DEVICE, SSA_E_OVERFLOW, SSA_E_EVENT_LIMIT,
  * SSA_E_UNSUPPORTED. */
 ssa_status ssa_run_device(const ssa_model *model, const double *rates, const double *log_rates,
@@ -271,7 +274,11 @@ void ssa_run_destroy(ssa_run_state *run);
  * (dL/dmean), mhat [G*S] (centring, usually the forward mean), grad [M] output.  The
  * per-trajectory sums are reduced in a fixed pairwise order, so the result is
  * deterministic.  Device inputs are checked as in ssa_run_device (a refused run gives a
- * NaN gradient and, with stats, SSA_E_INVALID).  Same status codes as ssa_run_device
+ * NaN gradient and, with stats, SSA_E_INVALID).  When the model's last ssa_run_device call
+ * was the same run (same n_traj, t_end, seed, max_events, n_grid and the same grid, rates
+ * and log_rates pointers) and recorded event counts, the trajectories are taken longest
+ * first (stats->ordered); the order changes the time, never a bit of grad, so arrays whose
+ * contents changed since only lose the speed-up.  Same status codes as ssa_run_device
  * (SSA_E_UNSUPPORTED for a SEQ model with more than 32 reactions or with rate laws). */
 ssa_status ssa_backward_device(const ssa_model *model, const double *rates, const double *log_rates,
                                int64_t n_traj, double t_end, const double *grid, int32_t n_grid,
