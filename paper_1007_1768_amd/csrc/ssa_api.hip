@@ -1119,7 +1119,7 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
     }
     FwdKernel k;
     wl.win_bins = window_bins(S, G, !use_jit, tune.win_bytes);
-    wl.win_words = wl.win_bins * S * 2;
+    wl.win_words = wl.win_bins * (use_jit ? win_stride(S * 2) : S * 2);
     // the specialised kernels run generations with one window per wave, the table-driven
     // kernel cohorts with kCohorts windows
     const size_t win_bytes = (size_t)(kBlock / kWave) * wl.win_words * sizeof(long long);
@@ -2046,7 +2046,7 @@ ssa_status ssa_run_cov_device(const ssa_model *m, const double *rates, int64_t n
     int32_t W = 1;
     while (W < 1024 && (size_t)(2 * W) * row * 8 <= window_budget(false) && W < G) W *= 2;
     wl.win_bins = W;
-    wl.win_words = (int32_t)(W * row);
+    wl.win_words = (int32_t)(W * win_stride((int32_t)row));
     const size_t lds = (size_t)(kBlock / kWave) * wl.win_words * sizeof(long long);
     int per_cu = 0;
     HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, jk->fwd_cov, kBlock, lds));

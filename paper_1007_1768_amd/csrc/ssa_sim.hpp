@@ -976,6 +976,12 @@ __device__ __forceinline__ void sim_pc(const WorkList &wl, Policy &p, double *ri
     }
 }
 
+// LDS stride, in 8-byte words, of a window row of row_words words: odd, so that the rows of
+// the bins a wave's lanes are in start on different LDS banks (an even stride such as the
+// 8 words of four species maps every bin to one of a few banks, and lanes in different
+// bins then conflict).
+__host__ __device__ __forceinline__ int32_t win_stride(int32_t row_words) { return row_words | 1; }
+
 // Smallest value over the wave's lanes (uniform result).
 __device__ __forceinline__ int32_t wave_min(int32_t v) {
     for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
@@ -985,8 +991,8 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 // Forward pass by generations (see the header comment): a wave takes one work item, runs
 // its (up to) 64 trajectories to the end with one window that follows the slowest lane,
 // then takes the next item.  The loop is tighter than the cohort form below, which pays
-// off for networks compiled into registers.  win: the wave's LDS window, wl.win_bins bins
-// x S species x (sum nu, sum (2x+nu)nu) as int64.  HIST: with the per-grid-point histogram
+// off for networks compiled into registers.  win: the wave's LDS window, wl.win_bins rows
+// of S species x (sum nu, sum (2x+nu)nu) as int64, at a stride of win_stride(2S) words.  HIST: with the per-grid-point histogram
 // (a separate instantiation, so runs without one carry none of its code).  COV: also the
 // difference sums of the cross products x_s x_r for the species covariance matrix.
 //
@@ -1097,10 +1103,11 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
         // matching high parts
         const int32_t npairs = COV ? S * (S - 1) / 2 : 0;
         const int32_t row_words = S * 2 + npairs;
+        const int32_t wstride = win_stride(row_words);
         const int32_t hi_words = S + npairs;
         unsigned long long *slab =
             SLAB ? wl.slabs + (size_t)wave_slot * (size_t)G * row_words : n0.D;
-        for (int32_t q = lane; q < W * row_words; q += kWave) win[q] = 0;
+        for (int32_t q = lane; q < W * wstride; q += kWave) win[q] = 0;
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
         int32_t base = 0;
@@ -1114,7 +1121,7 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
             const int32_t words = (hi - lo) * row_words;
             for (int32_t e = lane; e < words; e += kWave) {
                 const int32_t bin = lo + e / row_words, r = e - (e / row_words) * row_words;
-                long long *slot = win + (bin & (W - 1)) * row_words + r;
+                long long *slot = win + (bin & (W - 1)) * wstride + r;
                 const long long v = *slot;
                 if (v != 0) {
                     unsigned long long *dst = slab + (size_t)bin * row_words + r;
@@ -1244,7 +1251,7 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
                 }
                 const int32_t bin = binp;
                 const bool inb = bin < G;
-                long long *wrow = win + (bin & (W - 1)) * row_words;
+                long long *wrow = win + (bin & (W - 1)) * wstride;
                 bool big = false;
                 int32_t h_old = 0, h_new = 0;       // HIST: the histogram species before and after
                 p.apply(n, sel, [&](int32_t sp, int32_t xo, int32_t xn) {
