@@ -304,7 +304,9 @@ ssa_status ssa_backward_moments_device(const ssa_model *model, const double *rat
 /* Autotuning of the forward launch (the forward of ssa_run_device, Sections 2 and 3.2.1;
  * the search itself is no step of the paper's method) for this model and problem size: every candidate
  * configuration is timed on the caller's problem (grid [n_grid] device, the same outputs for
- * all: results never depend on the configuration): first the LDS window bytes 2048 .. 16384
+ * all: results never depend on the configuration) by the device time of everything the call
+ * launches (fills, slabs and their reduction included), the best of two calls after a
+ * warm-up: first the LDS window bytes 2048 .. 16384
  * with the windows flushed by atomics or through wave-private slabs, then, with the best
  * window, the launch form of the specialised kernels (two-wave blocks or generations) and
  * its block count (the default and smaller grids).  The fastest is remembered for (device
@@ -316,8 +318,8 @@ ssa_status ssa_backward_moments_device(const ssa_model *model, const double *rat
 typedef struct {
     int32_t win_bytes;
     int32_t slab;
-    float best_ms;      /* kernel time of the chosen configuration */
-    float default_ms;   /* kernel time with the built-in choices */
+    float best_ms;      /* device time of a call with the chosen configuration */
+    float default_ms;   /* device time of a call with the built-in choices */
     int32_t form;       /* ssa_launch_form chosen (0: by launch size) */
     int32_t blocks;     /* grid size chosen (0: the default) */
 } ssa_tune_result;
@@ -330,7 +332,9 @@ ssa_status ssa_autotune_forward(const ssa_model *model, const double *rates, int
  * gradient of Section 4's sensitivity; no step of the paper's method itself): the launch
  * forms of the specialised kernels (two-wave blocks, generations, refilled lanes) at their
  * default grids and at smaller ones are timed on the caller's problem with unit weights
- * (results never depend on the choice), and the fastest is remembered per (architecture,
+ * (results never depend on the choice), after one forward of the same run (so that the
+ * backward takes the order of the lengths it records, as after a forward in use), by the
+ * device time of everything a call launches, and the fastest is remembered per (architecture,
  * kernel kind, network, G and N rounded up to powers of two) for later ssa_backward_device
  * / ssa_backward_moments_device calls, and in SSA_TUNE_FILE.  Other kernels keep their
  * single form.  result may be NULL (win_bytes 0, slab -1).  Synchronous. */

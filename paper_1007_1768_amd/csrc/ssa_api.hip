@@ -838,6 +838,22 @@ struct EventPair {
     }
 };
 
+// Device time of everything one call launches on stream st (fill kernels, scratch set-up,
+// the simulation kernel, reductions, finalize), from events around the call: the tuners
+// compare configurations by it, so that a configuration's extra launches count against it.
+template <class Call>
+ssa_status time_call(hipStream_t st, Call call, float &ms) {
+    EventPair ev;
+    if (!ev.make()) return fail(SSA_E_DEVICE, "hipEventCreate failed");
+    HIP_TRY(hipEventRecord(ev.a, st));
+    const ssa_status s = call();
+    if (s) return s;
+    HIP_TRY(hipEventRecord(ev.b, st));
+    HIP_TRY(hipEventSynchronize(ev.b));
+    HIP_TRY(hipEventElapsedTime(&ms, ev.a, ev.b));
+    return SSA_OK;
+}
+
 // One-trajectory-per-wave kernels (64-chunk sum order).
 // Above kWaveMaxQ reactions per lane: one wave per block, chunk slots in LDS; the
 // dependency-graph update unless SSA_WIDE_DEPG=0 (or no graph was built) asks for the full
@@ -1840,14 +1856,24 @@ ssa_status ssa_autotune_forward(const ssa_model *m, const double *rates, int64_t
     FwdTune best;
     float best_ms = 0.f, default_ms = 0.f;
     ssa_status status = SSA_OK;
+    // a configuration's time: the best of two timed calls after one with statistics (which
+    // warms up, checks the run and reports the grid)
+    auto time_cfg = [&](const FwdTune &c, float &ms, ssa_stats &stt) {
+        status = run_device_impl(m, rates, nullptr, n_traj, t_end, grid, G, seed, 0, mean, var, nullptr, nullptr,
+                                 stream, &stt, &c);
+        for (int rep = 0; rep < 2 && status == SSA_OK; ++rep) {
+            float t = 0.f;
+            status = time_call(st, [&] {
+                return run_device_impl(m, rates, nullptr, n_traj, t_end, grid, G, seed, 0, mean, var, nullptr,
+                                       nullptr, stream, nullptr, &c);
+            }, t);
+            ms = rep ? std::min(ms, t) : t;
+        }
+    };
     for (size_t c = 0; c < cand.size() && status == SSA_OK; ++c) {
         float ms = 0.f;
-        for (int rep = 0; rep < 2 && status == SSA_OK; ++rep) {     // the first run warms up
-            ssa_stats stt;
-            status = run_device_impl(m, rates, nullptr, n_traj, t_end, grid, G, seed, 0, mean, var, nullptr, nullptr, stream,
-                                     &stt, &cand[c]);
-            ms = rep ? std::min(ms, stt.kernel_ms) : stt.kernel_ms;
-        }
+        ssa_stats stt;
+        time_cfg(cand[c], ms, stt);
         if (status) break;
         if (c == 0) default_ms = ms;
         if (c == 0 || ms < best_ms) {
@@ -1872,13 +1898,9 @@ ssa_status ssa_autotune_forward(const ssa_model *m, const double *rates, int64_t
                 if (k2 > 1 && !(c.blocks < b0 && c.blocks < n_items)) continue;
                 if (form == SSA_FORM_TWO_WAVE && (c.slab == 1)) c.slab = 0;   // two-wave blocks flush atomically
                 float ms = 0.f;
-                for (int rep = 0; rep < 2 && status == SSA_OK; ++rep) {
-                    ssa_stats stt;
-                    status = run_device_impl(m, rates, nullptr, n_traj, t_end, grid, G, seed, 0, mean, var, nullptr,
-                                             nullptr, stream, &stt, &c);
-                    ms = rep ? std::min(ms, stt.kernel_ms) : stt.kernel_ms;
-                    if (k2 == 1) b0 = stt.blocks;
-                }
+                ssa_stats stt;
+                time_cfg(c, ms, stt);
+                if (status == SSA_OK && k2 == 1) b0 = stt.blocks;
                 if (status) break;
                 if (ms < best_ms) {
                     best_ms = ms;
@@ -2258,16 +2280,32 @@ ssa_status ssa_autotune_backward(const ssa_model *m, const double *rates, int64_
     HIP_TRY(launch_fill(w, cells, one_bits, st));      // weights and centring: any values time the same work
     HIP_TRY(launch_zero(mhat, sizeof(double) * cells, st));
     ssa_status status = SSA_OK;
-    // time one configuration: best of two runs after one warm-up
+    // a configuration's time: the best of two timed calls after one with statistics
     auto time_cfg = [&](const FwdTune &c, float &ms, ssa_stats &last) {
         ms = 0.f;
-        for (int rep = 0; rep < 3 && status == SSA_OK; ++rep) {
-            status = backward_impl(m, rates, nullptr, n_traj, t_end, grid, G, seed, 0, w, mhat, nullptr, nullptr, grad,
-                                   stream, &last, &c);
-            if (rep == 1) ms = last.kernel_ms;
-            if (rep == 2) ms = std::min(ms, last.kernel_ms);
+        status = backward_impl(m, rates, nullptr, n_traj, t_end, grid, G, seed, 0, w, mhat, nullptr, nullptr, grad,
+                               stream, &last, &c);
+        for (int rep = 0; rep < 2 && status == SSA_OK; ++rep) {
+            float t = 0.f;
+            status = time_call(st, [&] {
+                return backward_impl(m, rates, nullptr, n_traj, t_end, grid, G, seed, 0, w, mhat, nullptr, nullptr,
+                                     grad, stream, nullptr, &c);
+            }, t);
+            ms = rep ? std::min(ms, t) : t;
         }
     };
+    // the forward of the same run first: a backward after it takes the trajectories in the
+    // order of their recorded lengths, as it will in use
+    {
+        double *mv = nullptr;
+        if (hipMallocAsync((void **)&mv, 2 * sizeof(double) * cells, st) != hipSuccess) {
+            status = fail(SSA_E_NOMEM, "autotune scratch");
+        } else {
+            status = run_device_impl(m, rates, nullptr, n_traj, t_end, grid, G, seed, 0, mv, mv + cells, nullptr,
+                                     nullptr, stream, nullptr, nullptr);
+            (void)hipFreeAsync(mv, st);
+        }
+    }
     FwdTune base;
     float default_ms = 0.f;
     ssa_stats s0;
