@@ -522,43 +522,55 @@ __global__ void __launch_bounds__(1024) moment_final_kernel(const unsigned long 
 }
 
 // The same finalize for long point sequences (the adaptive selective memory's Avg-Y), over
-// many blocks: chunks of kFinChunk points per block, which takes the species one after the
-// other (a point's S entries share cache lines, so the later species read them from L2
-// instead of fetching them again from HBM as blocks of one species each did).
+// many blocks: chunks of kFinChunk points per block.  A block takes up to kFinGroup species
+// per pass over its chunk, reading each point's slice of those species at once: a point's
+// S entries share cache lines, and a chunk (96 KB at four species) does not stay in L2 from
+// one species to the next while every CU streams its own chunks.
 // Step 1: the chunk totals of the three difference sums.
 constexpr int kFinChunk = 1024;
-__device__ __forceinline__ void chunk_total_one(const unsigned long long *__restrict__ D,
-                                                const unsigned long long *__restrict__ Dhi, int64_t G, int32_t S,
-                                                long long *__restrict__ T, int64_t c, int32_t s) {
+constexpr int kFinGroup = 4;
+
+__device__ __forceinline__ void chunk_total_group(const unsigned long long *__restrict__ D,
+                                                  const unsigned long long *__restrict__ Dhi, int64_t G, int32_t S,
+                                                  long long *__restrict__ T, int64_t c, int32_t s0, int32_t ns) {
     const int64_t g0 = c * kFinChunk, g1 = min(g0 + kFinChunk, G);
-    int64_t a1 = 0, a2 = 0, a3 = 0;
+    int64_t a[3][kFinGroup];
+#pragma unroll
+    for (int q = 0; q < kFinGroup; ++q) a[0][q] = a[1][q] = a[2][q] = 0;
     for (int64_t g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
-        a1 += (int64_t)D[((size_t)g * S + s) * 2];
-        a2 += (int64_t)D[((size_t)g * S + s) * 2 + 1];
-        a3 += (int64_t)Dhi[(size_t)g * S + s];
+        const unsigned long long *d = D + ((size_t)g * S + s0) * 2;
+        const unsigned long long *h = Dhi + (size_t)g * S + s0;
+#pragma unroll
+        for (int q = 0; q < kFinGroup; ++q) {
+            if (q < ns) {
+                a[0][q] += (int64_t)d[2 * q];
+                a[1][q] += (int64_t)d[2 * q + 1];
+                a[2][q] += (int64_t)h[q];
+            }
+        }
     }
-    __shared__ int64_t sh[3][256];
-    sh[0][threadIdx.x] = a1;
-    sh[1][threadIdx.x] = a2;
-    sh[2][threadIdx.x] = a3;
+    __shared__ int64_t sh[3 * kFinGroup][256];
+#pragma unroll
+    for (int q = 0; q < kFinGroup; ++q)
+        for (int i = 0; i < 3; ++i) sh[i * kFinGroup + q][threadIdx.x] = a[i][q];
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) {
-            sh[0][threadIdx.x] += sh[0][threadIdx.x + off];
-            sh[1][threadIdx.x] += sh[1][threadIdx.x + off];
-            sh[2][threadIdx.x] += sh[2][threadIdx.x + off];
-        }
+        if ((int)threadIdx.x < off)
+            for (int v = 0; v < 3 * kFinGroup; ++v) sh[v][threadIdx.x] += sh[v][threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x < 3) T[((size_t)c * S + s) * 3 + threadIdx.x] = sh[threadIdx.x][0];
+    if ((int)threadIdx.x < 3 * ns) {
+        const int32_t i = threadIdx.x / ns, q = threadIdx.x - i * ns;
+        T[((size_t)c * S + s0 + q) * 3 + i] = sh[i * kFinGroup + q][0];
+    }
 }
 
 __global__ void __launch_bounds__(256) chunk_total_kernel(const unsigned long long *__restrict__ D,
                                                           const unsigned long long *__restrict__ Dhi, int64_t G,
                                                           int32_t S, long long *__restrict__ T) {
-    for (int32_t s = 0; s < S; ++s) {
-        chunk_total_one(D, Dhi, G, S, T, blockIdx.x, s);
-        __syncthreads();                // the shared sums are reused by the next species
+    for (int32_t s0 = 0; s0 < S; s0 += kFinGroup) {
+        chunk_total_group(D, Dhi, G, S, T, blockIdx.x, s0, min(kFinGroup, S - s0));
+        __syncthreads();                // the shared sums are reused by the next group
     }
 }
 
@@ -601,62 +613,73 @@ __global__ void __launch_bounds__(1024) chunk_scan_kernel(long long *__restrict_
 }
 
 // Step 3: within each chunk, the inclusive prefix (4 points per thread, then a block scan)
-// plus the chunk's offset and the initial-state terms, then the moments per point.
-__device__ __forceinline__ void chunk_final_one(const unsigned long long *__restrict__ D,
-                                                const unsigned long long *__restrict__ Dhi, int64_t G, int32_t S,
-                                                const long long *__restrict__ T, const int32_t *__restrict__ x0,
-                                                int64_t n_traj, double *__restrict__ mean, double *__restrict__ var,
-                                                int64_t c, int32_t s) {
+// plus the chunk's offset and the initial-state terms, then the moments per point, for up
+// to kFinGroup species per pass.
+__device__ __forceinline__ void chunk_final_group(const unsigned long long *__restrict__ D,
+                                                  const unsigned long long *__restrict__ Dhi, int64_t G, int32_t S,
+                                                  const long long *__restrict__ T, const int32_t *__restrict__ x0,
+                                                  int64_t n_traj, double *__restrict__ mean, double *__restrict__ var,
+                                                  int64_t c, int32_t s0, int32_t ns) {
     static_assert(kFinChunk == 4 * 256, "four points per thread");
     const int64_t g0 = c * kFinChunk + 4 * (int64_t)threadIdx.x;
-    int64_t v1[4], v2[4], v3[4];
-    int64_t a1 = 0, a2 = 0, a3 = 0;
+    int64_t v[4][3][kFinGroup];
+    int64_t a[3][kFinGroup];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int64_t g = g0 + i;
-        v1[i] = g < G ? (int64_t)D[((size_t)g * S + s) * 2] : 0;
-        v2[i] = g < G ? (int64_t)D[((size_t)g * S + s) * 2 + 1] : 0;
-        v3[i] = g < G ? (int64_t)Dhi[(size_t)g * S + s] : 0;
-        a1 += v1[i];
-        a2 += v2[i];
-        a3 += v3[i];
+    for (int q = 0; q < kFinGroup; ++q) a[0][q] = a[1][q] = a[2][q] = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int64_t g = g0 + k;
+        const unsigned long long *d = D + ((size_t)g * S + s0) * 2;
+        const unsigned long long *h = Dhi + (size_t)g * S + s0;
+#pragma unroll
+        for (int q = 0; q < kFinGroup; ++q) {
+            const bool in = g < G && q < ns;
+            v[k][0][q] = in ? (int64_t)d[2 * q] : 0;
+            v[k][1][q] = in ? (int64_t)d[2 * q + 1] : 0;
+            v[k][2][q] = in ? (int64_t)h[q] : 0;
+            a[0][q] += v[k][0][q];
+            a[1][q] += v[k][1][q];
+            a[2][q] += v[k][2][q];
+        }
     }
-    __shared__ int64_t sh[3][256];
-    sh[0][threadIdx.x] = a1;
-    sh[1][threadIdx.x] = a2;
-    sh[2][threadIdx.x] = a3;
+    // inclusive block scan of the per-thread sums (3 per species)
+    __shared__ int64_t sh[3 * kFinGroup][256];
+#pragma unroll
+    for (int q = 0; q < kFinGroup; ++q)
+        for (int i = 0; i < 3; ++i) sh[i * kFinGroup + q][threadIdx.x] = a[i][q];
     __syncthreads();
     for (int off = 1; off < 256; off <<= 1) {
-        int64_t u1 = 0, u2 = 0, u3 = 0;
-        if ((int)threadIdx.x >= off) {
-            u1 = sh[0][threadIdx.x - off];
-            u2 = sh[1][threadIdx.x - off];
-            u3 = sh[2][threadIdx.x - off];
-        }
+        int64_t u[3 * kFinGroup];
+#pragma unroll
+        for (int x = 0; x < 3 * kFinGroup; ++x) u[x] = (int)threadIdx.x >= off ? sh[x][threadIdx.x - off] : 0;
         __syncthreads();
-        sh[0][threadIdx.x] += u1;
-        sh[1][threadIdx.x] += u2;
-        sh[2][threadIdx.x] += u3;
+#pragma unroll
+        for (int x = 0; x < 3 * kFinGroup; ++x) sh[x][threadIdx.x] += u[x];
         __syncthreads();
     }
-    int64_t c1 = T[((size_t)c * S + s) * 3 + 0] + sh[0][threadIdx.x] - a1;
-    int64_t c2 = T[((size_t)c * S + s) * 3 + 1] + sh[1][threadIdx.x] - a2;
-    int64_t c3 = T[((size_t)c * S + s) * 3 + 2] + sh[2][threadIdx.x] - a3;
-    const int64_t xs = x0[s];
-    const int64_t base1 = n_traj * xs;
-    const i128s base2 = i128_mul_u64(i128_sq(xs), (uint64_t)n_traj);
     const double dn = (double)n_traj;
     const double dd = dn * (double)(n_traj - 1);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int64_t g = g0 + i;
-        c1 += v1[i];
-        c2 += v2[i];
-        c3 += v3[i];
-        if (g < G) {
-            const int64_t sx = base1 + c1;
-            const i128s sx2 = i128_add(i128_add(base2, i128_from(c2)), i128_mul_u64(i128_from(c3), 1ull << 24));
-            moment_point(sx, sx2, n_traj, dn, dd, mean + (size_t)g * S + s, var + (size_t)g * S + s);
+    for (int q = 0; q < kFinGroup; ++q) {
+        if (q >= ns) continue;
+        const int32_t s = s0 + q;
+        int64_t c1 = T[((size_t)c * S + s) * 3 + 0] + sh[0 * kFinGroup + q][threadIdx.x] - a[0][q];
+        int64_t c2 = T[((size_t)c * S + s) * 3 + 1] + sh[1 * kFinGroup + q][threadIdx.x] - a[1][q];
+        int64_t c3 = T[((size_t)c * S + s) * 3 + 2] + sh[2 * kFinGroup + q][threadIdx.x] - a[2][q];
+        const int64_t xs = x0[s];
+        const int64_t base1 = n_traj * xs;
+        const i128s base2 = i128_mul_u64(i128_sq(xs), (uint64_t)n_traj);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int64_t g = g0 + k;
+            c1 += v[k][0][q];
+            c2 += v[k][1][q];
+            c3 += v[k][2][q];
+            if (g < G) {
+                const int64_t sx = base1 + c1;
+                const i128s sx2 = i128_add(i128_add(base2, i128_from(c2)), i128_mul_u64(i128_from(c3), 1ull << 24));
+                moment_point(sx, sx2, n_traj, dn, dd, mean + (size_t)g * S + s, var + (size_t)g * S + s);
+            }
         }
     }
 }
@@ -666,9 +689,9 @@ __global__ void __launch_bounds__(256) chunk_final_kernel(const unsigned long lo
                                                           int32_t S, const long long *__restrict__ T,
                                                           const int32_t *__restrict__ x0, int64_t n_traj,
                                                           double *__restrict__ mean, double *__restrict__ var) {
-    for (int32_t s = 0; s < S; ++s) {
-        chunk_final_one(D, Dhi, G, S, T, x0, n_traj, mean, var, blockIdx.x, s);
-        __syncthreads();                // the shared scan is reused by the next species
+    for (int32_t s0 = 0; s0 < S; s0 += kFinGroup) {
+        chunk_final_group(D, Dhi, G, S, T, x0, n_traj, mean, var, blockIdx.x, s0, min(kFinGroup, S - s0));
+        __syncthreads();                // the shared scan is reused by the next group
     }
 }
 
