@@ -58,6 +58,10 @@ RECORD_CASES = {
     "immigration_death": (inputs.immigration_death(), 1, 100.0, 101, range(0, 200)),
     "viral": (inputs.viral(), 2, 50.0, 1000, range(0, 150)),
     "viral_far_ids": (inputs.viral(), 2, 50.0, 1000, range(10**6 - 70, 10**6)),
+    # trajectory indices across 2^32 and near 2^40: the high word of the Philox counter's
+    # trajectory half is non-zero
+    "viral_ids_across_2_32": (inputs.viral(), 2, 50.0, 1000, range(2**32 - 40, 2**32 + 30)),
+    "viral_ids_2_40": (inputs.viral(), 7, 20.0, 200, range(2**40 + 3, 2**40 + 70)),
     "burst_200": (inputs._model("burst", ["I", "V"], [({"I": 1}, {"I": 1, "V": 200}, 2.0), ({"V": 1}, {}, 0.5),
                                                       ({"I": 1}, {}, 0.3)], [5, 0]), 3, 10.0, 41, range(0, 130)),
     "homodimer": (inputs._model("dimer", ["A", "B"], [({"A": 2}, {"B": 1}, 0.1), ({"B": 1}, {"A": 2}, 1.0)],
