@@ -56,6 +56,21 @@
  *     expect each capture to hold its scratch until then.  A refused call returns before its
  *     first stream operation, so the capture stays usable.  Replays of one graph on two
  *     streams at once share that scratch and race.
+ *   - Environment variables (read at each call; none changes a result bit, only which
+ *     kernel, launch form or buffer size computes it, except where stated):
+ *       SSA_KERNEL=generic        the table-driven kernels instead of the specialised ones
+ *       SSA_LAUNCH_FORM=two_wave|generations|refill   the specialised kernels' launch form
+ *       SSA_DRAW_WAVE=0           no drawing-wave (two-wave) blocks for small launches
+ *       SSA_DRAW_WAVE_BLOCKS=n    at most n two-wave blocks
+ *       SSA_WIN_BYTES=n           LDS bytes of a selective-memory window (512 .. 16384)
+ *       SSA_FWD_FLUSH=slab        windows flushed into wave-private slabs, not by atomics,
+ *       SSA_SLAB_BYTES=n            when the slabs fit in n bytes (default 1 GiB)
+ *       SSA_WIDE_DEPG=0           many-reaction kernels re-evaluate every propensity
+ *       SSA_JAC_BYTES=n           scratch budget of ssa_run_jacobian_device (default 4 GiB)
+ *       SSA_SORT_BINS=n           bins of the adaptive memory's time order
+ *       SSA_ADAPTIVE_RECORDS=n    event-log records per epoch of ssa_adaptive_device
+ *       SSA_BATCH_GRAPH=0         ssa_batch_run launches directly instead of replaying a graph
+ *       SSA_TUNE_FILE=path        autotuner choices kept in and read from a JSON file
  */
 #ifndef SSA_H
 #define SSA_H
