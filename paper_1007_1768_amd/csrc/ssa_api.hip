@@ -214,7 +214,8 @@ struct JitKernels {
                   fwd_cov = nullptr,
                   rec = nullptr, bwd = nullptr, bwd_var = nullptr, evt = nullptr, bwd_gen = nullptr,
                   bwd_var_gen = nullptr, bwd_pc = nullptr, bwd_var_pc = nullptr, fwd_pc = nullptr,
-                  fwd_hist_pc = nullptr, evt_pc = nullptr, fwd_epoch = nullptr, fwd_hist_epoch = nullptr;
+                  fwd_hist_pc = nullptr, evt_pc = nullptr, fwd_epoch = nullptr, fwd_hist_epoch = nullptr,
+                  fwd_epoch_pc = nullptr, fwd_hist_epoch_pc = nullptr;
 };
 
 std::mutex g_jit_mu;
@@ -528,6 +529,8 @@ ssa_status get_jit(const ssa_model *m, int dev, std::shared_ptr<JitKernels> &out
     HIP_TRY(hipModuleGetFunction(&k->fwd_hist_pc, k->module, "ssa_jit_fwd_hist_pc"));
     HIP_TRY(hipModuleGetFunction(&k->fwd_epoch, k->module, "ssa_jit_fwd_epoch"));
     HIP_TRY(hipModuleGetFunction(&k->fwd_hist_epoch, k->module, "ssa_jit_fwd_hist_epoch"));
+    HIP_TRY(hipModuleGetFunction(&k->fwd_epoch_pc, k->module, "ssa_jit_fwd_epoch_pc"));
+    HIP_TRY(hipModuleGetFunction(&k->fwd_hist_epoch_pc, k->module, "ssa_jit_fwd_hist_epoch_pc"));
     HIP_TRY(hipModuleGetFunction(&k->evt_pc, k->module, "ssa_jit_evt_pc"));
     std::lock_guard<std::mutex> lk(g_jit_mu);
     auto ins = g_jit_cache.emplace(key, k);
@@ -1108,8 +1111,8 @@ void tune_store(const ssa_model *m, int64_t n_traj, int32_t G, int dev, bool bac
 // (see want_slabs).  Dhi ([G][S], high parts) must be zero on entry.
 // may_compile false: the specialised kernels only if this device has them compiled already
 // (else the table-driven kernel, with the same results; networks with rate laws then fail).
-// epoch: one epoch of a resumable run (the generations form of the specialised kernels,
-// which saves and resumes trajectory states; D keeps the earlier epochs' sums).
+// epoch: one epoch of a resumable run (the specialised kernels in generations or two-wave
+// blocks, which save and resume trajectory states; D keeps the earlier epochs' sums).
 ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int dev, hipStream_t st,
                           const double *user_rates, Scratch &scr, unsigned long long *D, float *kernel_ms,
                           const FwdTune &tune, bool may_compile = true, bool epoch = false) {
@@ -1152,15 +1155,16 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
         uint32_t want = forced_form();
         if (want == SSA_FORM_NONE && (tune.form == SSA_FORM_TWO_WAVE || tune.form == SSA_FORM_GENERATIONS))
             want = (uint32_t)tune.form;
-        if (epoch) want = SSA_FORM_GENERATIONS;
         const bool two_wave = want == SSA_FORM_TWO_WAVE || (want == SSA_FORM_NONE && pc_launch(n_items, dev));
         if (two_wave) {
-            // one simulating wave per block: one window, flushed atomically into D
-            HIP_TRY(launch_zero(D, (size_t)G * S * 2 * sizeof(unsigned long long), st));
+            // one simulating wave per block: one window, flushed atomically into D (which a
+            // run in epochs keeps from epoch to epoch)
+            if (!epoch) HIP_TRY(launch_zero(D, (size_t)G * S * 2 * sizeof(unsigned long long), st));
+            hipFunction_t f = epoch ? (hist ? jk->fwd_hist_epoch_pc : jk->fwd_epoch_pc)
+                                    : (hist ? jk->fwd_hist_pc : jk->fwd_pc);
             EventPair ev;
             if (kernel_ms && ev.make()) HIP_TRY(hipEventRecord(ev.a, st));
-            HIP_TRY(launch_jit_pc(hist ? jk->fwd_hist_pc : jk->fwd_pc, wl, n_items, dev, st,
-                                  (size_t)wl.win_words * sizeof(long long), tune.blocks));
+            HIP_TRY(launch_jit_pc(f, wl, n_items, dev, st, (size_t)wl.win_words * sizeof(long long), tune.blocks));
             if (kernel_ms && ev.b) {
                 HIP_TRY(hipEventRecord(ev.b, st));
                 HIP_TRY(hipEventSynchronize(ev.b));

@@ -217,6 +217,29 @@ extern "C" __global__ void __launch_bounds__(2 * ssa::kWave) ssa_jit_fwd_hist_pc
     ssa::sim_fwd_gen<ssa_gen::Net::M, false, false, true, ssa::RegPolicy, false, true>(wl, p, ssa_win, ring, kl, ctl);
 }
 
+// One epoch of a run in epochs of simulation time with a drawing wave, without and with the
+// histogram (launches of about one block per CU, such as long horizons over few
+// trajectories).
+extern "C" __global__ void __launch_bounds__(2 * ssa::kWave) ssa_jit_fwd_epoch_pc(ssa::WorkList wl) {
+    extern __shared__ long long ssa_win[];
+    __shared__ double ring[2 * 2 * ssa::kPcRows * ssa::kWave];
+    __shared__ unsigned long long kl[2 * ssa::kWave];
+    __shared__ int32_t ctl[4];
+    ssa::RegPolicy p;
+    ssa::sim_fwd_gen<ssa_gen::Net::M, false, false, false, ssa::RegPolicy, false, true, true>(wl, p, ssa_win, ring, kl,
+                                                                                            ctl);
+}
+
+extern "C" __global__ void __launch_bounds__(2 * ssa::kWave) ssa_jit_fwd_hist_epoch_pc(ssa::WorkList wl) {
+    extern __shared__ long long ssa_win[];
+    __shared__ double ring[2 * 2 * ssa::kPcRows * ssa::kWave];
+    __shared__ unsigned long long kl[2 * ssa::kWave];
+    __shared__ int32_t ctl[4];
+    ssa::RegPolicy p;
+    ssa::sim_fwd_gen<ssa_gen::Net::M, false, false, true, ssa::RegPolicy, false, true, true>(wl, p, ssa_win, ring, kl,
+                                                                                           ctl);
+}
+
 // The event log (adaptive memory) in generations with a drawing wave, for launches of about
 // one block per CU.
 extern "C" __global__ void __launch_bounds__(2 * ssa::kWave) ssa_jit_evt_pc(ssa::WorkList wl) {

@@ -1006,13 +1006,15 @@ __device__ __forceinline__ int32_t wave_min(int32_t v) {
 // being refilled hold draws below K, already consumed.
 // EPOCH: one epoch of a run in epochs of simulation time (resume from n.rs_*, unless NULL,
 // pause before the first event beyond n.t_pause and save into n.ws_*); a template flag so
-// that the other launches carry none of it.
+// that the other launches carry none of it.  With PC the drawing wave starts each lane at
+// its saved draw number K0 (draws are indexed absolutely, so the ring and the published
+// numbers work unchanged).
 template <int MM, bool BATCH, bool SLAB, bool HIST, class Policy, bool COV = false, bool PC = false,
           bool EPOCH = false>
 __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long long *win, double *ring = nullptr,
                                             unsigned long long *kl = nullptr, int32_t *ctl = nullptr) {
     static_assert(!PC || (!BATCH && !SLAB), "the drawing wave serves single-network atomic-flush launches");
-    static_assert(!EPOCH || (!PC && !BATCH && !SLAB && !COV), "epochs run single-network atomic-flush launches");
+    static_assert(!EPOCH || (!BATCH && !SLAB && !COV), "epochs run single-network atomic-flush launches");
     constexpr int MR = MM > 0 ? MM : 1;
     constexpr uint64_t kRing = 2 * kPcRows;
     const uint32_t lane = __lane_id();
@@ -1074,8 +1076,12 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
             if (drawer) {
                 // the drawing wave: draws [F, K + 2 kPcRows) of each lane's trajectory
                 const int64_t dtraj = begin + lane;
-                const bool mine = (int64_t)lane < count;
-                uint64_t F = 0;
+                // an epoch resumes each trajectory at the draw it did not use (one that ended
+                // in an earlier epoch draws nothing)
+                const bool ended = EPOCH && (int64_t)lane < count && n0.rs_t && n0.rs_t[dtraj] < 0.0;
+                const bool mine = (int64_t)lane < count && !ended;
+                uint64_t F = (EPOCH && mine && n0.rs_t) ? n0.rs_k[dtraj] : 0;
+                const uint64_t K0 = F;
                 auto fill_to = [&](uint64_t upto) {
                     if (!mine) return;
                     for (; F < upto; ++F) {
@@ -1086,11 +1092,11 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
                         ring[(kRing + slot) * kWave + lane] = uniform_open1(o.v2, o.v3);
                     }
                 };
-                fill_to(kRing);
+                fill_to(K0 + kRing);
                 __syncthreads();
                 for (int32_t c = 0;; ++c) {
-                    // draw 0 is taken before the first step, so the first steps start at draw 1
-                    const uint64_t K = c == 0 ? 1 : kl[((c - 1) & 1) * kWave + lane];
+                    // draw K0 is taken before the first step, so the first steps start at K0 + 1
+                    const uint64_t K = c == 0 ? K0 + 1 : kl[((c - 1) & 1) * kWave + lane];
                     fill_to(K + kRing);
                     __syncthreads();
                     if (ctl[1 + (c & 1)]) break;

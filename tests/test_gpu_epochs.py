@@ -6,7 +6,9 @@ event beyond the epoch's end and resumes with the draw it did not use.  Cases: e
 arbitrary times (with repeated and backward times, which do nothing), an epoch ending
 exactly at an event time (the event belongs to that epoch), the HIV network of Table 1 with
 its rate laws, trajectories absorbed many epochs before the last, and the errors (finishing
-early, unsupported models).
+early, unsupported models).  Every case runs in both launch forms of the epochs: blocks of
+a simulating and a drawing wave (the drawing wave starting each lane at its saved draw
+number) and generations of one wave each.
 """
 import numpy as np
 import pytest
@@ -28,13 +30,24 @@ def ssa():
     return s
 
 
-def _epochs_vs_single(ssa, m, N, t_end, grid, seed, times, hist=None):
+@pytest.fixture(autouse=True, params=["two_wave", "generations"])
+def form(request, monkeypatch):
+    monkeypatch.setenv("SSA_LAUNCH_FORM", request.param)
+    return request.param
+
+
+def _epochs_vs_single(ssa, m, N, t_end, grid, seed, times, hist=None, form=None):
     model = ssa.Model.from_dict(m)
-    print("epochs N %d t_end %g G %d times %s" % (N, t_end, grid.shape[0], times), flush=True)
+    print("epochs %s N %d t_end %g G %d times %s" % (form, N, t_end, grid.shape[0], times), flush=True)
     run = ssa.Run(model, N, t_end, grid, seed, hist=hist)
     events = 0
+    forms = set()
     for t in times:
-        events += run.advance(t)["events"]
+        sa = run.advance(t)
+        events += sa["events"]
+        forms.add(sa["form"])
+    # advances to a time already reached launch nothing and report no form
+    assert form is None or forms - {"none"} == {form}, (forms, form)
     mean, var, h, st = run.finish()
     run.close()
     m1, v1, h1, s1 = ssa.run_device(model, N, t_end, torch.tensor(grid, device=DEV), seed, hist=hist,
@@ -48,46 +61,47 @@ def _epochs_vs_single(ssa, m, N, t_end, grid, seed, times, hist=None):
     return mean, var, h, st
 
 
-def test_epochs_equal_single_run_and_oracle(ssa):
+def test_epochs_equal_single_run_and_oracle(ssa, form):
     m = inputs.viral()
     N, t_end, G, seed = 3000, 20.0, 200, 17
     grid = inputs.uniform_grid(t_end, G)
     hist = (1, 0, 1, 16)
-    mean, var, h, st = _epochs_vs_single(ssa, m, N, t_end, grid, seed, [3.3, 3.3, 2.0, 7.77, 12.0, 25.0], hist)
+    mean, var, h, st = _epochs_vs_single(ssa, m, N, t_end, grid, seed, [3.3, 3.3, 2.0, 7.77, 12.0, 25.0], hist,
+                                         form=form)
     s, ref = orc.run(m, N, t_end, grid, seed, hist=hist)
     assert s == 0 and ref["events"] == st["events"]
     assert np.array_equal(mean.cpu().numpy(), ref["mean"]) and np.array_equal(var.cpu().numpy(), ref["var"])
     assert np.array_equal(h.cpu().numpy().astype(np.int64), ref["hist"].astype(np.int64))
 
 
-def test_epoch_ending_at_an_event_time(ssa):
+def test_epoch_ending_at_an_event_time(ssa, form):
     m = inputs.viral()
     t_end = 4.0
     s, r = orc.trajectory(m, 5, 0, 2.0, np.array([2.0]))
     assert s == 0
     tl = float(r["t_last"])                      # an event of trajectory 0 happens exactly then
     grid = np.array(sorted([0.0, np.nextafter(tl, 0.0), tl, 3.0, t_end]))
-    _epochs_vs_single(ssa, m, 300, t_end, grid, 5, [tl, np.nextafter(tl, np.inf), t_end])
+    _epochs_vs_single(ssa, m, 300, t_end, grid, 5, [tl, np.nextafter(tl, np.inf), t_end], form=form)
 
 
-def test_epochs_hiv_network(ssa):
+def test_epochs_hiv_network(ssa, form):
     m = inputs.hiv()
     N, t_end, G, seed = 128, 1.0, 21, 7
     grid = inputs.uniform_grid(t_end, G)
-    mean, var, _, st = _epochs_vs_single(ssa, m, N, t_end, grid, seed, [0.1, 0.35, 0.6, 1.0])
+    mean, var, _, st = _epochs_vs_single(ssa, m, N, t_end, grid, seed, [0.1, 0.35, 0.6, 1.0], form=form)
     s, ref = orc.run(m, N, t_end, grid, seed)
     assert s == 0 and ref["events"] == st["events"]
     assert np.array_equal(mean.cpu().numpy(), ref["mean"]) and np.array_equal(var.cpu().numpy(), ref["var"])
 
 
-def test_trajectories_that_end_early_stay_ended(ssa):
+def test_trajectories_that_end_early_stay_ended(ssa, form):
     # pure death from 5: every trajectory is absorbed within a few time units, long before
     # the last of 40 epochs; an ended trajectory must stay ended in both alternating state
     # buffers, whatever the number of epochs after its end
     m = inputs._model("death", ["X"], [({"X": 1}, {}, 1.0)], [5])
     N, t_end, G, seed = 3000, 20.0, 81, 12
     grid = inputs.uniform_grid(t_end, G)
-    mean, var, _, st = _epochs_vs_single(ssa, m, N, t_end, grid, seed, list(np.arange(1, 41) * 0.5))
+    mean, var, _, st = _epochs_vs_single(ssa, m, N, t_end, grid, seed, list(np.arange(1, 41) * 0.5), form=form)
     s, ref = orc.run(m, N, t_end, grid, seed)
     assert s == 0 and ref["events"] == st["events"] == 5 * N
     assert np.array_equal(mean.cpu().numpy(), ref["mean"]) and np.array_equal(var.cpu().numpy(), ref["var"])
