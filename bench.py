@@ -287,12 +287,14 @@ def hiv_long(ssa, torch, dev, N=2048, t_end=4000.0, G=101, seed=7, epoch_days=40
     grid = inputs.uniform_grid(t_end, G)
     run = ssa.Run(model, N, t_end, grid, seed)
     t, events, kms = 0.0, 0, 0.0
+    forms = set()
     a0 = time.perf_counter()
     while t < t_end:
         t = min(t_end, t + epoch_days)
         st = run.advance(t)
         events += st["events"]
         kms += st["kernel_ms"]
+        forms.add((st["form"], st["blocks"]))
         print(json.dumps({"hiv_long_epoch_to_day": t, "events": events, "kernel_ms": round(kms, 1),
                           "max_steps": st["max_steps"], "wall_s": round(time.perf_counter() - a0, 1)}), flush=True)
     mean, var, _, st = run.finish()
@@ -303,6 +305,7 @@ def hiv_long(ssa, torch, dev, N=2048, t_end=4000.0, G=101, seed=7, epoch_days=40
     mv = mean.cpu().numpy()
     return {"workload": "hiv: %d trajectories, t_end %g days, %d-point grid, epochs of %g days"
                         % (N, t_end, G, epoch_days),
+            "launch_forms": sorted(forms),
             "events": st["events"], "max_steps": st["max_steps"], "kernel_ms": round(st["kernel_ms"], 1),
             "wall_s": round(wall, 1), "events_per_s": round(st["events"] / (st["kernel_ms"] * 1e-3), 1),
             "mean_at_end": [round(float(v), 3) for v in mv[-1]]}
