@@ -64,7 +64,7 @@ def load(path=None):
         return _lib
     path = path or LIB_PATH
     if not os.path.exists(path):
-        raise ImportError("libssa.so not built (%s); run __graft_entry__.build()" % path)
+        raise ImportError("libssa.so not built (%s); run python paper_1007_1768_amd/build.py" % path)
     L = ctypes.CDLL(path)
     vp, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
     L.ssa_model_create.argtypes = [i32, i32, vp, vp, vp, vp, i32, ctypes.POINTER(vp)]
