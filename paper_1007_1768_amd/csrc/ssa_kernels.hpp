@@ -1281,6 +1281,10 @@ __global__ void evt_start_kernel(const unsigned long long *__restrict__ key, int
 // times, from 1) - 1 + off (off = 1 when no event happens at time 0, whose point then
 // holds the initial state), in the forward kernels' split (whole (2x+nu)nu below 2^24,
 // else its low 24 bits and the rest >> 24); the first record of a point writes its time.
+// D and Dhi are zero on entry.  A record alone at its point (no other record has its time:
+// an event that changed one species) is the only contribution to its words and stores
+// them; the records of a point with several (several species changed, or equal times) add
+// theirs atomically.
 __global__ void evt_diff_kernel(const unsigned long long *__restrict__ key, const unsigned long long *__restrict__ val,
                                 const int32_t *__restrict__ start, const int32_t *__restrict__ rank1, int64_t R,
                                 int32_t off, int32_t S, unsigned long long *__restrict__ D,
@@ -1292,15 +1296,21 @@ __global__ void evt_diff_kernel(const unsigned long long *__restrict__ key, cons
         const int32_t dl = ((int32_t)(((uint32_t)(v >> 12) & 0xfffffu) << 12)) >> 12;
         const int32_t xo = (int32_t)(uint32_t)(v >> 32);
         unsigned long long *dd = D + ((size_t)u * S + s) * 2;
-        atomicAdd(dd, (unsigned long long)(long long)dl);
         const long long d2 = (2ll * xo + dl) * (long long)dl;
-        if (d2 > -kSmallD2 && d2 < kSmallD2) {
-            atomicAdd(dd + 1, (unsigned long long)d2);
+        const bool small = d2 > -kSmallD2 && d2 < kSmallD2;
+        const unsigned long long lo = (unsigned long long)(small ? d2 : (d2 & ((1ll << 24) - 1)));
+        const bool first = start[r] != 0;
+        const bool alone = first && (r + 1 == R || start[r + 1] != 0);
+        if (alone) {
+            dd[0] = (unsigned long long)(long long)dl;
+            dd[1] = lo;
+            if (!small) Dhi[(size_t)u * S + s] = (unsigned long long)(d2 >> 24);
         } else {
-            atomicAdd(dd + 1, (unsigned long long)(d2 & ((1ll << 24) - 1)));
-            atomicAdd(Dhi + (size_t)u * S + s, (unsigned long long)(d2 >> 24));
+            atomicAdd(dd, (unsigned long long)(long long)dl);
+            atomicAdd(dd + 1, lo);
+            if (!small) atomicAdd(Dhi + (size_t)u * S + s, (unsigned long long)(d2 >> 24));
         }
-        if (start[r]) y_time[u] = __longlong_as_double((long long)key[r]);
+        if (first) y_time[u] = __longlong_as_double((long long)key[r]);
     }
 }
 
