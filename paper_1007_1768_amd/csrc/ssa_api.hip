@@ -2437,13 +2437,18 @@ hipError_t launch_scan(const int32_t *in, int32_t *out, int64_t n, int32_t *sums
     return hipGetLastError();
 }
 
-// Time order of one epoch's event log (see bin_count_kernel): the R records among the
-// first n_slots slots of (key, val), whose times lie in [t0, t1], end sorted by key in the
-// first R slots of (okey, oval).  Scratch: bins [>= B] and big [>= B] int32, n_big one
-// int32, sums as launch_scan's for n = B.  B: about R / 16 bins (SSA_SORT_BINS overrides).
-hipError_t sort_event_log(const unsigned long long *key, const unsigned long long *val, int64_t n_slots, int64_t R,
-                          double t0, double t1, unsigned long long *okey, unsigned long long *oval, int32_t *bins,
-                          int32_t *big, int32_t *n_big, int32_t *sums, int64_t max_bins, hipStream_t st) {
+// Time order of one epoch's event log (see time_bin): the R records among the first
+// n_slots slots of (key, val), whose times lie in [t0, t1], end sorted by key in the first R
+// slots of (okey, oval); (key, val) serve as the radix sort's second buffer and hold no
+// records afterwards.  Scratch: bins [>= B] and big [>= B] int32, n_big one int32, cnt and
+// incl [256 rdx_tiles(n_slots)] int32, sums as launch_scan's for 256 rdx_tiles(n_slots).
+// B: about R / 16 bins (SSA_SORT_BINS overrides).
+int64_t rdx_tiles(int64_t n_slots) { return (n_slots + kRdxTile - 1) / kRdxTile; }
+
+hipError_t sort_event_log(unsigned long long *key, unsigned long long *val, int64_t n_slots, int64_t R, double t0,
+                          double t1, unsigned long long *okey, unsigned long long *oval, int32_t *bins, int32_t *big,
+                          int32_t *n_big, int32_t *cnt, int32_t *incl, int32_t *sums, int64_t max_bins,
+                          hipStream_t st) {
     int64_t B = 1;
     while (B < R / 16 && B < ((int64_t)1 << 25)) B <<= 1;
     if (const char *e = std::getenv("SSA_SORT_BINS")) B = std::max<int64_t>(1, std::strtoll(e, nullptr, 10));
@@ -2453,14 +2458,35 @@ hipError_t sort_event_log(const unsigned long long *key, const unsigned long lon
     tb.scale = t1 > t0 ? (double)B / (t1 - t0) : 0.0;
     tb.B = (int32_t)B;
     tb.pad = 0;
-    hipError_t e = launch_zero(bins, sizeof(int32_t) * (size_t)B, st);
-    if (e == hipSuccess) e = launch_zero(n_big, sizeof(int32_t), st);
+    // bin indices 0 .. B (B: no record) need nbits bits; an odd number of passes of at most
+    // 8 bits each leaves the result in (okey, oval)
+    int32_t nbits = 1;
+    while (((int64_t)1 << nbits) <= B) ++nbits;
+    int32_t passes = (nbits + 7) / 8;
+    if (passes % 2 == 0) ++passes;
+    const int32_t width = (nbits + passes - 1) / passes;
+    const uint32_t mask = (1u << width) - 1u;
+    const int64_t tiles = rdx_tiles(n_slots);
+    unsigned long long *src_k = key, *src_v = val, *dst_k = okey, *dst_v = oval;
+    hipError_t e = hipSuccess;
+    for (int32_t p = 0; p < passes && e == hipSuccess; ++p) {
+        const int32_t shift = p * width;
+        hipLaunchKernelGGL(rdx_count_kernel, dim3((unsigned)tiles), dim3(256), 0, st, (const unsigned long long *)src_k,
+                           n_slots, tb, shift, mask, (int32_t)tiles, cnt);
+        e = launch_scan(cnt, incl, 256 * tiles, sums, st);
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(rdx_scatter_kernel, dim3((unsigned)tiles), dim3(256), 0, st, (const unsigned long long *)src_k,
+                           (const unsigned long long *)src_v, n_slots, tb, shift, mask, width, (int32_t)tiles,
+                           (const int32_t *)cnt, (const int32_t *)incl, dst_k, dst_v);
+        e = hipGetLastError();
+        std::swap(src_k, dst_k);
+        std::swap(src_v, dst_v);
+    }
     if (e != hipSuccess) return e;
-    const unsigned gs = (unsigned)std::min<int64_t>((n_slots + 255) / 256, 8192);
-    hipLaunchKernelGGL(bin_count_kernel, dim3(gs), dim3(256), 0, st, key, n_slots, tb, bins);
-    e = launch_scan(bins, bins, B, sums, st);
+    e = launch_zero(n_big, sizeof(int32_t), st);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(bin_scatter_kernel, dim3(gs), dim3(256), 0, st, key, val, n_slots, tb, bins, okey, oval);
+    const unsigned gs = (unsigned)std::min<int64_t>((R + 1 + 255) / 256, 8192);
+    hipLaunchKernelGGL(bin_start_kernel, dim3(gs), dim3(256), 0, st, (const unsigned long long *)okey, R, tb, bins);
     const unsigned gb = (unsigned)std::min<int64_t>((B + 3) / 4, 8192);
     hipLaunchKernelGGL(bin_sort_small_kernel, dim3(gb), dim3(256), 0, st, okey, oval, (const int32_t *)bins,
                        (int32_t)B, R, big, n_big);
@@ -2578,9 +2604,12 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
     HIP_TRY(scr.alloc(&vals1, sizeof(unsigned long long) * (size_t)slots));
     HIP_TRY(scr.alloc(&stf, sizeof(int32_t) * (size_t)cap));
     HIP_TRY(scr.alloc(&rk, sizeof(int32_t) * (size_t)cap));
-    void *scan_sums = nullptr, *n_big = nullptr;
-    HIP_TRY(scr.alloc(&scan_sums, sizeof(int32_t) * (size_t)(cap / kScanTile + 2)));
+    void *scan_sums = nullptr, *n_big = nullptr, *rdx_cnt = nullptr, *rdx_incl = nullptr;
+    const int64_t rdx_n = 256 * rdx_tiles(slots);
+    HIP_TRY(scr.alloc(&scan_sums, sizeof(int32_t) * (size_t)(std::max<int64_t>(cap, rdx_n) / kScanTile + 2)));
     HIP_TRY(scr.alloc(&n_big, sizeof(int32_t)));
+    HIP_TRY(scr.alloc(&rdx_cnt, sizeof(int32_t) * (size_t)rdx_n));
+    HIP_TRY(scr.alloc(&rdx_incl, sizeof(int32_t) * (size_t)rdx_n));
     // epochs: saved trajectory states, double-buffered
     void *sx[2] = {nullptr, nullptr}, *stt[2] = {nullptr, nullptr}, *skk[2] = {nullptr, nullptr},
          *sev[2] = {nullptr, nullptr};
@@ -2652,9 +2681,10 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
         unsigned long long first_key = 0;
         if (R > 0) {
             // bins and the big-bin list borrow the rank arrays (both >= R >= the bin count)
-            HIP_TRY(sort_event_log((const unsigned long long *)keys0, (const unsigned long long *)vals0, nSlots,
-                                   (int64_t)R, t0, t1, (unsigned long long *)keys1, (unsigned long long *)vals1,
-                                   (int32_t *)rk, (int32_t *)stf, (int32_t *)n_big, (int32_t *)scan_sums, cap, st));
+            HIP_TRY(sort_event_log((unsigned long long *)keys0, (unsigned long long *)vals0, nSlots, (int64_t)R, t0, t1,
+                                   (unsigned long long *)keys1, (unsigned long long *)vals1, (int32_t *)rk,
+                                   (int32_t *)stf, (int32_t *)n_big, (int32_t *)rdx_cnt, (int32_t *)rdx_incl,
+                                   (int32_t *)scan_sums, cap, st));
             const unsigned gb = (unsigned)std::min<int64_t>(((int64_t)R + 255) / 256, 65535);
             hipLaunchKernelGGL(evt_start_kernel, dim3(gb), dim3(256), 0, st, (const unsigned long long *)keys1,
                                (int64_t)R, (int32_t *)stf);

@@ -1102,12 +1102,12 @@ __global__ void __launch_bounds__(256) len_scatter_kernel(const uint32_t *__rest
 // times of one epoch, in [t0, t1] (non-negative binary64 values order like their bits), or
 // ~0 for a slot no record took.  A bucket sort by time: bin(t) = floor((t - t0) * scale),
 // clamped to [0, B - 1], is monotone in t, so every key of bin b is at most every key of
-// bin b + 1; the records are counted per bin, the counts scanned, each record scattered
-// into its bin's range (slots without a record are dropped), and then every bin is sorted
-// by key -- by one wave (rank by counting) up to 64 records, else by one block (bitonic
-// network with ascending comparators only, in LDS up to kBinLds records, in global memory
-// beyond).  Records with equal keys end in any order: only the distinct times and the
-// integer sums of their records are used.
+// bin b + 1; the records are put in bin order (slots without a record last), each bin's
+// first position is marked, and then every bin is sorted by key -- by one wave (rank by
+// counting) up to 64 records, else by one block (bitonic network with ascending
+// comparators only, in LDS up to kBinLds records, in global memory beyond).  Records with
+// equal keys end in any order: only the distinct times and the integer sums of their
+// records are used.
 // ---------------------------------------------------------------------------------------
 struct TimeBins {
     double t0, scale;
@@ -1122,44 +1122,126 @@ __device__ __forceinline__ int32_t time_bin(const TimeBins &tb, unsigned long lo
     return f > 0.0 ? (f < (double)tb.B ? (int32_t)f : tb.B - 1) : 0;
 }
 
-__global__ void __launch_bounds__(256) bin_count_kernel(const unsigned long long *__restrict__ key, int64_t n,
-                                                        TimeBins tb, int32_t *__restrict__ cnt) {
-    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += (int64_t)gridDim.x * blockDim.x) {
-        const unsigned long long k = key[r];
-        if (k != kNoRecord) atomicAdd(cnt + time_bin(tb, k), 1);
+// The records are first put in bin order by a stable least-significant-digit radix sort on
+// the bin index (a slot without a record has bin B, after every bin), kRdxTile records per
+// block and pass: rdx_count_kernel counts each tile's digits, their prefix sum in digit-major
+// order gives every (digit, tile) its first output position, and rdx_scatter_kernel ranks
+// each record within its tile (chunks of 256 in slot order; lanes of one digit matched by
+// ballots, so equal digits keep their order), stages the tile in LDS in digit order and
+// writes each digit's run contiguously.  No global atomic is taken.
+constexpr int kRdxTile = 4096;
+
+__device__ __forceinline__ uint32_t rdx_digit(const TimeBins &tb, unsigned long long k, int32_t shift,
+                                              uint32_t mask) {
+    const uint32_t b = k == kNoRecord ? (uint32_t)tb.B : (uint32_t)time_bin(tb, k);
+    return (b >> shift) & mask;
+}
+
+// cnt[d * n_tiles + t]: records of tile t whose digit is d (256 digits; those above the
+// pass's width count 0).
+__global__ void __launch_bounds__(256) rdx_count_kernel(const unsigned long long *__restrict__ key, int64_t n,
+                                                        TimeBins tb, int32_t shift, uint32_t mask, int32_t n_tiles,
+                                                        int32_t *__restrict__ cnt) {
+    __shared__ int32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t t0 = (int64_t)blockIdx.x * kRdxTile, t1 = min(t0 + (int64_t)kRdxTile, n);
+    for (int64_t i = t0 + threadIdx.x; i < t1; i += blockDim.x) atomicAdd(&h[rdx_digit(tb, key[i], shift, mask)], 1);
+    __syncthreads();
+    cnt[(int64_t)threadIdx.x * n_tiles + blockIdx.x] = h[threadIdx.x];
+}
+
+// incl: the inclusive prefix sum of cnt.  Moves tile blockIdx.x of (key, val) to its place
+// in (okey, oval) for this pass's digit.
+__global__ void __launch_bounds__(256) rdx_scatter_kernel(const unsigned long long *__restrict__ key,
+                                                          const unsigned long long *__restrict__ val, int64_t n,
+                                                          TimeBins tb, int32_t shift, uint32_t mask, int32_t bits,
+                                                          int32_t n_tiles, const int32_t *__restrict__ cnt,
+                                                          const int32_t *__restrict__ incl,
+                                                          unsigned long long *__restrict__ okey,
+                                                          unsigned long long *__restrict__ oval) {
+    __shared__ unsigned long long sk[kRdxTile], sv[kRdxTile];
+    __shared__ int32_t first[256];      // the tile's first local position of each digit
+    __shared__ int32_t run[256];        // the next local position of each digit
+    __shared__ int32_t wcnt[4][256];    // per wave: records of each digit in the chunk, then offsets
+    const int32_t t = threadIdx.x, w = t / kWave;
+    const uint32_t lane = __lane_id();
+    const int64_t t0 = (int64_t)blockIdx.x * kRdxTile, t1 = min(t0 + (int64_t)kRdxTile, n);
+    // exclusive prefix of this tile's digit counts (Hillis-Steele over 256 digits)
+    const int32_t mine = cnt[(int64_t)t * n_tiles + blockIdx.x];
+    first[t] = mine;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const int32_t x = t >= off ? first[t - off] : 0;
+        __syncthreads();
+        first[t] += x;
+        __syncthreads();
+    }
+    const int32_t excl = first[t] - mine;
+    __syncthreads();
+    first[t] = excl;
+    run[t] = excl;
+    __syncthreads();
+    for (int64_t c = t0; c < t1; c += 256) {
+        for (int q = t; q < 4 * 256; q += 256) wcnt[q / 256][q % 256] = 0;
+        __syncthreads();
+        const int64_t i = c + t;
+        const bool in = i < t1;
+        const unsigned long long k = in ? key[i] : kNoRecord;
+        const unsigned long long v = in ? val[i] : 0ull;
+        const uint32_t d = in ? rdx_digit(tb, k, shift, mask) : 0u;
+        uint64_t same = __ballot(in);
+        for (int32_t b = 0; b < bits; ++b) {
+            const bool one = ((d >> b) & 1u) != 0u;
+            const uint64_t bb = __ballot(one);
+            same &= one ? bb : ~bb;
+        }
+        const int32_t rank = __popcll(same & lanemask_lt());
+        if (in && rank == 0) wcnt[w][d] = __popcll(same);
+        __syncthreads();
+        {
+            // digit t: the waves' first positions in this chunk, in wave order
+            int32_t r = run[t];
+            for (int q = 0; q < 4; ++q) {
+                const int32_t m = wcnt[q][t];
+                wcnt[q][t] = r;
+                r += m;
+            }
+            run[t] = r;
+        }
+        __syncthreads();
+        if (in) {
+            const int32_t lp = wcnt[w][d] + rank;
+            sk[lp] = k;
+            sv[lp] = v;
+        }
+        __syncthreads();
+    }
+    // the staged tile in digit order: position j of digit d goes to the digit's first output
+    // position for this tile plus (j - first[d])
+    const int32_t tn = (int32_t)(t1 - t0);
+    for (int32_t j = t; j < tn; j += blockDim.x) {
+        const unsigned long long k = sk[j];
+        const uint32_t d = rdx_digit(tb, k, shift, mask);
+        const int64_t q = (int64_t)d * n_tiles + blockIdx.x;
+        const int64_t dst = (int64_t)incl[q] - cnt[q] + (j - first[d]);
+        if (dst >= 0 && dst < n) {
+            okey[dst] = k;
+            oval[dst] = sv[j];
+        }
     }
 }
 
-// cur: the inclusive scan of the counts on entry; each record takes the slot below its
-// bin's cursor, so on exit cur[b] is the first slot of bin b.  A thread takes kScatterPer
-// records at once, so their cursor atomics are in flight together before the dependent
-// stores.
-constexpr int kScatterPer = 4;
-__global__ void __launch_bounds__(256) bin_scatter_kernel(const unsigned long long *__restrict__ key,
-                                                          const unsigned long long *__restrict__ val, int64_t n,
-                                                          TimeBins tb, int32_t *__restrict__ cur,
-                                                          unsigned long long *__restrict__ okey,
-                                                          unsigned long long *__restrict__ oval) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t r0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r0 < n; r0 += kScatterPer * stride) {
-        unsigned long long k[kScatterPer], v[kScatterPer];
-        int32_t p[kScatterPer];
-#pragma unroll
-        for (int i = 0; i < kScatterPer; ++i) {
-            const int64_t r = r0 + i * stride;
-            k[i] = r < n ? key[r] : kNoRecord;
-            v[i] = r < n ? val[r] : 0ull;
-        }
-#pragma unroll
-        for (int i = 0; i < kScatterPer; ++i)
-            p[i] = k[i] != kNoRecord ? atomicSub(cur + time_bin(tb, k[i]), 1) - 1 : -1;
-#pragma unroll
-        for (int i = 0; i < kScatterPer; ++i) {
-            if (p[i] >= 0) {
-                okey[p[i]] = k[i];
-                oval[p[i]] = v[i];
-            }
-        }
+// start[b]: the first position of bin b among the R records sorted by bin (R for the bins
+// after the last record); every bin is written once, by the record that starts it or the
+// sentinel position R.
+__global__ void __launch_bounds__(256) bin_start_kernel(const unsigned long long *__restrict__ key, int64_t R,
+                                                        TimeBins tb, int32_t *__restrict__ start) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= R; i += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t b = i < R ? time_bin(tb, key[i]) : tb.B;
+        const int32_t bp = i > 0 ? time_bin(tb, key[i - 1]) : -1;
+        const int32_t hi = min(b, tb.B - 1);
+        for (int32_t x = bp + 1; x <= hi; ++x) start[x] = (int32_t)i;
     }
 }
 
