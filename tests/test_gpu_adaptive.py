@@ -194,9 +194,10 @@ def test_adaptive_64_chunk_order(ssa, monkeypatch, make, N, t_end, seed, k, epoc
 @pytest.mark.parametrize("bins", ["1", "5", "300"])
 @pytest.mark.parametrize("case", ["viral", "immigration_death", "closed"])
 def test_adaptive_time_order_paths(ssa, monkeypatch, bins, case):
-    """The time order of the event log with forced bin counts, so every path of the bucket
-    sort runs: one bin for the whole log (a block-wide network in global memory, beyond
-    2048 records), a few bins (networks in LDS), many bins (wave-sized bins)."""
+    """The time order of the event log with forced bin counts, so every path runs: one bin
+    for the whole log (one radix pass; a block-wide network in global memory, beyond 2048
+    records), a few bins (networks in LDS), many bins (wave-sized bins; 300 bins take three
+    radix passes of 3 bits, an odd count so the result lands in the output buffers)."""
     monkeypatch.setenv("SSA_SORT_BINS", bins)
     make, N, t_end, seed, k = CASES[case]
     m = make()
