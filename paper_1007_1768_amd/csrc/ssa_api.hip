@@ -2753,7 +2753,7 @@ ssa_status ssa_adaptive_device(const ssa_model *m, const double *rates, int64_t 
             const int64_t P_e = last ? (W + k - 1) / k : W / k;
             if (xy_time && P_e > 0 && P_done + P_e <= xy_cap) {
                 hipLaunchKernelGGL(xy_kernel, dim3((unsigned)P_e, (unsigned)((2 * S + 1 + kWave - 1) / kWave)),
-                                   dim3(kWave), 0, st,
+                                   dim3(kXyThreads), 0, st,
                                    (const double *)wt, (const double *)wm, (const double *)wv, W, S, k, P_e,
                                    xy_time + P_done, xy_mean + P_done * S, xy_var + P_done * S);
                 HIP_TRY(hipGetLastError());

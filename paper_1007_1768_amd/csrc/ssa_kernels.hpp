@@ -1398,37 +1398,40 @@ __global__ void evt_diff_kernel(const unsigned long long *__restrict__ key, cons
 
 // Avg-XY: groups of k successive Avg-Y points (the last one may be shorter).  A group has
 // C = 2S + 1 chains -- the time, S means and S variances -- each summed left to right in
-// binary64 and then divided once by the group's size.  One wave per group (and per 64
-// chains): the wave copies the group's points tile by tile into LDS with coalesced loads of
-// whole rows, and lane j adds chain j of the tile in order while the loads of the next tile
-// are in flight.  A wave per chain, adding 64 lane broadcasts in a row, spent most of the
-// adaptive run at k = 10^6 on that serial chain.
-constexpr int kXyRegs = 36;                 // doubles per lane staged for the next tile
-constexpr int kXyTile = kXyRegs * kWave;    // doubles per tile: T points of C values
+// binary64 and then divided once by the group's size.  One block of four waves per group
+// (and per 64 chains): the block copies the group's points tile by tile into LDS with
+// coalesced loads of whole rows, and lane j of the first wave adds chain j of the tile in
+// order while the loads of the next tile are in flight (four waves keep more bytes in
+// flight than one wave's loads alone could behind the adds).  A wave per chain, adding 64
+// lane broadcasts in a row, spent most of the adaptive run at k = 10^6 on that serial
+// chain.
+constexpr int kXyRegs = 16;                 // doubles per thread staged for the next tile
+constexpr int kXyThreads = 4 * kWave;       // threads per block: all load, the first wave adds
+constexpr int kXyTile = kXyRegs * kXyThreads;   // doubles per tile: T points of C values
 constexpr int kXyBatch = 16;                // LDS reads of a chain in flight together
 
-__global__ void __launch_bounds__(64) xy_kernel(const double *__restrict__ y_time, const double *__restrict__ y_mean,
+__global__ void __launch_bounds__(kXyThreads) xy_kernel(const double *__restrict__ y_time, const double *__restrict__ y_mean,
                                                 const double *__restrict__ y_var, int64_t U, int32_t S, int64_t k,
                                                 int64_t P, double *__restrict__ xy_time,
                                                 double *__restrict__ xy_mean, double *__restrict__ xy_var) {
     __shared__ double tile[kXyTile];
     const int64_t p = blockIdx.x;
-    const int32_t lane = (int32_t)threadIdx.x;
+    const int32_t tid = (int32_t)threadIdx.x, lane = tid % kWave;
     if (p >= P) return;
     const int32_t C = 2 * S + 1;
-    const int32_t T = kXyTile / C;          // points per tile, >= 1 for S <= 1151
+    const int32_t T = kXyTile / C;          // points per tile, >= 1 for S <= 2047
     const int32_t TS = T * S;
     const int64_t u0 = p * k, u1 = min(u0 + k, U);
     // tile layout: times at [0, T), means at [T, T + T*S), variances at [T + T*S, T*C),
     // each in the row-major order of the source arrays
-    // staged slot r of this lane: its source (time row, or a mean or variance entry) is the
-    // same for every tile; only the tile's first point and its point count change
+    // staged slot r of this thread: its source (time row, or a mean or variance entry) is
+    // the same for every tile; only the tile's first point and its point count change
     const double *pb[kXyRegs];
     int32_t po[kXyRegs];
     bool pt[kXyRegs];
 #pragma unroll
     for (int32_t r = 0; r < kXyRegs; ++r) {
-        const int32_t f = lane + r * kWave;
+        const int32_t f = tid + r * kXyThreads;
         pt[r] = f < T;
         if (f < T) {
             pb[r] = y_time + f;
@@ -1445,8 +1448,8 @@ __global__ void __launch_bounds__(64) xy_kernel(const double *__restrict__ y_tim
         }
     }
     double nx[kXyRegs];
-    // every lane loads (slots past the tile's points read y_time[0] and keep 0), so the loads
-    // stay unconditional and all of them are in flight together
+    // every thread loads (slots past the tile's points read y_time[0] and keep 0), so the
+    // loads stay unconditional and all of them are in flight together
     auto fetch = [&](int64_t base) {
         const int32_t n = (int32_t)min((int64_t)T, u1 - base), nS = n * S;
         const int64_t bS = base * S;
@@ -1457,8 +1460,8 @@ __global__ void __launch_bounds__(64) xy_kernel(const double *__restrict__ y_tim
             nx[r] = ok ? v : 0.0;
         }
     };
-    const int32_t j = (int32_t)blockIdx.y * kWave + lane;   // this lane's chain
-    const bool act = j < C;
+    const int32_t j = (int32_t)blockIdx.y * kWave + lane;   // this lane's chain (first wave)
+    const bool act = tid < kWave && j < C;
     int32_t off = 0, stride = 1;
     if (j >= 1 && j <= S) {
         off = T + (j - 1);
@@ -1472,7 +1475,7 @@ __global__ void __launch_bounds__(64) xy_kernel(const double *__restrict__ y_tim
     for (int64_t base = u0; base < u1; base += T) {
         __syncthreads();                    // every chain is done with the previous tile
 #pragma unroll
-        for (int32_t r = 0; r < kXyRegs; ++r) tile[lane + r * kWave] = nx[r];
+        for (int32_t r = 0; r < kXyRegs; ++r) tile[tid + r * kXyThreads] = nx[r];
         __syncthreads();
         if (base + T < u1) fetch(base + T);
         const int32_t n = (int32_t)min((int64_t)T, u1 - base);
