@@ -133,8 +133,8 @@ typedef struct {
     float kernel_ms;      /* device time of the simulation kernel(s) */
     uint32_t form;        /* ssa_launch_form of the simulation kernel */
     uint32_t blocks;      /* its grid size in blocks */
-    uint32_t ordered;     /* backward: 1 when its trajectories ran longest first, in the order of
-                             the event counts a forward over the same trajectories recorded */
+    uint32_t ordered;     /* 1 when the trajectories ran longest first, in the order of the event
+                             counts an earlier forward over the same trajectories recorded */
 } ssa_stats;
 
 /* Model (Section 3.2 model format).
@@ -222,6 +222,10 @@ ssa_status ssa_rates_from_log(const double *log_rates, int32_t n, double *rates,
  * A run of the specialised kernels (sequential order, M <= 32, S <= 64, n_traj <= 2^27) also
  * records each trajectory's event count into a device buffer of the model (4 bytes per
  * trajectory, grown as needed, released by ssa_model_destroy), for ssa_backward_device.
+ * When the record is that of a run with the same n_traj, t_end, seed and max_events (the
+ * rates may differ: a fit's previous step), a forward in generations takes its trajectories
+ * longest first by it (stats->ordered); the sums are exact integers, so the order changes
+ * the time, never a bit of the outputs.
  * Errors: SSA_E_INVALID, SSA_E_NOMEM, SSA_E_DEVICE, SSA_E_OVERFLOW, SSA_E_EVENT_LIMIT,
  * SSA_E_UNSUPPORTED. */
 ssa_status ssa_run_device(const ssa_model *model, const double *rates, const double *log_rates,

@@ -711,7 +711,7 @@ hipError_t fwd_blocks(const FwdKernel &k, bool slab, int dev, int64_t n_items, i
 // most one work item per CU
 hipError_t fwd_launch(const FwdKernel &k, bool slab, int64_t blocks, WorkList &wl, hipStream_t st,
                       bool lone = false) {
-    note_launch(k.jit ? SSA_FORM_GENERATIONS : SSA_FORM_TABLE, blocks);
+    note_launch(k.jit ? SSA_FORM_GENERATIONS : SSA_FORM_TABLE, blocks, wl.perm != nullptr);
     if (k.jit) {
         void *args[] = {&wl};
         if (lone)
@@ -1113,9 +1113,14 @@ void tune_store(const ssa_model *m, int64_t n_traj, int32_t G, int dev, bool bac
 // (else the table-driven kernel, with the same results; networks with rate laws then fail).
 // epoch: one epoch of a resumable run (the specialised kernels in generations or two-wave
 // blocks, which save and resume trajectory states; D keeps the earlier epochs' sums).
+ssa_status order_by_key(const uint32_t *key, int64_t n, Scratch &scr, hipStream_t st, const uint32_t **out);
+
+// order_keys: event counts a previous forward recorded for these positions, or NULL; a
+// specialised forward in generations then takes its trajectories longest first
 ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int dev, hipStream_t st,
                           const double *user_rates, Scratch &scr, unsigned long long *D, float *kernel_ms,
-                          const FwdTune &tune, bool may_compile = true, bool epoch = false) {
+                          const FwdTune &tune, bool may_compile = true, bool epoch = false,
+                          const uint32_t *order_keys = nullptr) {
     const int32_t G = wl.net0.G, S = m->S;
     if (epoch && (m->order != SSA_SUM_SEQ || !jit_eligible(m)))
         return fail(SSA_E_UNSUPPORTED, "runs in epochs need the specialised kernels (sequential order, at most %d "
@@ -1191,6 +1196,10 @@ ssa_status launch_forward(const ssa_model *m, WorkList &wl, int64_t n_items, int
                         "the sequential-order kernel needs %zu bytes of LDS for %d species and %d reactions "
                         "(limit %zu); the 64-chunk order runs such networks",
                         k.lds, S, m->M, lds_max(dev));
+    }
+    if (k.jit && order_keys && !epoch && wl.range_begin == 0) {
+        const ssa_status s = order_by_key(order_keys, wl.range_end, scr, st, &wl.perm);
+        if (s) return s;
     }
     const size_t cell_words = (size_t)G * S * 2;
     int64_t blocks = 0;
@@ -1503,6 +1512,17 @@ ssa_status hint_order(const ssa_model *m, const RunId &id, Scratch &scr, hipStre
     return order_by_key(len, id.n, scr, st, out);
 }
 
+// The event counts a forward of run id may take its trajectories in order of, or NULL: those
+// of the last recorded forward with the same trajectory count, horizon, seed and event cap
+// (the rates may have changed since: the counts are then a close hint, never a result).
+const uint32_t *fwd_hint(const ssa_model *m, const RunId &id) {
+    if (id.n > kMaxHintTraj) return nullptr;
+    std::lock_guard<std::mutex> lk(m->hint_mu);
+    const bool same = m->hint_valid && m->hint_n == id.n && m->hint_t_end == id.t_end && m->hint_seed == id.seed &&
+                      m->hint_max_events == id.max_events && m->hint_dev == id.dev;
+    return same ? m->hint_len : nullptr;
+}
+
 // Launch form of the specialised backward: two-wave blocks up to two work items per CU,
 // else generations; a tuned form, then SSA_LAUNCH_FORM, replace it (as launch_single does).
 uint32_t bwd_form(int64_t n_items, int dev, int32_t tuned_form) {
@@ -1586,6 +1606,7 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, const double
         n.h_lo = hist->lo;
         n.h_width = hist->width;
     }
+    const uint32_t *order_keys = fixed ? nullptr : fwd_hint(m, rid);
     n.len_out = fixed ? nullptr : hint_begin(m, rid, cap);
     WorkList wl;
     std::memset(&wl, 0, sizeof wl);
@@ -1600,7 +1621,7 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, const double
     FwdTune cfg = tune ? *tune : (fixed ? FwdTune() : tune_lookup(m, n_traj, G, dev));
     if (fixed) cfg.slab = 0;
     s = launch_forward(m, wl, n_items, dev, st, rates, scr, n.D, (stats && !fixed) ? &kms : nullptr, cfg,
-                       !fixed && !cap);
+                       !fixed && !cap, false, order_keys);
     if (n.len_out && !cap) hint_end(m, rid, s == SSA_OK && g_launch.form == SSA_FORM_GENERATIONS);
     if (s) return s;
     HIP_TRY(launch_finalize(n.D, n.Dhi, G, m->S, m->d_x0, n_traj, mean, var, ctl_status(ctl), st));

@@ -198,9 +198,10 @@ struct WorkList {
     double *jac_slabs;           // forward with Jacobian: [items][G][S+1][M] per-work-item sums
     unsigned int *counter;       // work-item counter (zeroed before launch)
     unsigned long long *stats;   // [0] events, [1] max steps, [2] flags
-    // single-network record / backward / event log: the trajectory at each position of
-    // [range_begin, range_end), or NULL for the positions themselves (any order gives the
-    // same results: a trajectory keeps its index, its random numbers and its output row)
+    // single-network forward in generations, record, backward, event log: the trajectory at
+    // each position of [range_begin, range_end), or NULL for the positions themselves (any
+    // order gives the same results: a trajectory keeps its index, its random numbers and its
+    // output row)
     const uint32_t *perm;
 };
 
@@ -1142,7 +1143,10 @@ __device__ __forceinline__ void sim_fwd_gen(const WorkList &wl, Policy &p, long 
 
         // lane state; every active lane holds a drawn event at t_next (bin binp) to apply
         bool active = (int64_t)lane < count;
-        const int64_t traj = begin + lane;
+        // a single-network forward in generations may take its positions in an order of
+        // recorded lengths (a permutation: the sums are exact integers, so order changes no bit)
+        const int64_t traj = (!BATCH && !PC && !EPOCH && wl.perm && active) ? (int64_t)wl.perm[begin + lane]
+                                                                            : begin + lane;
         double t = 0.0, t_next = 0.0, u = 0.0;
         double tg_next = gv.uniform ? 0.0 : ((const SSA_CONST double *)gv.grid)[0];
         uint64_t k = 0, ev = 0, ev_start = 0;

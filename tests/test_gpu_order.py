@@ -1,20 +1,24 @@
-"""GPU checks of the backward's trajectory order.
+"""GPU checks of the trajectory order of the backward and the forward.
 
 A forward in generations records every trajectory's event count; a backward of the same
 run (trajectory count, horizon, seed, event cap, grid and rate arrays) then takes its
-trajectories longest first.  The order must never change a bit of the gradient: each
-trajectory keeps its index, its Philox stream and its row of the fixed-order reduction.
+trajectories longest first, and so does a later forward with the same trajectory count,
+horizon, seed and event cap (its rates may differ).  The order must never change a bit:
+each trajectory keeps its index, its Philox stream and its row of the fixed-order
+reduction, and the forward's sums are exact integers.
 Cases: without and with a recorded order (mean and variance weights, generations and
 refilled lanes); a backward of another run (other seed, other grid array, other trajectory
 count) ignores the record; a record gone stale (rates changed in place after the forward)
 is still used and still gives the exact gradient; two models keep their own records; the
-statistics say which order ran.
+forward in recorded order gives the moments and histogram of an unordered one, also under
+other rates, and matches the CPU oracle; the statistics say which order ran.
 """
 import os
 
 import numpy as np
 import pytest
 
+from oracle import oracle as orc
 from paper_1007_1768_amd import inputs
 
 torch = pytest.importorskip("torch")
@@ -123,3 +127,55 @@ def test_models_keep_their_own_records(ssa):
     assert torch.equal(ga, gb)
     a.close()
     b.close()
+
+
+def test_forward_in_recorded_order_gives_the_same_outputs(ssa):
+    m = inputs.viral()
+    grid = _t(inputs.uniform_grid(T_END, G))
+    hist = (1, 0, 1, 64)
+    model = ssa.Model.from_dict(m)
+    print("forward order: record, ordered, other rates, other seed", flush=True)
+    a = ssa.run_device(model, N, T_END, grid, SEED, hist=hist, with_stats=True)
+    b = ssa.run_device(model, N, T_END, grid, SEED, hist=hist, with_stats=True)
+    torch.cuda.synchronize()
+    assert a[3]["form"] == b[3]["form"] == "generations", (a[3], b[3])
+    assert not a[3]["ordered"] and b[3]["ordered"], (a[3], b[3])
+    assert a[3]["events"] == b[3]["events"]
+    for x, y in zip(a[:3], b[:3]):
+        assert torch.equal(x, y)
+    # a fit's next step: the same trajectories under other rates, ordered by the old counts
+    rates = _t(np.asarray(m["rates"]) * np.exp(np.random.default_rng(8).normal(0.0, 0.3, 9)))
+    c = ssa.run_device(model, N, T_END, grid, SEED, hist=hist, rates=rates, with_stats=True)
+    ref = ssa.Model.from_dict(m)                      # a model with no record
+    r = ssa.run_device(ref, N, T_END, grid, SEED, hist=hist, rates=rates, with_stats=True)
+    # another seed: other trajectories, the record is not used
+    d = ssa.run_device(model, N, T_END, grid, SEED + 1, hist=hist, with_stats=True)
+    e = ssa.run_device(ref, N, T_END, grid, SEED + 1, hist=hist, with_stats=True)
+    torch.cuda.synchronize()
+    ref.close()
+    model.close()
+    assert c[3]["ordered"] and not r[3]["ordered"], (c[3], r[3])
+    assert not d[3]["ordered"] and not e[3]["ordered"], (d[3], e[3])
+    assert c[3]["events"] == r[3]["events"] and d[3]["events"] == e[3]["events"]
+    for x, y in list(zip(c[:3], r[:3])) + list(zip(d[:3], e[:3])):
+        assert torch.equal(x, y)
+
+
+def test_forward_in_recorded_order_matches_the_oracle(ssa, monkeypatch):
+    monkeypatch.setenv("SSA_LAUNCH_FORM", "generations")
+    m = inputs.viral()
+    n, t_end, g, seed, hist = 3001, 6.0, 41, 12, (1, 0, 1, 16)
+    grid_np = inputs.uniform_grid(t_end, g)
+    grid = _t(grid_np)
+    model = ssa.Model.from_dict(m)
+    print("forward order vs oracle: N %d" % n, flush=True)
+    ssa.run_device(model, n, t_end, grid, seed, hist=hist)
+    mean, var, h, st = ssa.run_device(model, n, t_end, grid, seed, hist=hist, with_stats=True)
+    torch.cuda.synchronize()
+    model.close()
+    assert st["ordered"] and st["form"] == "generations", st
+    s, ref = orc.run(m, n, t_end, grid_np, seed, hist=hist)
+    assert s == 0
+    assert np.array_equal(mean.cpu().numpy(), ref["mean"]) and np.array_equal(var.cpu().numpy(), ref["var"])
+    assert np.array_equal(h.cpu().numpy().astype(np.int64), ref["hist"].astype(np.int64))
+    assert st["events"] == ref["events"]
