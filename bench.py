@@ -432,6 +432,77 @@ def measure_step(ssa, torch, dev, name, steps, warmup, graph_steps=True):
     torch.cuda.synchronize()
     model.close()
 
+    # the forward's trajectory order.  The step above runs with SSA_FWD_ORDER=0: it repeats
+    # one run, and a forward of a run the model has recorded before takes its trajectories
+    # longest first by those counts -- exact for the same run again (another statistic of the
+    # same trajectories), a hint for other rates.  Here, with the order on: a run's first
+    # forward (no record), the same run again, and a run ordered by the counts of the same
+    # trajectories under rates 1 % and 10 % away (log-normal), each the best of two kernel
+    # times; eager steps of the same run again; and eager steps that draw new trajectories
+    # every step (a new seed each: no record for the forward, the backward takes its
+    # forward's)
+    def fwd_stats(mdl, rates=None, sd=seed):
+        return ssa.run_device(mdl, N, t_end, grid, sd, hist=hist, rates=rates, with_stats=True)[3]
+
+    def eager_steps(mdl, seeds, want_fwd_ordered):
+        def one(sd, check=True):
+            _, _, _, sf = ssa.run_device(mdl, N, t_end, grid, sd, hist=hist, out=(mean, var, hbuf),
+                                         with_stats=True)
+            torch.sub(mean, target, out=wts)
+            wts.mul_(2.0)
+            _, sb = ssa.backward_device(mdl, N, t_end, grid, sd, wts, mean, out=gbuf, with_stats=True)
+            assert not check or (sf["ordered"] == want_fwd_ordered and sb["ordered"]), (sf, sb)
+            assert sf["flags"] == 0 and sb["flags"] == 0, (sf, sb)
+            return sf
+        one(seeds[0] if want_fwd_ordered else seeds[0] - 1, check=False)   # untimed: the model's record
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sfs = [one(sd) for sd in seeds]
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / len(seeds)
+        ev = sum(f["events"] for f in sfs) / len(seeds)
+        return {"steps": len(seeds), "eager_ms_per_step": round(ms, 4),
+                "events_per_s": round(ev / (ms * 1e-3), 1),
+                "fwd_kernel_ms": round(float(np.mean([f["kernel_ms"] for f in sfs])), 4)}
+
+    order = None
+    if fs[0]["form"] == "generations":
+        near = {"1%": torch.tensor(inputs.perturbed_rates(m, 405, sigma=0.01), device=dev), "10%": prates}
+        saved = os.environ.pop("SSA_FWD_ORDER", None)
+        try:
+            cold, again, stale = [], [], {k: [] for k in near}
+            for _ in range(2):
+                fresh = ssa.Model.from_dict(m)
+                s = fwd_stats(fresh)
+                assert not s["ordered"] and s["events"] == events, s
+                cold.append(s["kernel_ms"])
+                s = fwd_stats(fresh)
+                fresh.close()
+                assert s["ordered"] and s["events"] == events, s
+                again.append(s["kernel_ms"])
+                for k, r in near.items():
+                    other = ssa.Model.from_dict(m)
+                    fwd_stats(other, r)
+                    s = fwd_stats(other)
+                    other.close()
+                    assert s["ordered"] and s["events"] == events, s
+                    stale[k].append(s["kernel_ms"])
+            model2 = ssa.Model.from_dict(m)
+            same = eager_steps(model2, [seed] * 5, True)
+            new_seed = eager_steps(model2, [seed + 1000 + i for i in range(5)], False)
+            model2.close()
+        finally:
+            if saved is not None:
+                os.environ["SSA_FWD_ORDER"] = saved
+        order = {"timed_steps_forward_ordered": any(f["ordered"] for f in fs),
+                 "no_record_fwd_kernel_ms": round(min(cold), 4),
+                 "same_run_again_fwd_kernel_ms": round(min(again), 4),
+                 "record_rates_1pct_away_fwd_kernel_ms": round(min(stale["1%"]), 4),
+                 "record_rates_10pct_away_fwd_kernel_ms": round(min(stale["10%"]), 4),
+                 "same_run_again_steps": same, "new_seed_every_step": new_seed}
+
     # roofline of the dominant simulation kernel: algorithmic lane-ops per launch / its mean
     # launch time over the timed steps
     crossings = G * N / max(events, 1)                 # grid points passed per event
@@ -465,7 +536,7 @@ def measure_step(ssa, torch, dev, name, steps, warmup, graph_steps=True):
                 graph_ms=graph_ms, graph_median_ms=float(np.median(graph_per)), graph_wall=g_wall,
                 fwd_ms=fwd_avg, bwd_ms=bwd_avg, fwd_only_ms=fwd_only_ms, wall=wall, roofline=roofline,
                 fwd_form=fs[0]["form"], bwd_form=bs[0]["form"], fwd_blocks=fs[0]["blocks"],
-                bwd_blocks=bs[0]["blocks"], target=target.cpu().numpy(), model=m, w=w)
+                bwd_blocks=bs[0]["blocks"], target=target.cpu().numpy(), model=m, w=w, order=order)
 
 
 def cpu_baseline(m, w, target):
@@ -538,6 +609,9 @@ def main():
                     help="only run the forward and backward autotuners on the viral, differentiated and large "
                          "workloads and print what they chose")
     args = ap.parse_args()
+    # the timed steps repeat one run: forwards in index order, as a run's first forward
+    # (the forward's order by a recorded run is measured on its own, see measure_step)
+    os.environ["SSA_FWD_ORDER"] = "0"
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path; trajectory "
@@ -617,6 +691,7 @@ def main():
         "launch_forms": {"forward": r["fwd_form"], "backward": r["bwd_form"], "forward_blocks": r["fwd_blocks"],
                          "backward_blocks": r["bwd_blocks"]},
         "fwd_only_ms": round(r["fwd_only_ms"], 4),
+        "forward_order": r["order"],
         "grad_vs_plain": round(r["step_ms"] / r["fwd_only_ms"], 3),
         "wall_s": round(r["graph_wall"], 3),
         "eager_wall_s": round(r["wall"], 3),

@@ -65,6 +65,7 @@
  *       SSA_WIN_BYTES=n           LDS bytes of a selective-memory window (512 .. 16384)
  *       SSA_FWD_FLUSH=slab        windows flushed into wave-private slabs, not by atomics,
  *       SSA_SLAB_BYTES=n            when the slabs fit in n bytes (default 1 GiB)
+ *       SSA_FWD_ORDER=0           forwards ignore recorded event counts (index order)
  *       SSA_WIDE_DEPG=0           many-reaction kernels re-evaluate every propensity
  *       SSA_JAC_BYTES=n           scratch budget of ssa_run_jacobian_device (default 4 GiB)
  *       SSA_SORT_BINS=n           bins of the adaptive memory's time order

@@ -1515,8 +1515,11 @@ ssa_status hint_order(const ssa_model *m, const RunId &id, Scratch &scr, hipStre
 // The event counts a forward of run id may take its trajectories in order of, or NULL: those
 // of the last recorded forward with the same trajectory count, horizon, seed and event cap
 // (the rates may have changed since: the counts are then a close hint, never a result).
+// SSA_FWD_ORDER=0 turns the forward's order off (timing a run's first forward).
 const uint32_t *fwd_hint(const ssa_model *m, const RunId &id) {
     if (id.n > kMaxHintTraj) return nullptr;
+    if (const char *e = std::getenv("SSA_FWD_ORDER"))
+        if (e[0] == '0' && e[1] == 0) return nullptr;
     std::lock_guard<std::mutex> lk(m->hint_mu);
     const bool same = m->hint_valid && m->hint_n == id.n && m->hint_t_end == id.t_end && m->hint_seed == id.seed &&
                       m->hint_max_events == id.max_events && m->hint_dev == id.dev;

@@ -179,3 +179,21 @@ def test_forward_in_recorded_order_matches_the_oracle(ssa, monkeypatch):
     assert np.array_equal(mean.cpu().numpy(), ref["mean"]) and np.array_equal(var.cpu().numpy(), ref["var"])
     assert np.array_equal(h.cpu().numpy().astype(np.int64), ref["hist"].astype(np.int64))
     assert st["events"] == ref["events"]
+
+
+def test_forward_order_switch(ssa, monkeypatch):
+    """SSA_FWD_ORDER=0: a forward of a recorded run stays in index order, with the same outputs."""
+    m = inputs.viral()
+    grid = _t(inputs.uniform_grid(T_END, G))
+    model = ssa.Model.from_dict(m)
+    print("forward order switch", flush=True)
+    a = ssa.run_device(model, N, T_END, grid, SEED, with_stats=True)
+    monkeypatch.setenv("SSA_FWD_ORDER", "0")
+    b = ssa.run_device(model, N, T_END, grid, SEED, with_stats=True)
+    monkeypatch.delenv("SSA_FWD_ORDER")
+    c = ssa.run_device(model, N, T_END, grid, SEED, with_stats=True)
+    torch.cuda.synchronize()
+    model.close()
+    assert not a[3]["ordered"] and not b[3]["ordered"] and c[3]["ordered"], (a[3], b[3], c[3])
+    for x, y, z in zip(a[:2], b[:2], c[:2]):
+        assert torch.equal(x, y) and torch.equal(x, z)
