@@ -326,7 +326,7 @@ ssa_status ssa_backward_moments_device(const ssa_model *model, const double *rat
  * configuration is timed on the caller's problem (grid [n_grid] device, the same outputs for
  * all: results never depend on the configuration) by the device time of everything the call
  * launches (fills, slabs and their reduction included), the best of two calls after a
- * warm-up: first the LDS window bytes 2048 .. 16384
+ * warm-up, each in index order as a run's first forward: first the LDS window bytes 2048 .. 16384
  * with the windows flushed by atomics or through wave-private slabs, then, with the best
  * window, the launch form of the specialised kernels (two-wave blocks or generations) and
  * its block count (the default and smaller grids).  The fastest is remembered for (device

@@ -1609,7 +1609,8 @@ ssa_status run_device_impl(const ssa_model *m, const double *rates, const double
         n.h_lo = hist->lo;
         n.h_width = hist->width;
     }
-    const uint32_t *order_keys = fixed ? nullptr : fwd_hint(m, rid);
+    // the forward tuner (tune given) times a run's first forward: index order
+    const uint32_t *order_keys = (fixed || tune) ? nullptr : fwd_hint(m, rid);
     n.len_out = fixed ? nullptr : hint_begin(m, rid, cap);
     WorkList wl;
     std::memset(&wl, 0, sizeof wl);
